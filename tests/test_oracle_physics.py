@@ -1,0 +1,292 @@
+"""Closed-form and invariant pins of the oracle's full step.
+
+Ballistic motion under symplectic Euler (exact discrete formula), the
+physical-pendulum period (exact AGM form), first-order energy behaviour,
+momentum conservation in zero-g collisions, the single-contact PGS closed
+form, resting boxes and stacks, stick/slip on an incline, Coulomb
+deceleration, and the level-schedule rule that lets the GPU run the
+canonical Gauss-Seidel order level by level.
+"""
+import math
+
+import numpy as np
+import pytest
+
+import oracle
+import scenegen as sg
+
+G = 9.81
+FLOOR = [(0.0, 0.0, 1.0, 0.0)]
+
+
+def free_rows(b, x):
+    return sg.split_state(x, b.n_scenes, b.n_free, b.n_aux)["free"]
+
+
+def run(b, n_steps, x=None, u=None, debug=False, dump_cap=0):
+    o = oracle.Oracle(b)
+    x = b.state0.astype(np.float64) if x is None else x
+    u = np.zeros((b.n_scenes, 16)) if u is None else u
+    out = []
+    for _ in range(n_steps):
+        r = o.step(x, u, debug=debug, dump_cap=dump_cap)
+        x = r[0] if (debug or dump_cap) else r
+        out.append(r)
+    return x, out
+
+
+def test_ballistic_exact_discrete_formula():
+    v0 = np.array([0.7, -0.3, 2.0])
+    w0 = np.array([0.0, 0.0, 3.0])
+    b = sg.custom_batch([sg.empty_model()], [dict(free=[sg.sphere_object(0.05, 0.4, (0.1, 0.2, 3.0), vel=v0,
+                                                                         angvel=w0)])], h=0.004, n_sub=25)
+    x, _ = run(b, 4)
+    fr = free_rows(b, x)[0]
+    n = 100
+    h = b.h
+    x0 = b.state0.astype(np.float64)[32:35]
+    v0f = v0.astype(np.float32).astype(np.float64)
+    g = np.array([0, 0, -G])
+    ref = x0 + n * h * v0f + g * h * h * n * (n + 1) / 2
+    assert np.allclose(fr[0:3], ref, atol=1e-12)
+    assert np.allclose(fr[8:11], v0f + n * h * g, atol=1e-12)
+    # isotropic body, no torque: the angular velocity is constant and the
+    # orientation turns by n * h * w about w
+    th = n * h * 3.0
+    assert np.allclose(fr[4:8], [math.cos(th / 2), 0, 0, math.sin(th / 2)], atol=1e-12)
+
+
+def _pendulum(d, m, Iy, theta0, h):
+    mb = sg.model_builder()
+    mb.body(-1, sg.JT_REVOLUTE, (0, 1, 0), (0, 0, 2.0), m, (0, 0, -d), (Iy, Iy, Iy))
+    q = np.zeros(16)
+    q[0] = theta0
+    return sg.custom_batch([mb.arrays()], [dict(q=q)], h=h, n_sub=1)
+
+
+def _agm(a, b):
+    for _ in range(60):
+        a, b = (a + b) / 2, math.sqrt(a * b)
+    return a
+
+
+def _measure_period(b, T_guess):
+    o = oracle.Oracle(b)
+    x = b.state0.astype(np.float64)
+    u = np.zeros((1, 16))
+    qs = [x[0]]
+    n = int(2.3 * T_guess / b.h)
+    for _ in range(n):
+        x = o.step(x, u)
+        qs.append(x[0])
+    qs = np.array(qs)
+    t = np.arange(len(qs)) * b.h
+    # downward zero crossings, linearly interpolated
+    idx = np.nonzero((qs[:-1] > 0) & (qs[1:] <= 0))[0]
+    tc = t[idx] + b.h * qs[idx] / (qs[idx] - qs[idx + 1])
+    return tc[1] - tc[0]
+
+
+def test_pendulum_period_agm_closed_form():
+    d, m, Iy, th0 = 0.4, 1.5, 0.02, 1.2
+    b = _pendulum(d, m, Iy, th0, 1e-3)
+    d = -float(b.model_com[0, 0, 2])
+    m = float(b.model_mass[0, 0])
+    Iy = float(b.model_inertia[0, 0, 1])
+    th0 = float(b.state0[0])
+    Ip = Iy + m * d * d
+    T = 2 * math.pi * math.sqrt(Ip / (m * G * d)) / _agm(1.0, math.cos(th0 / 2))
+    errs = []
+    for h in (2e-3, 1e-3, 5e-4):
+        errs.append(abs(_measure_period(_pendulum(0.4, 1.5, 0.02, 1.2, h), T) - T))
+    assert errs[1] < 2e-3 * T
+    assert errs[2] < errs[1] < errs[0]
+
+
+def test_double_pendulum_energy_first_order():
+    """No contact, no damping: the energy error is bounded and shrinks with h."""
+    def energy_drift(h):
+        mb = sg.model_builder()
+        b0 = mb.body(-1, sg.JT_REVOLUTE, (0, 1, 0), (0, 0, 2.0), 1.0, (0.15, 0, 0), (0.01, 0.01, 0.01))
+        mb.body(b0, sg.JT_REVOLUTE, (0, 1, 0), (0.3, 0, 0), 0.6, (0.12, 0, 0), (0.005, 0.005, 0.005))
+        q = np.zeros(16)
+        q[0], q[1] = 0.4, -0.8
+        b = sg.custom_batch([mb.arrays()], [dict(q=q)], h=h, n_sub=int(round(0.05 / h)))
+        o = oracle.Oracle(b)
+        x = b.state0.astype(np.float64)
+        mass = b.model_mass[0].astype(np.float64)
+        com = b.model_com[0].astype(np.float64)
+
+        def E(x):
+            q, qd = x[:16], x[16:32]
+            _, org, rot = o.fk(0, q)
+            V = sum(mass[i] * G * (rot[i] @ com[i] + org[i])[2] for i in range(2))
+            return o.kinetic_energy(0, q, qd) + V
+        E0 = E(x)
+        dev = 0.0
+        for _ in range(40):
+            x = o.step(x, np.zeros((1, 16)))
+            dev = max(dev, abs(E(x) - E0))
+        return dev
+    # potential-energy scale of the motion is ~3 J; symplectic Euler keeps the
+    # error bounded and first order: halving h halves it
+    d1, d2 = energy_drift(2e-3), energy_drift(1e-3)
+    assert d1 < 0.15
+    assert 0.4 * d1 < d2 < 0.6 * d1
+
+
+@pytest.mark.parametrize("mu", [0.0, 0.5])
+def test_zero_g_collision_conserves_momentum(mu):
+    a = sg.sphere_object(0.1, 1.0, (0.0, 0.0, 0.0), vel=(1.0, 0.1, 0.0), angvel=(0, 0, 2.0))
+    c = sg.sphere_object(0.08, 0.5, (0.25, 0.05, 0.0), vel=(-1.5, 0.0, 0.2), angvel=(1.0, 0, 0))
+    b = sg.custom_batch([sg.empty_model()], [dict(free=[a, c])], h=0.002, n_sub=10, mu=mu, gravity=(0, 0, 0))
+    mass = b.free_mass.astype(np.float64)
+    Ib = b.free_inertia[:, 0].astype(np.float64)
+
+    def moments(x):
+        fr = free_rows(b, x)
+        P = sum(mass[i] * fr[i, 8:11] for i in range(2))
+        L = sum(np.cross(fr[i, 0:3], mass[i] * fr[i, 8:11]) + Ib[i] * fr[i, 12:15] for i in range(2))
+        return P, L
+    x0 = b.state0.astype(np.float64)
+    P0, L0 = moments(x0)
+    x, outs = run(b, 10, debug=True)
+    assert max(d["n_contacts"].max() for _, d in outs) > 0   # the spheres did collide
+    P1, L1 = moments(x)
+    assert np.allclose(P1, P0, atol=1e-12)
+    assert np.allclose(L1, L0, atol=1e-12)
+
+
+def test_single_frictionless_contact_exact_after_one_sweep():
+    """One contact, one body: PGS is exact after one sweep, lambda =
+    max(0, -(J v* + b) / W); a speculative contact (phi >= 0) lands on phi = 0."""
+    r, m = 0.05, 0.3
+    gap = 0.004
+    for vz in (-2.0, -0.1):
+        s = sg.sphere_object(r, m, (0.0, 0.0, r + gap), vel=(0.0, 0.0, vz))
+        for K in (1, 7):
+            b = sg.custom_batch([sg.empty_model()], [dict(free=[s], planes=FLOOR)], h=0.005, n_sub=1,
+                                pgs_iters=K, mu=0.0)
+            x, (r_out,) = run(b, 1, dump_cap=4)
+            fr = free_rows(b, x)[0]
+            z0 = float(b.state0[32 + 2])
+            phi0 = z0 - float(b.free_size[0, 0])
+            vstar = float(np.float32(vz)) - G * b.h
+            lam = max(0.0, -(vstar + phi0 / b.h) * m)
+            assert r_out[1]["dump_lambda"][0, 0, 0] == pytest.approx(lam * float(b.free_mass[0]) / m, rel=1e-12)
+            if lam > 0:
+                assert fr[10] == pytest.approx(-phi0 / b.h, abs=1e-12)
+                assert fr[2] - float(b.free_size[0, 0]) == pytest.approx(0.0, abs=1e-14)
+            else:
+                assert fr[10] == pytest.approx(vstar, abs=1e-12)
+
+
+def test_resting_box_support_impulse():
+    half = (0.1, 0.08, 0.05)
+    m = 0.8
+    box = sg.box_object(half, m, (0.0, 0.0, half[2]))
+    b = sg.custom_batch([sg.empty_model()], [dict(free=[box], planes=FLOOR)], h=0.002, n_sub=10, pgs_iters=10)
+    x, outs = run(b, 20, dump_cap=8)
+    fr = free_rows(b, x)[0]
+    hz = float(b.free_size[0, 2])
+    assert abs(fr[2] - hz) < 1e-4
+    assert np.abs(fr[8:11]).max() < 1e-3 and np.abs(fr[12:15]).max() < 1e-2
+    lam = outs[-1][1]["dump_lambda"][0, :, 0]
+    assert lam.sum() == pytest.approx(float(b.free_mass[0]) * G * b.h, rel=1e-2)
+
+
+def test_resting_stack_drift():
+    boxes = []
+    z = 0.0
+    for k, (hx, hz, m) in enumerate([(0.15, 0.06, 1.0), (0.12, 0.05, 0.6), (0.1, 0.04, 0.3)]):
+        boxes.append(sg.box_object((hx, hx, hz), m, (0.0, 0.0, z + hz)))
+        z += 2 * hz
+    b = sg.custom_batch([sg.empty_model()], [dict(free=boxes, planes=FLOOR)], h=0.002, n_sub=10, pgs_iters=10)
+    x0 = free_rows(b, b.state0.astype(np.float64)).copy()
+    x, outs = run(b, 50, debug=True)   # 500 substeps
+    fr = free_rows(b, x)
+    assert np.abs(fr[:, 0:3] - x0[:, 0:3]).max() < 1e-3
+    assert max(d["n_contacts"].max() for _, d in outs) >= 12
+
+
+@pytest.mark.parametrize("theta,stick", [(0.3, True), (0.6, False)])
+def test_incline_stick_slip(theta, stick):
+    mu = 0.5          # tan(0.3) = 0.31 < 0.5 sticks, tan(0.6) = 0.68 > 0.5 slides
+    n = np.array([-math.sin(theta), 0.0, math.cos(theta)])
+    half = (0.08, 0.08, 0.05)
+    quat = (math.cos(-theta / 2), 0.0, math.sin(-theta / 2), 0.0)
+    box = sg.box_object(half, 0.5, tuple(n * half[2]), quat=quat)
+    plane = [(n[0], n[1], n[2], 0.0)]
+    b = sg.custom_batch([sg.empty_model()], [dict(free=[box], planes=plane)], h=0.002, n_sub=25, pgs_iters=20,
+                        mu=mu)
+    x, _ = run(b, 10)   # 0.5 s
+    fr = free_rows(b, x)[0]
+    down = np.array([math.cos(theta), 0.0, math.sin(theta)])   # down-slope direction points to +x, -z? -> use velocity
+    v = fr[8:11]
+    t = 0.5
+    if stick:
+        assert np.linalg.norm(v) < 1e-3
+    else:
+        a = G * (math.sin(theta) - mu * math.cos(theta))
+        assert np.linalg.norm(v) == pytest.approx(a * t, rel=0.03)
+        assert abs(np.dot(v, n)) < 1e-3
+    del down
+
+
+def test_sliding_box_coulomb_deceleration():
+    mu = 0.4
+    half = (0.1, 0.1, 0.05)
+    box = sg.box_object(half, 1.0, (0.0, 0.0, half[2]), vel=(2.0, 0.0, 0.0))
+    b = sg.custom_batch([sg.empty_model()], [dict(free=[box], planes=FLOOR)], h=0.002, n_sub=10, pgs_iters=10,
+                        mu=mu)
+    o = oracle.Oracle(b)
+    x = b.state0.astype(np.float64)
+    vs = [2.0]
+    for _ in range(10):
+        x = o.step(x, np.zeros((1, 16)))
+        vs.append(free_rows(b, x)[0, 8])
+    # after the first control step the box slides at constant deceleration mu g
+    dv = np.diff(vs[1:])
+    assert np.allclose(dv, -mu * G * b.h * b.n_sub, rtol=2e-2)
+
+
+def test_level_schedule_equals_sequential_order():
+    """Rows touching a common node are applied in canonical order when each row's
+    level is 1 + the max level of earlier conflicting rows and levels run in
+    order (rows of one level in any order): the per-node update sequences, and
+    so any Gauss-Seidel result, are identical."""
+    rng = np.random.default_rng(7)
+    for trial in range(50):
+        n_nodes = int(rng.integers(2, 12))
+        rows = []
+        for _ in range(int(rng.integers(1, 60))):
+            a = int(rng.integers(0, n_nodes))
+            b = int(rng.integers(-1, n_nodes))   # -1: static
+            rows.append((a, b if b != a else -1))
+        # level rule
+        last = np.zeros(n_nodes, int)
+        level = []
+        for a, b in rows:
+            lv = 1 + max(last[a], last[b] if b >= 0 else 0)
+            level.append(lv)
+            last[a] = lv
+            if b >= 0:
+                last[b] = lv
+        # a nonlinear, order-sensitive per-row update
+        def upd(vals, k, a, b):
+            va = vals[a]
+            vb = vals[b] if b >= 0 else 0.3
+            t = math.sin(va * 1.7 + k) - 0.5 * vb
+            vals[a] = va + max(0.0, t)
+            if b >= 0:
+                vals[b] = vb - 0.3 * max(0.0, t)
+        seq = list(rng.normal(size=n_nodes))
+        par = list(seq)
+        for k, (a, b) in enumerate(rows):
+            upd(seq, k, a, b)
+        for lv in range(1, max(level) + 1):
+            ks = [k for k in range(len(rows)) if level[k] == lv]
+            rng.shuffle(ks)
+            for k in ks:
+                upd(par, k, *rows[k])
+        assert seq == par
