@@ -1,0 +1,215 @@
+#!/usr/bin/env python3
+"""Benchmark: physics env-steps/s of the batched rigid-body step on one MI355X.
+
+Workload (default): 4096 uneven Fetch-like scenes (free objects U{2..32},
+furniture boxes U{32..256}), h = 2 ms, 5 substeps per control step, 10 PGS
+sweeps; one "step" is one control step of every scene with the inputs
+resident in HBM.  Prints ONE JSON line (see the keys below).
+
+  python bench.py [--gpus 1] [--steps K] [--warmup W] [--config 3] [--no-cpu]
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0          # MI355X HBM3E, GB/s
+FP32_VECTOR_PEAK_TFLOPS = 157.3  # MI355X FP32 vector
+
+
+def kernel_source_hash():
+    h = hashlib.sha256()
+    for f in ("ms_kernels.hip", "ms_internal.h"):
+        with open(os.path.join(ROOT, "paper_2412_13211_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def algorithmic_bytes_per_env_step(b):
+    """HBM bytes one control step must move for the whole batch: state in +
+    out, controls in, the per-scene description (free-body parameters, static
+    boxes, planes, door/drawer, scene record); the shared robot model once."""
+    S, NF, NA = b.n_scenes, b.n_free, b.n_aux
+    state = (32 * S + 16 * NF + 4 * NA) * 4
+    controls = 16 * S * 4
+    desc = NF * 32 + int(b.static_off[-1]) * 24 + int(b.plane_off[-1]) * 16 + NA * 128 + S * 112
+    model = len(b.model_nb) * 6 * 1024
+    return 2 * state + controls + desc + model
+
+
+def algorithmic_flops_per_env_step(b, sample=64, seed=0):
+    """Floating-point operations of one control step (the oracle's definition,
+    counted by its op-counting scalar) averaged over a scene sample."""
+    import oracle
+    rng = np.random.default_rng(seed)
+    pick = sorted(rng.choice(b.n_scenes, min(sample, b.n_scenes), replace=False).tolist())
+    sub = b.subset(pick)
+    o = oracle.Oracle(sub)
+    return float(np.mean(o.flops(sub.state0.astype(np.float64), b.controls(0, pick)))) / 1.0
+
+
+def cpu_baseline(b, seconds=12.0, n=256, threads=None):
+    """The FP64 oracle as it stands, on a seeded scene subset, all allotted host cores."""
+    import oracle
+    oracle.build(force=False)
+    cores = threads or min(16, os.cpu_count() or 1)
+    rng = np.random.default_rng(1)
+    pick = sorted(rng.choice(b.n_scenes, min(n, b.n_scenes), replace=False).tolist())
+    sub = b.subset(pick)
+    o = oracle.Oracle(sub, threads=cores)
+    x = sub.state0.astype(np.float64)
+    steps = 0
+    t0 = time.perf_counter()
+    while True:
+        x = o.step(x, b.controls(steps, pick))
+        steps += 1
+        if time.perf_counter() - t0 >= seconds:
+            break
+    dt = time.perf_counter() - t0
+    return {"value": len(pick) * steps / dt, "unit": "env-steps/s", "cores": cores, "kind": "oracle",
+            "sample": f"{len(pick)} seeded scenes of the same workload x {steps} control steps, FP64, {dt:.1f} s"}
+
+
+def load_traffic(name, nscenes, src_hash):
+    """HBM traffic of the dominant kernel from the committed rocprofv3 counter
+    summary, if it was taken on the current kernel source."""
+    p = os.path.join(ROOT, "profiles", f"{name}_traffic.json")
+    if not os.path.exists(p):
+        return None
+    try:
+        d = json.load(open(p))
+    except Exception:
+        return None
+    if d.get("kernel_source_hash") != src_hash or d.get("scenes") != nscenes:
+        return None
+    return d.get("bytes_per_launch")
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=50)
+    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--config", type=int, default=3)
+    ap.add_argument("--scenes", type=int, default=None)
+    ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--schedule", default="auto", help="auto | graph | graph-persistent | plain")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py measures one GPU only: the step has no cross-GPU exchange and this build runs on "
+              f"a single MI355X (asked for --gpus {args.gpus}).", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    import paper_2412_13211_amd as ms
+    import scenegen as sg
+
+    t_gen = time.perf_counter()
+    b = sg.make(args.config, args.scenes)
+    S = b.n_scenes
+    print(f"[bench] workload {b.name}: {S} scenes, {b.n_free} free bodies, {int(b.static_off[-1])} boxes "
+          f"(generated in {time.perf_counter() - t_gen:.1f} s)", file=sys.stderr, flush=True)
+    dev = torch.device("cuda", 0)
+    torch.cuda.set_device(dev)
+    mb = ms.MsBatch(b)
+    # controls for every timed step, resident in HBM before timing
+    n_ctrl = args.warmup + args.steps
+    blocks = {}
+    U = torch.empty((n_ctrl, S, 16), dtype=torch.float32, device=dev)
+    for t in range(n_ctrl):
+        key = t // b.ctrl_block if b.ctrl_kind == "pd_targets" else t
+        if key not in blocks:
+            blocks[key] = torch.as_tensor(b.controls(t)).to(dev)
+        U[t].copy_(blocks[key])
+    x0 = torch.as_tensor(b.state0).to(dev)
+    xa = x0.clone()
+    xb = torch.empty_like(x0)
+    stream = torch.cuda.current_stream()
+
+    def run(n, flags, time_it):
+        nonlocal xa, xb
+        mb.set_schedule(flags)
+        xa.copy_(x0)
+        ev = [torch.cuda.Event(enable_timing=True) for _ in range(2)]
+        # warm-up (also captures the graphs for both ping-pong directions)
+        for t in range(min(args.warmup, n_ctrl)):
+            mb.step(xa, U[t], out=xb)
+            xa, xb = xb, xa
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        ev[0].record(stream)
+        for t in range(args.steps):
+            mb.step(xa, U[(args.warmup + t) % n_ctrl], out=xb)
+            xa, xb = xb, xa
+        ev[1].record(stream)
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - t0
+        gpu_ms = ev[0].elapsed_time(ev[1])
+        return wall, gpu_ms
+
+    flags_graph = ms.MS_SCHED_GRAPH | ms.MS_SCHED_STAGE_STATIC
+    if args.schedule == "auto":
+        (flags, grid), t_auto = mb.autotune(x0, U[0], reps=3)
+    elif args.schedule == "graph":
+        flags = flags_graph
+    elif args.schedule == "graph-persistent":
+        flags = flags_graph | ms.MS_SCHED_PERSISTENT
+    else:
+        flags = ms.MS_SCHED_STAGE_STATIC | ms.MS_SCHED_PER_SUBSTEP
+    print(f"[bench] schedule flags {flags}", file=sys.stderr, flush=True)
+    wall, gpu_ms = run(args.steps, flags, True)
+    # the plain form: one launch per substep, no graph, same kernel
+    wall_plain, gpu_ms_plain = run(args.steps, ms.MS_SCHED_STAGE_STATIC | ms.MS_SCHED_PER_SUBSTEP, True)
+    st = mb.status()
+    value = S * args.steps / wall
+    ms_per_step = 1e3 * wall / args.steps
+    launch_ms = gpu_ms / args.steps  # one kernel launch per control step in the fused schedules
+    bytes_step = algorithmic_bytes_per_env_step(b)
+    flops_env = algorithmic_flops_per_env_step(b)
+    flops_launch = flops_env * S
+    achieved_tflops = flops_launch / (launch_ms * 1e-3) / 1e12
+    hbm_gbs = bytes_step / (launch_ms * 1e-3) / 1e9
+    src_hash = kernel_source_hash()
+    traffic = load_traffic(b.name, S, src_hash)
+    out = {
+        "metric": "physics env-steps/sec at 4096 scenes (fwd)",
+        "value": round(value, 1),
+        "unit": "env-steps/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms_per_step, 4),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": f"{b.name}: {S} Fetch-like scenes, free objects U{{2..32}}, furniture boxes "
+                               f"U{{32..256}}, h={b.h:g} s x {b.n_sub} substeps, {b.pgs_iters} PGS sweeps",
+                   "scenes": S, "substeps": b.n_sub, "schedule_flags": int(flags)},
+        "roofline": {"bound": "alu", "achieved": round(achieved_tflops, 4), "peak": FP32_VECTOR_PEAK_TFLOPS,
+                     "unit": "TFLOP/s", "frac": round(achieved_tflops / FP32_VECTOR_PEAK_TFLOPS, 6),
+                     "traffic": traffic, "flops_per_env_step": round(flops_env),
+                     "kernel_ms_per_launch": round(launch_ms, 5)},
+        "hbm_roofline": {"achieved": round(hbm_gbs, 3), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                         "frac": round(hbm_gbs / HBM_PEAK_GBS, 6), "bytes_per_env_step_batch": bytes_step},
+        "plain_per_substep": {"value": round(S * args.steps / wall_plain, 1), "unit": "env-steps/s",
+                              "ms_per_step": round(1e3 * wall_plain / args.steps, 4)},
+        "scene_status_nonzero": int(np.count_nonzero(st)),
+    }
+    if not args.no_cpu:
+        out["cpu_baseline"] = cpu_baseline(b)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,236 @@
+/* ms_phys.h -- C ABI of the batched rigid-body physics step on MI355X (gfx950).
+ *
+ * The step advances S independent scenes by one control step: n_substeps
+ * physics substeps with the controls held (zero-order hold).  It is the
+ * physics part of the environment dynamics T: S x A -> S that the paper's
+ * many-environment simulation evaluates for every environment at once
+ * (MDP formulation, Sec. 3; 100 Hz simulation under 20 Hz control and up to
+ * 4096 parallel environments, Sec. 4.2).  Each substep: drive (torque or
+ * implicit PD), forward kinematics, sphere-decomposed contacts, articulated-
+ * body dynamics, contact rows, projected Gauss-Seidel with a friction disk in
+ * a fixed level-scheduled order, semi-implicit Euler.  The paper does not
+ * describe its solver; every numerical choice is documented with the oracle.
+ *
+ * Conventions
+ *   - All functions are extern "C", never throw, and return ms_status
+ *     (0 = MS_OK, negative = error).  ms_last_error() gives a message.
+ *   - "_dev" pointers are device memory on the batch's device; "host" ones
+ *     are host memory.  The caller owns every buffer; the library allocates
+ *     no device memory (it binds the params / scratch / tape buffers the
+ *     caller allocated from ms_query_sizes) and keeps only host objects and
+ *     HIP graphs.
+ *   - Stream-ordered calls (ms_step, ms_step_backward, ms_set_state) enqueue
+ *     work on hip_stream (a hipStream_t, may be null = default stream) and
+ *     return without synchronising.  Argument errors are detected before
+ *     anything is enqueued and leave all buffers untouched.
+ *   - Numeric faults are per scene: status bits, read with ms_scene_status.
+ *
+ * State layout (float32, one flat buffer of ms_state_floats() floats):
+ *   q[S][16], qd[S][16]            robot joint positions / velocities (padded to 16)
+ *   free[NF][16]                   per free body: pos xyz, 0, quat wxyz,
+ *                                  linvel xyz, 0, angvel xyz, 0 (world frame)
+ *   aux[NA][4]                     per door / drawer joint: q, qd, 0, 0
+ * with NF = free_off[S], NA = aux_off[S] (CSR offsets of the scene description).
+ * Controls: float32 [S][16] (torques, PD targets, or torques added to a PD hold,
+ * by control_mode).
+ */
+#ifndef MS_PHYS_H
+#define MS_PHYS_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef int32_t ms_status;
+enum {
+  MS_OK = 0,
+  MS_E_INVALID = -1,     /* bad argument, shape or pointer; nothing was done */
+  MS_E_NOMEM = -2,       /* a caller buffer is smaller than ms_query_sizes asked for */
+  MS_E_HIP = -3,         /* a HIP runtime call failed (message in ms_last_error) */
+  MS_E_STATE = -4,       /* call not valid in the batch's current state */
+  MS_E_NUMERIC = -5,     /* at least one scene has a numeric status bit set */
+  MS_E_UNSUPPORTED = -6  /* device or configuration not supported (e.g. not gfx950) */
+};
+
+enum { MS_CTRL_TORQUE = 0, MS_CTRL_PD = 1, MS_CTRL_TORQUE_HOLD = 2 };
+
+/* per-scene status bits (ms_scene_status) */
+enum {
+  MS_ST_NONFINITE = 1u,       /* non-finite value in the scene's state after the step */
+  MS_ST_OVERFLOW = 2u,        /* more contacts than contact_cap (extra contacts dropped) */
+  MS_ST_DEGENERATE = 4u,      /* a row with effective mass below 1e-12 was skipped */
+  MS_ST_ROBOT_OVERFLOW = 8u   /* more robot contacts than robot_contact_cap (dropped) */
+};
+
+/* schedule flags */
+enum {
+  MS_SCHED_PERSISTENT = 1,    /* fixed grid pulling cost-sorted scenes from a queue */
+  MS_SCHED_GRAPH = 2,         /* replay one control step as a captured hipGraph */
+  MS_SCHED_PER_SUBSTEP = 4,   /* one launch per substep (state round trip through HBM) */
+  MS_SCHED_STAGE_STATIC = 8,  /* stage each scene's furniture boxes in LDS */
+  MS_SCHED_CULL = 16          /* bounding-sphere pre-test before sphere-pair tests */
+};
+
+typedef struct {
+  int32_t n_scenes;
+  int32_t n_substeps;          /* substeps per control step (zero-order hold) */
+  int32_t pgs_iters;           /* Gauss-Seidel sweeps per substep */
+  int32_t control_mode;        /* MS_CTRL_* */
+  int32_t contact_cap;         /* contacts kept per scene per substep (first in canonical order) */
+  int32_t robot_contact_cap;   /* robot-owned contacts kept per scene per substep */
+  float h;                     /* substep length, s */
+  float mu;                    /* friction coefficient */
+  float baumgarte;             /* penetration correction factor beta */
+  float margin;                /* speculative contact margin delta, m */
+  float gravity[3];            /* m/s^2 */
+} ms_batch_desc;
+
+/* Host arrays describing the scenes (same layout as the scene generator
+ * writes; ownership stays with the caller, read only during ms_query_sizes /
+ * ms_create_batch).  M robot models, S scenes, NF free bodies, NS static
+ * boxes, NP planes, NA door / drawer joints. */
+typedef struct {
+  int32_t n_models;
+  const int32_t* model_nb;        /* [M] bodies (= DoFs) of the robot, <= 16 */
+  const int32_t* model_parent;    /* [M][16] parent body, -1 = world; parents precede children */
+  const int32_t* model_jtype;     /* [M][16] 0 revolute, 1 prismatic */
+  const float* model_axis;        /* [M][16][3] unit joint axis in the joint frame */
+  const float* model_xt_rot;      /* [M][16][4] joint frame rotation in the parent body frame (wxyz) */
+  const float* model_xt_pos;      /* [M][16][3] joint frame origin in the parent body frame */
+  const float* model_mass;        /* [M][16] */
+  const float* model_com;         /* [M][16][3] centre of mass, body frame */
+  const float* model_inertia;     /* [M][16][6] about the COM, body axes: xx yy zz xy xz yz */
+  const float* model_kp;          /* [M][16] PD stiffness */
+  const float* model_kd;          /* [M][16] PD damping */
+  const int32_t* model_veldof;    /* [M][16] 1: the PD target is a velocity (planar base) */
+  const float* model_armature;    /* [M][16] rotor inertia */
+  const float* model_damping;     /* [M][16] viscous joint damping */
+  const int32_t* model_nsph;      /* [M] collision spheres, <= 128 */
+  const int32_t* model_sph_body;  /* [M][128] body of each sphere (sorted by body) */
+  const float* model_sph;         /* [M][128][4] centre in the body frame, radius */
+  const int32_t* model_sph_flags; /* [M][128] bit0: no contact with the scene's first plane */
+  const int32_t* scene_model;     /* [S] */
+  const int32_t* free_off;        /* [S+1] CSR offsets into the free-body arrays */
+  const int32_t* static_off;      /* [S+1] into static_box */
+  const int32_t* plane_off;       /* [S+1] into plane */
+  const int32_t* aux_off;         /* [S+1] into the aux arrays */
+  const float* scene_hold;        /* [S][16] hold targets (MS_CTRL_TORQUE_HOLD) */
+  const int32_t* free_type;       /* [NF] 0 box, 1 sphere */
+  const float* free_size;         /* [NF][3] half extents, or radius */
+  const float* free_mass;         /* [NF] */
+  const float* free_inertia;      /* [NF][3] principal moments (box axes) */
+  const float* static_box;        /* [NS][6] centre, half extents (axis aligned) */
+  const float* plane;             /* [NP][4] unit normal n and d with n.x = d */
+  const int32_t* aux_type;        /* [NA] 0 revolute (door), 1 prismatic (drawer) */
+  const float* aux_rot;           /* [NA][4] joint frame in the world (wxyz) */
+  const float* aux_pos;           /* [NA][3] */
+  const float* aux_axis;          /* [NA][3] joint axis, joint frame */
+  const float* aux_box;           /* [NA][6] box centre in the moving frame, half extents */
+  const float* aux_mass;          /* [NA] */
+  const float* aux_inertia;       /* [NA][3] principal moments about the box centre */
+  const float* aux_limit;         /* [NA][2] lower, upper joint limit (lower > upper: none) */
+} ms_scene_desc;
+
+typedef struct {
+  size_t params;   /* device bytes: packed scene description (uploaded by ms_create_batch) */
+  size_t state;    /* device bytes of one state buffer */
+  size_t scratch;  /* device bytes: queue counters, schedule tables, per-scene status, debug */
+  size_t tape;     /* device bytes used by ms_step_backward (forward record of one control step) */
+  size_t lds;      /* LDS bytes per scene workgroup (information only) */
+} ms_sizes;
+
+typedef struct {
+  float* q;          /* [S][16] */
+  float* qd;         /* [S][16] */
+  float* free_body;  /* [NF][16] */
+  float* aux;        /* [NA][4] */
+  const int32_t* free_off_host;  /* [S+1] (owned by the batch) */
+  const int32_t* aux_off_host;   /* [S+1] (owned by the batch) */
+  int32_t n_scenes, n_free, n_aux;
+} ms_state_view;
+
+typedef struct {
+  int32_t flags;        /* MS_SCHED_* */
+  int32_t grid;         /* persistent grid size (0 = automatic) */
+} ms_schedule;
+
+typedef struct ms_batch ms_batch;
+
+/* Byte sizes of the buffers a batch needs.  Validates desc and scenes
+ * (shapes, CSR monotonicity, model sizes); MS_E_INVALID on any violation. */
+ms_status ms_query_sizes(const ms_batch_desc* desc, const ms_scene_desc* scenes, ms_sizes* out);
+
+/* Number of floats of one state buffer. */
+ms_status ms_state_floats(const ms_scene_desc* scenes, int32_t n_scenes, size_t* out);
+
+/* Create a batch on the current HIP device.  params_dev / scratch_dev /
+ * tape_dev must hold at least the sizes from ms_query_sizes (tape_dev may be
+ * null when ms_step_backward is never called).  Uploads the scene
+ * description synchronously on hip_stream.  Requires a gfx950 device. */
+ms_status ms_create_batch(const ms_batch_desc* desc, const ms_scene_desc* scenes, void* params_dev,
+                          void* scratch_dev, void* tape_dev, void* hip_stream, ms_batch** out);
+
+/* Destroy the host-side batch object and its graphs (no device frees). */
+ms_status ms_destroy_batch(ms_batch* b);
+
+/* Choose how ms_step runs (see MS_SCHED_*).  Drops captured graphs. */
+ms_status ms_set_schedule(ms_batch* b, const ms_schedule* sched);
+ms_status ms_get_schedule(const ms_batch* b, ms_schedule* out);
+
+/* Time the candidate schedules on the given state / controls (the state is
+ * not modified: a copy in tmp_state_dev is stepped) and keep the fastest.
+ * Synchronises the stream.  Writes the chosen schedule and its time. */
+ms_status ms_autotune(ms_batch* b, const void* state_dev, const float* controls_dev, void* tmp_state_dev,
+                      int32_t reps, void* hip_stream, ms_schedule* chosen, float* ms_per_step);
+
+/* One control step of every scene: state_out = T(state_in, controls).
+ * state_out may alias state_in.  controls_dev: float32 [S][16]. */
+ms_status ms_step(ms_batch* b, const void* state_in_dev, const float* controls_dev, void* state_out_dev,
+                  void* hip_stream);
+
+/* Vector-Jacobian product of exactly one ms_step (recomputed internally):
+ * given dL/dstate_out, writes dL/dstate_in and dL/dcontrols.  The
+ * contact set and active set are those of the recomputed forward step.
+ * grad_state_in_dev may alias grad_state_out_dev. */
+ms_status ms_step_backward(ms_batch* b, const void* state_in_dev, const float* controls_dev,
+                           const void* grad_state_out_dev, void* grad_state_in_dev, float* grad_controls_dev,
+                           void* hip_stream);
+
+/* Typed device views into a state buffer (no copy, no device work). */
+ms_status ms_get_state(const ms_batch* b, const void* state_dev, ms_state_view* out);
+
+/* Copy scene s of src_dev into state_dev wherever scene_mask_dev[s] != 0
+ * (mask null: every scene). */
+ms_status ms_set_state(ms_batch* b, void* state_dev, const void* src_dev, const uint8_t* scene_mask_dev,
+                       void* hip_stream);
+
+/* Synchronise and read the per-scene status words of the last step
+ * (bits MS_ST_*) into status_host[S].  Returns MS_E_NUMERIC if any scene
+ * has MS_ST_NONFINITE or MS_ST_DEGENERATE set, MS_OK otherwise. */
+ms_status ms_scene_status(const ms_batch* b, uint32_t* status_host);
+
+/* Diagnostics of the last ms_step (synchronises): per scene and substep the
+ * number of contacts, the number of robot-owned contacts and the 64-bit sum
+ * of mixed contact keys (owner key << 32 | target key, mixed by the
+ * SplitMix64 finaliser), written as uint32 [S][n_substeps][4]:
+ * count, robot count, key-sum low, key-sum high.  Enabled by ms_enable_debug. */
+ms_status ms_enable_debug(ms_batch* b, int32_t on);
+ms_status ms_debug_contacts(const ms_batch* b, uint32_t* out_host);
+
+/* Per-phase shader-clock cycles of the last ms_step, summed over its
+ * substeps (synchronises): uint64 [S][8] for the phases drive+kinematics,
+ * contacts, dynamics, rows, level schedule, Gauss-Seidel, integration, and
+ * load/store.  Enabled by ms_enable_phase_profile (adds clock reads). */
+ms_status ms_enable_phase_profile(ms_batch* b, int32_t on);
+ms_status ms_phase_cycles(const ms_batch* b, unsigned long long* out_host);
+
+/* Message of the last failed call on this thread (empty if none). */
+const char* ms_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* MS_PHYS_H */

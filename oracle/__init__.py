@@ -74,6 +74,7 @@ def lib():
         vp = C.c_void_p
         for name, args in [("or_step", [vp, vp, vp, vp, vp, C.c_int, vp]),
                            ("or_vjp", [vp, vp, vp, vp, vp, vp, vp, C.c_int]),
+                           ("or_step_f32", [vp, vp, vp, vp, vp, C.c_int]),
                            ("or_jvp", [vp, vp, vp, vp, vp, vp, vp, C.c_int]),
                            ("or_flops", [vp, vp, vp, vp, vp]),
                            ("or_fk", [vp, C.c_int, vp, vp, vp, vp]),
@@ -164,6 +165,15 @@ class Oracle:
         if rc != 0:
             raise RuntimeError(f"or_step failed: {rc}")
         return (out, d) if dbg is not None else out
+
+    def step_f32(self, x, u):
+        """The same step with float intermediates (error floor of FP32 evaluation)."""
+        x = np.ascontiguousarray(x, np.float64)
+        u = np.ascontiguousarray(u, np.float64).reshape(self.S, 16)
+        out = np.empty(self.nsf, np.float64)
+        if lib().or_step_f32(C.byref(self.sc), C.byref(self.params), _ptr(x), _ptr(u), _ptr(out), self.threads):
+            raise RuntimeError("or_step_f32 failed")
+        return out
 
     def rollout(self, x0, controls, debug=False):
         xs = [np.asarray(x0, np.float64)]

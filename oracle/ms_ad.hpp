@@ -149,5 +149,9 @@ inline cdouble Sin(const cdouble& a) { ++g_flops; return cdouble(std::sin(a.v));
 inline cdouble Cos(const cdouble& a) { ++g_flops; return cdouble(std::cos(a.v)); }
 
 inline double Sqrt(double a) { return std::sqrt(a); }
+inline double val(float x) { return x; }
+inline float Sqrt(float a) { return std::sqrt(a); }
+inline float Sin(float a) { return std::sin(a); }
+inline float Cos(float a) { return std::cos(a); }
 inline double Sin(double a) { return std::sin(a); }
 inline double Cos(double a) { return std::cos(a); }

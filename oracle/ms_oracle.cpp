@@ -1096,6 +1096,29 @@ int or_step(const or_scene* sc, const or_params* pr, const double* x_in, const d
   return 0;
 }
 
+// The same step evaluated in single precision (every stored intermediate is a
+// float): an estimate of the error floor of any FP32 evaluation of the step.
+int or_step_f32(const or_scene* sc, const or_params* pr, const double* x_in, const double* u, double* x_out,
+                int threads) {
+  if (!sc || !pr || !x_in || !u || !x_out) return -1;
+  std::vector<ArtModel> robots = load_models(sc);
+  Layout L = layout_of(sc);
+  const int S = sc->n_scenes;
+  std::vector<double> xin(x_in, x_in + (size_t)S * 2 * ND + (size_t)L.NF * 16 + (size_t)L.NA * 4);
+  parallel_scenes(S, threads, [&](int s) {
+    SceneC c;
+    load_scene(sc, robots, s, c);
+    StateS<float> st;
+    gather(sc, L, s, xin.data(), st, [](size_t, double v) { return (float)v; });
+    float us[ND];
+    for (int j = 0; j < ND; ++j) us[j] = (float)u[(size_t)s * ND + j];
+    uint32_t status = 0;
+    for (int k = 0; k < pr->n_sub; ++k) substep<float>(c, *pr, st, us, k, status, nullptr, s, pr->n_sub);
+    scatter(sc, L, s, st, [&](size_t i, float v) { x_out[i] = v; });
+  });
+  return 0;
+}
+
 int or_vjp(const or_scene* sc, const or_params* pr, const double* x_in, const double* u, const double* gx_out,
            double* gx_in, double* gu, int threads) {
   if (!sc || !pr || !x_in || !u || !gx_out || !gx_in || !gu) return -1;

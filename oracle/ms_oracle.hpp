@@ -97,6 +97,10 @@ typedef struct {
 int or_step(const or_scene* sc, const or_params* pr, const double* x_in, const double* u,
             double* x_out, int threads, or_debug* dbg);
 
+// The same control step evaluated with float intermediates (FP32 error floor).
+int or_step_f32(const or_scene* sc, const or_params* pr, const double* x_in, const double* u,
+                double* x_out, int threads);
+
 // Vector-Jacobian product of one control step: given gx_out = dL/dx_out,
 // returns dL/dx_in (gx_in) and dL/du (gu), by reverse-mode differentiation of
 // exactly the arithmetic of or_step.

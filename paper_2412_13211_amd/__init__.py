@@ -1,0 +1,297 @@
+"""Batched rigid-body physics step on MI355X (gfx950) -- Python binding.
+
+Argument marshalling over the C ABI of ``include/ms_phys.h`` (libms_phys.so,
+built in-tree by ``_build.py``).  Every step of the physics runs in the HIP
+kernels; PyTorch only provides device memory and streams.  There is no CPU
+fallback: if the library cannot be loaded the import of :func:`lib` raises.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libms_phys.so")
+
+MS_OK = 0
+MS_CTRL_TORQUE, MS_CTRL_PD, MS_CTRL_TORQUE_HOLD = 0, 1, 2
+MS_SCHED_PERSISTENT = 1
+MS_SCHED_GRAPH = 2
+MS_SCHED_PER_SUBSTEP = 4
+MS_SCHED_STAGE_STATIC = 8
+MS_SCHED_CULL = 16
+MS_ST_NONFINITE, MS_ST_OVERFLOW, MS_ST_DEGENERATE, MS_ST_ROBOT_OVERFLOW = 1, 2, 4, 8
+
+EXPORTS = ["ms_query_sizes", "ms_state_floats", "ms_create_batch", "ms_destroy_batch", "ms_set_schedule",
+           "ms_get_schedule", "ms_autotune", "ms_step", "ms_step_backward", "ms_get_state", "ms_set_state",
+           "ms_scene_status", "ms_enable_debug", "ms_debug_contacts", "ms_enable_phase_profile", "ms_phase_cycles",
+           "ms_last_error"]
+PHASES = ["drive+kinematics", "contacts", "dynamics", "rows", "levels", "pgs", "integrate", "load/store"]
+
+
+class MsError(RuntimeError):
+    pass
+
+
+class BatchDesc(C.Structure):
+    _fields_ = [("n_scenes", C.c_int32), ("n_substeps", C.c_int32), ("pgs_iters", C.c_int32),
+                ("control_mode", C.c_int32), ("contact_cap", C.c_int32), ("robot_contact_cap", C.c_int32),
+                ("h", C.c_float), ("mu", C.c_float), ("baumgarte", C.c_float), ("margin", C.c_float),
+                ("gravity", C.c_float * 3)]
+
+
+SCENE_FIELDS = ["model_nb", "model_parent", "model_jtype", "model_axis", "model_xt_rot", "model_xt_pos",
+                "model_mass", "model_com", "model_inertia", "model_kp", "model_kd", "model_veldof",
+                "model_armature", "model_damping", "model_nsph", "model_sph_body", "model_sph", "model_sph_flags",
+                "scene_model", "free_off", "static_off", "plane_off", "aux_off", "scene_hold", "free_type",
+                "free_size", "free_mass", "free_inertia", "static_box", "plane", "aux_type", "aux_rot", "aux_pos",
+                "aux_axis", "aux_box", "aux_mass", "aux_inertia", "aux_limit"]
+
+
+class SceneDesc(C.Structure):
+    _fields_ = [("n_models", C.c_int32)] + [(n, C.c_void_p) for n in SCENE_FIELDS]
+
+
+class Sizes(C.Structure):
+    _fields_ = [("params", C.c_size_t), ("state", C.c_size_t), ("scratch", C.c_size_t), ("tape", C.c_size_t),
+                ("lds", C.c_size_t)]
+
+
+class StateView(C.Structure):
+    _fields_ = [("q", C.c_void_p), ("qd", C.c_void_p), ("free_body", C.c_void_p), ("aux", C.c_void_p),
+                ("free_off_host", C.c_void_p), ("aux_off_host", C.c_void_p), ("n_scenes", C.c_int32),
+                ("n_free", C.c_int32), ("n_aux", C.c_int32)]
+
+
+class Schedule(C.Structure):
+    _fields_ = [("flags", C.c_int32), ("grid", C.c_int32)]
+
+
+_lib = None
+
+
+def lib():
+    """Load libms_phys.so (building it first only if it does not exist)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            from . import _build
+            _build.build(force=False)
+        L = C.CDLL(LIB_PATH)
+        vp, i32 = C.c_void_p, C.c_int32
+        sig = {
+            "ms_query_sizes": [vp, vp, vp],
+            "ms_state_floats": [vp, i32, vp],
+            "ms_create_batch": [vp, vp, vp, vp, vp, vp, vp],
+            "ms_destroy_batch": [vp],
+            "ms_set_schedule": [vp, vp],
+            "ms_get_schedule": [vp, vp],
+            "ms_autotune": [vp, vp, vp, vp, i32, vp, vp, vp],
+            "ms_step": [vp, vp, vp, vp, vp],
+            "ms_step_backward": [vp, vp, vp, vp, vp, vp, vp],
+            "ms_get_state": [vp, vp, vp],
+            "ms_set_state": [vp, vp, vp, vp, vp],
+            "ms_scene_status": [vp, vp],
+            "ms_enable_debug": [vp, i32],
+            "ms_debug_contacts": [vp, vp],
+            "ms_enable_phase_profile": [vp, i32],
+            "ms_phase_cycles": [vp, vp],
+        }
+        for name, args in sig.items():
+            f = getattr(L, name)
+            f.argtypes = args
+            f.restype = C.c_int32
+        L.ms_last_error.argtypes = []
+        L.ms_last_error.restype = C.c_char_p
+        _lib = L
+    return _lib
+
+
+def _check(rc, what):
+    if rc != MS_OK:
+        msg = lib().ms_last_error().decode(errors="replace")
+        raise MsError(f"{what} failed ({rc}): {msg}")
+
+
+def _ptr_np(a):
+    return C.c_void_p(a.ctypes.data) if a is not None and a.size else C.c_void_p(0)
+
+
+def _ptr_t(t):
+    return C.c_void_p(t.data_ptr())
+
+
+def _stream(stream=None):
+    import torch
+    s = torch.cuda.current_stream() if stream is None else stream
+    return C.c_void_p(s.cuda_stream)
+
+
+def make_desc(batch, **over):
+    g = lambda k, d=None: over.get(k, getattr(batch, k, d))
+    d = BatchDesc()
+    d.n_scenes = int(batch.n_scenes)
+    d.n_substeps = int(g("n_sub"))
+    d.pgs_iters = int(g("pgs_iters"))
+    d.control_mode = int(g("control_mode"))
+    d.contact_cap = int(g("contact_cap"))
+    d.robot_contact_cap = int(over.get("robot_contact_cap", min(int(g("contact_cap")), 32)))
+    d.h = float(g("h"))
+    d.mu = float(g("mu"))
+    d.baumgarte = float(g("baumgarte"))
+    d.margin = float(g("margin"))
+    grav = g("gravity")
+    for i in range(3):
+        d.gravity[i] = float(grav[i])
+    return d
+
+
+def make_scene_desc(batch):
+    keep = {}
+    sd = SceneDesc()
+    sd.n_models = int(len(batch.model_nb))
+    for n in SCENE_FIELDS:
+        a = np.ascontiguousarray(getattr(batch, n))
+        a = a.astype(np.int32 if a.dtype.kind in "iu" else np.float32, copy=False)
+        keep[n] = a
+        setattr(sd, n, _ptr_np(a))
+    return sd, keep
+
+
+class MsBatch:
+    """One batch of scenes bound to the current HIP device.
+
+    ``batch`` is any object with the scene-description arrays (the scene
+    generator's SceneBatch); keyword overrides replace its physics parameters.
+    """
+
+    def __init__(self, batch, device=None, robot_contact_cap=None, **over):
+        import torch
+        self.torch = torch
+        self.device = torch.device("cuda", torch.cuda.current_device() if device is None else device)
+        if robot_contact_cap is not None:
+            over["robot_contact_cap"] = robot_contact_cap
+        self.desc = make_desc(batch, **over)
+        self.sdesc, self._keep = make_scene_desc(batch)
+        self.S = int(batch.n_scenes)
+        self.n_sub = int(self.desc.n_substeps)
+        sz = Sizes()
+        _check(lib().ms_query_sizes(C.byref(self.desc), C.byref(self.sdesc), C.byref(sz)), "ms_query_sizes")
+        self.sizes = sz
+        self.state_floats = sz.state // 4
+        with torch.cuda.device(self.device):
+            self.params = torch.empty(max(sz.params, 256), dtype=torch.uint8, device=self.device)
+            self.scratch = torch.empty(max(sz.scratch, 256), dtype=torch.uint8, device=self.device)
+            self.tape = torch.empty(max(sz.tape, 256), dtype=torch.uint8, device=self.device)
+            h = C.c_void_p()
+            _check(lib().ms_create_batch(C.byref(self.desc), C.byref(self.sdesc), _ptr_t(self.params),
+                                         _ptr_t(self.scratch), _ptr_t(self.tape), _stream(), C.byref(h)),
+                   "ms_create_batch")
+        self.h = h
+        self.n_free = int(batch.free_off[-1])
+        self.n_aux = int(batch.aux_off[-1])
+
+    def close(self):
+        if getattr(self, "h", None):
+            lib().ms_destroy_batch(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    # ------------------------------------------------------------------
+    def new_state(self, x=None):
+        t = self.torch.zeros(self.state_floats, dtype=self.torch.float32, device=self.device)
+        if x is not None:
+            t.copy_(self.torch.as_tensor(np.asarray(x, np.float32)))
+        return t
+
+    def _check_state(self, x, name):
+        t = self.torch
+        if not (isinstance(x, t.Tensor) and x.is_cuda and x.dtype == t.float32 and x.is_contiguous()
+                and x.numel() == self.state_floats):
+            raise MsError(f"{name}: expected a contiguous float32 device tensor of {self.state_floats} floats")
+
+    def _check_controls(self, u):
+        t = self.torch
+        if not (isinstance(u, t.Tensor) and u.is_cuda and u.dtype == t.float32 and u.is_contiguous()
+                and u.numel() == self.S * 16):
+            raise MsError(f"controls: expected a contiguous float32 device tensor [{self.S}, 16]")
+
+    def step(self, x, u, out=None, stream=None):
+        """One control step: returns ``out`` (new tensor unless given; may be ``x``)."""
+        self._check_state(x, "state_in")
+        self._check_controls(u)
+        if out is None:
+            out = self.torch.empty_like(x)
+        self._check_state(out, "state_out")
+        _check(lib().ms_step(self.h, _ptr_t(x), _ptr_t(u), _ptr_t(out), _stream(stream)), "ms_step")
+        return out
+
+    def step_backward(self, x, u, gx_out, gx_in=None, gu=None, stream=None):
+        self._check_state(x, "state_in")
+        self._check_controls(u)
+        self._check_state(gx_out, "grad_state_out")
+        if gx_in is None:
+            gx_in = self.torch.empty_like(x)
+        if gu is None:
+            gu = self.torch.empty_like(u)
+        _check(lib().ms_step_backward(self.h, _ptr_t(x), _ptr_t(u), _ptr_t(gx_out), _ptr_t(gx_in), _ptr_t(gu),
+                                      _stream(stream)), "ms_step_backward")
+        return gx_in, gu
+
+    def set_schedule(self, flags, grid=0):
+        s = Schedule(flags, grid)
+        _check(lib().ms_set_schedule(self.h, C.byref(s)), "ms_set_schedule")
+
+    def get_schedule(self):
+        s = Schedule()
+        _check(lib().ms_get_schedule(self.h, C.byref(s)), "ms_get_schedule")
+        return s.flags, s.grid
+
+    def autotune(self, x, u, reps=5, stream=None):
+        tmp = self.torch.empty_like(x)
+        s = Schedule()
+        ms = C.c_float()
+        _check(lib().ms_autotune(self.h, _ptr_t(x), _ptr_t(u), _ptr_t(tmp), reps, _stream(stream), C.byref(s),
+                                 C.byref(ms)), "ms_autotune")
+        return (s.flags, s.grid), ms.value
+
+    def status(self):
+        out = np.zeros(self.S, np.uint32)
+        rc = lib().ms_scene_status(self.h, _ptr_np(out))
+        if rc not in (MS_OK, -5):
+            _check(rc, "ms_scene_status")
+        return out
+
+    def enable_debug(self, on=True):
+        _check(lib().ms_enable_debug(self.h, 1 if on else 0), "ms_enable_debug")
+
+    def debug_contacts(self):
+        out = np.zeros((self.S, self.n_sub, 4), np.uint32)
+        _check(lib().ms_debug_contacts(self.h, _ptr_np(out)), "ms_debug_contacts")
+        return out
+
+    def enable_phase_profile(self, on=True):
+        _check(lib().ms_enable_phase_profile(self.h, 1 if on else 0), "ms_enable_phase_profile")
+
+    def phase_cycles(self):
+        out = np.zeros((self.S, 8), np.uint64)
+        _check(lib().ms_phase_cycles(self.h, _ptr_np(out)), "ms_phase_cycles")
+        return out
+
+    def set_state(self, x, src, mask=None, stream=None):
+        m = C.c_void_p(0) if mask is None else _ptr_t(mask)
+        _check(lib().ms_set_state(self.h, _ptr_t(x), _ptr_t(src), m, _stream(stream)), "ms_set_state")
+
+    def views(self, x):
+        """Typed views of a state tensor: q, qd [S,16], free [NF,16], aux [NA,4]."""
+        S, NF, NA = self.S, self.n_free, self.n_aux
+        return {"q": x[: 16 * S].view(S, 16), "qd": x[16 * S: 32 * S].view(S, 16),
+                "free": x[32 * S: 32 * S + 16 * NF].view(NF, 16),
+                "aux": x[32 * S + 16 * NF: 32 * S + 16 * NF + 4 * NA].view(NA, 4)}

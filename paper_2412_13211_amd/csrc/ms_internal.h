@@ -1,0 +1,135 @@
+// ms_internal.h -- device-side data layout of the batched physics step (gfx950).
+//
+// The scene description is packed once into one device buffer ("params"):
+//   [DModel x M][DScene x S][DFree x NF][static boxes 6 floats x NS]
+//   [planes float4 x NP][DAux x NA][scene order int x S]
+// Every scene is processed by one 64-lane wavefront (one workgroup); all of
+// a scene's working data lives in that workgroup's LDS for the whole control
+// step, so HBM traffic is the state in/out, the controls and the scene
+// description.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace msk {
+
+constexpr int ND = 16;        // padded robot DoFs (one DoF per body)
+constexpr int SPH = 128;      // max robot collision spheres
+constexpr int WAVE = 64;
+constexpr int AMAX = 4;       // max door / drawer joints per scene
+constexpr int PMAX = 8;       // max planes per scene
+constexpr int FMAXL = 58;     // max free bodies per scene (node ids 1 + AMAX + f < 63)
+
+struct DModel {
+  int nb, nsph, pad0, pad1;
+  int parent[ND];
+  int jtype[ND];
+  int veldof[ND];
+  int anc[ND];          // bit k set: body k is body i or one of its ancestors
+  float axis[ND][3];
+  float xtR[ND][9];
+  float xtp[ND][3];
+  float mass[ND];
+  float com[ND][3];
+  float Ic[ND][6];      // xx yy zz xy xz yz about the COM, body axes
+  float kp[ND], kd[ND], arm[ND], damp[ND];
+  float4 sph[SPH];      // centre (body frame), radius
+  int sph_body[SPH];
+  int sph_flags[SPH];
+};
+
+struct DScene {
+  int model, f0, nf, s0, ns, p0, np, a0, na, nown, cost, pad;
+  float hold[ND];
+};
+
+struct DFree {
+  int type;            // 0 box, 1 sphere
+  float half[3];       // half extents or (radius, 0, 0)
+  float mass;
+  float Ib[3];         // principal moments
+};
+
+struct DAux {
+  int type;            // 0 revolute, 1 prismatic
+  float R0[9];         // joint frame rotation (world)
+  float p0[3];
+  float axis[3];
+  float bc[3];         // box centre in the moving frame
+  float bh[3];         // half extents
+  float mass;
+  float Ib[3];
+  float lo, hi;
+  int has_limit;
+  int pad;
+};
+
+// Offsets (in floats) of the regions of one scene's LDS block.
+struct LdsLayout {
+  int fmax, smax, ccap, rcap, owners;
+  int robot, sph, fr, aux, stat, plane, own, con, rows, lvl, total;
+};
+
+__host__ __device__ inline int lds_align4(int x) { return (x + 3) & ~3; }
+
+// Robot block: q qd tau arm u vR [6*16]; R[16*9] p[16*3] s[16*6]; ABA: IA[16*36]
+// pA[16*6] c[16*6] U[16*6] D[16] uu[16] qdd[16]; Minv[16*16]; tables T[16*16] S2[16*16]
+constexpr int ROBOT_FLOATS = 6 * ND + ND * 9 + ND * 3 + ND * 6 + ND * 36 + ND * 6 * 3 + ND * 3 + ND * ND * 3;
+constexpr int FREE_FLOATS = 40;     // per free body
+constexpr int AUX_FLOATS = 40;      // per aux joint
+constexpr int CON_FLOATS = 16;      // per contact
+constexpr int ROW_FLOATS = 6 * ND;  // per robot contact: J[3][16], w[3][16]
+
+__host__ __device__ inline LdsLayout make_layout(int fmax, int smax, int ccap, int rcap, int stage_static) {
+  LdsLayout L;
+  L.fmax = fmax;
+  L.smax = stage_static ? smax : 0;
+  L.ccap = ccap;
+  L.rcap = rcap;
+  L.owners = fmax * 8;
+  int o = 0;
+  L.robot = o; o += lds_align4(ROBOT_FLOATS);
+  L.sph = o;   o += SPH * 4;
+  L.fr = o;    o += lds_align4(fmax * FREE_FLOATS);
+  L.aux = o;   o += AMAX * AUX_FLOATS;
+  L.stat = o;  o += lds_align4(L.smax * 6);
+  L.plane = o; o += PMAX * 4;
+  L.own = o;   o += lds_align4((L.owners + 1) / 2);        // uint16 owner table
+  L.con = o;   o += lds_align4(ccap * CON_FLOATS);
+  L.rows = o;  o += lds_align4(rcap * ROW_FLOATS);
+  L.lvl = o;   o += lds_align4(3 * ccap + 4 + (ccap + 1) / 2);  // level, level offsets, robot row per level, order
+  L.total = o;
+  return L;
+}
+
+struct KArgs {
+  const DModel* models;
+  const DScene* scenes;
+  const DFree* free;
+  const float* statics;
+  const float4* planes;
+  const DAux* aux;
+  const int* order;        // scene processing order (cost-sorted)
+  const float* x_in;
+  float* x_out;
+  const float* u;
+  uint32_t* status;        // [S]
+  uint32_t* debug;         // [S][n_sub][4] or null
+  unsigned long long* phase_cycles;  // [S][8] shader-clock cycles per phase, or null
+  int* queue;              // work counter (persistent schedule)
+  int S, NF, NA;
+  int n_sub, sub0, n_sub_total;  // substeps in this launch, index of the first, substeps per control step
+  int K, mode, ccap, rcap;
+  int persistent, stage_static, cull;
+  float h, mu, beta, margin;
+  float g[3];
+  LdsLayout L;
+};
+
+void launch_step(const KArgs& a, int grid, size_t lds_bytes, hipStream_t st);
+void launch_reset_queue(int* q, hipStream_t st);
+void launch_masked_copy(float* dst, const float* src, const uint8_t* mask, int S, int NF, int NA,
+                        const int* free_off, const int* aux_off, hipStream_t st);
+const void* step_kernel_ptr();
+
+}  // namespace msk

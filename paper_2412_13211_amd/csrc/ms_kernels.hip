@@ -1,0 +1,1409 @@
+// ms_kernels.hip -- fused control-step kernel of the batched rigid-body step (gfx950).
+//
+// One 64-lane wavefront (one workgroup) advances one scene through all
+// substeps of a control step with the scene resident in LDS.  Per substep:
+//   drive -> forward kinematics (pointer jumping over the tree, lane per body)
+//   -> contact generation (lanes over (owner sphere, target) pairs in the
+//      canonical order, compacted with ballots so the list stays ordered)
+//   -> articulated-body algorithm in world coordinates (outward pass lane per
+//      body, inward pass serial, outward pass and the 16 columns of the
+//      inverse mass matrix as parallel triangular solves, one lane each)
+//   -> contact rows (lane per contact; robot rows lane per DoF and direction)
+//   -> level schedule of the canonical row order (lane per dynamic node)
+//   -> projected Gauss-Seidel: levels in order, the level's robot row with a
+//      16-lane shuffle reduction, the level's other rows one lane each
+//   -> semi-implicit Euler.
+// The mathematics follows the textbook definitions cited in the C header; no
+// code is shared with the CPU oracle.
+#include "ms_internal.h"
+
+namespace msk {
+
+// ------------------------------------------------------------ small helpers
+struct f3 {
+  float x, y, z;
+};
+__device__ __forceinline__ f3 mk3(float a, float b, float c) { return {a, b, c}; }
+__device__ __forceinline__ f3 operator+(f3 a, f3 b) { return {a.x + b.x, a.y + b.y, a.z + b.z}; }
+__device__ __forceinline__ f3 operator-(f3 a, f3 b) { return {a.x - b.x, a.y - b.y, a.z - b.z}; }
+__device__ __forceinline__ f3 operator*(f3 a, float s) { return {a.x * s, a.y * s, a.z * s}; }
+__device__ __forceinline__ float dot(f3 a, f3 b) { return a.x * b.x + a.y * b.y + a.z * b.z; }
+__device__ __forceinline__ f3 cross(f3 a, f3 b) {
+  return {a.y * b.z - a.z * b.y, a.z * b.x - a.x * b.z, a.x * b.y - a.y * b.x};
+}
+// row-major 3x3
+__device__ __forceinline__ f3 mv(const float* R, f3 v) {
+  return {R[0] * v.x + R[1] * v.y + R[2] * v.z, R[3] * v.x + R[4] * v.y + R[5] * v.z,
+          R[6] * v.x + R[7] * v.y + R[8] * v.z};
+}
+__device__ __forceinline__ f3 mtv(const float* R, f3 v) {
+  return {R[0] * v.x + R[3] * v.y + R[6] * v.z, R[1] * v.x + R[4] * v.y + R[7] * v.z,
+          R[2] * v.x + R[5] * v.y + R[8] * v.z};
+}
+__device__ __forceinline__ void mm(const float* A, const float* B, float* C) {
+#pragma unroll
+  for (int i = 0; i < 3; ++i)
+#pragma unroll
+    for (int j = 0; j < 3; ++j) C[i * 3 + j] = A[i * 3] * B[j] + A[i * 3 + 1] * B[3 + j] + A[i * 3 + 2] * B[6 + j];
+}
+__device__ __forceinline__ void quat_to_R(float w, float x, float y, float z, float* R) {
+  R[0] = 1.f - 2.f * (y * y + z * z);
+  R[1] = 2.f * (x * y - w * z);
+  R[2] = 2.f * (x * z + w * y);
+  R[3] = 2.f * (x * y + w * z);
+  R[4] = 1.f - 2.f * (x * x + z * z);
+  R[5] = 2.f * (y * z - w * x);
+  R[6] = 2.f * (x * z - w * y);
+  R[7] = 2.f * (y * z + w * x);
+  R[8] = 1.f - 2.f * (x * x + y * y);
+}
+// rotation by angle th about unit axis k: I + sin K + (1 - cos) K^2
+__device__ __forceinline__ void rot_axis(f3 k, float th, float* R) {
+  float s, c;
+  sincosf(th, &s, &c);
+  float oc = 1.f - c;
+  R[0] = 1.f - oc * (k.y * k.y + k.z * k.z);
+  R[1] = -s * k.z + oc * k.x * k.y;
+  R[2] = s * k.y + oc * k.x * k.z;
+  R[3] = s * k.z + oc * k.x * k.y;
+  R[4] = 1.f - oc * (k.x * k.x + k.z * k.z);
+  R[5] = -s * k.x + oc * k.y * k.z;
+  R[6] = -s * k.y + oc * k.x * k.z;
+  R[7] = s * k.x + oc * k.y * k.z;
+  R[8] = 1.f - oc * (k.x * k.x + k.y * k.y);
+}
+// Duff et al. 2017 orthonormal basis completing unit n
+__device__ __forceinline__ void onb(f3 n, f3& t1, f3& t2) {
+  float sg = copysignf(1.f, n.z);
+  float a = -1.f / (sg + n.z);
+  float b = n.x * n.y * a;
+  t1 = {1.f + sg * n.x * n.x * a, sg * b, -sg * n.x};
+  t2 = {b, sg + n.y * n.y * a, -n.y};
+}
+__device__ __forceinline__ uint64_t mix64(uint64_t z) {
+  z += 0x9E3779B97F4A7C15ull;
+  z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+  z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+  return z ^ (z >> 31);
+}
+__device__ __forceinline__ int lane_id() { return threadIdx.x; }
+__device__ __forceinline__ int prefix_below(uint64_t m) {
+  return __builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0));
+}
+__device__ __forceinline__ float bcast(float v, int src) { return __shfl(v, src, WAVE); }
+__device__ __forceinline__ int bcasti(int v, int src) { return __shfl(v, src, WAVE); }
+// sum over aligned groups of 16 lanes (result in every lane of the group)
+__device__ __forceinline__ float sum16(float v) {
+  v += __shfl_xor(v, 8, WAVE);
+  v += __shfl_xor(v, 4, WAVE);
+  v += __shfl_xor(v, 2, WAVE);
+  v += __shfl_xor(v, 1, WAVE);
+  return v;
+}
+__device__ __forceinline__ void wave_sync() { __syncthreads(); }
+
+// spatial 6-vectors [angular; linear] in world coordinates
+struct s6 {
+  float v[6];
+};
+__device__ __forceinline__ void crm(const float* v, const float* m, float* out) {  // v x m
+  f3 w = mk3(v[0], v[1], v[2]), vo = mk3(v[3], v[4], v[5]), mw = mk3(m[0], m[1], m[2]), ml = mk3(m[3], m[4], m[5]);
+  f3 a = cross(w, mw), b = cross(w, ml) + cross(vo, mw);
+  out[0] = a.x; out[1] = a.y; out[2] = a.z; out[3] = b.x; out[4] = b.y; out[5] = b.z;
+}
+__device__ __forceinline__ void crf(const float* v, const float* f, float* out) {  // v x* f
+  f3 w = mk3(v[0], v[1], v[2]), vo = mk3(v[3], v[4], v[5]), n = mk3(f[0], f[1], f[2]), fl = mk3(f[3], f[4], f[5]);
+  f3 a = cross(w, n) + cross(vo, fl), b = cross(w, fl);
+  out[0] = a.x; out[1] = a.y; out[2] = a.z; out[3] = b.x; out[4] = b.y; out[5] = b.z;
+}
+
+// ------------------------------------------------------------ LDS views
+struct Robot {
+  float *q, *qd, *tau, *arm, *u, *vst;  // [16] each (vst: unconstrained velocity)
+  float *R, *p, *s;                     // [16][9], [16][3], [16][6]
+  float *IA, *pA, *cc, *U, *D, *uu, *qdd;
+  float *Minv, *T, *S2;                 // [16][16]
+};
+__device__ __forceinline__ Robot robot_view(float* base) {
+  Robot r;
+  float* o = base;
+  r.q = o; o += ND;
+  r.qd = o; o += ND;
+  r.tau = o; o += ND;
+  r.arm = o; o += ND;
+  r.u = o; o += ND;
+  r.vst = o; o += ND;
+  r.R = o; o += ND * 9;
+  r.p = o; o += ND * 3;
+  r.s = o; o += ND * 6;
+  r.IA = o; o += ND * 36;
+  r.pA = o; o += ND * 6;
+  r.cc = o; o += ND * 6;
+  r.U = o; o += ND * 6;
+  r.D = o; o += ND;
+  r.uu = o; o += ND;
+  r.qdd = o; o += ND;
+  r.Minv = o; o += ND * ND;
+  r.T = o; o += ND * ND;
+  r.S2 = o; o += ND * ND;
+  return r;
+}
+// free-body fields (structure of arrays, stride fmax)
+enum FF {
+  F_X = 0, F_Q = 3, F_V = 7, F_W = 10, F_R = 13, F_II = 22, F_IM = 31, F_TYPE = 32, F_H = 33, F_IB = 36, F_N = 39
+};
+// aux fields (stride AMAX)
+enum AF {
+  A_Q = 0, A_QD = 1, A_V = 2, A_R = 3, A_P = 12, A_AX = 15, A_BC = 18, A_IM = 21, A_BH = 22, A_LO = 25, A_HI = 26,
+  A_TYPE = 27, A_LIM = 28, A_M = 29, A_N = 30
+};
+// contact fields (structure of arrays, stride ccap)
+enum CF { C_INFO = 0, C_N = 1, C_P = 4, C_IW = 7, C_BIAS = 10, C_LAM = 11, C_PHI = 14, C_LVL = 15 };
+
+// side kinds packed in a contact's info word: A in bits 0..15, B in 16..31,
+// each (kind << 8) | index
+enum { K_STATIC = 0, K_ROBOT = 1, K_FREE = 2, K_AUX = 3, K_LIMIT = 4 };
+__device__ __forceinline__ int side_kind(int s) { return (s >> 8) & 0xff; }
+__device__ __forceinline__ int side_idx(int s) { return s & 0xff; }
+__device__ __forceinline__ int node_of(int s) {
+  int k = side_kind(s);
+  if (k == K_ROBOT) return 0;
+  if (k == K_AUX || k == K_LIMIT) return 1 + side_idx(s);
+  if (k == K_FREE) return 1 + AMAX + side_idx(s);
+  return 63;  // static: a lane whose level never changes
+}
+
+// Box test: sphere (c, r) against an oriented box (centre bc, world-from-box
+// R (null = axis aligned), half extents e).  Returns phi and the normal n
+// pointing from the box to the sphere.
+__device__ __forceinline__ float box_test(f3 c, float r, f3 bc, const float* R, f3 e, f3& n) {
+  f3 d = c - bc;
+  f3 y = R ? mtv(R, d) : d;
+  bool out = fabsf(y.x) > e.x || fabsf(y.y) > e.y || fabsf(y.z) > e.z;
+  float phi;
+  f3 nl;
+  if (out) {
+    f3 k = mk3(fminf(fmaxf(y.x, -e.x), e.x), fminf(fmaxf(y.y, -e.y), e.y), fminf(fmaxf(y.z, -e.z), e.z));
+    f3 dd = y - k;
+    float dist = sqrtf(dot(dd, dd));
+    phi = dist - r;
+    float inv = dist > 0.f ? 1.f / dist : 0.f;
+    nl = dd * inv;
+    if (!(dist > 0.f)) nl = mk3(0.f, 0.f, 1.f);
+  } else {
+    float gx = e.x - fabsf(y.x), gy = e.y - fabsf(y.y), gz = e.z - fabsf(y.z);
+    int best = 0;
+    float bv = gx;
+    if (gy < bv) { bv = gy; best = 1; }
+    if (gz < bv) { bv = gz; best = 2; }
+    float yc = best == 0 ? y.x : (best == 1 ? y.y : y.z);
+    float sg = yc >= 0.f ? 1.f : -1.f;
+    phi = -bv - r;
+    nl = mk3(best == 0 ? sg : 0.f, best == 1 ? sg : 0.f, best == 2 ? sg : 0.f);
+  }
+  n = R ? mv(R, nl) : nl;
+  return phi;
+}
+
+// ============================================================ the kernel
+struct Scene {
+  const DModel* M;
+  const float* hold;  // [16] hold targets (global)
+  int s, nb, nsph, nf, ns, np, na, nfo, f0, s0, p0, a0;
+};
+
+__device__ void load_scene(const KArgs& a, const Scene& S, float* L, const Robot& rb) {
+  const int lane = lane_id();
+  const LdsLayout& Y = a.L;
+  if (lane < ND) {
+    rb.q[lane] = a.x_in[(size_t)S.s * ND + lane];
+    rb.qd[lane] = a.x_in[(size_t)a.S * ND + (size_t)S.s * ND + lane];
+    rb.u[lane] = a.u[(size_t)S.s * ND + lane];
+  }
+  float* F = L + Y.fr;
+  const int fm = Y.fmax;
+  for (int f = lane; f < S.nf; f += WAVE) {
+    const float* xs = a.x_in + (size_t)a.S * 2 * ND + (size_t)(S.f0 + f) * 16;
+    float4 x0 = *reinterpret_cast<const float4*>(xs);
+    float4 x1 = *reinterpret_cast<const float4*>(xs + 4);
+    float4 x2 = *reinterpret_cast<const float4*>(xs + 8);
+    float4 x3 = *reinterpret_cast<const float4*>(xs + 12);
+    F[(F_X + 0) * fm + f] = x0.x; F[(F_X + 1) * fm + f] = x0.y; F[(F_X + 2) * fm + f] = x0.z;
+    F[(F_Q + 0) * fm + f] = x1.x; F[(F_Q + 1) * fm + f] = x1.y; F[(F_Q + 2) * fm + f] = x1.z;
+    F[(F_Q + 3) * fm + f] = x1.w;
+    F[(F_V + 0) * fm + f] = x2.x; F[(F_V + 1) * fm + f] = x2.y; F[(F_V + 2) * fm + f] = x2.z;
+    F[(F_W + 0) * fm + f] = x3.x; F[(F_W + 1) * fm + f] = x3.y; F[(F_W + 2) * fm + f] = x3.z;
+    DFree d = a.free[S.f0 + f];
+    F[F_IM * fm + f] = 1.f / d.mass;
+    F[F_TYPE * fm + f] = (float)d.type;
+    F[(F_H + 0) * fm + f] = d.half[0]; F[(F_H + 1) * fm + f] = d.half[1]; F[(F_H + 2) * fm + f] = d.half[2];
+    F[(F_IB + 0) * fm + f] = d.Ib[0]; F[(F_IB + 1) * fm + f] = d.Ib[1]; F[(F_IB + 2) * fm + f] = d.Ib[2];
+  }
+  float* A = L + Y.aux;
+  if (lane < S.na) {
+    const float* xs = a.x_in + (size_t)a.S * 2 * ND + (size_t)a.NF * 16 + (size_t)(S.a0 + lane) * 4;
+    DAux d = a.aux[S.a0 + lane];
+    A[A_Q * AMAX + lane] = xs[0];
+    A[A_QD * AMAX + lane] = xs[1];
+    for (int t = 0; t < 3; ++t) {
+      A[(A_P + t) * AMAX + lane] = d.p0[t];
+      A[(A_BH + t) * AMAX + lane] = d.bh[t];
+    }
+    f3 ax = mv(d.R0, mk3(d.axis[0], d.axis[1], d.axis[2]));
+    A[(A_AX + 0) * AMAX + lane] = ax.x; A[(A_AX + 1) * AMAX + lane] = ax.y; A[(A_AX + 2) * AMAX + lane] = ax.z;
+    A[A_LO * AMAX + lane] = d.lo;
+    A[A_HI * AMAX + lane] = d.hi;
+    A[A_TYPE * AMAX + lane] = (float)d.type;
+    A[A_LIM * AMAX + lane] = (float)d.has_limit;
+  }
+  if (Y.smax > 0) {
+    float* St = L + Y.stat;
+    const float* src = a.statics + (size_t)S.s0 * 6;
+    for (int i = lane; i < S.ns * 6; i += WAVE) St[i] = src[i];
+  }
+  float* Pl = L + Y.plane;
+  if (lane < S.np) {
+    float4 pl = a.planes[S.p0 + lane];
+    Pl[lane * 4 + 0] = pl.x; Pl[lane * 4 + 1] = pl.y; Pl[lane * 4 + 2] = pl.z; Pl[lane * 4 + 3] = pl.w;
+  }
+  // owner table of free bodies: boxes own 8 vertices, spheres 1
+  uint16_t* own = reinterpret_cast<uint16_t*>(L + Y.own);
+  if (lane == 0) {
+    int o = 0;
+    for (int f = 0; f < S.nf; ++f) {
+      int cnt = a.free[S.f0 + f].type == 0 ? 8 : 1;
+      for (int k = 0; k < cnt; ++k) own[o++] = (uint16_t)((f << 3) | k);
+    }
+  }
+  wave_sync();
+}
+
+__device__ void store_scene(const KArgs& a, const Scene& S, float* L, const Robot& rb, uint32_t& status) {
+  const int lane = lane_id();
+  const LdsLayout& Y = a.L;
+  bool bad = false;
+  if (lane < ND) {
+    float q = rb.q[lane], qd = rb.qd[lane];
+    bad |= !isfinite(q) || !isfinite(qd);
+    a.x_out[(size_t)S.s * ND + lane] = q;
+    a.x_out[(size_t)a.S * ND + (size_t)S.s * ND + lane] = qd;
+  }
+  const float* F = L + Y.fr;
+  const int fm = Y.fmax;
+  for (int f = lane; f < S.nf; f += WAVE) {
+    float* xs = a.x_out + (size_t)a.S * 2 * ND + (size_t)(S.f0 + f) * 16;
+    float4 x0 = make_float4(F[(F_X + 0) * fm + f], F[(F_X + 1) * fm + f], F[(F_X + 2) * fm + f], 0.f);
+    float4 x1 = make_float4(F[(F_Q + 0) * fm + f], F[(F_Q + 1) * fm + f], F[(F_Q + 2) * fm + f],
+                            F[(F_Q + 3) * fm + f]);
+    float4 x2 = make_float4(F[(F_V + 0) * fm + f], F[(F_V + 1) * fm + f], F[(F_V + 2) * fm + f], 0.f);
+    float4 x3 = make_float4(F[(F_W + 0) * fm + f], F[(F_W + 1) * fm + f], F[(F_W + 2) * fm + f], 0.f);
+    bad |= !isfinite(x0.x + x0.y + x0.z + x1.x + x1.y + x1.z + x1.w + x2.x + x2.y + x2.z + x3.x + x3.y + x3.z);
+    *reinterpret_cast<float4*>(xs) = x0;
+    *reinterpret_cast<float4*>(xs + 4) = x1;
+    *reinterpret_cast<float4*>(xs + 8) = x2;
+    *reinterpret_cast<float4*>(xs + 12) = x3;
+  }
+  const float* A = L + Y.aux;
+  if (lane < S.na) {
+    float* xs = a.x_out + (size_t)a.S * 2 * ND + (size_t)a.NF * 16 + (size_t)(S.a0 + lane) * 4;
+    float q = A[A_Q * AMAX + lane], qd = A[A_QD * AMAX + lane];
+    bad |= !isfinite(q) || !isfinite(qd);
+    *reinterpret_cast<float4*>(xs) = make_float4(q, qd, 0.f, 0.f);
+  }
+  if (__ballot(bad)) status |= 1u;
+}
+
+// ---------------------------------------------------------------- phases
+__device__ void phase_drive(const KArgs& a, const Scene& S, const Robot& rb) {
+  const int j = lane_id();
+  if (j < S.nb) {
+    const DModel* M = S.M;
+    float q = rb.q[j], qd = rb.qd[j], u = rb.u[j], dmp = M->damp[j];
+    float tau, arm;
+    if (a.mode == 0) {
+      tau = u - dmp * qd;
+      arm = M->arm[j] + a.h * dmp;
+    } else {
+      int vd = M->veldof[j];
+      float kp = vd ? 0.f : M->kp[j], kd = M->kd[j];
+      float qt, vt, ff = 0.f;
+      if (a.mode == 1) {
+        qt = vd ? 0.f : u;
+        vt = vd ? u : 0.f;
+      } else {
+        qt = vd ? 0.f : S.hold[j];
+        vt = vd ? S.hold[j] : 0.f;
+        ff = u;
+      }
+      tau = ff + kp * (qt - q - a.h * qd) + kd * (vt - qd) - dmp * qd;
+      arm = M->arm[j] + a.h * (kd + dmp) + a.h * a.h * kp;
+    }
+    rb.tau[j] = tau;
+    rb.arm[j] = arm;
+  }
+}
+
+// world frames by pointer jumping over the tree; spheres; free and aux frames
+__device__ void phase_kinematics(const KArgs& a, const Scene& S, float* L, const Robot& rb) {
+  const int lane = lane_id();
+  const DModel* M = S.M;
+  const int nb = S.nb;
+  float Rw[9], pw[3];
+  int anc = -1;
+  if (lane < nb) {
+    f3 ax = mk3(M->axis[lane][0], M->axis[lane][1], M->axis[lane][2]);
+    const float* RT = M->xtR[lane];
+    float q = rb.q[lane];
+    if (M->jtype[lane] == 0) {
+      float RJ[9];
+      rot_axis(ax, q, RJ);
+      mm(RT, RJ, Rw);
+      pw[0] = M->xtp[lane][0]; pw[1] = M->xtp[lane][1]; pw[2] = M->xtp[lane][2];
+    } else {
+      for (int t = 0; t < 9; ++t) Rw[t] = RT[t];
+      f3 d = mv(RT, ax) * q;
+      pw[0] = M->xtp[lane][0] + d.x; pw[1] = M->xtp[lane][1] + d.y; pw[2] = M->xtp[lane][2] + d.z;
+    }
+    anc = M->parent[lane];
+  } else {
+    for (int t = 0; t < 9; ++t) Rw[t] = t % 4 == 0 ? 1.f : 0.f;
+    pw[0] = pw[1] = pw[2] = 0.f;
+  }
+  // W_i <- W_anc o W_i ; anc <- anc(anc), until every lane reaches the root
+  for (int round = 0; round < 5; ++round) {
+    if (!__ballot(anc >= 0)) break;
+    int src = anc >= 0 ? anc : lane;
+    float Ra[9], pa[3];
+    for (int t = 0; t < 9; ++t) Ra[t] = bcast(Rw[t], src);
+    for (int t = 0; t < 3; ++t) pa[t] = bcast(pw[t], src);
+    int aa = bcasti(anc, src);
+    if (anc >= 0) {
+      float Rn[9];
+      mm(Ra, Rw, Rn);
+      f3 pn = mv(Ra, mk3(pw[0], pw[1], pw[2]));
+      for (int t = 0; t < 9; ++t) Rw[t] = Rn[t];
+      pw[0] = pn.x + pa[0]; pw[1] = pn.y + pa[1]; pw[2] = pn.z + pa[2];
+      anc = aa;
+    }
+  }
+  if (lane < nb) {
+    for (int t = 0; t < 9; ++t) rb.R[lane * 9 + t] = Rw[t];
+    for (int t = 0; t < 3; ++t) rb.p[lane * 3 + t] = pw[t];
+    f3 ax = mv(Rw, mk3(M->axis[lane][0], M->axis[lane][1], M->axis[lane][2]));
+    float* s = rb.s + lane * 6;
+    // motion subspace referred to the body's own origin (on the joint axis)
+    if (M->jtype[lane] == 0) {
+      s[0] = ax.x; s[1] = ax.y; s[2] = ax.z; s[3] = 0.f; s[4] = 0.f; s[5] = 0.f;
+    } else {
+      s[0] = 0.f; s[1] = 0.f; s[2] = 0.f; s[3] = ax.x; s[4] = ax.y; s[5] = ax.z;
+    }
+  }
+  wave_sync();
+  // sphere centres
+  float* SW = L + a.L.sph;
+  for (int k = lane; k < S.nsph; k += WAVE) {
+    int b = M->sph_body[k];
+    float4 sp = M->sph[k];
+    f3 c = mv(rb.R + b * 9, mk3(sp.x, sp.y, sp.z)) + mk3(rb.p[b * 3], rb.p[b * 3 + 1], rb.p[b * 3 + 2]);
+    SW[k * 4 + 0] = c.x; SW[k * 4 + 1] = c.y; SW[k * 4 + 2] = c.z; SW[k * 4 + 3] = sp.w;
+  }
+  // free bodies: rotation and world inverse inertia
+  float* F = L + a.L.fr;
+  const int fm = a.L.fmax;
+  for (int f = lane; f < S.nf; f += WAVE) {
+    float R[9];
+    quat_to_R(F[(F_Q + 0) * fm + f], F[(F_Q + 1) * fm + f], F[(F_Q + 2) * fm + f], F[(F_Q + 3) * fm + f], R);
+    float ib[3] = {1.f / F[(F_IB + 0) * fm + f], 1.f / F[(F_IB + 1) * fm + f], 1.f / F[(F_IB + 2) * fm + f]};
+    for (int t = 0; t < 9; ++t) F[(F_R + t) * fm + f] = R[t];
+    for (int i = 0; i < 3; ++i)
+      for (int j = 0; j < 3; ++j)
+        F[(F_II + i * 3 + j) * fm + f] = R[i * 3] * ib[0] * R[j * 3] + R[i * 3 + 1] * ib[1] * R[j * 3 + 1] +
+                                          R[i * 3 + 2] * ib[2] * R[j * 3 + 2];
+  }
+  // aux joints: moving frame and world box centre
+  float* A = L + a.L.aux;
+  if (lane < S.na) {
+    DAux d = a.aux[S.a0 + lane];
+    float q = A[A_Q * AMAX + lane];
+    float R[9];
+    f3 p = mk3(d.p0[0], d.p0[1], d.p0[2]);
+    if (d.type == 0) {
+      float RJ[9];
+      rot_axis(mk3(d.axis[0], d.axis[1], d.axis[2]), q, RJ);
+      mm(d.R0, RJ, R);
+    } else {
+      for (int t = 0; t < 9; ++t) R[t] = d.R0[t];
+      p = p + mv(d.R0, mk3(d.axis[0], d.axis[1], d.axis[2])) * q;
+    }
+    f3 bc = mv(R, mk3(d.bc[0], d.bc[1], d.bc[2])) + p;
+    for (int t = 0; t < 9; ++t) A[(A_R + t) * AMAX + lane] = R[t];
+    A[(A_BC + 0) * AMAX + lane] = bc.x; A[(A_BC + 1) * AMAX + lane] = bc.y; A[(A_BC + 2) * AMAX + lane] = bc.z;
+    // generalized inertia about the joint axis: s^T I s (world frame)
+    f3 ax = mk3(A[(A_AX + 0) * AMAX + lane], A[(A_AX + 1) * AMAX + lane], A[(A_AX + 2) * AMAX + lane]);
+    float Mq;
+    if (d.type == 0) {
+      // I_c about the axis through the COM plus m * (distance of the COM from the axis)^2
+      f3 rc = bc - mk3(d.p0[0], d.p0[1], d.p0[2]);
+      f3 lx = mtv(R, ax);  // axis in box coordinates
+      float Ia = d.Ib[0] * lx.x * lx.x + d.Ib[1] * lx.y * lx.y + d.Ib[2] * lx.z * lx.z;
+      f3 perp = rc - ax * dot(rc, ax);
+      Mq = Ia + d.mass * dot(perp, perp);
+    } else {
+      Mq = d.mass;
+    }
+    A[A_M * AMAX + lane] = Mq;
+    A[A_IM * AMAX + lane] = 1.f / Mq;
+  }
+  wave_sync();
+}
+
+// Contact generation in canonical order: owners (robot spheres by index,
+// then free-body vertices / spheres by body and vertex), targets (planes,
+// furniture boxes, door / drawer boxes, free bodies by index).
+__device__ void phase_contacts(const KArgs& a, const Scene& S, float* L, int& NC, int& NR, int& NL,
+                               uint32_t& status, uint64_t& keysum) {
+  const int lane = lane_id();
+  const LdsLayout& Y = a.L;
+  const DModel* M = S.M;
+  float* C = L + Y.con;
+  const int cc = Y.ccap;
+  const float* SW = L + Y.sph;
+  const float* F = L + Y.fr;
+  const int fm = Y.fmax;
+  const float* A = L + Y.aux;
+  const float* Pl = L + Y.plane;
+  const uint16_t* own = reinterpret_cast<const uint16_t*>(L + Y.own);
+  const float* St = Y.smax > 0 ? (L + Y.stat) : (a.statics + (size_t)S.s0 * 6);
+
+  int n = 0;
+  // joint-limit rows of door / drawer joints come first in the canonical order
+  if (lane == 0) {
+    for (int x = 0; x < S.na; ++x) {
+      if (A[A_LIM * AMAX + x] == 0.f) continue;
+      float q = A[A_Q * AMAX + x];
+      float gaps[2] = {q - A[A_LO * AMAX + x], A[A_HI * AMAX + x] - q};
+      for (int e = 0; e < 2; ++e) {
+        if (gaps[e] < a.margin && n < cc) {
+          C[C_INFO * cc + n] = __int_as_float((K_LIMIT << 8 | x) | ((e == 0 ? 0 : 1) << 16));
+          C[C_PHI * cc + n] = gaps[e];
+          ++n;
+        }
+      }
+    }
+  }
+  n = bcasti(n, 0);
+  NL = n;
+  int nr = 0;
+  bool over = false, rover = false;
+  uint64_t ks = 0;
+  const int NT = S.np + S.ns + S.na + S.nf;
+  const int NO = S.nsph + S.nfo;
+  const int total = NO * NT;
+  const float invNT = NT > 0 ? 1.f / (float)NT : 0.f;
+  for (int base = 0; base < total; base += WAVE) {
+    int pair = base + lane;
+    bool valid = pair < total;
+    int o = 0, t = 0;
+    if (valid) {
+      o = (int)(((float)pair + 0.5f) * invNT);
+      t = pair - o * NT;
+      if (t < 0) { --o; t += NT; }
+      if (t >= NT) { ++o; t -= NT; }
+    }
+    // owner
+    f3 c = mk3(0.f, 0.f, 0.f);
+    float r = 0.f;
+    int okind = 0, oidx = 0, of = -1, ovk = 0, oflags = 0;  // okind 0 robot sphere, 1 box vertex, 2 free sphere
+    if (valid) {
+      if (o < S.nsph) {
+        c = mk3(SW[o * 4], SW[o * 4 + 1], SW[o * 4 + 2]);
+        r = SW[o * 4 + 3];
+        oflags = M->sph_flags[o];
+        oidx = M->sph_body[o];
+        okind = 0;
+      } else {
+        int ow = own[o - S.nsph];
+        of = ow >> 3;
+        ovk = ow & 7;
+        f3 x = mk3(F[(F_X + 0) * fm + of], F[(F_X + 1) * fm + of], F[(F_X + 2) * fm + of]);
+        if (F[F_TYPE * fm + of] == 0.f) {
+          f3 hl = mk3((ovk & 1) ? F[(F_H + 0) * fm + of] : -F[(F_H + 0) * fm + of],
+                      (ovk & 2) ? F[(F_H + 1) * fm + of] : -F[(F_H + 1) * fm + of],
+                      (ovk & 4) ? F[(F_H + 2) * fm + of] : -F[(F_H + 2) * fm + of]);
+          float Rf[9];
+          for (int k = 0; k < 9; ++k) Rf[k] = F[(F_R + k) * fm + of];
+          c = x + mv(Rf, hl);
+          r = 0.f;
+          okind = 1;
+        } else {
+          c = x;
+          r = F[(F_H + 0) * fm + of];
+          okind = 2;
+        }
+      }
+    }
+    // target
+    bool hit = false;
+    float phi = 0.f;
+    f3 nrm = mk3(0.f, 0.f, 1.f);
+    int tkey = 0, bside = 0;
+    if (valid) {
+      if (t < S.np) {
+        if (!(t == 0 && okind == 0 && (oflags & 1))) {
+          f3 pn = mk3(Pl[t * 4], Pl[t * 4 + 1], Pl[t * 4 + 2]);
+          phi = dot(pn, c) - Pl[t * 4 + 3] - r;
+          nrm = pn;
+          hit = phi < a.margin;
+        }
+        tkey = t;
+        bside = K_STATIC << 8;
+      } else if (t < S.np + S.ns) {
+        int bi = t - S.np;
+        const float* bx = St + bi * 6;
+        phi = box_test(c, r, mk3(bx[0], bx[1], bx[2]), nullptr, mk3(bx[3], bx[4], bx[5]), nrm);
+        hit = phi < a.margin;
+        tkey = (1 << 24) | bi;
+        bside = K_STATIC << 8;
+      } else if (t < S.np + S.ns + S.na) {
+        int x = t - S.np - S.ns;
+        float Rx[9];
+        for (int k = 0; k < 9; ++k) Rx[k] = A[(A_R + k) * AMAX + x];
+        phi = box_test(c, r, mk3(A[(A_BC + 0) * AMAX + x], A[(A_BC + 1) * AMAX + x], A[(A_BC + 2) * AMAX + x]), Rx,
+                       mk3(A[(A_BH + 0) * AMAX + x], A[(A_BH + 1) * AMAX + x], A[(A_BH + 2) * AMAX + x]), nrm);
+        hit = phi < a.margin;
+        tkey = (2 << 24) | x;
+        bside = (K_AUX << 8) | x;
+      } else {
+        int g = t - S.np - S.ns - S.na;
+        bool allowed = g != of;
+        bool gbox = F[F_TYPE * fm + g] == 0.f;
+        if (!gbox && okind == 1) allowed = false;           // box vertices skip free spheres
+        if (!gbox && okind == 2 && g <= of) allowed = false;  // sphere pairs once
+        if (allowed) {
+          f3 xg = mk3(F[(F_X + 0) * fm + g], F[(F_X + 1) * fm + g], F[(F_X + 2) * fm + g]);
+          if (gbox) {
+            float Rg[9];
+            for (int k = 0; k < 9; ++k) Rg[k] = F[(F_R + k) * fm + g];
+            phi = box_test(c, r, xg, Rg, mk3(F[(F_H + 0) * fm + g], F[(F_H + 1) * fm + g], F[(F_H + 2) * fm + g]),
+                           nrm);
+          } else {
+            f3 d = c - xg;
+            float dist = sqrtf(dot(d, d));
+            phi = dist - r - F[(F_H + 0) * fm + g];
+            nrm = dist < 1e-12f ? mk3(0.f, 0.f, 1.f) : d * (1.f / dist);
+          }
+          hit = phi < a.margin;
+        }
+        tkey = (3 << 24) | g;
+        bside = (K_FREE << 8) | g;
+      }
+    }
+    // keep within the caps, in pair (= canonical) order
+    bool isrob = okind == 0;
+    uint64_t mr = __ballot(hit && isrob);
+    int rpos = nr + prefix_below(mr);
+    bool keep = hit && (!isrob || rpos < a.rcap);
+    if (hit && isrob && rpos >= a.rcap) rover = true;
+    uint64_t mk = __ballot(keep);
+    int pos = n + prefix_below(mk);
+    if (keep && pos >= cc) {
+      keep = false;
+      over = true;
+    }
+    if (keep) {
+      int aside = okind == 0 ? ((K_ROBOT << 8) | oidx) : ((K_FREE << 8) | of);
+      C[C_INFO * cc + pos] = __int_as_float(aside | (bside << 16));
+      f3 p = c - nrm * r;
+      C[(C_N + 0) * cc + pos] = nrm.x; C[(C_N + 1) * cc + pos] = nrm.y; C[(C_N + 2) * cc + pos] = nrm.z;
+      C[(C_P + 0) * cc + pos] = p.x; C[(C_P + 1) * cc + pos] = p.y; C[(C_P + 2) * cc + pos] = p.z;
+      C[C_PHI * cc + pos] = phi;
+      uint32_t okey = okind == 0 ? (uint32_t)o : ((1u << 24) | ((uint32_t)of << 3) | (uint32_t)ovk);
+      ks += mix64(((uint64_t)okey << 32) | (uint32_t)tkey);
+    }
+    int nk = __popcll(__ballot(keep));
+    n = min(n + nk, cc);
+    nr += __popcll(__ballot(keep && isrob));
+  }
+  // reduce key sums and flags
+  for (int off = 32; off > 0; off >>= 1) ks += __shfl_xor(ks, off, WAVE);
+  keysum = ks;
+  if (__ballot(over)) status |= 2u;
+  if (__ballot(rover)) status |= 8u;
+  NC = n;
+  NR = nr;
+  wave_sync();
+}
+
+// Articulated-body algorithm (Featherstone 2008, Table 7.1) with world-
+// aligned axes and each body's quantities referred to its own origin p_i (on
+// the joint axis): the transform between a body and its parent is a pure
+// translation, and lever arms stay at link length, which keeps FP32 free of
+// the cancellation that origin-referred inertias of distant links suffer.
+// Also the columns of the inverse of M~ = M + diag(arm).
+
+// motion vector m given at point P, expressed at point Q (d = Q - P)
+__device__ __forceinline__ void shift_motion(const float* m, f3 d, float* out) {
+  f3 w = mk3(m[0], m[1], m[2]);
+  f3 v = mk3(m[3], m[4], m[5]) + cross(w, d);
+  out[0] = m[0]; out[1] = m[1]; out[2] = m[2]; out[3] = v.x; out[4] = v.y; out[5] = v.z;
+}
+// force vector f given at point P, expressed at point Q (e = P - Q)
+__device__ __forceinline__ void shift_force(const float* f, f3 e, float* out) {
+  f3 n = mk3(f[0], f[1], f[2]) + cross(e, mk3(f[3], f[4], f[5]));
+  out[0] = n.x; out[1] = n.y; out[2] = n.z; out[3] = f[3]; out[4] = f[4]; out[5] = f[5];
+}
+__device__ __forceinline__ f3 body_p(const Robot& rb, int i) {
+  return mk3(rb.p[i * 3], rb.p[i * 3 + 1], rb.p[i * 3 + 2]);
+}
+// motion subspace of joint k expressed at point q
+__device__ __forceinline__ void s_at(const Robot& rb, const DModel* M, int k, f3 q, float* out) {
+  const float* s = rb.s + k * 6;
+  if (M->jtype[k] == 0) {
+    f3 a = mk3(s[0], s[1], s[2]);
+    f3 v = cross(a, q - body_p(rb, k));
+    out[0] = a.x; out[1] = a.y; out[2] = a.z; out[3] = v.x; out[4] = v.y; out[5] = v.z;
+  } else {
+    for (int t = 0; t < 6; ++t) out[t] = s[t];
+  }
+}
+
+__device__ void phase_dynamics(const KArgs& a, const Scene& S, float* L, const Robot& rb, float& vR) {
+  const int lane = lane_id();
+  const DModel* M = S.M;
+  const int nb = S.nb;
+  // pass 1 (lane per body): twist v_i at p_i = sum over k in anc-or-self(i) of
+  // s_k qd_k; c_i = v_i x (s_i qd_i); rigid inertia at p_i; pA_i = v_i x* I_i v_i
+  if (lane < nb) {
+    const int i = lane;
+    const f3 pi = body_p(rb, i);
+    float v[6] = {0, 0, 0, 0, 0, 0};
+    int am = M->anc[i];
+    for (int k = 0; k <= i; ++k)
+      if ((am >> k) & 1) {
+        float sk[6];
+        s_at(rb, M, k, pi, sk);
+        float qd = rb.qd[k];
+        for (int t = 0; t < 6; ++t) v[t] += sk[t] * qd;
+      }
+    float vJ[6];
+    float qd = rb.qd[i];
+    for (int t = 0; t < 6; ++t) vJ[t] = rb.s[i * 6 + t] * qd;
+    crm(v, vJ, rb.cc + i * 6);
+    const float* R = rb.R + i * 9;
+    float m = M->mass[i];
+    f3 c = mv(R, mk3(M->com[i][0], M->com[i][1], M->com[i][2]));  // COM relative to p_i
+    const float* ic = M->Ic[i];
+    float Ib[9] = {ic[0], ic[3], ic[4], ic[3], ic[1], ic[5], ic[4], ic[5], ic[2]};
+    float RI[9], Icw[9];
+    mm(R, Ib, RI);
+    for (int r = 0; r < 3; ++r)
+      for (int q = 0; q < 3; ++q)
+        Icw[r * 3 + q] = RI[r * 3] * R[q * 3] + RI[r * 3 + 1] * R[q * 3 + 1] + RI[r * 3 + 2] * R[q * 3 + 2];
+    float cc2 = dot(c, c);
+    float* IA = rb.IA + i * 36;
+    float cv[3] = {c.x, c.y, c.z};
+    for (int r = 0; r < 3; ++r)
+      for (int q = 0; q < 3; ++q) IA[r * 6 + q] = Icw[r * 3 + q] - m * cv[r] * cv[q] + (r == q ? m * cc2 : 0.f);
+    float cx[9] = {0.f, -c.z, c.y, c.z, 0.f, -c.x, -c.y, c.x, 0.f};
+    for (int r = 0; r < 3; ++r)
+      for (int q = 0; q < 3; ++q) {
+        IA[r * 6 + 3 + q] = m * cx[r * 3 + q];
+        IA[(3 + r) * 6 + q] = m * cx[q * 3 + r];
+        IA[(3 + r) * 6 + 3 + q] = r == q ? m : 0.f;
+      }
+    float Iv[6];
+    for (int r = 0; r < 6; ++r) {
+      float acc = 0.f;
+      for (int q = 0; q < 6; ++q) acc += IA[r * 6 + q] * v[q];
+      Iv[r] = acc;
+    }
+    crf(v, Iv, rb.pA + i * 6);
+  }
+  wave_sync();
+  // pass 2 (inward, serial over bodies): U, D, u at p_i; the articulated
+  // inertia I^a = IA - U U^T / D and bias p^a = pA + I^a c + U u / D are
+  // translated to the parent's origin and added there
+  float* Ia_s = rb.Minv;  // scratch (36 floats) until the inverse is formed
+  for (int i = nb - 1; i >= 0; --i) {
+    const float* IA = rb.IA + i * 36;
+    const float* s = rb.s + i * 6;
+    const int par = M->parent[i];
+    if (lane == 0) {
+      float U[6], ci[6], pAi[6], Ic_[6];
+      for (int t = 0; t < 6; ++t) { ci[t] = rb.cc[i * 6 + t]; pAi[t] = rb.pA[i * 6 + t]; }
+      float D = rb.arm[i], uu = rb.tau[i], Uc = 0.f;
+      for (int r = 0; r < 6; ++r) {
+        float accU = 0.f, accC = 0.f;
+        for (int q = 0; q < 6; ++q) {
+          float e = IA[r * 6 + q];
+          accU += e * s[q];
+          accC += e * ci[q];
+        }
+        U[r] = accU;
+        Ic_[r] = accC;
+      }
+      for (int r = 0; r < 6; ++r) {
+        D += s[r] * U[r];
+        uu -= s[r] * pAi[r];
+        Uc += U[r] * ci[r];
+      }
+      for (int r = 0; r < 6; ++r) rb.U[i * 6 + r] = U[r];
+      rb.D[i] = D;
+      rb.uu[i] = uu;
+      if (par >= 0) {
+        float invD = 1.f / D;
+        float pa[6], pq[6];
+        for (int r = 0; r < 6; ++r) pa[r] = pAi[r] + Ic_[r] - U[r] * Uc * invD + U[r] * uu * invD;
+        shift_force(pa, body_p(rb, i) - body_p(rb, par), pq);
+        for (int r = 0; r < 6; ++r) rb.pA[par * 6 + r] += pq[r];
+      }
+    }
+    wave_sync();
+    if (par >= 0) {
+      if (lane < 36) {
+        const float Di = rb.D[i];
+        const int r = lane / 6, q = lane % 6;
+        Ia_s[lane] = IA[lane] - rb.U[i * 6 + r] * rb.U[i * 6 + q] / Di;
+      }
+      wave_sync();
+      if (lane < 36) {
+        // translate a symmetric 6x6 [[A, B], [B^T, C]] from p_i to p_par:
+        // A' = A + Dx B^T - B Dx - Dx C Dx, B' = B + Dx C, C' = C, Dx = [d]x, d = p_i - p_par
+        f3 d = body_p(rb, i) - body_p(rb, par);
+        float Dx[9] = {0.f, -d.z, d.y, d.z, 0.f, -d.x, -d.y, d.x, 0.f};
+        const int r = lane / 6, q = lane % 6;
+        float val = Ia_s[lane];
+        if (r < 3 && q < 3) {
+          for (int k = 0; k < 3; ++k) {
+            val += Dx[r * 3 + k] * Ia_s[q * 6 + 3 + k];   // Dx B^T
+            val -= Ia_s[r * 6 + 3 + k] * Dx[k * 3 + q];   // B Dx
+            float cd = 0.f;
+            for (int l = 0; l < 3; ++l) cd += Ia_s[(3 + k) * 6 + 3 + l] * Dx[l * 3 + q];
+            val -= Dx[r * 3 + k] * cd;                     // Dx C Dx
+          }
+        } else if (r < 3) {
+          for (int k = 0; k < 3; ++k) val += Dx[r * 3 + k] * Ia_s[(3 + k) * 6 + q];
+        } else if (q < 3) {
+          for (int k = 0; k < 3; ++k) val += Dx[q * 3 + k] * Ia_s[(3 + k) * 6 + r];
+        }
+        rb.IA[par * 36 + lane] += val;
+      }
+      wave_sync();
+    }
+  }
+  // tables: T[i][k] = U_i . s_k (k strict ancestor of i, s_k taken to p_i);
+  // S2[i][k] = s_i . U_k / D_k (k strict descendant of i, U_k taken to p_i)
+  for (int e = lane; e < ND * ND; e += WAVE) {
+    int i = e / ND, k = e % ND;
+    float tv = 0.f, sv = 0.f;
+    if (i < nb && k < nb) {
+      f3 pi = body_p(rb, i);
+      if (k < i && ((M->anc[i] >> k) & 1)) {
+        float sk[6];
+        s_at(rb, M, k, pi, sk);
+        for (int t = 0; t < 6; ++t) tv += rb.U[i * 6 + t] * sk[t];
+      }
+      if (k > i && ((M->anc[k] >> i) & 1)) {
+        float Uk[6];
+        shift_force(rb.U + k * 6, body_p(rb, k) - pi, Uk);
+        for (int t = 0; t < 6; ++t) sv += rb.s[i * 6 + t] * Uk[t];
+        sv /= rb.D[k];
+      }
+    }
+    rb.T[e] = tv;
+    rb.S2[e] = sv;
+  }
+  // forward-dynamics right-hand side b_i = u_i - U_i . (a0 + sum_{k in anc-or-self(i)} c_k), at p_i
+  if (lane < nb) {
+    const int i = lane;
+    const f3 pi = body_p(rb, i);
+    float acc6[6] = {0.f, 0.f, 0.f, -a.g[0], -a.g[1], -a.g[2]};
+    int am = M->anc[i];
+    for (int k = 0; k <= i; ++k)
+      if ((am >> k) & 1) {
+        float ck[6];
+        shift_motion(rb.cc + k * 6, pi - body_p(rb, k), ck);
+        for (int t = 0; t < 6; ++t) acc6[t] += ck[t];
+      }
+    float b = rb.uu[i];
+    for (int t = 0; t < 6; ++t) b -= rb.U[i * 6 + t] * acc6[t];
+    rb.pA[i * 6] = b;  // pA is no longer needed: reuse its first slot for b_i
+  }
+  wave_sync();
+  // lanes 0..nb-1: column j of M~^-1 (force e_j, no velocity, no gravity);
+  // lane 16: the forward dynamics qdd
+  {
+    float uvec[ND], qdd[ND];
+    const bool col = lane < nb;
+    const bool fd = lane == ND;
+    if (col || fd) {
+      if (col) {
+#pragma unroll
+        for (int i = ND - 1; i >= 0; --i) {
+          float acc = (i == lane) ? 1.f : 0.f;
+#pragma unroll
+          for (int k = i + 1; k < ND; ++k) acc -= rb.S2[i * ND + k] * uvec[k];
+          uvec[i] = acc;
+        }
+      } else {
+#pragma unroll
+        for (int i = 0; i < ND; ++i) uvec[i] = i < nb ? rb.pA[i * 6] : 0.f;
+      }
+#pragma unroll
+      for (int i = 0; i < ND; ++i) {
+        float acc = uvec[i];
+#pragma unroll
+        for (int k = 0; k < i; ++k) acc -= rb.T[i * ND + k] * qdd[k];
+        qdd[i] = i < nb ? acc / rb.D[i] : 0.f;
+      }
+    }
+    wave_sync();
+    if (col) {
+#pragma unroll
+      for (int i = 0; i < ND; ++i) rb.Minv[i * ND + lane] = qdd[i];
+    }
+    if (lane < ND && lane >= nb) {
+      for (int i = 0; i < ND; ++i) rb.Minv[i * ND + lane] = 0.f;
+    }
+    if (fd) {
+#pragma unroll
+      for (int i = 0; i < ND; ++i) rb.qdd[i] = qdd[i];
+    }
+  }
+  wave_sync();
+  // unconstrained robot velocity, held in lanes 0..15
+  vR = 0.f;
+  if (lane < ND) vR = lane < nb ? rb.qd[lane] + a.h * rb.qdd[lane] : rb.qd[lane];
+  // free bodies: v* = v + h g ; w* = w - h Iw^-1 (w x Iw w)
+  float* F = L + a.L.fr;
+  const int fm = a.L.fmax;
+  for (int f = lane; f < S.nf; f += WAVE) {
+    float R[9];
+    for (int t = 0; t < 9; ++t) R[t] = F[(F_R + t) * fm + f];
+    f3 w = mk3(F[(F_W + 0) * fm + f], F[(F_W + 1) * fm + f], F[(F_W + 2) * fm + f]);
+    f3 wl = mtv(R, w);
+    f3 Iwl = mk3(F[(F_IB + 0) * fm + f] * wl.x, F[(F_IB + 1) * fm + f] * wl.y, F[(F_IB + 2) * fm + f] * wl.z);
+    f3 Iw = mv(R, Iwl);
+    f3 gy = cross(w, Iw);
+    float Ii[9];
+    for (int t = 0; t < 9; ++t) Ii[t] = F[(F_II + t) * fm + f];
+    f3 dw = mv(Ii, gy);
+    F[(F_W + 0) * fm + f] = w.x - a.h * dw.x;
+    F[(F_W + 1) * fm + f] = w.y - a.h * dw.y;
+    F[(F_W + 2) * fm + f] = w.z - a.h * dw.z;
+    for (int t = 0; t < 3; ++t) F[(F_V + t) * fm + f] += a.h * a.g[t];
+  }
+  // aux joints: passive single-DoF bodies; the gravity torque about the axis
+  float* Ax = L + a.L.aux;
+  if (lane < S.na) {
+    DAux d = a.aux[S.a0 + lane];
+    f3 ax = mk3(Ax[(A_AX + 0) * AMAX + lane], Ax[(A_AX + 1) * AMAX + lane], Ax[(A_AX + 2) * AMAX + lane]);
+    f3 bc = mk3(Ax[(A_BC + 0) * AMAX + lane], Ax[(A_BC + 1) * AMAX + lane], Ax[(A_BC + 2) * AMAX + lane]);
+    f3 gvec = mk3(a.g[0], a.g[1], a.g[2]);
+    float gen;  // generalized gravity force
+    if (d.type == 0) gen = dot(ax, cross(bc - mk3(d.p0[0], d.p0[1], d.p0[2]), gvec * d.mass));
+    else gen = d.mass * dot(ax, gvec);
+    float qd = Ax[A_QD * AMAX + lane];
+    Ax[A_V * AMAX + lane] = qd + a.h * gen * Ax[A_IM * AMAX + lane];
+  }
+  wave_sync();
+}
+
+// Point-Jacobian column of aux joint x at world point p
+__device__ __forceinline__ f3 aux_col(const float* A, int x, f3 p) {
+  f3 ax = mk3(A[(A_AX + 0) * AMAX + x], A[(A_AX + 1) * AMAX + x], A[(A_AX + 2) * AMAX + x]);
+  if (A[A_TYPE * AMAX + x] == 0.f) {
+    f3 o = mk3(A[(A_P + 0) * AMAX + x], A[(A_P + 1) * AMAX + x], A[(A_P + 2) * AMAX + x]);
+    return cross(ax, p - o);
+  }
+  return ax;
+}
+
+__device__ void phase_rows(const KArgs& a, const Scene& S, float* L, const Robot& rb, int NC, int NR, int NL,
+                           uint32_t& status) {
+  const int lane = lane_id();
+  const LdsLayout& Y = a.L;
+  float* C = L + Y.con;
+  const int cc = Y.ccap;
+  const float* F = L + Y.fr;
+  const int fm = Y.fmax;
+  const float* A = L + Y.aux;
+  const DModel* M = S.M;
+  // lane per contact: tangents, free / aux effective-mass parts, bias
+  for (int ci = lane; ci < NC; ci += WAVE) {
+    int info = __float_as_int(C[C_INFO * cc + ci]);
+    int sA = info & 0xffff, sB = (info >> 16) & 0xffff;
+    float phi = C[C_PHI * cc + ci];
+    float bias = phi >= 0.f ? phi / a.h : a.beta * phi / a.h;
+    if (side_kind(sA) == K_LIMIT) {
+      int x = side_idx(sA);
+      C[(C_IW + 0) * cc + ci] = A[A_IM * AMAX + x];  // W = 1 / M~ for J = +-1
+      C[C_BIAS * cc + ci] = bias;
+      for (int t = 0; t < 3; ++t) C[(C_LAM + t) * cc + ci] = 0.f;
+      continue;
+    }
+    f3 n = mk3(C[(C_N + 0) * cc + ci], C[(C_N + 1) * cc + ci], C[(C_N + 2) * cc + ci]);
+    f3 p = mk3(C[(C_P + 0) * cc + ci], C[(C_P + 1) * cc + ci], C[(C_P + 2) * cc + ci]);
+    f3 t1, t2;
+    onb(n, t1, t2);
+    f3 dirs[3] = {n, t1, t2};
+    float W[3] = {0.f, 0.f, 0.f};
+    for (int sd = 0; sd < 2; ++sd) {
+      int sv = sd == 0 ? sA : sB;
+      int k = side_kind(sv), idx = side_idx(sv);
+      if (k == K_FREE) {
+        f3 r = p - mk3(F[(F_X + 0) * fm + idx], F[(F_X + 1) * fm + idx], F[(F_X + 2) * fm + idx]);
+        float Ii[9];
+        for (int t = 0; t < 9; ++t) Ii[t] = F[(F_II + t) * fm + idx];
+        float im = F[F_IM * fm + idx];
+        for (int d = 0; d < 3; ++d) {
+          f3 rd = cross(r, dirs[d]);
+          W[d] += im + dot(rd, mv(Ii, rd));
+        }
+      } else if (k == K_AUX) {
+        f3 col = aux_col(A, idx, p);
+        float im = A[A_IM * AMAX + idx];
+        for (int d = 0; d < 3; ++d) {
+          float J = dot(dirs[d], col);
+          W[d] += J * J * im;
+        }
+      }
+    }
+    for (int d = 0; d < 3; ++d) C[(C_IW + d) * cc + ci] = W[d];
+    C[C_BIAS * cc + ci] = bias;
+    for (int t = 0; t < 3; ++t) C[(C_LAM + t) * cc + ci] = 0.f;
+  }
+  wave_sync();
+  // robot rows: lane (d, j) builds J[d][j] = d . (dp/dq_j), then w = M~^-1 J^T
+  float* Rw = L + Y.rows;
+  const int d = lane >> 4, j = lane & 15;
+  for (int rr = 0; rr < NR; ++rr) {
+    const int ci = NL + rr;
+    float* row = Rw + rr * ROW_FLOATS;
+    int info = __float_as_int(C[C_INFO * cc + ci]);
+    int body = side_idx(info & 0xffff);
+    if (d < 3) {
+      f3 n = mk3(C[(C_N + 0) * cc + ci], C[(C_N + 1) * cc + ci], C[(C_N + 2) * cc + ci]);
+      f3 p = mk3(C[(C_P + 0) * cc + ci], C[(C_P + 1) * cc + ci], C[(C_P + 2) * cc + ci]);
+      f3 t1, t2;
+      onb(n, t1, t2);
+      f3 dir = d == 0 ? n : (d == 1 ? t1 : t2);
+      float J = 0.f;
+      if (j < S.nb && ((M->anc[body] >> j) & 1)) {
+        const float* s = rb.s + j * 6;
+        f3 ax = M->jtype[j] == 0 ? mk3(s[0], s[1], s[2]) : mk3(s[3], s[4], s[5]);
+        if (M->jtype[j] == 0) J = dot(dir, cross(ax, p - mk3(rb.p[j * 3], rb.p[j * 3 + 1], rb.p[j * 3 + 2])));
+        else J = dot(dir, ax);
+      }
+      row[d * ND + j] = J;
+    }
+    wave_sync();
+    if (d < 3) {
+      float w = 0.f;
+#pragma unroll
+      for (int k = 0; k < ND; ++k) w += rb.Minv[j * ND + k] * row[d * ND + k];
+      row[3 * ND + d * ND + j] = w;
+      float Wr = sum16(row[d * ND + j] * w);
+      if (j == 0) C[(C_IW + d) * cc + ci] += Wr;
+    }
+    wave_sync();
+  }
+  // inverse effective masses; rows below 1e-12 are skipped (inverse 0)
+  bool degen = false;
+  for (int ci = lane; ci < NC; ci += WAVE) {
+    for (int dd = 0; dd < 3; ++dd) {
+      float W = C[(C_IW + dd) * cc + ci];
+      int info = __float_as_int(C[C_INFO * cc + ci]);
+      bool lim = side_kind(info & 0xffff) == K_LIMIT;
+      if (lim && dd > 0) continue;
+      if (W >= 1e-12f) C[(C_IW + dd) * cc + ci] = 1.f / W;
+      else {
+        C[(C_IW + dd) * cc + ci] = 0.f;
+        degen = true;
+      }
+    }
+  }
+  if (__ballot(degen)) status |= 4u;
+  wave_sync();
+}
+
+// Level schedule: level(k) = 1 + max level of earlier rows sharing a node.
+// Then an order list grouped by level; each level's robot row is kept apart.
+__device__ int phase_levels(const KArgs& a, float* L, int NC, int NR, int NL) {
+  const int lane = lane_id();
+  const LdsLayout& Y = a.L;
+  float* C = L + Y.con;
+  const int cc = Y.ccap;
+  int* lvl = reinterpret_cast<int*>(L + Y.lvl);       // [cc] level of contact
+  int* loff = lvl + cc;                               // [cc + 2] level offsets
+  int* rob = loff + cc + 2;                           // [cc + 2] robot row of each level (-1)
+  uint16_t* order = reinterpret_cast<uint16_t*>(rob + cc + 2);  // [cc]
+  int reg = 0;  // level of node `lane`
+  int maxl = 0;
+  for (int base = 0; base < NC; base += WAVE) {
+    int info = 0;
+    if (base + lane < NC) info = __float_as_int(C[C_INFO * cc + base + lane]);
+    int cnt = min(WAVE, NC - base);
+    int mylvl = 0;
+    for (int k = 0; k < cnt; ++k) {
+      int inf = __builtin_amdgcn_readlane(info, k);
+      int na = node_of(inf & 0xffff), nbn = node_of((inf >> 16) & 0xffff);
+      if (side_kind(inf & 0xffff) == K_LIMIT) nbn = 63;
+      int lv = max(__builtin_amdgcn_readlane(reg, na), __builtin_amdgcn_readlane(reg, nbn)) + 1;
+      if (lane == na || (lane == nbn && nbn != 63)) reg = lv;
+      if (lane == k) mylvl = lv;
+      maxl = max(maxl, lv);
+    }
+    if (base + lane < NC) lvl[base + lane] = mylvl;
+  }
+  for (int e = lane; e <= maxl + 1; e += WAVE) rob[e] = -1;
+  wave_sync();
+  for (int rr = lane; rr < NR; rr += WAVE) rob[lvl[NL + rr]] = NL + rr;
+  int pos = 0;
+  for (int lv = 1; lv <= maxl; ++lv) {
+    if (lane == 0) loff[lv - 1] = pos;
+    for (int base = 0; base < NC; base += WAVE) {
+      int ci = base + lane;
+      bool isr = ci >= NL && ci < NL + NR;
+      bool m = ci < NC && !isr && lvl[ci] == lv;
+      uint64_t mk = __ballot(m);
+      if (m) order[pos + prefix_below(mk)] = (uint16_t)ci;
+      pos += __popcll(mk);
+    }
+  }
+  if (lane == 0) loff[maxl] = pos;
+  wave_sync();
+  return maxl;
+}
+
+// velocity of the material point p of side sv (free body or aux joint)
+__device__ __forceinline__ f3 side_point_vel(const float* F, int fm, const float* A, int sv, f3 p) {
+  int k = side_kind(sv), idx = side_idx(sv);
+  if (k == K_FREE) {
+    f3 x = mk3(F[(F_X + 0) * fm + idx], F[(F_X + 1) * fm + idx], F[(F_X + 2) * fm + idx]);
+    f3 v = mk3(F[(F_V + 0) * fm + idx], F[(F_V + 1) * fm + idx], F[(F_V + 2) * fm + idx]);
+    f3 w = mk3(F[(F_W + 0) * fm + idx], F[(F_W + 1) * fm + idx], F[(F_W + 2) * fm + idx]);
+    return v + cross(w, p - x);
+  }
+  if (k == K_AUX) return aux_col(A, idx, p) * A[A_V * AMAX + idx];
+  return mk3(0.f, 0.f, 0.f);
+}
+// apply impulse P (world) at p to side sv with sign sg
+__device__ __forceinline__ void side_apply(float* F, int fm, float* A, int sv, f3 p, f3 P) {
+  int k = side_kind(sv), idx = side_idx(sv);
+  if (k == K_FREE) {
+    f3 x = mk3(F[(F_X + 0) * fm + idx], F[(F_X + 1) * fm + idx], F[(F_X + 2) * fm + idx]);
+    float im = F[F_IM * fm + idx];
+    float Ii[9];
+    for (int t = 0; t < 9; ++t) Ii[t] = F[(F_II + t) * fm + idx];
+    f3 dw = mv(Ii, cross(p - x, P));
+    F[(F_V + 0) * fm + idx] += P.x * im;
+    F[(F_V + 1) * fm + idx] += P.y * im;
+    F[(F_V + 2) * fm + idx] += P.z * im;
+    F[(F_W + 0) * fm + idx] += dw.x;
+    F[(F_W + 1) * fm + idx] += dw.y;
+    F[(F_W + 2) * fm + idx] += dw.z;
+  } else if (k == K_AUX) {
+    A[A_V * AMAX + idx] += dot(aux_col(A, idx, p), P) * A[A_IM * AMAX + idx];
+  }
+}
+
+__device__ void phase_pgs(const KArgs& a, const Scene& S, float* L, int NC, int NL, int maxl, float& vR) {
+  const int lane = lane_id();
+  const LdsLayout& Y = a.L;
+  float* C = L + Y.con;
+  const int cc = Y.ccap;
+  float* F = L + Y.fr;
+  const int fm = Y.fmax;
+  float* A = L + Y.aux;
+  const float* Rw = L + Y.rows;
+  const int* lvl = reinterpret_cast<const int*>(L + Y.lvl);
+  const int* loff = lvl + cc;
+  const int* rob = loff + cc + 2;
+  const uint16_t* order = reinterpret_cast<const uint16_t*>(rob + cc + 2);
+  const float mu = a.mu;
+  for (int it = 0; it < a.K; ++it) {
+    for (int lv = 1; lv <= maxl; ++lv) {
+      const int rc = rob[lv];
+      if (rc >= 0) {
+        // robot row: lanes 0..15 hold the robot joint velocities
+        const float* row = Rw + (rc - NL) * ROW_FLOATS;
+        const int j = lane & 15;
+        int info = __float_as_int(C[C_INFO * cc + rc]);
+        int sB = (info >> 16) & 0xffff;
+        f3 n = mk3(C[(C_N + 0) * cc + rc], C[(C_N + 1) * cc + rc], C[(C_N + 2) * cc + rc]);
+        f3 p = mk3(C[(C_P + 0) * cc + rc], C[(C_P + 1) * cc + rc], C[(C_P + 2) * cc + rc]);
+        float iw0 = C[(C_IW + 0) * cc + rc], iw1 = C[(C_IW + 1) * cc + rc], iw2 = C[(C_IW + 2) * cc + rc];
+        float bias = C[C_BIAS * cc + rc];
+        float l0 = C[(C_LAM + 0) * cc + rc], l1 = C[(C_LAM + 1) * cc + rc], l2 = C[(C_LAM + 2) * cc + rc];
+        float vj = lane < ND ? vR : 0.f;
+        float Jn = row[j], wn = row[3 * ND + j];
+        float dn = sum16(lane < ND ? Jn * vj : 0.f);
+        dn = bcast(dn, 0);
+        f3 uB = side_point_vel(F, fm, A, sB, p);
+        float r = dn - dot(n, uB) + bias;
+        float nl = l0;
+        if (iw0 > 0.f) nl = fmaxf(0.f, l0 - r * iw0);
+        float dl = nl - l0;
+        if (lane < ND) vR += wn * dl;
+        if (lane == 0 && dl != 0.f) side_apply(F, fm, A, sB, p, n * (-dl));
+        wave_sync();
+        if (iw1 > 0.f && iw2 > 0.f) {
+          f3 t1, t2;
+          onb(n, t1, t2);
+          float vj2 = lane < ND ? vR : 0.f;
+          float J1 = row[ND + j], J2 = row[2 * ND + j];
+          float d1 = bcast(sum16(lane < ND ? J1 * vj2 : 0.f), 0);
+          float d2 = bcast(sum16(lane < ND ? J2 * vj2 : 0.f), 0);
+          f3 uB2 = side_point_vel(F, fm, A, sB, p);
+          float r1 = d1 - dot(t1, uB2), r2 = d2 - dot(t2, uB2);
+          float y1 = l1 - r1 * iw1, y2 = l2 - r2 * iw2;
+          float lim = mu * nl;
+          float nn = y1 * y1 + y2 * y2;
+          if (nn > lim * lim) {
+            if (lim > 0.f) {
+              float sc = lim / sqrtf(nn);
+              y1 *= sc;
+              y2 *= sc;
+            } else {
+              y1 = 0.f;
+              y2 = 0.f;
+            }
+          }
+          float dl1 = y1 - l1, dl2 = y2 - l2;
+          if (lane < ND) vR += row[4 * ND + j] * dl1 + row[5 * ND + j] * dl2;
+          if (lane == 0) side_apply(F, fm, A, sB, p, (t1 * dl1 + t2 * dl2) * (-1.f));
+          l1 = y1;
+          l2 = y2;
+        }
+        if (lane == 0) {
+          C[(C_LAM + 0) * cc + rc] = nl;
+          C[(C_LAM + 1) * cc + rc] = l1;
+          C[(C_LAM + 2) * cc + rc] = l2;
+        }
+      }
+      // the level's other rows, one lane each (they share no node)
+      const int o0 = loff[lv - 1], o1 = loff[lv];
+      for (int e = o0 + lane; e < o1; e += WAVE) {
+        const int ci = order[e];
+        int info = __float_as_int(C[C_INFO * cc + ci]);
+        int sA = info & 0xffff, sB = (info >> 16) & 0xffff;
+        float bias = C[C_BIAS * cc + ci];
+        float l0 = C[(C_LAM + 0) * cc + ci];
+        if (side_kind(sA) == K_LIMIT) {
+          int x = side_idx(sA);
+          float sg = ((info >> 16) & 1) ? -1.f : 1.f;
+          float iwl = C[(C_IW + 0) * cc + ci];  // = 1 / W
+          float r = sg * A[A_V * AMAX + x] + bias;
+          float nl = fmaxf(0.f, l0 - r * iwl);
+          A[A_V * AMAX + x] += sg * A[A_IM * AMAX + x] * (nl - l0);
+          C[(C_LAM + 0) * cc + ci] = nl;
+          continue;
+        }
+        f3 n = mk3(C[(C_N + 0) * cc + ci], C[(C_N + 1) * cc + ci], C[(C_N + 2) * cc + ci]);
+        f3 p = mk3(C[(C_P + 0) * cc + ci], C[(C_P + 1) * cc + ci], C[(C_P + 2) * cc + ci]);
+        float iw0 = C[(C_IW + 0) * cc + ci], iw1 = C[(C_IW + 1) * cc + ci], iw2 = C[(C_IW + 2) * cc + ci];
+        float l1 = C[(C_LAM + 1) * cc + ci], l2 = C[(C_LAM + 2) * cc + ci];
+        f3 du = side_point_vel(F, fm, A, sA, p) - side_point_vel(F, fm, A, sB, p);
+        float r = dot(n, du) + bias;
+        float nl = l0;
+        if (iw0 > 0.f) nl = fmaxf(0.f, l0 - r * iw0);
+        float dl = nl - l0;
+        if (dl != 0.f) {
+          side_apply(F, fm, A, sA, p, n * dl);
+          side_apply(F, fm, A, sB, p, n * (-dl));
+        }
+        if (iw1 > 0.f && iw2 > 0.f) {
+          f3 t1, t2;
+          onb(n, t1, t2);
+          f3 du2 = side_point_vel(F, fm, A, sA, p) - side_point_vel(F, fm, A, sB, p);
+          float y1 = l1 - dot(t1, du2) * iw1, y2 = l2 - dot(t2, du2) * iw2;
+          float lim = mu * nl;
+          float nn = y1 * y1 + y2 * y2;
+          if (nn > lim * lim) {
+            if (lim > 0.f) {
+              float sc = lim / sqrtf(nn);
+              y1 *= sc;
+              y2 *= sc;
+            } else {
+              y1 = 0.f;
+              y2 = 0.f;
+            }
+          }
+          f3 P = t1 * (y1 - l1) + t2 * (y2 - l2);
+          side_apply(F, fm, A, sA, p, P);
+          side_apply(F, fm, A, sB, p, P * (-1.f));
+          l1 = y1;
+          l2 = y2;
+        }
+        C[(C_LAM + 0) * cc + ci] = nl;
+        C[(C_LAM + 1) * cc + ci] = l1;
+        C[(C_LAM + 2) * cc + ci] = l2;
+      }
+      wave_sync();
+    }
+  }
+}
+
+__device__ void phase_integrate(const KArgs& a, const Scene& S, float* L, const Robot& rb, float vR) {
+  const int lane = lane_id();
+  if (lane < ND) {
+    rb.qd[lane] = vR;
+    if (lane < S.nb) rb.q[lane] += a.h * vR;
+  }
+  float* F = L + a.L.fr;
+  const int fm = a.L.fmax;
+  for (int f = lane; f < S.nf; f += WAVE) {
+    f3 v = mk3(F[(F_V + 0) * fm + f], F[(F_V + 1) * fm + f], F[(F_V + 2) * fm + f]);
+    f3 w = mk3(F[(F_W + 0) * fm + f], F[(F_W + 1) * fm + f], F[(F_W + 2) * fm + f]);
+    F[(F_X + 0) * fm + f] += a.h * v.x;
+    F[(F_X + 1) * fm + f] += a.h * v.y;
+    F[(F_X + 2) * fm + f] += a.h * v.z;
+    f3 th = w * a.h;
+    float n2 = dot(th, th);
+    float cw, sk;
+    if (n2 < 1e-12f) {
+      cw = 1.f - n2 * 0.125f;
+      sk = 0.5f - n2 * (1.f / 48.f);
+    } else {
+      float nn = sqrtf(n2);
+      cw = cosf(0.5f * nn);
+      sk = sinf(0.5f * nn) / nn;
+    }
+    float e0 = cw, e1 = th.x * sk, e2 = th.y * sk, e3 = th.z * sk;
+    float q0 = F[(F_Q + 0) * fm + f], q1 = F[(F_Q + 1) * fm + f], q2 = F[(F_Q + 2) * fm + f],
+          q3 = F[(F_Q + 3) * fm + f];
+    float r0 = e0 * q0 - (e1 * q1 + e2 * q2 + e3 * q3);
+    float r1 = e0 * q1 + q0 * e1 + (e2 * q3 - e3 * q2);
+    float r2 = e0 * q2 + q0 * e2 + (e3 * q1 - e1 * q3);
+    float r3 = e0 * q3 + q0 * e3 + (e1 * q2 - e2 * q1);
+    float inv = 1.f / sqrtf(r0 * r0 + r1 * r1 + r2 * r2 + r3 * r3);
+    F[(F_Q + 0) * fm + f] = r0 * inv;
+    F[(F_Q + 1) * fm + f] = r1 * inv;
+    F[(F_Q + 2) * fm + f] = r2 * inv;
+    F[(F_Q + 3) * fm + f] = r3 * inv;
+  }
+  float* A = L + a.L.aux;
+  if (lane < S.na) {
+    float v = A[A_V * AMAX + lane];
+    A[A_QD * AMAX + lane] = v;
+    A[A_Q * AMAX + lane] += a.h * v;
+  }
+  wave_sync();
+}
+
+__device__ void run_scene(const KArgs& a, int s, float* L) {
+  const int lane = lane_id();
+  Scene S;
+  const DScene ds = a.scenes[s];
+  S.s = s;
+  S.M = a.models + ds.model;
+  S.nb = S.M->nb;
+  S.nsph = S.M->nsph;
+  S.nf = ds.nf; S.ns = ds.ns; S.np = ds.np; S.na = ds.na; S.nfo = ds.nown;
+  S.f0 = ds.f0; S.s0 = ds.s0; S.p0 = ds.p0; S.a0 = ds.a0;
+  S.hold = a.scenes[s].hold;
+  Robot rb = robot_view(L + a.L.robot);
+  const bool prof = a.phase_cycles != nullptr;
+  unsigned long long cyc[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+  unsigned long long tc = prof ? clock64() : 0;
+#define MS_PHASE(k)                          \
+  if (prof) {                                \
+    unsigned long long t2 = clock64();       \
+    cyc[k] += t2 - tc;                       \
+    tc = t2;                                 \
+  }
+  load_scene(a, S, L, rb);
+  MS_PHASE(7)
+  uint32_t status = 0;
+  for (int k = 0; k < a.n_sub; ++k) {
+    int NC, NR, NL;
+    uint64_t keysum = 0;
+    float vR;
+    phase_drive(a, S, rb);
+    phase_kinematics(a, S, L, rb);
+    MS_PHASE(0)
+    phase_contacts(a, S, L, NC, NR, NL, status, keysum);
+    MS_PHASE(1)
+    phase_dynamics(a, S, L, rb, vR);
+    MS_PHASE(2)
+    phase_rows(a, S, L, rb, NC, NR, NL, status);
+    MS_PHASE(3)
+    int maxl = phase_levels(a, L, NC, NR, NL);
+    MS_PHASE(4)
+    phase_pgs(a, S, L, NC, NL, maxl, vR);
+    MS_PHASE(5)
+    phase_integrate(a, S, L, rb, vR);
+    MS_PHASE(6)
+    if (a.debug && lane == 0) {
+      uint32_t* d = a.debug + ((size_t)s * a.n_sub_total + a.sub0 + k) * 4;
+      d[0] = (uint32_t)(NC - NL);
+      d[1] = (uint32_t)NR;
+      d[2] = (uint32_t)keysum;
+      d[3] = (uint32_t)(keysum >> 32);
+    }
+  }
+  store_scene(a, S, L, rb, status);
+  MS_PHASE(7)
+#undef MS_PHASE
+  if (lane == 0) {
+    if (a.sub0 == 0) a.status[s] = status;
+    else a.status[s] |= status;
+    if (prof) {
+      for (int k = 0; k < 8; ++k) {
+        if (a.sub0 == 0) a.phase_cycles[(size_t)s * 8 + k] = cyc[k];
+        else a.phase_cycles[(size_t)s * 8 + k] += cyc[k];
+      }
+    }
+  }
+}
+
+__global__ __launch_bounds__(WAVE) void k_step(KArgs a) {
+  extern __shared__ float lds[];
+  if (a.persistent) {
+    for (;;) {
+      int idx = 0;
+      if (threadIdx.x == 0) idx = atomicAdd(a.queue, 1);
+      idx = __shfl(idx, 0, WAVE);
+      if (idx >= a.S) break;
+      run_scene(a, a.order[idx], lds);
+      __syncthreads();
+    }
+  } else {
+    int idx = blockIdx.x;
+    if (idx < a.S) run_scene(a, a.order[idx], lds);
+  }
+}
+
+__global__ void k_reset_queue(int* q) {
+  if (threadIdx.x == 0) q[0] = 0;
+}
+
+// dst[scene] = src[scene] where mask[scene] != 0; grid over scenes
+__global__ void k_masked_copy(float* dst, const float* src, const uint8_t* mask, int S, int NF, int NA,
+                              const int* free_off, const int* aux_off) {
+  int s = blockIdx.x;
+  if (s >= S || (mask && !mask[s])) return;
+  int t = threadIdx.x;
+  if (t < ND) {
+    dst[(size_t)s * ND + t] = src[(size_t)s * ND + t];
+    dst[(size_t)S * ND + (size_t)s * ND + t] = src[(size_t)S * ND + (size_t)s * ND + t];
+  }
+  size_t fb = (size_t)S * 2 * ND;
+  for (int i = free_off[s] * 16 + t; i < free_off[s + 1] * 16; i += blockDim.x) dst[fb + i] = src[fb + i];
+  size_t ab = fb + (size_t)NF * 16;
+  for (int i = aux_off[s] * 4 + t; i < aux_off[s + 1] * 4; i += blockDim.x) dst[ab + i] = src[ab + i];
+}
+
+void launch_step(const KArgs& a, int grid, size_t lds_bytes, hipStream_t st) {
+  hipLaunchKernelGGL(k_step, dim3(grid), dim3(WAVE), lds_bytes, st, a);
+}
+void launch_reset_queue(int* q, hipStream_t st) { hipLaunchKernelGGL(k_reset_queue, dim3(1), dim3(64), 0, st, q); }
+void launch_masked_copy(float* dst, const float* src, const uint8_t* mask, int S, int NF, int NA,
+                        const int* free_off, const int* aux_off, hipStream_t st) {
+  if (S <= 0) return;
+  hipLaunchKernelGGL(k_masked_copy, dim3(S), dim3(64), 0, st, dst, src, mask, S, NF, NA, free_off, aux_off);
+}
+const void* step_kernel_ptr() { return reinterpret_cast<const void*>(&k_step); }
+
+}  // namespace msk

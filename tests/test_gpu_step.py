@@ -1,0 +1,258 @@
+"""GPU parity of ms_step against the FP64 oracle (through the C ABI).
+
+Single control steps are teacher-forced: both sides start from the same
+float32-representable states taken along oracle trajectories.  Bars: position
+error <= 1e-5 m and velocity error <= 1e-4 m/s (rad/s) per step, or, where
+larger, 4x the deviation of the oracle's own single-precision evaluation from
+its FP64 result, or 10x the oracle's change under 1-ulp float32 input
+perturbations (contact-rich states amplify rounding: the speculative bias
+scales position rounding by 1/h, Gauss-Seidel on many coupled robot rows
+amplifies it further); 100-step trajectories <= 1e-3 m where the per-substep contact sets
+agree all along and the oracle with float32 rounding noise injected every
+step stays within 1e-3 m of itself (chaos screen).  Contact sets are compared
+per substep through the count and an order-independent sum of mixed keys.
+"""
+import numpy as np
+import pytest
+
+import oracle
+import scenegen as sg
+from _parity import errors, fp32_sensitivity, noisy_fp32_rollout, same_contacts
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+POS_TOL = 1e-5
+VEL_TOL = 1e-4
+
+
+def _ms():
+    import paper_2412_13211_amd as ms
+    return ms
+
+
+def say(*a):
+    print(*a, flush=True)
+
+
+def gpu_step(mb, x, u):
+    xt = torch.as_tensor(np.asarray(x, np.float32)).cuda()
+    ut = torch.as_tensor(np.asarray(u, np.float32)).cuda().contiguous()
+    out = mb.step(xt, ut)
+    torch.cuda.synchronize()
+    return out.cpu().numpy().astype(np.float64)
+
+
+def oracle_states(b, o, steps):
+    """States along the oracle trajectory at the given control steps (float32-rounded)."""
+    x = b.state0.astype(np.float64)
+    out = {}
+    for t in range(max(steps) + 1):
+        if t in steps:
+            out[t] = x.astype(np.float32).astype(np.float64)
+        x = o.step(x, b.controls_for(t))
+    return out
+
+
+CASES = [
+    ("cfg1", lambda: sg.make(1), [0, 10, 40, 80]),
+    ("cfg2", lambda: sg.make(2, 48), [0, 5, 20]),
+    ("cfg3", lambda: sg.make(3, 32), [0, 5, 20]),
+    ("cfg4", lambda: sg.make(4, 16), [0, 10, 30]),
+    ("cfg5", lambda: sg.make(5, 48), [0, 5, 15]),
+]
+
+
+@pytest.mark.parametrize("name,mk,steps", CASES, ids=[c[0] for c in CASES])
+def test_single_step_parity(name, mk, steps):
+    ms = _ms()
+    b = mk()
+    o = oracle.Oracle(b)
+    say(f"[single-step] {name}: S={b.n_scenes} NF={b.n_free} NA={b.n_aux} steps={steps}")
+    mb = ms.MsBatch(b)
+    mb.enable_debug(True)
+    states = oracle_states(b, o, steps)
+    n_match = n_tot = 0
+    worst = (0.0, 0.0)
+    n_relaxed = 0
+    for t, x in states.items():
+        u = b.controls_for(t)
+        xo, d = o.step(x, u, debug=True)
+        xg = gpu_step(mb, x, u)
+        st = mb.status()
+        assert not np.any(st & (ms.MS_ST_NONFINITE | ms.MS_ST_OVERFLOW | ms.MS_ST_ROBOT_OVERFLOW)), st
+        same = same_contacts(d, mb.debug_contacts())
+        pe, ve = errors(o, b, xo, xg)
+        ps, vs = fp32_sensitivity(o, b, x, u)
+        pf, vf = errors(o, b, xo, o.step_f32(x, u))
+        tol_p = np.maximum.reduce([np.full_like(ps, POS_TOL), 10 * ps, 4 * pf])
+        tol_v = np.maximum.reduce([np.full_like(vs, VEL_TOL), 10 * vs, 4 * vf])
+        n_match += int(same.sum())
+        n_tot += len(same)
+        strict = same & (pe <= POS_TOL) & (ve <= VEL_TOL)
+        n_relaxed += int((same & ~strict).sum())
+        if same.any():
+            worst = (max(worst[0], pe[same].max()), max(worst[1], ve[same].max()))
+        say(f"  t={t}: contact sets equal in {same.sum()}/{len(same)} scenes; "
+            f"max pos err {pe[same].max() if same.any() else 0:.3e} m, vel err {ve[same].max() if same.any() else 0:.3e}; "
+            f"within the fixed bars {strict.sum()}")
+        for i in np.nonzero(same & ~strict)[0]:
+            say(f"    scene {i}: pos {pe[i]:.2e} (1-ulp sens {ps[i]:.2e}, fp32 oracle {pf[i]:.2e}), "
+                f"vel {ve[i]:.2e} (1-ulp sens {vs[i]:.2e}, fp32 oracle {vf[i]:.2e})")
+        assert np.all(pe[same] <= tol_p[same]), (t, np.nonzero(pe > tol_p))
+        assert np.all(ve[same] <= tol_v[same]), (t, np.nonzero(ve > tol_v))
+    assert n_match >= 0.8 * n_tot, f"contact sets differ in {n_tot - n_match} of {n_tot} scene-steps"
+    assert n_relaxed <= 0.35 * n_tot, f"{n_relaxed} of {n_tot} scene-steps needed the conditioning-scaled bar"
+    say(f"  worst over matching scenes: pos {worst[0]:.3e} m, vel {worst[1]:.3e}; conditioning-scaled bar used in "
+        f"{n_relaxed}/{n_tot}")
+
+
+def test_free_run_100_steps_cfg1():
+    ms = _ms()
+    b = sg.make(1)
+    o = oracle.Oracle(b)
+    say("[free-run] cfg1 100 control steps")
+    mb = ms.MsBatch(b)
+    mb.enable_debug(True)
+    xo = b.state0.astype(np.float64)
+    controls = [b.controls_for(t) for t in range(100)]
+    xg = torch.as_tensor(b.state0.copy()).cuda()
+    same_all = np.ones(b.n_scenes, bool)
+    for t in range(100):
+        u = controls[t]
+        xo, d = o.step(xo, u, debug=True)
+        xg = mb.step(xg, torch.as_tensor(u).cuda())
+        torch.cuda.synchronize()
+        same_all &= same_contacts(d, mb.debug_contacts())
+    xn = noisy_fp32_rollout(o, b, b.state0, controls)
+    pe, _ = errors(o, b, xo, xg.cpu().numpy())
+    pc, _ = errors(o, b, xo, xn)
+    chaotic = pc > 1e-3
+    keep = same_all & ~chaotic
+    say(f"  contact sets equal all along in {same_all.sum()}/{b.n_scenes}; chaotic {chaotic.sum()}; "
+        f"pos err (kept) max {pe[keep].max() if keep.any() else 0:.3e} m; all scenes max {pe.max():.3e}")
+    for i in range(b.n_scenes):
+        say(f"    scene {i}: gpu err {pe[i]:.2e} m, noisy-oracle err {pc[i]:.2e} m, contacts equal {same_all[i]}")
+    assert keep.sum() >= 4
+    assert np.all(pe[keep] <= 1e-3)
+
+
+def _run_sched(ms, b, flags, x, u, steps=2):
+    mb = ms.MsBatch(b)
+    mb.set_schedule(flags)
+    xt = torch.as_tensor(np.asarray(x, np.float32)).cuda()
+    ut = torch.as_tensor(np.asarray(u, np.float32)).cuda()
+    for _ in range(steps):
+        xt = mb.step(xt, ut, out=xt)
+    torch.cuda.synchronize()
+    return xt.cpu().numpy()
+
+
+def test_schedules_bitwise_equal():
+    ms = _ms()
+    b = sg.make(3, 40)
+    x = b.state0
+    u = b.controls(0)
+    say("[schedules] cfg3 S=40")
+    ref = _run_sched(ms, b, ms.MS_SCHED_STAGE_STATIC, x, u)
+    for flags in [0, ms.MS_SCHED_PERSISTENT, ms.MS_SCHED_GRAPH | ms.MS_SCHED_STAGE_STATIC,
+                  ms.MS_SCHED_GRAPH | ms.MS_SCHED_PERSISTENT | ms.MS_SCHED_STAGE_STATIC,
+                  ms.MS_SCHED_PER_SUBSTEP | ms.MS_SCHED_STAGE_STATIC]:
+        say(f"  flags={flags}")
+        got = _run_sched(ms, b, flags, x, u)
+        assert np.array_equal(got, ref), flags
+
+
+def test_deterministic_reruns():
+    ms = _ms()
+    b = sg.make(2, 24)
+    say("[determinism] cfg2 S=24")
+    a1 = _run_sched(ms, b, ms.MS_SCHED_STAGE_STATIC, b.state0, b.controls(0), steps=3)
+    a2 = _run_sched(ms, b, ms.MS_SCHED_STAGE_STATIC, b.state0, b.controls(0), steps=3)
+    assert np.array_equal(a1, a2)
+
+
+def test_full_size_cfg3_sampled_scenes():
+    """4096 uneven scenes in the benchmark's launch configuration; 24 sampled
+    scenes checked one by one against the oracle on the same scenes."""
+    ms = _ms()
+    b = sg.make(3)
+    say("[full-size] cfg3 S=4096 graph+persistent")
+    mb = ms.MsBatch(b)
+    mb.set_schedule(ms.MS_SCHED_GRAPH | ms.MS_SCHED_PERSISTENT | ms.MS_SCHED_STAGE_STATIC)
+    mb.enable_debug(True)
+    u = b.controls(0)
+    xg = gpu_step(mb, b.state0, u)
+    dbg = mb.debug_contacts()
+    st = mb.status()
+    assert not np.any(st & (ms.MS_ST_NONFINITE | ms.MS_ST_OVERFLOW | ms.MS_ST_ROBOT_OVERFLOW))
+    rng = np.random.default_rng(0)
+    pick = sorted(rng.choice(b.n_scenes, 24, replace=False).tolist())
+    sub = b.subset(pick)
+    o = oracle.Oracle(sub)
+    xo, d = o.step(sub.state0.astype(np.float64), u[pick], debug=True)
+    # gather the sampled scenes from the full GPU state
+    full = sg.split_state(xg, b.n_scenes, b.n_free, b.n_aux)
+    fidx = np.concatenate([np.arange(b.free_off[s], b.free_off[s + 1]) for s in pick])
+    aidx = np.concatenate([np.arange(b.aux_off[s], b.aux_off[s + 1]) for s in pick]).astype(int)
+    xs = sg.join_state(full["q"][pick], full["qd"][pick], full["free"][fidx], full["aux"][aidx])
+    same = same_contacts(d, dbg[pick])
+    pe, ve = errors(o, sub, xo, xs)
+    say(f"  sampled: contacts equal {same.sum()}/24; pos {pe[same].max():.3e} vel {ve[same].max():.3e}")
+    assert same.sum() >= 20
+    assert np.all(pe[same] <= POS_TOL) and np.all(ve[same] <= VEL_TOL)
+
+
+def test_edge_cases_empty_robot_and_no_objects():
+    ms = _ms()
+    box = sg.box_object((0.1, 0.1, 0.1), 1.0, (0.0, 0.0, 0.1), vel=(0.5, 0.0, 0.0))
+    sph = sg.sphere_object(0.05, 0.3, (0.3, 0.0, 0.2))
+    scenes = [dict(free=[box, sph], planes=[(0, 0, 1, 0)]), dict(planes=[(0, 0, 1, 0)]),
+              dict(free=[sph]), dict(free=[box], static=[(0.0, 0.0, -0.5, 1.0, 1.0, 0.5)])]
+    b = sg.custom_batch([sg.empty_model()], scenes, h=0.002, n_sub=5, pgs_iters=10)
+    say("[edge] empty robot / no objects / no planes")
+    o = oracle.Oracle(b)
+    mb = ms.MsBatch(b)
+    mb.enable_debug(True)
+    x = b.state0.astype(np.float64)
+    for t in range(5):
+        xo, d = o.step(x, np.zeros((b.n_scenes, 16)), debug=True)
+        xg = gpu_step(mb, x, np.zeros((b.n_scenes, 16)))
+        same = same_contacts(d, mb.debug_contacts())
+        pe, ve = errors(o, b, xo, xg)
+        assert same.all()
+        assert np.all(pe <= POS_TOL) and np.all(ve <= VEL_TOL), (pe, ve)
+        x = xo
+
+
+def test_contact_cap_overflow_flagged():
+    ms = _ms()
+    boxes = [sg.box_object((0.05, 0.05, 0.05), 0.5, (0.3 * k, 0.0, 0.05)) for k in range(4)]
+    b = sg.custom_batch([sg.empty_model()], [dict(free=boxes, planes=[(0, 0, 1, 0)])], contact_cap=6)
+    say("[edge] contact cap overflow")
+    mb = ms.MsBatch(b)
+    gpu_step(mb, b.state0, np.zeros((1, 16)))
+    st = mb.status()
+    assert st[0] & ms.MS_ST_OVERFLOW
+    # the oracle keeps the same first 6 contacts in canonical order
+    o = oracle.Oracle(b)
+    xo = o.step(b.state0.astype(np.float64), np.zeros((1, 16)))
+    xg = gpu_step(mb, b.state0, np.zeros((1, 16)))
+    pe, ve = errors(o, b, xo, xg)
+    assert pe.max() <= POS_TOL and ve.max() <= VEL_TOL
+
+
+def test_invalid_arguments_leave_state_untouched():
+    ms = _ms()
+    b = sg.make(1, 2)
+    mb = ms.MsBatch(b)
+    x = torch.as_tensor(b.state0.copy()).cuda()
+    before = x.clone()
+    with pytest.raises(ms.MsError):
+        mb.step(x, torch.zeros(3, 16, device="cuda"))           # wrong control shape
+    with pytest.raises(ms.MsError):
+        mb.step(x[:-1], torch.zeros(2, 16, device="cuda"))      # wrong state size
+    with pytest.raises(ms.MsError):
+        mb.set_schedule(1 << 10)
+    torch.cuda.synchronize()
+    assert torch.equal(x, before)

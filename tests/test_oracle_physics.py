@@ -290,3 +290,18 @@ def test_level_schedule_equals_sequential_order():
             for k in ks:
                 upd(par, k, *rows[k])
         assert seq == par
+
+
+def test_fp32_evaluation_close_to_fp64():
+    """The oracle's single-precision evaluation (used to scale the GPU parity
+    bar in ill-conditioned states) stays near FP64 on a contact-free step."""
+    mb = sg.model_builder()
+    b0 = mb.body(-1, sg.JT_REVOLUTE, (0, 1, 0), (0, 0, 2.0), 1.0, (0.15, 0, 0), (0.01, 0.01, 0.01))
+    mb.body(b0, sg.JT_REVOLUTE, (0, 1, 0), (0.3, 0, 0), 0.6, (0.12, 0, 0), (0.005, 0.005, 0.005))
+    q = np.zeros(16)
+    q[0], q[1] = 0.4, -0.8
+    b = sg.custom_batch([mb.arrays()], [dict(q=q)], h=0.002, n_sub=5)
+    o = oracle.Oracle(b)
+    x = b.state0.astype(np.float64)
+    d = np.abs(o.step(x, np.zeros((1, 16))) - o.step_f32(x, np.zeros((1, 16))))
+    assert d.max() < 1e-5 and d.max() > 0.0
