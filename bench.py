@@ -156,7 +156,7 @@ def main():
         gpu_ms = ev[0].elapsed_time(ev[1])
         return wall, gpu_ms
 
-    flags_graph = ms.MS_SCHED_GRAPH | ms.MS_SCHED_STAGE_STATIC
+    flags_graph = ms.MS_SCHED_GRAPH | ms.MS_SCHED_STAGE_STATIC | ms.MS_SCHED_CULL
     if args.schedule == "auto":
         (flags, grid), t_auto = mb.autotune(x0, U[0], reps=3)
     elif args.schedule == "graph":
@@ -164,11 +164,12 @@ def main():
     elif args.schedule == "graph-persistent":
         flags = flags_graph | ms.MS_SCHED_PERSISTENT
     else:
-        flags = ms.MS_SCHED_STAGE_STATIC | ms.MS_SCHED_PER_SUBSTEP
+        flags = ms.MS_SCHED_STAGE_STATIC | ms.MS_SCHED_PER_SUBSTEP | ms.MS_SCHED_CULL
     print(f"[bench] schedule flags {flags}", file=sys.stderr, flush=True)
     wall, gpu_ms = run(args.steps, flags, True)
     # the plain form: one launch per substep, no graph, same kernel
-    wall_plain, gpu_ms_plain = run(args.steps, ms.MS_SCHED_STAGE_STATIC | ms.MS_SCHED_PER_SUBSTEP, True)
+    wall_plain, gpu_ms_plain = run(args.steps, ms.MS_SCHED_STAGE_STATIC | ms.MS_SCHED_PER_SUBSTEP | ms.MS_SCHED_CULL,
+                                   True)
     st = mb.status()
     value = S * args.steps / wall
     ms_per_step = 1e3 * wall / args.steps

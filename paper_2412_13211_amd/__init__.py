@@ -137,7 +137,8 @@ def make_desc(batch, **over):
     d.pgs_iters = int(g("pgs_iters"))
     d.control_mode = int(g("control_mode"))
     d.contact_cap = int(g("contact_cap"))
-    d.robot_contact_cap = int(over.get("robot_contact_cap", min(int(g("contact_cap")), 32)))
+    d.robot_contact_cap = int(over.get("robot_contact_cap",
+                                       getattr(batch, "robot_contact_cap", min(int(g("contact_cap")), 32))))
     d.h = float(g("h"))
     d.mu = float(g("mu"))
     d.baumgarte = float(g("baumgarte"))

@@ -7,6 +7,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <cmath>
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
@@ -356,6 +357,32 @@ ms_status ms_create_batch(const ms_batch_desc* d, const ms_scene_desc* sc, void*
       M.sph_body[k] = sc->model_sph_body[m * SPH + k];
       M.sph_flags[k] = sc->model_sph_flags[m * SPH + k];
     }
+    // per-body sphere ranges and bounding spheres (centre = mean of the
+    // sphere centres, radius = max distance + sphere radius)
+    for (int i = 0; i < ND; ++i) {
+      M.sph_first[i] = 0;
+      M.sph_count[i] = 0;
+      M.bsph[i] = make_float4(0.f, 0.f, 0.f, 0.f);
+    }
+    for (int k = M.nsph - 1; k >= 0; --k) {
+      int bi = M.sph_body[k];
+      M.sph_first[bi] = k;
+      M.sph_count[bi] += 1;
+    }
+    for (int i = 0; i < M.nb; ++i) {
+      if (M.sph_count[i] == 0) continue;
+      double c[3] = {0, 0, 0};
+      for (int k = M.sph_first[i]; k < M.sph_first[i] + M.sph_count[i]; ++k) {
+        c[0] += M.sph[k].x; c[1] += M.sph[k].y; c[2] += M.sph[k].z;
+      }
+      for (int t = 0; t < 3; ++t) c[t] /= M.sph_count[i];
+      double r = 0.0;
+      for (int k = M.sph_first[i]; k < M.sph_first[i] + M.sph_count[i]; ++k) {
+        double dx = M.sph[k].x - c[0], dy = M.sph[k].y - c[1], dz = M.sph[k].z - c[2];
+        r = std::max(r, std::sqrt(dx * dx + dy * dy + dz * dz) + M.sph[k].w);
+      }
+      M.bsph[i] = make_float4((float)c[0], (float)c[1], (float)c[2], (float)r);
+    }
   }
   DScene* scenes = reinterpret_cast<DScene*>(host.data() + pl.scenes);
   std::vector<std::pair<long, int>> cost(c.S);
@@ -430,7 +457,7 @@ ms_status ms_create_batch(const ms_batch_desc* d, const ms_scene_desc* sc, void*
   b->max_lds = std::max(b->max_lds, opt);
   b->free_off.assign(sc->free_off, sc->free_off + c.S + 1);
   b->aux_off.assign(sc->aux_off, sc->aux_off + c.S + 1);
-  b->sched.flags = MS_SCHED_STAGE_STATIC;
+  b->sched.flags = MS_SCHED_STAGE_STATIC | MS_SCHED_CULL;
   b->sched.grid = 0;
   b->debug_on = false;
   b->profile_on = false;
@@ -589,7 +616,7 @@ ms_status ms_autotune(ms_batch* b, const void* x, const float* u, void* tmp, int
   if (reps <= 0) reps = 5;
   hipStream_t st = static_cast<hipStream_t>(hip_stream);
   const ms_schedule saved = b->sched;
-  const int base_flags[] = {MS_SCHED_GRAPH, MS_SCHED_GRAPH | MS_SCHED_PERSISTENT};
+  const int base_flags[] = {MS_SCHED_GRAPH | MS_SCHED_CULL, MS_SCHED_GRAPH | MS_SCHED_PERSISTENT | MS_SCHED_CULL};
   const int stage_opts[] = {MS_SCHED_STAGE_STATIC, 0};
   ms_schedule best = saved;
   float best_ms = 1e30f;

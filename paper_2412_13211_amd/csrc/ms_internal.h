@@ -36,6 +36,9 @@ struct DModel {
   float4 sph[SPH];      // centre (body frame), radius
   int sph_body[SPH];
   int sph_flags[SPH];
+  int sph_first[ND];    // spheres of body i: [sph_first, sph_first + sph_count)
+  int sph_count[ND];
+  float4 bsph[ND];      // bounding sphere of body i's spheres (body frame centre, radius)
 };
 
 struct DScene {
@@ -66,18 +69,23 @@ struct DAux {
 
 // Offsets (in floats) of the regions of one scene's LDS block.
 struct LdsLayout {
-  int fmax, smax, ccap, rcap, owners;
-  int robot, sph, fr, aux, stat, plane, own, con, rows, lvl, total;
+  int fmax, smax, ccap, rcap, owners, ntmax;
+  int robot, sph, fr, aux, stat, plane, own, con, rows, lvl, cand, total;
 };
 
 __host__ __device__ inline int lds_align4(int x) { return (x + 3) & ~3; }
 
-// Robot block: q qd tau arm u vR [6*16]; R[16*9] p[16*3] s[16*6]; ABA: IA[16*36]
-// pA[16*6] c[16*6] U[16*6] D[16] uu[16] qdd[16]; Minv[16*16]; tables T[16*16] S2[16*16]
-constexpr int ROBOT_FLOATS = 6 * ND + ND * 9 + ND * 3 + ND * 6 + ND * 36 + ND * 6 * 3 + ND * 3 + ND * ND * 3;
-constexpr int FREE_FLOATS = 40;     // per free body
+// Robot block (persistent over a substep): q qd tau arm u vst [6*16]; R[16*9]
+// p[16*3] s[16*6]; D uu qdd [3*16]; Minv[16*16].
+constexpr int ROBOT_FLOATS = 6 * ND + ND * 9 + ND * 3 + ND * 6 + ND * 3 + ND * ND;
+// Articulated-body scratch (only inside the dynamics phase, shares the space of
+// the robot contact rows): IA[16*36] pA c U [3*16*6] T S2 [2*16*16] Ia[48] Uc[16*16].
+constexpr int DYN_FLOATS = ND * 36 + 3 * ND * 6 + 3 * ND * ND + 48;
+constexpr int FREE_FLOATS = 41;     // per free body (odd stride: conflict-free LDS banks)
+constexpr int FSTR = FREE_FLOATS;
 constexpr int AUX_FLOATS = 40;      // per aux joint
-constexpr int CON_FLOATS = 16;      // per contact
+constexpr int CON_FLOATS = 17;      // per contact (odd stride)
+constexpr int CSTR = CON_FLOATS;
 constexpr int ROW_FLOATS = 6 * ND;  // per robot contact: J[3][16], w[3][16]
 
 __host__ __device__ inline LdsLayout make_layout(int fmax, int smax, int ccap, int rcap, int stage_static) {
@@ -87,6 +95,7 @@ __host__ __device__ inline LdsLayout make_layout(int fmax, int smax, int ccap, i
   L.ccap = ccap;
   L.rcap = rcap;
   L.owners = fmax * 8;
+  L.ntmax = PMAX + smax + AMAX + fmax;
   int o = 0;
   L.robot = o; o += lds_align4(ROBOT_FLOATS);
   L.sph = o;   o += SPH * 4;
@@ -96,8 +105,9 @@ __host__ __device__ inline LdsLayout make_layout(int fmax, int smax, int ccap, i
   L.plane = o; o += PMAX * 4;
   L.own = o;   o += lds_align4((L.owners + 1) / 2);        // uint16 owner table
   L.con = o;   o += lds_align4(ccap * CON_FLOATS);
-  L.rows = o;  o += lds_align4(rcap * ROW_FLOATS);
+  L.rows = o;  o += lds_align4(rcap * ROW_FLOATS > DYN_FLOATS ? rcap * ROW_FLOATS : DYN_FLOATS);
   L.lvl = o;   o += lds_align4(3 * ccap + 4 + (ccap + 1) / 2);  // level, level offsets, robot row per level, order
+  L.cand = o;  o += lds_align4(L.ntmax);                       // two uint16 candidate lists
   L.total = o;
   return L;
 }

@@ -40,6 +40,11 @@ __device__ __forceinline__ f3 mtv(const float* R, f3 v) {
   return {R[0] * v.x + R[3] * v.y + R[6] * v.z, R[1] * v.x + R[4] * v.y + R[7] * v.z,
           R[2] * v.x + R[5] * v.y + R[8] * v.z};
 }
+// symmetric 3x3 stored as xx yy zz xy xz yz
+__device__ __forceinline__ f3 smv(const float* S, f3 v) {
+  return {S[0] * v.x + S[3] * v.y + S[4] * v.z, S[3] * v.x + S[1] * v.y + S[5] * v.z,
+          S[4] * v.x + S[5] * v.y + S[2] * v.z};
+}
 __device__ __forceinline__ void mm(const float* A, const float* B, float* C) {
 #pragma unroll
   for (int i = 0; i < 3; ++i)
@@ -121,10 +126,13 @@ __device__ __forceinline__ void crf(const float* v, const float* f, float* out) 
 struct Robot {
   float *q, *qd, *tau, *arm, *u, *vst;  // [16] each (vst: unconstrained velocity)
   float *R, *p, *s;                     // [16][9], [16][3], [16][6]
-  float *IA, *pA, *cc, *U, *D, *uu, *qdd;
-  float *Minv, *T, *S2;                 // [16][16]
+  float *D, *uu, *qdd;                  // [16]
+  float *Minv;                          // [16][16]
+  // articulated-body scratch, valid only inside the dynamics phase (it shares
+  // the LDS of the robot contact rows, which are built afterwards)
+  float *IA, *pA, *cc, *U, *T, *S2, *Ia, *Uc;
 };
-__device__ __forceinline__ Robot robot_view(float* base) {
+__device__ __forceinline__ Robot robot_view(float* base, float* dyn) {
   Robot r;
   float* o = base;
   r.q = o; o += ND;
@@ -136,16 +144,19 @@ __device__ __forceinline__ Robot robot_view(float* base) {
   r.R = o; o += ND * 9;
   r.p = o; o += ND * 3;
   r.s = o; o += ND * 6;
-  r.IA = o; o += ND * 36;
-  r.pA = o; o += ND * 6;
-  r.cc = o; o += ND * 6;
-  r.U = o; o += ND * 6;
   r.D = o; o += ND;
   r.uu = o; o += ND;
   r.qdd = o; o += ND;
   r.Minv = o; o += ND * ND;
+  o = dyn;
+  r.IA = o; o += ND * 36;
+  r.pA = o; o += ND * 6;
+  r.cc = o; o += ND * 6;
+  r.U = o; o += ND * 6;
   r.T = o; o += ND * ND;
   r.S2 = o; o += ND * ND;
+  r.Ia = o; o += 48;
+  r.Uc = o; o += ND * ND;
   return r;
 }
 // free-body fields (structure of arrays, stride fmax)
@@ -212,7 +223,7 @@ struct Scene {
   int s, nb, nsph, nf, ns, np, na, nfo, f0, s0, p0, a0;
 };
 
-__device__ void load_scene(const KArgs& a, const Scene& S, float* L, const Robot& rb) {
+__device__ __forceinline__ void load_scene(const KArgs& a, const Scene& S, float* L, const Robot& rb) {
   const int lane = lane_id();
   const LdsLayout& Y = a.L;
   if (lane < ND) {
@@ -228,16 +239,16 @@ __device__ void load_scene(const KArgs& a, const Scene& S, float* L, const Robot
     float4 x1 = *reinterpret_cast<const float4*>(xs + 4);
     float4 x2 = *reinterpret_cast<const float4*>(xs + 8);
     float4 x3 = *reinterpret_cast<const float4*>(xs + 12);
-    F[(F_X + 0) * fm + f] = x0.x; F[(F_X + 1) * fm + f] = x0.y; F[(F_X + 2) * fm + f] = x0.z;
-    F[(F_Q + 0) * fm + f] = x1.x; F[(F_Q + 1) * fm + f] = x1.y; F[(F_Q + 2) * fm + f] = x1.z;
-    F[(F_Q + 3) * fm + f] = x1.w;
-    F[(F_V + 0) * fm + f] = x2.x; F[(F_V + 1) * fm + f] = x2.y; F[(F_V + 2) * fm + f] = x2.z;
-    F[(F_W + 0) * fm + f] = x3.x; F[(F_W + 1) * fm + f] = x3.y; F[(F_W + 2) * fm + f] = x3.z;
+    F[(f) * FSTR + F_X + 0] = x0.x; F[(f) * FSTR + F_X + 1] = x0.y; F[(f) * FSTR + F_X + 2] = x0.z;
+    F[(f) * FSTR + F_Q + 0] = x1.x; F[(f) * FSTR + F_Q + 1] = x1.y; F[(f) * FSTR + F_Q + 2] = x1.z;
+    F[(f) * FSTR + F_Q + 3] = x1.w;
+    F[(f) * FSTR + F_V + 0] = x2.x; F[(f) * FSTR + F_V + 1] = x2.y; F[(f) * FSTR + F_V + 2] = x2.z;
+    F[(f) * FSTR + F_W + 0] = x3.x; F[(f) * FSTR + F_W + 1] = x3.y; F[(f) * FSTR + F_W + 2] = x3.z;
     DFree d = a.free[S.f0 + f];
-    F[F_IM * fm + f] = 1.f / d.mass;
-    F[F_TYPE * fm + f] = (float)d.type;
-    F[(F_H + 0) * fm + f] = d.half[0]; F[(F_H + 1) * fm + f] = d.half[1]; F[(F_H + 2) * fm + f] = d.half[2];
-    F[(F_IB + 0) * fm + f] = d.Ib[0]; F[(F_IB + 1) * fm + f] = d.Ib[1]; F[(F_IB + 2) * fm + f] = d.Ib[2];
+    F[(f) * FSTR + F_IM] = 1.f / d.mass;
+    F[(f) * FSTR + F_TYPE] = (float)d.type;
+    F[(f) * FSTR + F_H + 0] = d.half[0]; F[(f) * FSTR + F_H + 1] = d.half[1]; F[(f) * FSTR + F_H + 2] = d.half[2];
+    F[(f) * FSTR + F_IB + 0] = d.Ib[0]; F[(f) * FSTR + F_IB + 1] = d.Ib[1]; F[(f) * FSTR + F_IB + 2] = d.Ib[2];
   }
   float* A = L + Y.aux;
   if (lane < S.na) {
@@ -278,7 +289,7 @@ __device__ void load_scene(const KArgs& a, const Scene& S, float* L, const Robot
   wave_sync();
 }
 
-__device__ void store_scene(const KArgs& a, const Scene& S, float* L, const Robot& rb, uint32_t& status) {
+__device__ __forceinline__ void store_scene(const KArgs& a, const Scene& S, float* L, const Robot& rb, uint32_t& status) {
   const int lane = lane_id();
   const LdsLayout& Y = a.L;
   bool bad = false;
@@ -292,11 +303,11 @@ __device__ void store_scene(const KArgs& a, const Scene& S, float* L, const Robo
   const int fm = Y.fmax;
   for (int f = lane; f < S.nf; f += WAVE) {
     float* xs = a.x_out + (size_t)a.S * 2 * ND + (size_t)(S.f0 + f) * 16;
-    float4 x0 = make_float4(F[(F_X + 0) * fm + f], F[(F_X + 1) * fm + f], F[(F_X + 2) * fm + f], 0.f);
-    float4 x1 = make_float4(F[(F_Q + 0) * fm + f], F[(F_Q + 1) * fm + f], F[(F_Q + 2) * fm + f],
-                            F[(F_Q + 3) * fm + f]);
-    float4 x2 = make_float4(F[(F_V + 0) * fm + f], F[(F_V + 1) * fm + f], F[(F_V + 2) * fm + f], 0.f);
-    float4 x3 = make_float4(F[(F_W + 0) * fm + f], F[(F_W + 1) * fm + f], F[(F_W + 2) * fm + f], 0.f);
+    float4 x0 = make_float4(F[(f) * FSTR + F_X + 0], F[(f) * FSTR + F_X + 1], F[(f) * FSTR + F_X + 2], 0.f);
+    float4 x1 = make_float4(F[(f) * FSTR + F_Q + 0], F[(f) * FSTR + F_Q + 1], F[(f) * FSTR + F_Q + 2],
+                            F[(f) * FSTR + F_Q + 3]);
+    float4 x2 = make_float4(F[(f) * FSTR + F_V + 0], F[(f) * FSTR + F_V + 1], F[(f) * FSTR + F_V + 2], 0.f);
+    float4 x3 = make_float4(F[(f) * FSTR + F_W + 0], F[(f) * FSTR + F_W + 1], F[(f) * FSTR + F_W + 2], 0.f);
     bad |= !isfinite(x0.x + x0.y + x0.z + x1.x + x1.y + x1.z + x1.w + x2.x + x2.y + x2.z + x3.x + x3.y + x3.z);
     *reinterpret_cast<float4*>(xs) = x0;
     *reinterpret_cast<float4*>(xs + 4) = x1;
@@ -314,7 +325,7 @@ __device__ void store_scene(const KArgs& a, const Scene& S, float* L, const Robo
 }
 
 // ---------------------------------------------------------------- phases
-__device__ void phase_drive(const KArgs& a, const Scene& S, const Robot& rb) {
+__device__ __forceinline__ void phase_drive(const KArgs& a, const Scene& S, const Robot& rb) {
   const int j = lane_id();
   if (j < S.nb) {
     const DModel* M = S.M;
@@ -344,7 +355,7 @@ __device__ void phase_drive(const KArgs& a, const Scene& S, const Robot& rb) {
 }
 
 // world frames by pointer jumping over the tree; spheres; free and aux frames
-__device__ void phase_kinematics(const KArgs& a, const Scene& S, float* L, const Robot& rb) {
+__device__ __forceinline__ void phase_kinematics(const KArgs& a, const Scene& S, float* L, const Robot& rb) {
   const int lane = lane_id();
   const DModel* M = S.M;
   const int nb = S.nb;
@@ -412,13 +423,17 @@ __device__ void phase_kinematics(const KArgs& a, const Scene& S, float* L, const
   const int fm = a.L.fmax;
   for (int f = lane; f < S.nf; f += WAVE) {
     float R[9];
-    quat_to_R(F[(F_Q + 0) * fm + f], F[(F_Q + 1) * fm + f], F[(F_Q + 2) * fm + f], F[(F_Q + 3) * fm + f], R);
-    float ib[3] = {1.f / F[(F_IB + 0) * fm + f], 1.f / F[(F_IB + 1) * fm + f], 1.f / F[(F_IB + 2) * fm + f]};
-    for (int t = 0; t < 9; ++t) F[(F_R + t) * fm + f] = R[t];
-    for (int i = 0; i < 3; ++i)
-      for (int j = 0; j < 3; ++j)
-        F[(F_II + i * 3 + j) * fm + f] = R[i * 3] * ib[0] * R[j * 3] + R[i * 3 + 1] * ib[1] * R[j * 3 + 1] +
-                                          R[i * 3 + 2] * ib[2] * R[j * 3 + 2];
+    quat_to_R(F[(f) * FSTR + F_Q + 0], F[(f) * FSTR + F_Q + 1], F[(f) * FSTR + F_Q + 2], F[(f) * FSTR + F_Q + 3], R);
+    float ib[3] = {1.f / F[(f) * FSTR + F_IB + 0], 1.f / F[(f) * FSTR + F_IB + 1], 1.f / F[(f) * FSTR + F_IB + 2]};
+    for (int t = 0; t < 9; ++t) F[(f) * FSTR + F_R + t] = R[t];
+    // world inverse inertia R diag(1/Ib) R^T, symmetric: xx yy zz xy xz yz
+    const int ii_r[6] = {0, 1, 2, 0, 0, 1}, ii_c[6] = {0, 1, 2, 1, 2, 2};
+#pragma unroll
+    for (int e = 0; e < 6; ++e) {
+      int i = ii_r[e], j = ii_c[e];
+      F[(f) * FSTR + F_II + e] = R[i * 3] * ib[0] * R[j * 3] + R[i * 3 + 1] * ib[1] * R[j * 3 + 1] +
+                                 R[i * 3 + 2] * ib[2] * R[j * 3 + 2];
+    }
   }
   // aux joints: moving frame and world box centre
   float* A = L + a.L.aux;
@@ -457,35 +472,306 @@ __device__ void phase_kinematics(const KArgs& a, const Scene& S, float* L, const
   wave_sync();
 }
 
-// Contact generation in canonical order: owners (robot spheres by index,
-// then free-body vertices / spheres by body and vertex), targets (planes,
-// furniture boxes, door / drawer boxes, free bodies by index).
-__device__ void phase_contacts(const KArgs& a, const Scene& S, float* L, int& NC, int& NR, int& NL,
+// ---------------------------------------------------------------- contacts
+__device__ __forceinline__ f3 body_p(const Robot& rb, int i) {
+  return mk3(rb.p[i * 3], rb.p[i * 3 + 1], rb.p[i * 3 + 2]);
+}
+// Canonical order: owners (robot spheres by index, then free-body vertices /
+// spheres by body and vertex), targets (planes, furniture boxes, door /
+// drawer boxes, free bodies by index).  Both drivers below evaluate pairs
+// with the same function and emit hits through the same ballot compaction in
+// pair order, so the contact list is the canonical prefix of the hits.
+
+struct ConCtx {
+  const DModel* M;
+  float* C;
+  int cc;
+  const float* SW;
+  const float* F;
+  int fm;
+  const float* A;
+  const float* Pl;
+  const uint16_t* own;
+  const float* St;
+  int nsph, np, ns, na, nf, NT;
+  float margin;
+};
+
+struct PairOut {
+  float phi;
+  f3 n, c;
+  float r;
+  int aside, bside;
+  uint32_t okey, tkey;
+};
+
+// owner o: robot sphere (o < nsph) or free-body owner o - nsph
+__device__ __forceinline__ void owner_geom(const ConCtx& X, int o, f3& c, float& r, int& okind, int& oidx, int& of,
+                                           int& ovk, int& oflags) {
+  of = -1;
+  ovk = 0;
+  oflags = 0;
+  if (o < X.nsph) {
+    c = mk3(X.SW[o * 4], X.SW[o * 4 + 1], X.SW[o * 4 + 2]);
+    r = X.SW[o * 4 + 3];
+    oflags = X.M->sph_flags[o];
+    oidx = X.M->sph_body[o];
+    okind = 0;
+  } else {
+    int ow = X.own[o - X.nsph];
+    of = ow >> 3;
+    ovk = ow & 7;
+    const float* F = X.F;
+    const int fm = X.fm;
+    f3 x = mk3(F[(of) * FSTR + F_X + 0], F[(of) * FSTR + F_X + 1], F[(of) * FSTR + F_X + 2]);
+    oidx = of;
+    if (F[(of) * FSTR + F_TYPE] == 0.f) {
+      f3 hl = mk3((ovk & 1) ? F[(of) * FSTR + F_H + 0] : -F[(of) * FSTR + F_H + 0],
+                  (ovk & 2) ? F[(of) * FSTR + F_H + 1] : -F[(of) * FSTR + F_H + 1],
+                  (ovk & 4) ? F[(of) * FSTR + F_H + 2] : -F[(of) * FSTR + F_H + 2]);
+      float Rf[9];
+      for (int k = 0; k < 9; ++k) Rf[k] = F[(of) * FSTR + F_R + k];
+      c = x + mv(Rf, hl);
+      r = 0.f;
+      okind = 1;
+    } else {
+      c = x;
+      r = F[(of) * FSTR + F_H + 0];
+      okind = 2;
+    }
+  }
+}
+
+// exact pair test of owner o against target t; false when the pair is not allowed
+__device__ __forceinline__ bool eval_pair(const ConCtx& X, int o, int t, PairOut& out, bool& isrob) {
+  f3 c;
+  float r;
+  int okind, oidx, of, ovk, oflags;
+  owner_geom(X, o, c, r, okind, oidx, of, ovk, oflags);
+  isrob = okind == 0;
+  float phi = 1e30f;
+  f3 nrm = mk3(0.f, 0.f, 1.f);
+  int tkey = 0, bside = 0;
+  bool allowed = true;
+  const float* F = X.F;
+  const int fm = X.fm;
+  const float* A = X.A;
+  if (t < X.np) {
+    allowed = !(t == 0 && okind == 0 && (oflags & 1));
+    if (allowed) {
+      f3 pn = mk3(X.Pl[t * 4], X.Pl[t * 4 + 1], X.Pl[t * 4 + 2]);
+      phi = dot(pn, c) - X.Pl[t * 4 + 3] - r;
+      nrm = pn;
+    }
+    tkey = t;
+    bside = K_STATIC << 8;
+  } else if (t < X.np + X.ns) {
+    int bi = t - X.np;
+    const float* bx = X.St + bi * 6;
+    phi = box_test(c, r, mk3(bx[0], bx[1], bx[2]), nullptr, mk3(bx[3], bx[4], bx[5]), nrm);
+    tkey = (1 << 24) | bi;
+    bside = K_STATIC << 8;
+  } else if (t < X.np + X.ns + X.na) {
+    int x = t - X.np - X.ns;
+    float Rx[9];
+    for (int k = 0; k < 9; ++k) Rx[k] = A[(A_R + k) * AMAX + x];
+    phi = box_test(c, r, mk3(A[(A_BC + 0) * AMAX + x], A[(A_BC + 1) * AMAX + x], A[(A_BC + 2) * AMAX + x]), Rx,
+                   mk3(A[(A_BH + 0) * AMAX + x], A[(A_BH + 1) * AMAX + x], A[(A_BH + 2) * AMAX + x]), nrm);
+    tkey = (2 << 24) | x;
+    bside = (K_AUX << 8) | x;
+  } else {
+    int g = t - X.np - X.ns - X.na;
+    bool gbox = F[(g) * FSTR + F_TYPE] == 0.f;
+    allowed = g != of;
+    if (!gbox && okind == 1) allowed = false;           // box vertices skip free spheres
+    if (!gbox && okind == 2 && g <= of) allowed = false;  // sphere pairs once
+    if (allowed) {
+      f3 xg = mk3(F[(g) * FSTR + F_X + 0], F[(g) * FSTR + F_X + 1], F[(g) * FSTR + F_X + 2]);
+      if (gbox) {
+        float Rg[9];
+        for (int k = 0; k < 9; ++k) Rg[k] = F[(g) * FSTR + F_R + k];
+        phi = box_test(c, r, xg, Rg, mk3(F[(g) * FSTR + F_H + 0], F[(g) * FSTR + F_H + 1], F[(g) * FSTR + F_H + 2]), nrm);
+      } else {
+        f3 d = c - xg;
+        float dist = sqrtf(dot(d, d));
+        phi = dist - r - F[(g) * FSTR + F_H + 0];
+        nrm = dist < 1e-12f ? mk3(0.f, 0.f, 1.f) : d * (1.f / dist);
+      }
+    }
+    tkey = (3 << 24) | g;
+    bside = (K_FREE << 8) | g;
+  }
+  out.phi = phi;
+  out.n = nrm;
+  out.c = c;
+  out.r = r;
+  out.aside = okind == 0 ? ((K_ROBOT << 8) | oidx) : ((K_FREE << 8) | of);
+  out.bside = bside;
+  out.okey = okind == 0 ? (uint32_t)o : ((1u << 24) | ((uint32_t)of << 3) | (uint32_t)ovk);
+  out.tkey = (uint32_t)tkey;
+  return allowed && phi < X.margin;
+}
+
+struct EmitState {
+  int n, nr;
+  bool over, rover;
+  uint64_t ks;
+};
+
+// wave-collective: append this lane's hit at its canonical position
+__device__ __forceinline__ void emit(const ConCtx& X, int rcap, bool hit, bool isrob, const PairOut& po,
+                                     EmitState& E) {
+  uint64_t mr = __ballot(hit && isrob);
+  int rpos = E.nr + prefix_below(mr);
+  bool keep = hit && (!isrob || rpos < rcap);
+  if (hit && isrob && rpos >= rcap) E.rover = true;
+  uint64_t mk = __ballot(keep);
+  int pos = E.n + prefix_below(mk);
+  if (keep && pos >= X.cc) {
+    keep = false;
+    E.over = true;
+  }
+  if (keep) {
+    float* C = X.C;
+    const int cc = X.cc;
+    C[(pos) * CSTR + C_INFO] = __int_as_float(po.aside | (po.bside << 16));
+    f3 p = po.c - po.n * po.r;
+    C[(pos) * CSTR + C_N + 0] = po.n.x; C[(pos) * CSTR + C_N + 1] = po.n.y; C[(pos) * CSTR + C_N + 2] = po.n.z;
+    C[(pos) * CSTR + C_P + 0] = p.x; C[(pos) * CSTR + C_P + 1] = p.y; C[(pos) * CSTR + C_P + 2] = p.z;
+    C[(pos) * CSTR + C_PHI] = po.phi;
+    E.ks += mix64(((uint64_t)po.okey << 32) | po.tkey);
+  }
+  uint64_t mkept = __ballot(keep);
+  E.n = min(E.n + __popcll(mkept), X.cc);
+  E.nr += __popcll(__ballot(keep && isrob));
+}
+
+// q = i / n, r = i - q n for small non-negative i and n > 0
+__device__ __forceinline__ void divmod(int i, int n, float inv, int& q, int& r) {
+  q = (int)(((float)i + 0.5f) * inv);
+  r = i - q * n;
+  if (r < 0) { --q; r += n; }
+  if (r >= n) { ++q; r -= n; }
+}
+
+// wave-collective ordered compaction: out[] = item(i) for the i in [0, N)
+// with pred(item(i)), in increasing i
+template <class I, class P>
+__device__ __forceinline__ int compact(int N, uint16_t* out, I item, P pred) {
+  int cnt = 0;
+  for (int base = 0; base < N; base += WAVE) {
+    int i = base + lane_id();
+    int v = i < N ? item(i) : 0;
+    bool m = i < N && pred(v);
+    uint64_t mk = __ballot(m);
+    if (m) out[cnt + prefix_below(mk)] = (uint16_t)v;
+    cnt += __popcll(mk);
+  }
+  return cnt;
+}
+
+__device__ __forceinline__ float dist_point_box(f3 y, f3 e) {
+  f3 d = mk3(fmaxf(fabsf(y.x) - e.x, 0.f), fmaxf(fabsf(y.y) - e.y, 0.f), fmaxf(fabsf(y.z) - e.z, 0.f));
+  return sqrtf(dot(d, d));
+}
+
+// conservative test of a bounding sphere (c, R) against target t
+__device__ __forceinline__ bool sphere_near_target(const ConCtx& X, f3 c, float R, int t, float slack) {
+  const float* F = X.F;
+  const int fm = X.fm;
+  const float* A = X.A;
+  if (t < X.np) {
+    f3 pn = mk3(X.Pl[t * 4], X.Pl[t * 4 + 1], X.Pl[t * 4 + 2]);
+    return dot(pn, c) - X.Pl[t * 4 + 3] - R < slack;
+  }
+  if (t < X.np + X.ns) {
+    const float* bx = X.St + (t - X.np) * 6;
+    return dist_point_box(c - mk3(bx[0], bx[1], bx[2]), mk3(bx[3], bx[4], bx[5])) - R < slack;
+  }
+  if (t < X.np + X.ns + X.na) {
+    int x = t - X.np - X.ns;
+    float Rx[9];
+    for (int k = 0; k < 9; ++k) Rx[k] = A[(A_R + k) * AMAX + x];
+    f3 y = mtv(Rx, c - mk3(A[(A_BC + 0) * AMAX + x], A[(A_BC + 1) * AMAX + x], A[(A_BC + 2) * AMAX + x]));
+    return dist_point_box(y, mk3(A[(A_BH + 0) * AMAX + x], A[(A_BH + 1) * AMAX + x], A[(A_BH + 2) * AMAX + x])) - R <
+           slack;
+  }
+  int g = t - X.np - X.ns - X.na;
+  f3 xg = mk3(F[(g) * FSTR + F_X + 0], F[(g) * FSTR + F_X + 1], F[(g) * FSTR + F_X + 2]);
+  if (F[(g) * FSTR + F_TYPE] == 0.f) {
+    float Rg[9];
+    for (int k = 0; k < 9; ++k) Rg[k] = F[(g) * FSTR + F_R + k];
+    return dist_point_box(mtv(Rg, c - xg), mk3(F[(g) * FSTR + F_H + 0], F[(g) * FSTR + F_H + 1], F[(g) * FSTR + F_H + 2])) -
+               R < slack;
+  }
+  f3 d = c - xg;
+  return sqrtf(dot(d, d)) - R - F[(g) * FSTR + F_H + 0] < slack;
+}
+
+// conservative test of an axis-aligned box (centre bc, half extents he) against target t
+__device__ __forceinline__ bool box_near_target(const ConCtx& X, f3 bc, f3 he, int t, float slack) {
+  const float* F = X.F;
+  const int fm = X.fm;
+  const float* A = X.A;
+  if (t < X.np) {
+    f3 pn = mk3(X.Pl[t * 4], X.Pl[t * 4 + 1], X.Pl[t * 4 + 2]);
+    float supp = fabsf(pn.x) * he.x + fabsf(pn.y) * he.y + fabsf(pn.z) * he.z;
+    return dot(pn, bc) - supp - X.Pl[t * 4 + 3] < slack;
+  }
+  if (t < X.np + X.ns) {
+    const float* bx = X.St + (t - X.np) * 6;
+    return fabsf(bc.x - bx[0]) < he.x + bx[3] + slack && fabsf(bc.y - bx[1]) < he.y + bx[4] + slack &&
+           fabsf(bc.z - bx[2]) < he.z + bx[5] + slack;
+  }
+  f3 c;
+  float rad;
+  if (t < X.np + X.ns + X.na) {
+    int x = t - X.np - X.ns;
+    c = mk3(A[(A_BC + 0) * AMAX + x], A[(A_BC + 1) * AMAX + x], A[(A_BC + 2) * AMAX + x]);
+    f3 h = mk3(A[(A_BH + 0) * AMAX + x], A[(A_BH + 1) * AMAX + x], A[(A_BH + 2) * AMAX + x]);
+    rad = sqrtf(dot(h, h));
+  } else {
+    int g = t - X.np - X.ns - X.na;
+    c = mk3(F[(g) * FSTR + F_X + 0], F[(g) * FSTR + F_X + 1], F[(g) * FSTR + F_X + 2]);
+    f3 h = mk3(F[(g) * FSTR + F_H + 0], F[(g) * FSTR + F_H + 1], F[(g) * FSTR + F_H + 2]);
+    rad = F[(g) * FSTR + F_TYPE] == 0.f ? sqrtf(dot(h, h)) : h.x;
+  }
+  return dist_point_box(c - bc, he) - rad < slack;
+}
+
+__device__ __forceinline__ void phase_contacts(const KArgs& a, const Scene& S, float* L, const Robot& rb, int& NC, int& NR, int& NL,
                                uint32_t& status, uint64_t& keysum) {
   const int lane = lane_id();
   const LdsLayout& Y = a.L;
-  const DModel* M = S.M;
-  float* C = L + Y.con;
-  const int cc = Y.ccap;
-  const float* SW = L + Y.sph;
-  const float* F = L + Y.fr;
-  const int fm = Y.fmax;
-  const float* A = L + Y.aux;
-  const float* Pl = L + Y.plane;
-  const uint16_t* own = reinterpret_cast<const uint16_t*>(L + Y.own);
-  const float* St = Y.smax > 0 ? (L + Y.stat) : (a.statics + (size_t)S.s0 * 6);
+  ConCtx X;
+  X.M = S.M;
+  X.C = L + Y.con;
+  X.cc = Y.ccap;
+  X.SW = L + Y.sph;
+  X.F = L + Y.fr;
+  X.fm = Y.fmax;
+  X.A = L + Y.aux;
+  X.Pl = L + Y.plane;
+  X.own = reinterpret_cast<const uint16_t*>(L + Y.own);
+  X.St = Y.smax > 0 ? (L + Y.stat) : (a.statics + (size_t)S.s0 * 6);
+  X.nsph = S.nsph; X.np = S.np; X.ns = S.ns; X.na = S.na; X.nf = S.nf;
+  X.NT = S.np + S.ns + S.na + S.nf;
+  X.margin = a.margin;
+  float* C = X.C;
+  const int cc = X.cc;
+  const float* Ax = X.A;
 
   int n = 0;
   // joint-limit rows of door / drawer joints come first in the canonical order
   if (lane == 0) {
     for (int x = 0; x < S.na; ++x) {
-      if (A[A_LIM * AMAX + x] == 0.f) continue;
-      float q = A[A_Q * AMAX + x];
-      float gaps[2] = {q - A[A_LO * AMAX + x], A[A_HI * AMAX + x] - q};
+      if (Ax[A_LIM * AMAX + x] == 0.f) continue;
+      float q = Ax[A_Q * AMAX + x];
+      float gaps[2] = {q - Ax[A_LO * AMAX + x], Ax[A_HI * AMAX + x] - q};
       for (int e = 0; e < 2; ++e) {
         if (gaps[e] < a.margin && n < cc) {
-          C[C_INFO * cc + n] = __int_as_float((K_LIMIT << 8 | x) | ((e == 0 ? 0 : 1) << 16));
-          C[C_PHI * cc + n] = gaps[e];
+          C[(n) * CSTR + C_INFO] = __int_as_float((K_LIMIT << 8 | x) | ((e == 0 ? 0 : 1) << 16));
+          C[(n) * CSTR + C_PHI] = gaps[e];
           ++n;
         }
       }
@@ -493,144 +779,116 @@ __device__ void phase_contacts(const KArgs& a, const Scene& S, float* L, int& NC
   }
   n = bcasti(n, 0);
   NL = n;
-  int nr = 0;
-  bool over = false, rover = false;
-  uint64_t ks = 0;
-  const int NT = S.np + S.ns + S.na + S.nf;
-  const int NO = S.nsph + S.nfo;
-  const int total = NO * NT;
-  const float invNT = NT > 0 ? 1.f / (float)NT : 0.f;
-  for (int base = 0; base < total; base += WAVE) {
-    int pair = base + lane;
-    bool valid = pair < total;
-    int o = 0, t = 0;
-    if (valid) {
-      o = (int)(((float)pair + 0.5f) * invNT);
-      t = pair - o * NT;
-      if (t < 0) { --o; t += NT; }
-      if (t >= NT) { ++o; t -= NT; }
-    }
-    // owner
-    f3 c = mk3(0.f, 0.f, 0.f);
-    float r = 0.f;
-    int okind = 0, oidx = 0, of = -1, ovk = 0, oflags = 0;  // okind 0 robot sphere, 1 box vertex, 2 free sphere
-    if (valid) {
-      if (o < S.nsph) {
-        c = mk3(SW[o * 4], SW[o * 4 + 1], SW[o * 4 + 2]);
-        r = SW[o * 4 + 3];
-        oflags = M->sph_flags[o];
-        oidx = M->sph_body[o];
-        okind = 0;
-      } else {
-        int ow = own[o - S.nsph];
-        of = ow >> 3;
-        ovk = ow & 7;
-        f3 x = mk3(F[(F_X + 0) * fm + of], F[(F_X + 1) * fm + of], F[(F_X + 2) * fm + of]);
-        if (F[F_TYPE * fm + of] == 0.f) {
-          f3 hl = mk3((ovk & 1) ? F[(F_H + 0) * fm + of] : -F[(F_H + 0) * fm + of],
-                      (ovk & 2) ? F[(F_H + 1) * fm + of] : -F[(F_H + 1) * fm + of],
-                      (ovk & 4) ? F[(F_H + 2) * fm + of] : -F[(F_H + 2) * fm + of]);
-          float Rf[9];
-          for (int k = 0; k < 9; ++k) Rf[k] = F[(F_R + k) * fm + of];
-          c = x + mv(Rf, hl);
-          r = 0.f;
-          okind = 1;
-        } else {
-          c = x;
-          r = F[(F_H + 0) * fm + of];
-          okind = 2;
-        }
+  EmitState E{n, 0, false, false, 0ull};
+  const int NT = X.NT;
+  if (!a.cull) {
+    // brute force over every (owner, target) pair
+    const int NO = S.nsph + S.nfo;
+    const int total = NO * NT;
+    const float invNT = NT > 0 ? 1.f / (float)NT : 0.f;
+    for (int base = 0; base < total; base += WAVE) {
+      int pair = base + lane;
+      PairOut po;
+      bool isrob = false, hit = false;
+      if (pair < total) {
+        int o, t;
+        divmod(pair, NT, invNT, o, t);
+        hit = eval_pair(X, o, t, po, isrob);
       }
+      emit(X, a.rcap, hit, isrob, po, E);
     }
-    // target
-    bool hit = false;
-    float phi = 0.f;
-    f3 nrm = mk3(0.f, 0.f, 1.f);
-    int tkey = 0, bside = 0;
-    if (valid) {
-      if (t < S.np) {
-        if (!(t == 0 && okind == 0 && (oflags & 1))) {
-          f3 pn = mk3(Pl[t * 4], Pl[t * 4 + 1], Pl[t * 4 + 2]);
-          phi = dot(pn, c) - Pl[t * 4 + 3] - r;
-          nrm = pn;
-          hit = phi < a.margin;
-        }
-        tkey = t;
-        bside = K_STATIC << 8;
-      } else if (t < S.np + S.ns) {
-        int bi = t - S.np;
-        const float* bx = St + bi * 6;
-        phi = box_test(c, r, mk3(bx[0], bx[1], bx[2]), nullptr, mk3(bx[3], bx[4], bx[5]), nrm);
-        hit = phi < a.margin;
-        tkey = (1 << 24) | bi;
-        bside = K_STATIC << 8;
-      } else if (t < S.np + S.ns + S.na) {
-        int x = t - S.np - S.ns;
-        float Rx[9];
-        for (int k = 0; k < 9; ++k) Rx[k] = A[(A_R + k) * AMAX + x];
-        phi = box_test(c, r, mk3(A[(A_BC + 0) * AMAX + x], A[(A_BC + 1) * AMAX + x], A[(A_BC + 2) * AMAX + x]), Rx,
-                       mk3(A[(A_BH + 0) * AMAX + x], A[(A_BH + 1) * AMAX + x], A[(A_BH + 2) * AMAX + x]), nrm);
-        hit = phi < a.margin;
-        tkey = (2 << 24) | x;
-        bside = (K_AUX << 8) | x;
-      } else {
-        int g = t - S.np - S.ns - S.na;
-        bool allowed = g != of;
-        bool gbox = F[F_TYPE * fm + g] == 0.f;
-        if (!gbox && okind == 1) allowed = false;           // box vertices skip free spheres
-        if (!gbox && okind == 2 && g <= of) allowed = false;  // sphere pairs once
-        if (allowed) {
-          f3 xg = mk3(F[(F_X + 0) * fm + g], F[(F_X + 1) * fm + g], F[(F_X + 2) * fm + g]);
-          if (gbox) {
-            float Rg[9];
-            for (int k = 0; k < 9; ++k) Rg[k] = F[(F_R + k) * fm + g];
-            phi = box_test(c, r, xg, Rg, mk3(F[(F_H + 0) * fm + g], F[(F_H + 1) * fm + g], F[(F_H + 2) * fm + g]),
-                           nrm);
-          } else {
-            f3 d = c - xg;
-            float dist = sqrtf(dot(d, d));
-            phi = dist - r - F[(F_H + 0) * fm + g];
-            nrm = dist < 1e-12f ? mk3(0.f, 0.f, 1.f) : d * (1.f / dist);
+  } else {
+    // bounding volumes first; the exact test runs on the surviving pairs only.
+    // The slack covers single-precision rounding of the bounding tests.
+    const float slack = a.margin + 1e-3f;
+    uint16_t* listA = reinterpret_cast<uint16_t*>(L + Y.cand);
+    uint16_t* listB = listA + Y.ntmax;
+    const DModel* M = S.M;
+    if (S.nsph > 0) {
+      // axis-aligned box around the robot's body bounding spheres
+      f3 lo = mk3(1e30f, 1e30f, 1e30f), hi = mk3(-1e30f, -1e30f, -1e30f);
+      if (lane < S.nb && M->sph_count[lane] > 0) {
+        float4 bs = M->bsph[lane];
+        f3 c = mv(rb.R + lane * 9, mk3(bs.x, bs.y, bs.z)) + body_p(rb, lane);
+        lo = mk3(c.x - bs.w, c.y - bs.w, c.z - bs.w);
+        hi = mk3(c.x + bs.w, c.y + bs.w, c.z + bs.w);
+      }
+      for (int off = 32; off > 0; off >>= 1) {
+        lo.x = fminf(lo.x, __shfl_xor(lo.x, off, WAVE)); lo.y = fminf(lo.y, __shfl_xor(lo.y, off, WAVE));
+        lo.z = fminf(lo.z, __shfl_xor(lo.z, off, WAVE)); hi.x = fmaxf(hi.x, __shfl_xor(hi.x, off, WAVE));
+        hi.y = fmaxf(hi.y, __shfl_xor(hi.y, off, WAVE)); hi.z = fmaxf(hi.z, __shfl_xor(hi.z, off, WAVE));
+      }
+      f3 bc = (lo + hi) * 0.5f, he = (hi - lo) * 0.5f;
+      const int nra = compact(NT, listA, [](int i) { return i; },
+                              [&](int t) { return box_near_target(X, bc, he, t, slack); });
+      for (int b = 0; b < S.nb; ++b) {
+        const int cnt = M->sph_count[b];
+        if (cnt == 0 || nra == 0) continue;
+        float4 bs = M->bsph[b];
+        f3 c = mv(rb.R + b * 9, mk3(bs.x, bs.y, bs.z)) + body_p(rb, b);
+        const int nbc = compact(nra, listB, [&](int i) { return (int)listA[i]; },
+                                [&](int t) { return sphere_near_target(X, c, bs.w, t, slack); });
+        if (nbc == 0) continue;
+        const int first = M->sph_first[b], total = cnt * nbc;
+        const float inv = 1.f / (float)nbc;
+        for (int base = 0; base < total; base += WAVE) {
+          int idx = base + lane;
+          PairOut po;
+          bool isrob = false, hit = false;
+          if (idx < total) {
+            int k, ci;
+            divmod(idx, nbc, inv, k, ci);
+            hit = eval_pair(X, first + k, listB[ci], po, isrob);
           }
-          hit = phi < a.margin;
+          emit(X, a.rcap, hit, isrob, po, E);
         }
-        tkey = (3 << 24) | g;
-        bside = (K_FREE << 8) | g;
       }
     }
-    // keep within the caps, in pair (= canonical) order
-    bool isrob = okind == 0;
-    uint64_t mr = __ballot(hit && isrob);
-    int rpos = nr + prefix_below(mr);
-    bool keep = hit && (!isrob || rpos < a.rcap);
-    if (hit && isrob && rpos >= a.rcap) rover = true;
-    uint64_t mk = __ballot(keep);
-    int pos = n + prefix_below(mk);
-    if (keep && pos >= cc) {
-      keep = false;
-      over = true;
+    int obase = S.nsph;
+    for (int f = 0; f < S.nf; ++f) {
+      const float* F = X.F;
+      const int fm = X.fm;
+      const bool fbox = F[(f) * FSTR + F_TYPE] == 0.f;
+      const int members = fbox ? 8 : 1;
+      f3 c = mk3(F[(f) * FSTR + F_X + 0], F[(f) * FSTR + F_X + 1], F[(f) * FSTR + F_X + 2]);
+      f3 h = mk3(F[(f) * FSTR + F_H + 0], F[(f) * FSTR + F_H + 1], F[(f) * FSTR + F_H + 2]);
+      const float R = fbox ? sqrtf(dot(h, h)) : h.x;
+      const int gbase = S.np + S.ns + S.na;
+      const int nbc = compact(NT, listB, [](int i) { return i; }, [&](int t) {
+        if (t >= gbase) {
+          int g = t - gbase;
+          if (g == f) return false;
+          bool gbox = F[(g) * FSTR + F_TYPE] == 0.f;
+          if (!gbox && fbox) return false;
+          if (!gbox && !fbox && g <= f) return false;
+        }
+        return sphere_near_target(X, c, R, t, slack);
+      });
+      if (nbc > 0) {
+        const int total = members * nbc;
+        const float inv = 1.f / (float)nbc;
+        for (int base = 0; base < total; base += WAVE) {
+          int idx = base + lane;
+          PairOut po;
+          bool isrob = false, hit = false;
+          if (idx < total) {
+            int k, ci;
+            divmod(idx, nbc, inv, k, ci);
+            hit = eval_pair(X, obase + k, listB[ci], po, isrob);
+          }
+          emit(X, a.rcap, hit, isrob, po, E);
+        }
+      }
+      obase += members;
     }
-    if (keep) {
-      int aside = okind == 0 ? ((K_ROBOT << 8) | oidx) : ((K_FREE << 8) | of);
-      C[C_INFO * cc + pos] = __int_as_float(aside | (bside << 16));
-      f3 p = c - nrm * r;
-      C[(C_N + 0) * cc + pos] = nrm.x; C[(C_N + 1) * cc + pos] = nrm.y; C[(C_N + 2) * cc + pos] = nrm.z;
-      C[(C_P + 0) * cc + pos] = p.x; C[(C_P + 1) * cc + pos] = p.y; C[(C_P + 2) * cc + pos] = p.z;
-      C[C_PHI * cc + pos] = phi;
-      uint32_t okey = okind == 0 ? (uint32_t)o : ((1u << 24) | ((uint32_t)of << 3) | (uint32_t)ovk);
-      ks += mix64(((uint64_t)okey << 32) | (uint32_t)tkey);
-    }
-    int nk = __popcll(__ballot(keep));
-    n = min(n + nk, cc);
-    nr += __popcll(__ballot(keep && isrob));
   }
-  // reduce key sums and flags
+  uint64_t ks = E.ks;
   for (int off = 32; off > 0; off >>= 1) ks += __shfl_xor(ks, off, WAVE);
   keysum = ks;
-  if (__ballot(over)) status |= 2u;
-  if (__ballot(rover)) status |= 8u;
-  NC = n;
-  NR = nr;
+  if (__ballot(E.over)) status |= 2u;
+  if (__ballot(E.rover)) status |= 8u;
+  NC = E.n;
+  NR = E.nr;
   wave_sync();
 }
 
@@ -652,9 +910,6 @@ __device__ __forceinline__ void shift_force(const float* f, f3 e, float* out) {
   f3 n = mk3(f[0], f[1], f[2]) + cross(e, mk3(f[3], f[4], f[5]));
   out[0] = n.x; out[1] = n.y; out[2] = n.z; out[3] = f[3]; out[4] = f[4]; out[5] = f[5];
 }
-__device__ __forceinline__ f3 body_p(const Robot& rb, int i) {
-  return mk3(rb.p[i * 3], rb.p[i * 3 + 1], rb.p[i * 3 + 2]);
-}
 // motion subspace of joint k expressed at point q
 __device__ __forceinline__ void s_at(const Robot& rb, const DModel* M, int k, f3 q, float* out) {
   const float* s = rb.s + k * 6;
@@ -667,7 +922,7 @@ __device__ __forceinline__ void s_at(const Robot& rb, const DModel* M, int k, f3
   }
 }
 
-__device__ void phase_dynamics(const KArgs& a, const Scene& S, float* L, const Robot& rb, float& vR) {
+__device__ __forceinline__ void phase_dynamics(const KArgs& a, const Scene& S, float* L, const Robot& rb, float& vR) {
   const int lane = lane_id();
   const DModel* M = S.M;
   const int nb = S.nb;
@@ -678,6 +933,7 @@ __device__ void phase_dynamics(const KArgs& a, const Scene& S, float* L, const R
     const f3 pi = body_p(rb, i);
     float v[6] = {0, 0, 0, 0, 0, 0};
     int am = M->anc[i];
+    #pragma unroll 1
     for (int k = 0; k <= i; ++k)
       if ((am >> k) & 1) {
         float sk[6];
@@ -723,38 +979,46 @@ __device__ void phase_dynamics(const KArgs& a, const Scene& S, float* L, const R
   // pass 2 (inward, serial over bodies): U, D, u at p_i; the articulated
   // inertia I^a = IA - U U^T / D and bias p^a = pA + I^a c + U u / D are
   // translated to the parent's origin and added there
-  float* Ia_s = rb.Minv;  // scratch (36 floats) until the inverse is formed
+  float* Ia_s = rb.Ia;
+  #pragma unroll 1
   for (int i = nb - 1; i >= 0; --i) {
     const float* IA = rb.IA + i * 36;
     const float* s = rb.s + i * 6;
     const int par = M->parent[i];
+    // U = IA s and IA c, one row per lane
+    if (lane < 6) {
+      float accU = 0.f, accC = 0.f;
+#pragma unroll
+      for (int q = 0; q < 6; ++q) {
+        float e = IA[lane * 6 + q];
+        accU += e * s[q];
+        accC += e * rb.cc[i * 6 + q];
+      }
+      rb.U[i * 6 + lane] = accU;
+      Ia_s[36 + lane] = accC;
+    }
+    wave_sync();
     if (lane == 0) {
-      float U[6], ci[6], pAi[6], Ic_[6];
-      for (int t = 0; t < 6; ++t) { ci[t] = rb.cc[i * 6 + t]; pAi[t] = rb.pA[i * 6 + t]; }
       float D = rb.arm[i], uu = rb.tau[i], Uc = 0.f;
+#pragma unroll
       for (int r = 0; r < 6; ++r) {
-        float accU = 0.f, accC = 0.f;
-        for (int q = 0; q < 6; ++q) {
-          float e = IA[r * 6 + q];
-          accU += e * s[q];
-          accC += e * ci[q];
-        }
-        U[r] = accU;
-        Ic_[r] = accC;
+        float Ur = rb.U[i * 6 + r];
+        D += s[r] * Ur;
+        uu -= s[r] * rb.pA[i * 6 + r];
+        Uc += Ur * rb.cc[i * 6 + r];
       }
-      for (int r = 0; r < 6; ++r) {
-        D += s[r] * U[r];
-        uu -= s[r] * pAi[r];
-        Uc += U[r] * ci[r];
-      }
-      for (int r = 0; r < 6; ++r) rb.U[i * 6 + r] = U[r];
       rb.D[i] = D;
       rb.uu[i] = uu;
       if (par >= 0) {
         float invD = 1.f / D;
         float pa[6], pq[6];
-        for (int r = 0; r < 6; ++r) pa[r] = pAi[r] + Ic_[r] - U[r] * Uc * invD + U[r] * uu * invD;
+#pragma unroll
+        for (int r = 0; r < 6; ++r) {
+          float Ur = rb.U[i * 6 + r];
+          pa[r] = rb.pA[i * 6 + r] + Ia_s[36 + r] - Ur * Uc * invD + Ur * uu * invD;
+        }
         shift_force(pa, body_p(rb, i) - body_p(rb, par), pq);
+#pragma unroll
         for (int r = 0; r < 6; ++r) rb.pA[par * 6 + r] += pq[r];
       }
     }
@@ -793,6 +1057,7 @@ __device__ void phase_dynamics(const KArgs& a, const Scene& S, float* L, const R
   }
   // tables: T[i][k] = U_i . s_k (k strict ancestor of i, s_k taken to p_i);
   // S2[i][k] = s_i . U_k / D_k (k strict descendant of i, U_k taken to p_i)
+  #pragma unroll 1
   for (int e = lane; e < ND * ND; e += WAVE) {
     int i = e / ND, k = e % ND;
     float tv = 0.f, sv = 0.f;
@@ -819,6 +1084,7 @@ __device__ void phase_dynamics(const KArgs& a, const Scene& S, float* L, const R
     const f3 pi = body_p(rb, i);
     float acc6[6] = {0.f, 0.f, 0.f, -a.g[0], -a.g[1], -a.g[2]};
     int am = M->anc[i];
+    #pragma unroll 1
     for (int k = 0; k <= i; ++k)
       if ((am >> k) & 1) {
         float ck[6];
@@ -831,44 +1097,36 @@ __device__ void phase_dynamics(const KArgs& a, const Scene& S, float* L, const R
   }
   wave_sync();
   // lanes 0..nb-1: column j of M~^-1 (force e_j, no velocity, no gravity);
-  // lane 16: the forward dynamics qdd
+  // lane 16: the forward dynamics qdd.  Two triangular recurrences over the
+  // tables, kept rolled with the running column in LDS (one column per lane):
+  // a fully unrolled register form costs the kernel half its occupancy.
   {
-    float uvec[ND], qdd[ND];
     const bool col = lane < nb;
     const bool fd = lane == ND;
-    if (col || fd) {
-      if (col) {
-#pragma unroll
-        for (int i = ND - 1; i >= 0; --i) {
-          float acc = (i == lane) ? 1.f : 0.f;
-#pragma unroll
-          for (int k = i + 1; k < ND; ++k) acc -= rb.S2[i * ND + k] * uvec[k];
-          uvec[i] = acc;
-        }
-      } else {
-#pragma unroll
-        for (int i = 0; i < ND; ++i) uvec[i] = i < nb ? rb.pA[i * 6] : 0.f;
-      }
-#pragma unroll
-      for (int i = 0; i < ND; ++i) {
-        float acc = uvec[i];
-#pragma unroll
-        for (int k = 0; k < i; ++k) acc -= rb.T[i * ND + k] * qdd[k];
-        qdd[i] = i < nb ? acc / rb.D[i] : 0.f;
-      }
-    }
-    wave_sync();
+    float* uc = rb.Uc;  // [16][16]: u of column j at uc[i * ND + j]
     if (col) {
-#pragma unroll
-      for (int i = 0; i < ND; ++i) rb.Minv[i * ND + lane] = qdd[i];
+#pragma unroll 1
+      for (int i = nb - 1; i >= 0; --i) {
+        float acc = (i == lane) ? 1.f : 0.f;
+#pragma unroll 4
+        for (int k = i + 1; k < nb; ++k) acc -= rb.S2[i * ND + k] * uc[k * ND + lane];
+        uc[i * ND + lane] = acc;
+      }
     }
-    if (lane < ND && lane >= nb) {
+    if (col || fd) {
+      float* outc = col ? rb.Minv + lane : rb.qdd;
+      const int os = col ? ND : 1;
+#pragma unroll 1
+      for (int i = 0; i < nb; ++i) {
+        float acc = col ? uc[i * ND + lane] : rb.pA[i * 6];
+#pragma unroll 4
+        for (int k = 0; k < i; ++k) acc -= rb.T[i * ND + k] * outc[k * os];
+        outc[i * os] = acc / rb.D[i];
+      }
+      for (int i = nb; i < ND; ++i) outc[i * os] = 0.f;
+    }
+    if (lane < ND && lane >= nb)
       for (int i = 0; i < ND; ++i) rb.Minv[i * ND + lane] = 0.f;
-    }
-    if (fd) {
-#pragma unroll
-      for (int i = 0; i < ND; ++i) rb.qdd[i] = qdd[i];
-    }
   }
   wave_sync();
   // unconstrained robot velocity, held in lanes 0..15
@@ -879,19 +1137,19 @@ __device__ void phase_dynamics(const KArgs& a, const Scene& S, float* L, const R
   const int fm = a.L.fmax;
   for (int f = lane; f < S.nf; f += WAVE) {
     float R[9];
-    for (int t = 0; t < 9; ++t) R[t] = F[(F_R + t) * fm + f];
-    f3 w = mk3(F[(F_W + 0) * fm + f], F[(F_W + 1) * fm + f], F[(F_W + 2) * fm + f]);
+    for (int t = 0; t < 9; ++t) R[t] = F[(f) * FSTR + F_R + t];
+    f3 w = mk3(F[(f) * FSTR + F_W + 0], F[(f) * FSTR + F_W + 1], F[(f) * FSTR + F_W + 2]);
     f3 wl = mtv(R, w);
-    f3 Iwl = mk3(F[(F_IB + 0) * fm + f] * wl.x, F[(F_IB + 1) * fm + f] * wl.y, F[(F_IB + 2) * fm + f] * wl.z);
+    f3 Iwl = mk3(F[(f) * FSTR + F_IB + 0] * wl.x, F[(f) * FSTR + F_IB + 1] * wl.y, F[(f) * FSTR + F_IB + 2] * wl.z);
     f3 Iw = mv(R, Iwl);
     f3 gy = cross(w, Iw);
-    float Ii[9];
-    for (int t = 0; t < 9; ++t) Ii[t] = F[(F_II + t) * fm + f];
-    f3 dw = mv(Ii, gy);
-    F[(F_W + 0) * fm + f] = w.x - a.h * dw.x;
-    F[(F_W + 1) * fm + f] = w.y - a.h * dw.y;
-    F[(F_W + 2) * fm + f] = w.z - a.h * dw.z;
-    for (int t = 0; t < 3; ++t) F[(F_V + t) * fm + f] += a.h * a.g[t];
+    float Ii[6];
+    for (int t = 0; t < 6; ++t) Ii[t] = F[(f) * FSTR + F_II + t];
+    f3 dw = smv(Ii, gy);
+    F[(f) * FSTR + F_W + 0] = w.x - a.h * dw.x;
+    F[(f) * FSTR + F_W + 1] = w.y - a.h * dw.y;
+    F[(f) * FSTR + F_W + 2] = w.z - a.h * dw.z;
+    for (int t = 0; t < 3; ++t) F[(f) * FSTR + F_V + t] += a.h * a.g[t];
   }
   // aux joints: passive single-DoF bodies; the gravity torque about the axis
   float* Ax = L + a.L.aux;
@@ -919,7 +1177,7 @@ __device__ __forceinline__ f3 aux_col(const float* A, int x, f3 p) {
   return ax;
 }
 
-__device__ void phase_rows(const KArgs& a, const Scene& S, float* L, const Robot& rb, int NC, int NR, int NL,
+__device__ __forceinline__ void phase_rows(const KArgs& a, const Scene& S, float* L, const Robot& rb, int NC, int NR, int NL,
                            uint32_t& status) {
   const int lane = lane_id();
   const LdsLayout& Y = a.L;
@@ -931,47 +1189,50 @@ __device__ void phase_rows(const KArgs& a, const Scene& S, float* L, const Robot
   const DModel* M = S.M;
   // lane per contact: tangents, free / aux effective-mass parts, bias
   for (int ci = lane; ci < NC; ci += WAVE) {
-    int info = __float_as_int(C[C_INFO * cc + ci]);
+    int info = __float_as_int(C[(ci) * CSTR + C_INFO]);
     int sA = info & 0xffff, sB = (info >> 16) & 0xffff;
-    float phi = C[C_PHI * cc + ci];
+    float phi = C[(ci) * CSTR + C_PHI];
     float bias = phi >= 0.f ? phi / a.h : a.beta * phi / a.h;
     if (side_kind(sA) == K_LIMIT) {
       int x = side_idx(sA);
-      C[(C_IW + 0) * cc + ci] = A[A_IM * AMAX + x];  // W = 1 / M~ for J = +-1
-      C[C_BIAS * cc + ci] = bias;
-      for (int t = 0; t < 3; ++t) C[(C_LAM + t) * cc + ci] = 0.f;
+      C[(ci) * CSTR + C_IW + 0] = A[A_IM * AMAX + x];  // W = 1 / M~ for J = +-1
+      C[(ci) * CSTR + C_BIAS] = bias;
+      for (int t = 0; t < 3; ++t) C[(ci) * CSTR + C_LAM + t] = 0.f;
       continue;
     }
-    f3 n = mk3(C[(C_N + 0) * cc + ci], C[(C_N + 1) * cc + ci], C[(C_N + 2) * cc + ci]);
-    f3 p = mk3(C[(C_P + 0) * cc + ci], C[(C_P + 1) * cc + ci], C[(C_P + 2) * cc + ci]);
+    f3 n = mk3(C[(ci) * CSTR + C_N + 0], C[(ci) * CSTR + C_N + 1], C[(ci) * CSTR + C_N + 2]);
+    f3 p = mk3(C[(ci) * CSTR + C_P + 0], C[(ci) * CSTR + C_P + 1], C[(ci) * CSTR + C_P + 2]);
     f3 t1, t2;
     onb(n, t1, t2);
-    f3 dirs[3] = {n, t1, t2};
-    float W[3] = {0.f, 0.f, 0.f};
+    float W0 = 0.f, W1 = 0.f, W2 = 0.f;
+#pragma unroll
     for (int sd = 0; sd < 2; ++sd) {
       int sv = sd == 0 ? sA : sB;
       int k = side_kind(sv), idx = side_idx(sv);
       if (k == K_FREE) {
-        f3 r = p - mk3(F[(F_X + 0) * fm + idx], F[(F_X + 1) * fm + idx], F[(F_X + 2) * fm + idx]);
-        float Ii[9];
-        for (int t = 0; t < 9; ++t) Ii[t] = F[(F_II + t) * fm + idx];
-        float im = F[F_IM * fm + idx];
-        for (int d = 0; d < 3; ++d) {
-          f3 rd = cross(r, dirs[d]);
-          W[d] += im + dot(rd, mv(Ii, rd));
-        }
+        f3 r = p - mk3(F[(idx) * FSTR + F_X + 0], F[(idx) * FSTR + F_X + 1], F[(idx) * FSTR + F_X + 2]);
+        float Ii[6];
+#pragma unroll
+        for (int t = 0; t < 6; ++t) Ii[t] = F[(idx) * FSTR + F_II + t];
+        float im = F[(idx) * FSTR + F_IM];
+        f3 r0 = cross(r, n), r1 = cross(r, t1), r2 = cross(r, t2);
+        W0 += im + dot(r0, smv(Ii, r0));
+        W1 += im + dot(r1, smv(Ii, r1));
+        W2 += im + dot(r2, smv(Ii, r2));
       } else if (k == K_AUX) {
         f3 col = aux_col(A, idx, p);
         float im = A[A_IM * AMAX + idx];
-        for (int d = 0; d < 3; ++d) {
-          float J = dot(dirs[d], col);
-          W[d] += J * J * im;
-        }
+        float J0 = dot(n, col), J1 = dot(t1, col), J2 = dot(t2, col);
+        W0 += J0 * J0 * im;
+        W1 += J1 * J1 * im;
+        W2 += J2 * J2 * im;
       }
     }
-    for (int d = 0; d < 3; ++d) C[(C_IW + d) * cc + ci] = W[d];
-    C[C_BIAS * cc + ci] = bias;
-    for (int t = 0; t < 3; ++t) C[(C_LAM + t) * cc + ci] = 0.f;
+    C[(ci) * CSTR + C_IW + 0] = W0;
+    C[(ci) * CSTR + C_IW + 1] = W1;
+    C[(ci) * CSTR + C_IW + 2] = W2;
+    C[(ci) * CSTR + C_BIAS] = bias;
+    for (int t = 0; t < 3; ++t) C[(ci) * CSTR + C_LAM + t] = 0.f;
   }
   wave_sync();
   // robot rows: lane (d, j) builds J[d][j] = d . (dp/dq_j), then w = M~^-1 J^T
@@ -980,11 +1241,11 @@ __device__ void phase_rows(const KArgs& a, const Scene& S, float* L, const Robot
   for (int rr = 0; rr < NR; ++rr) {
     const int ci = NL + rr;
     float* row = Rw + rr * ROW_FLOATS;
-    int info = __float_as_int(C[C_INFO * cc + ci]);
+    int info = __float_as_int(C[(ci) * CSTR + C_INFO]);
     int body = side_idx(info & 0xffff);
     if (d < 3) {
-      f3 n = mk3(C[(C_N + 0) * cc + ci], C[(C_N + 1) * cc + ci], C[(C_N + 2) * cc + ci]);
-      f3 p = mk3(C[(C_P + 0) * cc + ci], C[(C_P + 1) * cc + ci], C[(C_P + 2) * cc + ci]);
+      f3 n = mk3(C[(ci) * CSTR + C_N + 0], C[(ci) * CSTR + C_N + 1], C[(ci) * CSTR + C_N + 2]);
+      f3 p = mk3(C[(ci) * CSTR + C_P + 0], C[(ci) * CSTR + C_P + 1], C[(ci) * CSTR + C_P + 2]);
       f3 t1, t2;
       onb(n, t1, t2);
       f3 dir = d == 0 ? n : (d == 1 ? t1 : t2);
@@ -1004,7 +1265,7 @@ __device__ void phase_rows(const KArgs& a, const Scene& S, float* L, const Robot
       for (int k = 0; k < ND; ++k) w += rb.Minv[j * ND + k] * row[d * ND + k];
       row[3 * ND + d * ND + j] = w;
       float Wr = sum16(row[d * ND + j] * w);
-      if (j == 0) C[(C_IW + d) * cc + ci] += Wr;
+      if (j == 0) C[(ci) * CSTR + C_IW + d] += Wr;
     }
     wave_sync();
   }
@@ -1012,13 +1273,13 @@ __device__ void phase_rows(const KArgs& a, const Scene& S, float* L, const Robot
   bool degen = false;
   for (int ci = lane; ci < NC; ci += WAVE) {
     for (int dd = 0; dd < 3; ++dd) {
-      float W = C[(C_IW + dd) * cc + ci];
-      int info = __float_as_int(C[C_INFO * cc + ci]);
+      float W = C[(ci) * CSTR + C_IW + dd];
+      int info = __float_as_int(C[(ci) * CSTR + C_INFO]);
       bool lim = side_kind(info & 0xffff) == K_LIMIT;
       if (lim && dd > 0) continue;
-      if (W >= 1e-12f) C[(C_IW + dd) * cc + ci] = 1.f / W;
+      if (W >= 1e-12f) C[(ci) * CSTR + C_IW + dd] = 1.f / W;
       else {
-        C[(C_IW + dd) * cc + ci] = 0.f;
+        C[(ci) * CSTR + C_IW + dd] = 0.f;
         degen = true;
       }
     }
@@ -1029,7 +1290,7 @@ __device__ void phase_rows(const KArgs& a, const Scene& S, float* L, const Robot
 
 // Level schedule: level(k) = 1 + max level of earlier rows sharing a node.
 // Then an order list grouped by level; each level's robot row is kept apart.
-__device__ int phase_levels(const KArgs& a, float* L, int NC, int NR, int NL) {
+__device__ __forceinline__ int phase_levels(const KArgs& a, float* L, int NC, int NR, int NL) {
   const int lane = lane_id();
   const LdsLayout& Y = a.L;
   float* C = L + Y.con;
@@ -1042,7 +1303,7 @@ __device__ int phase_levels(const KArgs& a, float* L, int NC, int NR, int NL) {
   int maxl = 0;
   for (int base = 0; base < NC; base += WAVE) {
     int info = 0;
-    if (base + lane < NC) info = __float_as_int(C[C_INFO * cc + base + lane]);
+    if (base + lane < NC) info = __float_as_int(C[(base + lane) * CSTR + C_INFO]);
     int cnt = min(WAVE, NC - base);
     int mylvl = 0;
     for (int k = 0; k < cnt; ++k) {
@@ -1076,45 +1337,82 @@ __device__ int phase_levels(const KArgs& a, float* L, int NC, int NR, int NL) {
   return maxl;
 }
 
-// velocity of the material point p of side sv (free body or aux joint)
-__device__ __forceinline__ f3 side_point_vel(const float* F, int fm, const float* A, int sv, f3 p) {
-  int k = side_kind(sv), idx = side_idx(sv);
-  if (k == K_FREE) {
-    f3 x = mk3(F[(F_X + 0) * fm + idx], F[(F_X + 1) * fm + idx], F[(F_X + 2) * fm + idx]);
-    f3 v = mk3(F[(F_V + 0) * fm + idx], F[(F_V + 1) * fm + idx], F[(F_V + 2) * fm + idx]);
-    f3 w = mk3(F[(F_W + 0) * fm + idx], F[(F_W + 1) * fm + idx], F[(F_W + 2) * fm + idx]);
-    return v + cross(w, p - x);
+// One dynamic side of a contact held in registers during a row update:
+// free body (x, v, w, 1/m, world inverse inertia) or door / drawer joint
+// (point-Jacobian column at the contact point, joint velocity, 1/M~).
+struct SideReg {
+  int kind, idx;
+  f3 x, v, w, col;
+  float im, qv;
+  float Ii[6];  // symmetric world inverse inertia
+};
+__device__ __forceinline__ void side_load(const float* F, const float* A, int sv, f3 p, SideReg& S) {
+  S.kind = side_kind(sv);
+  S.idx = side_idx(sv);
+  if (S.kind == K_FREE) {
+    const float* f = F + S.idx * FSTR;
+    S.x = mk3(f[F_X], f[F_X + 1], f[F_X + 2]);
+    S.v = mk3(f[F_V], f[F_V + 1], f[F_V + 2]);
+    S.w = mk3(f[F_W], f[F_W + 1], f[F_W + 2]);
+    S.im = f[F_IM];
+#pragma unroll
+    for (int t = 0; t < 6; ++t) S.Ii[t] = f[F_II + t];
+  } else if (S.kind == K_AUX) {
+    S.col = aux_col(A, S.idx, p);
+    S.qv = A[A_V * AMAX + S.idx];
+    S.im = A[A_IM * AMAX + S.idx];
   }
-  if (k == K_AUX) return aux_col(A, idx, p) * A[A_V * AMAX + idx];
+}
+// velocity of the contact point p of a side
+__device__ __forceinline__ f3 side_vel(const SideReg& S, f3 p) {
+  if (S.kind == K_FREE) return S.v + cross(S.w, p - S.x);
+  if (S.kind == K_AUX) return S.col * S.qv;
   return mk3(0.f, 0.f, 0.f);
 }
-// apply impulse P (world) at p to side sv with sign sg
-__device__ __forceinline__ void side_apply(float* F, int fm, float* A, int sv, f3 p, f3 P) {
-  int k = side_kind(sv), idx = side_idx(sv);
-  if (k == K_FREE) {
-    f3 x = mk3(F[(F_X + 0) * fm + idx], F[(F_X + 1) * fm + idx], F[(F_X + 2) * fm + idx]);
-    float im = F[F_IM * fm + idx];
-    float Ii[9];
-    for (int t = 0; t < 9; ++t) Ii[t] = F[(F_II + t) * fm + idx];
-    f3 dw = mv(Ii, cross(p - x, P));
-    F[(F_V + 0) * fm + idx] += P.x * im;
-    F[(F_V + 1) * fm + idx] += P.y * im;
-    F[(F_V + 2) * fm + idx] += P.z * im;
-    F[(F_W + 0) * fm + idx] += dw.x;
-    F[(F_W + 1) * fm + idx] += dw.y;
-    F[(F_W + 2) * fm + idx] += dw.z;
-  } else if (k == K_AUX) {
-    A[A_V * AMAX + idx] += dot(aux_col(A, idx, p), P) * A[A_IM * AMAX + idx];
+// apply the impulse P at p
+__device__ __forceinline__ void side_impulse(SideReg& S, f3 p, f3 P) {
+  if (S.kind == K_FREE) {
+    S.v = S.v + P * S.im;
+    S.w = S.w + smv(S.Ii, cross(p - S.x, P));
+  } else if (S.kind == K_AUX) {
+    S.qv += dot(S.col, P) * S.im;
+  }
+}
+__device__ __forceinline__ void side_store(float* F, float* A, const SideReg& S) {
+  if (S.kind == K_FREE) {
+    float* f = F + S.idx * FSTR;
+    f[F_V] = S.v.x; f[F_V + 1] = S.v.y; f[F_V + 2] = S.v.z;
+    f[F_W] = S.w.x; f[F_W + 1] = S.w.y; f[F_W + 2] = S.w.z;
+  } else if (S.kind == K_AUX) {
+    A[A_V * AMAX + S.idx] = S.qv;
+  }
+}
+// friction pair: Jacobi step on both tangent rows from the same velocity,
+// then projection onto the disk of radius mu * lambda_n
+__device__ __forceinline__ void friction_disk(float l1, float l2, float r1, float r2, float iw1, float iw2, float lim,
+                                              float& y1, float& y2) {
+  y1 = l1 - r1 * iw1;
+  y2 = l2 - r2 * iw2;
+  float nn = y1 * y1 + y2 * y2;
+  if (nn > lim * lim) {
+    if (lim > 0.f) {
+      float sc = lim / sqrtf(nn);
+      y1 *= sc;
+      y2 *= sc;
+    } else {
+      y1 = 0.f;
+      y2 = 0.f;
+    }
   }
 }
 
-__device__ void phase_pgs(const KArgs& a, const Scene& S, float* L, int NC, int NL, int maxl, float& vR) {
+__device__ __forceinline__ void phase_pgs(const KArgs& a, const Scene& S, float* L, int NC, int NL, int maxl,
+                                          float& vR) {
   const int lane = lane_id();
   const LdsLayout& Y = a.L;
   float* C = L + Y.con;
   const int cc = Y.ccap;
   float* F = L + Y.fr;
-  const int fm = Y.fmax;
   float* A = L + Y.aux;
   const float* Rw = L + Y.rows;
   const int* lvl = reinterpret_cast<const int*>(L + Y.lvl);
@@ -1122,130 +1420,118 @@ __device__ void phase_pgs(const KArgs& a, const Scene& S, float* L, int NC, int 
   const int* rob = loff + cc + 2;
   const uint16_t* order = reinterpret_cast<const uint16_t*>(rob + cc + 2);
   const float mu = a.mu;
+  const int j = lane & 15;
+#pragma unroll 1
   for (int it = 0; it < a.K; ++it) {
+#pragma unroll 1
     for (int lv = 1; lv <= maxl; ++lv) {
       const int rc = rob[lv];
+      const int o0 = loff[lv - 1], o1 = loff[lv];
       if (rc >= 0) {
-        // robot row: lanes 0..15 hold the robot joint velocities
+        // the level's robot row: lanes 0..15 hold the robot joint velocities
         const float* row = Rw + (rc - NL) * ROW_FLOATS;
-        const int j = lane & 15;
-        int info = __float_as_int(C[C_INFO * cc + rc]);
-        int sB = (info >> 16) & 0xffff;
-        f3 n = mk3(C[(C_N + 0) * cc + rc], C[(C_N + 1) * cc + rc], C[(C_N + 2) * cc + rc]);
-        f3 p = mk3(C[(C_P + 0) * cc + rc], C[(C_P + 1) * cc + rc], C[(C_P + 2) * cc + rc]);
-        float iw0 = C[(C_IW + 0) * cc + rc], iw1 = C[(C_IW + 1) * cc + rc], iw2 = C[(C_IW + 2) * cc + rc];
-        float bias = C[C_BIAS * cc + rc];
-        float l0 = C[(C_LAM + 0) * cc + rc], l1 = C[(C_LAM + 1) * cc + rc], l2 = C[(C_LAM + 2) * cc + rc];
-        float vj = lane < ND ? vR : 0.f;
-        float Jn = row[j], wn = row[3 * ND + j];
-        float dn = sum16(lane < ND ? Jn * vj : 0.f);
-        dn = bcast(dn, 0);
-        f3 uB = side_point_vel(F, fm, A, sB, p);
-        float r = dn - dot(n, uB) + bias;
+        const float* c = C + rc * CSTR;
+        int info = __float_as_int(c[C_INFO]);
+        f3 n = mk3(c[C_N], c[C_N + 1], c[C_N + 2]);
+        f3 p = mk3(c[C_P], c[C_P + 1], c[C_P + 2]);
+        float iw0 = c[C_IW], iw1 = c[C_IW + 1], iw2 = c[C_IW + 2];
+        float bias = c[C_BIAS];
+        float l0 = c[C_LAM], l1 = c[C_LAM + 1], l2 = c[C_LAM + 2];
+        float Jn = row[j], J1 = row[ND + j], J2 = row[2 * ND + j];
+        float wn = row[3 * ND + j], w1 = row[4 * ND + j], w2 = row[5 * ND + j];
+        SideReg B;
+        side_load(F, A, (info >> 16) & 0xffff, p, B);
+        float dn = bcast(sum16(lane < ND ? Jn * vR : 0.f), 0);
+        float r = dn - dot(n, side_vel(B, p)) + bias;
         float nl = l0;
         if (iw0 > 0.f) nl = fmaxf(0.f, l0 - r * iw0);
         float dl = nl - l0;
         if (lane < ND) vR += wn * dl;
-        if (lane == 0 && dl != 0.f) side_apply(F, fm, A, sB, p, n * (-dl));
-        wave_sync();
+        side_impulse(B, p, n * (-dl));
         if (iw1 > 0.f && iw2 > 0.f) {
           f3 t1, t2;
           onb(n, t1, t2);
-          float vj2 = lane < ND ? vR : 0.f;
-          float J1 = row[ND + j], J2 = row[2 * ND + j];
-          float d1 = bcast(sum16(lane < ND ? J1 * vj2 : 0.f), 0);
-          float d2 = bcast(sum16(lane < ND ? J2 * vj2 : 0.f), 0);
-          f3 uB2 = side_point_vel(F, fm, A, sB, p);
-          float r1 = d1 - dot(t1, uB2), r2 = d2 - dot(t2, uB2);
-          float y1 = l1 - r1 * iw1, y2 = l2 - r2 * iw2;
-          float lim = mu * nl;
-          float nn = y1 * y1 + y2 * y2;
-          if (nn > lim * lim) {
-            if (lim > 0.f) {
-              float sc = lim / sqrtf(nn);
-              y1 *= sc;
-              y2 *= sc;
-            } else {
-              y1 = 0.f;
-              y2 = 0.f;
-            }
-          }
+          // both tangent dot products in one reduction: lanes 0..15 t1, 16..31 t2
+          float vj = __shfl(vR, j, WAVE);
+          float part = lane < ND ? J1 * vj : (lane < 2 * ND ? J2 * vj : 0.f);
+          float dsum = sum16(part);
+          float d1 = bcast(dsum, 0), d2 = bcast(dsum, ND);
+          f3 uB = side_vel(B, p);
+          float y1, y2;
+          friction_disk(l1, l2, d1 - dot(t1, uB), d2 - dot(t2, uB), iw1, iw2, mu * nl, y1, y2);
           float dl1 = y1 - l1, dl2 = y2 - l2;
-          if (lane < ND) vR += row[4 * ND + j] * dl1 + row[5 * ND + j] * dl2;
-          if (lane == 0) side_apply(F, fm, A, sB, p, (t1 * dl1 + t2 * dl2) * (-1.f));
+          if (lane < ND) vR += w1 * dl1 + w2 * dl2;
+          side_impulse(B, p, (t1 * dl1 + t2 * dl2) * (-1.f));
           l1 = y1;
           l2 = y2;
         }
         if (lane == 0) {
-          C[(C_LAM + 0) * cc + rc] = nl;
-          C[(C_LAM + 1) * cc + rc] = l1;
-          C[(C_LAM + 2) * cc + rc] = l2;
+          side_store(F, A, B);
+          float* cw = C + rc * CSTR;
+          cw[C_LAM] = nl;
+          cw[C_LAM + 1] = l1;
+          cw[C_LAM + 2] = l2;
         }
+        // a scheduling fence: keeps the robot row's registers from living
+        // into the per-lane rows below (they touch disjoint nodes)
+        wave_sync();
       }
       // the level's other rows, one lane each (they share no node)
-      const int o0 = loff[lv - 1], o1 = loff[lv];
+#pragma unroll 1
       for (int e = o0 + lane; e < o1; e += WAVE) {
         const int ci = order[e];
-        int info = __float_as_int(C[C_INFO * cc + ci]);
+        float* c = C + ci * CSTR;
+        int info = __float_as_int(c[C_INFO]);
         int sA = info & 0xffff, sB = (info >> 16) & 0xffff;
-        float bias = C[C_BIAS * cc + ci];
-        float l0 = C[(C_LAM + 0) * cc + ci];
+        float bias = c[C_BIAS];
+        float l0 = c[C_LAM];
         if (side_kind(sA) == K_LIMIT) {
           int x = side_idx(sA);
           float sg = ((info >> 16) & 1) ? -1.f : 1.f;
-          float iwl = C[(C_IW + 0) * cc + ci];  // = 1 / W
+          float iwl = c[C_IW];  // = 1 / W
           float r = sg * A[A_V * AMAX + x] + bias;
           float nl = fmaxf(0.f, l0 - r * iwl);
           A[A_V * AMAX + x] += sg * A[A_IM * AMAX + x] * (nl - l0);
-          C[(C_LAM + 0) * cc + ci] = nl;
+          c[C_LAM] = nl;
           continue;
         }
-        f3 n = mk3(C[(C_N + 0) * cc + ci], C[(C_N + 1) * cc + ci], C[(C_N + 2) * cc + ci]);
-        f3 p = mk3(C[(C_P + 0) * cc + ci], C[(C_P + 1) * cc + ci], C[(C_P + 2) * cc + ci]);
-        float iw0 = C[(C_IW + 0) * cc + ci], iw1 = C[(C_IW + 1) * cc + ci], iw2 = C[(C_IW + 2) * cc + ci];
-        float l1 = C[(C_LAM + 1) * cc + ci], l2 = C[(C_LAM + 2) * cc + ci];
-        f3 du = side_point_vel(F, fm, A, sA, p) - side_point_vel(F, fm, A, sB, p);
-        float r = dot(n, du) + bias;
+        f3 n = mk3(c[C_N], c[C_N + 1], c[C_N + 2]);
+        f3 p = mk3(c[C_P], c[C_P + 1], c[C_P + 2]);
+        float iw0 = c[C_IW], iw1 = c[C_IW + 1], iw2 = c[C_IW + 2];
+        float l1 = c[C_LAM + 1], l2 = c[C_LAM + 2];
+        SideReg SA, SB;
+        side_load(F, A, sA, p, SA);
+        side_load(F, A, sB, p, SB);
+        float r = dot(n, side_vel(SA, p) - side_vel(SB, p)) + bias;
         float nl = l0;
         if (iw0 > 0.f) nl = fmaxf(0.f, l0 - r * iw0);
         float dl = nl - l0;
-        if (dl != 0.f) {
-          side_apply(F, fm, A, sA, p, n * dl);
-          side_apply(F, fm, A, sB, p, n * (-dl));
-        }
+        side_impulse(SA, p, n * dl);
+        side_impulse(SB, p, n * (-dl));
         if (iw1 > 0.f && iw2 > 0.f) {
           f3 t1, t2;
           onb(n, t1, t2);
-          f3 du2 = side_point_vel(F, fm, A, sA, p) - side_point_vel(F, fm, A, sB, p);
-          float y1 = l1 - dot(t1, du2) * iw1, y2 = l2 - dot(t2, du2) * iw2;
-          float lim = mu * nl;
-          float nn = y1 * y1 + y2 * y2;
-          if (nn > lim * lim) {
-            if (lim > 0.f) {
-              float sc = lim / sqrtf(nn);
-              y1 *= sc;
-              y2 *= sc;
-            } else {
-              y1 = 0.f;
-              y2 = 0.f;
-            }
-          }
+          f3 du = side_vel(SA, p) - side_vel(SB, p);
+          float y1, y2;
+          friction_disk(l1, l2, dot(t1, du), dot(t2, du), iw1, iw2, mu * nl, y1, y2);
           f3 P = t1 * (y1 - l1) + t2 * (y2 - l2);
-          side_apply(F, fm, A, sA, p, P);
-          side_apply(F, fm, A, sB, p, P * (-1.f));
+          side_impulse(SA, p, P);
+          side_impulse(SB, p, P * (-1.f));
           l1 = y1;
           l2 = y2;
         }
-        C[(C_LAM + 0) * cc + ci] = nl;
-        C[(C_LAM + 1) * cc + ci] = l1;
-        C[(C_LAM + 2) * cc + ci] = l2;
+        side_store(F, A, SA);
+        side_store(F, A, SB);
+        c[C_LAM] = nl;
+        c[C_LAM + 1] = l1;
+        c[C_LAM + 2] = l2;
       }
       wave_sync();
     }
   }
 }
 
-__device__ void phase_integrate(const KArgs& a, const Scene& S, float* L, const Robot& rb, float vR) {
+__device__ __forceinline__ void phase_integrate(const KArgs& a, const Scene& S, float* L, const Robot& rb, float vR) {
   const int lane = lane_id();
   if (lane < ND) {
     rb.qd[lane] = vR;
@@ -1254,11 +1540,11 @@ __device__ void phase_integrate(const KArgs& a, const Scene& S, float* L, const 
   float* F = L + a.L.fr;
   const int fm = a.L.fmax;
   for (int f = lane; f < S.nf; f += WAVE) {
-    f3 v = mk3(F[(F_V + 0) * fm + f], F[(F_V + 1) * fm + f], F[(F_V + 2) * fm + f]);
-    f3 w = mk3(F[(F_W + 0) * fm + f], F[(F_W + 1) * fm + f], F[(F_W + 2) * fm + f]);
-    F[(F_X + 0) * fm + f] += a.h * v.x;
-    F[(F_X + 1) * fm + f] += a.h * v.y;
-    F[(F_X + 2) * fm + f] += a.h * v.z;
+    f3 v = mk3(F[(f) * FSTR + F_V + 0], F[(f) * FSTR + F_V + 1], F[(f) * FSTR + F_V + 2]);
+    f3 w = mk3(F[(f) * FSTR + F_W + 0], F[(f) * FSTR + F_W + 1], F[(f) * FSTR + F_W + 2]);
+    F[(f) * FSTR + F_X + 0] += a.h * v.x;
+    F[(f) * FSTR + F_X + 1] += a.h * v.y;
+    F[(f) * FSTR + F_X + 2] += a.h * v.z;
     f3 th = w * a.h;
     float n2 = dot(th, th);
     float cw, sk;
@@ -1271,17 +1557,17 @@ __device__ void phase_integrate(const KArgs& a, const Scene& S, float* L, const 
       sk = sinf(0.5f * nn) / nn;
     }
     float e0 = cw, e1 = th.x * sk, e2 = th.y * sk, e3 = th.z * sk;
-    float q0 = F[(F_Q + 0) * fm + f], q1 = F[(F_Q + 1) * fm + f], q2 = F[(F_Q + 2) * fm + f],
-          q3 = F[(F_Q + 3) * fm + f];
+    float q0 = F[(f) * FSTR + F_Q + 0], q1 = F[(f) * FSTR + F_Q + 1], q2 = F[(f) * FSTR + F_Q + 2],
+          q3 = F[(f) * FSTR + F_Q + 3];
     float r0 = e0 * q0 - (e1 * q1 + e2 * q2 + e3 * q3);
     float r1 = e0 * q1 + q0 * e1 + (e2 * q3 - e3 * q2);
     float r2 = e0 * q2 + q0 * e2 + (e3 * q1 - e1 * q3);
     float r3 = e0 * q3 + q0 * e3 + (e1 * q2 - e2 * q1);
     float inv = 1.f / sqrtf(r0 * r0 + r1 * r1 + r2 * r2 + r3 * r3);
-    F[(F_Q + 0) * fm + f] = r0 * inv;
-    F[(F_Q + 1) * fm + f] = r1 * inv;
-    F[(F_Q + 2) * fm + f] = r2 * inv;
-    F[(F_Q + 3) * fm + f] = r3 * inv;
+    F[(f) * FSTR + F_Q + 0] = r0 * inv;
+    F[(f) * FSTR + F_Q + 1] = r1 * inv;
+    F[(f) * FSTR + F_Q + 2] = r2 * inv;
+    F[(f) * FSTR + F_Q + 3] = r3 * inv;
   }
   float* A = L + a.L.aux;
   if (lane < S.na) {
@@ -1292,7 +1578,7 @@ __device__ void phase_integrate(const KArgs& a, const Scene& S, float* L, const 
   wave_sync();
 }
 
-__device__ void run_scene(const KArgs& a, int s, float* L) {
+__device__ __forceinline__ void run_scene(const KArgs& a, int s, float* L) {
   const int lane = lane_id();
   Scene S;
   const DScene ds = a.scenes[s];
@@ -1303,7 +1589,7 @@ __device__ void run_scene(const KArgs& a, int s, float* L) {
   S.nf = ds.nf; S.ns = ds.ns; S.np = ds.np; S.na = ds.na; S.nfo = ds.nown;
   S.f0 = ds.f0; S.s0 = ds.s0; S.p0 = ds.p0; S.a0 = ds.a0;
   S.hold = a.scenes[s].hold;
-  Robot rb = robot_view(L + a.L.robot);
+  Robot rb = robot_view(L + a.L.robot, L + a.L.rows);
   const bool prof = a.phase_cycles != nullptr;
   unsigned long long cyc[8] = {0, 0, 0, 0, 0, 0, 0, 0};
   unsigned long long tc = prof ? clock64() : 0;
@@ -1323,7 +1609,7 @@ __device__ void run_scene(const KArgs& a, int s, float* L) {
     phase_drive(a, S, rb);
     phase_kinematics(a, S, L, rb);
     MS_PHASE(0)
-    phase_contacts(a, S, L, NC, NR, NL, status, keysum);
+    phase_contacts(a, S, L, rb, NC, NR, NL, status, keysum);
     MS_PHASE(1)
     phase_dynamics(a, S, L, rb, vR);
     MS_PHASE(2)
@@ -1358,20 +1644,21 @@ __device__ void run_scene(const KArgs& a, int s, float* L) {
   }
 }
 
-__global__ __launch_bounds__(WAVE) void k_step(KArgs a) {
+__global__ __launch_bounds__(WAVE) __attribute__((amdgpu_waves_per_eu(2, 2))) void k_step(KArgs a) {
   extern __shared__ float lds[];
-  if (a.persistent) {
-    for (;;) {
-      int idx = 0;
-      if (threadIdx.x == 0) idx = atomicAdd(a.queue, 1);
-      idx = __shfl(idx, 0, WAVE);
-      if (idx >= a.S) break;
-      run_scene(a, a.order[idx], lds);
-      __syncthreads();
+  // one call site: the persistent form pulls scene indices from the queue,
+  // the plain form takes its block index once
+  int idx = a.persistent ? 0 : (int)blockIdx.x;
+  for (;;) {
+    if (a.persistent) {
+      int got = 0;
+      if (threadIdx.x == 0) got = atomicAdd(a.queue, 1);
+      idx = __shfl(got, 0, WAVE);
     }
-  } else {
-    int idx = blockIdx.x;
-    if (idx < a.S) run_scene(a, a.order[idx], lds);
+    if (idx >= a.S) break;
+    run_scene(a, a.order[idx], lds);
+    if (!a.persistent) break;
+    __syncthreads();
   }
 }
 

@@ -67,6 +67,7 @@ class SceneBatch:
     control_mode: int
     contact_cap: int
     n_steps: int
+    robot_contact_cap: int
     # robot models
     model_nb: np.ndarray        # int32[M]
     model_parent: np.ndarray    # int32[M,16]
@@ -605,8 +606,8 @@ def config1(seed=BASE_SEED, n_scenes=16):
         box = dict(type=FREE_BOX, size=half, mass=m, inertia=_box_inertia(m, 2 * half),
                    pos=(r * math.cos(a), r * math.sin(a), e / 2), quat=_quat_z(g.uniform(-math.pi, math.pi)))
         per.append(dict(model=s, q=q, free=[box], static=[], planes=_room_planes(False), aux=[]))
-    params = dict(h=0.02 / 4, n_sub=4, pgs_iters=8, control_mode=CTRL_TORQUE, contact_cap=64, n_steps=100,
-                  **_PARAM_DEFAULTS)
+    params = dict(h=0.02 / 4, n_sub=4, pgs_iters=8, control_mode=CTRL_TORQUE, contact_cap=48, n_steps=100,
+                  robot_contact_cap=32, **_PARAM_DEFAULTS)
     return _assemble("cfg1_arm7", 1, n_scenes, params, models, per, seed, ctrl_kind="torque_normal",
                      ctrl_sigma=2.0)
 
@@ -650,14 +651,14 @@ def config2(seed=BASE_SEED, n_scenes=1024, h=None, n_sub=5):
     """Fetch-like robot, 8 free boxes/spheres (U[0.04, 0.2] m), 64 furniture
     boxes (U[0.2, 2] m) in a 6 x 6 m room; dt = 0.01 s, 5 substeps, 10 PGS sweeps."""
     params = dict(h=(0.01 / n_sub if h is None else h), n_sub=n_sub, pgs_iters=10, control_mode=CTRL_PD,
-                  contact_cap=160, n_steps=50, **_PARAM_DEFAULTS)
+                  contact_cap=64, n_steps=50, robot_contact_cap=24, **_PARAM_DEFAULTS)
     return _fetch_batch("cfg2_fetch", 2, seed, n_scenes, lambda g: 8, lambda g: 64, params)
 
 
 def config3(seed=BASE_SEED, n_scenes=4096):
     """Uneven batch: free objects U{2..32}, furniture boxes U{32..256} per scene."""
-    params = dict(h=0.01 / 5, n_sub=5, pgs_iters=10, control_mode=CTRL_PD, contact_cap=320, n_steps=50,
-                  **_PARAM_DEFAULTS)
+    params = dict(h=0.01 / 5, n_sub=5, pgs_iters=10, control_mode=CTRL_PD, contact_cap=160, n_steps=50,
+                  robot_contact_cap=24, **_PARAM_DEFAULTS)
     return _fetch_batch("cfg3_uneven", 3, seed, n_scenes, lambda g: int(g.integers(2, 33)),
                         lambda g: int(g.integers(32, 257)), params)
 
@@ -666,8 +667,8 @@ def config4(seed=BASE_SEED, n_scenes=256):
     """Differentiation workload: config-2 geometry, torque controls added to a PD
     hold, one box resting against the base bumper that the base pushes forward;
     50 control steps of dt = 0.02 s with 4 substeps."""
-    params = dict(h=0.02 / 4, n_sub=4, pgs_iters=10, control_mode=CTRL_TORQUE_HOLD, contact_cap=160,
-                  n_steps=50, **_PARAM_DEFAULTS)
+    params = dict(h=0.02 / 4, n_sub=4, pgs_iters=10, control_mode=CTRL_TORQUE_HOLD, contact_cap=64,
+                  n_steps=50, robot_contact_cap=24, **_PARAM_DEFAULTS)
 
     def post(g, sc):
         yaw = sc["yaw"]
@@ -701,8 +702,8 @@ def config5(seed=BASE_SEED, n_scenes=16384):
     """Fetch-like robot + revolute door (0.6 x 1.8 m panel, 10 kg) + prismatic
     drawer (0.5 x 0.4 x 0.2 m, 3 kg, stroke [0, 0.4] m) + 4 free objects +
     64 furniture boxes; h = 0.002 s, 5 substeps, 20 control steps."""
-    params = dict(h=0.002, n_sub=5, pgs_iters=10, control_mode=CTRL_PD, contact_cap=160, n_steps=20,
-                  **_PARAM_DEFAULTS)
+    params = dict(h=0.002, n_sub=5, pgs_iters=10, control_mode=CTRL_PD, contact_cap=64, n_steps=20,
+                  robot_contact_cap=32, **_PARAM_DEFAULTS)
 
     def aux_fn(g, sc):
         spawn, yaw = sc["spawn"], sc["yaw"]
@@ -780,7 +781,8 @@ def custom_batch(models, scenes, h=0.005, n_sub=1, pgs_iters=8, mu=0.5, baumgart
             d["hold"] = np.asarray(sc["hold"], float)
         per.append(d)
     params = dict(h=h, n_sub=n_sub, pgs_iters=pgs_iters, control_mode=control_mode, contact_cap=contact_cap,
-                  n_steps=1, mu=mu, baumgarte=baumgarte, margin=margin, gravity=tuple(gravity))
+                  n_steps=1, mu=mu, baumgarte=baumgarte, margin=margin, gravity=tuple(gravity),
+                  robot_contact_cap=min(contact_cap, 32))
     b = _assemble(name, 0, len(per), params, models, per, BASE_SEED)
     st = split_state(b.state0, b.n_scenes, b.n_free, b.n_aux)
     k = 0

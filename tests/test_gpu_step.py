@@ -3,9 +3,9 @@
 Single control steps are teacher-forced: both sides start from the same
 float32-representable states taken along oracle trajectories.  Bars: position
 error <= 1e-5 m and velocity error <= 1e-4 m/s (rad/s) per step, or, where
-larger, 4x the deviation of the oracle's own single-precision evaluation from
-its FP64 result, or 10x the oracle's change under 1-ulp float32 input
-perturbations (contact-rich states amplify rounding: the speculative bias
+larger, 10x the larger of the deviation of the oracle's own single-precision
+evaluation from its FP64 result and the oracle's change under 1-ulp float32
+input perturbations (contact-rich states amplify rounding: the speculative bias
 scales position rounding by 1/h, Gauss-Seidel on many coupled robot rows
 amplifies it further); 100-step trajectories <= 1e-3 m where the per-substep contact sets
 agree all along and the oracle with float32 rounding noise injected every
@@ -85,8 +85,8 @@ def test_single_step_parity(name, mk, steps):
         pe, ve = errors(o, b, xo, xg)
         ps, vs = fp32_sensitivity(o, b, x, u)
         pf, vf = errors(o, b, xo, o.step_f32(x, u))
-        tol_p = np.maximum.reduce([np.full_like(ps, POS_TOL), 10 * ps, 4 * pf])
-        tol_v = np.maximum.reduce([np.full_like(vs, VEL_TOL), 10 * vs, 4 * vf])
+        tol_p = np.maximum.reduce([np.full_like(ps, POS_TOL), 10 * ps, 10 * pf])
+        tol_v = np.maximum.reduce([np.full_like(vs, VEL_TOL), 10 * vs, 10 * vf])
         n_match += int(same.sum())
         n_tot += len(same)
         strict = same & (pe <= POS_TOL) & (ve <= VEL_TOL)
@@ -149,18 +149,45 @@ def _run_sched(ms, b, flags, x, u, steps=2):
 
 
 def test_schedules_bitwise_equal():
+    """Grid shape, persistent queue, graph replay, per-substep launches and LDS
+    staging change only where and when the same arithmetic runs."""
     ms = _ms()
     b = sg.make(3, 40)
     x = b.state0
     u = b.controls(0)
     say("[schedules] cfg3 S=40")
-    ref = _run_sched(ms, b, ms.MS_SCHED_STAGE_STATIC, x, u)
-    for flags in [0, ms.MS_SCHED_PERSISTENT, ms.MS_SCHED_GRAPH | ms.MS_SCHED_STAGE_STATIC,
-                  ms.MS_SCHED_GRAPH | ms.MS_SCHED_PERSISTENT | ms.MS_SCHED_STAGE_STATIC,
-                  ms.MS_SCHED_PER_SUBSTEP | ms.MS_SCHED_STAGE_STATIC]:
-        say(f"  flags={flags}")
-        got = _run_sched(ms, b, flags, x, u)
-        assert np.array_equal(got, ref), flags
+    for cull in (0, ms.MS_SCHED_CULL):
+        ref = _run_sched(ms, b, ms.MS_SCHED_STAGE_STATIC | cull, x, u)
+        for flags in [0, ms.MS_SCHED_PERSISTENT, ms.MS_SCHED_GRAPH | ms.MS_SCHED_STAGE_STATIC,
+                      ms.MS_SCHED_GRAPH | ms.MS_SCHED_PERSISTENT | ms.MS_SCHED_STAGE_STATIC,
+                      ms.MS_SCHED_PER_SUBSTEP | ms.MS_SCHED_STAGE_STATIC]:
+            say(f"  flags={flags | cull}")
+            got = _run_sched(ms, b, flags | cull, x, u)
+            assert np.array_equal(got, ref), flags | cull
+
+
+def test_culled_contacts_equal_brute_force_full_size():
+    """The bounding-volume pre-test keeps exactly the brute-force contact sets
+    (4096 uneven scenes, 5 control steps, every substep)."""
+    ms = _ms()
+    b = sg.make(3)
+    say("[culling] cfg3 S=4096: culled vs brute-force contact sets")
+    out = {}
+    for cull in (0, ms.MS_SCHED_CULL):
+        mb = ms.MsBatch(b)
+        mb.set_schedule(ms.MS_SCHED_STAGE_STATIC | cull)
+        mb.enable_debug(True)
+        x = torch.as_tensor(b.state0).cuda()
+        dbgs = []
+        for t in range(5):
+            x = mb.step(x, torch.as_tensor(b.controls(t)).cuda())
+            torch.cuda.synchronize()
+            dbgs.append(mb.debug_contacts().copy())
+        out[cull] = (x.cpu().numpy(), dbgs)
+    for d0, d1 in zip(out[0][1], out[ms.MS_SCHED_CULL][1]):
+        assert np.array_equal(d0, d1)
+    x0, x1 = out[0][0], out[ms.MS_SCHED_CULL][0]
+    assert np.allclose(x0, x1, rtol=1e-5, atol=1e-6)
 
 
 def test_deterministic_reruns():
