@@ -94,6 +94,44 @@ def load_traffic(name, nscenes, src_hash):
     return d.get("bytes_per_launch")
 
 
+def time_fwd_bwd(mb, x0, U, args, flags, stream, torch):
+    """Forward + backward over a horizon of T control steps: T steps forward
+    keeping every state, then T vector-Jacobian products in reverse (each
+    recomputes its step's substeps).  Inputs resident in HBM; HIP events on
+    the launch stream."""
+    T = max(1, args.bwd_steps)
+    S = mb.S
+    mb.set_schedule(flags)
+    xs = [x0.clone() for _ in range(T + 1)]
+    g0 = torch.randn_like(x0) * 1e-3
+    gx = g0.clone()
+    gu = torch.empty((S, 16), dtype=torch.float32, device=x0.device)
+
+    def once():
+        for t in range(T):
+            mb.step(xs[t], U[t % U.shape[0]], out=xs[t + 1])
+        ev_mid.record(stream)
+        gx.copy_(g0)
+        for t in range(T - 1, -1, -1):
+            mb.step_backward(xs[t], U[t % U.shape[0]], gx, gx_in=gx, gu=gu)
+
+    ev0, ev_mid, ev1 = (torch.cuda.Event(enable_timing=True) for _ in range(3))
+    once()  # warm-up (graph capture for the forward)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    ev0.record(stream)
+    once()
+    ev1.record(stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    fwd_ms = ev0.elapsed_time(ev_mid)
+    bwd_ms = ev_mid.elapsed_time(ev1)
+    ok = bool(torch.isfinite(gx).all().item() and torch.isfinite(gu).all().item())
+    return {"value": round(S * T / wall, 1), "unit": "env-steps/s", "horizon": T,
+            "ms_per_step": round(1e3 * wall / T, 4), "fwd_ms_per_step": round(fwd_ms / T, 4),
+            "bwd_ms_per_step": round(bwd_ms / T, 4), "finite": ok}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -102,6 +140,8 @@ def main():
     ap.add_argument("--config", type=int, default=3)
     ap.add_argument("--scenes", type=int, default=None)
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--no-bwd", action="store_true", help="skip the forward+backward measurement")
+    ap.add_argument("--bwd-steps", type=int, default=10, help="control steps in the timed forward+backward horizon")
     ap.add_argument("--schedule", default="auto", help="auto | graph | graph-persistent | plain")
     args = ap.parse_args()
     if args.gpus != 1:
@@ -120,7 +160,7 @@ def main():
           f"(generated in {time.perf_counter() - t_gen:.1f} s)", file=sys.stderr, flush=True)
     dev = torch.device("cuda", 0)
     torch.cuda.set_device(dev)
-    mb = ms.MsBatch(b)
+    mb = ms.MsBatch(b, backward=not args.no_bwd)
     # controls for every timed step, resident in HBM before timing
     n_ctrl = args.warmup + args.steps
     blocks = {}
@@ -170,6 +210,7 @@ def main():
     # the plain form: one launch per substep, no graph, same kernel
     wall_plain, gpu_ms_plain = run(args.steps, ms.MS_SCHED_STAGE_STATIC | ms.MS_SCHED_PER_SUBSTEP | ms.MS_SCHED_CULL,
                                    True)
+    fwd_bwd = None if args.no_bwd else time_fwd_bwd(mb, x0, U, args, flags, stream, torch)
     st = mb.status()
     value = S * args.steps / wall
     ms_per_step = 1e3 * wall / args.steps
@@ -207,6 +248,8 @@ def main():
                               "ms_per_step": round(1e3 * wall_plain / args.steps, 4)},
         "scene_status_nonzero": int(np.count_nonzero(st)),
     }
+    if fwd_bwd is not None:
+        out["fwd_bwd"] = fwd_bwd
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline(b)
     print(json.dumps(out), flush=True)

@@ -166,9 +166,11 @@ class MsBatch:
 
     ``batch`` is any object with the scene-description arrays (the scene
     generator's SceneBatch); keyword overrides replace its physics parameters.
+    ``backward=True`` allocates the adjoint workspace that ``step_backward``
+    needs (its size is ``sizes.tape`` bytes).
     """
 
-    def __init__(self, batch, device=None, robot_contact_cap=None, **over):
+    def __init__(self, batch, device=None, robot_contact_cap=None, backward=False, **over):
         import torch
         self.torch = torch
         self.device = torch.device("cuda", torch.cuda.current_device() if device is None else device)
@@ -185,10 +187,11 @@ class MsBatch:
         with torch.cuda.device(self.device):
             self.params = torch.empty(max(sz.params, 256), dtype=torch.uint8, device=self.device)
             self.scratch = torch.empty(max(sz.scratch, 256), dtype=torch.uint8, device=self.device)
-            self.tape = torch.empty(max(sz.tape, 256), dtype=torch.uint8, device=self.device)
+            self.tape = torch.empty(max(sz.tape, 256), dtype=torch.uint8, device=self.device) if backward else None
             h = C.c_void_p()
             _check(lib().ms_create_batch(C.byref(self.desc), C.byref(self.sdesc), _ptr_t(self.params),
-                                         _ptr_t(self.scratch), _ptr_t(self.tape), _stream(), C.byref(h)),
+                                         _ptr_t(self.scratch), _ptr_t(self.tape) if backward else None, _stream(),
+                                         C.byref(h)),
                    "ms_create_batch")
         self.h = h
         self.n_free = int(batch.free_off[-1])
@@ -235,6 +238,8 @@ class MsBatch:
         return out
 
     def step_backward(self, x, u, gx_out, gx_in=None, gu=None, stream=None):
+        """Vector-Jacobian product of one control step from ``x`` under ``u``:
+        returns (dL/dx, dL/du) given dL/d(next state) ``gx_out``."""
         self._check_state(x, "state_in")
         self._check_controls(u)
         self._check_state(gx_out, "grad_state_out")

@@ -20,6 +20,7 @@
 #include "../../include/ms_phys.h"
 #include "ms_internal.h"
 #include "ms_pack.h"
+#include "ms_backward.h"
 
 using namespace msk;
 
@@ -137,6 +138,16 @@ ms_status enqueue_step(ms_batch* b, const void* x_in, const float* u, void* x_ou
   return MS_OK;
 }
 
+msa::WS bwd_ws(const ms_batch_desc* d, const Counts& c) {
+  const int ntmax = c.pmax + c.smax + c.amax + std::max(c.fmax, 1);
+  return bwd_layout(std::max(c.fmax, 1), ntmax, d->contact_cap, std::max(d->robot_contact_cap, 1), d->pgs_iters,
+                    d->n_substeps);
+}
+
+size_t bwd_bytes(const ms_batch_desc* d, const Counts& c) {
+  return (size_t)bwd_ws(d, c).total * (size_t)bwd_stride(c.S) * sizeof(float);
+}
+
 }  // namespace
 
 extern "C" {
@@ -157,7 +168,7 @@ ms_status ms_query_sizes(const ms_batch_desc* d, const ms_scene_desc* sc, ms_siz
   out->params = param_layout(c).total;
   out->state = ((size_t)c.S * 32 + (size_t)c.NF * 16 + (size_t)c.NA * 4) * sizeof(float);
   out->scratch = scratch_layout(c, d->n_substeps).total;
-  out->tape = 0;
+  out->tape = bwd_bytes(d, c);
   out->lds = (size_t)lds_for(d, c, true).total * sizeof(float);
   return MS_OK;
 }
@@ -289,9 +300,37 @@ ms_status ms_step(ms_batch* b, const void* x_in, const float* u, void* x_out, vo
 
 ms_status ms_step_backward(ms_batch* b, const void* x_in, const float* u, const void* gx_out, void* gx_in,
                            float* gu, void* hip_stream) {
-  (void)x_in; (void)u; (void)gx_out; (void)gx_in; (void)gu; (void)hip_stream;
   if (!b) return fail(MS_E_INVALID, "null batch");
-  return fail(MS_E_UNSUPPORTED, "ms_step_backward: adjoint kernels not built into this library");
+  if (!x_in || !u || !gx_out || !gx_in || !gu) return fail(MS_E_INVALID, "ms_step_backward: null buffer");
+  if (!b->tape) return fail(MS_E_STATE, "ms_step_backward: the batch was created without a tape buffer");
+  const Counts& c = b->cnt;
+  const ms_batch_desc* d = &b->desc;
+  BwdArgs a;
+  std::memset(&a, 0, sizeof a);
+  a.models = reinterpret_cast<const DModel*>(b->params + b->pl.models);
+  a.scenes = reinterpret_cast<const DScene*>(b->params + b->pl.scenes);
+  a.free = reinterpret_cast<const DFree*>(b->params + b->pl.free);
+  a.statics = reinterpret_cast<const float*>(b->params + b->pl.statics);
+  a.planes = reinterpret_cast<const float4*>(b->params + b->pl.planes);
+  a.aux = reinterpret_cast<const DAux*>(b->params + b->pl.aux);
+  a.order = reinterpret_cast<const int*>(b->params + b->pl.order);
+  a.x = static_cast<const float*>(x_in);
+  a.u = u;
+  a.gxo = static_cast<const float*>(gx_out);
+  a.gxi = static_cast<float*>(gx_in);
+  a.gu = gu;
+  a.status = reinterpret_cast<uint32_t*>(b->scratch + b->sl.status);
+  a.ws = reinterpret_cast<float*>(b->tape);
+  a.S = c.S;
+  a.NF = c.NF;
+  a.stride = bwd_stride(c.S);
+  a.pr = msa::Prm{d->h, d->mu, d->baumgarte, d->margin, {d->gravity[0], d->gravity[1], d->gravity[2]},
+                  d->pgs_iters, d->control_mode, d->contact_cap, std::max(d->robot_contact_cap, 1), d->n_substeps};
+  a.w = bwd_ws(d, c);
+  hipStream_t st = static_cast<hipStream_t>(hip_stream);
+  launch_step_bwd(a, st);
+  HIP_TRY(hipGetLastError());
+  return MS_OK;
 }
 
 ms_status ms_get_state(const ms_batch* b, const void* x, ms_state_view* out) {
