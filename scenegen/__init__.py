@@ -131,11 +131,16 @@ class SceneBatch:
         return state_floats(self.n_scenes, self.n_free, self.n_aux)
 
     def controls(self, step: int, scenes=None) -> np.ndarray:
-        """Controls u[S,16] for control step ``step`` (float32)."""
-        idx = range(self.n_scenes) if scenes is None else scenes
-        out = np.zeros((len(idx), NDOF), np.float32)
-        for r, s in enumerate(idx):
-            m = int(self.scene_model[s])
+        """Controls u[len(scenes),16] for control step ``step`` (float32);
+        ``scenes`` are rows of this batch (default: all).  The random stream
+        of a scene is keyed by its id in the batch it was generated in, so a
+        subset draws the same controls as the full batch."""
+        rows = range(self.n_scenes) if scenes is None else scenes
+        ids = self.scene_ids()
+        out = np.zeros((len(rows), NDOF), np.float32)
+        for r, row in enumerate(rows):
+            s = int(ids[row])
+            m = int(self.scene_model[row])
             nb = int(self.model_nb[m])
             if self.ctrl_kind == "torque_normal":
                 g = _rng(self.seed, self.cfg_id, s, step)
@@ -194,15 +199,16 @@ class SceneBatch:
             aux_type=aux[0], aux_rot=aux[1], aux_pos=aux[2], aux_axis=aux[3],
             aux_box=aux[4], aux_mass=aux[5], aux_inertia=aux[6], aux_limit=aux[7],
             state0=state0)
-        sub._scene_ids = scenes
+        base = self.scene_ids()
+        sub._scene_ids = [base[s] for s in scenes]
         return sub
 
     def scene_ids(self):
         return getattr(self, "_scene_ids", list(range(self.n_scenes)))
 
     def controls_for(self, step):
-        """Controls at ``step`` for this batch's scenes (subset-aware)."""
-        return self.controls(step, self.scene_ids())
+        """Controls at ``step`` for every scene of this batch."""
+        return self.controls(step)
 
 
 def state_floats(S, NF, NA):

@@ -48,5 +48,6 @@ def oracle_vjp_smooth(o, b, x, u, g, trials=3, eps=1e-7, seed=1):
 
 
 def compare(ref, mask, scale, mine):
-    """Per scene: max error over smooth components relative to the scene's gradient scale."""
-    return np.array([np.abs(mine[s] - ref[s])[mask[s]].max(initial=0.0) / scale[s] for s in range(len(ref))])
+    """Per scene: ||g - g*||_2 over the smooth components / max(||g*||_2, 1e-8)."""
+    return np.array([np.linalg.norm((mine[s] - ref[s])[mask[s]]) / max(np.linalg.norm(ref[s]), 1e-8)
+                     for s in range(len(ref))])
