@@ -141,8 +141,11 @@ def main():
     ap.add_argument("--scenes", type=int, default=None)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-bwd", action="store_true", help="skip the forward+backward measurement")
+    ap.add_argument("--no-plain", action="store_true", help="skip the plain per-substep comparison run")
     ap.add_argument("--bwd-steps", type=int, default=10, help="control steps in the timed forward+backward horizon")
-    ap.add_argument("--schedule", default="auto", help="auto | graph | graph-persistent | plain")
+    ap.add_argument("--schedule", default="auto", help="auto | graph | graph-persistent | fused | plain")
+    ap.add_argument("--calibrate-copy", type=int, default=0, metavar="BYTES",
+                    help="only run a plain device copy of BYTES bytes 5 times (HBM counter calibration)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only: the step has no cross-GPU exchange and this build runs on "
@@ -150,6 +153,15 @@ def main():
         sys.exit(2)
 
     import torch
+    if args.calibrate_copy:
+        n = args.calibrate_copy // 4
+        src = torch.ones(n, dtype=torch.float32, device="cuda")
+        dst = torch.empty_like(src)
+        for _ in range(5):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_bytes": 4 * n, "launches": 5}), flush=True)
+        return
     import paper_2412_13211_amd as ms
     import scenegen as sg
 
@@ -203,13 +215,18 @@ def main():
         flags = flags_graph
     elif args.schedule == "graph-persistent":
         flags = flags_graph | ms.MS_SCHED_PERSISTENT
+    elif args.schedule == "fused":
+        flags = ms.MS_SCHED_STAGE_STATIC | ms.MS_SCHED_CULL
     else:
         flags = ms.MS_SCHED_STAGE_STATIC | ms.MS_SCHED_PER_SUBSTEP | ms.MS_SCHED_CULL
     print(f"[bench] schedule flags {flags}", file=sys.stderr, flush=True)
     wall, gpu_ms = run(args.steps, flags, True)
     # the plain form: one launch per substep, no graph, same kernel
-    wall_plain, gpu_ms_plain = run(args.steps, ms.MS_SCHED_STAGE_STATIC | ms.MS_SCHED_PER_SUBSTEP | ms.MS_SCHED_CULL,
-                                   True)
+    if args.no_plain:
+        wall_plain = float("nan")
+    else:
+        wall_plain, gpu_ms_plain = run(args.steps, ms.MS_SCHED_STAGE_STATIC | ms.MS_SCHED_PER_SUBSTEP |
+                                       ms.MS_SCHED_CULL, True)
     fwd_bwd = None if args.no_bwd else time_fwd_bwd(mb, x0, U, args, flags, stream, torch)
     st = mb.status()
     value = S * args.steps / wall
@@ -244,8 +261,9 @@ def main():
                      "kernel_ms_per_launch": round(launch_ms, 5)},
         "hbm_roofline": {"achieved": round(hbm_gbs, 3), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                          "frac": round(hbm_gbs / HBM_PEAK_GBS, 6), "bytes_per_env_step_batch": bytes_step},
-        "plain_per_substep": {"value": round(S * args.steps / wall_plain, 1), "unit": "env-steps/s",
-                              "ms_per_step": round(1e3 * wall_plain / args.steps, 4)},
+        "plain_per_substep": None if args.no_plain else {
+            "value": round(S * args.steps / wall_plain, 1), "unit": "env-steps/s",
+            "ms_per_step": round(1e3 * wall_plain / args.steps, 4)},
         "scene_status_nonzero": int(np.count_nonzero(st)),
     }
     if fwd_bwd is not None:
