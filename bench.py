@@ -79,10 +79,12 @@ def cpu_baseline(b, seconds=12.0, n=256, threads=None):
             "sample": f"{len(pick)} seeded scenes of the same workload x {steps} control steps, FP64, {dt:.1f} s"}
 
 
-def load_traffic(name, nscenes, src_hash):
+def load_traffic(name, nscenes, src_hash, flags, graph_bit):
     """HBM traffic of the dominant kernel from the committed rocprofv3 counter
-    summary, if it was taken on the current kernel source."""
-    p = os.path.join(ROOT, "profiles", f"{name}_traffic.json")
+    summary, if it was taken on the current kernel source, the same batch
+    size and the same schedule (graph replay or direct launch of the same
+    kernel does not change its traffic)."""
+    p = os.path.join(ROOT, "profiles", f"k_step_{name.split('_')[0]}_{nscenes}_traffic.json")
     if not os.path.exists(p):
         return None
     try:
@@ -90,6 +92,8 @@ def load_traffic(name, nscenes, src_hash):
     except Exception:
         return None
     if d.get("kernel_source_hash") != src_hash or d.get("scenes") != nscenes:
+        return None
+    if (int(d.get("schedule_flags", -1)) & ~graph_bit) != (int(flags) & ~graph_bit):
         return None
     return d.get("bytes_per_launch")
 
@@ -143,7 +147,7 @@ def main():
     ap.add_argument("--no-bwd", action="store_true", help="skip the forward+backward measurement")
     ap.add_argument("--no-plain", action="store_true", help="skip the plain per-substep comparison run")
     ap.add_argument("--bwd-steps", type=int, default=10, help="control steps in the timed forward+backward horizon")
-    ap.add_argument("--schedule", default="auto", help="auto | graph | graph-persistent | fused | plain")
+    ap.add_argument("--schedule", default="auto", help="auto | graph | graph-persistent | persistent | fused | plain")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="BYTES",
                     help="only run a plain device copy of BYTES bytes 5 times (HBM counter calibration)")
     args = ap.parse_args()
@@ -215,6 +219,8 @@ def main():
         flags = flags_graph
     elif args.schedule == "graph-persistent":
         flags = flags_graph | ms.MS_SCHED_PERSISTENT
+    elif args.schedule == "persistent":
+        flags = ms.MS_SCHED_PERSISTENT | ms.MS_SCHED_CULL
     elif args.schedule == "fused":
         flags = ms.MS_SCHED_STAGE_STATIC | ms.MS_SCHED_CULL
     else:
@@ -238,7 +244,7 @@ def main():
     achieved_tflops = flops_launch / (launch_ms * 1e-3) / 1e12
     hbm_gbs = bytes_step / (launch_ms * 1e-3) / 1e9
     src_hash = kernel_source_hash()
-    traffic = load_traffic(b.name, S, src_hash)
+    traffic = load_traffic(b.name, S, src_hash, flags, ms.MS_SCHED_GRAPH)
     out = {
         "metric": "physics env-steps/sec at 4096 scenes (fwd)",
         "value": round(value, 1),

@@ -138,7 +138,7 @@ typedef struct {
   size_t params;   /* device bytes: packed scene description (uploaded by ms_create_batch) */
   size_t state;    /* device bytes of one state buffer */
   size_t scratch;  /* device bytes: queue counters, schedule tables, per-scene status, debug */
-  size_t tape;     /* device bytes used by ms_step_backward (forward record of one control step) */
+  size_t tape;     /* device bytes of the adjoint workspace ms_step_backward needs */
   size_t lds;      /* LDS bytes per scene workgroup (information only) */
 } ms_sizes;
 
@@ -191,10 +191,17 @@ ms_status ms_autotune(ms_batch* b, const void* state_dev, const float* controls_
 ms_status ms_step(ms_batch* b, const void* state_in_dev, const float* controls_dev, void* state_out_dev,
                   void* hip_stream);
 
-/* Vector-Jacobian product of exactly one ms_step (recomputed internally):
- * given dL/dstate_out, writes dL/dstate_in and dL/dcontrols.  The
- * contact set and active set are those of the recomputed forward step.
- * grad_state_in_dev may alias grad_state_out_dev. */
+/* Vector-Jacobian product of exactly one ms_step (the adjoint of the step
+ * T: S x A -> S of Sec. 3, recomputed internally): given dL/dstate_out
+ * (float32, state layout), writes dL/dstate_in (state layout) and
+ * dL/dcontrols (float32 [S][16]).  The contact set and the Gauss-Seidel
+ * active set are those of the recomputed step; at a kink the derivative of
+ * max(0, y) is taken as 0 at y = 0 and a disk projection exactly on the
+ * boundary counts as inside.  Needs the batch to have been created with a
+ * tape buffer of ms_query_sizes().tape bytes (else MS_E_STATE); the buffer is
+ * scratch owned by the caller and overwritten by every call.
+ * grad_state_in_dev may alias grad_state_out_dev.  Stream-ordered; OR-s the
+ * MS_ST_* bits it meets into the scene status words. */
 ms_status ms_step_backward(ms_batch* b, const void* state_in_dev, const float* controls_dev,
                            const void* grad_state_out_dev, void* grad_state_in_dev, float* grad_controls_dev,
                            void* hip_stream);
