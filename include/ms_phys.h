@@ -71,7 +71,9 @@ enum {
   MS_SCHED_GRAPH = 2,         /* replay one control step as a captured hipGraph */
   MS_SCHED_PER_SUBSTEP = 4,   /* one launch per substep (state round trip through HBM) */
   MS_SCHED_STAGE_STATIC = 8,  /* stage each scene's furniture boxes in LDS */
-  MS_SCHED_CULL = 16          /* bounding-sphere pre-test before sphere-pair tests */
+  MS_SCHED_CULL = 16,         /* bounding-sphere pre-test before sphere-pair tests */
+  MS_SCHED_BWD_REFERENCE = 32 /* ms_step_backward on the lane-per-scene kernel that
+                                 recomputes everything itself (slow; a cross-check) */
 };
 
 typedef struct {

@@ -151,13 +151,18 @@ enum {
   C_OK = 0, C_OI = 1, C_OV = 2, C_TK = 3, C_TI = 4, C_R = 5, C_C = 6, C_PHI = 9, C_N = 10, C_P = 13, C_T1 = 16,
   C_T2 = 19, C_W = 22, C_BIAS = 25, CR = 28
 };
-// contact adjoint record: direction adjoints (n, t1, t2), point, W, bias,
-// and per side and direction the adjoints of a free body's (lin, ang) rows
-enum { B_D = 0, B_P = 9, B_W = 12, B_BIAS = 15, B_FS = 16, CB = 52 };
+// contact adjoint record: direction adjoints (n, t1, t2), contact point, W,
+// bias, and the adjoint of a door/drawer target's Jacobian entry per direction
+enum { B_D = 0, B_P = 9, B_W = 12, B_BIAS = 15, B_AJ = 16, CB = 19 };
 // free-body adjoint record
 enum { F_XB = 0, F_RB = 3, F_IIB = 12, F_IWB = 21, FB = 32 };
 // door / drawer adjoint record
 enum { X_RB = 0, X_BCB = 9, X_QB = 12, XB = 16 };
+
+// level schedule arrays (ints): level of row, rows by level, level offsets,
+// robot row of each level, last level of each dynamic node, counters
+MSA_HD inline int lv_rows(int ccap) { return 2 * AMAX + ccap; }
+MSA_HD inline int lv_ints(int ccap) { return 4 * lv_rows(ccap) + 4 + 64 + 8; }
 
 struct WS {
   int fmax, ntmax, ccap, rcap, K, nsub, ss;
@@ -169,10 +174,13 @@ struct WS {
   int vR, vA, vF, lam, llam, con, lim, rJ, rw;
   int vRb, vAb, vFb, lamb, llamb, limb, conb, rJb, rwb, fb, xb;
   int Mb, sb, Ib, Icb, fbar, abar, vbar, bacc;
+  int lv;  // level schedule (wavefront kernel only)
   int total;
 };
 
-MSA_HD inline WS ws_layout(int fmax, int ntmax, int ccap, int rcap, int K, int nsub) {
+// wave = true: the layout of the wavefront kernel's LDS block (one state
+// record, the tape and candidate lists elsewhere, plus the level schedule)
+MSA_HD inline WS ws_layout(int fmax, int ntmax, int ccap, int rcap, int K, int nsub, bool wave = false) {
   WS w;
   w.fmax = fmax < 1 ? 1 : fmax;
   w.ntmax = ntmax < 1 ? 1 : ntmax;
@@ -184,15 +192,15 @@ MSA_HD inline WS ws_layout(int fmax, int ntmax, int ccap, int rcap, int K, int n
   const int fm = w.fmax;
   int o = 0;
   auto take = [&](int n) { int r = o; o += n; return r; };
-  w.st = take((nsub + 1) * w.ss);
+  w.st = take((wave ? 1 : nsub + 1) * w.ss);
   w.gA = take(w.ss);
   w.gB = take(w.ss);
   w.ub = take(ND);
-  w.tape = take(K * (2 * AMAX + 3 * ccap));
+  w.tape = take(wave ? 0 : K * 3 * (2 * AMAX + ccap));
   w.kR = take(ND * 9); w.kp = take(ND * 3); w.ka = take(ND * 3); w.ko = take(ND * 3); w.kc = take(ND * 3);
   w.kIcw = take(ND * 6); w.ks = take(ND * 6); w.kI = take(ND * 36); w.kIc = take(ND * 36);
   w.sph = take(SPH * 3);
-  w.tl = take((ND + 1) * (w.ntmax + 1));
+  w.tl = take(wave ? 0 : (ND + 1) * (w.ntmax + 1));
   w.fR = take(fm * 9); w.fIw = take(fm * 9); w.fIi = take(fm * 9);
   w.xR = take(AMAX * 9); w.xbc = take(AMAX * 3); w.xa = take(AMAX * 3); w.xo = take(AMAX * 3);
   w.xM = take(AMAX); w.xC = take(AMAX);
@@ -211,6 +219,7 @@ MSA_HD inline WS ws_layout(int fmax, int ntmax, int ccap, int rcap, int K, int n
   w.Mb = take(ND * ND); w.sb = take(ND * 6); w.Ib = take(ND * 36); w.Icb = take(ND * 36);
   w.fbar = take(ND * 6); w.abar = take(ND * 6); w.vbar = take(ND * 6);
   w.bacc = take(ND * 9);
+  w.lv = take(wave ? lv_ints(ccap) : 0);
   w.total = o;
   return w;
 }
@@ -330,6 +339,11 @@ struct Eng {
   Buf b;
   int nb, nsph, nc, nrob, nlim;
   uint32_t status;
+  // pre-projection values of the row updates: sweep it, row r (limit rows
+  // first, then contacts), slot d (normal, tangent 1, tangent 2)
+  Buf tb;
+  int tsw;  // floats per sweep
+  MSA_HD float& tape_at(int it, int r, int d) const { return tb[(long)it * tsw + 3 * r + d]; }
 
   MSA_HD float& at(long e) const { return b[e]; }
   MSA_HD V v3(long e) const { return bl3(b, e); }
@@ -737,7 +751,7 @@ struct Eng {
     r[0] = a.x; r[1] = a.y; r[2] = a.z; r[3] = c.x; r[4] = c.y; r[5] = c.z;
   }
 
-  MSA_HD void dynamics(long s) {
+  MSA_HD void dynamics(long s, bool set_vel = true) {
     const DModel& M = *sc.M;
     const float h = pr.h;
     // composite inertias and the joint-space mass matrix (CRBA)
@@ -819,15 +833,11 @@ struct Eng {
     float z[ND];
     for (int j = 0; j < nb; ++j) z[j] = at(w.tau + j) - C[j];
     chol_solve(z);
+    for (int j = 0; j < ND; ++j) at(w.z + j) = j < nb ? z[j] : 0.f;
+    if (!set_vel) return;
     for (int j = 0; j < ND; ++j) {
       float qd = at(s + ND + j);
-      if (j < nb) {
-        at(w.z + j) = z[j];
-        at(w.vR + j) = qd + h * z[j];
-      } else {
-        at(w.z + j) = 0.f;
-        at(w.vR + j) = qd;
-      }
+      at(w.vR + j) = j < nb ? qd + h * z[j] : qd;
     }
     for (int x = 0; x < sc.na; ++x) at(w.vA + x) = at(s + axo(x) + 1) + h * ((0.f - at(w.xC + x)) / at(w.xM + x));
     for (int f = 0; f < sc.nf; ++f) {
@@ -939,26 +949,31 @@ struct Eng {
   }
 
   // ---------------------------------------------------------------- Gauss-Seidel
-  MSA_HD long tslot(int it) const { return w.tape + (long)it * (2 * AMAX + 3 * w.ccap); }
-  MSA_HD float rowvel(int ci, int di) const {
+  // side masks of a contact's row primitives: A = owner, B = target
+  static constexpr int SA = 1, SB = 2, SAB = 3;
+  MSA_HD float rowvel(int ci, int di, int sides = SAB) const {
     long e = w.con + (long)ci * CR;
     int ok = (int)at(e + C_OK), oi = (int)at(e + C_OI), tk = (int)at(e + C_TK), ti = (int)at(e + C_TI);
     V d = dir(e, di), p = v3(e + C_P);
     float r = 0.f;
-    if (ok == 0) {
-      long rj = w.rJ + ((long)ci * 3 + di) * ND;
-      for (int j = 0; j < nb; ++j) r += at(rj + j) * at(w.vR + j);
-    } else {
-      V lin, ang;
-      free_side(oi, d, p, 1.f, lin, ang);
-      r += dot(lin, v3(w.vF + oi * 6)) + dot(ang, v3(w.vF + oi * 6 + 3));
+    if (sides & SA) {
+      if (ok == 0) {
+        long rj = w.rJ + ((long)ci * 3 + di) * ND;
+        for (int j = 0; j < nb; ++j) r += at(rj + j) * at(w.vR + j);
+      } else {
+        V lin, ang;
+        free_side(oi, d, p, 1.f, lin, ang);
+        r += dot(lin, v3(w.vF + oi * 6)) + dot(ang, v3(w.vF + oi * 6 + 3));
+      }
     }
-    if (tk == 2) {
-      r += aux_J(ti, d, p, -1.f) * at(w.vA + ti);
-    } else if (tk == 3) {
-      V lin, ang;
-      free_side(ti, d, p, -1.f, lin, ang);
-      r += dot(lin, v3(w.vF + ti * 6)) + dot(ang, v3(w.vF + ti * 6 + 3));
+    if (sides & SB) {
+      if (tk == 2) {
+        r += aux_J(ti, d, p, -1.f) * at(w.vA + ti);
+      } else if (tk == 3) {
+        V lin, ang;
+        free_side(ti, d, p, -1.f, lin, ang);
+        r += dot(lin, v3(w.vF + ti * 6)) + dot(ang, v3(w.vF + ti * 6 + 3));
+      }
     }
     return r;
   }
@@ -968,74 +983,82 @@ struct Eng {
     a3(w.vF + f * 6, lin * (1.f / sc.F[f].mass) * dl);
     a3(w.vF + f * 6 + 3, rmv(Ii, ang) * dl);
   }
-  MSA_HD void apply(int ci, int di, float dl) const {
+  MSA_HD void apply(int ci, int di, float dl, int sides = SAB) const {
     long e = w.con + (long)ci * CR;
     int ok = (int)at(e + C_OK), oi = (int)at(e + C_OI), tk = (int)at(e + C_TK), ti = (int)at(e + C_TI);
     V d = dir(e, di), p = v3(e + C_P);
-    if (ok == 0) {
-      long rw = w.rw + ((long)ci * 3 + di) * ND;
-      for (int j = 0; j < nb; ++j) at(w.vR + j) += at(rw + j) * dl;
-    } else {
-      V lin, ang;
-      free_side(oi, d, p, 1.f, lin, ang);
-      free_apply(oi, lin, ang, dl);
+    if (sides & SA) {
+      if (ok == 0) {
+        long rw = w.rw + ((long)ci * 3 + di) * ND;
+        for (int j = 0; j < nb; ++j) at(w.vR + j) += at(rw + j) * dl;
+      } else {
+        V lin, ang;
+        free_side(oi, d, p, 1.f, lin, ang);
+        free_apply(oi, lin, ang, dl);
+      }
     }
-    if (tk == 2) {
-      float J = aux_J(ti, d, p, -1.f);
-      at(w.vA + ti) += (J / at(w.xM + ti)) * dl;
-    } else if (tk == 3) {
-      V lin, ang;
-      free_side(ti, d, p, -1.f, lin, ang);
-      free_apply(ti, lin, ang, dl);
+    if (sides & SB) {
+      if (tk == 2) {
+        float J = aux_J(ti, d, p, -1.f);
+        at(w.vA + ti) += (J / at(w.xM + ti)) * dl;
+      } else if (tk == 3) {
+        V lin, ang;
+        free_side(ti, d, p, -1.f, lin, ang);
+        free_apply(ti, lin, ang, dl);
+      }
     }
   }
   MSA_HD bool row_ok(int ci, int di) const { return at(w.con + (long)ci * CR + C_W + di) >= 1e-12f; }
 
+  // one limit row update (sweep it); records its pre-projection value
+  MSA_HD void limit_update(int it, int li, bool tape) const {
+    long e = w.lim + li * 4;
+    int x = (int)at(e);
+    float sgn = at(e + 1), bias = at(e + 2), W = at(e + 3);
+    float r = sgn * at(w.vA + x) + bias;
+    float y = at(w.llam + li) - r / W;
+    if (tape) tape_at(it, li, 0) = y;
+    float nl = y > 0.f ? y : 0.f;
+    float dl = nl - at(w.llam + li);
+    at(w.vA + x) += (sgn * W) * dl;
+    at(w.llam + li) = nl;
+  }
+  // one contact's normal then friction-pair update (sweep it)
+  MSA_HD void contact_update(int it, int ci, bool tape) const {
+    long e = w.con + (long)ci * CR;
+    long lm = w.lam + ci * 3;
+    const int row = nlim + ci;
+    if (row_ok(ci, 0)) {
+      float r = rowvel(ci, 0) + at(e + C_BIAS);
+      float y = at(lm) - r / at(e + C_W);
+      if (tape) tape_at(it, row, 0) = y;
+      float nl = y > 0.f ? y : 0.f;
+      apply(ci, 0, nl - at(lm));
+      at(lm) = nl;
+    }
+    if (row_ok(ci, 1) && row_ok(ci, 2)) {
+      float r1 = rowvel(ci, 1), r2 = rowvel(ci, 2);
+      float y1 = at(lm + 1) - r1 / at(e + C_W + 1);
+      float y2 = at(lm + 2) - r2 / at(e + C_W + 2);
+      if (tape) {
+        tape_at(it, row, 1) = y1;
+        tape_at(it, row, 2) = y2;
+      }
+      float o1, o2;
+      disk_proj(y1, y2, pr.mu * at(lm), o1, o2);
+      float d1 = o1 - at(lm + 1), d2 = o2 - at(lm + 2);
+      apply(ci, 1, d1);
+      apply(ci, 2, d2);
+      at(lm + 1) = o1;
+      at(lm + 2) = o2;
+    }
+  }
   MSA_HD void pgs(bool tape) {
     for (int i = 0; i < 3 * nc; ++i) at(w.lam + i) = 0.f;
     for (int i = 0; i < nlim; ++i) at(w.llam + i) = 0.f;
     for (int it = 0; it < pr.K; ++it) {
-      long ts = tslot(it);
-      for (int li = 0; li < nlim; ++li) {
-        long e = w.lim + li * 4;
-        int x = (int)at(e);
-        float sgn = at(e + 1), bias = at(e + 2), W = at(e + 3);
-        float r = sgn * at(w.vA + x) + bias;
-        float y = at(w.llam + li) - r / W;
-        if (tape) at(ts + li) = y;
-        float nl = y > 0.f ? y : 0.f;
-        float dl = nl - at(w.llam + li);
-        at(w.vA + x) += (sgn * W) * dl;
-        at(w.llam + li) = nl;
-      }
-      for (int ci = 0; ci < nc; ++ci) {
-        long e = w.con + (long)ci * CR;
-        long lm = w.lam + ci * 3;
-        if (row_ok(ci, 0)) {
-          float r = rowvel(ci, 0) + at(e + C_BIAS);
-          float y = at(lm) - r / at(e + C_W);
-          if (tape) at(ts + 2 * AMAX + ci * 3) = y;
-          float nl = y > 0.f ? y : 0.f;
-          apply(ci, 0, nl - at(lm));
-          at(lm) = nl;
-        }
-        if (row_ok(ci, 1) && row_ok(ci, 2)) {
-          float r1 = rowvel(ci, 1), r2 = rowvel(ci, 2);
-          float y1 = at(lm + 1) - r1 / at(e + C_W + 1);
-          float y2 = at(lm + 2) - r2 / at(e + C_W + 2);
-          if (tape) {
-            at(ts + 2 * AMAX + ci * 3 + 1) = y1;
-            at(ts + 2 * AMAX + ci * 3 + 2) = y2;
-          }
-          float o1, o2;
-          disk_proj(y1, y2, pr.mu * at(lm), o1, o2);
-          float d1 = o1 - at(lm + 1), d2 = o2 - at(lm + 2);
-          apply(ci, 1, d1);
-          apply(ci, 2, d2);
-          at(lm + 1) = o1;
-          at(lm + 2) = o2;
-        }
-      }
+      for (int li = 0; li < nlim; ++li) limit_update(it, li, tape);
+      for (int ci = 0; ci < nc; ++ci) contact_update(it, ci, tape);
     }
   }
 
@@ -1181,219 +1204,237 @@ struct Eng {
   }
 
   // --------------------------------------------------------------- Gauss-Seidel^T
-  MSA_HD long fs_slot(int ci, int side, int di) const { return w.conb + (long)ci * CB + B_FS + (side * 3 + di) * 6; }
+  // adjoint of a free side's row vectors lin = sgn d, ang = sgn (p - x) x d,
+  // folded at once into the direction, contact-point and body-position adjoints
+  MSA_HD void free_row_bar(int ci, int di, int f, float sgn, V linb, V angb) const {
+    long e = w.con + (long)ci * CR, cb = w.conb + (long)ci * CB;
+    V d = dir(e, di), p = v3(e + C_P);
+    V rr = p - v3(cur_s + fro(f));
+    a3(cb + B_D + di * 3, linb * sgn + cross(angb, rr) * sgn);
+    V rrb = cross(d, angb) * sgn;
+    a3(cb + B_P, rrb);
+    a3(w.fb + f * FB + F_XB, -rrb);
+  }
   // adjoint of r = J . v (v = the velocities before the update): Jbar += rb v, vbar += rb J
-  MSA_HD void rowvel_bar(int ci, int di, float rb) const {
+  MSA_HD void rowvel_bar(int ci, int di, float rb, int sides = SAB) const {
     long e = w.con + (long)ci * CR;
     int ok = (int)at(e + C_OK), oi = (int)at(e + C_OI), tk = (int)at(e + C_TK), ti = (int)at(e + C_TI);
     V d = dir(e, di), p = v3(e + C_P);
-    if (ok == 0) {
-      long rj = w.rJ + ((long)ci * 3 + di) * ND, rjb = w.rJb + ((long)ci * 3 + di) * ND;
-      for (int j = 0; j < nb; ++j) {
-        at(rjb + j) += rb * at(w.vR + j);
-        at(w.vRb + j) += rb * at(rj + j);
+    if (sides & SA) {
+      if (ok == 0) {
+        long rj = w.rJ + ((long)ci * 3 + di) * ND, rjb = w.rJb + ((long)ci * 3 + di) * ND;
+        for (int j = 0; j < nb; ++j) {
+          at(rjb + j) += rb * at(w.vR + j);
+          at(w.vRb + j) += rb * at(rj + j);
+        }
+      } else {
+        V lin, ang;
+        free_side(oi, d, p, 1.f, lin, ang);
+        free_row_bar(ci, di, oi, 1.f, v3(w.vF + oi * 6) * rb, v3(w.vF + oi * 6 + 3) * rb);
+        a3(w.vFb + oi * 6, lin * rb);
+        a3(w.vFb + oi * 6 + 3, ang * rb);
       }
-    } else {
-      V lin, ang;
-      free_side(oi, d, p, 1.f, lin, ang);
-      long fsl = fs_slot(ci, 0, di);
-      a3(fsl, v3(w.vF + oi * 6) * rb);
-      a3(fsl + 3, v3(w.vF + oi * 6 + 3) * rb);
-      a3(w.vFb + oi * 6, lin * rb);
-      a3(w.vFb + oi * 6 + 3, ang * rb);
     }
-    if (tk == 2) {
-      float J = aux_J(ti, d, p, -1.f);
-      at(fs_slot(ci, 1, di)) += rb * at(w.vA + ti);
-      at(w.vAb + ti) += rb * J;
-    } else if (tk == 3) {
-      V lin, ang;
-      free_side(ti, d, p, -1.f, lin, ang);
-      long fsl = fs_slot(ci, 1, di);
-      a3(fsl, v3(w.vF + ti * 6) * rb);
-      a3(fsl + 3, v3(w.vF + ti * 6 + 3) * rb);
-      a3(w.vFb + ti * 6, lin * rb);
-      a3(w.vFb + ti * 6 + 3, ang * rb);
+    if (sides & SB) {
+      if (tk == 2) {
+        float J = aux_J(ti, d, p, -1.f);
+        at(w.conb + (long)ci * CB + B_AJ + di) += rb * at(w.vA + ti);
+        at(w.vAb + ti) += rb * J;
+      } else if (tk == 3) {
+        V lin, ang;
+        free_side(ti, d, p, -1.f, lin, ang);
+        free_row_bar(ci, di, ti, -1.f, v3(w.vF + ti * 6) * rb, v3(w.vF + ti * 6 + 3) * rb);
+        a3(w.vFb + ti * 6, lin * rb);
+        a3(w.vFb + ti * 6 + 3, ang * rb);
+      }
     }
   }
-  MSA_HD float free_apply_bar(int f, V ang, float dl, long fsl) const {
-    float Ii[9];
-    ld9(w.fIi + f * 9, Ii);
-    float im = 1.f / sc.F[f].mass;
-    V vb = v3(w.vFb + f * 6), wb = v3(w.vFb + f * 6 + 3);
-    V lin_unused{0.f, 0.f, 0.f};
-    (void)lin_unused;
-    // v += (lin / m) dl ; w += (I^-1 ang) dl
-    a3(fsl, vb * (im * dl));
-    V iab = wb * dl;
-    a3(fsl + 3, rtmv(Ii, iab));
-    long ib = w.fb + f * FB + F_IIB;
-    for (int r = 0; r < 3; ++r) {
-      float ir = r == 0 ? iab.x : (r == 1 ? iab.y : iab.z);
-      at(ib + r * 3 + 0) += ir * ang.x;
-      at(ib + r * 3 + 1) += ir * ang.y;
-      at(ib + r * 3 + 2) += ir * ang.z;
-    }
-    return 0.f;
-  }
-  // adjoint of v += w dl: returns dlbar = w . vbar and accumulates wbar += vbar dl
-  MSA_HD float apply_bar(int ci, int di, float dl) const {
+  // adjoint of a free side's v += (lin / m) dl, w += (I^-1 ang) dl; returns its part of dlbar
+  MSA_HD float free_apply_bar(int ci, int di, int f, float sgn, float dl) const {
     long e = w.con + (long)ci * CR;
-    int ok = (int)at(e + C_OK), oi = (int)at(e + C_OI), tk = (int)at(e + C_TK), ti = (int)at(e + C_TI);
     V d = dir(e, di), p = v3(e + C_P);
-    float dlb = 0.f;
-    if (ok == 0) {
-      long rw = w.rw + ((long)ci * 3 + di) * ND, rwb = w.rwb + ((long)ci * 3 + di) * ND;
-      for (int j = 0; j < nb; ++j) {
-        dlb += at(rw + j) * at(w.vRb + j);
-        at(rwb + j) += at(w.vRb + j) * dl;
-      }
-    } else {
-      V lin, ang;
-      free_side(oi, d, p, 1.f, lin, ang);
-      float Ii[9];
-      ld9(w.fIi + oi * 9, Ii);
-      dlb += dot(lin * (1.f / sc.F[oi].mass), v3(w.vFb + oi * 6)) + dot(rmv(Ii, ang), v3(w.vFb + oi * 6 + 3));
-      free_apply_bar(oi, ang, dl, fs_slot(ci, 0, di));
-    }
-    if (tk == 2) {
-      float J = aux_J(ti, d, p, -1.f);
-      float Mx = at(w.xM + ti);
-      dlb += (J / Mx) * at(w.vAb + ti);
-      at(fs_slot(ci, 1, di)) += at(w.vAb + ti) * dl / Mx;
-    } else if (tk == 3) {
-      V lin, ang;
-      free_side(ti, d, p, -1.f, lin, ang);
-      float Ii[9];
-      ld9(w.fIi + ti * 9, Ii);
-      dlb += dot(lin * (1.f / sc.F[ti].mass), v3(w.vFb + ti * 6)) + dot(rmv(Ii, ang), v3(w.vFb + ti * 6 + 3));
-      free_apply_bar(ti, ang, dl, fs_slot(ci, 1, di));
-    }
-    return dlb;
-  }
-  MSA_HD float prev_normal(int it, int ci) const {
-    if (it == 0 || !row_ok(ci, 0)) return 0.f;
-    float y = at(tslot(it - 1) + 2 * AMAX + ci * 3);
-    return y > 0.f ? y : 0.f;
-  }
-  MSA_HD void prev_fric(int it, int ci, float& o1, float& o2) const {
-    o1 = o2 = 0.f;
-    if (it == 0) return;
-    long ts = tslot(it - 1) + 2 * AMAX + ci * 3;
-    disk_proj(at(ts + 1), at(ts + 2), pr.mu * prev_normal(it, ci), o1, o2);
-  }
-
-  MSA_HD void pgs_bar() {
-    for (int i = 0; i < 3 * nc; ++i) at(w.lamb + i) = 0.f;
-    for (int i = 0; i < nlim; ++i) at(w.llamb + i) = 0.f;
-    for (int it = pr.K - 1; it >= 0; --it) {
-      long ts = tslot(it);
-      for (int ci = nc - 1; ci >= 0; --ci) {
-        long e = w.con + (long)ci * CR;
-        long lm = w.lam + ci * 3, lb = w.lamb + ci * 3;
-        if (row_ok(ci, 1) && row_ok(ci, 2)) {
-          float y1 = at(ts + 2 * AMAX + ci * 3 + 1), y2 = at(ts + 2 * AMAX + ci * 3 + 2);
-          float lim = pr.mu * at(lm);
-          float o1, o2, p1, p2;
-          bool proj = disk_proj(y1, y2, lim, o1, o2);
-          prev_fric(it, ci, p1, p2);
-          float d1 = o1 - p1, d2 = o2 - p2;
-          apply(ci, 2, -d2);
-          apply(ci, 1, -d1);
-          float d1b = apply_bar(ci, 1, d1), d2b = apply_bar(ci, 2, d2);
-          float yb1 = at(lb + 1) + d1b, yb2 = at(lb + 2) + d2b;
-          float l1 = -d1b, l2 = -d2b;
-          float limb = 0.f;
-          if (proj) {
-            if (lim > 0.f) {
-              float nn = sqrtf(y1 * y1 + y2 * y2);
-              float u1 = y1 / nn, u2 = y2 / nn;
-              float g = u1 * yb1 + u2 * yb2;
-              limb = g;
-              float sc2 = lim / nn;
-              yb1 = sc2 * (yb1 - u1 * g);
-              yb2 = sc2 * (yb2 - u2 * g);
-            } else {
-              yb1 = 0.f;
-              yb2 = 0.f;
-            }
-          }
-          at(lb) += pr.mu * limb;
-          l1 += yb1;
-          l2 += yb2;
-          float W1 = at(e + C_W + 1), W2 = at(e + C_W + 2);
-          float r1 = rowvel(ci, 1), r2 = rowvel(ci, 2);
-          float rb1 = -yb1 / W1, rb2 = -yb2 / W2;
-          long cb = w.conb + (long)ci * CB;
-          at(cb + B_W + 1) += yb1 * r1 / (W1 * W1);
-          at(cb + B_W + 2) += yb2 * r2 / (W2 * W2);
-          rowvel_bar(ci, 1, rb1);
-          rowvel_bar(ci, 2, rb2);
-          at(lb + 1) = l1;
-          at(lb + 2) = l2;
-          at(lm + 1) = p1;
-          at(lm + 2) = p2;
-        }
-        if (row_ok(ci, 0)) {
-          float y = at(ts + 2 * AMAX + ci * 3);
-          float nl = y > 0.f ? y : 0.f;
-          float pl = prev_normal(it, ci);
-          float dl = nl - pl;
-          apply(ci, 0, -dl);
-          float dlb = apply_bar(ci, 0, dl);
-          float nlb = at(lb) + dlb;
-          float lold = -dlb;
-          float yb = y > 0.f ? nlb : 0.f;
-          lold += yb;
-          float W = at(e + C_W);
-          float r = rowvel(ci, 0) + at(e + C_BIAS);
-          float rb = -yb / W;
-          long cb = w.conb + (long)ci * CB;
-          at(cb + B_W) += yb * r / (W * W);
-          at(cb + B_BIAS) += rb;
-          rowvel_bar(ci, 0, rb);
-          at(lb) = lold;
-          at(lm) = pl;
-        }
-      }
-      for (int li = nlim - 1; li >= 0; --li) {
-        long e = w.lim + li * 4;
-        int x = (int)at(e);
-        float sgn = at(e + 1), W = at(e + 3);
-        float y = at(ts + li);
-        float nl = y > 0.f ? y : 0.f;
-        float pl = 0.f;
-        if (it > 0) {
-          float yp = at(tslot(it - 1) + li);
-          pl = yp > 0.f ? yp : 0.f;
-        }
-        float dl = nl - pl;
-        at(w.vA + x) -= (sgn * W) * dl;
-        float dlb = sgn * W * at(w.vAb + x);
-        float nlb = at(w.llamb + li) + dlb;
-        float lold = -dlb;
-        float yb = y > 0.f ? nlb : 0.f;
-        lold += yb;
-        float rb = -yb / W;
-        at(w.vAb + x) += rb * sgn;
-        at(w.limb + li) += rb;
-        at(w.llamb + li) = lold;
-        at(w.llam + li) = pl;
-      }
-    }
-  }
-
-  // --------------------------------------------------------------- rows^T
-  // adjoint of a free side (lin = sgn d, ang = sgn (p - x) x d) given the
-  // accumulated (linbar, angbar) of the Gauss-Seidel sweeps and Wbar
-  MSA_HD void free_side_bar(int f, V d, V p, float sgn, long fsl, float Wb, V& db, V& pb) const {
     V lin, ang;
     free_side(f, d, p, sgn, lin, ang);
     float Ii[9];
     ld9(w.fIi + f * 9, Ii);
     float im = 1.f / sc.F[f].mass;
-    V linb = v3(fsl) + lin * (2.f * Wb * im);
-    V angb = v3(fsl + 3) + (rmv(Ii, ang) + rtmv(Ii, ang)) * Wb;
+    V vb = v3(w.vFb + f * 6), wb = v3(w.vFb + f * 6 + 3);
+    float dlb = dot(lin * im, vb) + dot(rmv(Ii, ang), wb);
+    V iab = wb * dl;
+    long ib = w.fb + f * FB + F_IIB;
+    float iv[3] = {iab.x, iab.y, iab.z};
+    for (int r = 0; r < 3; ++r) {
+      at(ib + r * 3 + 0) += iv[r] * ang.x;
+      at(ib + r * 3 + 1) += iv[r] * ang.y;
+      at(ib + r * 3 + 2) += iv[r] * ang.z;
+    }
+    free_row_bar(ci, di, f, sgn, vb * (im * dl), rtmv(Ii, iab));
+    return dlb;
+  }
+  // adjoint of v += w dl: returns dlbar = w . vbar and accumulates wbar += vbar dl
+  MSA_HD float apply_bar(int ci, int di, float dl, int sides = SAB) const {
+    long e = w.con + (long)ci * CR;
+    int ok = (int)at(e + C_OK), oi = (int)at(e + C_OI), tk = (int)at(e + C_TK), ti = (int)at(e + C_TI);
+    V d = dir(e, di), p = v3(e + C_P);
+    float dlb = 0.f;
+    if (sides & SA) {
+      if (ok == 0) {
+        long rw = w.rw + ((long)ci * 3 + di) * ND, rwb = w.rwb + ((long)ci * 3 + di) * ND;
+        for (int j = 0; j < nb; ++j) {
+          dlb += at(rw + j) * at(w.vRb + j);
+          at(rwb + j) += at(w.vRb + j) * dl;
+        }
+      } else {
+        dlb += free_apply_bar(ci, di, oi, 1.f, dl);
+      }
+    }
+    if (sides & SB) {
+      if (tk == 2) {
+        float J = aux_J(ti, d, p, -1.f);
+        float Mx = at(w.xM + ti);
+        dlb += (J / Mx) * at(w.vAb + ti);
+        at(w.conb + (long)ci * CB + B_AJ + di) += at(w.vAb + ti) * dl / Mx;
+      } else if (tk == 3) {
+        dlb += free_apply_bar(ci, di, ti, -1.f, dl);
+      }
+    }
+    return dlb;
+  }
+  MSA_HD float prev_normal(int it, int ci) const {
+    if (it == 0 || !row_ok(ci, 0)) return 0.f;
+    float y = tape_at(it - 1, nlim + ci, 0);
+    return y > 0.f ? y : 0.f;
+  }
+  MSA_HD void prev_fric(int it, int ci, float& o1, float& o2) const {
+    o1 = o2 = 0.f;
+    if (it == 0) return;
+    disk_proj(tape_at(it - 1, nlim + ci, 1), tape_at(it - 1, nlim + ci, 2), pr.mu * prev_normal(it, ci), o1, o2);
+  }
+  // reverse of limit_update (sweep it): the velocities are set back to
+  // their values before the update, the adjoints carried through it
+  MSA_HD void limit_bar(int it, int li) const {
+    long e = w.lim + li * 4;
+    int x = (int)at(e);
+    float sgn = at(e + 1), W = at(e + 3);
+    float y = tape_at(it, li, 0);
+    float nl = y > 0.f ? y : 0.f;
+    float pl = 0.f;
+    if (it > 0) {
+      float yp = tape_at(it - 1, li, 0);
+      pl = yp > 0.f ? yp : 0.f;
+    }
+    float dl = nl - pl;
+    at(w.vA + x) -= (sgn * W) * dl;
+    float dlb = sgn * W * at(w.vAb + x);
+    float nlb = at(w.llamb + li) + dlb;
+    float lold = -dlb;
+    float yb = y > 0.f ? nlb : 0.f;
+    lold += yb;
+    float rb = -yb / W;
+    at(w.vAb + x) += rb * sgn;
+    at(w.limb + li) += rb;
+    at(w.llamb + li) = lold;
+    at(w.llam + li) = pl;
+  }
+  // reverse of contact_update (sweep it): friction pair, then normal
+  MSA_HD void contact_bar(int it, int ci) const {
+    long e = w.con + (long)ci * CR, cb = w.conb + (long)ci * CB;
+    long lm = w.lam + ci * 3, lb = w.lamb + ci * 3;
+    const int row = nlim + ci;
+    if (row_ok(ci, 1) && row_ok(ci, 2)) {
+      float y1 = tape_at(it, row, 1), y2 = tape_at(it, row, 2);
+      float lim = pr.mu * at(lm);
+      float o1, o2, p1, p2;
+      bool proj = disk_proj(y1, y2, lim, o1, o2);
+      prev_fric(it, ci, p1, p2);
+      float d1 = o1 - p1, d2 = o2 - p2;
+      apply(ci, 2, -d2);
+      apply(ci, 1, -d1);
+      float d1b = apply_bar(ci, 1, d1), d2b = apply_bar(ci, 2, d2);
+      float yb1, yb2, limb;
+      fric_bar(y1, y2, lim, proj, at(lb + 1) + d1b, at(lb + 2) + d2b, yb1, yb2, limb);
+      at(lb) += pr.mu * limb;
+      float l1 = -d1b + yb1, l2 = -d2b + yb2;
+      float W1 = at(e + C_W + 1), W2 = at(e + C_W + 2);
+      float r1 = rowvel(ci, 1), r2 = rowvel(ci, 2);
+      float rb1 = -yb1 / W1, rb2 = -yb2 / W2;
+      at(cb + B_W + 1) += yb1 * r1 / (W1 * W1);
+      at(cb + B_W + 2) += yb2 * r2 / (W2 * W2);
+      rowvel_bar(ci, 1, rb1);
+      rowvel_bar(ci, 2, rb2);
+      at(lb + 1) = l1;
+      at(lb + 2) = l2;
+      at(lm + 1) = p1;
+      at(lm + 2) = p2;
+    }
+    if (row_ok(ci, 0)) {
+      float y = tape_at(it, row, 0);
+      float nl = y > 0.f ? y : 0.f;
+      float pl = prev_normal(it, ci);
+      float dl = nl - pl;
+      apply(ci, 0, -dl);
+      float dlb = apply_bar(ci, 0, dl);
+      float lold, yb;
+      normal_bar(y, at(lb) + dlb, dlb, lold, yb);
+      float W = at(e + C_W);
+      float r = rowvel(ci, 0) + at(e + C_BIAS);
+      float rb = -yb / W;
+      at(cb + B_W) += yb * r / (W * W);
+      at(cb + B_BIAS) += rb;
+      rowvel_bar(ci, 0, rb);
+      at(lb) = lold;
+      at(lm) = pl;
+    }
+  }
+  // scalar parts of the reverse updates, shared with the wavefront kernel.
+  // normal: nl = max(0, y), dl = nl - lold; given nlbar (incl. dlbar) and
+  // dlbar, returns the adjoint of lold and ybar
+  static MSA_HD void normal_bar(float y, float nlb, float dlb, float& lold, float& yb) {
+    yb = y > 0.f ? nlb : 0.f;
+    lold = -dlb + yb;
+  }
+  // friction pair: from the adjoints of the projected values (incl. dlbar)
+  // to the adjoints of the unprojected values and of the disk radius
+  static MSA_HD void fric_bar(float y1, float y2, float lim, bool proj, float yb1p, float yb2p, float& yb1,
+                              float& yb2, float& limb) {
+    yb1 = yb1p;
+    yb2 = yb2p;
+    limb = 0.f;
+    if (proj) {
+      if (lim > 0.f) {
+        float nn = sqrtf(y1 * y1 + y2 * y2);
+        float u1 = y1 / nn, u2 = y2 / nn;
+        float g = u1 * yb1 + u2 * yb2;
+        limb = g;
+        float sc2 = lim / nn;
+        yb1 = sc2 * (yb1 - u1 * g);
+        yb2 = sc2 * (yb2 - u2 * g);
+      } else {
+        yb1 = 0.f;
+        yb2 = 0.f;
+      }
+    }
+  }
+  MSA_HD void pgs_bar() {
+    for (int i = 0; i < 3 * nc; ++i) at(w.lamb + i) = 0.f;
+    for (int i = 0; i < nlim; ++i) at(w.llamb + i) = 0.f;
+    for (int it = pr.K - 1; it >= 0; --it) {
+      for (int ci = nc - 1; ci >= 0; --ci) contact_bar(it, ci);
+      for (int li = nlim - 1; li >= 0; --li) limit_bar(it, li);
+    }
+  }
+
+  // --------------------------------------------------------------- rows^T
+  // adjoint of a free side's share of W, lin . lin / m + ang . I^-1 ang,
+  // with lin = sgn d, ang = sgn (p - x) x d
+  MSA_HD void free_side_bar(int f, V d, V p, float sgn, float Wb, V& db, V& pb) const {
+    V lin, ang;
+    free_side(f, d, p, sgn, lin, ang);
+    float Ii[9];
+    ld9(w.fIi + f * 9, Ii);
+    float im = 1.f / sc.F[f].mass;
+    V linb = lin * (2.f * Wb * im);
+    V angb = (rmv(Ii, ang) + rtmv(Ii, ang)) * Wb;
     long ib = w.fb + f * FB + F_IIB;
     float av[3] = {ang.x, ang.y, ang.z};
     for (int r = 0; r < 3; ++r)
@@ -1450,11 +1491,11 @@ struct Eng {
             }
           }
         } else {
-          free_side_bar(oi, d, p, 1.f, fs_slot(ci, 0, di), Wb, db, pb);
+          free_side_bar(oi, d, p, 1.f, Wb, db, pb);
         }
         if (tk == 2) {
           float J = aux_J(ti, d, p, -1.f);
-          float Jb = at(fs_slot(ci, 1, di)) + Wb * 2.f * J / at(w.xM + ti);
+          float Jb = at(cb + B_AJ + di) + Wb * 2.f * J / at(w.xM + ti);
           V a = v3(w.xa + ti * 3);
           if (sc.A[ti].type == 0) {
             V ev = p - v3(w.xo + ti * 3);
@@ -1464,7 +1505,7 @@ struct Eng {
             db = db - a * Jb;
           }
         } else if (tk == 3) {
-          free_side_bar(ti, d, p, -1.f, fs_slot(ci, 1, di), Wb, db, pb);
+          free_side_bar(ti, d, p, -1.f, Wb, db, pb);
         }
         a3(cb + B_D + di * 3, db);
       }
@@ -1864,6 +1905,8 @@ struct Eng {
     nsph = M.nsph;
     status = 0;
     nc = nrob = nlim = 0;
+    tb = Buf{b.p + (long)w.tape * b.st, b.st};
+    tsw = 3 * (2 * AMAX + w.ccap);
     long s0 = srec(0);
     zero(s0, w.ss);
     for (int j = 0; j < ND; ++j) {

@@ -140,12 +140,28 @@ ms_status enqueue_step(ms_batch* b, const void* x_in, const float* u, void* x_ou
 
 msa::WS bwd_ws(const ms_batch_desc* d, const Counts& c) {
   const int ntmax = c.pmax + c.smax + c.amax + std::max(c.fmax, 1);
-  return bwd_layout(std::max(c.fmax, 1), ntmax, d->contact_cap, std::max(d->robot_contact_cap, 1), d->pgs_iters,
+  return msa::ws_layout(std::max(c.fmax, 1), ntmax, d->contact_cap, std::max(d->robot_contact_cap, 1), d->pgs_iters,
                     d->n_substeps);
 }
 
+// LDS block of the wavefront adjoint kernel
+msa::WS bwd_ws_wave(const ms_batch_desc* d, const Counts& c) {
+  const int ntmax = c.pmax + c.smax + c.amax + std::max(c.fmax, 1);
+  return msa::ws_layout(std::max(c.fmax, 1), ntmax, d->contact_cap, std::max(d->robot_contact_cap, 1), d->pgs_iters,
+                        d->n_substeps, true);
+}
+
+// record of a control step written by the forward kernel for the wavefront adjoint kernel
+RecLayout bwd_rec(const ms_batch_desc* d, const Counts& c) {
+  return rec_layout(std::max(c.fmax, 1), d->contact_cap, d->pgs_iters, d->n_substeps);
+}
+
+// the tape buffer holds either the record (wavefront kernel) or the
+// interleaved workspace of the lane kernel
 size_t bwd_bytes(const ms_batch_desc* d, const Counts& c) {
-  return (size_t)bwd_ws(d, c).total * (size_t)bwd_stride(c.S) * sizeof(float);
+  size_t lane = (size_t)bwd_ws(d, c).total * (size_t)bwd_stride(c.S) * sizeof(float);
+  size_t rec = (size_t)bwd_rec(d, c).total * (size_t)c.S * sizeof(float);
+  return std::max(lane, rec);
 }
 
 }  // namespace
@@ -219,8 +235,10 @@ ms_status ms_create_batch(const ms_batch_desc* d, const ms_scene_desc* sc, void*
     delete b;
     return fail(MS_E_HIP, "hipStreamCreateWithFlags failed");
   }
-  // allow the kernel the whole LDS of a workgroup
+  // allow the kernels the whole LDS of a workgroup
   (void)hipFuncSetAttribute(step_kernel_ptr(), hipFuncAttributeMaxDynamicSharedMemorySize, (int)b->max_lds);
+  (void)hipFuncSetAttribute(step_rec_kernel_ptr(), hipFuncAttributeMaxDynamicSharedMemorySize, (int)b->max_lds);
+  (void)hipFuncSetAttribute(step_bwd_wave_ptr(), hipFuncAttributeMaxDynamicSharedMemorySize, (int)b->max_lds);
   // status starts at zero
   hipError_t e = hipMemsetAsync(b->scratch + b->sl.status, 0, sizeof(uint32_t) * c.S, stream);
   if (e == hipSuccess) e = hipStreamSynchronize(stream);
@@ -243,7 +261,8 @@ ms_status ms_destroy_batch(ms_batch* b) {
 
 ms_status ms_set_schedule(ms_batch* b, const ms_schedule* s) {
   if (!b || !s) return fail(MS_E_INVALID, "null argument");
-  const int known = MS_SCHED_PERSISTENT | MS_SCHED_GRAPH | MS_SCHED_PER_SUBSTEP | MS_SCHED_STAGE_STATIC | MS_SCHED_CULL;
+  const int known = MS_SCHED_PERSISTENT | MS_SCHED_GRAPH | MS_SCHED_PER_SUBSTEP | MS_SCHED_STAGE_STATIC | MS_SCHED_CULL |
+                    MS_SCHED_BWD_REFERENCE;
   if (s->flags & ~known) return fail(MS_E_INVALID, "unknown schedule flags 0x%x", s->flags);
   if (s->grid < 0) return fail(MS_E_INVALID, "grid must be >= 0");
   KArgs a = make_args(b, nullptr, nullptr, nullptr);
@@ -298,6 +317,26 @@ ms_status ms_step(ms_batch* b, const void* x_in, const float* u, void* x_out, vo
   return MS_OK;
 }
 
+// The forward kernel in record mode: one fused launch per control step (the
+// batch's persistent / staging / culling choices), no state output.
+ms_status enqueue_record(ms_batch* b, const void* x_in, const float* u, float* rec, hipStream_t st) {
+  KArgs a = make_args(b, x_in, u, nullptr);
+  a.debug = nullptr;
+  a.phase_cycles = nullptr;
+  a.rec = rec;
+  a.RL = bwd_rec(&b->desc, b->cnt);
+  size_t lds = lds_bytes_of(a);
+  if (lds > b->max_lds) return fail(MS_E_UNSUPPORTED, "scene working set needs %zu B of LDS", lds);
+  int grid = b->cnt.S;
+  if (a.persistent) {
+    launch_reset_queue(a.queue, st);
+    grid = persistent_grid(b, lds);
+  }
+  launch_step(a, grid, lds, st);
+  HIP_TRY(hipGetLastError());
+  return MS_OK;
+}
+
 ms_status ms_step_backward(ms_batch* b, const void* x_in, const float* u, const void* gx_out, void* gx_in,
                            float* gu, void* hip_stream) {
   if (!b) return fail(MS_E_INVALID, "null batch");
@@ -326,9 +365,21 @@ ms_status ms_step_backward(ms_batch* b, const void* x_in, const float* u, const 
   a.stride = bwd_stride(c.S);
   a.pr = msa::Prm{d->h, d->mu, d->baumgarte, d->margin, {d->gravity[0], d->gravity[1], d->gravity[2]},
                   d->pgs_iters, d->control_mode, d->contact_cap, std::max(d->robot_contact_cap, 1), d->n_substeps};
-  a.w = bwd_ws(d, c);
   hipStream_t st = static_cast<hipStream_t>(hip_stream);
-  launch_step_bwd(a, st);
+  const msa::WS ww = bwd_ws_wave(d, c);
+  const size_t lds = (size_t)ww.total * sizeof(float);
+  if ((b->sched.flags & MS_SCHED_BWD_REFERENCE) || lds > b->max_lds) {
+    a.w = bwd_ws(d, c);
+    launch_step_bwd(a, st);
+  } else {
+    float* rec = reinterpret_cast<float*>(b->tape);
+    ms_status rs = enqueue_record(b, x_in, u, rec, st);
+    if (rs != MS_OK) return rs;
+    a.rec = rec;
+    a.RL = bwd_rec(d, c);
+    a.w = ww;
+    launch_step_bwd_wave(a, lds, st);
+  }
   HIP_TRY(hipGetLastError());
   return MS_OK;
 }

@@ -1,5 +1,17 @@
 // ms_backward.h -- launch interface of the adjoint (vector-Jacobian product)
 // of one control step; the arithmetic is in ms_adjoint.h.
+//
+// Two kernels compute it:
+//   k_step_bwd_wave  one wavefront per scene.  It reads the record of the
+//                    control step that the forward kernel writes in record
+//                    mode (substep states, contact lists, pre-projection
+//                    values of the Gauss-Seidel updates), keeps the scene's
+//                    adjoint workspace in LDS and reverses the Gauss-Seidel
+//                    sweeps level by level (rows of one level touch disjoint
+//                    bodies, so they are reversed in parallel);
+//   k_step_bwd       one lane per scene, recomputing everything itself with
+//                    the workspace interleaved in global memory (the
+//                    reference the wavefront kernel is tested against).
 #pragma once
 #include "ms_adjoint.h"
 
@@ -19,16 +31,20 @@ struct BwdArgs {
   float* gxi;             // adjoint of the state in (may alias gxo)
   float* gu;              // adjoint of the controls [S][16]
   uint32_t* status;       // [S], bits OR-ed in
-  float* ws;              // workspace, w.total floats per slot, interleaved with stride `stride`
+  float* ws;              // lane kernel: workspace, w.total floats per slot, interleaved with stride `stride`
+  const float* rec;       // wavefront kernel: forward record, RL.total floats per scene
+  RecLayout RL;
   int S, NF, stride;
   msa::Prm pr;
-  msa::WS w;
+  msa::WS w;              // lane kernel: global layout; wavefront kernel: LDS layout
 };
 
 inline int bwd_stride(int S) { return (S + 63) & ~63; }
-inline msa::WS bwd_layout(int fmax, int ntmax, int ccap, int rcap, int K, int nsub) {
-  return msa::ws_layout(fmax, ntmax, ccap, rcap, K, nsub);
-}
 void launch_step_bwd(const BwdArgs& a, hipStream_t st);
+void launch_step_bwd_wave(const BwdArgs& a, size_t lds_bytes, hipStream_t st);
+const void* step_bwd_wave_ptr();
+
+// status bit set when the record and the recomputed joint-limit rows disagree
+constexpr uint32_t MS_ST_RECORD = 16u;
 
 }  // namespace msk

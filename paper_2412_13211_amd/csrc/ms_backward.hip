@@ -1,10 +1,11 @@
-// ms_backward.hip -- the adjoint of one control step on gfx950: one lane per
-// scene (scenes taken in the cost-sorted order so that a wavefront holds
-// scenes of similar size), workspace interleaved across the lanes.
+// ms_backward.hip -- the adjoint of one control step on gfx950.
 #include "ms_backward.h"
 
 namespace msk {
 
+// ============================================================ lane per scene
+// (scenes taken in the cost-sorted order so that a wavefront holds scenes of
+// similar size; workspace interleaved across the lanes)
 __global__ __launch_bounds__(64) void k_step_bwd(BwdArgs a) {
   const int slot = blockIdx.x * 64 + threadIdx.x;
   if (slot >= a.S) return;
@@ -28,5 +29,434 @@ void launch_step_bwd(const BwdArgs& a, hipStream_t st) {
   const int grid = (a.S + 63) / 64;
   hipLaunchKernelGGL(k_step_bwd, dim3(grid), dim3(64), 0, st, a);
 }
+
+// ============================================================ wavefront per scene
+namespace {
+
+__device__ __forceinline__ int lane_id() { return threadIdx.x; }
+__device__ __forceinline__ void wsync() { __syncthreads(); }
+__device__ __forceinline__ float bcast0(float v) { return __shfl(v, 0, 64); }
+// sum over lanes 0..15 (other lanes pass 0), returned in every lane
+__device__ __forceinline__ float sum16_b(float v) {
+  v += __shfl_xor(v, 8, 64);
+  v += __shfl_xor(v, 4, 64);
+  v += __shfl_xor(v, 2, 64);
+  v += __shfl_xor(v, 1, 64);
+  return __shfl(v, 0, 64);
+}
+
+// level-schedule views inside the LDS block
+struct Lv {
+  int *lvl, *order, *loff, *rob, *last, *cnt;
+};
+__device__ __forceinline__ Lv lv_view(float* L, const msa::WS& w) {
+  Lv v;
+  int* p = reinterpret_cast<int*>(L + w.lv);
+  const int R = msa::lv_rows(w.ccap);
+  v.lvl = p; p += R;
+  v.order = p; p += R;
+  v.loff = p; p += R + 2;
+  v.rob = p; p += R + 2;
+  v.last = p; p += 64;
+  v.cnt = p;  // [0] nc, [1] nrob, [2] nlim, [3] maxl, [4] status
+  return v;
+}
+
+// dynamic node of a row (robot 0, door/drawer 1 + x, free body 1 + AMAX + f; -1 none)
+__device__ __forceinline__ void row_nodes(const msa::Eng& E, int r, int& na, int& nbn) {
+  if (r < E.nlim) {
+    na = 1 + (int)E.at(E.w.lim + r * 4);
+    nbn = -1;
+    return;
+  }
+  long e = E.w.con + (long)(r - E.nlim) * msa::CR;
+  int ok = (int)E.at(e + msa::C_OK), oi = (int)E.at(e + msa::C_OI);
+  int tk = (int)E.at(e + msa::C_TK), ti = (int)E.at(e + msa::C_TI);
+  na = ok == 0 ? 0 : 1 + AMAX + oi;
+  nbn = tk == 2 ? 1 + ti : (tk == 3 ? 1 + AMAX + ti : -1);
+}
+
+// Reverse of a robot contact's row updates in sweep it.  Lanes 0..15 carry the
+// robot's joints; lane 0 carries the target side and the scalars.
+__device__ void robot_contact_bar(msa::Eng& E, int it, int ci, float* L) {
+  using namespace msa;
+  const int lane = lane_id(), j = lane & 15;
+  const bool own = lane < 16 && j < E.nb;
+  const WS& w = E.w;
+  const long e = w.con + (long)ci * CR, cb = w.conb + (long)ci * CB;
+  const long lm = w.lam + ci * 3, lb = w.lamb + ci * 3;
+  const int row = E.nlim + ci;
+  float* vR = L + w.vR;
+  float* vRb = L + w.vRb;
+  const float* rJ = L + w.rJ + (long)ci * 3 * ND;
+  const float* rW = L + w.rw + (long)ci * 3 * ND;
+  float* rJb = L + w.rJb + (long)ci * 3 * ND;
+  float* rWb = L + w.rwb + (long)ci * 3 * ND;
+  const float mu = E.pr.mu;
+  if (E.row_ok(ci, 1) && E.row_ok(ci, 2)) {
+    const float y1 = E.tape_at(it, row, 1), y2 = E.tape_at(it, row, 2);
+    const float lim = mu * L[lm];
+    float o1, o2, p1, p2;
+    const bool proj = disk_proj(y1, y2, lim, o1, o2);
+    E.prev_fric(it, ci, p1, p2);
+    const float d1 = o1 - p1, d2 = o2 - p2;
+    if (own) {
+      float v = vR[j];
+      v += rW[2 * ND + j] * (-d2);
+      v += rW[ND + j] * (-d1);
+      vR[j] = v;
+    }
+    if (lane == 0) {
+      E.apply(ci, 2, -d2, Eng::SB);
+      E.apply(ci, 1, -d1, Eng::SB);
+    }
+    wsync();
+    float a1 = 0.f, a2 = 0.f;
+    if (own) {
+      float vb = vRb[j];
+      a1 = rW[ND + j] * vb;
+      a2 = rW[2 * ND + j] * vb;
+      rWb[ND + j] += vb * d1;
+      rWb[2 * ND + j] += vb * d2;
+    }
+    float b1 = 0.f, b2 = 0.f;
+    if (lane == 0) {
+      b1 = E.apply_bar(ci, 1, d1, Eng::SB);
+      b2 = E.apply_bar(ci, 2, d2, Eng::SB);
+    }
+    const float d1b = sum16_b(a1) + bcast0(b1), d2b = sum16_b(a2) + bcast0(b2);
+    float yb1, yb2, limb;
+    Eng::fric_bar(y1, y2, lim, proj, L[lb + 1] + d1b, L[lb + 2] + d2b, yb1, yb2, limb);
+    const float l1 = -d1b + yb1, l2 = -d2b + yb2;
+    const float W1 = L[e + C_W + 1], W2 = L[e + C_W + 2];
+    float c1 = 0.f, c2 = 0.f;
+    if (own) {
+      c1 = rJ[ND + j] * vR[j];
+      c2 = rJ[2 * ND + j] * vR[j];
+    }
+    float s1 = 0.f, s2 = 0.f;
+    if (lane == 0) {
+      s1 = E.rowvel(ci, 1, Eng::SB);
+      s2 = E.rowvel(ci, 2, Eng::SB);
+    }
+    const float r1 = sum16_b(c1) + bcast0(s1), r2 = sum16_b(c2) + bcast0(s2);
+    const float rb1 = -yb1 / W1, rb2 = -yb2 / W2;
+    wsync();
+    if (lane == 0) {
+      L[lb] += mu * limb;
+      L[cb + B_W + 1] += yb1 * r1 / (W1 * W1);
+      L[cb + B_W + 2] += yb2 * r2 / (W2 * W2);
+      E.rowvel_bar(ci, 1, rb1, Eng::SB);
+      E.rowvel_bar(ci, 2, rb2, Eng::SB);
+      L[lb + 1] = l1;
+      L[lb + 2] = l2;
+      L[lm + 1] = p1;
+      L[lm + 2] = p2;
+    }
+    if (own) {
+      float v = vR[j];
+      rJb[ND + j] += rb1 * v;
+      rJb[2 * ND + j] += rb2 * v;
+      float vb = vRb[j];
+      vb += rb1 * rJ[ND + j];
+      vb += rb2 * rJ[2 * ND + j];
+      vRb[j] = vb;
+    }
+    wsync();
+  }
+  if (E.row_ok(ci, 0)) {
+    const float y = E.tape_at(it, row, 0);
+    const float nl = y > 0.f ? y : 0.f;
+    const float pl = E.prev_normal(it, ci);
+    const float dl = nl - pl;
+    if (own) vR[j] += rW[j] * (-dl);
+    if (lane == 0) E.apply(ci, 0, -dl, Eng::SB);
+    wsync();
+    float a0 = 0.f;
+    if (own) {
+      float vb = vRb[j];
+      a0 = rW[j] * vb;
+      rWb[j] += vb * dl;
+    }
+    float b0 = 0.f;
+    if (lane == 0) b0 = E.apply_bar(ci, 0, dl, Eng::SB);
+    const float dlb = sum16_b(a0) + bcast0(b0);
+    float lold, yb;
+    Eng::normal_bar(y, L[lb] + dlb, dlb, lold, yb);
+    const float W = L[e + C_W];
+    float c0 = own ? rJ[j] * vR[j] : 0.f;
+    float s0 = 0.f;
+    if (lane == 0) s0 = E.rowvel(ci, 0, Eng::SB);
+    const float r = sum16_b(c0) + bcast0(s0) + L[e + C_BIAS];
+    const float rb = -yb / W;
+    wsync();
+    if (lane == 0) {
+      L[cb + B_W] += yb * r / (W * W);
+      L[cb + B_BIAS] += rb;
+      E.rowvel_bar(ci, 0, rb, Eng::SB);
+      L[lb] = lold;
+      L[lm] = pl;
+    }
+    if (own) {
+      rJb[j] += rb * vR[j];
+      vRb[j] += rb * rJ[j];
+    }
+    wsync();
+  }
+}
+
+__device__ __forceinline__ void zero_lds(float* L, long off, int n) {
+  for (int i = lane_id(); i < n; i += 64) L[off + i] = 0.f;
+}
+
+__device__ void bwd_scene(const BwdArgs& a, int s, float* L) {
+  using namespace msa;
+  const int lane = lane_id();
+  const DScene& D = a.scenes[s];
+  Eng E;
+  E.sc = SceneRef{a.models + D.model, a.free + D.f0, a.statics + 6 * (size_t)D.s0, a.planes + D.p0, a.aux + D.a0,
+                  D.hold, D.nf, D.ns, D.np, D.na};
+  E.pr = a.pr;
+  E.w = a.w;
+  E.b = Buf{L, 1};
+  E.nb = E.sc.M->nb;
+  E.nsph = E.sc.M->nsph;
+  E.status = 0;
+  E.nc = E.nrob = E.nlim = 0;
+  E.cur_s = a.w.st;
+  const WS& w = a.w;
+  const RecLayout& RL = a.RL;
+  const float* rec = a.rec + (size_t)s * RL.total;
+  const int nf = D.nf, na = D.na, fm = w.fmax;
+  const size_t S = (size_t)a.S;
+  const size_t oq = 16 * (size_t)s, oqd = 16 * S + 16 * (size_t)s;
+  const size_t ofr = 32 * S + 16 * (size_t)D.f0, oax = 32 * S + 16 * (size_t)a.NF + 4 * (size_t)D.a0;
+  const float* u = a.u + 16 * (size_t)s;
+  Lv LV = lv_view(L, w);
+
+  // adjoint of the end state
+  zero_lds(L, w.gA, w.ss);
+  zero_lds(L, w.ub, ND);
+  wsync();
+  if (lane < ND) {
+    L[w.gA + lane] = a.gxo[oq + lane];
+    L[w.gA + ND + lane] = a.gxo[oqd + lane];
+  }
+  for (int i = lane; i < nf * 16; i += 64) L[w.gA + 32 + i] = a.gxo[ofr + i];
+  if (lane < na * 4) L[w.gA + 32 + 16 * fm + lane] = a.gxo[oax + lane];
+  wsync();
+
+  for (int si = a.pr.nsub - 1; si >= 0; --si) {
+    const float* st0 = rec + (size_t)si * RL.ss;
+    const float* st1 = rec + (size_t)(si + 1) * RL.ss;
+    const float* cr = rec + RL.con + (size_t)si * RL.cstride;
+    // state at the substep start; velocities at its end (after Gauss-Seidel)
+    for (int i = lane; i < w.ss; i += 64) L[w.st + i] = st0[i];
+    if (lane < ND) L[w.vR + lane] = st1[ND + lane];
+    if (lane < na) L[w.vA + lane] = st1[32 + 16 * fm + 4 * lane + 1];
+    for (int f = lane; f < nf; f += 64) {
+      const float* x = st1 + 32 + 16 * f;
+      L[w.vF + f * 6 + 0] = x[8]; L[w.vF + f * 6 + 1] = x[9]; L[w.vF + f * 6 + 2] = x[10];
+      L[w.vF + f * 6 + 3] = x[12]; L[w.vF + f * 6 + 4] = x[13]; L[w.vF + f * 6 + 5] = x[14];
+    }
+    // the substep's contacts as the forward kernel emitted them
+    const int NCf = __float_as_int(cr[0]), NL = __float_as_int(cr[1]), NR = __float_as_int(cr[2]);
+    const int nc = NCf - NL;
+    for (int ci = lane; ci < nc; ci += 64) {
+      const float* c = cr + 4 + (size_t)(NL + ci) * CSTR;
+      const int info = __float_as_int(c[0]);
+      const int key = __float_as_int(c[16]);
+      const int aside = info & 0xffff;
+      const int akind = (aside >> 8) & 0xff, aidx = aside & 0xff;
+      const int osub = key & 0xff, tk = (key >> 8) & 3, ti = key >> 10;
+      int ok, oi, ov = 0;
+      float r;
+      if (akind == 1) {  // robot sphere
+        ok = 0;
+        oi = osub;
+        r = E.sc.M->sph[osub].w;
+      } else {  // free body
+        oi = aidx;
+        if (E.sc.F[aidx].type == 0) {
+          ok = 1;
+          ov = osub;
+          r = 0.f;
+        } else {
+          ok = 2;
+          r = E.sc.F[aidx].half[0];
+        }
+      }
+      const long eo = w.con + (long)ci * CR;
+      V n{c[1], c[2], c[3]}, p{c[4], c[5], c[6]};
+      L[eo + C_OK] = (float)ok;
+      L[eo + C_OI] = (float)oi;
+      L[eo + C_OV] = (float)ov;
+      L[eo + C_TK] = (float)tk;
+      L[eo + C_TI] = (float)ti;
+      L[eo + C_R] = r;
+      bs3(E.b, eo + C_C, p + n * r);
+      L[eo + C_PHI] = c[14];
+      bs3(E.b, eo + C_N, n);
+      bs3(E.b, eo + C_P, p);
+    }
+    wsync();
+    // recompute on one lane: drive, kinematics, frames, dynamics (without the
+    // unconstrained velocities), rows; then the level schedule
+    if (lane == 0) {
+      E.nc = nc;
+      E.nrob = NR;
+      E.drive(w.st, u);
+      E.kinematics(w.st);
+      E.aux_frames(w.st);
+      E.free_frames(w.st);
+      E.dynamics(w.st, false);
+      E.rows();
+      if (E.nlim != NL) E.status |= MS_ST_RECORD;
+      const int R = E.nlim + E.nc;
+      for (int k = 0; k < 64; ++k) LV.last[k] = 0;
+      int maxl = 0;
+      for (int r = 0; r < R; ++r) {
+        int n1, n2;
+        row_nodes(E, r, n1, n2);
+        int lv = LV.last[n1];
+        if (n2 >= 0 && LV.last[n2] > lv) lv = LV.last[n2];
+        ++lv;
+        LV.last[n1] = lv;
+        if (n2 >= 0) LV.last[n2] = lv;
+        LV.lvl[r] = lv;
+        if (lv > maxl) maxl = lv;
+      }
+      for (int l = 0; l <= maxl + 1; ++l) {
+        LV.loff[l] = 0;
+        LV.rob[l] = -1;
+      }
+      for (int r = 0; r < R; ++r) {
+        bool robot = r >= E.nlim && (int)E.at(w.con + (long)(r - E.nlim) * CR + C_OK) == 0;
+        if (robot) LV.rob[LV.lvl[r]] = r;
+        else LV.loff[LV.lvl[r]] += 1;
+      }
+      int acc = 0;
+      for (int l = 1; l <= maxl; ++l) {
+        int c = LV.loff[l];
+        LV.loff[l - 1] = acc;
+        acc += c;
+      }
+      LV.loff[maxl] = acc;
+      // fill: loff[l - 1] is the running write position of level l
+      for (int r = 0; r < R; ++r) {
+        bool robot = r >= E.nlim && (int)E.at(w.con + (long)(r - E.nlim) * CR + C_OK) == 0;
+        if (!robot) LV.order[LV.loff[LV.lvl[r] - 1]++] = r;
+      }
+      // restore the offsets
+      acc = 0;
+      for (int l = 1; l <= maxl; ++l) {
+        int end = LV.loff[l - 1];
+        LV.loff[l - 1] = acc;
+        acc = end;
+      }
+      LV.loff[maxl] = acc;
+      LV.cnt[0] = E.nc;
+      LV.cnt[1] = E.nrob;
+      LV.cnt[2] = E.nlim;
+      LV.cnt[3] = maxl;
+      LV.cnt[4] = (int)E.status;
+    }
+    wsync();
+    E.nc = LV.cnt[0];
+    E.nrob = LV.cnt[1];
+    E.nlim = LV.cnt[2];
+    E.status = (uint32_t)LV.cnt[4];
+    const int maxl = LV.cnt[3];
+    E.tb = Buf{const_cast<float*>(rec + RL.tape + (size_t)si * a.pr.K * RL.tsw), 1};
+    E.tsw = RL.tsw;
+    // impulses after the last sweep
+    const int R = E.nlim + E.nc;
+    for (int r = lane; r < R; r += 64) {
+      if (r < E.nlim) {
+        float y = a.pr.K > 0 ? E.tape_at(a.pr.K - 1, r, 0) : 0.f;
+        L[w.llam + r] = y > 0.f ? y : 0.f;
+      } else {
+        const int ci = r - E.nlim;
+        float l0 = 0.f, l1 = 0.f, l2 = 0.f;
+        if (a.pr.K > 0) {
+          if (E.row_ok(ci, 0)) {
+            float y = E.tape_at(a.pr.K - 1, r, 0);
+            l0 = y > 0.f ? y : 0.f;
+          }
+          if (E.row_ok(ci, 1) && E.row_ok(ci, 2))
+            disk_proj(E.tape_at(a.pr.K - 1, r, 1), E.tape_at(a.pr.K - 1, r, 2), a.pr.mu * l0, l1, l2);
+        }
+        L[w.lam + ci * 3] = l0;
+        L[w.lam + ci * 3 + 1] = l1;
+        L[w.lam + ci * 3 + 2] = l2;
+      }
+    }
+    // adjoint accumulators of this substep
+    zero_lds(L, w.gB, w.ss);
+    zero_lds(L, w.vRb, ND);
+    zero_lds(L, w.vAb, AMAX);
+    zero_lds(L, w.vFb, fm * 6);
+    zero_lds(L, w.limb, 2 * AMAX);
+    zero_lds(L, w.llamb, 2 * AMAX);
+    zero_lds(L, w.lamb, 3 * E.nc);
+    zero_lds(L, w.conb, E.nc * CB);
+    zero_lds(L, w.rJb, E.nrob * 3 * ND);
+    zero_lds(L, w.rwb, E.nrob * 3 * ND);
+    zero_lds(L, w.fb, fm * FB);
+    zero_lds(L, w.xb, AMAX * XB);
+    zero_lds(L, w.bacc, ND * 9);
+    wsync();
+    if (lane == 0) E.integrate_bar(w.st);
+    wsync();
+    // Gauss-Seidel sweeps in reverse, levels in reverse
+    for (int it = a.pr.K - 1; it >= 0; --it) {
+      for (int lv = maxl; lv >= 1; --lv) {
+        const int rr = LV.rob[lv];
+        if (rr >= 0) robot_contact_bar(E, it, rr - E.nlim, L);
+        const int o0 = LV.loff[lv - 1], o1 = LV.loff[lv];
+        for (int k = o0 + lane; k < o1; k += 64) {
+          const int r = LV.order[k];
+          if (r < E.nlim) E.limit_bar(it, r);
+          else E.contact_bar(it, r - E.nlim);
+        }
+        wsync();
+      }
+    }
+    // the rest of the reverse substep on one lane
+    if (lane == 0) {
+      E.rows_bar();
+      E.dynamics_bar(w.st, u);
+      E.contacts_bar();
+      E.frames_bar(w.st);
+      E.kin_bar();
+      LV.cnt[4] = (int)E.status;
+    }
+    wsync();
+    for (int i = lane; i < w.ss; i += 64) L[w.gA + i] = L[w.gB + i];
+    wsync();
+  }
+  if (lane < ND) {
+    a.gxi[oq + lane] = L[w.gA + lane];
+    a.gxi[oqd + lane] = L[w.gA + ND + lane];
+    a.gu[16 * (size_t)s + lane] = L[w.ub + lane];
+  }
+  for (int i = lane; i < nf * 16; i += 64) a.gxi[ofr + i] = L[w.gA + 32 + i];
+  if (lane < na * 4) a.gxi[oax + lane] = L[w.gA + 32 + 16 * fm + lane];
+  if (lane == 0 && LV.cnt[4]) a.status[s] |= (uint32_t)LV.cnt[4];
+}
+
+}  // namespace
+
+__global__ __launch_bounds__(64) void k_step_bwd_wave(BwdArgs a) {
+  extern __shared__ float lds[];
+  const int slot = blockIdx.x;
+  if (slot >= a.S) return;
+  bwd_scene(a, a.order[slot], lds);
+}
+
+void launch_step_bwd_wave(const BwdArgs& a, size_t lds_bytes, hipStream_t st) {
+  hipLaunchKernelGGL(k_step_bwd_wave, dim3(a.S), dim3(64), lds_bytes, st, a);
+}
+const void* step_bwd_wave_ptr() { return reinterpret_cast<const void*>(&k_step_bwd_wave); }
 
 }  // namespace msk

@@ -112,6 +112,26 @@ __host__ __device__ inline LdsLayout make_layout(int fmax, int smax, int ccap, i
   return L;
 }
 
+// Record of one control step written by the forward kernel for the adjoint
+// (floats, per scene, contiguous): the state at every substep start and at the
+// end (each 32 + 16 fmax + 4 AMAX floats: q, qd, free bodies, door/drawer),
+// per substep the contact list (header NC, NL, NR, 0, then NC records of
+// CSTR floats), and per substep the pre-projection value of every
+// Gauss-Seidel row update (sweep-major, 3 slots per list entry).
+struct RecLayout {
+  int ss, con, cstride, tape, tsw, total;
+};
+__host__ __device__ inline RecLayout rec_layout(int fmax, int ccap, int K, int nsub) {
+  RecLayout r;
+  r.ss = 32 + 16 * fmax + 4 * AMAX;
+  r.con = (nsub + 1) * r.ss;
+  r.cstride = 4 + ccap * CSTR;
+  r.tape = r.con + nsub * r.cstride;
+  r.tsw = 3 * ccap;
+  r.total = (r.tape + nsub * K * r.tsw + 3) & ~3;
+  return r;
+}
+
 struct KArgs {
   const DModel* models;
   const DScene* scenes;
@@ -134,6 +154,8 @@ struct KArgs {
   float h, mu, beta, margin;
   float g[3];
   LdsLayout L;
+  float* rec;              // record of the control step for the adjoint, or null
+  RecLayout RL;
 };
 
 void launch_step(const KArgs& a, int grid, size_t lds_bytes, hipStream_t st);
@@ -141,5 +163,6 @@ void launch_reset_queue(int* q, hipStream_t st);
 void launch_masked_copy(float* dst, const float* src, const uint8_t* mask, int S, int NF, int NA,
                         const int* free_off, const int* aux_off, hipStream_t st);
 const void* step_kernel_ptr();
+const void* step_rec_kernel_ptr();
 
 }  // namespace msk

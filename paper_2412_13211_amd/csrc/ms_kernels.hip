@@ -169,7 +169,9 @@ enum AF {
   A_TYPE = 27, A_LIM = 28, A_M = 29, A_N = 30
 };
 // contact fields (structure of arrays, stride ccap)
-enum CF { C_INFO = 0, C_N = 1, C_P = 4, C_IW = 7, C_BIAS = 10, C_LAM = 11, C_PHI = 14, C_LVL = 15 };
+// C_KEY: owner sphere index or box vertex (bits 0..7), target class (8..9),
+// target index (10..31)
+enum CF { C_INFO = 0, C_N = 1, C_P = 4, C_IW = 7, C_BIAS = 10, C_LAM = 11, C_PHI = 14, C_LVL = 15, C_KEY = 16 };
 
 // side kinds packed in a contact's info word: A in bits 0..15, B in 16..31,
 // each (kind << 8) | index
@@ -293,6 +295,7 @@ __device__ __forceinline__ void store_scene(const KArgs& a, const Scene& S, floa
   const int lane = lane_id();
   const LdsLayout& Y = a.L;
   bool bad = false;
+  if (!a.x_out) return;  // record mode: the state goes to the record only
   if (lane < ND) {
     float q = rb.q[lane], qd = rb.qd[lane];
     bad |= !isfinite(q) || !isfinite(qd);
@@ -322,6 +325,48 @@ __device__ __forceinline__ void store_scene(const KArgs& a, const Scene& S, floa
     *reinterpret_cast<float4*>(xs) = make_float4(q, qd, 0.f, 0.f);
   }
   if (__ballot(bad)) status |= 1u;
+}
+
+// ---------------------------------------------------------------- record for the adjoint
+// state at a substep boundary (q, qd, free bodies, door/drawer joints)
+__device__ __forceinline__ void rec_state(const KArgs& a, const Scene& S, const float* L, const Robot& rb, float* R) {
+  const int lane = lane_id();
+  const LdsLayout& Y = a.L;
+  if (lane < ND) {
+    R[lane] = rb.q[lane];
+    R[ND + lane] = rb.qd[lane];
+  }
+  const float* F = L + Y.fr;
+  const int fm = Y.fmax;
+  for (int f = lane; f < S.nf; f += WAVE) {
+    float* x = R + 32 + 16 * f;
+    x[0] = F[(f) * FSTR + F_X + 0]; x[1] = F[(f) * FSTR + F_X + 1]; x[2] = F[(f) * FSTR + F_X + 2]; x[3] = 0.f;
+    x[4] = F[(f) * FSTR + F_Q + 0]; x[5] = F[(f) * FSTR + F_Q + 1]; x[6] = F[(f) * FSTR + F_Q + 2];
+    x[7] = F[(f) * FSTR + F_Q + 3];
+    x[8] = F[(f) * FSTR + F_V + 0]; x[9] = F[(f) * FSTR + F_V + 1]; x[10] = F[(f) * FSTR + F_V + 2]; x[11] = 0.f;
+    x[12] = F[(f) * FSTR + F_W + 0]; x[13] = F[(f) * FSTR + F_W + 1]; x[14] = F[(f) * FSTR + F_W + 2]; x[15] = 0.f;
+  }
+  const float* A = L + Y.aux;
+  if (lane < AMAX) {
+    float* x = R + 32 + 16 * fm + 4 * lane;
+    bool on = lane < S.na;
+    x[0] = on ? A[A_Q * AMAX + lane] : 0.f;
+    x[1] = on ? A[A_QD * AMAX + lane] : 0.f;
+    x[2] = 0.f;
+    x[3] = 0.f;
+  }
+}
+// the substep's contact list as emitted (before the rows overwrite it)
+__device__ __forceinline__ void rec_contacts(const KArgs& a, const float* L, int NC, int NL, int NR, float* R) {
+  const int lane = lane_id();
+  if (lane == 0) {
+    R[0] = __int_as_float(NC);
+    R[1] = __int_as_float(NL);
+    R[2] = __int_as_float(NR);
+    R[3] = 0.f;
+  }
+  const float* C = L + a.L.con;
+  for (int i = lane; i < NC * CSTR; i += WAVE) R[4 + i] = C[i];
 }
 
 // ---------------------------------------------------------------- phases
@@ -501,7 +546,7 @@ struct PairOut {
   float phi;
   f3 n, c;
   float r;
-  int aside, bside;
+  int aside, bside, osub;
   uint32_t okey, tkey;
 };
 
@@ -608,6 +653,7 @@ __device__ __forceinline__ bool eval_pair(const ConCtx& X, int o, int t, PairOut
   out.aside = okind == 0 ? ((K_ROBOT << 8) | oidx) : ((K_FREE << 8) | of);
   out.bside = bside;
   out.okey = okind == 0 ? (uint32_t)o : ((1u << 24) | ((uint32_t)of << 3) | (uint32_t)ovk);
+  out.osub = okind == 0 ? o : ovk;
   out.tkey = (uint32_t)tkey;
   return allowed && phi < X.margin;
 }
@@ -639,6 +685,7 @@ __device__ __forceinline__ void emit(const ConCtx& X, int rcap, bool hit, bool i
     C[(pos) * CSTR + C_N + 0] = po.n.x; C[(pos) * CSTR + C_N + 1] = po.n.y; C[(pos) * CSTR + C_N + 2] = po.n.z;
     C[(pos) * CSTR + C_P + 0] = p.x; C[(pos) * CSTR + C_P + 1] = p.y; C[(pos) * CSTR + C_P + 2] = p.z;
     C[(pos) * CSTR + C_PHI] = po.phi;
+    C[(pos) * CSTR + C_KEY] = __int_as_float(po.osub | (int)((po.tkey >> 24) << 8) | (int)((po.tkey & 0xffffffu) << 10));
     E.ks += mix64(((uint64_t)po.okey << 32) | po.tkey);
   }
   uint64_t mkept = __ballot(keep);
@@ -1407,7 +1454,7 @@ __device__ __forceinline__ void friction_disk(float l1, float l2, float r1, floa
 }
 
 __device__ __forceinline__ void phase_pgs(const KArgs& a, const Scene& S, float* L, int NC, int NL, int maxl,
-                                          float& vR) {
+                                          float& vR, float* tape) {
   const int lane = lane_id();
   const LdsLayout& Y = a.L;
   float* C = L + Y.con;
@@ -1445,6 +1492,7 @@ __device__ __forceinline__ void phase_pgs(const KArgs& a, const Scene& S, float*
         float r = dn - dot(n, side_vel(B, p)) + bias;
         float nl = l0;
         if (iw0 > 0.f) nl = fmaxf(0.f, l0 - r * iw0);
+        if (tape && lane == 0) tape[it * a.RL.tsw + rc * 3] = l0 - r * iw0;
         float dl = nl - l0;
         if (lane < ND) vR += wn * dl;
         side_impulse(B, p, n * (-dl));
@@ -1459,6 +1507,10 @@ __device__ __forceinline__ void phase_pgs(const KArgs& a, const Scene& S, float*
           f3 uB = side_vel(B, p);
           float y1, y2;
           friction_disk(l1, l2, d1 - dot(t1, uB), d2 - dot(t2, uB), iw1, iw2, mu * nl, y1, y2);
+          if (tape && lane == 0) {
+            tape[it * a.RL.tsw + rc * 3 + 1] = l1 - (d1 - dot(t1, uB)) * iw1;
+            tape[it * a.RL.tsw + rc * 3 + 2] = l2 - (d2 - dot(t2, uB)) * iw2;
+          }
           float dl1 = y1 - l1, dl2 = y2 - l2;
           if (lane < ND) vR += w1 * dl1 + w2 * dl2;
           side_impulse(B, p, (t1 * dl1 + t2 * dl2) * (-1.f));
@@ -1491,6 +1543,7 @@ __device__ __forceinline__ void phase_pgs(const KArgs& a, const Scene& S, float*
           float iwl = c[C_IW];  // = 1 / W
           float r = sg * A[A_V * AMAX + x] + bias;
           float nl = fmaxf(0.f, l0 - r * iwl);
+          if (tape) tape[it * a.RL.tsw + ci * 3] = l0 - r * iwl;
           A[A_V * AMAX + x] += sg * A[A_IM * AMAX + x] * (nl - l0);
           c[C_LAM] = nl;
           continue;
@@ -1505,6 +1558,7 @@ __device__ __forceinline__ void phase_pgs(const KArgs& a, const Scene& S, float*
         float r = dot(n, side_vel(SA, p) - side_vel(SB, p)) + bias;
         float nl = l0;
         if (iw0 > 0.f) nl = fmaxf(0.f, l0 - r * iw0);
+        if (tape) tape[it * a.RL.tsw + ci * 3] = l0 - r * iw0;
         float dl = nl - l0;
         side_impulse(SA, p, n * dl);
         side_impulse(SB, p, n * (-dl));
@@ -1514,6 +1568,10 @@ __device__ __forceinline__ void phase_pgs(const KArgs& a, const Scene& S, float*
           f3 du = side_vel(SA, p) - side_vel(SB, p);
           float y1, y2;
           friction_disk(l1, l2, dot(t1, du), dot(t2, du), iw1, iw2, mu * nl, y1, y2);
+          if (tape) {
+            tape[it * a.RL.tsw + ci * 3 + 1] = l1 - dot(t1, du) * iw1;
+            tape[it * a.RL.tsw + ci * 3 + 2] = l2 - dot(t2, du) * iw2;
+          }
           f3 P = t1 * (y1 - l1) + t2 * (y2 - l2);
           side_impulse(SA, p, P);
           side_impulse(SB, p, P * (-1.f));
@@ -1578,6 +1636,9 @@ __device__ __forceinline__ void phase_integrate(const KArgs& a, const Scene& S, 
   wave_sync();
 }
 
+// REC: also write the record of the control step for the adjoint (a
+// separate instantiation, so the plain step keeps its register allocation)
+template <bool REC>
 __device__ __forceinline__ void run_scene(const KArgs& a, int s, float* L) {
   const int lane = lane_id();
   Scene S;
@@ -1602,14 +1663,18 @@ __device__ __forceinline__ void run_scene(const KArgs& a, int s, float* L) {
   load_scene(a, S, L, rb);
   MS_PHASE(7)
   uint32_t status = 0;
+  float* rec = REC ? a.rec + (size_t)s * a.RL.total : nullptr;
   for (int k = 0; k < a.n_sub; ++k) {
     int NC, NR, NL;
     uint64_t keysum = 0;
     float vR;
+    const int ks = a.sub0 + k;
+    if (rec) rec_state(a, S, L, rb, rec + ks * a.RL.ss);
     phase_drive(a, S, rb);
     phase_kinematics(a, S, L, rb);
     MS_PHASE(0)
     phase_contacts(a, S, L, rb, NC, NR, NL, status, keysum);
+    if (rec) rec_contacts(a, L, NC, NL, NR, rec + a.RL.con + ks * a.RL.cstride);
     MS_PHASE(1)
     phase_dynamics(a, S, L, rb, vR);
     MS_PHASE(2)
@@ -1617,10 +1682,11 @@ __device__ __forceinline__ void run_scene(const KArgs& a, int s, float* L) {
     MS_PHASE(3)
     int maxl = phase_levels(a, L, NC, NR, NL);
     MS_PHASE(4)
-    phase_pgs(a, S, L, NC, NL, maxl, vR);
+    phase_pgs(a, S, L, NC, NL, maxl, vR, rec ? rec + a.RL.tape + (size_t)ks * a.K * a.RL.tsw : nullptr);
     MS_PHASE(5)
     phase_integrate(a, S, L, rb, vR);
     MS_PHASE(6)
+    if (rec && ks == a.n_sub_total - 1) rec_state(a, S, L, rb, rec + (ks + 1) * a.RL.ss);
     if (a.debug && lane == 0) {
       uint32_t* d = a.debug + ((size_t)s * a.n_sub_total + a.sub0 + k) * 4;
       d[0] = (uint32_t)(NC - NL);
@@ -1644,8 +1710,8 @@ __device__ __forceinline__ void run_scene(const KArgs& a, int s, float* L) {
   }
 }
 
-__global__ __launch_bounds__(WAVE) __attribute__((amdgpu_waves_per_eu(2, 2))) void k_step(KArgs a) {
-  extern __shared__ float lds[];
+template <bool REC>
+__device__ __forceinline__ void step_body(const KArgs& a, float* lds) {
   // one call site: the persistent form pulls scene indices from the queue,
   // the plain form takes its block index once
   int idx = a.persistent ? 0 : (int)blockIdx.x;
@@ -1656,10 +1722,19 @@ __global__ __launch_bounds__(WAVE) __attribute__((amdgpu_waves_per_eu(2, 2))) vo
       idx = __shfl(got, 0, WAVE);
     }
     if (idx >= a.S) break;
-    run_scene(a, a.order[idx], lds);
+    run_scene<REC>(a, a.order[idx], lds);
     if (!a.persistent) break;
     __syncthreads();
   }
+}
+
+__global__ __launch_bounds__(WAVE) __attribute__((amdgpu_waves_per_eu(2, 2))) void k_step(KArgs a) {
+  extern __shared__ float lds[];
+  step_body<false>(a, lds);
+}
+__global__ __launch_bounds__(WAVE) __attribute__((amdgpu_waves_per_eu(2, 2))) void k_step_rec(KArgs a) {
+  extern __shared__ float lds[];
+  step_body<true>(a, lds);
 }
 
 __global__ void k_reset_queue(int* q) {
@@ -1683,7 +1758,8 @@ __global__ void k_masked_copy(float* dst, const float* src, const uint8_t* mask,
 }
 
 void launch_step(const KArgs& a, int grid, size_t lds_bytes, hipStream_t st) {
-  hipLaunchKernelGGL(k_step, dim3(grid), dim3(WAVE), lds_bytes, st, a);
+  if (a.rec) hipLaunchKernelGGL(k_step_rec, dim3(grid), dim3(WAVE), lds_bytes, st, a);
+  else hipLaunchKernelGGL(k_step, dim3(grid), dim3(WAVE), lds_bytes, st, a);
 }
 void launch_reset_queue(int* q, hipStream_t st) { hipLaunchKernelGGL(k_reset_queue, dim3(1), dim3(64), 0, st, q); }
 void launch_masked_copy(float* dst, const float* src, const uint8_t* mask, int S, int NF, int NA,
@@ -1692,5 +1768,6 @@ void launch_masked_copy(float* dst, const float* src, const uint8_t* mask, int S
   hipLaunchKernelGGL(k_masked_copy, dim3(S), dim3(64), 0, st, dst, src, mask, S, NF, NA, free_off, aux_off);
 }
 const void* step_kernel_ptr() { return reinterpret_cast<const void*>(&k_step); }
+const void* step_rec_kernel_ptr() { return reinterpret_cast<const void*>(&k_step_rec); }
 
 }  // namespace msk

@@ -150,6 +150,26 @@ def test_backward_full_size_sampled():
     assert np.all(err <= GRAD_TOL), err
 
 
+def test_reference_kernel_agrees():
+    """The lane-per-scene kernel (recomputes everything itself) and the
+    wavefront kernel (reads the forward kernel's record) both meet the bar."""
+    ms = _ms()
+    b = sg.make(5, 8)
+    x = advanced_state(b, 3)
+    u = b.controls_for(3)
+    g = np.random.default_rng(21).normal(size=x.size)
+    o = oracle.Oracle(b, threads=8)
+    ref, mask, scale = oracle_vjp_smooth(o, b, x, u, g)
+    mb = ms.MsBatch(b, backward=True)
+    wave = scene_vectors(b, *gpu_vjp(mb, x, u, g))
+    mb.set_schedule(mb.get_schedule()[0] | ms.MS_SCHED_BWD_REFERENCE)
+    lane = scene_vectors(b, *gpu_vjp(mb, x, u, g))
+    e_wave, e_lane = compare(ref, mask, scale, wave), compare(ref, mask, scale, lane)
+    say(f"wavefront kernel rel err {np.array2string(e_wave, precision=2)}")
+    say(f"lane kernel rel err {np.array2string(e_lane, precision=2)}")
+    assert np.all(e_wave <= GRAD_TOL) and np.all(e_lane <= GRAD_TOL)
+
+
 def test_backward_alias_and_determinism():
     ms = _ms()
     b = sg.make(2, 16)
