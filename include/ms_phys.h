@@ -216,6 +216,20 @@ ms_status ms_get_state(const ms_batch* b, const void* state_dev, ms_state_view* 
 ms_status ms_set_state(ms_batch* b, void* state_dev, const void* src_dev, const uint8_t* scene_mask_dev,
                        void* hip_stream);
 
+/* Contact-force outputs (the inputs of contact-based task predicates: the
+ * robot's cumulative collision force and per-object contact forces, Sec. 4.3
+ * and App. A).  When both pointers are non-null, every following ms_step
+ * also writes, for its control step:
+ *   robot_force_dev[S]       sum over the substeps of the robot's total
+ *                            normal contact force (sum of its normal impulses
+ *                            / h), N;
+ *   body_force_dev[NF][4]    per free body, sum over the substeps of the force
+ *                            the robot's contacts exert on it (x, y, z; then 0).
+ * Divide by n_substeps for the mean over the control step.  Both null: off
+ * (the default).  Device float32 buffers owned by the caller; only one
+ * non-null is MS_E_INVALID.  Drops captured graphs. */
+ms_status ms_set_force_outputs(ms_batch* b, float* robot_force_dev, float* body_force_dev);
+
 /* Synchronise and read the per-scene status words of the last step
  * (bits MS_ST_*) into status_host[S].  Returns MS_E_NUMERIC if any scene
  * has MS_ST_NONFINITE or MS_ST_DEGENERATE set, MS_OK otherwise. */

@@ -59,7 +59,8 @@ class OrParams(C.Structure):
 class OrDebug(C.Structure):
     _fields_ = [("status", C.c_void_p), ("n_contacts", C.c_void_p), ("key_hash", C.c_void_p),
                 ("act_hash", C.c_void_p), ("dump_cap", C.c_int32), ("dump_keys", C.c_void_p),
-                ("dump_phi", C.c_void_p), ("dump_lambda", C.c_void_p), ("robot_force", C.c_void_p)]
+                ("dump_phi", C.c_void_p), ("dump_lambda", C.c_void_p), ("robot_force", C.c_void_p),
+                ("robot_body_force", C.c_void_p)]
 
 
 _lib = None
@@ -151,7 +152,8 @@ class Oracle:
             ns = self.params.n_sub
             d = dict(status=np.zeros(self.S, np.uint32), n_contacts=np.zeros((self.S, ns), np.int32),
                      key_hash=np.zeros((self.S, ns), np.uint64), act_hash=np.zeros((self.S, ns), np.uint64),
-                     robot_force=np.zeros(self.S, np.float64))
+                     robot_force=np.zeros(self.S, np.float64),
+                     robot_body_force=np.zeros((max(self.batch.n_free, 1), 3), np.float64))
             if dump_cap:
                 d["dump_keys"] = np.zeros((self.S, dump_cap), np.uint64)
                 d["dump_phi"] = np.zeros((self.S, dump_cap), np.float64)

@@ -449,6 +449,7 @@ struct SceneC {
   std::vector<std::array<double, 6>> aux_box;
   std::vector<std::array<double, 2>> aux_lim;
   double hold[ND];
+  int f0;  // global index of the scene's first free body
 };
 
 void load_scene(const or_scene* sc, const std::vector<ArtModel>& robots, int s, SceneC& c) {
@@ -493,6 +494,7 @@ void load_scene(const or_scene* sc, const std::vector<ArtModel>& robots, int s, 
   c.aux_lim.resize(na);
   for (int x = 0; x < na; ++x) load_aux(sc, sc->aux_off[s] + x, c.aux[x], c.aux_box[x].data(), c.aux_lim[x].data());
   for (int j = 0; j < ND; ++j) c.hold[j] = sc->scene_hold[s * ND + j];
+  c.f0 = sc->free_off[s];
 }
 
 template <class T> struct FreeS {
@@ -951,6 +953,19 @@ template <class T> void substep(const SceneC& c, const or_params& pr, StateS<T>&
         if (con[ci].robot_owner) fsum += std::fabs(val(lam[ci][0])) / h;
       dbg->robot_force[s] += fsum;
     }
+    if (dbg->robot_body_force) {
+      // the impulse on the owner A is sum_d d lambda_d; the target B receives its negative
+      for (int ci = 0; ci < NC; ++ci) {
+        const Contact<T>& ct = con[ci];
+        if (!ct.robot_owner || ct.B.kind != 2) continue;
+        double* F = dbg->robot_body_force + (size_t)(c.f0 + ct.B.body) * 3;
+        for (int t = 0; t < 3; ++t) {
+          double P = 0.0;
+          for (int d = 0; d < 3; ++d) P += val(rows[ci].d[d][t]) * val(lam[ci][d]);
+          F[t] -= P / h;
+        }
+      }
+    }
     if (isub == n_sub - 1 && dbg->dump_cap > 0) {
       for (int ci = 0; ci < dbg->dump_cap; ++ci) {
         size_t o = (size_t)s * dbg->dump_cap + ci;
@@ -1079,6 +1094,8 @@ int or_step(const or_scene* sc, const or_params* pr, const double* x_in, const d
   const int S = sc->n_scenes;
   if (dbg && dbg->robot_force)
     for (int s = 0; s < S; ++s) dbg->robot_force[s] = 0.0;
+  if (dbg && dbg->robot_body_force)
+    for (size_t i = 0; i < (size_t)L.NF * 3; ++i) dbg->robot_body_force[i] = 0.0;
   std::vector<double> xin(x_in, x_in + (size_t)S * 2 * ND + (size_t)L.NF * 16 + (size_t)L.NA * 4);
   parallel_scenes(S, threads, [&](int s) {
     SceneC c;

@@ -89,6 +89,8 @@ typedef struct {
   double* dump_phi;        // [S][dump_cap]
   double* dump_lambda;     // [S][dump_cap][3] final impulses
   double* robot_force;     // [S] sum over substeps of robot-owned normal impulses / h
+  double* robot_body_force;  // [NF][3] sum over substeps of the force the robot's
+                             // contacts exert on each free body (impulse / h)
 } or_debug;
 
 // One control step for every scene.  x_in / x_out: flat state

@@ -27,7 +27,7 @@ MS_ST_NONFINITE, MS_ST_OVERFLOW, MS_ST_DEGENERATE, MS_ST_ROBOT_OVERFLOW = 1, 2, 
 
 EXPORTS = ["ms_query_sizes", "ms_state_floats", "ms_create_batch", "ms_destroy_batch", "ms_set_schedule",
            "ms_get_schedule", "ms_autotune", "ms_step", "ms_step_backward", "ms_get_state", "ms_set_state",
-           "ms_scene_status", "ms_enable_debug", "ms_debug_contacts", "ms_enable_phase_profile", "ms_phase_cycles",
+           "ms_scene_status", "ms_set_force_outputs", "ms_enable_debug", "ms_debug_contacts", "ms_enable_phase_profile", "ms_phase_cycles",
            "ms_last_error"]
 PHASES = ["drive+kinematics", "contacts", "dynamics", "rows", "levels", "pgs", "integrate", "load/store"]
 
@@ -95,6 +95,7 @@ def lib():
             "ms_get_state": [vp, vp, vp],
             "ms_set_state": [vp, vp, vp, vp, vp],
             "ms_scene_status": [vp, vp],
+            "ms_set_force_outputs": [vp, vp, vp],
             "ms_enable_debug": [vp, i32],
             "ms_debug_contacts": [vp, vp],
             "ms_enable_phase_profile": [vp, i32],
@@ -251,6 +252,21 @@ class MsBatch:
         _check(lib().ms_step_backward(self.h, _ptr_t(x), _ptr_t(u), _ptr_t(gx_out), _ptr_t(gx_in), _ptr_t(gu),
                                       _stream(stream)), "ms_step_backward")
         return gx_in, gu
+
+    def enable_forces(self, on=True):
+        """Contact-force outputs written by every following ``step``: returns
+        (robot_force [S], body_force [NF, 4]) device tensors (sums over the
+        substeps of a control step), or None after ``enable_forces(False)``."""
+        t = self.torch
+        if on:
+            self.robot_force = t.zeros(self.S, dtype=t.float32, device=self.device)
+            self.body_force = t.zeros((max(self.n_free, 1), 4), dtype=t.float32, device=self.device)
+            _check(lib().ms_set_force_outputs(self.h, _ptr_t(self.robot_force), _ptr_t(self.body_force)),
+                   "ms_set_force_outputs")
+            return self.robot_force, self.body_force
+        _check(lib().ms_set_force_outputs(self.h, None, None), "ms_set_force_outputs")
+        self.robot_force = self.body_force = None
+        return None
 
     def set_schedule(self, flags, grid=0):
         s = Schedule(flags, grid)

@@ -47,6 +47,8 @@ struct ms_batch {
   ms_schedule sched;
   bool debug_on;
   bool profile_on;
+  float* frc_robot;
+  float* frc_body;
   hipStream_t cap_stream;
   // graphs keyed by (x_in, u, x_out)
   std::map<std::tuple<const void*, const void*, void*>, hipGraphExec_t> graphs;
@@ -98,6 +100,8 @@ KArgs make_args(const ms_batch* b, const void* x_in, const float* u, void* x_out
   a.margin = b->desc.margin;
   for (int t = 0; t < 3; ++t) a.g[t] = b->desc.gravity[t];
   a.L = lds_for(&b->desc, b->cnt, a.stage_static);
+  a.frc_robot = b->frc_robot;
+  a.frc_body = b->frc_body;
   return a;
 }
 
@@ -231,6 +235,8 @@ ms_status ms_create_batch(const ms_batch_desc* d, const ms_scene_desc* sc, void*
   b->sched.grid = 0;
   b->debug_on = false;
   b->profile_on = false;
+  b->frc_robot = nullptr;
+  b->frc_body = nullptr;
   if (hipStreamCreateWithFlags(&b->cap_stream, hipStreamNonBlocking) != hipSuccess) {
     delete b;
     return fail(MS_E_HIP, "hipStreamCreateWithFlags failed");
@@ -238,6 +244,7 @@ ms_status ms_create_batch(const ms_batch_desc* d, const ms_scene_desc* sc, void*
   // allow the kernels the whole LDS of a workgroup
   (void)hipFuncSetAttribute(step_kernel_ptr(), hipFuncAttributeMaxDynamicSharedMemorySize, (int)b->max_lds);
   (void)hipFuncSetAttribute(step_rec_kernel_ptr(), hipFuncAttributeMaxDynamicSharedMemorySize, (int)b->max_lds);
+  (void)hipFuncSetAttribute(step_frc_kernel_ptr(), hipFuncAttributeMaxDynamicSharedMemorySize, (int)b->max_lds);
   (void)hipFuncSetAttribute(step_bwd_wave_ptr(), hipFuncAttributeMaxDynamicSharedMemorySize, (int)b->max_lds);
   // status starts at zero
   hipError_t e = hipMemsetAsync(b->scratch + b->sl.status, 0, sizeof(uint32_t) * c.S, stream);
@@ -323,6 +330,8 @@ ms_status enqueue_record(ms_batch* b, const void* x_in, const float* u, float* r
   KArgs a = make_args(b, x_in, u, nullptr);
   a.debug = nullptr;
   a.phase_cycles = nullptr;
+  a.frc_robot = nullptr;
+  a.frc_body = nullptr;
   a.rec = rec;
   a.RL = bwd_rec(&b->desc, b->cnt);
   size_t lds = lds_bytes_of(a);
@@ -334,6 +343,16 @@ ms_status enqueue_record(ms_batch* b, const void* x_in, const float* u, float* r
   }
   launch_step(a, grid, lds, st);
   HIP_TRY(hipGetLastError());
+  return MS_OK;
+}
+
+ms_status ms_set_force_outputs(ms_batch* b, float* robot_force, float* body_force) {
+  if (!b) return fail(MS_E_INVALID, "null batch");
+  if ((robot_force == nullptr) != (body_force == nullptr))
+    return fail(MS_E_INVALID, "ms_set_force_outputs: give both outputs or neither");
+  drop_graphs(b);
+  b->frc_robot = robot_force;
+  b->frc_body = body_force;
   return MS_OK;
 }
 

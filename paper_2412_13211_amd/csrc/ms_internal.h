@@ -156,6 +156,8 @@ struct KArgs {
   LdsLayout L;
   float* rec;              // record of the control step for the adjoint, or null
   RecLayout RL;
+  float* frc_robot;        // [S] contact-force outputs, or null
+  float* frc_body;         // [NF][4]
 };
 
 void launch_step(const KArgs& a, int grid, size_t lds_bytes, hipStream_t st);
@@ -164,5 +166,6 @@ void launch_masked_copy(float* dst, const float* src, const uint8_t* mask, int S
                         const int* free_off, const int* aux_off, hipStream_t st);
 const void* step_kernel_ptr();
 const void* step_rec_kernel_ptr();
+const void* step_frc_kernel_ptr();
 
 }  // namespace msk

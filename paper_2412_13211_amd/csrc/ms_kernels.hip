@@ -161,7 +161,8 @@ __device__ __forceinline__ Robot robot_view(float* base, float* dyn) {
 }
 // free-body fields (structure of arrays, stride fmax)
 enum FF {
-  F_X = 0, F_Q = 3, F_V = 7, F_W = 10, F_R = 13, F_II = 22, F_IM = 31, F_TYPE = 32, F_H = 33, F_IB = 36, F_N = 39
+  F_X = 0, F_Q = 3, F_V = 7, F_W = 10, F_R = 13, F_II = 22, F_FRC = 28, F_IM = 31, F_TYPE = 32, F_H = 33, F_IB = 36,
+  F_N = 39
 };
 // aux fields (stride AMAX)
 enum AF {
@@ -1636,10 +1637,42 @@ __device__ __forceinline__ void phase_integrate(const KArgs& a, const Scene& S, 
   wave_sync();
 }
 
-// REC: also write the record of the control step for the adjoint (a
-// separate instantiation, so the plain step keeps its register allocation)
-template <bool REC>
+// Contact-force outputs of a substep: the sum of the robot's normal impulses
+// / h (all lanes hold it), and per free body the force the robot's contacts
+// exert on it (the negative of the impulse on the robot side, / h),
+// accumulated in the body's record.
+__device__ __forceinline__ void phase_forces(const KArgs& a, const Scene& S, float* L, int NL, int NR, float& frc) {
+  const int lane = lane_id();
+  const float* C = L + a.L.con;
+  float* F = L + a.L.fr;
+  const int fm = a.L.fmax;
+  float part = 0.f;
+  for (int ci = NL + lane; ci < NL + NR; ci += WAVE) part += C[ci * CSTR + C_LAM];
+  for (int off = 32; off > 0; off >>= 1) part += __shfl_xor(part, off, WAVE);
+  frc += part / a.h;
+  if (lane == 0) {
+    for (int ci = NL; ci < NL + NR; ++ci) {
+      const float* c = C + ci * CSTR;
+      int bside = (__float_as_int(c[C_INFO]) >> 16) & 0xffff;
+      if (side_kind(bside) != K_FREE) continue;
+      int g = side_idx(bside);
+      f3 n = mk3(c[C_N], c[C_N + 1], c[C_N + 2]), t1, t2;
+      onb(n, t1, t2);
+      f3 P = n * c[C_LAM] + t1 * c[C_LAM + 1] + t2 * c[C_LAM + 2];
+      F[(g) * FSTR + F_FRC + 0] -= P.x / a.h;
+      F[(g) * FSTR + F_FRC + 1] -= P.y / a.h;
+      F[(g) * FSTR + F_FRC + 2] -= P.z / a.h;
+    }
+  }
+  wave_sync();
+}
+
+// MODE 0: the plain step; 1: also the record of the control step for the
+// adjoint; 2: also the contact-force outputs.  Separate instantiations, so
+// the plain step keeps its register allocation.
+template <int MODE>
 __device__ __forceinline__ void run_scene(const KArgs& a, int s, float* L) {
+  constexpr bool REC = MODE == 1;
   const int lane = lane_id();
   Scene S;
   const DScene ds = a.scenes[s];
@@ -1663,6 +1696,14 @@ __device__ __forceinline__ void run_scene(const KArgs& a, int s, float* L) {
   load_scene(a, S, L, rb);
   MS_PHASE(7)
   uint32_t status = 0;
+  float frc = 0.f;
+  if (MODE == 2) {
+    float* F = L + a.L.fr;
+    const int fm = a.L.fmax;
+    for (int f = lane; f < S.nf; f += WAVE)
+      for (int t = 0; t < 3; ++t) F[(f) * FSTR + F_FRC + t] = 0.f;
+    wave_sync();
+  }
   float* rec = REC ? a.rec + (size_t)s * a.RL.total : nullptr;
   for (int k = 0; k < a.n_sub; ++k) {
     int NC, NR, NL;
@@ -1683,6 +1724,7 @@ __device__ __forceinline__ void run_scene(const KArgs& a, int s, float* L) {
     int maxl = phase_levels(a, L, NC, NR, NL);
     MS_PHASE(4)
     phase_pgs(a, S, L, NC, NL, maxl, vR, rec ? rec + a.RL.tape + (size_t)ks * a.K * a.RL.tsw : nullptr);
+    if (MODE == 2) phase_forces(a, S, L, NL, NR, frc);
     MS_PHASE(5)
     phase_integrate(a, S, L, rb, vR);
     MS_PHASE(6)
@@ -1696,6 +1738,19 @@ __device__ __forceinline__ void run_scene(const KArgs& a, int s, float* L) {
     }
   }
   store_scene(a, S, L, rb, status);
+  if (MODE == 2) {
+    const float* F = L + a.L.fr;
+    const int fm = a.L.fmax;
+    if (lane == 0) a.frc_robot[s] = a.sub0 == 0 ? frc : a.frc_robot[s] + frc;
+    for (int f = lane; f < S.nf; f += WAVE) {
+      float* dst = a.frc_body + (size_t)(S.f0 + f) * 4;
+      for (int t = 0; t < 3; ++t) {
+        float v = F[(f) * FSTR + F_FRC + t];
+        dst[t] = a.sub0 == 0 ? v : dst[t] + v;
+      }
+      dst[3] = 0.f;
+    }
+  }
   MS_PHASE(7)
 #undef MS_PHASE
   if (lane == 0) {
@@ -1710,7 +1765,7 @@ __device__ __forceinline__ void run_scene(const KArgs& a, int s, float* L) {
   }
 }
 
-template <bool REC>
+template <int MODE>
 __device__ __forceinline__ void step_body(const KArgs& a, float* lds) {
   // one call site: the persistent form pulls scene indices from the queue,
   // the plain form takes its block index once
@@ -1722,7 +1777,7 @@ __device__ __forceinline__ void step_body(const KArgs& a, float* lds) {
       idx = __shfl(got, 0, WAVE);
     }
     if (idx >= a.S) break;
-    run_scene<REC>(a, a.order[idx], lds);
+    run_scene<MODE>(a, a.order[idx], lds);
     if (!a.persistent) break;
     __syncthreads();
   }
@@ -1730,11 +1785,15 @@ __device__ __forceinline__ void step_body(const KArgs& a, float* lds) {
 
 __global__ __launch_bounds__(WAVE) __attribute__((amdgpu_waves_per_eu(2, 2))) void k_step(KArgs a) {
   extern __shared__ float lds[];
-  step_body<false>(a, lds);
+  step_body<0>(a, lds);
 }
 __global__ __launch_bounds__(WAVE) __attribute__((amdgpu_waves_per_eu(2, 2))) void k_step_rec(KArgs a) {
   extern __shared__ float lds[];
-  step_body<true>(a, lds);
+  step_body<1>(a, lds);
+}
+__global__ __launch_bounds__(WAVE) __attribute__((amdgpu_waves_per_eu(2, 2))) void k_step_frc(KArgs a) {
+  extern __shared__ float lds[];
+  step_body<2>(a, lds);
 }
 
 __global__ void k_reset_queue(int* q) {
@@ -1759,6 +1818,7 @@ __global__ void k_masked_copy(float* dst, const float* src, const uint8_t* mask,
 
 void launch_step(const KArgs& a, int grid, size_t lds_bytes, hipStream_t st) {
   if (a.rec) hipLaunchKernelGGL(k_step_rec, dim3(grid), dim3(WAVE), lds_bytes, st, a);
+  else if (a.frc_robot) hipLaunchKernelGGL(k_step_frc, dim3(grid), dim3(WAVE), lds_bytes, st, a);
   else hipLaunchKernelGGL(k_step, dim3(grid), dim3(WAVE), lds_bytes, st, a);
 }
 void launch_reset_queue(int* q, hipStream_t st) { hipLaunchKernelGGL(k_reset_queue, dim3(1), dim3(64), 0, st, q); }
@@ -1769,5 +1829,6 @@ void launch_masked_copy(float* dst, const float* src, const uint8_t* mask, int S
 }
 const void* step_kernel_ptr() { return reinterpret_cast<const void*>(&k_step); }
 const void* step_rec_kernel_ptr() { return reinterpret_cast<const void*>(&k_step_rec); }
+const void* step_frc_kernel_ptr() { return reinterpret_cast<const void*>(&k_step_frc); }
 
 }  // namespace msk

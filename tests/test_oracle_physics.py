@@ -305,3 +305,32 @@ def test_fp32_evaluation_close_to_fp64():
     x = b.state0.astype(np.float64)
     d = np.abs(o.step(x, np.zeros((1, 16))) - o.step_f32(x, np.zeros((1, 16))))
     assert d.max() < 1e-5 and d.max() > 0.0
+
+
+@pytest.mark.parametrize("mu", [0.0, 0.5])
+def test_robot_contact_force_is_the_momentum_change(mu):
+    """Contact-force output: with no gravity and no other contact, the force
+    the robot exerts on a free body, times h and summed over the substeps,
+    equals the body's momentum change; frictionless, it equals the robot's
+    normal-force output."""
+    mb = sg.model_builder()
+    b0 = mb.body(-1, sg.JT_REVOLUTE, (0, 0, 1), (0, 0, 0), 2.0, (0.25, 0, 0), (0.01, 0.05, 0.05))
+    mb.segment(b0, (0.5, 0, 0), (0.5, 0, 0), 0.05, 1)
+    qd = np.zeros(16)
+    qd[0] = 2.0
+    ball = sg.sphere_object(0.1, 0.7, (0.5, 0.149, 0.01))
+    b = sg.custom_batch([mb.arrays()], [dict(qd=qd, free=[ball])], h=0.004, n_sub=5, pgs_iters=8, mu=mu,
+                        gravity=(0.0, 0.0, 0.0))
+    o = oracle.Oracle(b)
+    x0 = b.state0.astype(np.float64)
+    x1, d = o.step(x0, np.zeros((1, 16)), debug=True)
+    f0 = sg.split_state(x0, 1, b.n_free, b.n_aux)["free"][0]
+    f1 = sg.split_state(x1, 1, b.n_free, b.n_aux)["free"][0]
+    m = float(b.free_mass[0])
+    dp = m * (f1[8:11] - f0[8:11])
+    F = d["robot_body_force"][0]
+    assert d["n_contacts"][0].min() >= 1
+    assert np.linalg.norm(dp) > 1e-3
+    np.testing.assert_allclose(F * b.h, dp, rtol=1e-9, atol=1e-12)
+    if mu == 0.0:
+        assert abs(np.linalg.norm(F) - d["robot_force"][0]) <= 1e-9 * d["robot_force"][0]
