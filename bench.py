@@ -246,7 +246,7 @@ def main():
     src_hash = kernel_source_hash()
     traffic = load_traffic(b.name, S, src_hash, flags, ms.MS_SCHED_GRAPH)
     out = {
-        "metric": "physics env-steps/sec at 4096 scenes (fwd)",
+        "metric": f"physics env-steps/sec at {S} scenes (fwd)",
         "value": round(value, 1),
         "unit": "env-steps/s",
         "n_gpus": 1,
@@ -258,8 +258,8 @@ def main():
         "vs_baseline": None,
         "dtype": "f32",
         "data": "synthetic",
-        "config": {"workload": f"{b.name}: {S} Fetch-like scenes, free objects U{{2..32}}, furniture boxes "
-                               f"U{{32..256}}, h={b.h:g} s x {b.n_sub} substeps, {b.pgs_iters} PGS sweeps",
+        "config": {"workload": f"{b.name}: {S} scenes, {b.n_free} free objects, {int(b.static_off[-1])} furniture "
+                               f"boxes, h={b.h:g} s x {b.n_sub} substeps, {b.pgs_iters} PGS sweeps",
                    "scenes": S, "substeps": b.n_sub, "schedule_flags": int(flags)},
         "roofline": {"bound": "alu", "achieved": round(achieved_tflops, 4), "peak": FP32_VECTOR_PEAK_TFLOPS,
                      "unit": "TFLOP/s", "frac": round(achieved_tflops / FP32_VECTOR_PEAK_TFLOPS, 6),

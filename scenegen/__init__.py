@@ -116,6 +116,7 @@ class SceneBatch:
     ctrl_sigma: float = 2.0
     ctrl_rest: np.ndarray | None = None   # f32[M,16]
     ctrl_block: int = 10
+    ctrl_clip: float = 0.3
     notes: str = ""
 
     @property
@@ -145,6 +146,19 @@ class SceneBatch:
             if self.ctrl_kind == "torque_normal":
                 g = _rng(self.seed, self.cfg_id, s, step)
                 out[r, :nb] = f32(g.normal(0.0, self.ctrl_sigma, nb))
+            elif self.ctrl_kind == "random_actions":
+                # fresh every control step: joint targets rest + U[-a, a], base
+                # velocity targets U[-a, a], fingers within their stroke
+                g = _rng(self.seed, self.cfg_id, s, 2_000_000 + step)
+                rest = self.ctrl_rest[m]
+                a = self.ctrl_clip
+                u = np.zeros(NDOF)
+                for j in range(nb):
+                    u[j] = g.uniform(-a, a) + (0.0 if self.model_veldof[m, j] else rest[j])
+                if nb == 15:
+                    u[13] = g.uniform(0.0, 0.05)
+                    u[14] = g.uniform(0.0, 0.05)
+                out[r] = f32(u)
             elif self.ctrl_kind == "pd_targets":
                 g = _rng(self.seed, self.cfg_id, s, 1_000_000 + step // self.ctrl_block)
                 rest = self.ctrl_rest[m]
@@ -736,7 +750,20 @@ def config5(seed=BASE_SEED, n_scenes=16384):
     return _fetch_batch("cfg5_articulated", 5, seed, n_scenes, lambda g: 4, lambda g: 64, params, aux_fn=aux_fn)
 
 
-CONFIGS = {1: config1, 2: config2, 3: config3, 4: config4, 5: config5}
+def config6(seed=BASE_SEED, n_scenes=1024):
+    """Second physics regime: the config-2 scene at 120 Hz simulation under
+    30 Hz control (4 substeps of h = 1/120 s), 300 control steps of random
+    actions clipped to [-0.3, 0.3] (joint targets about the rest pose, base
+    velocity targets)."""
+    params = dict(h=1.0 / 120.0, n_sub=4, pgs_iters=10, control_mode=CTRL_PD, contact_cap=64, n_steps=300,
+                  robot_contact_cap=24, **_PARAM_DEFAULTS)
+    b = _fetch_batch("cfg6_random_actions", 6, seed, n_scenes, lambda g: 8, lambda g: 64, params)
+    b.ctrl_kind = "random_actions"
+    b.ctrl_clip = 0.3
+    return b
+
+
+CONFIGS = {1: config1, 2: config2, 3: config3, 4: config4, 5: config5, 6: config6}
 
 
 def make(cfg: int, n_scenes=None, seed=BASE_SEED, **kw):

@@ -60,6 +60,7 @@ CASES = [
     ("cfg3", lambda: sg.make(3, 32), [0, 5, 20]),
     ("cfg4", lambda: sg.make(4, 16), [0, 10, 30]),
     ("cfg5", lambda: sg.make(5, 48), [0, 5, 15]),
+    ("cfg6", lambda: sg.make(6, 32), [0, 10, 40]),
 ]
 
 
