@@ -55,7 +55,21 @@ enum {
   MS_E_UNSUPPORTED = -6  /* device or configuration not supported (e.g. not gfx950) */
 };
 
-enum { MS_CTRL_TORQUE = 0, MS_CTRL_PD = 1, MS_CTRL_TORQUE_HOLD = 2 };
+/* control modes: joint torques; PD targets (position, or velocity for base
+ * DoFs); torques added to a PD hold of scene_hold; normalized actions in
+ * [-1, 1] mapped per DoF to PD targets once per control step (joint delta
+ * position for arm, torso and head, base linear and angular velocity,
+ * gripper opening: the action space of Sec. 4.1, see model_act_kind) */
+enum { MS_CTRL_TORQUE = 0, MS_CTRL_PD = 1, MS_CTRL_TORQUE_HOLD = 2, MS_CTRL_ACTIONS = 3 };
+/* normalized-action channel of a DoF (a = the action clipped to [-1, 1],
+ * q = the state at the control step's start, s = model_act_scale) */
+enum {
+  MS_ACT_DELTA = 0,       /* position target q + a s */
+  MS_ACT_BASE_FWD_X = 1,  /* velocity target a s cos(yaw) (yaw: the MS_ACT_BASE_YAW DoF's position) */
+  MS_ACT_BASE_FWD_Y = 2,  /* velocity target a_x s sin(yaw) (a_x: the MS_ACT_BASE_FWD_X DoF's action) */
+  MS_ACT_BASE_YAW = 3,    /* velocity target a s */
+  MS_ACT_ABSOLUTE = 4     /* position target (a + 1) / 2 s */
+};
 
 /* per-scene status bits (ms_scene_status) */
 enum {
@@ -110,6 +124,8 @@ typedef struct {
   const int32_t* model_veldof;    /* [M][16] 1: the PD target is a velocity (planar base) */
   const float* model_armature;    /* [M][16] rotor inertia */
   const float* model_damping;     /* [M][16] viscous joint damping */
+  const int32_t* model_act_kind;  /* [M][16] MS_ACT_* channel (read by MS_CTRL_ACTIONS only; may be null) */
+  const float* model_act_scale;   /* [M][16] its scale (may be null with model_act_kind) */
   const int32_t* model_nsph;      /* [M] collision spheres, <= 128 */
   const int32_t* model_sph_body;  /* [M][128] body of each sphere (sorted by body) */
   const float* model_sph;         /* [M][128][4] centre in the body frame, radius */

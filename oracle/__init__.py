@@ -43,7 +43,7 @@ class OrScene(C.Structure):
         (n, C.c_void_p) for n in [
             "model_nb", "model_parent", "model_jtype", "model_axis", "model_xt_rot", "model_xt_pos",
             "model_mass", "model_com", "model_inertia", "model_kp", "model_kd", "model_veldof", "model_armature",
-            "model_damping", "model_nsph",
+            "model_damping", "model_act_kind", "model_act_scale", "model_nsph",
             "model_sph_body", "model_sph", "model_sph_flags", "scene_model", "free_off", "static_off",
             "plane_off", "aux_off", "scene_hold", "free_type", "free_size", "free_mass", "free_inertia",
             "static_box", "plane", "aux_type", "aux_rot", "aux_pos", "aux_axis", "aux_box", "aux_mass",
@@ -104,7 +104,7 @@ class Oracle:
 
     _ARRS = ["model_nb", "model_parent", "model_jtype", "model_axis", "model_xt_rot", "model_xt_pos",
              "model_mass", "model_com", "model_inertia", "model_kp", "model_kd", "model_veldof", "model_armature",
-            "model_damping", "model_nsph",
+            "model_damping", "model_act_kind", "model_act_scale", "model_nsph",
              "model_sph_body", "model_sph", "model_sph_flags", "scene_model", "free_off", "static_off",
              "plane_off", "aux_off", "scene_hold", "free_type", "free_size", "free_mass", "free_inertia",
              "static_box", "plane", "aux_type", "aux_rot", "aux_pos", "aux_axis", "aux_box", "aux_mass",

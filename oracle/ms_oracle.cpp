@@ -183,6 +183,8 @@ struct ArtModel {
   int parent[ND], jtype[ND], veldof[ND];
   double axis[ND][3], xtR[ND][9], xtp[ND][3], mass[ND], com[ND][3], Ic[ND][9], kp[ND], kd[ND];
   double armature[ND], damping[ND];
+  int act_kind[ND];
+  double act_scale[ND];
 };
 
 void load_robot(const or_scene* sc, int m, ArtModel& a) {
@@ -208,6 +210,8 @@ void load_robot(const or_scene* sc, int m, ArtModel& a) {
     a.kd[i] = sc->model_kd[k];
     a.armature[i] = sc->model_armature[k];
     a.damping[i] = sc->model_damping[k];
+    a.act_kind[i] = sc->model_act_kind ? sc->model_act_kind[k] : 0;
+    a.act_scale[i] = sc->model_act_scale ? sc->model_act_scale[k] : 0.0;
   }
 }
 
@@ -233,6 +237,8 @@ void load_aux(const or_scene* sc, int x, ArtModel& a, double box[6], double lim[
   a.kd[0] = 0.0;
   a.armature[0] = 0.0;
   a.damping[0] = 0.0;
+  a.act_kind[0] = 0;
+  a.act_scale[0] = 0.0;
   for (int t = 0; t < 6; ++t) box[t] = sc->aux_box[x * 6 + t];
   lim[0] = sc->aux_limit[x * 2 + 0];
   lim[1] = sc->aux_limit[x * 2 + 1];
@@ -979,6 +985,47 @@ template <class T> void substep(const SceneC& c, const or_params& pr, StateS<T>&
   }
 }
 
+// Normalized actions in [-1, 1] to PD targets, once per control step from the
+// state at its start (the action space of Sec. 4.1: joint delta position for
+// arm, torso and head, base linear and angular velocity, gripper opening).
+template <class T> T clip_unit(const T& a) { return val(a) > 1.0 ? T(1.0) : (val(a) < -1.0 ? T(-1.0) : a); }
+template <class T> void actions_to_targets(const ArtModel& m, const T* q, const T* a, T* tgt) {
+  int jx = -1, jyaw = -1;
+  for (int j = 0; j < m.nb; ++j) {
+    if (m.act_kind[j] == 1) jx = j;
+    if (m.act_kind[j] == 3) jyaw = j;
+  }
+  for (int j = 0; j < ND; ++j) tgt[j] = T(0.0);
+  for (int j = 0; j < m.nb; ++j) {
+    const double sc = m.act_scale[j];
+    const T aj = clip_unit(a[j]);
+    switch (m.act_kind[j]) {
+      case 0: tgt[j] = q[j] + aj * sc; break;
+      case 1: tgt[j] = jyaw >= 0 ? aj * sc * Cos(q[jyaw]) : aj * sc; break;
+      case 2: {
+        const T ax = jx >= 0 ? clip_unit(a[jx]) : T(0.0);
+        tgt[j] = jyaw >= 0 ? ax * sc * Sin(q[jyaw]) : T(0.0);
+        break;
+      }
+      case 3: tgt[j] = aj * sc; break;
+      default: tgt[j] = (aj + 1.0) * 0.5 * sc; break;
+    }
+  }
+}
+// One control step of one scene: n_sub substeps under zero-order hold.
+template <class T> void control_step(const SceneC& c, const or_params& pr, StateS<T>& st, const T* us,
+                                     uint32_t& status, or_debug* dbg, int s) {
+  const T* uu = us;
+  T tgt[ND];
+  or_params p = pr;
+  if (pr.control_mode == 3) {
+    actions_to_targets(*c.robot, st.q, us, tgt);
+    uu = tgt;
+    p.control_mode = 1;
+  }
+  for (int k = 0; k < pr.n_sub; ++k) substep<T>(c, p, st, uu, k, status, dbg, s, pr.n_sub);
+}
+
 // --------------------------------------------------------- state packing
 struct Layout {
   int S, NF, NA;
@@ -1104,7 +1151,7 @@ int or_step(const or_scene* sc, const or_params* pr, const double* x_in, const d
     gather(sc, L, s, xin.data(), st, [](size_t, double v) { return v; });
     uint32_t status = 0;
     const double* us = u + (size_t)s * ND;
-    for (int k = 0; k < pr->n_sub; ++k) substep<double>(c, *pr, st, us, k, status, dbg, s, pr->n_sub);
+    control_step<double>(c, *pr, st, us, status, dbg, s);
     std::vector<double> vals;
     scatter(sc, L, s, st, [&](size_t i, double v) { x_out[i] = v; vals.push_back(v); });
     if (!finite_state(vals)) status |= 1u;
@@ -1130,7 +1177,7 @@ int or_step_f32(const or_scene* sc, const or_params* pr, const double* x_in, con
     float us[ND];
     for (int j = 0; j < ND; ++j) us[j] = (float)u[(size_t)s * ND + j];
     uint32_t status = 0;
-    for (int k = 0; k < pr->n_sub; ++k) substep<float>(c, *pr, st, us, k, status, nullptr, s, pr->n_sub);
+    control_step<float>(c, *pr, st, us, status, nullptr, s);
     scatter(sc, L, s, st, [&](size_t i, float v) { x_out[i] = v; });
   });
   return 0;
@@ -1161,7 +1208,7 @@ int or_vjp(const or_scene* sc, const or_params* pr, const double* x_in, const do
       u_idx[j] = us[j].i;
     }
     uint32_t status = 0;
-    for (int k = 0; k < pr->n_sub; ++k) substep<adouble>(c, *pr, st, us, k, status, nullptr, s, pr->n_sub);
+    control_step<adouble>(c, *pr, st, us, status, nullptr, s);
     tape.adj.assign(tape.nodes.size(), 0.0);
     scatter(sc, L, s, st, [&](size_t i, const adouble& v) {
       if (v.i >= 0) tape.adj[(size_t)v.i] += gx_out[i];
@@ -1188,7 +1235,7 @@ int or_jvp(const or_scene* sc, const or_params* pr, const double* x_in, const do
     dual us[ND];
     for (int j = 0; j < ND; ++j) us[j] = dual(u[(size_t)s * ND + j], du[(size_t)s * ND + j]);
     uint32_t status = 0;
-    for (int k = 0; k < pr->n_sub; ++k) substep<dual>(c, *pr, st, us, k, status, nullptr, s, pr->n_sub);
+    control_step<dual>(c, *pr, st, us, status, nullptr, s);
     scatter(sc, L, s, st, [&](size_t i, const dual& v) { dx_out[i] = v.d; });
   });
   return 0;
@@ -1207,7 +1254,7 @@ int or_flops(const or_scene* sc, const or_params* pr, const double* x_in, const 
     cdouble us[ND];
     for (int j = 0; j < ND; ++j) us[j] = cdouble(u[(size_t)s * ND + j]);
     uint32_t status = 0;
-    for (int k = 0; k < pr->n_sub; ++k) substep<cdouble>(c, *pr, st, us, k, status, nullptr, s, pr->n_sub);
+    control_step<cdouble>(c, *pr, st, us, status, nullptr, s);
     flops[s] = (double)g_flops;
   });
   return 0;

@@ -47,6 +47,8 @@ typedef struct {
   const int32_t* model_veldof;    // [M][16]
   const float* model_armature;    // [M][16]
   const float* model_damping;     // [M][16]
+  const int32_t* model_act_kind;  // [M][16] normalized-action channel
+  const float* model_act_scale;   // [M][16]
   const int32_t* model_nsph;      // [M]
   const int32_t* model_sph_body;  // [M][128]
   const float* model_sph;         // [M][128][4]

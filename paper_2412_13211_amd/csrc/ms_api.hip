@@ -115,9 +115,24 @@ int persistent_grid(const ms_batch* b, size_t lds) {
   return std::min(b->cnt.S, per_cu * b->n_cu);
 }
 
+// MS_CTRL_ACTIONS: the PD targets of the control step (in scratch), computed
+// from the actions and the step's start state; other modes pass u through.
+const float* control_targets(ms_batch* b, const void* x_in, const float* u, hipStream_t st) {
+  if (b->desc.control_mode != MS_CTRL_ACTIONS) return u;
+  float* tgt = reinterpret_cast<float*>(b->scratch + b->sl.act);
+  launch_actions(reinterpret_cast<const DModel*>(b->params + b->pl.models),
+                 reinterpret_cast<const DScene*>(b->params + b->pl.scenes), static_cast<const float*>(x_in), u, tgt,
+                 b->cnt.S, st);
+  return tgt;
+}
+int step_mode(const ms_batch* b) { return b->desc.control_mode == MS_CTRL_ACTIONS ? MS_CTRL_PD : b->desc.control_mode; }
+
 // Enqueue one control step with the current schedule (no graph).
 ms_status enqueue_step(ms_batch* b, const void* x_in, const float* u, void* x_out, hipStream_t st) {
+  u = control_targets(b, x_in, u, st);
+  HIP_TRY(hipGetLastError());
   KArgs a = make_args(b, x_in, u, x_out);
+  a.mode = step_mode(b);
   size_t lds = lds_bytes_of(a);
   if (lds > b->max_lds)
     return fail(MS_E_UNSUPPORTED, "scene working set needs %zu B of LDS (device limit %zu B); lower contact_cap "
@@ -328,6 +343,7 @@ ms_status ms_step(ms_batch* b, const void* x_in, const float* u, void* x_out, vo
 // batch's persistent / staging / culling choices), no state output.
 ms_status enqueue_record(ms_batch* b, const void* x_in, const float* u, float* rec, hipStream_t st) {
   KArgs a = make_args(b, x_in, u, nullptr);
+  a.mode = step_mode(b);
   a.debug = nullptr;
   a.phase_cycles = nullptr;
   a.frc_robot = nullptr;
@@ -372,19 +388,22 @@ ms_status ms_step_backward(ms_batch* b, const void* x_in, const float* u, const 
   a.planes = reinterpret_cast<const float4*>(b->params + b->pl.planes);
   a.aux = reinterpret_cast<const DAux*>(b->params + b->pl.aux);
   a.order = reinterpret_cast<const int*>(b->params + b->pl.order);
+  hipStream_t st = static_cast<hipStream_t>(hip_stream);
+  const bool actions = d->control_mode == MS_CTRL_ACTIONS;
+  const float* ut = control_targets(b, x_in, u, st);
+  HIP_TRY(hipGetLastError());
   a.x = static_cast<const float*>(x_in);
-  a.u = u;
+  a.u = ut;
   a.gxo = static_cast<const float*>(gx_out);
   a.gxi = static_cast<float*>(gx_in);
-  a.gu = gu;
+  a.gu = actions ? reinterpret_cast<float*>(b->scratch + b->sl.actb) : gu;
   a.status = reinterpret_cast<uint32_t*>(b->scratch + b->sl.status);
   a.ws = reinterpret_cast<float*>(b->tape);
   a.S = c.S;
   a.NF = c.NF;
   a.stride = bwd_stride(c.S);
   a.pr = msa::Prm{d->h, d->mu, d->baumgarte, d->margin, {d->gravity[0], d->gravity[1], d->gravity[2]},
-                  d->pgs_iters, d->control_mode, d->contact_cap, std::max(d->robot_contact_cap, 1), d->n_substeps};
-  hipStream_t st = static_cast<hipStream_t>(hip_stream);
+                  d->pgs_iters, step_mode(b), d->contact_cap, std::max(d->robot_contact_cap, 1), d->n_substeps};
   const msa::WS ww = bwd_ws_wave(d, c);
   const size_t lds = (size_t)ww.total * sizeof(float);
   if ((b->sched.flags & MS_SCHED_BWD_REFERENCE) || lds > b->max_lds) {
@@ -392,13 +411,15 @@ ms_status ms_step_backward(ms_batch* b, const void* x_in, const float* u, const 
     launch_step_bwd(a, st);
   } else {
     float* rec = reinterpret_cast<float*>(b->tape);
-    ms_status rs = enqueue_record(b, x_in, u, rec, st);
+    ms_status rs = enqueue_record(b, x_in, ut, rec, st);
     if (rs != MS_OK) return rs;
     a.rec = rec;
     a.RL = bwd_rec(d, c);
     a.w = ww;
     launch_step_bwd_wave(a, lds, st);
   }
+  if (actions)
+    launch_actions_bwd(a.models, a.scenes, a.x, u, a.gu, gu, a.gxi, c.S, st);
   HIP_TRY(hipGetLastError());
   return MS_OK;
 }

@@ -33,6 +33,10 @@ struct DModel {
   float com[ND][3];
   float Ic[ND][6];      // xx yy zz xy xz yz about the COM, body axes
   float kp[ND], kd[ND], arm[ND], damp[ND];
+  int act_kind[ND];     // normalized-action channel of each DoF
+  float act_scale[ND];
+  int act_x, act_yaw;   // DoF of the base forward action and of the base heading (-1: none)
+  int pad2, pad3;
   float4 sph[SPH];      // centre (body frame), radius
   int sph_body[SPH];
   int sph_flags[SPH];
@@ -162,6 +166,10 @@ struct KArgs {
 
 void launch_step(const KArgs& a, int grid, size_t lds_bytes, hipStream_t st);
 void launch_reset_queue(int* q, hipStream_t st);
+void launch_actions(const DModel* models, const DScene* scenes, const float* x, const float* a, float* tgt, int S,
+                    hipStream_t st);
+void launch_actions_bwd(const DModel* models, const DScene* scenes, const float* x, const float* a,
+                        const float* gtgt, float* ga, float* gx, int S, hipStream_t st);
 void launch_masked_copy(float* dst, const float* src, const uint8_t* mask, int S, int NF, int NA,
                         const int* free_off, const int* aux_off, hipStream_t st);
 const void* step_kernel_ptr();

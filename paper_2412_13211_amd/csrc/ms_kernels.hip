@@ -1800,6 +1800,84 @@ __global__ void k_reset_queue(int* q) {
   if (threadIdx.x == 0) q[0] = 0;
 }
 
+// Normalized actions (clipped to [-1, 1]) to PD targets from the state at the
+// control step's start: joint delta position, base linear velocity along the
+// heading (world x and y shares), base angular velocity, gripper opening.
+// One thread per (scene, DoF).
+__device__ __forceinline__ float clip_unit(float a) { return fminf(fmaxf(a, -1.f), 1.f); }
+__global__ void k_actions(const DModel* models, const DScene* scenes, const float* x, const float* a, float* tgt,
+                          int S) {
+  const int s = blockIdx.x * 4 + (threadIdx.x >> 4), j = threadIdx.x & 15;
+  if (s >= S) return;
+  const DModel& M = models[scenes[s].model];
+  const float* q = x + (size_t)s * ND;
+  const float* as = a + (size_t)s * ND;
+  float t = 0.f;
+  if (j < M.nb) {
+    const float sc = M.act_scale[j], aj = clip_unit(as[j]);
+    const float yaw = M.act_yaw >= 0 ? q[M.act_yaw] : 0.f;
+    switch (M.act_kind[j]) {
+      case 0: t = q[j] + aj * sc; break;
+      case 1: t = M.act_yaw >= 0 ? aj * sc * cosf(yaw) : aj * sc; break;
+      case 2: t = (M.act_x >= 0 && M.act_yaw >= 0) ? clip_unit(as[M.act_x]) * sc * sinf(yaw) : 0.f; break;
+      case 3: t = aj * sc; break;
+      default: t = (aj + 1.f) * 0.5f * sc; break;
+    }
+  }
+  tgt[(size_t)s * ND + j] = t;
+}
+// Reverse of k_actions: given the adjoint of the targets, writes the adjoint of
+// the actions and adds the targets' dependence on the start state into the
+// state adjoint's joint positions.  One thread per scene.
+__global__ void k_actions_bwd(const DModel* models, const DScene* scenes, const float* x, const float* a,
+                              const float* gtgt, float* ga, float* gx, int S) {
+  const int s = blockIdx.x * blockDim.x + threadIdx.x;
+  if (s >= S) return;
+  const DModel& M = models[scenes[s].model];
+  const float* q = x + (size_t)s * ND;
+  const float* as = a + (size_t)s * ND;
+  const float* gt = gtgt + (size_t)s * ND;
+  float gav[ND], gq[ND];
+  for (int j = 0; j < ND; ++j) gav[j] = gq[j] = 0.f;
+  const float yaw = M.act_yaw >= 0 ? q[M.act_yaw] : 0.f;
+  const float cy = cosf(yaw), sy = sinf(yaw);
+  for (int j = 0; j < M.nb; ++j) {
+    const float sc = M.act_scale[j], g = gt[j];
+    const bool in = as[j] >= -1.f && as[j] <= 1.f;  // the clip's slope (1 on the boundary)
+    switch (M.act_kind[j]) {
+      case 0:
+        gq[j] += g;
+        if (in) gav[j] += g * sc;
+        break;
+      case 1:
+        if (M.act_yaw >= 0) {
+          if (in) gav[j] += g * sc * cy;
+          gq[M.act_yaw] -= g * clip_unit(as[j]) * sc * sy;
+        } else if (in) {
+          gav[j] += g * sc;
+        }
+        break;
+      case 2:
+        if (M.act_x >= 0 && M.act_yaw >= 0) {
+          const float ax = as[M.act_x];
+          if (ax >= -1.f && ax <= 1.f) gav[M.act_x] += g * sc * sy;
+          gq[M.act_yaw] += g * clip_unit(ax) * sc * cy;
+        }
+        break;
+      case 3:
+        if (in) gav[j] += g * sc;
+        break;
+      default:
+        if (in) gav[j] += g * 0.5f * sc;
+        break;
+    }
+  }
+  for (int j = 0; j < ND; ++j) {
+    ga[(size_t)s * ND + j] = gav[j];
+    gx[(size_t)s * ND + j] += gq[j];
+  }
+}
+
 // dst[scene] = src[scene] where mask[scene] != 0; grid over scenes
 __global__ void k_masked_copy(float* dst, const float* src, const uint8_t* mask, int S, int NF, int NA,
                               const int* free_off, const int* aux_off) {
@@ -1822,6 +1900,16 @@ void launch_step(const KArgs& a, int grid, size_t lds_bytes, hipStream_t st) {
   else hipLaunchKernelGGL(k_step, dim3(grid), dim3(WAVE), lds_bytes, st, a);
 }
 void launch_reset_queue(int* q, hipStream_t st) { hipLaunchKernelGGL(k_reset_queue, dim3(1), dim3(64), 0, st, q); }
+void launch_actions(const DModel* models, const DScene* scenes, const float* x, const float* a, float* tgt, int S,
+                    hipStream_t st) {
+  if (S <= 0) return;
+  hipLaunchKernelGGL(k_actions, dim3((S + 3) / 4), dim3(64), 0, st, models, scenes, x, a, tgt, S);
+}
+void launch_actions_bwd(const DModel* models, const DScene* scenes, const float* x, const float* a,
+                        const float* gtgt, float* ga, float* gx, int S, hipStream_t st) {
+  if (S <= 0) return;
+  hipLaunchKernelGGL(k_actions_bwd, dim3((S + 63) / 64), dim3(64), 0, st, models, scenes, x, a, gtgt, ga, gx, S);
+}
 void launch_masked_copy(float* dst, const float* src, const uint8_t* mask, int S, int NF, int NA,
                         const int* free_off, const int* aux_off, hipStream_t st) {
   if (S <= 0) return;

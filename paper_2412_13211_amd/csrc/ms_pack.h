@@ -42,7 +42,9 @@ inline ms_status validate(const ms_batch_desc* d, const ms_scene_desc* sc, Count
   if (d->n_scenes <= 0) return fail(MS_E_INVALID, "n_scenes must be positive (got %d)", d->n_scenes);
   if (d->n_substeps <= 0 || d->n_substeps > 1000) return fail(MS_E_INVALID, "n_substeps out of range");
   if (d->pgs_iters < 0 || d->pgs_iters > 1000) return fail(MS_E_INVALID, "pgs_iters out of range");
-  if (d->control_mode < 0 || d->control_mode > 2) return fail(MS_E_INVALID, "unknown control_mode %d", d->control_mode);
+  if (d->control_mode < 0 || d->control_mode > 3) return fail(MS_E_INVALID, "unknown control_mode %d", d->control_mode);
+  if (d->control_mode == MS_CTRL_ACTIONS && sc && (!sc->model_act_kind || !sc->model_act_scale))
+    return fail(MS_E_INVALID, "MS_CTRL_ACTIONS needs model_act_kind and model_act_scale");
   if (d->contact_cap <= 0 || d->contact_cap > 4096) return fail(MS_E_INVALID, "contact_cap out of range (1..4096)");
   if (d->robot_contact_cap < 0 || d->robot_contact_cap > d->contact_cap)
     return fail(MS_E_INVALID, "robot_contact_cap out of range (0..contact_cap)");
@@ -68,6 +70,11 @@ inline ms_status validate(const ms_batch_desc* d, const ms_scene_desc* sc, Count
       int jt = sc->model_jtype[m * ND + i];
       if (jt != 0 && jt != 1) return fail(MS_E_INVALID, "model %d body %d: joint type %d", m, i, jt);
     }
+    if (sc->model_act_kind)
+      for (int i = 0; i < nb; ++i) {
+        int ak = sc->model_act_kind[m * ND + i];
+        if (ak < 0 || ak > 4) return fail(MS_E_INVALID, "model %d DoF %d: action channel %d", m, i, ak);
+      }
     int prev = 0;
     for (int k = 0; k < ns; ++k) {
       int b = sc->model_sph_body[m * SPH + k];
@@ -143,7 +150,7 @@ inline ParamLayout param_layout(const Counts& c) {
 }
 
 struct ScratchLayout {
-  size_t queue, status, debug, cycles, total;
+  size_t queue, status, debug, cycles, act, actb, total;
 };
 inline ScratchLayout scratch_layout(const Counts& c, int n_sub) {
   ScratchLayout s;
@@ -152,6 +159,8 @@ inline ScratchLayout scratch_layout(const Counts& c, int n_sub) {
   s.status = o; o = align256(o + sizeof(uint32_t) * c.S);
   s.debug = o; o = align256(o + sizeof(uint32_t) * 4 * (size_t)c.S * n_sub);
   s.cycles = o; o = align256(o + sizeof(unsigned long long) * 8 * (size_t)c.S);
+  s.act = o; o = align256(o + sizeof(float) * 16 * (size_t)c.S);
+  s.actb = o; o = align256(o + sizeof(float) * 16 * (size_t)c.S);
   s.total = o;
   return s;
 }
@@ -197,6 +206,13 @@ inline void pack_params(const ms_scene_desc* sc, const Counts& c, const ParamLay
       M.kd[i] = sc->model_kd[k];
       M.arm[i] = sc->model_armature[k];
       M.damp[i] = sc->model_damping[k];
+      M.act_kind[i] = sc->model_act_kind ? sc->model_act_kind[k] : 0;
+      M.act_scale[i] = sc->model_act_scale ? sc->model_act_scale[k] : 0.f;
+    }
+    M.act_x = M.act_yaw = -1;
+    for (int i = 0; i < M.nb; ++i) {
+      if (M.act_kind[i] == MS_ACT_BASE_FWD_X) M.act_x = i;
+      if (M.act_kind[i] == MS_ACT_BASE_YAW) M.act_yaw = i;
     }
     for (int k = 0; k < SPH; ++k) {
       const float* sp = sc->model_sph + (m * SPH + k) * 4;

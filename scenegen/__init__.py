@@ -37,6 +37,15 @@ BASE_SEED = 20241217
 CTRL_TORQUE = 0    # controls are joint torques / forces
 CTRL_PD = 1        # controls are PD targets (position, or velocity for base DoFs)
 CTRL_TORQUE_HOLD = 2  # controls are torques added to an implicit PD hold
+CTRL_ACTIONS = 3   # controls are normalized actions in [-1, 1] mapped to PD targets
+
+# normalized-action channel of a DoF (target computed once per control step
+# from the action a, clipped to [-1, 1], and the state q at the step start)
+ACT_DELTA = 0         # position target q + a * scale (joint delta position)
+ACT_BASE_FWD_X = 1    # velocity target a_fwd * scale * cos(yaw) (base linear velocity, world x)
+ACT_BASE_FWD_Y = 2    # velocity target a_fwd * scale * sin(yaw) (a_fwd: the ACT_BASE_FWD_X action)
+ACT_BASE_YAW = 3      # velocity target a * scale (base angular velocity)
+ACT_ABSOLUTE = 4      # position target (a + 1) / 2 * scale (gripper opening)
 
 JT_REVOLUTE = 0
 JT_PRISMATIC = 1
@@ -83,6 +92,8 @@ class SceneBatch:
     model_veldof: np.ndarray    # int32[M,16]   1: PD target is a velocity
     model_armature: np.ndarray  # f32[M,16]     rotor inertia added to the mass-matrix diagonal
     model_damping: np.ndarray   # f32[M,16]     viscous joint damping (integrated implicitly)
+    model_act_kind: np.ndarray  # int32[M,16]   normalized-action channel kind (ACT_*)
+    model_act_scale: np.ndarray  # f32[M,16]    its scale (rad, m, m/s or rad/s per unit action)
     model_nsph: np.ndarray      # int32[M]
     model_sph_body: np.ndarray  # int32[M,SMAX]
     model_sph: np.ndarray       # f32[M,SMAX,4] local centre + radius
@@ -147,18 +158,11 @@ class SceneBatch:
                 g = _rng(self.seed, self.cfg_id, s, step)
                 out[r, :nb] = f32(g.normal(0.0, self.ctrl_sigma, nb))
             elif self.ctrl_kind == "random_actions":
-                # fresh every control step: joint targets rest + U[-a, a], base
-                # velocity targets U[-a, a], fingers within their stroke
+                # normalized actions drawn uniformly from [-1, 1] and clipped
+                # to [-c, c], fresh every control step
                 g = _rng(self.seed, self.cfg_id, s, 2_000_000 + step)
-                rest = self.ctrl_rest[m]
-                a = self.ctrl_clip
-                u = np.zeros(NDOF)
-                for j in range(nb):
-                    u[j] = g.uniform(-a, a) + (0.0 if self.model_veldof[m, j] else rest[j])
-                if nb == 15:
-                    u[13] = g.uniform(0.0, 0.05)
-                    u[14] = g.uniform(0.0, 0.05)
-                out[r] = f32(u)
+                c = self.ctrl_clip
+                out[r, :nb] = f32(np.clip(g.uniform(-1.0, 1.0, nb), -c, c))
             elif self.ctrl_kind == "pd_targets":
                 g = _rng(self.seed, self.cfg_id, s, 1_000_000 + step // self.ctrl_block)
                 rest = self.ctrl_rest[m]
@@ -267,11 +271,12 @@ class _ModelBuilder:
         self.spheres = []
 
     def body(self, parent, jtype, axis, pos, mass, com, inertia_diag, kp=0.0, kd=0.0, veldof=0,
-             rot=(1.0, 0.0, 0.0, 0.0), armature=0.0, damping=0.0):
+             rot=(1.0, 0.0, 0.0, 0.0), armature=0.0, damping=0.0, act=(ACT_DELTA, 0.1)):
+        """``act``: (kind, scale) of the DoF's normalized-action channel (ACT_*)."""
         self.bodies.append(dict(parent=parent, jtype=jtype, axis=np.array(axis, float), pos=np.array(pos, float),
                                 rot=np.array(rot, float), mass=mass, com=np.array(com, float),
                                 inertia=np.array(list(inertia_diag) + [0.0, 0.0, 0.0]), kp=kp, kd=kd, veldof=veldof,
-                                armature=armature, damping=damping))
+                                armature=armature, damping=damping, act=act))
         return len(self.bodies) - 1
 
     def segment(self, body, a, b, r, n, flags=0):
@@ -289,7 +294,8 @@ class _ModelBuilder:
             ("xt_rot", (NDOF, 4), np.float64), ("xt_pos", (NDOF, 3), np.float64), ("mass", NDOF, np.float64),
             ("com", (NDOF, 3), np.float64), ("inertia", (NDOF, 6), np.float64), ("kp", NDOF, np.float64),
             ("kd", NDOF, np.float64), ("veldof", NDOF, np.int32), ("armature", NDOF, np.float64),
-            ("damping", NDOF, np.float64), ("sph_body", SMAX, np.int32),
+            ("damping", NDOF, np.float64), ("act_kind", NDOF, np.int32), ("act_scale", NDOF, np.float64),
+            ("sph_body", SMAX, np.int32),
             ("sph", (SMAX, 4), np.float64), ("sph_flags", SMAX, np.int32)]}
         d["parent"][:] = -1
         d["xt_rot"][:, 0] = 1.0
@@ -308,6 +314,8 @@ class _ModelBuilder:
             d["veldof"][i] = b["veldof"]
             d["armature"][i] = b["armature"]
             d["damping"][i] = b["damping"]
+            d["act_kind"][i] = b["act"][0]
+            d["act_scale"][i] = b["act"][1]
         for k, (body, c, r, fl) in enumerate(self.spheres):
             d["sph_body"][k] = body
             d["sph"][k, :3] = c
@@ -364,10 +372,12 @@ def fetch_like_model(g):
     """
     mb = _ModelBuilder()
     n = lambda: int(g.integers(2, 7))
-    px = mb.body(-1, JT_PRISMATIC, (1, 0, 0), (0, 0, 0), 0.0, (0, 0, 0), (0, 0, 0), kd=2000.0, veldof=1)
-    py = mb.body(px, JT_PRISMATIC, (0, 1, 0), (0, 0, 0), 0.0, (0, 0, 0), (0, 0, 0), kd=2000.0, veldof=1)
+    px = mb.body(-1, JT_PRISMATIC, (1, 0, 0), (0, 0, 0), 0.0, (0, 0, 0), (0, 0, 0), kd=2000.0, veldof=1,
+                 act=(ACT_BASE_FWD_X, 1.0))
+    py = mb.body(px, JT_PRISMATIC, (0, 1, 0), (0, 0, 0), 0.0, (0, 0, 0), (0, 0, 0), kd=2000.0, veldof=1,
+                 act=(ACT_BASE_FWD_Y, 1.0))
     base = mb.body(py, JT_REVOLUTE, (0, 0, 1), (0, 0, 0), 60.0, (0, 0, 0.2),
-                   _box_inertia(60.0, (0.56, 0.56, 0.36)), kd=500.0, veldof=1)
+                   _box_inertia(60.0, (0.56, 0.56, 0.36)), kd=500.0, veldof=1, act=(ACT_BASE_YAW, 1.0))
     torso = mb.body(base, JT_PRISMATIC, (0, 0, 1), (-0.08, 0, 0.37), 10.0, (0, 0, 0.3),
                     _box_inertia(10.0, (0.2, 0.24, 0.6)), kp=5000.0, kd=500.0, armature=0.1)
     hpan = mb.body(torso, JT_REVOLUTE, (0, 0, 1), (0.05, 0, 0.62), 2.0, (0.05, 0, 0.05),
@@ -388,9 +398,9 @@ def fetch_like_model(g):
                        armature=0.02)
         arm.append(prev)
     fl = mb.body(arm[-1], JT_PRISMATIC, (0, 1, 0), (0.16, 0, 0), 0.1, (0.03, 0, 0),
-                 _box_inertia(0.1, (0.06, 0.015, 0.03)), kp=500.0, kd=50.0, armature=0.001)
+                 _box_inertia(0.1, (0.06, 0.015, 0.03)), kp=500.0, kd=50.0, armature=0.001, act=(ACT_ABSOLUTE, 0.05))
     fr = mb.body(arm[-1], JT_PRISMATIC, (0, -1, 0), (0.16, 0, 0), 0.1, (0.03, 0, 0),
-                 _box_inertia(0.1, (0.06, 0.015, 0.03)), kp=500.0, kd=50.0, armature=0.001)
+                 _box_inertia(0.1, (0.06, 0.015, 0.03)), kp=500.0, kd=50.0, armature=0.001, act=(ACT_ABSOLUTE, 0.05))
     # geometric links: (body, segment a, segment b, radius, flags)
     links = [
         (base, (-0.18, 0, 0.2), (0.18, 0, 0.2), 0.2, SPH_SKIP_FLOOR),          # base
@@ -416,7 +426,7 @@ def fetch_like_model(g):
 
 def _stack_models(models):
     keys = ["parent", "jtype", "axis", "xt_rot", "xt_pos", "mass", "com", "inertia", "kp", "kd", "veldof",
-            "armature", "damping", "sph_body", "sph", "sph_flags"]
+            "armature", "damping", "act_kind", "act_scale", "sph_body", "sph", "sph_flags"]
     out = {k: np.stack([m[k] for m in models]) for k in keys}
     out["nb"] = np.array([m["nb"] for m in models], np.int32)
     out["nsph"] = np.array([m["nsph"] for m in models], np.int32)
@@ -581,6 +591,7 @@ def _assemble(name, cfg_id, S, params, models, per_scene, seed, **extra):
         model_mass=f32(mk["mass"]), model_com=f32(mk["com"]), model_inertia=f32(mk["inertia"]),
         model_kp=f32(mk["kp"]), model_kd=f32(mk["kd"]), model_veldof=mk["veldof"].astype(np.int32),
         model_armature=f32(mk["armature"]), model_damping=f32(mk["damping"]),
+        model_act_kind=mk["act_kind"].astype(np.int32), model_act_scale=f32(mk["act_scale"]),
         model_nsph=mk["nsph"], model_sph_body=mk["sph_body"].astype(np.int32), model_sph=f32(mk["sph"]),
         model_sph_flags=mk["sph_flags"].astype(np.int32),
         scene_model=scene_model, free_off=off("free"), static_off=off("static"), plane_off=off("planes"),
@@ -753,9 +764,8 @@ def config5(seed=BASE_SEED, n_scenes=16384):
 def config6(seed=BASE_SEED, n_scenes=1024):
     """Second physics regime: the config-2 scene at 120 Hz simulation under
     30 Hz control (4 substeps of h = 1/120 s), 300 control steps of random
-    actions clipped to [-0.3, 0.3] (joint targets about the rest pose, base
-    velocity targets)."""
-    params = dict(h=1.0 / 120.0, n_sub=4, pgs_iters=10, control_mode=CTRL_PD, contact_cap=64, n_steps=300,
+    normalized actions clipped to [-0.3, 0.3] through the action front-end."""
+    params = dict(h=1.0 / 120.0, n_sub=4, pgs_iters=10, control_mode=CTRL_ACTIONS, contact_cap=64, n_steps=300,
                   robot_contact_cap=24, **_PARAM_DEFAULTS)
     b = _fetch_batch("cfg6_random_actions", 6, seed, n_scenes, lambda g: 8, lambda g: 64, params)
     b.ctrl_kind = "random_actions"

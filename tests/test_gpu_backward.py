@@ -90,7 +90,7 @@ def test_backward_contact_primitives(mu, iters, n_sub):
         assert err <= GRAD_TOL, (s, err)
 
 
-GEN_CASES = [("cfg1", 1, 6, 10), ("cfg2", 2, 8, 5), ("cfg4", 4, 8, 3), ("cfg5", 5, 8, 3)]
+GEN_CASES = [("cfg1", 1, 6, 10), ("cfg2", 2, 8, 5), ("cfg4", 4, 8, 3), ("cfg5", 5, 8, 3), ("cfg6", 6, 8, 6)]
 
 
 @pytest.mark.parametrize("name,cfg,n,steps", GEN_CASES)
