@@ -246,6 +246,24 @@ ms_status ms_set_state(ms_batch* b, void* state_dev, const void* src_dev, const 
  * non-null is MS_E_INVALID.  Drops captured graphs. */
 ms_status ms_set_force_outputs(ms_batch* b, float* robot_force_dev, float* body_force_dev);
 
+/* Per-scene robot resets (the episode initialisation of App. A.1: rest pose
+ * plus clipped Gaussian noise on the arm joints, base position and base
+ * rotation).  For every scene with mask_dev[s] != 0 (mask null: all):
+ * q[s][j] = base_dev[s][j] + clip(noise_dev[s][j], -clip_host[j], clip_host[j])
+ * and qd[s][j] = 0; free bodies and doors / drawers are left as they are.
+ * base_dev, noise_dev: device float32 [S][16] (the noise is drawn by the
+ * caller, e.g. N(0, 0.1) arm and base position, N(0, 0.25) base yaw);
+ * clip_host: host float32 [16].  Stream-ordered. */
+ms_status ms_reset_robots(ms_batch* b, void* state_dev, const uint8_t* mask_dev, const float* base_dev,
+                          const float* noise_dev, const float* clip_host, void* hip_stream);
+
+/* Spawn check for rejection sampling of resets (spawn without collisions,
+ * App. A.2): collide_dev[s] (uint8, device) = 1 where a robot sphere
+ * penetrates (phi < 0) a plane (the base's spheres not the floor), a
+ * furniture box, a door / drawer box or a free body; 0 otherwise.
+ * Stream-ordered. */
+ms_status ms_spawn_check(ms_batch* b, const void* state_dev, uint8_t* collide_dev, void* hip_stream);
+
 /* Synchronise and read the per-scene status words of the last step
  * (bits MS_ST_*) into status_host[S].  Returns MS_E_NUMERIC if any scene
  * has MS_ST_NONFINITE or MS_ST_DEGENERATE set, MS_OK otherwise. */

@@ -81,7 +81,8 @@ def lib():
                            ("or_fk", [vp, C.c_int, vp, vp, vp, vp]),
                            ("or_dynamics", [vp, C.c_int, vp, vp, vp, vp, vp]),
                            ("or_aba", [vp, C.c_int, vp, vp, vp, vp, vp, vp]),
-                           ("or_pair", [C.c_int, vp, C.c_double, vp, vp])]:
+                           ("or_pair", [C.c_int, vp, C.c_double, vp, vp]),
+                           ("or_spawn_check", [vp, vp, vp, C.c_int])]:
             f = getattr(L, name)
             f.argtypes = args
             f.restype = C.c_int
@@ -188,6 +189,14 @@ class Oracle:
             else:
                 xs.append(r)
         return (xs, dbgs) if debug else xs
+
+    def spawn_check(self, x):
+        """Per scene 1 where a robot sphere penetrates another body (phi < 0)."""
+        x = np.ascontiguousarray(x, np.float64)
+        out = np.zeros(self.S, np.int32)
+        if lib().or_spawn_check(C.byref(self.sc), _ptr(x), _ptr(out), self.threads):
+            raise RuntimeError("or_spawn_check failed")
+        return out
 
     def vjp(self, x, u, gx_out):
         x = np.ascontiguousarray(x, np.float64)

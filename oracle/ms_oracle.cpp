@@ -1260,6 +1260,50 @@ int or_flops(const or_scene* sc, const or_params* pr, const double* x_in, const 
   return 0;
 }
 
+int or_spawn_check(const or_scene* sc, const double* x, int32_t* collide, int threads) {
+  if (!sc || !x || !collide) return -1;
+  std::vector<ArtModel> robots = load_models(sc);
+  Layout L = layout_of(sc);
+  parallel_scenes(sc->n_scenes, threads, [&](int s) {
+    SceneC c;
+    load_scene(sc, robots, s, c);
+    StateS<double> st;
+    gather(sc, L, s, x, st, [](size_t, double v) { return v; });
+    Kin<double> rk;
+    fk(*c.robot, st.q, rk, false);
+    const int NA = (int)c.aux.size(), NF = (int)c.fr.size();
+    std::vector<Kin<double>> ak(NA);
+    for (int a = 0; a < NA; ++a) {
+      double qa[1] = {st.aq[a]};
+      fk(c.aux[a], qa, ak[a], false);
+    }
+    bool hit = false;
+    V3<double> n, p;
+    for (const Sphere& sp : c.sph) {
+      V3<double> cw = add(mv(rk.R[sp.body], cv3<double>(sp.c)), rk.p[sp.body]);
+      for (int pl = 0; pl < (int)c.planes.size(); ++pl) {
+        if (pl == 0 && (sp.flags & 1)) continue;
+        hit |= g_plane<double>(cw, sp.r, c.planes[pl].data(), n, p) < 0.0;
+      }
+      for (const auto& bx : c.boxes)
+        hit |= g_box<double>(cw, sp.r, cv3<double>(bx.data()), ident3<double>(), &bx[3], n, p) < 0.0;
+      for (int a = 0; a < NA; ++a) {
+        V3<double> bc = add(mv(ak[a].R[0], cv3<double>(c.aux_box[a].data())), ak[a].p[0]);
+        hit |= g_box<double>(cw, sp.r, bc, ak[a].R[0], &c.aux_box[a][3], n, p) < 0.0;
+      }
+      for (int f = 0; f < NF; ++f) {
+        const FreeC& fc = c.fr[f];
+        if (fc.type == 0)
+          hit |= g_box<double>(cw, sp.r, st.fr[f].x, quat_R(st.fr[f].Q), fc.half, n, p) < 0.0;
+        else
+          hit |= g_sphere<double>(cw, sp.r, st.fr[f].x, fc.half[0], n, p) < 0.0;
+      }
+    }
+    collide[s] = hit ? 1 : 0;
+  });
+  return 0;
+}
+
 int or_fk(const or_scene* sc, int model, const double* q, double* sph_out, double* origin_out, double* rot_out) {
   ArtModel m;
   load_robot(sc, model, m);

@@ -120,6 +120,11 @@ int or_jvp(const or_scene* sc, const or_params* pr, const double* x_in, const do
 int or_flops(const or_scene* sc, const or_params* pr, const double* x_in, const double* u,
              double* flops_per_scene);
 
+// Spawn check of a reset: collide[s] = 1 where a robot sphere penetrates
+// (phi < 0) a plane (the base's spheres not the first plane), a furniture
+// box, a door / drawer box or a free body; brute force over every pair.
+int or_spawn_check(const or_scene* sc, const double* x, int32_t* collide, int threads);
+
 // ---- single-function probes used by the closed-form tests ----
 // Robot model m: world sphere centres [nsph][3] and body origins [nb][3].
 int or_fk(const or_scene* sc, int model, const double* q, double* sph_out, double* origin_out,

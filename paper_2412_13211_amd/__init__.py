@@ -27,7 +27,7 @@ MS_ST_NONFINITE, MS_ST_OVERFLOW, MS_ST_DEGENERATE, MS_ST_ROBOT_OVERFLOW = 1, 2, 
 
 EXPORTS = ["ms_query_sizes", "ms_state_floats", "ms_create_batch", "ms_destroy_batch", "ms_set_schedule",
            "ms_get_schedule", "ms_autotune", "ms_step", "ms_step_backward", "ms_get_state", "ms_set_state",
-           "ms_scene_status", "ms_set_force_outputs", "ms_enable_debug", "ms_debug_contacts", "ms_enable_phase_profile", "ms_phase_cycles",
+           "ms_scene_status", "ms_set_force_outputs", "ms_reset_robots", "ms_spawn_check", "ms_enable_debug", "ms_debug_contacts", "ms_enable_phase_profile", "ms_phase_cycles",
            "ms_last_error"]
 PHASES = ["drive+kinematics", "contacts", "dynamics", "rows", "levels", "pgs", "integrate", "load/store"]
 
@@ -96,6 +96,8 @@ def lib():
             "ms_set_state": [vp, vp, vp, vp, vp],
             "ms_scene_status": [vp, vp],
             "ms_set_force_outputs": [vp, vp, vp],
+            "ms_reset_robots": [vp, vp, vp, vp, vp, vp, vp],
+            "ms_spawn_check": [vp, vp, vp, vp],
             "ms_enable_debug": [vp, i32],
             "ms_debug_contacts": [vp, vp],
             "ms_enable_phase_profile": [vp, i32],
@@ -267,6 +269,31 @@ class MsBatch:
         _check(lib().ms_set_force_outputs(self.h, None, None), "ms_set_force_outputs")
         self.robot_force = self.body_force = None
         return None
+
+    def reset_robots(self, x, base, noise, clip, mask=None, stream=None):
+        """Robot resets of the masked scenes in place: q = base + clip(noise), qd = 0."""
+        self._check_state(x, "state")
+        t = self.torch
+        for v, n in ((base, "base"), (noise, "noise")):
+            if not (isinstance(v, t.Tensor) and v.is_cuda and v.dtype == t.float32 and v.is_contiguous()
+                    and v.numel() == self.S * 16):
+                raise MsError(f"{n}: expected a contiguous float32 device tensor [{self.S}, 16]")
+        if mask is not None and not (isinstance(mask, t.Tensor) and mask.is_cuda and mask.dtype == t.uint8
+                                     and mask.numel() == self.S):
+            raise MsError(f"mask: expected a uint8 device tensor of {self.S} entries")
+        c = np.ascontiguousarray(np.asarray(clip, np.float32).reshape(16))
+        _check(lib().ms_reset_robots(self.h, _ptr_t(x), _ptr_t(mask) if mask is not None else None, _ptr_t(base),
+                                     _ptr_t(noise), _ptr_np(c), _stream(stream)), "ms_reset_robots")
+        return x
+
+    def spawn_check(self, x, out=None, stream=None):
+        """uint8 [S]: 1 where a robot sphere penetrates another body."""
+        self._check_state(x, "state")
+        t = self.torch
+        if out is None:
+            out = t.empty(self.S, dtype=t.uint8, device=self.device)
+        _check(lib().ms_spawn_check(self.h, _ptr_t(x), _ptr_t(out), _stream(stream)), "ms_spawn_check")
+        return out
 
     def set_schedule(self, flags, grid=0):
         s = Schedule(flags, grid)

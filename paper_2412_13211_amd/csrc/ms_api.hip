@@ -260,6 +260,7 @@ ms_status ms_create_batch(const ms_batch_desc* d, const ms_scene_desc* sc, void*
   (void)hipFuncSetAttribute(step_kernel_ptr(), hipFuncAttributeMaxDynamicSharedMemorySize, (int)b->max_lds);
   (void)hipFuncSetAttribute(step_rec_kernel_ptr(), hipFuncAttributeMaxDynamicSharedMemorySize, (int)b->max_lds);
   (void)hipFuncSetAttribute(step_frc_kernel_ptr(), hipFuncAttributeMaxDynamicSharedMemorySize, (int)b->max_lds);
+  (void)hipFuncSetAttribute(spawn_check_kernel_ptr(), hipFuncAttributeMaxDynamicSharedMemorySize, (int)b->max_lds);
   (void)hipFuncSetAttribute(step_bwd_wave_ptr(), hipFuncAttributeMaxDynamicSharedMemorySize, (int)b->max_lds);
   // status starts at zero
   hipError_t e = hipMemsetAsync(b->scratch + b->sl.status, 0, sizeof(uint32_t) * c.S, stream);
@@ -358,6 +359,29 @@ ms_status enqueue_record(ms_batch* b, const void* x_in, const float* u, float* r
     grid = persistent_grid(b, lds);
   }
   launch_step(a, grid, lds, st);
+  HIP_TRY(hipGetLastError());
+  return MS_OK;
+}
+
+ms_status ms_reset_robots(ms_batch* b, void* x, const uint8_t* mask, const float* base, const float* noise,
+                          const float* clip, void* hip_stream) {
+  if (!b || !x || !base || !noise || !clip) return fail(MS_E_INVALID, "ms_reset_robots: null argument");
+  for (int j = 0; j < ND; ++j)
+    if (!(clip[j] >= 0.f)) return fail(MS_E_INVALID, "ms_reset_robots: clip[%d] must be >= 0", j);
+  launch_reset_robots(static_cast<float*>(x), mask, base, noise, clip, b->cnt.S, static_cast<hipStream_t>(hip_stream));
+  HIP_TRY(hipGetLastError());
+  return MS_OK;
+}
+
+ms_status ms_spawn_check(ms_batch* b, const void* x, uint8_t* collide, void* hip_stream) {
+  if (!b || !x || !collide) return fail(MS_E_INVALID, "ms_spawn_check: null argument");
+  // the kernel loads a scene like a step does; the control slot reads the scratch targets
+  KArgs a = make_args(b, x, reinterpret_cast<const float*>(b->scratch + b->sl.act), nullptr);
+  a.debug = nullptr;
+  a.phase_cycles = nullptr;
+  size_t lds = lds_bytes_of(a);
+  if (lds > b->max_lds) return fail(MS_E_UNSUPPORTED, "scene working set needs %zu B of LDS", lds);
+  launch_spawn_check(a, collide, lds, static_cast<hipStream_t>(hip_stream));
   HIP_TRY(hipGetLastError());
   return MS_OK;
 }

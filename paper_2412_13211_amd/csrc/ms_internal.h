@@ -175,5 +175,9 @@ void launch_masked_copy(float* dst, const float* src, const uint8_t* mask, int S
 const void* step_kernel_ptr();
 const void* step_rec_kernel_ptr();
 const void* step_frc_kernel_ptr();
+const void* spawn_check_kernel_ptr();
+void launch_spawn_check(const KArgs& a, uint8_t* collide, size_t lds_bytes, hipStream_t st);
+void launch_reset_robots(float* x, const uint8_t* mask, const float* base, const float* noise, const float* clip,
+                         int S, hipStream_t st);
 
 }  // namespace msk

@@ -1800,6 +1800,72 @@ __global__ void k_reset_queue(int* q) {
   if (threadIdx.x == 0) q[0] = 0;
 }
 
+// Spawn check of a reset: collide[s] = 1 where a robot sphere penetrates
+// (phi < 0) another body; every (robot sphere, target) pair is tested with
+// the contact phase's pair function and a zero margin.
+__global__ __launch_bounds__(WAVE) void k_spawn_check(KArgs a, uint8_t* collide) {
+  extern __shared__ float lds[];
+  const int s = blockIdx.x;
+  if (s >= a.S) return;
+  const int lane = lane_id();
+  Scene S;
+  const DScene ds = a.scenes[s];
+  S.s = s;
+  S.M = a.models + ds.model;
+  S.nb = S.M->nb;
+  S.nsph = S.M->nsph;
+  S.nf = ds.nf; S.ns = ds.ns; S.np = ds.np; S.na = ds.na; S.nfo = ds.nown;
+  S.f0 = ds.f0; S.s0 = ds.s0; S.p0 = ds.p0; S.a0 = ds.a0;
+  S.hold = a.scenes[s].hold;
+  float* L = lds;
+  Robot rb = robot_view(L + a.L.robot, L + a.L.rows);
+  load_scene(a, S, L, rb);
+  phase_kinematics(a, S, L, rb);
+  const LdsLayout& Y = a.L;
+  ConCtx X;
+  X.M = S.M;
+  X.C = L + Y.con;
+  X.cc = Y.ccap;
+  X.SW = L + Y.sph;
+  X.F = L + Y.fr;
+  X.fm = Y.fmax;
+  X.A = L + Y.aux;
+  X.Pl = L + Y.plane;
+  X.own = reinterpret_cast<const uint16_t*>(L + Y.own);
+  X.St = Y.smax > 0 ? (L + Y.stat) : (a.statics + (size_t)S.s0 * 6);
+  X.nsph = S.nsph; X.np = S.np; X.ns = S.ns; X.na = S.na; X.nf = S.nf;
+  X.NT = S.np + S.ns + S.na + S.nf;
+  X.margin = 0.f;
+  const int NT = X.NT, total = S.nsph * NT;
+  const float invNT = NT > 0 ? 1.f / (float)NT : 0.f;
+  bool hit = false;
+  for (int base = 0; base < total; base += WAVE) {
+    int pair = base + lane;
+    if (pair < total) {
+      int o, t;
+      divmod(pair, NT, invNT, o, t);
+      PairOut po;
+      bool isrob;
+      hit |= eval_pair(X, o, t, po, isrob);
+    }
+  }
+  uint64_t any = __ballot(hit);
+  if (lane == 0) collide[s] = any ? 1 : 0;
+}
+
+// Robot resets of the masked scenes: q = base + clip(noise, -c_j, c_j), qd = 0.
+struct Clip16 {
+  float c[ND];
+};
+__global__ void k_reset_robots(float* x, const uint8_t* mask, const float* base, const float* noise, Clip16 clip,
+                               int S) {
+  const int s = blockIdx.x * 4 + (threadIdx.x >> 4), j = threadIdx.x & 15;
+  if (s >= S || (mask && !mask[s])) return;
+  const size_t i = (size_t)s * ND + j;
+  x[i] = base[i] + fminf(fmaxf(noise[i], -clip.c[j]), clip.c[j]);
+  x[(size_t)S * ND + i] = 0.f;
+}
+
 // Normalized actions (clipped to [-1, 1]) to PD targets from the state at the
 // control step's start: joint delta position, base linear velocity along the
 // heading (world x and y shares), base angular velocity, gripper opening.
@@ -1918,5 +1984,16 @@ void launch_masked_copy(float* dst, const float* src, const uint8_t* mask, int S
 const void* step_kernel_ptr() { return reinterpret_cast<const void*>(&k_step); }
 const void* step_rec_kernel_ptr() { return reinterpret_cast<const void*>(&k_step_rec); }
 const void* step_frc_kernel_ptr() { return reinterpret_cast<const void*>(&k_step_frc); }
+const void* spawn_check_kernel_ptr() { return reinterpret_cast<const void*>(&k_spawn_check); }
+void launch_spawn_check(const KArgs& a, uint8_t* collide, size_t lds_bytes, hipStream_t st) {
+  hipLaunchKernelGGL(k_spawn_check, dim3(a.S), dim3(WAVE), lds_bytes, st, a, collide);
+}
+void launch_reset_robots(float* x, const uint8_t* mask, const float* base, const float* noise, const float* clip,
+                         int S, hipStream_t st) {
+  if (S <= 0) return;
+  Clip16 c;
+  for (int j = 0; j < ND; ++j) c.c[j] = clip[j];
+  hipLaunchKernelGGL(k_reset_robots, dim3((S + 3) / 4), dim3(64), 0, st, x, mask, base, noise, c, S);
+}
 
 }  // namespace msk

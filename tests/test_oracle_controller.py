@@ -76,3 +76,21 @@ def test_action_adjoint_central_differences(batch_state):
     eps = 1e-6
     fd = (g @ o.step(x, a + eps * du) - g @ o.step(x, a - eps * du)) / (2 * eps)
     assert abs(fd - np.sum(ga * du)) <= 1e-5 * max(1.0, abs(fd))
+
+
+def test_spawn_check_detects_penetration_only():
+    """Spawn check: a clear scene passes; a free box moved onto a robot sphere,
+    or the robot base pushed into a furniture box, is flagged."""
+    b = sg.make(2, 4)
+    o = oracle.Oracle(b)
+    x = b.state0.astype(np.float64)
+    assert np.all(o.spawn_check(x) == 0)
+    sph, org, _ = o.fk(int(b.scene_model[0]), sg.split_state(x, b.n_scenes, b.n_free, b.n_aux)["q"][0])
+    x1 = x.copy()
+    fr = sg.split_state(x1, b.n_scenes, b.n_free, b.n_aux)["free"]
+    fr[b.free_off[0], 0:3] = sph[20]               # scene 0: a free body centred on robot sphere 20
+    q = sg.split_state(x1, b.n_scenes, b.n_free, b.n_aux)["q"]
+    box = b.static_box[b.static_off[1]]
+    q[1, 0:2] = box[0:2]                          # scene 1: base moved into its first furniture box
+    res = o.spawn_check(x1)
+    assert res[0] == 1 and res[1] == 1 and res[2] == 0 and res[3] == 0
