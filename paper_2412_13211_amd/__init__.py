@@ -339,6 +339,24 @@ class MsBatch:
         m = C.c_void_p(0) if mask is None else _ptr_t(mask)
         _check(lib().ms_set_state(self.h, _ptr_t(x), _ptr_t(src), m, _stream(stream)), "ms_set_state")
 
+    def get_state(self, x):
+        """Typed device views of a state tensor through ms_get_state: q, qd
+        [S,16], free [NF,16], aux [NA,4] (torch views sharing x's memory) and
+        the CSR offsets free_off, aux_off (numpy copies)."""
+        self._check_state(x, "state")
+        v = StateView()
+        _check(lib().ms_get_state(self.h, _ptr_t(x), C.byref(v)), "ms_get_state")
+        base = x.data_ptr()
+        elem = lambda p: (p - base) // 4
+        S, NF, NA = v.n_scenes, v.n_free, v.n_aux
+        out = {"q": x[elem(v.q): elem(v.q) + 16 * S].view(S, 16),
+               "qd": x[elem(v.qd): elem(v.qd) + 16 * S].view(S, 16),
+               "free": x[elem(v.free_body): elem(v.free_body) + 16 * NF].view(NF, 16),
+               "aux": x[elem(v.aux): elem(v.aux) + 4 * NA].view(NA, 4)}
+        out["free_off"] = np.ctypeslib.as_array(C.cast(v.free_off_host, C.POINTER(C.c_int32)), (S + 1,)).copy()
+        out["aux_off"] = np.ctypeslib.as_array(C.cast(v.aux_off_host, C.POINTER(C.c_int32)), (S + 1,)).copy()
+        return out
+
     def views(self, x):
         """Typed views of a state tensor: q, qd [S,16], free [NF,16], aux [NA,4]."""
         S, NF, NA = self.S, self.n_free, self.n_aux
