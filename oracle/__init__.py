@@ -82,7 +82,7 @@ def lib():
                            ("or_dynamics", [vp, C.c_int, vp, vp, vp, vp, vp]),
                            ("or_aba", [vp, C.c_int, vp, vp, vp, vp, vp, vp]),
                            ("or_pair", [C.c_int, vp, C.c_double, vp, vp]),
-                           ("or_spawn_check", [vp, vp, vp, C.c_int])]:
+                           ("or_spawn_check", [vp, vp, vp, vp, C.c_int])]:
             f = getattr(L, name)
             f.argtypes = args
             f.restype = C.c_int
@@ -190,13 +190,15 @@ class Oracle:
                 xs.append(r)
         return (xs, dbgs) if debug else xs
 
-    def spawn_check(self, x):
-        """Per scene 1 where a robot sphere penetrates another body (phi < 0)."""
+    def spawn_check(self, x, with_phi=False):
+        """Per scene 1 where a robot sphere penetrates another body (phi < 0);
+        with_phi: also the smallest signed distance per scene."""
         x = np.ascontiguousarray(x, np.float64)
         out = np.zeros(self.S, np.int32)
-        if lib().or_spawn_check(C.byref(self.sc), _ptr(x), _ptr(out), self.threads):
+        phi = np.zeros(self.S, np.float64)
+        if lib().or_spawn_check(C.byref(self.sc), _ptr(x), _ptr(out), _ptr(phi), self.threads):
             raise RuntimeError("or_spawn_check failed")
-        return out
+        return (out, phi) if with_phi else out
 
     def vjp(self, x, u, gx_out):
         x = np.ascontiguousarray(x, np.float64)

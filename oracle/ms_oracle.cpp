@@ -1260,7 +1260,7 @@ int or_flops(const or_scene* sc, const or_params* pr, const double* x_in, const 
   return 0;
 }
 
-int or_spawn_check(const or_scene* sc, const double* x, int32_t* collide, int threads) {
+int or_spawn_check(const or_scene* sc, const double* x, int32_t* collide, double* min_phi, int threads) {
   if (!sc || !x || !collide) return -1;
   std::vector<ArtModel> robots = load_models(sc);
   Layout L = layout_of(sc);
@@ -1277,29 +1277,31 @@ int or_spawn_check(const or_scene* sc, const double* x, int32_t* collide, int th
       double qa[1] = {st.aq[a]};
       fk(c.aux[a], qa, ak[a], false);
     }
-    bool hit = false;
+    double mphi = 1e300;
     V3<double> n, p;
+    auto see = [&](double phi) { mphi = std::min(mphi, phi); };
     for (const Sphere& sp : c.sph) {
       V3<double> cw = add(mv(rk.R[sp.body], cv3<double>(sp.c)), rk.p[sp.body]);
       for (int pl = 0; pl < (int)c.planes.size(); ++pl) {
         if (pl == 0 && (sp.flags & 1)) continue;
-        hit |= g_plane<double>(cw, sp.r, c.planes[pl].data(), n, p) < 0.0;
+        see(g_plane<double>(cw, sp.r, c.planes[pl].data(), n, p));
       }
       for (const auto& bx : c.boxes)
-        hit |= g_box<double>(cw, sp.r, cv3<double>(bx.data()), ident3<double>(), &bx[3], n, p) < 0.0;
+        see(g_box<double>(cw, sp.r, cv3<double>(bx.data()), ident3<double>(), &bx[3], n, p));
       for (int a = 0; a < NA; ++a) {
         V3<double> bc = add(mv(ak[a].R[0], cv3<double>(c.aux_box[a].data())), ak[a].p[0]);
-        hit |= g_box<double>(cw, sp.r, bc, ak[a].R[0], &c.aux_box[a][3], n, p) < 0.0;
+        see(g_box<double>(cw, sp.r, bc, ak[a].R[0], &c.aux_box[a][3], n, p));
       }
       for (int f = 0; f < NF; ++f) {
         const FreeC& fc = c.fr[f];
         if (fc.type == 0)
-          hit |= g_box<double>(cw, sp.r, st.fr[f].x, quat_R(st.fr[f].Q), fc.half, n, p) < 0.0;
+          see(g_box<double>(cw, sp.r, st.fr[f].x, quat_R(st.fr[f].Q), fc.half, n, p));
         else
-          hit |= g_sphere<double>(cw, sp.r, st.fr[f].x, fc.half[0], n, p) < 0.0;
+          see(g_sphere<double>(cw, sp.r, st.fr[f].x, fc.half[0], n, p));
       }
     }
-    collide[s] = hit ? 1 : 0;
+    collide[s] = mphi < 0.0 ? 1 : 0;
+    if (min_phi) min_phi[s] = mphi;
   });
   return 0;
 }

@@ -123,7 +123,8 @@ int or_flops(const or_scene* sc, const or_params* pr, const double* x_in, const 
 // Spawn check of a reset: collide[s] = 1 where a robot sphere penetrates
 // (phi < 0) a plane (the base's spheres not the first plane), a furniture
 // box, a door / drawer box or a free body; brute force over every pair.
-int or_spawn_check(const or_scene* sc, const double* x, int32_t* collide, int threads);
+// min_phi (may be null): per scene the smallest signed distance over those pairs.
+int or_spawn_check(const or_scene* sc, const double* x, int32_t* collide, double* min_phi, int threads);
 
 // ---- single-function probes used by the closed-form tests ----
 // Robot model m: world sphere centres [nsph][3] and body origins [nb][3].

@@ -1,6 +1,8 @@
 """GPU robot resets and spawn check (ms_reset_robots / ms_spawn_check):
 resets follow their definition exactly; the spawn check equals the oracle's
-brute-force penetration test, scene by scene."""
+brute-force penetration test scene by scene, except where the smallest signed
+distance is within 1e-5 m of zero (the decision then depends on the
+precision the distances are computed in)."""
 import numpy as np
 import pytest
 
@@ -52,9 +54,11 @@ def test_spawn_check_matches_oracle(cfg):
     st["q"][:, 0:2] += rng.uniform(-1.5, 1.5, (b.n_scenes, 2))
     st["q"][:, 6:13] += rng.uniform(-1.0, 1.0, (b.n_scenes, 7))
     x = x.astype(np.float32).astype(np.float64)
-    want = o.spawn_check(x)
+    want, phi = o.spawn_check(x, with_phi=True)
+    clear = np.abs(phi) >= 1e-5
     mb = ms.MsBatch(b)
     got = mb.spawn_check(torch.as_tensor(x.astype(np.float32)).cuda()).cpu().numpy()
-    print(f"cfg{cfg}: {int(want.sum())} of {b.n_scenes} spawns collide", flush=True)
-    assert 0 < want.sum() < b.n_scenes
-    assert np.array_equal(got.astype(np.int32), want)
+    print(f"cfg{cfg}: {int(want.sum())} of {b.n_scenes} spawns collide, {int((~clear).sum())} within 1e-5 m of "
+          f"contact", flush=True)
+    assert 0 < want.sum() < b.n_scenes and clear.sum() >= 0.9 * b.n_scenes
+    assert np.array_equal(got.astype(np.int32)[clear], want[clear])
