@@ -422,6 +422,7 @@ ms_status ms_step_backward(ms_batch* b, const void* x_in, const float* u, const 
   a.gxi = static_cast<float*>(gx_in);
   a.gu = actions ? reinterpret_cast<float*>(b->scratch + b->sl.actb) : gu;
   a.status = reinterpret_cast<uint32_t*>(b->scratch + b->sl.status);
+  a.cycles = b->profile_on ? reinterpret_cast<unsigned long long*>(b->scratch + b->sl.cycles) : nullptr;
   a.ws = reinterpret_cast<float*>(b->tape);
   a.S = c.S;
   a.NF = c.NF;

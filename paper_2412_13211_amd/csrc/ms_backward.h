@@ -31,6 +31,7 @@ struct BwdArgs {
   float* gxi;             // adjoint of the state in (may alias gxo)
   float* gu;              // adjoint of the controls [S][16]
   uint32_t* status;       // [S], bits OR-ed in
+  unsigned long long* cycles;  // [S][8] shader-clock cycles per phase of the wavefront kernel, or null
   float* ws;              // lane kernel: workspace, w.total floats per slot, interleaved with stride `stride`
   const float* rec;       // wavefront kernel: forward record, RL.total floats per scene
   RecLayout RL;

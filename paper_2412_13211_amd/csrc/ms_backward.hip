@@ -233,6 +233,16 @@ __device__ void bwd_scene(const BwdArgs& a, int s, float* L) {
   const size_t ofr = 32 * S + 16 * (size_t)D.f0, oax = 32 * S + 16 * (size_t)a.NF + 4 * (size_t)D.a0;
   const float* u = a.u + 16 * (size_t)s;
   Lv LV = lv_view(L, w);
+  const bool prof = a.cycles != nullptr;
+  unsigned long long cyc[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+  unsigned long long tc = prof ? clock64() : 0;
+  auto phase = [&](int k) {
+    if (prof) {
+      unsigned long long t2 = clock64();
+      cyc[k] += t2 - tc;
+      tc = t2;
+    }
+  };
 
   // adjoint of the end state
   zero_lds(L, w.gA, w.ss);
@@ -300,6 +310,7 @@ __device__ void bwd_scene(const BwdArgs& a, int s, float* L) {
       bs3(E.b, eo + C_P, p);
     }
     wsync();
+    phase(0);
     // recompute on one lane: drive, kinematics, frames, dynamics (without the
     // unconstrained velocities), rows; then the level schedule
     if (lane == 0) {
@@ -362,6 +373,7 @@ __device__ void bwd_scene(const BwdArgs& a, int s, float* L) {
       LV.cnt[4] = (int)E.status;
     }
     wsync();
+    phase(1);
     E.nc = LV.cnt[0];
     E.nrob = LV.cnt[1];
     E.nlim = LV.cnt[2];
@@ -408,6 +420,7 @@ __device__ void bwd_scene(const BwdArgs& a, int s, float* L) {
     wsync();
     if (lane == 0) E.integrate_bar(w.st);
     wsync();
+    phase(2);
     // Gauss-Seidel sweeps in reverse, levels in reverse
     for (int it = a.pr.K - 1; it >= 0; --it) {
       for (int lv = maxl; lv >= 1; --lv) {
@@ -422,6 +435,7 @@ __device__ void bwd_scene(const BwdArgs& a, int s, float* L) {
         wsync();
       }
     }
+    phase(3);
     // the rest of the reverse substep on one lane
     if (lane == 0) {
       E.rows_bar();
@@ -432,8 +446,10 @@ __device__ void bwd_scene(const BwdArgs& a, int s, float* L) {
       LV.cnt[4] = (int)E.status;
     }
     wsync();
+    phase(4);
     for (int i = lane; i < w.ss; i += 64) L[w.gA + i] = L[w.gB + i];
     wsync();
+    phase(5);
   }
   if (lane < ND) {
     a.gxi[oq + lane] = L[w.gA + lane];
@@ -443,6 +459,8 @@ __device__ void bwd_scene(const BwdArgs& a, int s, float* L) {
   for (int i = lane; i < nf * 16; i += 64) a.gxi[ofr + i] = L[w.gA + 32 + i];
   if (lane < na * 4) a.gxi[oax + lane] = L[w.gA + 32 + 16 * fm + lane];
   if (lane == 0 && LV.cnt[4]) a.status[s] |= (uint32_t)LV.cnt[4];
+  if (prof && lane == 0)
+    for (int k = 0; k < 8; ++k) a.cycles[(size_t)s * 8 + k] = cyc[k];
 }
 
 }  // namespace
