@@ -16,6 +16,10 @@ HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-shared",
          # packed FP32 VALU ops stay off (see the design notes)
          "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+         # the wavefront adjoint kernel exceeds the backend's default basic-block
+         # budget for inlining; calls left out of line would put the engine
+         # object in scratch memory
+         "-mllvm", "-amdgpu-inline-max-bb=3000",
          "-Wall", "-Wno-unused-function", "-Wno-unused-variable", "-Wno-unused-but-set-variable"]
 
 

@@ -174,7 +174,8 @@ struct WS {
   int vR, vA, vF, lam, llam, con, lim, rJ, rw;
   int vRb, vAb, vFb, lamb, llamb, limb, conb, rJb, rwb, fb, xb;
   int Mb, sb, Ib, Icb, fbar, abar, vbar, bacc;
-  int lv;  // level schedule (wavefront kernel only)
+  int lv;    // level schedule (wavefront kernel only)
+  int Minv;  // explicit M~^-1 (wavefront kernel only)
   int total;
 };
 
@@ -220,6 +221,7 @@ MSA_HD inline WS ws_layout(int fmax, int ntmax, int ccap, int rcap, int K, int n
   w.fbar = take(ND * 6); w.abar = take(ND * 6); w.vbar = take(ND * 6);
   w.bacc = take(ND * 9);
   w.lv = take(wave ? lv_ints(ccap) : 0);
+  w.Minv = take(wave ? ND * ND : 0);
   w.total = o;
   return w;
 }
@@ -912,6 +914,10 @@ struct Eng {
       float phi = at(e + C_PHI);
       at(e + C_BIAS) = phi >= 0.f ? phi / h : pr.beta * phi / h;
     }
+    build_lims();
+  }
+  // joint-limit rows of the door / drawer joints (first in the canonical order)
+  MSA_HD void build_lims() {
     nlim = 0;
     for (int x = 0; x < sc.na; ++x) {
       const DAux& A = sc.A[x];
@@ -1445,10 +1451,11 @@ struct Eng {
     pb = pb + rrb;
     a3(w.fb + f * FB + F_XB, -rrb);
   }
-  MSA_HD void rows_bar() {
+  // robot_side = false: the robot owners' rows are reversed elsewhere (the
+  // wavefront kernel spreads them over lanes); M~bar must be zeroed before
+  MSA_HD void rows_bar(bool robot_side = true) {
     const DModel& M = *sc.M;
     const float h = pr.h;
-    for (int i = 0; i < ND * ND; ++i) at(w.Mb + i) = 0.f;
     for (int ci = 0; ci < nc; ++ci) {
       long e = w.con + (long)ci * CR, cb = w.conb + (long)ci * CB;
       int ok = (int)at(e + C_OK), oi = (int)at(e + C_OI), tk = (int)at(e + C_TK), ti = (int)at(e + C_TI);
@@ -1458,7 +1465,9 @@ struct Eng {
         V d = dir(e, di);
         V db{0.f, 0.f, 0.f};
         float Wb = at(cb + B_W + di);
-        if (ok == 0) {
+        if (ok == 0 && !robot_side) {
+          // nothing: this side is handled by the caller
+        } else if (ok == 0) {
           long rj = w.rJ + ((long)ci * 3 + di) * ND, rwv = w.rw + ((long)ci * 3 + di) * ND;
           long rjb = w.rJb + ((long)ci * 3 + di) * ND, rwb = w.rwb + ((long)ci * 3 + di) * ND;
           float Jb[ND], al[ND];
@@ -1883,6 +1892,7 @@ struct Eng {
     zero(w.fb, w.fmax * FB);
     zero(w.xb, AMAX * XB);
     zero(w.bacc, ND * 9);
+    zero(w.Mb, ND * ND);
     integrate_bar(s);
     pgs_bar();
     rows_bar();

@@ -45,6 +45,15 @@ __device__ __forceinline__ float sum16_b(float v) {
   return __shfl(v, 0, 64);
 }
 
+// sum within each 16-lane group, returned in every lane of the group
+__device__ __forceinline__ float sum16(float v) {
+  v += __shfl_xor(v, 8, 64);
+  v += __shfl_xor(v, 4, 64);
+  v += __shfl_xor(v, 2, 64);
+  v += __shfl_xor(v, 1, 64);
+  return v;
+}
+
 // level-schedule views inside the LDS block
 struct Lv {
   int *lvl, *order, *loff, *rob, *last, *cnt;
@@ -209,6 +218,190 @@ __device__ __forceinline__ void zero_lds(float* L, long off, int n) {
   for (int i = lane_id(); i < n; i += 64) L[off + i] = 0.f;
 }
 
+// explicit M~^-1 from the Cholesky factor: lane k < ND solves M~ x = e_k
+// (rows and columns past the robot's degrees of freedom are zero); M~ is
+// symmetric, so column k is stored as row k
+__device__ __forceinline__ void build_minv(const msa::Eng& E, float* L) {
+  const int lane = lane_id();
+  if (lane >= ND) return;
+  const int nb = E.nb;
+  const long Lf = E.w.L;
+  float x[ND];
+#pragma unroll
+  for (int i = 0; i < ND; ++i) x[i] = i == lane ? 1.f : 0.f;
+#pragma unroll
+  for (int i = 0; i < ND; ++i) {
+    float s = x[i];
+#pragma unroll
+    for (int k = 0; k < i; ++k) s -= L[Lf + i * ND + k] * x[k];
+    x[i] = i < nb && lane < nb ? s / L[Lf + i * ND + i] : 0.f;
+  }
+#pragma unroll
+  for (int i = ND - 1; i >= 0; --i) {
+    float s = x[i];
+#pragma unroll
+    for (int k = i + 1; k < ND; ++k) s -= L[Lf + k * ND + i] * x[k];
+    x[i] = i < nb && lane < nb ? s / L[Lf + i * ND + i] : 0.f;
+  }
+#pragma unroll
+  for (int i = 0; i < ND; ++i) L[E.w.Minv + lane * ND + i] = x[i];
+}
+
+// contact rows (the same quantities as the engine's rows(), limit rows
+// excepted): one lane per contact for the tangents, bias and the free-body
+// and door/drawer shares of W; then one lane per robot row (contact,
+// direction) for J, w = M~^-1 J^T and the robot share of W
+__device__ __forceinline__ void rows_wave(msa::Eng& E, float* L) {
+  using namespace msa;
+  const int lane = lane_id();
+  const WS& w = E.w;
+  const DModel& M = *E.sc.M;
+  const float h = E.pr.h;
+  for (int ci = lane; ci < E.nc; ci += 64) {
+    const long e = w.con + (long)ci * CR;
+    V n = E.v3(e + C_N), t1, t2;
+    onb(n, t1, t2);
+    E.s3(e + C_T1, t1);
+    E.s3(e + C_T2, t2);
+    const V p = E.v3(e + C_P);
+    const int ok = (int)L[e + C_OK], oi = (int)L[e + C_OI], tk = (int)L[e + C_TK], ti = (int)L[e + C_TI];
+    for (int di = 0; di < 3; ++di) {
+      const V d = di == 0 ? n : (di == 1 ? t1 : t2);
+      float W = ok == 0 ? 0.f : E.free_W(oi, d, p, 1.f);
+      if (tk == 2) {
+        float J = E.aux_J(ti, d, p, -1.f);
+        W += J * (J / L[w.xM + ti]);
+      } else if (tk == 3) {
+        W += E.free_W(ti, d, p, -1.f);
+      }
+      L[e + C_W + di] = W;
+    }
+    const float phi = L[e + C_PHI];
+    L[e + C_BIAS] = phi >= 0.f ? phi / h : E.pr.beta * phi / h;
+  }
+  wsync();
+  // robot rows, four at a time: lane j of a 16-lane group owns joint j
+  const int g = lane >> 4, j = lane & 15, nr = 3 * E.nrob;
+  for (int r0 = 0; r0 < nr; r0 += 4) {
+    const int r = r0 + g;
+    const bool act = r < nr;
+    const int ci = r / 3, di = r - 3 * (r / 3);
+    const long e = w.con + (long)ci * CR;
+    float Jj = 0.f;
+    if (act) {
+      const int anc = M.anc[M.sph_body[(int)L[e + C_OI]]];
+      if (j < E.nb && ((anc >> j) & 1)) {
+        const V a = E.v3(w.ka + j * 3), d = E.dir(e, di);
+        Jj = M.jtype[j] == 0 ? dot(d, cross(a, E.v3(e + C_P) - E.v3(w.ko + j * 3))) : dot(d, a);
+      }
+      L[w.rJ + (long)r * ND + j] = Jj;
+    }
+    wsync();
+    // w_j = sum_k (M~^-1)_jk J_k; Minv row k holds M~^-1 e_k
+    float s = 0.f;
+    if (act)
+      for (int k = 0; k < ND; ++k) s += L[w.Minv + k * ND + j] * L[w.rJ + (long)r * ND + k];
+    const float W = sum16(Jj * s);
+    if (act) {
+      L[w.rw + (long)r * ND + j] = s;
+      if (j == 0) L[e + C_W + di] += W;
+    }
+  }
+  wsync();
+  bool bad = false;
+  for (int ci = lane; ci < E.nc; ci += 64)
+    for (int di = 0; di < 3; ++di) bad |= !(L[w.con + (long)ci * CR + C_W + di] >= 1e-12f);
+  if (__ballot(bad)) E.status |= Eng::MS_DEGENERATE_BIT;
+}
+
+// adjoint of the robot rows (the robot owners' share; the engine's
+// rows_bar(false) does the rest).  With w = M~^-1 J^T and W += J . w:
+// Jbar += Wbar w + M~^-1 (wbar + Wbar J), M~bar -= M~^-1 (wbar + Wbar J) w^T;
+// Jbar then reaches the directions, the contact point and the joint axes
+__device__ __forceinline__ void robot_rows_bar_wave(msa::Eng& E, float* L) {
+  using namespace msa;
+  const int lane = lane_id();
+  const WS& w = E.w;
+  const DModel& M = *E.sc.M;
+  const int nb = E.nb, nr = 3 * E.nrob;
+  // robot rows four at a time (lane j of a 16-lane group owns entry j):
+  // Jbar into rJb, alpha = M~^-1 (wbar + Wbar J) into rwb
+  const int g = lane >> 4, jj = lane & 15;
+  for (int r0 = 0; r0 < nr; r0 += 4) {
+    const int r = r0 + g;
+    const bool act = r < nr;
+    const int ci = r / 3, di = r - 3 * (r / 3);
+    const long rb = (long)r * ND + jj;
+    float Wb = 0.f;
+    if (act) {
+      Wb = L[w.conb + (long)ci * CB + B_W + di];
+      L[w.rwb + rb] += Wb * L[w.rJ + rb];
+    }
+    wsync();
+    float s = 0.f;
+    if (act)
+      for (int k = 0; k < ND; ++k) s += L[w.Minv + k * ND + jj] * L[w.rwb + (long)r * ND + k];
+    wsync();
+    if (act) {
+      L[w.rJb + rb] += Wb * L[w.rw + rb] + s;
+      L[w.rwb + rb] = s;
+    }
+  }
+  wsync();
+  // M~bar: lane owns entries lane, lane + 64, ...
+  for (int idx = lane; idx < ND * ND; idx += 64) {
+    const int rr = idx / ND, cc = idx - ND * (idx / ND);
+    float s = 0.f;
+    for (int q = 0; q < nr; ++q) s += L[w.rwb + (long)q * ND + rr] * L[w.rw + (long)q * ND + cc];
+    L[w.Mb + idx] -= s;
+  }
+  // lane per robot contact: direction and contact-point adjoints
+  for (int ci = lane; ci < E.nrob; ci += 64) {
+    const long e = w.con + (long)ci * CR, cb = w.conb + (long)ci * CB;
+    const V p = E.v3(e + C_P);
+    const int anc = M.anc[M.sph_body[(int)L[e + C_OI]]];
+    V pb{0.f, 0.f, 0.f};
+    for (int di = 0; di < 3; ++di) {
+      const V d = E.dir(e, di);
+      const long rjb = w.rJb + ((long)ci * 3 + di) * ND;
+      V db{0.f, 0.f, 0.f};
+      for (int j = 0; j < nb; ++j) {
+        const float Jb = L[rjb + j];
+        if (!((anc >> j) & 1) || Jb == 0.f) continue;
+        const V a = E.v3(w.ka + j * 3);
+        if (M.jtype[j] == 0) {
+          db = db + cross(a, p - E.v3(w.ko + j * 3)) * Jb;
+          pb = pb + cross(d, a) * Jb;
+        } else {
+          db = db + a * Jb;
+        }
+      }
+      E.a3(cb + B_D + di * 3, db);
+    }
+    E.a3(cb + B_P, pb);
+  }
+  // lane per joint: the joint's own body accumulators
+  for (int j = lane; j < nb; j += 64) {
+    const V a = E.v3(w.ka + j * 3), o = E.v3(w.ko + j * 3);
+    const bool rev = M.jtype[j] == 0;
+    for (int r = 0; r < nr; ++r) {
+      const int ci = r / 3, di = r - 3 * ci;
+      const long e = w.con + (long)ci * CR;
+      const float Jb = L[w.rJb + (long)r * ND + j];
+      if (!((M.anc[M.sph_body[(int)L[e + C_OI]]] >> j) & 1) || Jb == 0.f) continue;
+      const V d = E.dir(e, di);
+      if (rev) {
+        const V ev = E.v3(e + C_P) - o;
+        E.acc_dir(j, a, cross(ev, d) * Jb);
+        E.acc_point(j, o, -(cross(d, a) * Jb));
+      } else {
+        E.acc_dir(j, a, d * Jb);
+      }
+    }
+  }
+  wsync();
+}
+
 __device__ void bwd_scene(const BwdArgs& a, int s, float* L) {
   using namespace msa;
   const int lane = lane_id();
@@ -311,17 +504,25 @@ __device__ void bwd_scene(const BwdArgs& a, int s, float* L) {
     }
     wsync();
     phase(0);
-    // recompute on one lane: drive, kinematics, frames, dynamics (without the
-    // unconstrained velocities), rows; then the level schedule
+    // recompute: drive, kinematics, frames and dynamics (without the
+    // unconstrained velocities) on one lane; M~^-1 and the contact rows over
+    // the lanes; the limit rows and the level schedule on one lane
+    E.nc = nc;
+    E.nrob = NR;
     if (lane == 0) {
-      E.nc = nc;
-      E.nrob = NR;
       E.drive(w.st, u);
       E.kinematics(w.st);
       E.aux_frames(w.st);
       E.free_frames(w.st);
       E.dynamics(w.st, false);
-      E.rows();
+    }
+    wsync();
+    phase(1);
+    build_minv(E, L);
+    wsync();
+    rows_wave(E, L);
+    if (lane == 0) {
+      E.build_lims();
       if (E.nlim != NL) E.status |= MS_ST_RECORD;
       const int R = E.nlim + E.nc;
       for (int k = 0; k < 64; ++k) LV.last[k] = 0;
@@ -373,7 +574,7 @@ __device__ void bwd_scene(const BwdArgs& a, int s, float* L) {
       LV.cnt[4] = (int)E.status;
     }
     wsync();
-    phase(1);
+    phase(2);
     E.nc = LV.cnt[0];
     E.nrob = LV.cnt[1];
     E.nlim = LV.cnt[2];
@@ -417,10 +618,11 @@ __device__ void bwd_scene(const BwdArgs& a, int s, float* L) {
     zero_lds(L, w.fb, fm * FB);
     zero_lds(L, w.xb, AMAX * XB);
     zero_lds(L, w.bacc, ND * 9);
+    zero_lds(L, w.Mb, ND * ND);
     wsync();
     if (lane == 0) E.integrate_bar(w.st);
     wsync();
-    phase(2);
+    phase(3);
     // Gauss-Seidel sweeps in reverse, levels in reverse
     for (int it = a.pr.K - 1; it >= 0; --it) {
       for (int lv = maxl; lv >= 1; --lv) {
@@ -435,21 +637,24 @@ __device__ void bwd_scene(const BwdArgs& a, int s, float* L) {
         wsync();
       }
     }
-    phase(3);
+    phase(4);
+    // rows^T: robot rows over the lanes, the rest on one lane
+    robot_rows_bar_wave(E, L);
+    if (lane == 0) E.rows_bar(false);
+    phase(5);
     // the rest of the reverse substep on one lane
     if (lane == 0) {
-      E.rows_bar();
       E.dynamics_bar(w.st, u);
+      phase(6);
       E.contacts_bar();
       E.frames_bar(w.st);
       E.kin_bar();
       LV.cnt[4] = (int)E.status;
     }
     wsync();
-    phase(4);
     for (int i = lane; i < w.ss; i += 64) L[w.gA + i] = L[w.gB + i];
     wsync();
-    phase(5);
+    phase(7);
   }
   if (lane < ND) {
     a.gxi[oq + lane] = L[w.gA + lane];
