@@ -264,6 +264,128 @@ ms_status ms_reset_robots(ms_batch* b, void* state_dev, const uint8_t* mask_dev,
  * Stream-ordered. */
 ms_status ms_spawn_check(ms_batch* b, const void* state_dev, uint8_t* collide_dev, void* hip_stream);
 
+/* ---------------------------------------------------------------- tasks
+ * Success predicates, event labels and trajectory categories of the four
+ * rearrangement subtasks (App. A.2 subtask definitions; App. A.3 event
+ * labeling and success / failure modes), evaluated for every scene after
+ * each control step.  Readings of points the appendix leaves open:
+ *   - distances d are Euclidean norms in m;
+ *   - is_static compares absolute values: max |qd_arm| <= 0.2 and |qd| <= 0.05
+ *     for the base x, y and yaw DoFs;
+ *   - the cumulative robot collision force C_t adds, per control step, the
+ *     mean over its substeps of the robot's total normal contact force;
+ *   - grasped(x): each of the two finger bodies presses on x with a normal
+ *     force >= grasp_force in the last substep of the control step;
+ *   - F_ee,x (contact events): the mean over the control step of the normal
+ *     force the end effector's bodies exert on x; "contact" is 0 -> > 0;
+ *   - an event index i_e is the position of e's latest occurrence in the
+ *     event list (-1 absent); modes are tested in the order given with
+ *     ms_task_categorize, the first that holds wins. */
+enum { MS_TASK_PICK = 0, MS_TASK_PLACE = 1, MS_TASK_OPEN = 2, MS_TASK_CLOSE = 3 };
+
+/* the robot as the predicates see it (body / DoF indices of the model) */
+typedef struct {
+  int32_t ee_body;          /* body carrying the end effector */
+  int32_t base_body;        /* body whose frame is the base frame */
+  int32_t base_x, base_y, base_yaw;  /* DoFs of the base's x, y and yaw velocity */
+  int32_t arm0, narm;       /* arm DoFs arm0 .. arm0 + narm - 1 */
+  int32_t torso;            /* torso DoF, -1: none */
+  int32_t finger_l, finger_r;        /* finger bodies (grasp test) */
+  uint32_t ee_bodies;       /* bit b set: body b belongs to the end effector */
+  float ee_offset[3];       /* end-effector point in ee_body's frame */
+  float ee_rest[3];         /* its rest position in the base frame (the caller's
+                               choice, e.g. the point at q_rest) */
+  float q_rest[16];         /* resting joint positions */
+  float grasp_force;        /* N */
+} ms_task_robot;
+
+/* one scene's subtask (device array [S]) */
+typedef struct {
+  int32_t kind;             /* MS_TASK_* */
+  int32_t target;           /* scene-local free body (pick, place) or door / drawer joint (open, close) */
+  float goal[3];            /* place: goal position, world */
+  float open_frac;          /* open: 0.75 for a fridge, 0.9 otherwise */
+} ms_task;
+
+/* indicator bits of ms_episode.ind (values after the last evaluated step) */
+enum {
+  MS_IND_GRASPED = 1u, MS_IND_SUCCESS = 2u, MS_IND_OPEN = 4u /* open (open task) / closed (close task) */,
+  MS_IND_SLIGHT = 8u /* slightly opened / slightly closed */, MS_IND_AT_GOAL = 16u, MS_IND_CONTACT = 32u,
+  MS_IND_EXCESSIVE = 64u /* C_t above the subtask's limit: the failure condition */
+};
+/* event codes, in the order the appendix evaluates them per step */
+enum { MS_EV_PICK_CONTACT = 0, MS_EV_PICK_GRASPED, MS_EV_PICK_DROPPED, MS_EV_PICK_SUCCESS, MS_EV_PICK_EXCESSIVE };
+enum {
+  MS_EV_PLACE_GRASPED = 0, MS_EV_PLACE_AT_GOAL, MS_EV_PLACE_RELEASED_AT_GOAL, MS_EV_PLACE_RELEASED_OUTSIDE,
+  MS_EV_PLACE_LEFT_GOAL, MS_EV_PLACE_SUCCESS, MS_EV_PLACE_EXCESSIVE
+};
+enum { MS_EV_OPEN_CONTACT = 0, MS_EV_OPEN_OPENED, MS_EV_OPEN_SLIGHT, MS_EV_OPEN_CLOSED, MS_EV_OPEN_SUCCESS,
+       MS_EV_OPEN_EXCESSIVE };
+enum { MS_EV_CLOSE_CONTACT = 0, MS_EV_CLOSE_CLOSED, MS_EV_CLOSE_SLIGHT, MS_EV_CLOSE_OPENED, MS_EV_CLOSE_SUCCESS,
+       MS_EV_CLOSE_EXCESSIVE };
+
+#define MS_EP_LIST 16
+/* per-scene episode record (device array [S], caller-owned; written by
+ * ms_task_begin / ms_task_update) */
+typedef struct {
+  float cumcol;             /* C_t, N */
+  float aq0;                /* door / drawer position at the episode start */
+  float d0;                 /* place: object-goal distance at the start */
+  uint32_t ind;             /* MS_IND_* bits of the last evaluated step */
+  int32_t t;                /* control steps evaluated since the start */
+  int32_t n;                /* events so far (list keeps the first MS_EP_LIST) */
+  int32_t last[8];          /* list index of each event code's latest occurrence, -1: none */
+  uint8_t list[MS_EP_LIST]; /* event codes in chronological order */
+} ms_episode;
+
+/* predicate values written per scene when pred_dev is non-null: float32 [S][8] */
+enum { MS_PRED_D_EE = 0, MS_PRED_J_ARM, MS_PRED_J_TORSO, MS_PRED_QD_MAX, MS_PRED_D_GOAL, MS_PRED_AQ,
+       MS_PRED_F_EE, MS_PRED_F_FINGER };
+
+/* Sets the robot description used by the task calls and the gripper outputs
+ * (copied; host struct).  Indices are checked against every model of the
+ * batch.  Drops captured graphs. */
+ms_status ms_set_task_robot(ms_batch* b, const ms_task_robot* robot_host);
+
+/* Gripper contact outputs: when grip_dev is non-null, every following
+ * ms_step writes float32 [NF + NA][2]: rows 0 .. NF-1 the free bodies, rows
+ * NF .. NF+NA-1 the door / drawer joints; [0] the normal force the end
+ * effector's bodies exert on it, summed over the substeps (N; divide by
+ * n_substeps for the mean), [1] the smaller of the two fingers' normal
+ * forces on it in the last substep (N).  Needs ms_set_task_robot first
+ * (else MS_E_STATE).  Null: off.  Drops captured graphs. */
+ms_status ms_set_grip_outputs(ms_batch* b, float* grip_dev);
+
+/* Starts the episodes of the scenes with mask_dev[s] != 0 (null: all) at
+ * state_dev: C = 0, t = 0, empty event list, the indicators of the start
+ * state (grip_dev as written by ms_set_grip_outputs, or null: no contact and
+ * not grasped), aq0 and d0.  pred_dev: optional predicate values.
+ * Stream-ordered; MS_E_STATE without ms_set_task_robot; an out-of-range task
+ * kind or target, or an open / close target without joint limits, leaves
+ * that scene's record with ind = 0xffffffff (also after ms_task_update). */
+ms_status ms_task_begin(ms_batch* b, const void* state_dev, const ms_task* tasks_dev, const float* grip_dev,
+                        ms_episode* ep_dev, const uint8_t* mask_dev, float* pred_dev, void* hip_stream);
+
+/* Evaluates the predicates after one control step (state_dev the state it
+ * produced, robot_force_dev and grip_dev its force outputs; grip_dev may be
+ * null), adds the step's events to every scene's list in the appendix's
+ * order, and advances t.  Stream-ordered. */
+ms_status ms_task_update(ms_batch* b, const void* state_dev, const ms_task* tasks_dev, const float* robot_force_dev,
+                         const float* grip_dev, ms_episode* ep_dev, float* pred_dev, void* hip_stream);
+
+/* Success / failure mode of every scene's trajectory (App. A.3), int32
+ * mode_dev[S]: the appendix's roman numeral (pick: i-iv success, v-ix
+ * failure; place: i-v success, vi-xii failure; open and close: i-iii
+ * success, iv-ix failure) as 1, 2, ...; 0 when no mode's condition holds.
+ * Modes are tested in this order, the first that holds wins:
+ *   pick success: iv, iii, i, ii; failure: v, vi, vii, viii, ix;
+ *   place success: v, i, ii, iii, iv; failure: vi, vii, viii, ix, x, xi, xii;
+ *   open / close success: iii, i, ii; failure: iv, v, vi, vii, viii, ix.
+ * The success modes "success then excessive collisions" are read with
+ * e_excessive in the list.  Stream-ordered. */
+ms_status ms_task_categorize(ms_batch* b, const ms_task* tasks_dev, const ms_episode* ep_dev, int32_t* mode_dev,
+                             void* hip_stream);
+
 /* Synchronise and read the per-scene status words of the last step
  * (bits MS_ST_*) into status_host[S].  Returns MS_E_NUMERIC if any scene
  * has MS_ST_NONFINITE or MS_ST_DEGENERATE set, MS_OK otherwise. */

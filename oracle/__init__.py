@@ -60,7 +60,8 @@ class OrDebug(C.Structure):
     _fields_ = [("status", C.c_void_p), ("n_contacts", C.c_void_p), ("key_hash", C.c_void_p),
                 ("act_hash", C.c_void_p), ("dump_cap", C.c_int32), ("dump_keys", C.c_void_p),
                 ("dump_phi", C.c_void_p), ("dump_lambda", C.c_void_p), ("robot_force", C.c_void_p),
-                ("robot_body_force", C.c_void_p)]
+                ("robot_body_force", C.c_void_p), ("grip_ee", C.c_uint32), ("grip_finger_l", C.c_int32),
+                ("grip_finger_r", C.c_int32), ("grip", C.c_void_p)]
 
 
 _lib = None
@@ -140,6 +141,8 @@ class Oracle:
         self.params = p
         self.S = batch.n_scenes
         self.nsf = batch.state_floats
+        # gripper outputs of step(debug=True): (end-effector body mask, finger L, finger R) or None
+        self.grip_cfg = None
 
     # ------------------------------------------------------------------
     def step(self, x, u, debug=False, dump_cap=0):
@@ -155,6 +158,8 @@ class Oracle:
                      key_hash=np.zeros((self.S, ns), np.uint64), act_hash=np.zeros((self.S, ns), np.uint64),
                      robot_force=np.zeros(self.S, np.float64),
                      robot_body_force=np.zeros((max(self.batch.n_free, 1), 3), np.float64))
+            if self.grip_cfg is not None:
+                d["grip"] = np.zeros((max(self.batch.n_free + self.batch.n_aux, 1), 2), np.float64)
             if dump_cap:
                 d["dump_keys"] = np.zeros((self.S, dump_cap), np.uint64)
                 d["dump_phi"] = np.zeros((self.S, dump_cap), np.float64)
@@ -163,6 +168,8 @@ class Oracle:
             for k, v in d.items():
                 setattr(dbg, k, _ptr(v))
             dbg.dump_cap = dump_cap
+            if self.grip_cfg is not None:
+                dbg.grip_ee, dbg.grip_finger_l, dbg.grip_finger_r = self.grip_cfg
         rc = lib().or_step(C.byref(self.sc), C.byref(self.params), _ptr(x), _ptr(u), _ptr(out), self.threads,
                            C.byref(dbg) if dbg is not None else None)
         if rc != 0:

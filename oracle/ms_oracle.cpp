@@ -456,6 +456,8 @@ struct SceneC {
   std::vector<std::array<double, 2>> aux_lim;
   double hold[ND];
   int f0;  // global index of the scene's first free body
+  int a0;  // global index of the scene's first door / drawer joint
+  int nf_all;  // free bodies in the batch (rows of the gripper output before the joints)
 };
 
 void load_scene(const or_scene* sc, const std::vector<ArtModel>& robots, int s, SceneC& c) {
@@ -501,6 +503,8 @@ void load_scene(const or_scene* sc, const std::vector<ArtModel>& robots, int s, 
   for (int x = 0; x < na; ++x) load_aux(sc, sc->aux_off[s] + x, c.aux[x], c.aux_box[x].data(), c.aux_lim[x].data());
   for (int j = 0; j < ND; ++j) c.hold[j] = sc->scene_hold[s * ND + j];
   c.f0 = sc->free_off[s];
+  c.a0 = sc->aux_off[s];
+  c.nf_all = sc->free_off[sc->n_scenes];
 }
 
 template <class T> struct FreeS {
@@ -972,6 +976,31 @@ template <class T> void substep(const SceneC& c, const or_params& pr, StateS<T>&
         }
       }
     }
+    if (dbg->grip) {
+      // gripper contacts per free body / door-drawer joint: the normal force
+      // of the end effector's bodies (summed over the substeps) and, in the
+      // last substep, the smaller of the two fingers' normal forces
+      const int nobj = (int)c.fr.size() + (int)c.aux.size();
+      for (int o = 0; o < nobj; ++o) {
+        const bool isf = o < (int)c.fr.size();
+        double fe = 0.0, fl = 0.0, fr = 0.0;
+        for (int ci = 0; ci < NC; ++ci) {
+          const Contact<T>& ct = con[ci];
+          if (!ct.robot_owner) continue;
+          const bool hit = isf ? (ct.B.kind == 2 && ct.B.body == o)
+                               : (ct.B.kind == 1 && ct.B.art == 1 + (o - (int)c.fr.size()));
+          if (!hit) continue;
+          const double fn = val(lam[ci][0]) / h;
+          const int body = ct.A.body;
+          if ((dbg->grip_ee >> body) & 1u) fe += fn;
+          if (body == dbg->grip_finger_l) fl += fn;
+          if (body == dbg->grip_finger_r) fr += fn;
+        }
+        double* g = dbg->grip + 2 * (isf ? (size_t)(c.f0 + o) : (size_t)c.nf_all + c.a0 + (o - (int)c.fr.size()));
+        g[0] += fe;
+        if (isub == n_sub - 1) g[1] = std::min(fl, fr);
+      }
+    }
     if (isub == n_sub - 1 && dbg->dump_cap > 0) {
       for (int ci = 0; ci < dbg->dump_cap; ++ci) {
         size_t o = (size_t)s * dbg->dump_cap + ci;
@@ -1143,6 +1172,8 @@ int or_step(const or_scene* sc, const or_params* pr, const double* x_in, const d
     for (int s = 0; s < S; ++s) dbg->robot_force[s] = 0.0;
   if (dbg && dbg->robot_body_force)
     for (size_t i = 0; i < (size_t)L.NF * 3; ++i) dbg->robot_body_force[i] = 0.0;
+  if (dbg && dbg->grip)
+    for (size_t i = 0; i < 2 * ((size_t)L.NF + L.NA); ++i) dbg->grip[i] = 0.0;
   std::vector<double> xin(x_in, x_in + (size_t)S * 2 * ND + (size_t)L.NF * 16 + (size_t)L.NA * 4);
   parallel_scenes(S, threads, [&](int s) {
     SceneC c;

@@ -93,6 +93,11 @@ typedef struct {
   double* robot_force;     // [S] sum over substeps of robot-owned normal impulses / h
   double* robot_body_force;  // [NF][3] sum over substeps of the force the robot's
                              // contacts exert on each free body (impulse / h)
+  uint32_t grip_ee;          // robot bodies of the end effector (bit mask)
+  int32_t grip_finger_l, grip_finger_r;  // finger bodies
+  double* grip;              // [NF + NA][2] end-effector normal force on each free body /
+                             // door-drawer joint summed over substeps; smaller finger
+                             // normal force on it in the last substep
 } or_debug;
 
 // One control step for every scene.  x_in / x_out: flat state

@@ -27,8 +27,9 @@ MS_ST_NONFINITE, MS_ST_OVERFLOW, MS_ST_DEGENERATE, MS_ST_ROBOT_OVERFLOW = 1, 2, 
 
 EXPORTS = ["ms_query_sizes", "ms_state_floats", "ms_create_batch", "ms_destroy_batch", "ms_set_schedule",
            "ms_get_schedule", "ms_autotune", "ms_step", "ms_step_backward", "ms_get_state", "ms_set_state",
-           "ms_scene_status", "ms_set_force_outputs", "ms_reset_robots", "ms_spawn_check", "ms_enable_debug", "ms_debug_contacts", "ms_enable_phase_profile", "ms_phase_cycles",
-           "ms_last_error"]
+           "ms_scene_status", "ms_set_force_outputs", "ms_reset_robots", "ms_spawn_check", "ms_enable_debug",
+           "ms_debug_contacts", "ms_enable_phase_profile", "ms_phase_cycles", "ms_set_task_robot",
+           "ms_set_grip_outputs", "ms_task_begin", "ms_task_update", "ms_task_categorize", "ms_last_error"]
 PHASES = ["drive+kinematics", "contacts", "dynamics", "rows", "levels", "pgs", "integrate", "load/store"]
 
 
@@ -70,6 +71,27 @@ class Schedule(C.Structure):
     _fields_ = [("flags", C.c_int32), ("grid", C.c_int32)]
 
 
+# subtask predicates / events (ms_task_* calls)
+MS_TASK_PICK, MS_TASK_PLACE, MS_TASK_OPEN, MS_TASK_CLOSE = 0, 1, 2, 3
+MS_IND_GRASPED, MS_IND_SUCCESS, MS_IND_OPEN, MS_IND_SLIGHT = 1, 2, 4, 8
+MS_IND_AT_GOAL, MS_IND_CONTACT, MS_IND_EXCESSIVE = 16, 32, 64
+MS_EP_LIST = 16
+PRED_FIELDS = ["d_ee", "j_arm", "j_torso", "qd_arm", "d_goal", "aq", "f_ee", "f_finger"]
+
+
+class TaskRobot(C.Structure):
+    _fields_ = [(n, C.c_int32) for n in ("ee_body", "base_body", "base_x", "base_y", "base_yaw", "arm0", "narm",
+                                          "torso", "finger_l", "finger_r")] + [
+        ("ee_bodies", C.c_uint32), ("ee_offset", C.c_float * 3), ("ee_rest", C.c_float * 3),
+        ("q_rest", C.c_float * 16), ("grasp_force", C.c_float)]
+
+
+# device layouts of ms_task [S] and ms_episode [S]
+TASK_DTYPE = np.dtype([("kind", "<i4"), ("target", "<i4"), ("goal", "<f4", 3), ("open_frac", "<f4")])
+EPISODE_DTYPE = np.dtype([("cumcol", "<f4"), ("aq0", "<f4"), ("d0", "<f4"), ("ind", "<u4"), ("t", "<i4"),
+                          ("n", "<i4"), ("last", "<i4", 8), ("list", "u1", MS_EP_LIST)])
+
+
 _lib = None
 
 
@@ -102,6 +124,11 @@ def lib():
             "ms_debug_contacts": [vp, vp],
             "ms_enable_phase_profile": [vp, i32],
             "ms_phase_cycles": [vp, vp],
+            "ms_set_task_robot": [vp, vp],
+            "ms_set_grip_outputs": [vp, vp],
+            "ms_task_begin": [vp, vp, vp, vp, vp, vp, vp, vp],
+            "ms_task_update": [vp, vp, vp, vp, vp, vp, vp, vp],
+            "ms_task_categorize": [vp, vp, vp, vp, vp],
         }
         for name, args in sig.items():
             f = getattr(L, name)
@@ -269,6 +296,90 @@ class MsBatch:
         _check(lib().ms_set_force_outputs(self.h, None, None), "ms_set_force_outputs")
         self.robot_force = self.body_force = None
         return None
+
+    # ------------------------------------------------------------------ tasks
+    def set_task_robot(self, robot):
+        """The robot as the task predicates see it: a dict with the fields of
+        ms_task_robot (ee_body, base_body, base_x, base_y, base_yaw, arm0, narm,
+        torso, finger_l, finger_r, ee_bodies, ee_offset, ee_rest, q_rest,
+        grasp_force)."""
+        r = TaskRobot()
+        for k, _ in TaskRobot._fields_:
+            v = robot[k]
+            if k in ("ee_offset", "ee_rest", "q_rest"):
+                arr = getattr(r, k)
+                for i, e in enumerate(np.asarray(v, np.float64).reshape(-1)):
+                    arr[i] = float(e)
+            else:
+                setattr(r, k, float(v) if k == "grasp_force" else int(v))
+        _check(lib().ms_set_task_robot(self.h, C.byref(r)), "ms_set_task_robot")
+
+    def enable_grip(self, on=True):
+        """Gripper contact outputs of every following ``step``: float32
+        [NF + NA, 2] (end-effector normal force summed over the substeps; the
+        smaller finger force in the last substep), or None when off."""
+        t = self.torch
+        if on:
+            self.grip = t.zeros((max(self.n_free + self.n_aux, 1), 2), dtype=t.float32, device=self.device)
+            _check(lib().ms_set_grip_outputs(self.h, _ptr_t(self.grip)), "ms_set_grip_outputs")
+            return self.grip
+        _check(lib().ms_set_grip_outputs(self.h, None), "ms_set_grip_outputs")
+        self.grip = None
+        return None
+
+    def task_tensor(self, tasks):
+        """Device copy of per-scene tasks (a TASK_DTYPE array or a list of dicts)."""
+        if not (isinstance(tasks, np.ndarray) and tasks.dtype == TASK_DTYPE):
+            arr = np.zeros(self.S, TASK_DTYPE)
+            for s, tk in enumerate(tasks):
+                arr[s]["kind"], arr[s]["target"] = int(tk["kind"]), int(tk["target"])
+                arr[s]["goal"] = np.asarray(tk.get("goal", (0.0, 0.0, 0.0)), np.float32)
+                arr[s]["open_frac"] = float(tk.get("open_frac", 0.9))
+            tasks = arr
+        if tasks.shape != (self.S,):
+            raise MsError(f"tasks: expected {self.S} entries")
+        return self.torch.from_numpy(np.ascontiguousarray(tasks).view(np.uint8).copy()).to(self.device)
+
+    def new_episodes(self):
+        return self.torch.zeros(self.S * EPISODE_DTYPE.itemsize, dtype=self.torch.uint8, device=self.device)
+
+    @staticmethod
+    def episodes(ep):
+        """Host copy of an episode tensor as an EPISODE_DTYPE array."""
+        return ep.cpu().numpy().view(EPISODE_DTYPE)
+
+    def _pred(self, pred):
+        if pred is True:
+            return self.torch.zeros((self.S, 8), dtype=self.torch.float32, device=self.device)
+        return pred if pred is not None and pred is not False else None
+
+    def task_begin(self, x, tasks_t, ep=None, grip=None, mask=None, pred=None, stream=None):
+        """Starts the episodes of the masked scenes (all when mask is None);
+        returns (episodes, predicate values or None)."""
+        self._check_state(x, "state")
+        ep = self.new_episodes() if ep is None else ep
+        pred = self._pred(pred)
+        _check(lib().ms_task_begin(self.h, _ptr_t(x), _ptr_t(tasks_t), _ptr_t(grip) if grip is not None else None,
+                                   _ptr_t(ep), _ptr_t(mask) if mask is not None else None,
+                                   _ptr_t(pred) if pred is not None else None, _stream(stream)), "ms_task_begin")
+        return ep, pred
+
+    def task_update(self, x, tasks_t, ep, robot_force, grip=None, pred=None, stream=None):
+        """Predicates and events after one control step; returns the
+        predicate values (or None)."""
+        self._check_state(x, "state")
+        pred = self._pred(pred)
+        _check(lib().ms_task_update(self.h, _ptr_t(x), _ptr_t(tasks_t), _ptr_t(robot_force),
+                                    _ptr_t(grip) if grip is not None else None, _ptr_t(ep),
+                                    _ptr_t(pred) if pred is not None else None, _stream(stream)), "ms_task_update")
+        return pred
+
+    def task_categorize(self, tasks_t, ep, stream=None):
+        """int32 [S]: success / failure mode of every episode (0: none)."""
+        out = self.torch.zeros(self.S, dtype=self.torch.int32, device=self.device)
+        _check(lib().ms_task_categorize(self.h, _ptr_t(tasks_t), _ptr_t(ep), _ptr_t(out), _stream(stream)),
+               "ms_task_categorize")
+        return out
 
     def reset_robots(self, x, base, noise, clip, mask=None, stream=None):
         """Robot resets of the masked scenes in place: q = base + clip(noise), qd = 0."""

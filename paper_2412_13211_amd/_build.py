@@ -8,8 +8,8 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 LIB = os.path.join(HERE, "libms_phys.so")
-SOURCES = [os.path.join(HERE, "csrc", f) for f in ("ms_kernels.hip", "ms_backward.hip", "ms_api.hip")]
-HEADERS = [os.path.join(HERE, "csrc", f) for f in ("ms_internal.h", "ms_pack.h", "ms_adjoint.h", "ms_backward.h")] + \
+SOURCES = [os.path.join(HERE, "csrc", f) for f in ("ms_kernels.hip", "ms_backward.hip", "ms_tasks.hip", "ms_api.hip")]
+HEADERS = [os.path.join(HERE, "csrc", f) for f in ("ms_internal.h", "ms_pack.h", "ms_adjoint.h", "ms_backward.h", "ms_tasks.h")] + \
     [os.path.join(ROOT, "include", "ms_phys.h")]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")

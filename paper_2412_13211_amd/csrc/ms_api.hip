@@ -21,6 +21,7 @@
 #include "ms_internal.h"
 #include "ms_pack.h"
 #include "ms_backward.h"
+#include "ms_tasks.h"
 
 using namespace msk;
 
@@ -49,6 +50,10 @@ struct ms_batch {
   bool profile_on;
   float* frc_robot;
   float* frc_body;
+  std::vector<int> model_nb;
+  bool task_robot_set;
+  ms_task_robot task_robot;
+  float* grip;
   hipStream_t cap_stream;
   // graphs keyed by (x_in, u, x_out)
   std::map<std::tuple<const void*, const void*, void*>, hipGraphExec_t> graphs;
@@ -102,6 +107,10 @@ KArgs make_args(const ms_batch* b, const void* x_in, const float* u, void* x_out
   a.L = lds_for(&b->desc, b->cnt, a.stage_static);
   a.frc_robot = b->frc_robot;
   a.frc_body = b->frc_body;
+  a.grip = b->grip;
+  a.grip_ee = b->task_robot.ee_bodies;
+  a.grip_fl = b->task_robot.finger_l;
+  a.grip_fr = b->task_robot.finger_r;
   return a;
 }
 
@@ -252,6 +261,11 @@ ms_status ms_create_batch(const ms_batch_desc* d, const ms_scene_desc* sc, void*
   b->profile_on = false;
   b->frc_robot = nullptr;
   b->frc_body = nullptr;
+  b->model_nb.assign(sc->model_nb, sc->model_nb + c.M);
+  b->task_robot_set = false;
+  std::memset(&b->task_robot, 0, sizeof b->task_robot);
+  b->task_robot.finger_l = b->task_robot.finger_r = -1;
+  b->grip = nullptr;
   if (hipStreamCreateWithFlags(&b->cap_stream, hipStreamNonBlocking) != hipSuccess) {
     delete b;
     return fail(MS_E_HIP, "hipStreamCreateWithFlags failed");
@@ -349,6 +363,7 @@ ms_status enqueue_record(ms_batch* b, const void* x_in, const float* u, float* r
   a.phase_cycles = nullptr;
   a.frc_robot = nullptr;
   a.frc_body = nullptr;
+  a.grip = nullptr;
   a.rec = rec;
   a.RL = bwd_rec(&b->desc, b->cnt);
   size_t lds = lds_bytes_of(a);
@@ -393,6 +408,86 @@ ms_status ms_set_force_outputs(ms_batch* b, float* robot_force, float* body_forc
   drop_graphs(b);
   b->frc_robot = robot_force;
   b->frc_body = body_force;
+  return MS_OK;
+}
+
+ms_status ms_set_task_robot(ms_batch* b, const ms_task_robot* r) {
+  if (!b || !r) return fail(MS_E_INVALID, "ms_set_task_robot: null argument");
+  for (size_t m = 0; m < b->model_nb.size(); ++m) {
+    const int nb = b->model_nb[m];
+    auto in = [&](int i) { return i >= 0 && i < nb; };
+    if (!in(r->ee_body) || !in(r->base_body) || !in(r->finger_l) || !in(r->finger_r))
+      return fail(MS_E_INVALID, "ms_set_task_robot: body index out of range for model %zu (%d bodies)", m, nb);
+    if (!in(r->base_x) || !in(r->base_y) || !in(r->base_yaw) || (r->torso != -1 && !in(r->torso)))
+      return fail(MS_E_INVALID, "ms_set_task_robot: DoF index out of range for model %zu (%d DoFs)", m, nb);
+    if (r->narm < 0 || (r->narm > 0 && (!in(r->arm0) || !in(r->arm0 + r->narm - 1))))
+      return fail(MS_E_INVALID, "ms_set_task_robot: arm DoFs out of range for model %zu", m);
+    if (nb < 32 && (r->ee_bodies >> nb) != 0u)
+      return fail(MS_E_INVALID, "ms_set_task_robot: ee_bodies names a body past model %zu's %d", m, nb);
+  }
+  if (!(r->grasp_force >= 0.f)) return fail(MS_E_INVALID, "ms_set_task_robot: grasp_force must be >= 0");
+  drop_graphs(b);
+  b->task_robot = *r;
+  b->task_robot_set = true;
+  return MS_OK;
+}
+
+ms_status ms_set_grip_outputs(ms_batch* b, float* grip) {
+  if (!b) return fail(MS_E_INVALID, "null batch");
+  if (grip && !b->task_robot_set) return fail(MS_E_STATE, "ms_set_grip_outputs: call ms_set_task_robot first");
+  drop_graphs(b);
+  b->grip = grip;
+  return MS_OK;
+}
+
+}  // extern "C"
+
+namespace {
+ms_status task_eval(ms_batch* b, const void* x, const ms_task* tasks, const float* robot_force, const float* grip,
+                    ms_episode* ep, const uint8_t* mask, float* pred, void* hip_stream) {
+  if (!b) return fail(MS_E_INVALID, "null batch");
+  if (!x || !tasks || !ep) return fail(MS_E_INVALID, "task call: null state, tasks or episode buffer");
+  if (!b->task_robot_set) return fail(MS_E_STATE, "task call: call ms_set_task_robot first");
+  TaskArgs a;
+  std::memset(&a, 0, sizeof a);
+  a.models = reinterpret_cast<const DModel*>(b->params + b->pl.models);
+  a.scenes = reinterpret_cast<const DScene*>(b->params + b->pl.scenes);
+  a.aux = reinterpret_cast<const DAux*>(b->params + b->pl.aux);
+  a.x = static_cast<const float*>(x);
+  a.tasks = tasks;
+  a.robot_force = robot_force;
+  a.grip = grip;
+  a.mask = mask;
+  a.ep = ep;
+  a.pred = pred;
+  a.robot = b->task_robot;
+  a.S = b->cnt.S;
+  a.NF = b->cnt.NF;
+  a.n_sub = b->desc.n_substeps;
+  launch_task_eval(a, static_cast<hipStream_t>(hip_stream));
+  HIP_TRY(hipGetLastError());
+  return MS_OK;
+}
+}  // namespace
+
+extern "C" {
+
+ms_status ms_task_begin(ms_batch* b, const void* x, const ms_task* tasks, const float* grip, ms_episode* ep,
+                        const uint8_t* mask, float* pred, void* hip_stream) {
+  return task_eval(b, x, tasks, nullptr, grip, ep, mask, pred, hip_stream);
+}
+
+ms_status ms_task_update(ms_batch* b, const void* x, const ms_task* tasks, const float* robot_force, const float* grip,
+                         ms_episode* ep, float* pred, void* hip_stream) {
+  if (!robot_force) return fail(MS_E_INVALID, "ms_task_update: robot_force_dev is required");
+  return task_eval(b, x, tasks, robot_force, grip, ep, nullptr, pred, hip_stream);
+}
+
+ms_status ms_task_categorize(ms_batch* b, const ms_task* tasks, const ms_episode* ep, int32_t* mode, void* hip_stream) {
+  if (!b) return fail(MS_E_INVALID, "null batch");
+  if (!tasks || !ep || !mode) return fail(MS_E_INVALID, "ms_task_categorize: null buffer");
+  launch_task_categorize(tasks, ep, mode, b->cnt.S, static_cast<hipStream_t>(hip_stream));
+  HIP_TRY(hipGetLastError());
   return MS_OK;
 }
 

@@ -162,6 +162,9 @@ struct KArgs {
   RecLayout RL;
   float* frc_robot;        // [S] contact-force outputs, or null
   float* frc_body;         // [NF][4]
+  float* grip;             // [NF + NA][2] gripper contact outputs, or null
+  uint32_t grip_ee;        // robot bodies of the end effector (bit mask)
+  int grip_fl, grip_fr;    // finger bodies
 };
 
 void launch_step(const KArgs& a, int grid, size_t lds_bytes, hipStream_t st);

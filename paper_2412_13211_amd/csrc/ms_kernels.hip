@@ -162,12 +162,12 @@ __device__ __forceinline__ Robot robot_view(float* base, float* dyn) {
 // free-body fields (structure of arrays, stride fmax)
 enum FF {
   F_X = 0, F_Q = 3, F_V = 7, F_W = 10, F_R = 13, F_II = 22, F_FRC = 28, F_IM = 31, F_TYPE = 32, F_H = 33, F_IB = 36,
-  F_N = 39
+  F_EE = 39, F_FMIN = 40, F_N = 41
 };
 // aux fields (stride AMAX)
 enum AF {
   A_Q = 0, A_QD = 1, A_V = 2, A_R = 3, A_P = 12, A_AX = 15, A_BC = 18, A_IM = 21, A_BH = 22, A_LO = 25, A_HI = 26,
-  A_TYPE = 27, A_LIM = 28, A_M = 29, A_N = 30
+  A_TYPE = 27, A_LIM = 28, A_M = 29, A_EE = 30, A_FMIN = 31, A_N = 32
 };
 // contact fields (structure of arrays, stride ccap)
 // C_KEY: owner sphere index or box vertex (bits 0..7), target class (8..9),
@@ -1641,11 +1641,44 @@ __device__ __forceinline__ void phase_integrate(const KArgs& a, const Scene& S, 
 // / h (all lanes hold it), and per free body the force the robot's contacts
 // exert on it (the negative of the impulse on the robot side, / h),
 // accumulated in the body's record.
-__device__ __forceinline__ void phase_forces(const KArgs& a, const Scene& S, float* L, int NL, int NR, float& frc) {
+__device__ __forceinline__ void phase_forces(const KArgs& a, const Scene& S, float* L, int NL, int NR, float& frc,
+                                             bool last) {
   const int lane = lane_id();
   const float* C = L + a.L.con;
   float* F = L + a.L.fr;
   const int fm = a.L.fmax;
+  if (a.grip) {
+    // gripper contacts, one lane per free body / door-drawer joint: the
+    // normal force of the end effector's bodies on it (accumulated), and in
+    // the last substep the smaller of the two fingers' normal forces on it
+    float* A = L + a.L.aux;
+    for (int o = lane; o < S.nf + S.na; o += WAVE) {
+      const bool isf = o < S.nf;
+      const int want = isf ? ((K_FREE << 8) | o) : ((K_AUX << 8) | (o - S.nf));
+      float fe = 0.f, fl = 0.f, fr = 0.f;
+      for (int ci = NL; ci < NL + NR; ++ci) {
+        const float* c = C + ci * CSTR;
+        const int info = __float_as_int(c[C_INFO]);
+        if (((info >> 16) & 0xffff) != want) continue;
+        const int body = side_idx(info & 0xffff);  // a robot side carries its body
+        const float fn = c[C_LAM] / a.h;
+        if ((a.grip_ee >> body) & 1u) fe += fn;
+        if (body == a.grip_fl) fl += fn;
+        if (body == a.grip_fr) fr += fn;
+      }
+      if (isf) {
+        F[o * FSTR + F_EE] += fe;
+        if (last) F[o * FSTR + F_FMIN] = fminf(fl, fr);
+      } else {
+        A[A_EE * AMAX + o - S.nf] += fe;
+        if (last) A[A_FMIN * AMAX + o - S.nf] = fminf(fl, fr);
+      }
+    }
+  }
+  if (!a.frc_robot) {
+    wave_sync();
+    return;
+  }
   float part = 0.f;
   for (int ci = NL + lane; ci < NL + NR; ci += WAVE) part += C[ci * CSTR + C_LAM];
   for (int off = 32; off > 0; off >>= 1) part += __shfl_xor(part, off, WAVE);
@@ -1699,9 +1732,17 @@ __device__ __forceinline__ void run_scene(const KArgs& a, int s, float* L) {
   float frc = 0.f;
   if (MODE == 2) {
     float* F = L + a.L.fr;
+    float* A = L + a.L.aux;
     const int fm = a.L.fmax;
-    for (int f = lane; f < S.nf; f += WAVE)
+    for (int f = lane; f < S.nf; f += WAVE) {
       for (int t = 0; t < 3; ++t) F[(f) * FSTR + F_FRC + t] = 0.f;
+      F[(f) * FSTR + F_EE] = 0.f;
+      F[(f) * FSTR + F_FMIN] = 0.f;
+    }
+    if (lane < S.na) {
+      A[A_EE * AMAX + lane] = 0.f;
+      A[A_FMIN * AMAX + lane] = 0.f;
+    }
     wave_sync();
   }
   float* rec = REC ? a.rec + (size_t)s * a.RL.total : nullptr;
@@ -1724,7 +1765,7 @@ __device__ __forceinline__ void run_scene(const KArgs& a, int s, float* L) {
     int maxl = phase_levels(a, L, NC, NR, NL);
     MS_PHASE(4)
     phase_pgs(a, S, L, NC, NL, maxl, vR, rec ? rec + a.RL.tape + (size_t)ks * a.K * a.RL.tsw : nullptr);
-    if (MODE == 2) phase_forces(a, S, L, NL, NR, frc);
+    if (MODE == 2) phase_forces(a, S, L, NL, NR, frc, ks == a.n_sub_total - 1);
     MS_PHASE(5)
     phase_integrate(a, S, L, rb, vR);
     MS_PHASE(6)
@@ -1738,7 +1779,20 @@ __device__ __forceinline__ void run_scene(const KArgs& a, int s, float* L) {
     }
   }
   store_scene(a, S, L, rb, status);
-  if (MODE == 2) {
+  if (MODE == 2 && a.grip) {
+    const float* F = L + a.L.fr;
+    const float* A = L + a.L.aux;
+    const int fm = a.L.fmax;
+    const bool last = a.sub0 + a.n_sub == a.n_sub_total;
+    for (int o = lane; o < S.nf + S.na; o += WAVE) {
+      const bool isf = o < S.nf;
+      float* dst = a.grip + 2 * (isf ? (size_t)(S.f0 + o) : (size_t)a.NF + S.a0 + (o - S.nf));
+      const float fe = isf ? F[o * FSTR + F_EE] : A[A_EE * AMAX + o - S.nf];
+      dst[0] = a.sub0 == 0 ? fe : dst[0] + fe;
+      if (last) dst[1] = isf ? F[o * FSTR + F_FMIN] : A[A_FMIN * AMAX + o - S.nf];
+    }
+  }
+  if (MODE == 2 && a.frc_robot) {
     const float* F = L + a.L.fr;
     const int fm = a.L.fmax;
     if (lane == 0) a.frc_robot[s] = a.sub0 == 0 ? frc : a.frc_robot[s] + frc;
@@ -1962,7 +2016,7 @@ __global__ void k_masked_copy(float* dst, const float* src, const uint8_t* mask,
 
 void launch_step(const KArgs& a, int grid, size_t lds_bytes, hipStream_t st) {
   if (a.rec) hipLaunchKernelGGL(k_step_rec, dim3(grid), dim3(WAVE), lds_bytes, st, a);
-  else if (a.frc_robot) hipLaunchKernelGGL(k_step_frc, dim3(grid), dim3(WAVE), lds_bytes, st, a);
+  else if (a.frc_robot || a.grip) hipLaunchKernelGGL(k_step_frc, dim3(grid), dim3(WAVE), lds_bytes, st, a);
   else hipLaunchKernelGGL(k_step, dim3(grid), dim3(WAVE), lds_bytes, st, a);
 }
 void launch_reset_queue(int* q, hipStream_t st) { hipLaunchKernelGGL(k_reset_queue, dim3(1), dim3(64), 0, st, q); }

@@ -424,6 +424,48 @@ def fetch_like_model(g):
     return mb.arrays()
 
 
+# Bodies and DoFs of the Fetch-like model as the subtask predicates use them:
+# end effector = the last arm link with the point between the fingers, base
+# frame = the yaw body, fingers = the two prismatic finger bodies.  The
+# end-effector rest position is the caller's (e.g. the point at FETCH_REST).
+FETCH_TASK_ROBOT = dict(ee_body=12, base_body=2, base_x=0, base_y=1, base_yaw=2, arm0=6, narm=7, torso=3,
+                        finger_l=13, finger_r=14, ee_bodies=(1 << 12) | (1 << 13) | (1 << 14),
+                        ee_offset=(0.19, 0.0, 0.0), q_rest=tuple(float(v) for v in FETCH_REST), grasp_force=0.5)
+
+TASK_PICK, TASK_PLACE, TASK_OPEN, TASK_CLOSE = 0, 1, 2, 3
+
+
+def tasks(batch, kinds=(TASK_PICK, TASK_PLACE, TASK_OPEN, TASK_CLOSE), seed=BASE_SEED):
+    """Per-scene subtasks (list of dicts kind, target, goal, open_frac).
+
+    Scene s takes kinds[s % len(kinds)] (a kind whose target does not exist
+    in the scene falls back to pick / place); draws come from
+    SeedSequence([seed, 1000 + cfg, s]): a random free body (pick, place), a
+    place goal within 0.3 m of that body's start position in x and y, a
+    random door / drawer joint (open, close) and open_frac 0.75 for every
+    fourth scene (the fridge case) else 0.9."""
+    ids = batch.scene_ids()
+    st = split_state(batch.state0, batch.n_scenes, batch.n_free, batch.n_aux)
+    out = []
+    for s in range(batch.n_scenes):
+        g = _rng(seed, 1000 + batch.cfg_id, int(ids[s]))
+        kind = int(kinds[s % len(kinds)])
+        nf = int(batch.free_off[s + 1] - batch.free_off[s])
+        na = int(batch.aux_off[s + 1] - batch.aux_off[s])
+        if kind in (TASK_OPEN, TASK_CLOSE) and na == 0:
+            kind = TASK_PICK if kind == TASK_OPEN else TASK_PLACE
+        t = dict(kind=kind, target=0, goal=(0.0, 0.0, 0.0), open_frac=0.75 if int(ids[s]) % 4 == 3 else 0.9)
+        if kind in (TASK_PICK, TASK_PLACE):
+            t["target"] = int(g.integers(0, max(nf, 1)))
+            if nf:
+                p = st["free"][batch.free_off[s] + t["target"], :3].astype(np.float64)
+                t["goal"] = (float(p[0] + g.uniform(-0.3, 0.3)), float(p[1] + g.uniform(-0.3, 0.3)), float(p[2]))
+        else:
+            t["target"] = int(g.integers(0, na))
+        out.append(t)
+    return out
+
+
 def _stack_models(models):
     keys = ["parent", "jtype", "axis", "xt_rot", "xt_pos", "mass", "com", "inertia", "kp", "kd", "veldof",
             "armature", "damping", "act_kind", "act_scale", "sph_body", "sph", "sph_flags"]
