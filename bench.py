@@ -136,6 +136,47 @@ def time_fwd_bwd(mb, x0, U, args, flags, stream, torch):
             "bwd_ms_per_step": round(bwd_ms / T, 4), "finite": ok}
 
 
+def time_env_outputs(mb, b, x0, U, args, flags, stream, torch, ms, sg):
+    """Cost of the environment outputs around the step: the forward step with
+    the contact-force and gripper outputs on, and one subtask predicate /
+    event update (ms_task_update) per control step.  Fetch-like robots only.
+    The end-effector rest position is the paper's (0.5, 0, 1.25) m; it does
+    not change the cost."""
+    r = dict(sg.FETCH_TASK_ROBOT)
+    r["ee_rest"] = (0.5, 0.0, 1.25)
+    try:
+        mb.set_task_robot(r)
+    except ms.MsError:
+        return None
+    rf, _ = mb.enable_forces()
+    grip = mb.enable_grip()
+    tt = mb.task_tensor(sg.tasks(b))
+    mb.set_schedule(flags)
+    xa, xb = x0.clone(), torch.empty_like(x0)
+    ep, _ = mb.task_begin(xa, tt)
+    for t in range(min(args.warmup, U.shape[0])):
+        mb.step(xa, U[t], out=xb)
+        mb.task_update(xb, tt, ep, rf, grip=grip)
+        xa, xb = xb, xa
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(4)]
+    n = args.steps
+    ev[0].record(stream)
+    for t in range(n):
+        mb.step(xa, U[t % U.shape[0]], out=xb)
+        xa, xb = xb, xa
+    ev[1].record(stream)
+    ev[2].record(stream)
+    for t in range(n):
+        mb.task_update(xa, tt, ep, rf, grip=grip)
+    ev[3].record(stream)
+    torch.cuda.synchronize()
+    events = int(mb.episodes(ep)["n"].sum())
+    mb.enable_grip(False)
+    mb.enable_forces(False)
+    return {"fwd_with_outputs_ms_per_step": round(ev[0].elapsed_time(ev[1]) / n, 4),
+            "task_update_ms": round(ev[2].elapsed_time(ev[3]) / n, 4), "events_recorded": events}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -235,6 +276,7 @@ def main():
                                        ms.MS_SCHED_CULL, True)
     fwd_bwd = None if args.no_bwd else time_fwd_bwd(mb, x0, U, args, flags, stream, torch)
     st = mb.status()
+    env_out = time_env_outputs(mb, b, x0, U, args, flags, stream, torch, ms, sg)
     value = S * args.steps / wall
     ms_per_step = 1e3 * wall / args.steps
     launch_ms = gpu_ms / args.steps  # one kernel launch per control step in the fused schedules
@@ -274,6 +316,8 @@ def main():
     }
     if fwd_bwd is not None:
         out["fwd_bwd"] = fwd_bwd
+    if env_out is not None:
+        out["env_outputs"] = env_out
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline(b)
     print(json.dumps(out), flush=True)

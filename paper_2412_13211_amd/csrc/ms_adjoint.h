@@ -146,16 +146,26 @@ struct Prm {
 // per-scene state record: q[16] qd[16] | free[fmax][16] | aux[AMAX][4]
 MSA_HD inline int state_rec_floats(int fmax) { return 32 + 16 * fmax + 4 * AMAX; }
 
-// contact record
-enum {
-  C_OK = 0, C_OI = 1, C_OV = 2, C_TK = 3, C_TI = 4, C_R = 5, C_C = 6, C_PHI = 9, C_N = 10, C_P = 13, C_T1 = 16,
-  C_T2 = 19, C_W = 22, C_BIAS = 25, CR = 28
+// contact record: packed side codes, owner radius, phi, normal, contact
+// point, tangents, W per direction, bias (the owner's centre is p + r n)
+enum { C_ID = 0, C_R = 1, C_PHI = 2, C_N = 3, C_P = 6, C_T1 = 9, C_T2 = 12, C_W = 15, C_BIAS = 18, CR = 19 };
+// side codes of a contact packed into the bits of one float: owner kind
+// (bits 0-1), owner vertex (2-4), target kind (5-6), owner index (7-14),
+// target index (15-30)
+struct Ids {
+  int ok, oi, ov, tk, ti;
 };
-// contact adjoint record: direction adjoints (n, t1, t2), contact point, W,
-// bias, and the adjoint of a door/drawer target's Jacobian entry per direction
-enum { B_D = 0, B_P = 9, B_W = 12, B_BIAS = 15, B_AJ = 16, CB = 19 };
+MSA_HD inline float pack_ids(int ok, int oi, int ov, int tk, int ti) {
+  return __builtin_bit_cast(float, ok | (ov << 2) | (tk << 5) | (oi << 7) | (ti << 15));
+}
+MSA_HD inline Ids unpack_ids(float f) {
+  const int v = __builtin_bit_cast(int, f);
+  return Ids{v & 3, (v >> 7) & 255, (v >> 2) & 7, (v >> 5) & 3, (v >> 15) & 0xffff};
+}
+// contact adjoint record: direction adjoints (n, t1, t2), contact point, W, bias
+enum { B_D = 0, B_P = 9, B_W = 12, B_BIAS = 15, CB = 16 };
 // free-body adjoint record
-enum { F_XB = 0, F_RB = 3, F_IIB = 12, F_IWB = 21, FB = 32 };
+enum { F_XB = 0, F_RB = 3, F_IIB = 12, F_IWB = 21, FB = 30 };
 // door / drawer adjoint record
 enum { X_RB = 0, X_BCB = 9, X_QB = 12, XB = 16 };
 
@@ -165,6 +175,7 @@ MSA_HD inline int lv_rows(int ccap) { return 2 * AMAX + ccap; }
 MSA_HD inline int lv_ints(int ccap) { return 4 * lv_rows(ccap) + 4 + 64 + 8; }
 
 struct WS {
+  int wave;  // the wavefront kernel's LDS layout
   int fmax, ntmax, ccap, rcap, K, nsub, ss;
   int st, gA, gB, ub, tape;
   int kR, kp, ka, ko, kc, kIcw, ks, kI, kIc, sph, tl;
@@ -183,6 +194,7 @@ struct WS {
 // record, the tape and candidate lists elsewhere, plus the level schedule)
 MSA_HD inline WS ws_layout(int fmax, int ntmax, int ccap, int rcap, int K, int nsub, bool wave = false) {
   WS w;
+  w.wave = wave ? 1 : 0;
   w.fmax = fmax < 1 ? 1 : fmax;
   w.ntmax = ntmax < 1 ? 1 : ntmax;
   w.ccap = ccap;
@@ -200,7 +212,7 @@ MSA_HD inline WS ws_layout(int fmax, int ntmax, int ccap, int rcap, int K, int n
   w.tape = take(wave ? 0 : K * 3 * (2 * AMAX + ccap));
   w.kR = take(ND * 9); w.kp = take(ND * 3); w.ka = take(ND * 3); w.ko = take(ND * 3); w.kc = take(ND * 3);
   w.kIcw = take(ND * 6); w.ks = take(ND * 6); w.kI = take(ND * 36); w.kIc = take(ND * 36);
-  w.sph = take(SPH * 3);
+  w.sph = take(wave ? 0 : SPH * 3);  // sphere centres: only the lane kernel's contact search reads them
   w.tl = take(wave ? 0 : (ND + 1) * (w.ntmax + 1));
   w.fR = take(fm * 9); w.fIw = take(fm * 9); w.fIi = take(fm * 9);
   w.xR = take(AMAX * 9); w.xbc = take(AMAX * 3); w.xa = take(AMAX * 3); w.xo = take(AMAX * 3);
@@ -215,10 +227,15 @@ MSA_HD inline WS ws_layout(int fmax, int ntmax, int ccap, int rcap, int K, int n
   w.vRb = take(ND); w.vAb = take(AMAX); w.vFb = take(fm * 6);
   w.lamb = take(3 * ccap); w.llamb = take(2 * AMAX); w.limb = take(2 * AMAX);
   w.conb = take(ccap * CB);
-  w.rJb = take(w.rcap * 3 * ND); w.rwb = take(w.rcap * 3 * ND);
+  // the robot rows' adjoints are dead once rows^T is done; the dynamics^T
+  // scratch (written before it is read) shares their space
+  const int rows_b = 2 * w.rcap * 3 * ND, dyn_b = ND * 6 + 2 * ND * 36 + 3 * ND * 6;
+  const int kb = take(rows_b > dyn_b ? rows_b : dyn_b);
+  w.rJb = kb; w.rwb = kb + w.rcap * 3 * ND;
+  w.sb = kb; w.Ib = w.sb + ND * 6; w.Icb = w.Ib + ND * 36;
+  w.fbar = w.Icb + ND * 36; w.abar = w.fbar + ND * 6; w.vbar = w.abar + ND * 6;
   w.fb = take(fm * FB); w.xb = take(AMAX * XB);
-  w.Mb = take(ND * ND); w.sb = take(ND * 6); w.Ib = take(ND * 36); w.Icb = take(ND * 36);
-  w.fbar = take(ND * 6); w.abar = take(ND * 6); w.vbar = take(ND * 6);
+  w.Mb = take(ND * ND);
   w.bacc = take(ND * 9);
   w.lv = take(wave ? lv_ints(ccap) : 0);
   w.Minv = take(wave ? ND * ND : 0);
@@ -348,6 +365,7 @@ struct Eng {
   MSA_HD float& tape_at(int it, int r, int d) const { return tb[(long)it * tsw + 3 * r + d]; }
 
   MSA_HD float& at(long e) const { return b[e]; }
+  MSA_HD Ids ids(long e) const { return unpack_ids(b[e + C_ID]); }
   MSA_HD V v3(long e) const { return bl3(b, e); }
   MSA_HD void s3(long e, V v) const { bs3(b, e, v); }
   MSA_HD void a3(long e, V v) const { ba3(b, e, v); }
@@ -442,7 +460,7 @@ struct Eng {
       for (int t = 0; t < 6; ++t) at(w.kIcw + i * 6 + t) = Sw[t];
       spatial_inertia(M.mass[i], c, W, w.kI + i * 36);
     }
-    for (int k = 0; k < nsph; ++k) {
+    for (int k = 0; k < nsph && !w.wave; ++k) {
       int bi = M.sph_body[k];
       float R[9];
       ld9(w.kR + bi * 9, R);
@@ -614,13 +632,8 @@ struct Eng {
     long e = w.con + (long)nc * CR;
     int tk, ti;
     target_code(t, tk, ti);
-    at(e + C_OK) = (float)okind;
-    at(e + C_OI) = (float)oidx;
-    at(e + C_OV) = (float)overt;
-    at(e + C_TK) = (float)tk;
-    at(e + C_TI) = (float)ti;
+    at(e + C_ID) = pack_ids(okind, oidx, overt, tk, ti);
     at(e + C_R) = r;
-    s3(e + C_C, c);
     at(e + C_PHI) = phi;
     s3(e + C_N, n);
     s3(e + C_P, c - n * r);
@@ -883,7 +896,8 @@ struct Eng {
       s3(e + C_T1, t1);
       s3(e + C_T2, t2);
       V p = v3(e + C_P);
-      int ok = (int)at(e + C_OK), oi = (int)at(e + C_OI), tk = (int)at(e + C_TK), ti = (int)at(e + C_TI);
+      const Ids id = ids(e);
+      const int ok = id.ok, oi = id.oi, tk = id.tk, ti = id.ti;
       for (int di = 0; di < 3; ++di) {
         V d = di == 0 ? n : (di == 1 ? t1 : t2);
         float W = 0.f;
@@ -959,7 +973,8 @@ struct Eng {
   static constexpr int SA = 1, SB = 2, SAB = 3;
   MSA_HD float rowvel(int ci, int di, int sides = SAB) const {
     long e = w.con + (long)ci * CR;
-    int ok = (int)at(e + C_OK), oi = (int)at(e + C_OI), tk = (int)at(e + C_TK), ti = (int)at(e + C_TI);
+    const Ids id = ids(e);
+    const int ok = id.ok, oi = id.oi, tk = id.tk, ti = id.ti;
     V d = dir(e, di), p = v3(e + C_P);
     float r = 0.f;
     if (sides & SA) {
@@ -991,7 +1006,8 @@ struct Eng {
   }
   MSA_HD void apply(int ci, int di, float dl, int sides = SAB) const {
     long e = w.con + (long)ci * CR;
-    int ok = (int)at(e + C_OK), oi = (int)at(e + C_OI), tk = (int)at(e + C_TK), ti = (int)at(e + C_TI);
+    const Ids id = ids(e);
+    const int ok = id.ok, oi = id.oi, tk = id.tk, ti = id.ti;
     V d = dir(e, di), p = v3(e + C_P);
     if (sides & SA) {
       if (ok == 0) {
@@ -1221,10 +1237,24 @@ struct Eng {
     a3(cb + B_P, rrb);
     a3(w.fb + f * FB + F_XB, -rrb);
   }
+  // a door / drawer target's Jacobian entry J = -(d . (a x (p - o))) (revolute)
+  // or -(d . a) (prismatic): its adjoint Jb goes at once to the direction and
+  // contact-point adjoints (the joint axis and origin do not move)
+  MSA_HD void aux_J_bar(long e, long cb, int di, int ti, float Jb) const {
+    V d = dir(e, di), a = v3(w.xa + ti * 3);
+    if (sc.A[ti].type == 0) {
+      V ev = v3(e + C_P) - v3(w.xo + ti * 3);
+      a3(cb + B_D + di * 3, -(cross(a, ev) * Jb));
+      a3(cb + B_P, -(cross(d, a) * Jb));
+    } else {
+      a3(cb + B_D + di * 3, -(a * Jb));
+    }
+  }
   // adjoint of r = J . v (v = the velocities before the update): Jbar += rb v, vbar += rb J
   MSA_HD void rowvel_bar(int ci, int di, float rb, int sides = SAB) const {
     long e = w.con + (long)ci * CR;
-    int ok = (int)at(e + C_OK), oi = (int)at(e + C_OI), tk = (int)at(e + C_TK), ti = (int)at(e + C_TI);
+    const Ids id = ids(e);
+    const int ok = id.ok, oi = id.oi, tk = id.tk, ti = id.ti;
     V d = dir(e, di), p = v3(e + C_P);
     if (sides & SA) {
       if (ok == 0) {
@@ -1244,7 +1274,7 @@ struct Eng {
     if (sides & SB) {
       if (tk == 2) {
         float J = aux_J(ti, d, p, -1.f);
-        at(w.conb + (long)ci * CB + B_AJ + di) += rb * at(w.vA + ti);
+        aux_J_bar(e, w.conb + (long)ci * CB, di, ti, rb * at(w.vA + ti));
         at(w.vAb + ti) += rb * J;
       } else if (tk == 3) {
         V lin, ang;
@@ -1280,7 +1310,8 @@ struct Eng {
   // adjoint of v += w dl: returns dlbar = w . vbar and accumulates wbar += vbar dl
   MSA_HD float apply_bar(int ci, int di, float dl, int sides = SAB) const {
     long e = w.con + (long)ci * CR;
-    int ok = (int)at(e + C_OK), oi = (int)at(e + C_OI), tk = (int)at(e + C_TK), ti = (int)at(e + C_TI);
+    const Ids id = ids(e);
+    const int ok = id.ok, oi = id.oi, tk = id.tk, ti = id.ti;
     V d = dir(e, di), p = v3(e + C_P);
     float dlb = 0.f;
     if (sides & SA) {
@@ -1299,7 +1330,7 @@ struct Eng {
         float J = aux_J(ti, d, p, -1.f);
         float Mx = at(w.xM + ti);
         dlb += (J / Mx) * at(w.vAb + ti);
-        at(w.conb + (long)ci * CB + B_AJ + di) += at(w.vAb + ti) * dl / Mx;
+        aux_J_bar(e, w.conb + (long)ci * CB, di, ti, at(w.vAb + ti) * dl / Mx);
       } else if (tk == 3) {
         dlb += free_apply_bar(ci, di, ti, -1.f, dl);
       }
@@ -1458,7 +1489,8 @@ struct Eng {
     const float h = pr.h;
     for (int ci = 0; ci < nc; ++ci) {
       long e = w.con + (long)ci * CR, cb = w.conb + (long)ci * CB;
-      int ok = (int)at(e + C_OK), oi = (int)at(e + C_OI), tk = (int)at(e + C_TK), ti = (int)at(e + C_TI);
+      const Ids id = ids(e);
+      const int ok = id.ok, oi = id.oi, tk = id.tk, ti = id.ti;
       V p = v3(e + C_P);
       V pb{0.f, 0.f, 0.f};
       for (int di = 0; di < 3; ++di) {
@@ -1504,7 +1536,7 @@ struct Eng {
         }
         if (tk == 2) {
           float J = aux_J(ti, d, p, -1.f);
-          float Jb = at(cb + B_AJ + di) + Wb * 2.f * J / at(w.xM + ti);
+          float Jb = Wb * 2.f * J / at(w.xM + ti);
           V a = v3(w.xa + ti * 3);
           if (sc.A[ti].type == 0) {
             V ev = p - v3(w.xo + ti * 3);
@@ -1745,10 +1777,11 @@ struct Eng {
     const float h = pr.h;
     for (int ci = 0; ci < nc; ++ci) {
       long e = w.con + (long)ci * CR, cb = w.conb + (long)ci * CB;
-      int ok = (int)at(e + C_OK), oi = (int)at(e + C_OI), ov = (int)at(e + C_OV), tk = (int)at(e + C_TK),
-          ti = (int)at(e + C_TI);
+      const Ids id = ids(e);
+      const int ok = id.ok, oi = id.oi, ov = id.ov, tk = id.tk, ti = id.ti;
       float r = at(e + C_R), phi = at(e + C_PHI);
-      V c = v3(e + C_C), n = v3(e + C_N);
+      V n = v3(e + C_N);
+      V c = v3(e + C_P) + n * r;
       float phib = at(cb + B_BIAS) * (phi >= 0.f ? 1.f / h : pr.beta / h);
       float nbv[3] = {0.f, 0.f, 0.f};
       onb_bar(n, v3(cb + B_D + 3), v3(cb + B_D + 6), nbv);

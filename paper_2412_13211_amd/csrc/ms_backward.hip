@@ -79,8 +79,8 @@ __device__ __forceinline__ void row_nodes(const msa::Eng& E, int r, int& na, int
     return;
   }
   long e = E.w.con + (long)(r - E.nlim) * msa::CR;
-  int ok = (int)E.at(e + msa::C_OK), oi = (int)E.at(e + msa::C_OI);
-  int tk = (int)E.at(e + msa::C_TK), ti = (int)E.at(e + msa::C_TI);
+  const msa::Ids id = E.ids(e);
+  const int ok = id.ok, oi = id.oi, tk = id.tk, ti = id.ti;
   na = ok == 0 ? 0 : 1 + AMAX + oi;
   nbn = tk == 2 ? 1 + ti : (tk == 3 ? 1 + AMAX + ti : -1);
 }
@@ -264,7 +264,8 @@ __device__ __forceinline__ void rows_wave(msa::Eng& E, float* L) {
     E.s3(e + C_T1, t1);
     E.s3(e + C_T2, t2);
     const V p = E.v3(e + C_P);
-    const int ok = (int)L[e + C_OK], oi = (int)L[e + C_OI], tk = (int)L[e + C_TK], ti = (int)L[e + C_TI];
+    const Ids id = unpack_ids(L[e + C_ID]);
+    const int ok = id.ok, oi = id.oi, tk = id.tk, ti = id.ti;
     for (int di = 0; di < 3; ++di) {
       const V d = di == 0 ? n : (di == 1 ? t1 : t2);
       float W = ok == 0 ? 0.f : E.free_W(oi, d, p, 1.f);
@@ -289,7 +290,7 @@ __device__ __forceinline__ void rows_wave(msa::Eng& E, float* L) {
     const long e = w.con + (long)ci * CR;
     float Jj = 0.f;
     if (act) {
-      const int anc = M.anc[M.sph_body[(int)L[e + C_OI]]];
+      const int anc = M.anc[M.sph_body[unpack_ids(L[e + C_ID]).oi]];
       if (j < E.nb && ((anc >> j) & 1)) {
         const V a = E.v3(w.ka + j * 3), d = E.dir(e, di);
         Jj = M.jtype[j] == 0 ? dot(d, cross(a, E.v3(e + C_P) - E.v3(w.ko + j * 3))) : dot(d, a);
@@ -359,7 +360,7 @@ __device__ __forceinline__ void robot_rows_bar_wave(msa::Eng& E, float* L) {
   for (int ci = lane; ci < E.nrob; ci += 64) {
     const long e = w.con + (long)ci * CR, cb = w.conb + (long)ci * CB;
     const V p = E.v3(e + C_P);
-    const int anc = M.anc[M.sph_body[(int)L[e + C_OI]]];
+    const int anc = M.anc[M.sph_body[unpack_ids(L[e + C_ID]).oi]];
     V pb{0.f, 0.f, 0.f};
     for (int di = 0; di < 3; ++di) {
       const V d = E.dir(e, di);
@@ -388,7 +389,7 @@ __device__ __forceinline__ void robot_rows_bar_wave(msa::Eng& E, float* L) {
       const int ci = r / 3, di = r - 3 * ci;
       const long e = w.con + (long)ci * CR;
       const float Jb = L[w.rJb + (long)r * ND + j];
-      if (!((M.anc[M.sph_body[(int)L[e + C_OI]]] >> j) & 1) || Jb == 0.f) continue;
+      if (!((M.anc[M.sph_body[unpack_ids(L[e + C_ID]).oi]] >> j) & 1) || Jb == 0.f) continue;
       const V d = E.dir(e, di);
       if (rev) {
         const V ev = E.v3(e + C_P) - o;
@@ -491,13 +492,8 @@ __device__ void bwd_scene(const BwdArgs& a, int s, float* L) {
       }
       const long eo = w.con + (long)ci * CR;
       V n{c[1], c[2], c[3]}, p{c[4], c[5], c[6]};
-      L[eo + C_OK] = (float)ok;
-      L[eo + C_OI] = (float)oi;
-      L[eo + C_OV] = (float)ov;
-      L[eo + C_TK] = (float)tk;
-      L[eo + C_TI] = (float)ti;
+      L[eo + C_ID] = pack_ids(ok, oi, ov, tk, ti);
       L[eo + C_R] = r;
-      bs3(E.b, eo + C_C, p + n * r);
       L[eo + C_PHI] = c[14];
       bs3(E.b, eo + C_N, n);
       bs3(E.b, eo + C_P, p);
@@ -543,7 +539,7 @@ __device__ void bwd_scene(const BwdArgs& a, int s, float* L) {
         LV.rob[l] = -1;
       }
       for (int r = 0; r < R; ++r) {
-        bool robot = r >= E.nlim && (int)E.at(w.con + (long)(r - E.nlim) * CR + C_OK) == 0;
+        bool robot = r >= E.nlim && E.ids(w.con + (long)(r - E.nlim) * CR).ok == 0;
         if (robot) LV.rob[LV.lvl[r]] = r;
         else LV.loff[LV.lvl[r]] += 1;
       }
@@ -556,7 +552,7 @@ __device__ void bwd_scene(const BwdArgs& a, int s, float* L) {
       LV.loff[maxl] = acc;
       // fill: loff[l - 1] is the running write position of level l
       for (int r = 0; r < R; ++r) {
-        bool robot = r >= E.nlim && (int)E.at(w.con + (long)(r - E.nlim) * CR + C_OK) == 0;
+        bool robot = r >= E.nlim && E.ids(w.con + (long)(r - E.nlim) * CR).ok == 0;
         if (!robot) LV.order[LV.loff[LV.lvl[r] - 1]++] = r;
       }
       // restore the offsets

@@ -100,6 +100,8 @@ inline ms_status validate(const ms_batch_desc* d, const ms_scene_desc* sc, Count
   }
   c.NF = cnt[0]; c.NS = cnt[1]; c.NP = cnt[2]; c.NA = cnt[3];
   c.fmax = mx[0]; c.smax = mx[1]; c.pmax = mx[2]; c.amax = mx[3];
+  // a contact's target index is stored in 16 bits by the adjoint
+  if (c.smax > 65535) return fail(MS_E_INVALID, "a scene has %d furniture boxes (at most 65535)", c.smax);
   for (int s = 0; s < c.S; ++s) {
     int m = sc->scene_model[s];
     if (m < 0 || m >= c.M) return fail(MS_E_INVALID, "scene %d: model %d out of range", s, m);
