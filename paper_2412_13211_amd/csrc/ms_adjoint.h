@@ -187,6 +187,8 @@ struct WS {
   int Mb, sb, Ib, Icb, fbar, abar, vbar, bacc;
   int lv;    // level schedule (wavefront kernel only)
   int Minv;  // explicit M~^-1 (wavefront kernel only)
+  int lz;    // bias torques, then M~^-1 h vRbar (wavefront kernel only)
+  int tF, tFb, tA, tV, tV2;  // per-body scratch of the wavefront dynamics^T
   int total;
 };
 
@@ -229,16 +231,19 @@ MSA_HD inline WS ws_layout(int fmax, int ntmax, int ccap, int rcap, int K, int n
   w.conb = take(ccap * CB);
   // the robot rows' adjoints are dead once rows^T is done; the dynamics^T
   // scratch (written before it is read) shares their space
-  const int rows_b = 2 * w.rcap * 3 * ND, dyn_b = ND * 6 + 2 * ND * 36 + 3 * ND * 6;
+  const int rows_b = 2 * w.rcap * 3 * ND, dyn_b = ND * 6 + 2 * ND * 36 + 8 * ND * 6;
   const int kb = take(rows_b > dyn_b ? rows_b : dyn_b);
   w.rJb = kb; w.rwb = kb + w.rcap * 3 * ND;
   w.sb = kb; w.Ib = w.sb + ND * 6; w.Icb = w.Ib + ND * 36;
   w.fbar = w.Icb + ND * 36; w.abar = w.fbar + ND * 6; w.vbar = w.abar + ND * 6;
+  w.tF = w.vbar + ND * 6; w.tFb = w.tF + ND * 6; w.tA = w.tFb + ND * 6; w.tV = w.tA + ND * 6;
+  w.tV2 = w.tV + ND * 6;
   w.fb = take(fm * FB); w.xb = take(AMAX * XB);
   w.Mb = take(ND * ND);
   w.bacc = take(ND * 9);
   w.lv = take(wave ? lv_ints(ccap) : 0);
   w.Minv = take(wave ? ND * ND : 0);
+  w.lz = take(wave ? ND : 0);
   w.total = o;
   return w;
 }
@@ -381,9 +386,12 @@ struct Eng {
 
   // ---------------------------------------------------------------- drive
   MSA_HD void drive(long s, const float* u) {
+    for (int j = 0; j < ND; ++j) drive_one(s, u, j);
+  }
+  MSA_HD void drive_one(long s, const float* u, int j) {
     const DModel& M = *sc.M;
     const float h = pr.h;
-    for (int j = 0; j < ND; ++j) {
+    {
       float tau = 0.f, arm = 0.f;
       if (j < nb) {
         float q = at(s + j), qd = at(s + ND + j), dmp = M.damp[j];
@@ -413,8 +421,16 @@ struct Eng {
 
   // ---------------------------------------------------------------- kinematics
   MSA_HD void kinematics(long s) {
-    const DModel& M = *sc.M;
     for (int i = 0; i < nb; ++i) {
+      kin_pose(s, i);
+      kin_body(i);
+    }
+    kin_spheres();
+  }
+  // world pose of body i (its parent's pose known): R, p, joint axis a and origin o
+  MSA_HD void kin_pose(long s, int i) {
+    const DModel& M = *sc.M;
+    {
       int par = M.parent[i];
       float Rj[9], R[9];
       V o;
@@ -443,6 +459,15 @@ struct Eng {
       s3(w.kp + i * 3, p);
       s3(w.ka + i * 3, a);
       s3(w.ko + i * 3, o);
+    }
+  }
+  // per-body quantities from the pose: motion subspace, COM, inertias
+  MSA_HD void kin_body(int i) {
+    const DModel& M = *sc.M;
+    {
+      float R[9];
+      ld9(w.kR + i * 9, R);
+      const V a = v3(w.ka + i * 3), o = v3(w.ko + i * 3), p = v3(w.kp + i * 3);
       V top = M.jtype[i] == 0 ? a : V{0.f, 0.f, 0.f};
       V bot = M.jtype[i] == 0 ? cross(o, a) : a;
       s3(w.ks + i * 6, top);
@@ -460,6 +485,9 @@ struct Eng {
       for (int t = 0; t < 6; ++t) at(w.kIcw + i * 6 + t) = Sw[t];
       spatial_inertia(M.mass[i], c, W, w.kI + i * 36);
     }
+  }
+  MSA_HD void kin_spheres() {
+    const DModel& M = *sc.M;
     for (int k = 0; k < nsph && !w.wave; ++k) {
       int bi = M.sph_body[k];
       float R[9];
@@ -488,7 +516,10 @@ struct Eng {
   }
 
   MSA_HD void aux_frames(long s) {
-    for (int x = 0; x < sc.na; ++x) {
+    for (int x = 0; x < sc.na; ++x) aux_frame(s, x);
+  }
+  MSA_HD void aux_frame(long s, int x) {
+    {
       const DAux& A = sc.A[x];
       float q = at(s + axo(x));
       V ax = ld3(A.axis);
@@ -527,7 +558,10 @@ struct Eng {
   }
 
   MSA_HD void free_frames(long s) {
-    for (int f = 0; f < sc.nf; ++f) {
+    for (int f = 0; f < sc.nf; ++f) free_frame(s, f);
+  }
+  MSA_HD void free_frame(long s, int f) {
+    {
       float Q[4] = {at(s + fro(f) + 4), at(s + fro(f) + 5), at(s + fro(f) + 6), at(s + fro(f) + 7)};
       float R[9];
       quatR(Q, R);
@@ -1565,6 +1599,24 @@ struct Eng {
   }
 
   // --------------------------------------------------------------- dynamics^T
+  // drive^T of DoF j, tb = the adjoint of its torque
+  MSA_HD void drive_bar_one(int j, float tb) const {
+    const DModel& M = *sc.M;
+    const float h = pr.h;
+    const long gB = w.gB;
+    float dmp = M.damp[j];
+    if (pr.mode == 0) {
+      at(w.ub + j) += tb;
+      at(gB + ND + j) -= dmp * tb;
+    } else {
+      bool vel = M.veldof[j] != 0;
+      float kp = vel ? 0.f : M.kp[j], kd = M.kd[j];
+      if (pr.mode == 1) at(w.ub + j) += (vel ? kd : kp) * tb;
+      else at(w.ub + j) += tb;
+      at(gB + j) -= kp * tb;
+      at(gB + ND + j) -= (h * kp + kd + dmp) * tb;
+    }
+  }
   MSA_HD void dynamics_bar(long s, const float* u) {
     const DModel& M = *sc.M;
     const float h = pr.h;
@@ -1579,21 +1631,7 @@ struct Eng {
     for (int r = 0; r < nb; ++r)
       for (int c = 0; c < nb; ++c) at(w.Mb + r * ND + c) -= lz[r] * at(w.z + c);
     // drive^T (tau bar = lz)
-    for (int j = 0; j < nb; ++j) {
-      float tb = lz[j];
-      float dmp = M.damp[j];
-      if (pr.mode == 0) {
-        at(w.ub + j) += tb;
-        at(gB + ND + j) -= dmp * tb;
-      } else {
-        bool vel = M.veldof[j] != 0;
-        float kp = vel ? 0.f : M.kp[j], kd = M.kd[j];
-        if (pr.mode == 1) at(w.ub + j) += (vel ? kd : kp) * tb;
-        else at(w.ub + j) += tb;
-        at(gB + j) -= kp * tb;
-        at(gB + ND + j) -= (h * kp + kd + dmp) * tb;
-      }
-    }
+    for (int j = 0; j < nb; ++j) drive_bar_one(j, lz[j]);
     // CRBA^T: M_ij = s_j . (Ic_i s_i), j an ancestor of i (or i)
     for (int i = 0; i < nb * 36; ++i) at(w.Ib + i) = 0.f;
     for (int i = 0; i < nb * 6; ++i) at(w.sb + i) = 0.f;
@@ -1683,9 +1721,15 @@ struct Eng {
       }
       at(gB + ND + i) += qdb;
     }
-    // I_i (spatial, about the origin) -> COM point and rotational inertia;
-    // s_i -> axis and joint origin
-    for (int i = 0; i < nb; ++i) {
+    for (int i = 0; i < nb; ++i) body_bar_one(i);
+    for (int x = 0; x < sc.na; ++x) aux_dyn_bar_one(x);
+    for (int f = 0; f < sc.nf; ++f) free_dyn_bar_one(s, f);
+  }
+  // I_i (spatial, about the origin) -> COM point and rotational inertia;
+  // s_i -> axis and joint origin
+  MSA_HD void body_bar_one(int i) const {
+    const DModel& M = *sc.M;
+    {
       long Ib = w.Ib + i * 36;
       float m = M.mass[i];
       V c = v3(w.kc + i * 3);
@@ -1732,9 +1776,13 @@ struct Eng {
         acc_dir(i, a, sbo);
       }
     }
-    // door / drawer joints: vA = qd + h (-C / M)
+  }
+  // door / drawer joint x: vA = qd + h (-C / M)
+  MSA_HD void aux_dyn_bar_one(int x) const {
+    const float h = pr.h;
+    const long gB = w.gB;
     V g{pr.g[0], pr.g[1], pr.g[2]};
-    for (int x = 0; x < sc.na; ++x) {
+    {
       float vb = at(w.vAb + x);
       at(gB + axo(x) + 1) += vb;
       if (sc.A[x].type == 0) {
@@ -1744,8 +1792,12 @@ struct Eng {
         at(w.xb + x * XB + X_QB) += Cb * (-sc.A[x].mass * dot(g, dc));
       }
     }
-    // free bodies: v* = v + h g ; w* = w - h I^-1 (w x I w)
-    for (int f = 0; f < sc.nf; ++f) {
+  }
+  // free body f: v* = v + h g ; w* = w - h I^-1 (w x I w)
+  MSA_HD void free_dyn_bar_one(long s, int f) const {
+    const float h = pr.h;
+    const long gB = w.gB;
+    {
       long gi = gB + fro(f);
       a3(gi + 8, v3(w.vFb + f * 6));
       V wFb = v3(w.vFb + f * 6 + 3);
@@ -1847,8 +1899,12 @@ struct Eng {
 
   // --------------------------------------------------------------- frames^T
   MSA_HD void frames_bar(long s) {
-    long gB = w.gB;
-    for (int f = 0; f < sc.nf; ++f) {
+    for (int f = 0; f < sc.nf; ++f) free_frame_bar(s, f);
+    for (int x = 0; x < sc.na; ++x) aux_frame_bar(x);
+  }
+  MSA_HD void free_frame_bar(long s, int f) const {
+    const long gB = w.gB;
+    {
       long fb = w.fb + f * FB;
       const DFree& F = sc.F[f];
       float R[9], Rb[9];
@@ -1873,7 +1929,10 @@ struct Eng {
       for (int t = 0; t < 4; ++t) at(gB + fro(f) + 4 + t) += Qb[t];
       a3(gB + fro(f), v3(fb + F_XB));
     }
-    for (int x = 0; x < sc.na; ++x) {
+  }
+  MSA_HD void aux_frame_bar(int x) const {
+    const long gB = w.gB;
+    {
       long xb = w.xb + x * XB;
       float qb = at(xb + X_QB);
       V a = v3(w.xa + x * 3);

@@ -403,6 +403,302 @@ __device__ __forceinline__ void robot_rows_bar_wave(msa::Eng& E, float* L) {
   wsync();
 }
 
+// Recompute of a substep's articulated quantities over the lanes: drive
+// (lane per DoF), door/drawer and free-body frames (lane per joint / body),
+// body poses down the tree on lane 0, per-body quantities (lane per body),
+// then CRBA + RNEA with every recursion written as a sum over ancestors or
+// descendants (lane per body or per matrix entry), and a column-by-column
+// Cholesky factor of M~.  The bias torques are left in w.lz.
+__device__ __forceinline__ void recompute_wave(msa::Eng& E, float* L, const float* u) {
+  using namespace msa;
+  const int lane = lane_id();
+  const WS& w = E.w;
+  const DModel& M = *E.sc.M;
+  const int nb = E.nb;
+  const long s = w.st;
+  if (lane < ND) E.drive_one(s, u, lane);
+  if (lane >= ND && lane < ND + E.sc.na) E.aux_frame(s, lane - ND);
+  for (int f = lane; f < E.sc.nf; f += 64) E.free_frame(s, f);
+  if (lane == 0)
+    for (int i = 0; i < nb; ++i) E.kin_pose(s, i);
+  wsync();
+  if (lane < nb) E.kin_body(lane);
+  for (int idx = lane; idx < ND * ND; idx += 64) L[w.L + idx] = 0.f;
+  wsync();
+  // composite inertias: Ic_i = sum of I_k over the subtree of i
+  for (int idx = lane; idx < nb * 36; idx += 64) {
+    const int i = idx / 36, t = idx - 36 * (idx / 36);
+    float acc = 0.f;
+    for (int k = i; k < nb; ++k)
+      if ((M.anc[k] >> i) & 1) acc += L[w.kI + k * 36 + t];
+    L[w.kIc + i * 36 + t] = acc;
+  }
+  // velocities v_i = sum over the ancestors k of s_k qd_k; the terms
+  // v_i x (s_i qd_i) go to rff for the accelerations
+  if (lane < nb) {
+    const int i = lane;
+    float v[6] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
+    for (int k = 0; k <= i; ++k)
+      if ((M.anc[i] >> k) & 1) {
+        const float qd = L[s + ND + k];
+        for (int t = 0; t < 6; ++t) v[t] += L[w.ks + k * 6 + t] * qd;
+      }
+    E.st6(w.rv + i * 6, v);
+    float vJ[6], t6[6];
+    const float qd = L[s + ND + i];
+    for (int t = 0; t < 6; ++t) vJ[t] = L[w.ks + i * 6 + t] * qd;
+    Eng::crm6(v, vJ, t6);
+    E.st6(w.rff + i * 6, t6);
+  }
+  wsync();
+  if (lane < nb) {
+    const int i = lane;
+    // mass matrix row / column i: M_ij = s_j . (Ic_i s_i), j an ancestor of i
+    float si[6], F[6];
+    E.ld6(w.ks + i * 6, si);
+    E.mul6(w.kIc + i * 36, si, F);
+    for (int j = i; j >= 0; j = M.parent[j]) {
+      float v = 0.f;
+      for (int t = 0; t < 6; ++t) v += L[w.ks + j * 6 + t] * F[t];
+      L[w.L + i * ND + j] = v;
+      L[w.L + j * ND + i] = v;
+    }
+    // accelerations a_i = -g + sum over the ancestors of v_k x (s_k qd_k)
+    float acc[6] = {0.f, 0.f, 0.f, -E.pr.g[0], -E.pr.g[1], -E.pr.g[2]};
+    for (int k = 0; k <= i; ++k)
+      if ((M.anc[i] >> k) & 1)
+        for (int t = 0; t < 6; ++t) acc[t] += L[w.rff + k * 6 + t];
+    E.st6(w.ra + i * 6, acc);
+  }
+  wsync();
+  // body forces f_i = I_i a_i + v_i x* (I_i v_i)
+  if (lane < nb) {
+    const int i = lane;
+    float v[6], acc[6], fl[6], hv[6], t6[6];
+    E.ld6(w.rv + i * 6, v);
+    E.ld6(w.ra + i * 6, acc);
+    E.mul6(w.kI + i * 36, acc, fl);
+    E.mul6(w.kI + i * 36, v, hv);
+    Eng::crf6(v, hv, t6);
+    for (int t = 0; t < 6; ++t) fl[t] += t6[t];
+    E.st6(w.rfl + i * 6, fl);
+  }
+  wsync();
+  // subtree force sums and the bias torques C_i = s_i . sum
+  if (lane < nb) {
+    const int i = lane;
+    float f[6] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
+    for (int k = i; k < nb; ++k)
+      if ((M.anc[k] >> i) & 1)
+        for (int t = 0; t < 6; ++t) f[t] += L[w.rfl + k * 6 + t];
+    E.st6(w.rff + i * 6, f);
+    float c = 0.f;
+    for (int t = 0; t < 6; ++t) c += L[w.ks + i * 6 + t] * f[t];
+    L[w.lz + i] = c;
+    L[w.L + i * ND + i] += L[w.arm + i];
+  }
+  wsync();
+  // Cholesky factor of M~ (lower triangle), one column at a time
+  for (int j = 0; j < nb; ++j) {
+    if (lane == 0) {
+      float d = L[w.L + j * ND + j];
+      for (int k = 0; k < j; ++k) d -= L[w.L + j * ND + k] * L[w.L + j * ND + k];
+      if (!(d > 0.f)) {
+        E.status |= Eng::MS_DEGENERATE_BIT;
+        d = 1e-30f;
+      }
+      L[w.L + j * ND + j] = sqrtf(d);
+    }
+    wsync();
+    if (lane > j && lane < nb) {
+      float sm = L[w.L + lane * ND + j];
+      for (int k = 0; k < j; ++k) sm -= L[w.L + lane * ND + k] * L[w.L + j * ND + k];
+      L[w.L + lane * ND + j] = sm / L[w.L + j * ND + j];
+    }
+    wsync();
+  }
+}
+
+// z = M~^-1 (tau - C) from the explicit inverse (lane per DoF)
+__device__ __forceinline__ void solve_z_wave(const msa::Eng& E, float* L) {
+  const int lane = lane_id();
+  const msa::WS& w = E.w;
+  if (lane < ND) {
+    float z = 0.f;
+    for (int k = 0; k < E.nb; ++k) z += L[w.Minv + k * ND + lane] * (L[w.tau + k] - L[w.lz + k]);
+    L[w.z + lane] = lane < E.nb ? z : 0.f;
+  }
+}
+
+// dynamics^T over the lanes (the same adjoint as the engine's dynamics_bar,
+// with its recursions written as ancestor / descendant sums)
+__device__ __forceinline__ void dynamics_bar_wave(msa::Eng& E, float* L) {
+  using namespace msa;
+  const int lane = lane_id();
+  const WS& w = E.w;
+  const DModel& M = *E.sc.M;
+  const int nb = E.nb;
+  const float h = E.pr.h;
+  const long s = w.st, gB = w.gB;
+  // vR = qd + h z: qd gets vRbar; lz = M~^-1 h vRbar is tau's adjoint
+  if (lane < ND) {
+    L[gB + ND + lane] += L[w.vRb + lane];
+    float lz = 0.f;
+    for (int k = 0; k < nb; ++k) lz += L[w.Minv + k * ND + lane] * (h * L[w.vRb + k]);
+    L[w.lz + lane] = lane < nb ? lz : 0.f;
+  }
+  wsync();
+  // M~bar -= lz z^T; drive^T
+  for (int idx = lane; idx < ND * ND; idx += 64) {
+    const int r = idx / ND, c = idx - ND * (idx / ND);
+    if (r < nb && c < nb) L[w.Mb + idx] -= L[w.lz + r] * L[w.z + c];
+  }
+  if (lane < nb) E.drive_bar_one(lane, L[w.lz + lane]);
+  wsync();
+  // CRBA^T, per body i: F_i = Ic_i s_i, Fbar_i = sum over the ancestors j of
+  // c_ij s_j (c_ii = Mbar_ii, c_ij = Mbar_ij + Mbar_ji), Icbar_i = Fbar_i s_i^T
+  if (lane < nb) {
+    const int i = lane;
+    float si[6], F[6], Fb[6] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
+    E.ld6(w.ks + i * 6, si);
+    E.mul6(w.kIc + i * 36, si, F);
+    E.st6(w.tF + i * 6, F);
+    for (int j = i; j >= 0; j = M.parent[j]) {
+      const float c = j == i ? L[w.Mb + i * ND + i] : L[w.Mb + i * ND + j] + L[w.Mb + j * ND + i];
+      for (int t = 0; t < 6; ++t) Fb[t] += c * L[w.ks + j * 6 + t];
+    }
+    E.st6(w.tFb + i * 6, Fb);
+    for (int r = 0; r < 6; ++r)
+      for (int c = 0; c < 6; ++c) L[w.Icb + i * 36 + r * 6 + c] = Fb[r] * si[c];
+  }
+  wsync();
+  // sbar_j = sum over the descendants i of c_ij F_i + Ic_j^T Fbar_j; then
+  // RNEA^T: fbar_i = -sum over the ancestors of s_k lz_k, sbar_i -= lz_i f_i
+  if (lane < nb) {
+    const int j = lane;
+    float sb[6], Fb[6];
+    E.ld6(w.tFb + j * 6, Fb);
+    E.mul6t(w.kIc + j * 36, Fb, sb);
+    for (int i = j; i < nb; ++i) {
+      if (!((M.anc[i] >> j) & 1)) continue;
+      const float c = j == i ? L[w.Mb + i * ND + i] : L[w.Mb + i * ND + j] + L[w.Mb + j * ND + i];
+      for (int t = 0; t < 6; ++t) sb[t] += c * L[w.tF + i * 6 + t];
+    }
+    const float Cb = -L[w.lz + j];
+    float fb[6] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
+    for (int k = 0; k <= j; ++k)
+      if ((M.anc[j] >> k) & 1) {
+        const float ck = -L[w.lz + k];
+        for (int t = 0; t < 6; ++t) fb[t] += L[w.ks + k * 6 + t] * ck;
+      }
+    E.st6(w.fbar + j * 6, fb);
+    for (int t = 0; t < 6; ++t) sb[t] += Cb * L[w.rff + j * 6 + t];
+    E.st6(w.sb + j * 6, sb);
+  }
+  // Ibar_i = sum over the ancestors of Icbar_k (entry per lane)
+  for (int idx = lane; idx < nb * 36; idx += 64) {
+    const int i = idx / 36, t = idx - 36 * (idx / 36);
+    float acc = 0.f;
+    for (int k = 0; k <= i; ++k)
+      if ((M.anc[i] >> k) & 1) acc += L[w.Icb + k * 36 + t];
+    L[w.Ib + i * 36 + t] = acc;
+  }
+  wsync();
+  // body terms of f = I a + v x* (I v): Ibar, the own parts of abar and vbar
+  if (lane < nb) {
+    const int i = lane;
+    const long I = w.kI + i * 36;
+    float v[6], acc[6], fb[6], t6[6], hv[6];
+    E.ld6(w.rv + i * 6, v);
+    E.ld6(w.ra + i * 6, acc);
+    E.ld6(w.fbar + i * 6, fb);
+    for (int r = 0; r < 6; ++r)
+      for (int c = 0; c < 6; ++c) L[w.Ib + i * 36 + r * 6 + c] += fb[r] * acc[c];
+    E.mul6t(I, fb, t6);
+    E.st6(w.tA + i * 6, t6);
+    E.mul6(I, v, hv);
+    V om{v[0], v[1], v[2]}, nu{v[3], v[4], v[5]}, hn{hv[0], hv[1], hv[2]}, hf{hv[3], hv[4], hv[5]};
+    V fn{fb[0], fb[1], fb[2]}, ff{fb[3], fb[4], fb[5]};
+    V omb = cross(hn, fn) + cross(hf, ff), nub = cross(hf, fn);
+    V hnb = cross(fn, om), hfb = cross(fn, nu) + cross(ff, om);
+    float hb[6] = {hnb.x, hnb.y, hnb.z, hfb.x, hfb.y, hfb.z};
+    for (int r = 0; r < 6; ++r)
+      for (int c = 0; c < 6; ++c) L[w.Ib + i * 36 + r * 6 + c] += hb[r] * v[c];
+    E.mul6t(I, hb, t6);
+    float ov[6] = {omb.x + t6[0], omb.y + t6[1], omb.z + t6[2], nub.x + t6[3], nub.y + t6[4], nub.z + t6[5]};
+    E.st6(w.tV + i * 6, ov);
+  }
+  wsync();
+  // abar_i = subtree sum of the own parts; the a = a_par + v x vJ term's
+  // share of vbar_i
+  if (lane < nb) {
+    const int i = lane;
+    float ab[6] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
+    for (int k = i; k < nb; ++k)
+      if ((M.anc[k] >> i) & 1)
+        for (int t = 0; t < 6; ++t) ab[t] += L[w.tA + k * 6 + t];
+    E.st6(w.abar + i * 6, ab);
+    const float qd = L[s + ND + i];
+    const float* si = L + w.ks + i * 6;
+    V vJw{si[0] * qd, si[1] * qd, si[2] * qd}, vJv{si[3] * qd, si[4] * qd, si[5] * qd};
+    V aw{ab[0], ab[1], ab[2]}, av{ab[3], ab[4], ab[5]};
+    V omb2 = cross(vJw, aw) + cross(vJv, av), nub2 = cross(vJw, av);
+    float o2[6] = {omb2.x, omb2.y, omb2.z, nub2.x, nub2.y, nub2.z};
+    E.st6(w.tV2 + i * 6, o2);
+  }
+  wsync();
+  // vbar_i = subtree sum of both own parts; the joint velocity's adjoint
+  if (lane < nb) {
+    const int i = lane;
+    float vb[6] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
+    for (int k = i; k < nb; ++k)
+      if ((M.anc[k] >> i) & 1)
+        for (int t = 0; t < 6; ++t) vb[t] += L[w.tV + k * 6 + t] + L[w.tV2 + k * 6 + t];
+    E.st6(w.vbar + i * 6, vb);
+    float v[6], ab[6], si[6];
+    E.ld6(w.rv + i * 6, v);
+    E.ld6(w.abar + i * 6, ab);
+    E.ld6(w.ks + i * 6, si);
+    V om{v[0], v[1], v[2]}, nu{v[3], v[4], v[5]}, aw{ab[0], ab[1], ab[2]}, av{ab[3], ab[4], ab[5]};
+    V vJwb = cross(aw, om) + cross(av, nu), vJvb = cross(av, om);
+    float vJb[6] = {vJwb.x + vb[0], vJwb.y + vb[1], vJwb.z + vb[2], vJvb.x + vb[3], vJvb.y + vb[4], vJvb.z + vb[5]};
+    const float qd = L[s + ND + i];
+    float qdb = 0.f;
+    for (int t = 0; t < 6; ++t) {
+      L[w.sb + i * 6 + t] += qd * vJb[t];
+      qdb += si[t] * vJb[t];
+    }
+    L[gB + ND + i] += qdb;
+  }
+  wsync();
+  // per body, door / drawer joint and free body
+  if (lane < nb) E.body_bar_one(lane);
+  if (lane >= ND && lane < ND + E.sc.na) E.aux_dyn_bar_one(lane - ND);
+  for (int f = lane; f < E.sc.nf; f += 64) E.free_dyn_bar_one(s, f);
+  wsync();
+}
+
+// kinematics^T: joint k receives a_k . (Mo - o_k x F + Md) (revolute) or
+// a_k . F (prismatic) with F, Mo, Md summed over the subtree of k
+__device__ __forceinline__ void kin_bar_wave(const msa::Eng& E, float* L) {
+  using namespace msa;
+  const int lane = lane_id();
+  const WS& w = E.w;
+  const DModel& M = *E.sc.M;
+  if (lane < E.nb) {
+    const int i = lane;
+    V F{0.f, 0.f, 0.f}, Mo{0.f, 0.f, 0.f}, Md{0.f, 0.f, 0.f};
+    for (int k = i; k < E.nb; ++k)
+      if ((M.anc[k] >> i) & 1) {
+        F = F + E.v3(w.bacc + k * 9);
+        Mo = Mo + E.v3(w.bacc + k * 9 + 3);
+        Md = Md + E.v3(w.bacc + k * 9 + 6);
+      }
+    const V a = E.v3(w.ka + i * 3);
+    L[w.gB + i] += M.jtype[i] == 0 ? dot(a, Mo + Md - cross(E.v3(w.ko + i * 3), F)) : dot(a, F);
+  }
+}
+
 __device__ void bwd_scene(const BwdArgs& a, int s, float* L) {
   using namespace msa;
   const int lane = lane_id();
@@ -505,17 +801,11 @@ __device__ void bwd_scene(const BwdArgs& a, int s, float* L) {
     // the lanes; the limit rows and the level schedule on one lane
     E.nc = nc;
     E.nrob = NR;
-    if (lane == 0) {
-      E.drive(w.st, u);
-      E.kinematics(w.st);
-      E.aux_frames(w.st);
-      E.free_frames(w.st);
-      E.dynamics(w.st, false);
-    }
-    wsync();
+    recompute_wave(E, L, u);
     phase(1);
     build_minv(E, L);
     wsync();
+    solve_z_wave(E, L);
     rows_wave(E, L);
     if (lane == 0) {
       E.build_lims();
@@ -638,15 +928,18 @@ __device__ void bwd_scene(const BwdArgs& a, int s, float* L) {
     robot_rows_bar_wave(E, L);
     if (lane == 0) E.rows_bar(false);
     phase(5);
-    // the rest of the reverse substep on one lane
+    wsync();
+    dynamics_bar_wave(E, L);
+    phase(6);
+    // contacts^T on one lane; frames^T per free body / joint; kinematics^T per joint
     if (lane == 0) {
-      E.dynamics_bar(w.st, u);
-      phase(6);
       E.contacts_bar();
-      E.frames_bar(w.st);
-      E.kin_bar();
       LV.cnt[4] = (int)E.status;
     }
+    wsync();
+    for (int f = lane; f < E.sc.nf; f += 64) E.free_frame_bar(w.st, f);
+    if (lane >= ND && lane < ND + E.sc.na) E.aux_frame_bar(lane - ND);
+    kin_bar_wave(E, L);
     wsync();
     for (int i = lane; i < w.ss; i += 64) L[w.gA + i] = L[w.gB + i];
     wsync();
