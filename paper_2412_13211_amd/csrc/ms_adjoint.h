@@ -186,6 +186,7 @@ struct WS {
   int vRb, vAb, vFb, lamb, llamb, limb, conb, rJb, rwb, fb, xb;
   int Mb, sb, Ib, Icb, fbar, abar, vbar, bacc;
   int lv;    // level schedule (wavefront kernel only)
+  int tring;  // two sweeps of the tape staged from the record (wavefront kernel only)
   int Minv;  // explicit M~^-1 (wavefront kernel only)
   int lz;    // bias torques, then M~^-1 h vRbar (wavefront kernel only)
   int tF, tFb, tA, tV, tV2;  // per-body scratch of the wavefront dynamics^T
@@ -222,7 +223,9 @@ MSA_HD inline WS ws_layout(int fmax, int ntmax, int ccap, int rcap, int K, int n
   w.tau = take(ND); w.arm = take(ND); w.L = take(ND * ND); w.z = take(ND);
   w.rv = take(ND * 6); w.ra = take(ND * 6); w.rfl = take(ND * 6); w.rff = take(ND * 6);
   w.vR = take(ND); w.vA = take(AMAX); w.vF = take(fm * 6);
-  w.lam = take(3 * ccap); w.llam = take(2 * AMAX);
+  // impulses: working storage of the lane kernel's forward sweeps (the
+  // reverse sweeps read them from the tape)
+  w.lam = take(wave ? 0 : 3 * ccap); w.llam = take(wave ? 0 : 2 * AMAX);
   w.con = take(ccap * CR);
   w.lim = take(2 * AMAX * 4);
   w.rJ = take(w.rcap * 3 * ND); w.rw = take(w.rcap * 3 * ND);
@@ -242,6 +245,7 @@ MSA_HD inline WS ws_layout(int fmax, int ntmax, int ccap, int rcap, int K, int n
   w.Mb = take(ND * ND);
   w.bacc = take(ND * 9);
   w.lv = take(wave ? lv_ints(ccap) : 0);
+  w.tring = take(wave ? 2 * 3 * ccap : 0);
   w.Minv = take(wave ? ND * ND : 0);
   w.lz = take(wave ? ND : 0);
   w.total = o;
@@ -366,8 +370,9 @@ struct Eng {
   // pre-projection values of the row updates: sweep it, row r (limit rows
   // first, then contacts), slot d (normal, tangent 1, tangent 2)
   Buf tb;
-  int tsw;  // floats per sweep
-  MSA_HD float& tape_at(int it, int r, int d) const { return tb[(long)it * tsw + 3 * r + d]; }
+  int tsw;    // floats per sweep
+  int tmask;  // sweep index mask: all bits (the whole tape), or 1 (a two-sweep ring)
+  MSA_HD float& tape_at(int it, int r, int d) const { return tb[(long)(it & tmask) * tsw + 3 * r + d]; }
 
   MSA_HD float& at(long e) const { return b[e]; }
   MSA_HD Ids ids(long e) const { return unpack_ids(b[e + C_ID]); }
@@ -1405,16 +1410,186 @@ struct Eng {
     at(w.vAb + x) += rb * sgn;
     at(w.limb + li) += rb;
     at(w.llamb + li) = lold;
-    at(w.llam + li) = pl;
   }
+  // contact ci's normal impulse after sweep it's normal update (the
+  // friction disk radius is mu times it)
+  MSA_HD float normal_after(int it, int ci) const {
+    if (!row_ok(ci, 0)) return 0.f;
+    float y = tape_at(it, nlim + ci, 0);
+    return y > 0.f ? y : 0.f;
+  }
+  // ---- register form of a contact's reverse update (free-body owner;
+  // plane, furniture or free-body target): the sides' velocities, adjoints
+  // and inverse inertias are read once, updated in registers and written
+  // back once.  The arithmetic is that of apply / apply_bar / rowvel /
+  // rowvel_bar / free_row_bar for these side kinds.
+  struct FSide {
+    int f;
+    float sgn, im;
+    V x, v, w, vb, wb, xb;
+    float Ii[9], IIb[9];
+  };
+  MSA_HD void fs_load(FSide& S, int f, float sgn) const {
+    S.f = f;
+    S.sgn = sgn;
+    S.im = 1.f / sc.F[f].mass;
+    S.x = v3(cur_s + fro(f));
+    ld9(w.fIi + f * 9, S.Ii);
+    S.v = v3(w.vF + f * 6);
+    S.w = v3(w.vF + f * 6 + 3);
+    S.vb = v3(w.vFb + f * 6);
+    S.wb = v3(w.vFb + f * 6 + 3);
+    S.xb = V{0.f, 0.f, 0.f};
+    for (int t = 0; t < 9; ++t) S.IIb[t] = 0.f;
+  }
+  MSA_HD void fs_store(const FSide& S) const {
+    s3(w.vF + S.f * 6, S.v);
+    s3(w.vF + S.f * 6 + 3, S.w);
+    s3(w.vFb + S.f * 6, S.vb);
+    s3(w.vFb + S.f * 6 + 3, S.wb);
+    long fb = w.fb + S.f * FB;
+    a3(fb + F_XB, S.xb);
+    for (int t = 0; t < 9; ++t) at(fb + F_IIB + t) += S.IIb[t];
+  }
+  struct RowAcc {
+    V p, d[3], db[3], pb;
+  };
+  // (lin, ang) of side S for direction d: lin = sgn d, ang = sgn (p - x) x d
+  MSA_HD static void fs_row(const FSide& S, const RowAcc& A, int di, V& lin, V& ang) {
+    lin = A.d[di] * S.sgn;
+    ang = cross(A.p - S.x, A.d[di]) * S.sgn;
+  }
+  MSA_HD static void fs_row_bar(FSide& S, RowAcc& A, int di, V linb, V angb) {
+    V rr = A.p - S.x;
+    A.db[di] = A.db[di] + linb * S.sgn + cross(angb, rr) * S.sgn;
+    V rrb = cross(A.d[di], angb) * S.sgn;
+    A.pb = A.pb + rrb;
+    S.xb = S.xb - rrb;
+  }
+  MSA_HD static void fs_apply(FSide& S, const RowAcc& A, int di, float dl) {
+    V lin, ang;
+    fs_row(S, A, di, lin, ang);
+    S.v = S.v + lin * S.im * dl;
+    S.w = S.w + rmv(S.Ii, ang) * dl;
+  }
+  MSA_HD static float fs_rowvel(const FSide& S, const RowAcc& A, int di) {
+    V lin, ang;
+    fs_row(S, A, di, lin, ang);
+    return dot(lin, S.v) + dot(ang, S.w);
+  }
+  MSA_HD static float fs_apply_bar(FSide& S, RowAcc& A, int di, float dl) {
+    V lin, ang;
+    fs_row(S, A, di, lin, ang);
+    float dlb = dot(lin * S.im, S.vb) + dot(rmv(S.Ii, ang), S.wb);
+    V iab = S.wb * dl;
+    float iv[3] = {iab.x, iab.y, iab.z}, av[3] = {ang.x, ang.y, ang.z};
+    for (int r = 0; r < 3; ++r)
+      for (int c = 0; c < 3; ++c) S.IIb[r * 3 + c] += iv[r] * av[c];
+    fs_row_bar(S, A, di, S.vb * (S.im * dl), rtmv(S.Ii, iab));
+    return dlb;
+  }
+  MSA_HD static void fs_rowvel_bar(FSide& S, RowAcc& A, int di, float rb) {
+    V lin, ang;
+    fs_row(S, A, di, lin, ang);
+    fs_row_bar(S, A, di, S.v * rb, S.w * rb);
+    S.vb = S.vb + lin * rb;
+    S.wb = S.wb + ang * rb;
+  }
+  MSA_HD void contact_bar_reg(int it, int ci, int oi, int tk, int ti) const {
+    const long e = w.con + (long)ci * CR, cb = w.conb + (long)ci * CB, lb = w.lamb + ci * 3;
+    const int row = nlim + ci;
+    const bool two = tk == 3;
+    FSide A, B;
+    fs_load(A, oi, 1.f);
+    if (two) fs_load(B, ti, -1.f);
+    RowAcc R;
+    R.p = v3(e + C_P);
+    R.d[0] = v3(e + C_N);
+    R.d[1] = v3(e + C_T1);
+    R.d[2] = v3(e + C_T2);
+    for (int k = 0; k < 3; ++k) R.db[k] = V{0.f, 0.f, 0.f};
+    R.pb = V{0.f, 0.f, 0.f};
+    const float W0 = at(e + C_W), W1 = at(e + C_W + 1), W2 = at(e + C_W + 2);
+    float lb0 = at(lb), lb1 = at(lb + 1), lb2 = at(lb + 2);
+    float Wb0 = 0.f, Wb1 = 0.f, Wb2 = 0.f, biasb = 0.f;
+    if (W1 >= 1e-12f && W2 >= 1e-12f) {
+      float y1 = tape_at(it, row, 1), y2 = tape_at(it, row, 2);
+      float lim = pr.mu * normal_after(it, ci);
+      float o1, o2, p1, p2;
+      bool proj = disk_proj(y1, y2, lim, o1, o2);
+      prev_fric(it, ci, p1, p2);
+      float d1 = o1 - p1, d2 = o2 - p2;
+      fs_apply(A, R, 2, -d2);
+      if (two) fs_apply(B, R, 2, -d2);
+      fs_apply(A, R, 1, -d1);
+      if (two) fs_apply(B, R, 1, -d1);
+      float d1b = fs_apply_bar(A, R, 1, d1);
+      if (two) d1b += fs_apply_bar(B, R, 1, d1);
+      float d2b = fs_apply_bar(A, R, 2, d2);
+      if (two) d2b += fs_apply_bar(B, R, 2, d2);
+      float yb1, yb2, limb;
+      fric_bar(y1, y2, lim, proj, lb1 + d1b, lb2 + d2b, yb1, yb2, limb);
+      lb0 += pr.mu * limb;
+      float l1 = -d1b + yb1, l2 = -d2b + yb2;
+      float r1 = fs_rowvel(A, R, 1) + (two ? fs_rowvel(B, R, 1) : 0.f);
+      float r2 = fs_rowvel(A, R, 2) + (two ? fs_rowvel(B, R, 2) : 0.f);
+      float rb1 = -yb1 / W1, rb2 = -yb2 / W2;
+      Wb1 += yb1 * r1 / (W1 * W1);
+      Wb2 += yb2 * r2 / (W2 * W2);
+      fs_rowvel_bar(A, R, 1, rb1);
+      if (two) fs_rowvel_bar(B, R, 1, rb1);
+      fs_rowvel_bar(A, R, 2, rb2);
+      if (two) fs_rowvel_bar(B, R, 2, rb2);
+      lb1 = l1;
+      lb2 = l2;
+    }
+    if (W0 >= 1e-12f) {
+      float y = tape_at(it, row, 0);
+      float nl = y > 0.f ? y : 0.f;
+      float pl = prev_normal(it, ci);
+      float dl = nl - pl;
+      fs_apply(A, R, 0, -dl);
+      if (two) fs_apply(B, R, 0, -dl);
+      float dlb = fs_apply_bar(A, R, 0, dl);
+      if (two) dlb += fs_apply_bar(B, R, 0, dl);
+      float lold, yb;
+      normal_bar(y, lb0 + dlb, dlb, lold, yb);
+      float r = fs_rowvel(A, R, 0) + (two ? fs_rowvel(B, R, 0) : 0.f) + at(e + C_BIAS);
+      float rb = -yb / W0;
+      Wb0 += yb * r / (W0 * W0);
+      biasb += rb;
+      fs_rowvel_bar(A, R, 0, rb);
+      if (two) fs_rowvel_bar(B, R, 0, rb);
+      lb0 = lold;
+    }
+    at(lb) = lb0;
+    at(lb + 1) = lb1;
+    at(lb + 2) = lb2;
+    for (int k = 0; k < 3; ++k) a3(cb + B_D + k * 3, R.db[k]);
+    a3(cb + B_P, R.pb);
+    at(cb + B_W) += Wb0;
+    at(cb + B_W + 1) += Wb1;
+    at(cb + B_W + 2) += Wb2;
+    at(cb + B_BIAS) += biasb;
+    fs_store(A);
+    if (two) fs_store(B);
+  }
+
   // reverse of contact_update (sweep it): friction pair, then normal
   MSA_HD void contact_bar(int it, int ci) const {
+    {
+      const Ids id = ids(w.con + (long)ci * CR);
+      if (id.ok != 0 && id.tk != 2) {
+        contact_bar_reg(it, ci, id.oi, id.tk, id.ti);
+        return;
+      }
+    }
     long e = w.con + (long)ci * CR, cb = w.conb + (long)ci * CB;
-    long lm = w.lam + ci * 3, lb = w.lamb + ci * 3;
+    long lb = w.lamb + ci * 3;
     const int row = nlim + ci;
     if (row_ok(ci, 1) && row_ok(ci, 2)) {
       float y1 = tape_at(it, row, 1), y2 = tape_at(it, row, 2);
-      float lim = pr.mu * at(lm);
+      float lim = pr.mu * normal_after(it, ci);
       float o1, o2, p1, p2;
       bool proj = disk_proj(y1, y2, lim, o1, o2);
       prev_fric(it, ci, p1, p2);
@@ -1435,8 +1610,6 @@ struct Eng {
       rowvel_bar(ci, 2, rb2);
       at(lb + 1) = l1;
       at(lb + 2) = l2;
-      at(lm + 1) = p1;
-      at(lm + 2) = p2;
     }
     if (row_ok(ci, 0)) {
       float y = tape_at(it, row, 0);
@@ -1454,7 +1627,6 @@ struct Eng {
       at(cb + B_BIAS) += rb;
       rowvel_bar(ci, 0, rb);
       at(lb) = lold;
-      at(lm) = pl;
     }
   }
   // scalar parts of the reverse updates, shared with the wavefront kernel.
@@ -1519,9 +1691,14 @@ struct Eng {
   // robot_side = false: the robot owners' rows are reversed elsewhere (the
   // wavefront kernel spreads them over lanes); M~bar must be zeroed before
   MSA_HD void rows_bar(bool robot_side = true) {
+    for (int ci = 0; ci < nc; ++ci) rows_bar_one(ci, robot_side);
+    for (int li = 0; li < nlim; ++li) rows_bar_limit(li);
+  }
+  // rows^T of contact ci (touches the contact's own adjoint record and its
+  // sides' accumulators)
+  MSA_HD void rows_bar_one(int ci, bool robot_side) const {
     const DModel& M = *sc.M;
-    const float h = pr.h;
-    for (int ci = 0; ci < nc; ++ci) {
+    {
       long e = w.con + (long)ci * CR, cb = w.conb + (long)ci * CB;
       const Ids id = ids(e);
       const int ok = id.ok, oi = id.oi, tk = id.tk, ti = id.ti;
@@ -1586,7 +1763,11 @@ struct Eng {
       }
       a3(cb + B_P, pb);
     }
-    for (int li = 0; li < nlim; ++li) {
+  }
+  // rows^T of joint-limit row li: its bias depends on the joint position
+  MSA_HD void rows_bar_limit(int li) const {
+    const float h = pr.h;
+    {
       long e = w.lim + li * 4;
       int x = (int)at(e);
       float sgn = at(e + 1);
@@ -1825,9 +2006,14 @@ struct Eng {
 
   // --------------------------------------------------------------- contacts^T
   MSA_HD void contacts_bar() {
+    for (int ci = 0; ci < nc; ++ci) contact_geom_bar(ci);
+  }
+  // contacts^T of contact ci: from its point / direction / bias adjoints to
+  // the geometry of its sides
+  MSA_HD void contact_geom_bar(int ci) const {
     const DModel& M = *sc.M;
     const float h = pr.h;
-    for (int ci = 0; ci < nc; ++ci) {
+    {
       long e = w.con + (long)ci * CR, cb = w.conb + (long)ci * CB;
       const Ids id = ids(e);
       const int ok = id.ok, oi = id.oi, ov = id.ov, tk = id.tk, ti = id.ti;
@@ -2009,6 +2195,7 @@ struct Eng {
     nc = nrob = nlim = 0;
     tb = Buf{b.p + (long)w.tape * b.st, b.st};
     tsw = 3 * (2 * AMAX + w.ccap);
+    tmask = -1;
     long s0 = srec(0);
     zero(s0, w.ss);
     for (int j = 0; j < ND; ++j) {

@@ -93,7 +93,7 @@ __device__ void robot_contact_bar(msa::Eng& E, int it, int ci, float* L) {
   const bool own = lane < 16 && j < E.nb;
   const WS& w = E.w;
   const long e = w.con + (long)ci * CR, cb = w.conb + (long)ci * CB;
-  const long lm = w.lam + ci * 3, lb = w.lamb + ci * 3;
+  const long lb = w.lamb + ci * 3;
   const int row = E.nlim + ci;
   float* vR = L + w.vR;
   float* vRb = L + w.vRb;
@@ -104,7 +104,7 @@ __device__ void robot_contact_bar(msa::Eng& E, int it, int ci, float* L) {
   const float mu = E.pr.mu;
   if (E.row_ok(ci, 1) && E.row_ok(ci, 2)) {
     const float y1 = E.tape_at(it, row, 1), y2 = E.tape_at(it, row, 2);
-    const float lim = mu * L[lm];
+    const float lim = mu * E.normal_after(it, ci);
     float o1, o2, p1, p2;
     const bool proj = disk_proj(y1, y2, lim, o1, o2);
     E.prev_fric(it, ci, p1, p2);
@@ -159,8 +159,6 @@ __device__ void robot_contact_bar(msa::Eng& E, int it, int ci, float* L) {
       E.rowvel_bar(ci, 2, rb2, Eng::SB);
       L[lb + 1] = l1;
       L[lb + 2] = l2;
-      L[lm + 1] = p1;
-      L[lm + 2] = p2;
     }
     if (own) {
       float v = vR[j];
@@ -204,7 +202,6 @@ __device__ void robot_contact_bar(msa::Eng& E, int it, int ci, float* L) {
       L[cb + B_BIAS] += rb;
       E.rowvel_bar(ci, 0, rb, Eng::SB);
       L[lb] = lold;
-      L[lm] = pl;
     }
     if (own) {
       rJb[j] += rb * vR[j];
@@ -866,30 +863,20 @@ __device__ void bwd_scene(const BwdArgs& a, int s, float* L) {
     E.nlim = LV.cnt[2];
     E.status = (uint32_t)LV.cnt[4];
     const int maxl = LV.cnt[3];
-    E.tb = Buf{const_cast<float*>(rec + RL.tape + (size_t)si * a.pr.K * RL.tsw), 1};
+    // the tape of this substep's sweeps: two sweeps at a time staged in an
+    // LDS ring (sweep it in slot it & 1); the reverse sweep it reads sweeps
+    // it and it - 1
+    const float* tape_g = rec + RL.tape + (size_t)si * a.pr.K * RL.tsw;
+    E.tb = Buf{L + w.tring, 1};
     E.tsw = RL.tsw;
-    // impulses after the last sweep
-    const int R = E.nlim + E.nc;
-    for (int r = lane; r < R; r += 64) {
-      if (r < E.nlim) {
-        float y = a.pr.K > 0 ? E.tape_at(a.pr.K - 1, r, 0) : 0.f;
-        L[w.llam + r] = y > 0.f ? y : 0.f;
-      } else {
-        const int ci = r - E.nlim;
-        float l0 = 0.f, l1 = 0.f, l2 = 0.f;
-        if (a.pr.K > 0) {
-          if (E.row_ok(ci, 0)) {
-            float y = E.tape_at(a.pr.K - 1, r, 0);
-            l0 = y > 0.f ? y : 0.f;
-          }
-          if (E.row_ok(ci, 1) && E.row_ok(ci, 2))
-            disk_proj(E.tape_at(a.pr.K - 1, r, 1), E.tape_at(a.pr.K - 1, r, 2), a.pr.mu * l0, l1, l2);
-        }
-        L[w.lam + ci * 3] = l0;
-        L[w.lam + ci * 3 + 1] = l1;
-        L[w.lam + ci * 3 + 2] = l2;
-      }
-    }
+    E.tmask = 1;
+    const int R3 = 3 * (E.nlim + E.nc);
+    auto stage = [&](int it) {
+      float* dst = L + w.tring + (it & 1) * RL.tsw;
+      const float* src = tape_g + (size_t)it * RL.tsw;
+      for (int i = lane; i < R3; i += 64) dst[i] = src[i];
+    };
+    if (a.pr.K > 0) stage(a.pr.K - 1);
     // adjoint accumulators of this substep
     zero_lds(L, w.gB, w.ss);
     zero_lds(L, w.vRb, ND);
@@ -911,6 +898,8 @@ __device__ void bwd_scene(const BwdArgs& a, int s, float* L) {
     phase(3);
     // Gauss-Seidel sweeps in reverse, levels in reverse
     for (int it = a.pr.K - 1; it >= 0; --it) {
+      if (it >= 1) stage(it - 1);
+      wsync();
       for (int lv = maxl; lv >= 1; --lv) {
         const int rr = LV.rob[lv];
         if (rr >= 0) robot_contact_bar(E, it, rr - E.nlim, L);
@@ -924,19 +913,37 @@ __device__ void bwd_scene(const BwdArgs& a, int s, float* L) {
       }
     }
     phase(4);
-    // rows^T: robot rows over the lanes, the rest on one lane
+    // rows^T: robot rows over the lanes; then level by level (rows of a
+    // level touch disjoint bodies) the other rows, the robot rows' target
+    // sides and the limit rows, one lane each
     robot_rows_bar_wave(E, L);
-    if (lane == 0) E.rows_bar(false);
+    for (int lv = 1; lv <= maxl; ++lv) {
+      const int rr = LV.rob[lv];
+      if (rr >= 0 && lane == 0) E.rows_bar_one(rr - E.nlim, false);
+      const int o0 = LV.loff[lv - 1], o1 = LV.loff[lv];
+      for (int k = o0 + lane; k < o1; k += 64) {
+        const int r = LV.order[k];
+        if (r < E.nlim) E.rows_bar_limit(r);
+        else E.rows_bar_one(r - E.nlim, false);
+      }
+      wsync();
+    }
     phase(5);
-    wsync();
     dynamics_bar_wave(E, L);
     phase(6);
-    // contacts^T on one lane; frames^T per free body / joint; kinematics^T per joint
-    if (lane == 0) {
-      E.contacts_bar();
-      LV.cnt[4] = (int)E.status;
+    // contacts^T level by level (rows of a level touch disjoint bodies);
+    // frames^T per free body / joint; kinematics^T per joint
+    for (int lv = 1; lv <= maxl; ++lv) {
+      const int rr = LV.rob[lv];
+      if (rr >= 0 && lane == 0) E.contact_geom_bar(rr - E.nlim);
+      const int o0 = LV.loff[lv - 1], o1 = LV.loff[lv];
+      for (int k = o0 + lane; k < o1; k += 64) {
+        const int r = LV.order[k];
+        if (r >= E.nlim) E.contact_geom_bar(r - E.nlim);
+      }
+      wsync();
     }
-    wsync();
+    if (lane == 0) LV.cnt[4] = (int)E.status;
     for (int f = lane; f < E.sc.nf; f += 64) E.free_frame_bar(w.st, f);
     if (lane >= ND && lane < ND + E.sc.na) E.aux_frame_bar(lane - ND);
     kin_bar_wave(E, L);
