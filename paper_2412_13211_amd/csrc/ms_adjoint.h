@@ -1205,14 +1205,23 @@ struct Eng {
   MSA_HD void acc_dir(int bi, V d, V db) const { a3(w.bacc + bi * 9 + 6, cross(d, db)); }
 
   MSA_HD void integrate_bar(long s) {
+    for (int j = 0; j < ND; ++j) integrate_bar_dof(j);
+    for (int x = 0; x < AMAX; ++x) integrate_bar_aux(x);
+    for (int f = 0; f < sc.nf; ++f) integrate_bar_free(s, f);
+  }
+  MSA_HD void integrate_bar_dof(int j) const {
     const float h = pr.h;
     long gA = w.gA, gB = w.gB;
-    for (int j = 0; j < ND; ++j) {
+    {
       float qb = at(gA + j), qdb = at(gA + ND + j);
       at(gB + j) += qb;
       at(w.vRb + j) = qdb + (j < nb ? h * qb : 0.f);
     }
-    for (int x = 0; x < AMAX; ++x) {
+  }
+  MSA_HD void integrate_bar_aux(int x) const {
+    const float h = pr.h;
+    long gA = w.gA, gB = w.gB;
+    {
       if (x < sc.na) {
         float qb = at(gA + axo(x)), qdb = at(gA + axo(x) + 1);
         at(gB + axo(x)) += qb;
@@ -1222,7 +1231,11 @@ struct Eng {
         at(gB + axo(x) + 1) += at(gA + axo(x) + 1);
       }
     }
-    for (int f = 0; f < sc.nf; ++f) {
+  }
+  MSA_HD void integrate_bar_free(long s, int f) const {
+    const float h = pr.h;
+    long gA = w.gA, gB = w.gB;
+    {
       long go = gA + fro(f), gi = gB + fro(f);
       V xb = v3(go);
       a3(gi, xb);

@@ -893,7 +893,10 @@ __device__ void bwd_scene(const BwdArgs& a, int s, float* L) {
     zero_lds(L, w.bacc, ND * 9);
     zero_lds(L, w.Mb, ND * ND);
     wsync();
-    if (lane == 0) E.integrate_bar(w.st);
+    // integrate^T: lane per DoF, door / drawer joint and free body
+    if (lane < ND) E.integrate_bar_dof(lane);
+    if (lane >= ND && lane < ND + AMAX) E.integrate_bar_aux(lane - ND);
+    for (int f = lane; f < nf; f += 64) E.integrate_bar_free(w.st, f);
     wsync();
     phase(3);
     // Gauss-Seidel sweeps in reverse, levels in reverse
