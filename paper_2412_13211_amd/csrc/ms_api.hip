@@ -104,7 +104,7 @@ KArgs make_args(const ms_batch* b, const void* x_in, const float* u, void* x_out
   a.beta = b->desc.baumgarte;
   a.margin = b->desc.margin;
   for (int t = 0; t < 3; ++t) a.g[t] = b->desc.gravity[t];
-  a.L = lds_for(&b->desc, b->cnt, a.stage_static);
+  a.L = lds_for(&b->desc, b->cnt, a.stage_static, b->frc_robot != nullptr || b->grip != nullptr);
   a.frc_robot = b->frc_robot;
   a.frc_body = b->frc_body;
   a.grip = b->grip;

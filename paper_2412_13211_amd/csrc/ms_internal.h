@@ -74,7 +74,7 @@ struct DAux {
 // Offsets (in floats) of the regions of one scene's LDS block.
 struct LdsLayout {
   int fmax, smax, ccap, rcap, owners, ntmax;
-  int robot, sph, fr, aux, stat, plane, own, con, rows, lvl, cand, total;
+  int robot, sph, fr, aux, stat, plane, own, con, rows, lvl, cand, frc, total;
 };
 
 __host__ __device__ inline int lds_align4(int x) { return (x + 3) & ~3; }
@@ -85,14 +85,16 @@ constexpr int ROBOT_FLOATS = 6 * ND + ND * 9 + ND * 3 + ND * 6 + ND * 3 + ND * N
 // Articulated-body scratch (only inside the dynamics phase, shares the space of
 // the robot contact rows): IA[16*36] pA c U [3*16*6] T S2 [2*16*16] Ia[48] Uc[16*16].
 constexpr int DYN_FLOATS = ND * 36 + 3 * ND * 6 + 3 * ND * ND + 48;
-constexpr int FREE_FLOATS = 41;     // per free body (odd stride: conflict-free LDS banks)
+constexpr int FREE_FLOATS = 37;     // per free body (odd stride: conflict-free LDS banks)
 constexpr int FSTR = FREE_FLOATS;
-constexpr int AUX_FLOATS = 40;      // per aux joint
+constexpr int AUX_FLOATS = 32;      // per aux joint
+constexpr int FRC_FLOATS = 5;       // per free body, force-output mode: force on it (3), end-effector and finger force
 constexpr int CON_FLOATS = 17;      // per contact (odd stride)
 constexpr int CSTR = CON_FLOATS;
-constexpr int ROW_FLOATS = 6 * ND;  // per robot contact: J[3][16], w[3][16]
+constexpr int ROW_FLOATS = 3 * ND;  // per robot contact: w = M~^-1 J^T [3][16] (J is formed where it is used)
 
-__host__ __device__ inline LdsLayout make_layout(int fmax, int smax, int ccap, int rcap, int stage_static) {
+__host__ __device__ inline LdsLayout make_layout(int fmax, int smax, int ccap, int rcap, int stage_static,
+                                                 int force = 0, int nsph = SPH) {
   LdsLayout L;
   L.fmax = fmax;
   L.smax = stage_static ? smax : 0;
@@ -102,7 +104,7 @@ __host__ __device__ inline LdsLayout make_layout(int fmax, int smax, int ccap, i
   L.ntmax = PMAX + smax + AMAX + fmax;
   int o = 0;
   L.robot = o; o += lds_align4(ROBOT_FLOATS);
-  L.sph = o;   o += SPH * 4;
+  L.sph = o;   o += nsph * 4;   // world sphere centres and radii of the robot
   L.fr = o;    o += lds_align4(fmax * FREE_FLOATS);
   L.aux = o;   o += AMAX * AUX_FLOATS;
   L.stat = o;  o += lds_align4(L.smax * 6);
@@ -112,6 +114,7 @@ __host__ __device__ inline LdsLayout make_layout(int fmax, int smax, int ccap, i
   L.rows = o;  o += lds_align4(rcap * ROW_FLOATS > DYN_FLOATS ? rcap * ROW_FLOATS : DYN_FLOATS);
   L.lvl = o;   o += lds_align4(3 * ccap + 4 + (ccap + 1) / 2);  // level, level offsets, robot row per level, order
   L.cand = o;  o += lds_align4(L.ntmax);                       // two uint16 candidate lists
+  L.frc = o;   o += force ? lds_align4(fmax * FRC_FLOATS) : 0;  // force-output accumulators
   L.total = o;
   return L;
 }

@@ -161,9 +161,10 @@ __device__ __forceinline__ Robot robot_view(float* base, float* dyn) {
 }
 // free-body fields (structure of arrays, stride fmax)
 enum FF {
-  F_X = 0, F_Q = 3, F_V = 7, F_W = 10, F_R = 13, F_II = 22, F_FRC = 28, F_IM = 31, F_TYPE = 32, F_H = 33, F_IB = 36,
-  F_EE = 39, F_FMIN = 40, F_N = 41
+  F_X = 0, F_Q = 3, F_V = 7, F_W = 10, F_R = 13, F_II = 22, F_IM = 28, F_TYPE = 29, F_H = 30, F_IB = 33, F_N = 36
 };
+// force-output accumulators per free body (own region, force mode only)
+enum FRF { R_FRC = 0, R_EE = 3, R_FMIN = 4 };
 // aux fields (stride AMAX)
 enum AF {
   A_Q = 0, A_QD = 1, A_V = 2, A_R = 3, A_P = 12, A_AX = 15, A_BC = 18, A_IM = 21, A_BH = 22, A_LO = 25, A_HI = 26,
@@ -1225,6 +1226,19 @@ __device__ __forceinline__ f3 aux_col(const float* A, int x, f3 p) {
   return ax;
 }
 
+// Entry j of the robot's Jacobian row for direction d at the point p of a
+// contact on body `body`: d . (a_j x (p - o_j)) for a revolute joint, d . a_j
+// for a prismatic one, 0 when joint j does not move the body
+__device__ __forceinline__ float robot_J(const DModel* M, const Robot& rb, int nb, int body, int j, f3 d, f3 p) {
+  float J = 0.f;
+  if (j < nb && ((M->anc[body] >> j) & 1)) {
+    const float* s = rb.s + j * 6;
+    if (M->jtype[j] == 0) J = dot(d, cross(mk3(s[0], s[1], s[2]), p - mk3(rb.p[j * 3], rb.p[j * 3 + 1], rb.p[j * 3 + 2])));
+    else J = dot(d, mk3(s[3], s[4], s[5]));
+  }
+  return J;
+}
+
 __device__ __forceinline__ void phase_rows(const KArgs& a, const Scene& S, float* L, const Robot& rb, int NC, int NR, int NL,
                            uint32_t& status) {
   const int lane = lane_id();
@@ -1283,7 +1297,8 @@ __device__ __forceinline__ void phase_rows(const KArgs& a, const Scene& S, float
     for (int t = 0; t < 3; ++t) C[(ci) * CSTR + C_LAM + t] = 0.f;
   }
   wave_sync();
-  // robot rows: lane (d, j) builds J[d][j] = d . (dp/dq_j), then w = M~^-1 J^T
+  // robot rows: lane (d, j) builds J[d][j] = d . (dp/dq_j) and W = J M~^-1 J^T
+  // (the sweeps form w = M~^-1 J^T from a register copy of M~^-1's rows)
   float* Rw = L + Y.rows;
   const int d = lane >> 4, j = lane & 15;
   for (int rr = 0; rr < NR; ++rr) {
@@ -1297,21 +1312,13 @@ __device__ __forceinline__ void phase_rows(const KArgs& a, const Scene& S, float
       f3 t1, t2;
       onb(n, t1, t2);
       f3 dir = d == 0 ? n : (d == 1 ? t1 : t2);
-      float J = 0.f;
-      if (j < S.nb && ((M->anc[body] >> j) & 1)) {
-        const float* s = rb.s + j * 6;
-        f3 ax = M->jtype[j] == 0 ? mk3(s[0], s[1], s[2]) : mk3(s[3], s[4], s[5]);
-        if (M->jtype[j] == 0) J = dot(dir, cross(ax, p - mk3(rb.p[j * 3], rb.p[j * 3 + 1], rb.p[j * 3 + 2])));
-        else J = dot(dir, ax);
-      }
-      row[d * ND + j] = J;
+      row[d * ND + j] = robot_J(M, rb, S.nb, body, j, dir, p);
     }
     wave_sync();
+    float w = 0.f;
     if (d < 3) {
-      float w = 0.f;
 #pragma unroll
       for (int k = 0; k < ND; ++k) w += rb.Minv[j * ND + k] * row[d * ND + k];
-      row[3 * ND + d * ND + j] = w;
       float Wr = sum16(row[d * ND + j] * w);
       if (j == 0) C[(ci) * CSTR + C_IW + d] += Wr;
     }
@@ -1463,6 +1470,7 @@ __device__ __forceinline__ void phase_pgs(const KArgs& a, const Scene& S, float*
   float* F = L + Y.fr;
   float* A = L + Y.aux;
   const float* Rw = L + Y.rows;
+  const Robot RB = robot_view(L + Y.robot, L + Y.rows);
   const int* lvl = reinterpret_cast<const int*>(L + Y.lvl);
   const int* loff = lvl + cc;
   const int* rob = loff + cc + 2;
@@ -1485,8 +1493,19 @@ __device__ __forceinline__ void phase_pgs(const KArgs& a, const Scene& S, float*
         float iw0 = c[C_IW], iw1 = c[C_IW + 1], iw2 = c[C_IW + 2];
         float bias = c[C_BIAS];
         float l0 = c[C_LAM], l1 = c[C_LAM + 1], l2 = c[C_LAM + 2];
-        float Jn = row[j], J1 = row[ND + j], J2 = row[2 * ND + j];
-        float wn = row[3 * ND + j], w1 = row[4 * ND + j], w2 = row[5 * ND + j];
+        const float Jn = row[j], J1 = row[ND + j], J2 = row[2 * ND + j];
+        // lane j's entries of w = M~^-1 J^T; M~^-1 is symmetric, so lane j
+        // reads its column (consecutive across the lanes: no bank conflicts)
+        float wn = 0.f, w1 = 0.f, w2 = 0.f;
+#pragma unroll 8
+        for (int k = 0; k < ND; ++k) {
+          const float m = RB.Minv[k * ND + j];
+          wn += m * row[k];
+          w1 += m * row[ND + k];
+          w2 += m * row[2 * ND + k];
+        }
+        f3 t1, t2;
+        onb(n, t1, t2);
         SideReg B;
         side_load(F, A, (info >> 16) & 0xffff, p, B);
         float dn = bcast(sum16(lane < ND ? Jn * vR : 0.f), 0);
@@ -1498,8 +1517,6 @@ __device__ __forceinline__ void phase_pgs(const KArgs& a, const Scene& S, float*
         if (lane < ND) vR += wn * dl;
         side_impulse(B, p, n * (-dl));
         if (iw1 > 0.f && iw2 > 0.f) {
-          f3 t1, t2;
-          onb(n, t1, t2);
           // both tangent dot products in one reduction: lanes 0..15 t1, 16..31 t2
           float vj = __shfl(vR, j, WAVE);
           float part = lane < ND ? J1 * vj : (lane < 2 * ND ? J2 * vj : 0.f);
@@ -1645,8 +1662,7 @@ __device__ __forceinline__ void phase_forces(const KArgs& a, const Scene& S, flo
                                              bool last) {
   const int lane = lane_id();
   const float* C = L + a.L.con;
-  float* F = L + a.L.fr;
-  const int fm = a.L.fmax;
+  float* FR = L + a.L.frc;
   if (a.grip) {
     // gripper contacts, one lane per free body / door-drawer joint: the
     // normal force of the end effector's bodies on it (accumulated), and in
@@ -1667,8 +1683,8 @@ __device__ __forceinline__ void phase_forces(const KArgs& a, const Scene& S, flo
         if (body == a.grip_fr) fr += fn;
       }
       if (isf) {
-        F[o * FSTR + F_EE] += fe;
-        if (last) F[o * FSTR + F_FMIN] = fminf(fl, fr);
+        FR[o * FRC_FLOATS + R_EE] += fe;
+        if (last) FR[o * FRC_FLOATS + R_FMIN] = fminf(fl, fr);
       } else {
         A[A_EE * AMAX + o - S.nf] += fe;
         if (last) A[A_FMIN * AMAX + o - S.nf] = fminf(fl, fr);
@@ -1692,9 +1708,9 @@ __device__ __forceinline__ void phase_forces(const KArgs& a, const Scene& S, flo
       f3 n = mk3(c[C_N], c[C_N + 1], c[C_N + 2]), t1, t2;
       onb(n, t1, t2);
       f3 P = n * c[C_LAM] + t1 * c[C_LAM + 1] + t2 * c[C_LAM + 2];
-      F[(g) * FSTR + F_FRC + 0] -= P.x / a.h;
-      F[(g) * FSTR + F_FRC + 1] -= P.y / a.h;
-      F[(g) * FSTR + F_FRC + 2] -= P.z / a.h;
+      FR[(g) * FRC_FLOATS + R_FRC + 0] -= P.x / a.h;
+      FR[(g) * FRC_FLOATS + R_FRC + 1] -= P.y / a.h;
+      FR[(g) * FRC_FLOATS + R_FRC + 2] -= P.z / a.h;
     }
   }
   wave_sync();
@@ -1731,13 +1747,10 @@ __device__ __forceinline__ void run_scene(const KArgs& a, int s, float* L) {
   uint32_t status = 0;
   float frc = 0.f;
   if (MODE == 2) {
-    float* F = L + a.L.fr;
+    float* FR = L + a.L.frc;
     float* A = L + a.L.aux;
-    const int fm = a.L.fmax;
     for (int f = lane; f < S.nf; f += WAVE) {
-      for (int t = 0; t < 3; ++t) F[(f) * FSTR + F_FRC + t] = 0.f;
-      F[(f) * FSTR + F_EE] = 0.f;
-      F[(f) * FSTR + F_FMIN] = 0.f;
+      for (int t = 0; t < FRC_FLOATS; ++t) FR[(f) * FRC_FLOATS + t] = 0.f;
     }
     if (lane < S.na) {
       A[A_EE * AMAX + lane] = 0.f;
@@ -1780,26 +1793,24 @@ __device__ __forceinline__ void run_scene(const KArgs& a, int s, float* L) {
   }
   store_scene(a, S, L, rb, status);
   if (MODE == 2 && a.grip) {
-    const float* F = L + a.L.fr;
+    const float* FR = L + a.L.frc;
     const float* A = L + a.L.aux;
-    const int fm = a.L.fmax;
     const bool last = a.sub0 + a.n_sub == a.n_sub_total;
     for (int o = lane; o < S.nf + S.na; o += WAVE) {
       const bool isf = o < S.nf;
       float* dst = a.grip + 2 * (isf ? (size_t)(S.f0 + o) : (size_t)a.NF + S.a0 + (o - S.nf));
-      const float fe = isf ? F[o * FSTR + F_EE] : A[A_EE * AMAX + o - S.nf];
+      const float fe = isf ? FR[o * FRC_FLOATS + R_EE] : A[A_EE * AMAX + o - S.nf];
       dst[0] = a.sub0 == 0 ? fe : dst[0] + fe;
-      if (last) dst[1] = isf ? F[o * FSTR + F_FMIN] : A[A_FMIN * AMAX + o - S.nf];
+      if (last) dst[1] = isf ? FR[o * FRC_FLOATS + R_FMIN] : A[A_FMIN * AMAX + o - S.nf];
     }
   }
   if (MODE == 2 && a.frc_robot) {
-    const float* F = L + a.L.fr;
-    const int fm = a.L.fmax;
+    const float* FR = L + a.L.frc;
     if (lane == 0) a.frc_robot[s] = a.sub0 == 0 ? frc : a.frc_robot[s] + frc;
     for (int f = lane; f < S.nf; f += WAVE) {
       float* dst = a.frc_body + (size_t)(S.f0 + f) * 4;
       for (int t = 0; t < 3; ++t) {
-        float v = F[(f) * FSTR + F_FRC + t];
+        float v = FR[(f) * FRC_FLOATS + R_FRC + t];
         dst[t] = a.sub0 == 0 ? v : dst[t] + v;
       }
       dst[3] = 0.f;

@@ -35,6 +35,7 @@ inline size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
 struct Counts {
   int S, M, NF, NS, NP, NA;
   int fmax, smax, pmax, amax;
+  int nsph_max;  // most robot spheres of a model
 };
 
 inline ms_status validate(const ms_batch_desc* d, const ms_scene_desc* sc, Counts& c) {
@@ -59,11 +60,13 @@ inline ms_status validate(const ms_batch_desc* d, const ms_scene_desc* sc, Count
     if (!p) return fail(MS_E_INVALID, "a required scene array is null");
   c.S = d->n_scenes;
   c.M = sc->n_models;
+  c.nsph_max = 0;
   if (c.M <= 0) return fail(MS_E_INVALID, "n_models must be positive");
   for (int m = 0; m < c.M; ++m) {
     int nb = sc->model_nb[m], ns = sc->model_nsph[m];
     if (nb < 0 || nb > ND) return fail(MS_E_INVALID, "model %d: %d bodies (max %d)", m, nb, ND);
     if (ns < 0 || ns > SPH) return fail(MS_E_INVALID, "model %d: %d spheres (max %d)", m, ns, SPH);
+    c.nsph_max = std::max(c.nsph_max, ns);
     for (int i = 0; i < nb; ++i) {
       int p = sc->model_parent[m * ND + i];
       if (p >= i || p < -1) return fail(MS_E_INVALID, "model %d body %d: parent %d must precede it", m, i, p);
@@ -169,8 +172,9 @@ inline ScratchLayout scratch_layout(const Counts& c, int n_sub) {
 
 inline int lds_ccap(const ms_batch_desc* d) { return d->contact_cap; }
 
-inline LdsLayout lds_for(const ms_batch_desc* d, const Counts& c, bool stage_static) {
-  return make_layout(std::max(c.fmax, 1), c.smax, lds_ccap(d), std::max(d->robot_contact_cap, 1), stage_static ? 1 : 0);
+inline LdsLayout lds_for(const ms_batch_desc* d, const Counts& c, bool stage_static, bool force = false) {
+  return make_layout(std::max(c.fmax, 1), c.smax, lds_ccap(d), std::max(d->robot_contact_cap, 1), stage_static ? 1 : 0,
+                     force ? 1 : 0, std::max(c.nsph_max, 1));
 }
 
 
