@@ -402,10 +402,11 @@ __device__ __forceinline__ void robot_rows_bar_wave(msa::Eng& E, float* L) {
 
 // Recompute of a substep's articulated quantities over the lanes: drive
 // (lane per DoF), door/drawer and free-body frames (lane per joint / body),
-// body poses down the tree on lane 0, per-body quantities (lane per body),
-// then CRBA + RNEA with every recursion written as a sum over ancestors or
-// descendants (lane per body or per matrix entry), and a column-by-column
-// Cholesky factor of M~.  The bias torques are left in w.lz.
+// body poses by pointer jumping (lane per body, four doubling rounds),
+// per-body quantities (lane per body); CRBA and RNEA with the tree
+// recursions run down or up the tree by one lane per matrix or vector
+// component, the per-body terms one lane per body; M~^-1 by Gauss-Jordan
+// elimination over the lanes.  The bias torques are left in w.lz.
 __device__ __forceinline__ void recompute_wave(msa::Eng& E, float* L, const float* u) {
   using namespace msa;
   const int lane = lane_id();
@@ -416,41 +417,99 @@ __device__ __forceinline__ void recompute_wave(msa::Eng& E, float* L, const floa
   if (lane < ND) E.drive_one(s, u, lane);
   if (lane >= ND && lane < ND + E.sc.na) E.aux_frame(s, lane - ND);
   for (int f = lane; f < E.sc.nf; f += 64) E.free_frame(s, f);
-  if (lane == 0)
-    for (int i = 0; i < nb; ++i) E.kin_pose(s, i);
+  // body poses: each body's joint transform relative to its parent, then
+  // X_i <- X_a X_i with a the current ancestor, a <- a's ancestor, until the
+  // root (the ancestor index lives in w.z, free until z is solved)
+  int anc = -1;
+  if (lane < nb) {
+    const int i = lane;
+    const V ax = ld3(M.axis[i]);
+    float R[9];
+    V p = ld3(M.xtp[i]);
+    if (M.jtype[i] == 0) {
+      float Rr[9];
+      rot_axis(ax, L[s + i], Rr);
+      mm3(M.xtR[i], Rr, R);
+    } else {
+      for (int t = 0; t < 9; ++t) R[t] = M.xtR[i][t];
+      p = p + rmv(M.xtR[i], ax) * L[s + i];
+    }
+    for (int t = 0; t < 9; ++t) L[w.kR + i * 9 + t] = R[t];
+    E.s3(w.kp + i * 3, p);
+    anc = M.parent[i];
+    L[w.z + i] = __int_as_float(anc);
+  }
+  wsync();
+  for (int round = 0; round < 4; ++round) {
+    float Ra[9], R[9], Rn[9];
+    V pa{0.f, 0.f, 0.f}, p{0.f, 0.f, 0.f};
+    int anc2 = -1;
+    const bool act = lane < nb && anc >= 0;
+    if (act) {
+      for (int t = 0; t < 9; ++t) {
+        Ra[t] = L[w.kR + anc * 9 + t];
+        R[t] = L[w.kR + lane * 9 + t];
+      }
+      pa = E.v3(w.kp + anc * 3);
+      p = E.v3(w.kp + lane * 3);
+      anc2 = __float_as_int(L[w.z + anc]);
+    }
+    wsync();
+    if (act) {
+      mm3(Ra, R, Rn);
+      for (int t = 0; t < 9; ++t) L[w.kR + lane * 9 + t] = Rn[t];
+      E.s3(w.kp + lane * 3, pa + rmv(Ra, p));
+      anc = anc2;
+      L[w.z + lane] = __int_as_float(anc);
+    }
+    wsync();
+  }
+  // joint axis and origin from the parent's world pose
+  if (lane < nb) {
+    const int i = lane, par = M.parent[i];
+    float Rj[9];
+    V o;
+    if (par < 0) {
+      for (int t = 0; t < 9; ++t) Rj[t] = M.xtR[i][t];
+      o = ld3(M.xtp[i]);
+    } else {
+      float Rp[9];
+      E.ld9(w.kR + par * 9, Rp);
+      mm3(Rp, M.xtR[i], Rj);
+      o = E.v3(w.kp + par * 3) + rmv(Rp, ld3(M.xtp[i]));
+    }
+    E.s3(w.ka + i * 3, rmv(Rj, ld3(M.axis[i])));
+    E.s3(w.ko + i * 3, o);
+  }
   wsync();
   if (lane < nb) E.kin_body(lane);
-  for (int idx = lane; idx < ND * ND; idx += 64) L[w.L + idx] = 0.f;
   wsync();
-  // composite inertias: Ic_i = sum of I_k over the subtree of i
-  for (int idx = lane; idx < nb * 36; idx += 64) {
-    const int i = idx / 36, t = idx - 36 * (idx / 36);
-    float acc = 0.f;
-    for (int k = i; k < nb; ++k)
-      if ((M.anc[k] >> i) & 1) acc += L[w.kI + k * 36 + t];
-    L[w.kIc + i * 36 + t] = acc;
-  }
-  // velocities v_i = sum over the ancestors k of s_k qd_k; the terms
-  // v_i x (s_i qd_i) go to rff for the accelerations
-  if (lane < nb) {
-    const int i = lane;
-    float v[6] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
-    for (int k = 0; k <= i; ++k)
-      if ((M.anc[i] >> k) & 1) {
-        const float qd = L[s + ND + k];
-        for (int t = 0; t < 6; ++t) v[t] += L[w.ks + k * 6 + t] * qd;
-      }
-    E.st6(w.rv + i * 6, v);
-    float vJ[6], t6[6];
-    const float qd = L[s + ND + i];
-    for (int t = 0; t < 6; ++t) vJ[t] = L[w.ks + i * 6 + t] * qd;
-    Eng::crm6(v, vJ, t6);
-    E.st6(w.rff + i * 6, t6);
+  // composite inertias (one lane per entry, up the tree) and velocities
+  // v_i = v_par + s_i qd_i (one lane per component, down the tree)
+  for (int idx = lane; idx < nb * 36; idx += 64) L[w.kIc + idx] = L[w.kI + idx];
+  // M~: zero, identity past the robot's DoFs
+  for (int e = lane; e < ND * ND; e += 64) {
+    const int r = e >> 4, c = e & 15;
+    L[w.L + e] = (r >= nb || c >= nb) && r == c ? 1.f : 0.f;
   }
   wsync();
+  if (lane < 36) {
+    for (int i = nb - 1; i > 0; --i) {
+      const int par = M.parent[i];
+      if (par >= 0) L[w.kIc + par * 36 + lane] += L[w.kIc + i * 36 + lane];
+    }
+  } else if (lane < 42) {
+    const int t = lane - 36;
+    for (int i = 0; i < nb; ++i) {
+      const int par = M.parent[i];
+      L[w.rv + i * 6 + t] = (par >= 0 ? L[w.rv + par * 6 + t] : 0.f) + L[w.ks + i * 6 + t] * L[s + ND + i];
+    }
+  }
+  wsync();
+  // mass matrix row / column i: M_ij = s_j . (Ic_i s_i), j an ancestor of i;
+  // the terms v_i x (s_i qd_i) (into ra, summed down the tree below)
   if (lane < nb) {
     const int i = lane;
-    // mass matrix row / column i: M_ij = s_j . (Ic_i s_i), j an ancestor of i
     float si[6], F[6];
     E.ld6(w.ks + i * 6, si);
     E.mul6(w.kIc + i * 36, si, F);
@@ -460,15 +519,29 @@ __device__ __forceinline__ void recompute_wave(msa::Eng& E, float* L, const floa
       L[w.L + i * ND + j] = v;
       L[w.L + j * ND + i] = v;
     }
-    // accelerations a_i = -g + sum over the ancestors of v_k x (s_k qd_k)
-    float acc[6] = {0.f, 0.f, 0.f, -E.pr.g[0], -E.pr.g[1], -E.pr.g[2]};
-    for (int k = 0; k <= i; ++k)
-      if ((M.anc[i] >> k) & 1)
-        for (int t = 0; t < 6; ++t) acc[t] += L[w.rff + k * 6 + t];
-    E.st6(w.ra + i * 6, acc);
+    float v[6], vJ[6], t6[6];
+    E.ld6(w.rv + i * 6, v);
+    const float qd = L[s + ND + i];
+    for (int t = 0; t < 6; ++t) vJ[t] = si[t] * qd;
+    Eng::crm6(v, vJ, t6);
+    E.st6(w.ra + i * 6, t6);
   }
   wsync();
-  // body forces f_i = I_i a_i + v_i x* (I_i v_i)
+  // accelerations a_i = a_par + v_i x (s_i qd_i), a_root's parent = -g
+  if (lane < 6) {
+    const int t = lane;
+    // the base acceleration's component t, formed arithmetically: a lane-
+    // dependent index into the parameters (or a select the compiler turns
+    // into one) would put the engine object in scratch memory
+    const float g0 = E.pr.g[0], g1 = E.pr.g[1], g2 = E.pr.g[2];
+    const float base = -(g0 * (float)(t == 3) + g1 * (float)(t == 4) + g2 * (float)(t == 5));
+    for (int i = 0; i < nb; ++i) {
+      const int par = M.parent[i];
+      L[w.ra + i * 6 + t] += par >= 0 ? L[w.ra + par * 6 + t] : base;
+    }
+  }
+  wsync();
+  // body forces f_i = I_i a_i + v_i x* (I_i v_i) into rfl and rff
   if (lane < nb) {
     const int i = lane;
     float v[6], acc[6], fl[6], hv[6], t6[6];
@@ -479,40 +552,55 @@ __device__ __forceinline__ void recompute_wave(msa::Eng& E, float* L, const floa
     Eng::crf6(v, hv, t6);
     for (int t = 0; t < 6; ++t) fl[t] += t6[t];
     E.st6(w.rfl + i * 6, fl);
+    E.st6(w.rff + i * 6, fl);
   }
   wsync();
-  // subtree force sums and the bias torques C_i = s_i . sum
+  // subtree force sums (one lane per component, up the tree)
+  if (lane < 6) {
+    for (int i = nb - 1; i > 0; --i) {
+      const int par = M.parent[i];
+      if (par >= 0) L[w.rff + par * 6 + lane] += L[w.rff + i * 6 + lane];
+    }
+  }
+  wsync();
+  // bias torques C_i = s_i . f_i; M~ = M + diag(armature), copied to the
+  // M~^-1 buffer for the elimination
   if (lane < nb) {
     const int i = lane;
-    float f[6] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
-    for (int k = i; k < nb; ++k)
-      if ((M.anc[k] >> i) & 1)
-        for (int t = 0; t < 6; ++t) f[t] += L[w.rfl + k * 6 + t];
-    E.st6(w.rff + i * 6, f);
     float c = 0.f;
-    for (int t = 0; t < 6; ++t) c += L[w.ks + i * 6 + t] * f[t];
+    for (int t = 0; t < 6; ++t) c += L[w.ks + i * 6 + t] * L[w.rff + i * 6 + t];
     L[w.lz + i] = c;
     L[w.L + i * ND + i] += L[w.arm + i];
   }
   wsync();
-  // Cholesky factor of M~ (lower triangle), one column at a time
-  for (int j = 0; j < nb; ++j) {
-    if (lane == 0) {
-      float d = L[w.L + j * ND + j];
-      for (int k = 0; k < j; ++k) d -= L[w.L + j * ND + k] * L[w.L + j * ND + k];
-      if (!(d > 0.f)) {
-        E.status |= Eng::MS_DEGENERATE_BIT;
-        d = 1e-30f;
-      }
-      L[w.L + j * ND + j] = sqrtf(d);
+  // Gauss-Jordan elimination without pivoting (M~ is symmetric positive
+  // definite): 16 pivots between the two buffers, so the inverse ends where
+  // it started; lane owns entries lane, lane + 64, lane + 128, lane + 192
+  for (int p = 0; p < ND; ++p) {
+    const float* A = L + ((p & 1) ? w.Minv : w.L);
+    float* B = L + ((p & 1) ? w.L : w.Minv);
+    float piv = A[p * ND + p];
+    if (p < nb && !(piv > 0.f)) {
+      if (lane == 0) E.status |= Eng::MS_DEGENERATE_BIT;
+      piv = 1e-30f;
+    }
+    const float inv = 1.f / piv;
+    for (int e = lane; e < ND * ND; e += 64) {
+      const int i = e >> 4, k = e & 15;
+      float v;
+      if (i == p && k == p) v = inv;
+      else if (i == p) v = A[p * ND + k] * inv;
+      else if (k == p) v = -A[i * ND + p] * inv;
+      else v = A[e] - A[i * ND + p] * (A[p * ND + k] * inv);
+      B[e] = v;
     }
     wsync();
-    if (lane > j && lane < nb) {
-      float sm = L[w.L + lane * ND + j];
-      for (int k = 0; k < j; ++k) sm -= L[w.L + lane * ND + k] * L[w.L + j * ND + k];
-      L[w.L + lane * ND + j] = sm / L[w.L + j * ND + j];
-    }
-    wsync();
+  }
+  // the inverse is in w.L after an even number of pivots: move it and clear
+  // the padding
+  for (int e = lane; e < ND * ND; e += 64) {
+    const int i = e >> 4, k = e & 15;
+    L[w.Minv + e] = i < nb && k < nb ? L[w.L + e] : 0.f;
   }
 }
 
@@ -592,13 +680,13 @@ __device__ __forceinline__ void dynamics_bar_wave(msa::Eng& E, float* L) {
     for (int t = 0; t < 6; ++t) sb[t] += Cb * L[w.rff + j * 6 + t];
     E.st6(w.sb + j * 6, sb);
   }
-  // Ibar_i = sum over the ancestors of Icbar_k (entry per lane)
-  for (int idx = lane; idx < nb * 36; idx += 64) {
-    const int i = idx / 36, t = idx - 36 * (idx / 36);
-    float acc = 0.f;
-    for (int k = 0; k <= i; ++k)
-      if ((M.anc[i] >> k) & 1) acc += L[w.Icb + k * 36 + t];
-    L[w.Ib + i * 36 + t] = acc;
+  wsync();
+  // Ibar_i = Icbar_i + Ibar_par (one lane per entry, down the tree)
+  if (lane < 36) {
+    for (int i = 0; i < nb; ++i) {
+      const int par = M.parent[i];
+      L[w.Ib + i * 36 + lane] = L[w.Icb + i * 36 + lane] + (par >= 0 ? L[w.Ib + par * 36 + lane] : 0.f);
+    }
   }
   wsync();
   // body terms of f = I a + v x* (I v): Ibar, the own parts of abar and vbar
@@ -626,15 +714,20 @@ __device__ __forceinline__ void dynamics_bar_wave(msa::Eng& E, float* L) {
     E.st6(w.tV + i * 6, ov);
   }
   wsync();
-  // abar_i = subtree sum of the own parts; the a = a_par + v x vJ term's
-  // share of vbar_i
+  // abar_i = subtree sum of the own parts (one lane per component, up the
+  // tree); then the a = a_par + v x vJ term's share of vbar_i
+  if (lane < 6) {
+    for (int i = 0; i < nb; ++i) L[w.abar + i * 6 + lane] = L[w.tA + i * 6 + lane];
+    for (int i = nb - 1; i > 0; --i) {
+      const int par = M.parent[i];
+      if (par >= 0) L[w.abar + par * 6 + lane] += L[w.abar + i * 6 + lane];
+    }
+  }
+  wsync();
   if (lane < nb) {
     const int i = lane;
-    float ab[6] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
-    for (int k = i; k < nb; ++k)
-      if ((M.anc[k] >> i) & 1)
-        for (int t = 0; t < 6; ++t) ab[t] += L[w.tA + k * 6 + t];
-    E.st6(w.abar + i * 6, ab);
+    float ab[6];
+    E.ld6(w.abar + i * 6, ab);
     const float qd = L[s + ND + i];
     const float* si = L + w.ks + i * 6;
     V vJw{si[0] * qd, si[1] * qd, si[2] * qd}, vJv{si[3] * qd, si[4] * qd, si[5] * qd};
@@ -644,14 +737,20 @@ __device__ __forceinline__ void dynamics_bar_wave(msa::Eng& E, float* L) {
     E.st6(w.tV2 + i * 6, o2);
   }
   wsync();
-  // vbar_i = subtree sum of both own parts; the joint velocity's adjoint
+  // vbar_i = subtree sum of both own parts (one lane per component, up the
+  // tree); the joint velocity's adjoint
+  if (lane < 6) {
+    for (int i = 0; i < nb; ++i) L[w.vbar + i * 6 + lane] = L[w.tV + i * 6 + lane] + L[w.tV2 + i * 6 + lane];
+    for (int i = nb - 1; i > 0; --i) {
+      const int par = M.parent[i];
+      if (par >= 0) L[w.vbar + par * 6 + lane] += L[w.vbar + i * 6 + lane];
+    }
+  }
+  wsync();
   if (lane < nb) {
     const int i = lane;
-    float vb[6] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
-    for (int k = i; k < nb; ++k)
-      if ((M.anc[k] >> i) & 1)
-        for (int t = 0; t < 6; ++t) vb[t] += L[w.tV + k * 6 + t] + L[w.tV2 + k * 6 + t];
-    E.st6(w.vbar + i * 6, vb);
+    float vb[6];
+    E.ld6(w.vbar + i * 6, vb);
     float v[6], ab[6], si[6];
     E.ld6(w.rv + i * 6, v);
     E.ld6(w.abar + i * 6, ab);
@@ -800,7 +899,6 @@ __device__ void bwd_scene(const BwdArgs& a, int s, float* L) {
     E.nrob = NR;
     recompute_wave(E, L, u);
     phase(1);
-    build_minv(E, L);
     wsync();
     solve_z_wave(E, L);
     rows_wave(E, L);
