@@ -86,8 +86,14 @@ enum {
   MS_SCHED_PER_SUBSTEP = 4,   /* one launch per substep (state round trip through HBM) */
   MS_SCHED_STAGE_STATIC = 8,  /* stage each scene's furniture boxes in LDS */
   MS_SCHED_CULL = 16,         /* bounding-sphere pre-test before sphere-pair tests */
-  MS_SCHED_BWD_REFERENCE = 32 /* ms_step_backward on the lane-per-scene kernel that
-                                 recomputes everything itself (slow; a cross-check) */
+  MS_SCHED_BWD_REFERENCE = 32, /* ms_step_backward on the lane-per-scene kernel that
+                                  recomputes everything itself (slow; a cross-check) */
+  MS_SCHED_BWD_ONE_LAUNCH = 64  /* ms_step_backward in one wavefront launch sized for the
+                                  contact caps.  Without it the scenes whose contact
+                                  lists fit a smaller LDS layout (more workgroups per
+                                  CU) run in one launch and the rest in a second launch
+                                  on a library-owned stream, joined back onto the
+                                  caller's stream; the results are the same bit for bit */
 };
 
 typedef struct {
@@ -197,6 +203,17 @@ ms_status ms_destroy_batch(ms_batch* b);
 /* Choose how ms_step runs (see MS_SCHED_*).  Drops captured graphs. */
 ms_status ms_set_schedule(ms_batch* b, const ms_schedule* sched);
 ms_status ms_get_schedule(const ms_batch* b, ms_schedule* out);
+
+/* Contact caps of the smaller LDS layout of the split ms_step_backward (see
+ * MS_SCHED_BWD_ONE_LAUNCH): scenes whose contact lists hold at most
+ * contact_cap contacts and robot_contact_cap robot contacts in every substep
+ * of the step run in the smaller layout, the others in the full one.  At
+ * creation the library picks the caps that raise the number of workgroups per
+ * CU (contact_cap 0: no such caps, one launch).  contact_cap 0 turns the
+ * split off; contact_cap < 0 restores the library's choice.  Error
+ * MS_E_INVALID when a cap exceeds the batch's.  Either output may be null. */
+ms_status ms_set_backward_split(ms_batch* b, int32_t contact_cap, int32_t robot_contact_cap);
+ms_status ms_get_backward_split(const ms_batch* b, int32_t* contact_cap, int32_t* robot_contact_cap);
 
 /* Time the candidate schedules on the given state / controls (the state is
  * not modified: a copy in tmp_state_dev is stepped) and keep the fastest.

@@ -23,10 +23,11 @@ MS_SCHED_PER_SUBSTEP = 4
 MS_SCHED_STAGE_STATIC = 8
 MS_SCHED_CULL = 16
 MS_SCHED_BWD_REFERENCE = 32
+MS_SCHED_BWD_ONE_LAUNCH = 64
 MS_ST_NONFINITE, MS_ST_OVERFLOW, MS_ST_DEGENERATE, MS_ST_ROBOT_OVERFLOW = 1, 2, 4, 8
 
 EXPORTS = ["ms_query_sizes", "ms_state_floats", "ms_create_batch", "ms_destroy_batch", "ms_set_schedule",
-           "ms_get_schedule", "ms_autotune", "ms_step", "ms_step_backward", "ms_get_state", "ms_set_state",
+           "ms_get_schedule", "ms_set_backward_split", "ms_get_backward_split", "ms_autotune", "ms_step", "ms_step_backward", "ms_get_state", "ms_set_state",
            "ms_scene_status", "ms_set_force_outputs", "ms_reset_robots", "ms_spawn_check", "ms_enable_debug",
            "ms_debug_contacts", "ms_enable_phase_profile", "ms_phase_cycles", "ms_set_task_robot",
            "ms_set_grip_outputs", "ms_task_begin", "ms_task_update", "ms_task_categorize", "ms_last_error"]
@@ -111,6 +112,8 @@ def lib():
             "ms_destroy_batch": [vp],
             "ms_set_schedule": [vp, vp],
             "ms_get_schedule": [vp, vp],
+            "ms_set_backward_split": [vp, i32, i32],
+            "ms_get_backward_split": [vp, vp, vp],
             "ms_autotune": [vp, vp, vp, vp, i32, vp, vp, vp],
             "ms_step": [vp, vp, vp, vp, vp],
             "ms_step_backward": [vp, vp, vp, vp, vp, vp, vp],
@@ -414,6 +417,17 @@ class MsBatch:
         s = Schedule()
         _check(lib().ms_get_schedule(self.h, C.byref(s)), "ms_get_schedule")
         return s.flags, s.grid
+
+    def set_backward_split(self, contact_cap, robot_contact_cap=1):
+        """Caps of the smaller adjoint layout (0: one launch; < 0: the
+        library's choice)."""
+        _check(lib().ms_set_backward_split(self.h, int(contact_cap), int(robot_contact_cap)),
+               "ms_set_backward_split")
+
+    def get_backward_split(self):
+        cc, rc = C.c_int32(), C.c_int32()
+        _check(lib().ms_get_backward_split(self.h, C.byref(cc), C.byref(rc)), "ms_get_backward_split")
+        return cc.value, rc.value
 
     def autotune(self, x, u, reps=5, stream=None):
         tmp = self.torch.empty_like(x)

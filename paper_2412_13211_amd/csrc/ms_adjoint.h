@@ -187,6 +187,7 @@ struct WS {
   int Mb, sb, Ib, Icb, fbar, abar, vbar, bacc;
   int lv;    // level schedule (wavefront kernel only)
   int tring;  // two sweeps of the tape staged from the record (wavefront kernel only)
+  int trs;    // floats per staged sweep
   int Minv;  // explicit M~^-1 (wavefront kernel only)
   int lz;    // bias torques, then M~^-1 h vRbar (wavefront kernel only)
   int tF, tFb, tA, tV, tV2;  // per-body scratch of the wavefront dynamics^T
@@ -232,12 +233,18 @@ MSA_HD inline WS ws_layout(int fmax, int ntmax, int ccap, int rcap, int K, int n
   w.vRb = take(ND); w.vAb = take(AMAX); w.vFb = take(fm * 6);
   w.lamb = take(3 * ccap); w.llamb = take(2 * AMAX); w.limb = take(2 * AMAX);
   w.conb = take(ccap * CB);
-  // the robot rows' adjoints are dead once rows^T is done; the dynamics^T
-  // scratch (written before it is read) shares their space
-  const int rows_b = 2 * w.rcap * 3 * ND, dyn_b = ND * 6 + 2 * ND * 36 + 8 * ND * 6;
-  const int kb = take(rows_b > dyn_b ? rows_b : dyn_b);
+  // the robot rows' adjoints (and in the wavefront kernel the staged tape)
+  // are dead once rows^T is done; the dynamics^T scratch (written before it
+  // is read) shares their space.  The wavefront kernel forms Ibar in place
+  // of Icbar.
+  w.trs = 3 * (2 * AMAX + ccap);
+  const int rows_b = 2 * w.rcap * 3 * ND;
+  const int live_b = rows_b + (wave ? 2 * w.trs : 0);
+  const int dyn_b = ND * 6 + (wave ? 1 : 2) * ND * 36 + 8 * ND * 6;
+  const int kb = take(live_b > dyn_b ? live_b : dyn_b);
   w.rJb = kb; w.rwb = kb + w.rcap * 3 * ND;
-  w.sb = kb; w.Ib = w.sb + ND * 6; w.Icb = w.Ib + ND * 36;
+  w.tring = wave ? kb + rows_b : 0;
+  w.sb = kb; w.Ib = w.sb + ND * 6; w.Icb = wave ? w.Ib : w.Ib + ND * 36;
   w.fbar = w.Icb + ND * 36; w.abar = w.fbar + ND * 6; w.vbar = w.abar + ND * 6;
   w.tF = w.vbar + ND * 6; w.tFb = w.tF + ND * 6; w.tA = w.tFb + ND * 6; w.tV = w.tA + ND * 6;
   w.tV2 = w.tV + ND * 6;
@@ -245,7 +252,6 @@ MSA_HD inline WS ws_layout(int fmax, int ntmax, int ccap, int rcap, int K, int n
   w.Mb = take(ND * ND);
   w.bacc = take(ND * 9);
   w.lv = take(wave ? lv_ints(ccap) : 0);
-  w.tring = take(wave ? 2 * 3 * ccap : 0);
   w.Minv = take(wave ? ND * ND : 0);
   w.lz = take(wave ? ND : 0);
   w.total = o;
@@ -1507,6 +1513,51 @@ struct Eng {
     fs_row_bar(S, A, di, S.v * rb, S.w * rb);
     S.vb = S.vb + lin * rb;
     S.wb = S.wb + ang * rb;
+  }
+  // a door / drawer target in registers: J = -(d . (a x (p - o))) (revolute)
+  // or -(d . a) (prismatic), v += (J / M) dl; the arithmetic of the aux
+  // branches of apply / apply_bar / rowvel / rowvel_bar / aux_J_bar, with the
+  // direction and point adjoints accumulated in the RowAcc
+  struct XSide {
+    int x, type;
+    V a, o;
+    float M, v, vb;
+  };
+  MSA_HD void xs_load(XSide& X, int x) const {
+    X.x = x;
+    X.type = sc.A[x].type;
+    X.a = v3(w.xa + x * 3);
+    X.o = v3(w.xo + x * 3);
+    X.M = at(w.xM + x);
+    X.v = at(w.vA + x);
+    X.vb = at(w.vAb + x);
+  }
+  MSA_HD void xs_store(const XSide& X) const {
+    at(w.vA + X.x) = X.v;
+    at(w.vAb + X.x) = X.vb;
+  }
+  MSA_HD static float xs_J(const XSide& X, const RowAcc& A, int di) {
+    return X.type == 0 ? -dot(A.d[di], cross(X.a, A.p - X.o)) : -dot(A.d[di], X.a);
+  }
+  MSA_HD static void xs_J_bar(const XSide& X, RowAcc& A, int di, float Jb) {
+    if (X.type == 0) {
+      A.db[di] = A.db[di] - cross(X.a, A.p - X.o) * Jb;
+      A.pb = A.pb - cross(A.d[di], X.a) * Jb;
+    } else {
+      A.db[di] = A.db[di] - X.a * Jb;
+    }
+  }
+  MSA_HD static void xs_apply(XSide& X, const RowAcc& A, int di, float dl) { X.v += (xs_J(X, A, di) / X.M) * dl; }
+  MSA_HD static float xs_apply_bar(XSide& X, RowAcc& A, int di, float dl) {
+    const float J = xs_J(X, A, di);
+    xs_J_bar(X, A, di, X.vb * dl / X.M);
+    return (J / X.M) * X.vb;
+  }
+  MSA_HD static float xs_rowvel(const XSide& X, const RowAcc& A, int di) { return xs_J(X, A, di) * X.v; }
+  MSA_HD static void xs_rowvel_bar(XSide& X, RowAcc& A, int di, float rb) {
+    const float J = xs_J(X, A, di);
+    xs_J_bar(X, A, di, rb * X.v);
+    X.vb += rb * J;
   }
   MSA_HD void contact_bar_reg(int it, int ci, int oi, int tk, int ti) const {
     const long e = w.con + (long)ci * CR, cb = w.conb + (long)ci * CB, lb = w.lamb + ci * 3;

@@ -55,12 +55,24 @@ struct ms_batch {
   ms_task_robot task_robot;
   float* grip;
   hipStream_t cap_stream;
+  // split adjoint launches: contact caps of the smaller LDS layout (0: no
+  // split), the stream of the full-size launch and the fork / join events
+  int split_c, split_r;
+  hipStream_t bwd_stream;
+  hipEvent_t ev_fork, ev_join;
   // graphs keyed by (x_in, u, x_out)
   std::map<std::tuple<const void*, const void*, void*>, hipGraphExec_t> graphs;
   std::map<std::tuple<const void*, const void*, void*>, hipGraph_t> graph_defs;
 };
 
 namespace {
+
+void release_handles(ms_batch* b) {
+  if (b->cap_stream) (void)hipStreamDestroy(b->cap_stream);
+  if (b->bwd_stream) (void)hipStreamDestroy(b->bwd_stream);
+  if (b->ev_fork) (void)hipEventDestroy(b->ev_fork);
+  if (b->ev_join) (void)hipEventDestroy(b->ev_join);
+}
 
 void drop_graphs(ms_batch* b) {
   for (auto& kv : b->graphs) (void)hipGraphExecDestroy(kv.second);
@@ -172,11 +184,48 @@ msa::WS bwd_ws(const ms_batch_desc* d, const Counts& c) {
                     d->n_substeps);
 }
 
-// LDS block of the wavefront adjoint kernel
-msa::WS bwd_ws_wave(const ms_batch_desc* d, const Counts& c) {
+// LDS block of the wavefront adjoint kernel, for the batch's contact caps or
+// for smaller ones (cc contacts, rc robot contacts)
+msa::WS bwd_ws_wave(const ms_batch_desc* d, const Counts& c, int cc = -1, int rc = -1) {
   const int ntmax = c.pmax + c.smax + c.amax + std::max(c.fmax, 1);
-  return msa::ws_layout(std::max(c.fmax, 1), ntmax, d->contact_cap, std::max(d->robot_contact_cap, 1), d->pgs_iters,
-                        d->n_substeps, true);
+  return msa::ws_layout(std::max(c.fmax, 1), ntmax, cc < 0 ? d->contact_cap : cc,
+                        rc < 0 ? std::max(d->robot_contact_cap, 1) : rc, d->pgs_iters, d->n_substeps, true);
+}
+
+// Workgroups of the wavefront adjoint per CU at an LDS size.  Near the
+// thresholds gfx950 fits fewer single-wave workgroups than the occupancy
+// query reports (timed: three fit at 53760 B but not at 53768 B, five at
+// 32000 B but not at 32064 B, while the query allows 54528 B and 32768 B);
+// n workgroups are counted as fitting only when n (size + 1 KiB) stays
+// within the CU's 160 KiB, which stays below every measured threshold.
+int bwd_per_cu(size_t lds) {
+  int n = 0;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, step_bwd_wave_ptr(), 64, lds) != hipSuccess) n = 0;
+  const int by_size = (int)(size_t{163840} / (lds + 1024));
+  return std::min(n, by_size);
+}
+
+// Contact caps of a second, smaller LDS layout of the wavefront adjoint that
+// fits more workgroups per CU: at most 8 robot contacts and the largest
+// contact count (not below half the batch's cap) that raises the occupancy.
+// Scenes whose lists fit it run at that occupancy; the rest run beside them
+// in a launch sized for the batch's caps.  0, 0 when no such layout exists.
+void choose_bwd_split(const ms_batch* b, int& cc, int& rc) {
+  cc = rc = 0;
+  const ms_batch_desc* d = &b->desc;
+  const size_t full = (size_t)bwd_ws_wave(d, b->cnt).total * sizeof(float);
+  if (full > b->max_lds) return;
+  const int occ = bwd_per_cu(full);
+  if (occ <= 0) return;
+  const int r = std::min(std::max(d->robot_contact_cap, 1), 8);
+  for (int k = d->contact_cap; k >= std::max(d->contact_cap / 2, 1); --k) {
+    if (k == d->contact_cap && r == std::max(d->robot_contact_cap, 1)) continue;
+    if (bwd_per_cu((size_t)bwd_ws_wave(d, b->cnt, k, r).total * sizeof(float)) > occ) {
+      cc = k;
+      rc = r;
+      return;
+    }
+  }
 }
 
 // record of a control step written by the forward kernel for the wavefront adjoint kernel
@@ -266,9 +315,15 @@ ms_status ms_create_batch(const ms_batch_desc* d, const ms_scene_desc* sc, void*
   std::memset(&b->task_robot, 0, sizeof b->task_robot);
   b->task_robot.finger_l = b->task_robot.finger_r = -1;
   b->grip = nullptr;
-  if (hipStreamCreateWithFlags(&b->cap_stream, hipStreamNonBlocking) != hipSuccess) {
+  b->cap_stream = b->bwd_stream = nullptr;
+  b->ev_fork = b->ev_join = nullptr;
+  if (hipStreamCreateWithFlags(&b->cap_stream, hipStreamNonBlocking) != hipSuccess ||
+      hipStreamCreateWithFlags(&b->bwd_stream, hipStreamNonBlocking) != hipSuccess ||
+      hipEventCreateWithFlags(&b->ev_fork, hipEventDisableTiming) != hipSuccess ||
+      hipEventCreateWithFlags(&b->ev_join, hipEventDisableTiming) != hipSuccess) {
+    release_handles(b);
     delete b;
-    return fail(MS_E_HIP, "hipStreamCreateWithFlags failed");
+    return fail(MS_E_HIP, "stream / event creation failed");
   }
   // allow the kernels the whole LDS of a workgroup
   (void)hipFuncSetAttribute(step_kernel_ptr(), hipFuncAttributeMaxDynamicSharedMemorySize, (int)b->max_lds);
@@ -276,11 +331,12 @@ ms_status ms_create_batch(const ms_batch_desc* d, const ms_scene_desc* sc, void*
   (void)hipFuncSetAttribute(step_frc_kernel_ptr(), hipFuncAttributeMaxDynamicSharedMemorySize, (int)b->max_lds);
   (void)hipFuncSetAttribute(spawn_check_kernel_ptr(), hipFuncAttributeMaxDynamicSharedMemorySize, (int)b->max_lds);
   (void)hipFuncSetAttribute(step_bwd_wave_ptr(), hipFuncAttributeMaxDynamicSharedMemorySize, (int)b->max_lds);
+  choose_bwd_split(b, b->split_c, b->split_r);
   // status starts at zero
   hipError_t e = hipMemsetAsync(b->scratch + b->sl.status, 0, sizeof(uint32_t) * c.S, stream);
   if (e == hipSuccess) e = hipStreamSynchronize(stream);
   if (e != hipSuccess) {
-    (void)hipStreamDestroy(b->cap_stream);
+    release_handles(b);
     delete b;
     return fail(MS_E_HIP, "status init: %s", hipGetErrorString(e));
   }
@@ -291,7 +347,7 @@ ms_status ms_create_batch(const ms_batch_desc* d, const ms_scene_desc* sc, void*
 ms_status ms_destroy_batch(ms_batch* b) {
   if (!b) return fail(MS_E_INVALID, "null batch");
   drop_graphs(b);
-  (void)hipStreamDestroy(b->cap_stream);
+  release_handles(b);
   delete b;
   return MS_OK;
 }
@@ -299,7 +355,7 @@ ms_status ms_destroy_batch(ms_batch* b) {
 ms_status ms_set_schedule(ms_batch* b, const ms_schedule* s) {
   if (!b || !s) return fail(MS_E_INVALID, "null argument");
   const int known = MS_SCHED_PERSISTENT | MS_SCHED_GRAPH | MS_SCHED_PER_SUBSTEP | MS_SCHED_STAGE_STATIC | MS_SCHED_CULL |
-                    MS_SCHED_BWD_REFERENCE;
+                    MS_SCHED_BWD_REFERENCE | MS_SCHED_BWD_ONE_LAUNCH;
   if (s->flags & ~known) return fail(MS_E_INVALID, "unknown schedule flags 0x%x", s->flags);
   if (s->grid < 0) return fail(MS_E_INVALID, "grid must be >= 0");
   KArgs a = make_args(b, nullptr, nullptr, nullptr);
@@ -314,6 +370,32 @@ ms_status ms_set_schedule(ms_batch* b, const ms_schedule* s) {
 ms_status ms_get_schedule(const ms_batch* b, ms_schedule* out) {
   if (!b || !out) return fail(MS_E_INVALID, "null argument");
   *out = b->sched;
+  return MS_OK;
+}
+
+ms_status ms_set_backward_split(ms_batch* b, int32_t contact_cap, int32_t robot_contact_cap) {
+  if (!b) return fail(MS_E_INVALID, "null batch");
+  if (contact_cap < 0) {
+    choose_bwd_split(b, b->split_c, b->split_r);
+    return MS_OK;
+  }
+  if (contact_cap == 0) {
+    b->split_c = b->split_r = 0;
+    return MS_OK;
+  }
+  if (contact_cap > b->desc.contact_cap || robot_contact_cap < 1 ||
+      robot_contact_cap > std::max(b->desc.robot_contact_cap, 1))
+    return fail(MS_E_INVALID, "split caps %d / %d outside [1, %d] / [1, %d]", contact_cap, robot_contact_cap,
+                b->desc.contact_cap, std::max(b->desc.robot_contact_cap, 1));
+  b->split_c = contact_cap;
+  b->split_r = robot_contact_cap;
+  return MS_OK;
+}
+
+ms_status ms_get_backward_split(const ms_batch* b, int32_t* contact_cap, int32_t* robot_contact_cap) {
+  if (!b) return fail(MS_E_INVALID, "null batch");
+  if (contact_cap) *contact_cap = b->split_c;
+  if (robot_contact_cap) *robot_contact_cap = b->split_r;
   return MS_OK;
 }
 
@@ -536,7 +618,38 @@ ms_status ms_step_backward(ms_batch* b, const void* x_in, const float* u, const 
     a.rec = rec;
     a.RL = bwd_rec(d, c);
     a.w = ww;
-    launch_step_bwd_wave(a, lds, st);
+    // scene order by the cost the record shows (overflowing scenes first)
+    const bool split = b->split_c > 0 && !(b->sched.flags & MS_SCHED_BWD_ONE_LAUNCH);
+    int* bord = reinterpret_cast<int*>(b->scratch + b->sl.bwd_order);
+    int* nover = reinterpret_cast<int*>(b->scratch + b->sl.bwd_nover);
+    launch_bwd_order(rec, a.RL, c.S, d->n_substeps, split ? b->split_c : 0, split ? b->split_r : 0, bord, nover, st);
+    HIP_TRY(hipGetLastError());
+    a.order = bord;
+    a.n_over = nover;
+    if (!split) {
+      a.fit_mode = 0;
+      launch_step_bwd_wave(a, lds, c.S, st);
+    } else {
+      // fork: the scenes that overflow the smaller layout (the costliest
+      // ones) on st in the full layout, a fixed grid looping over them; the
+      // others on the second stream at the higher occupancy, joined back
+      // onto st.  The second stream first waits 15 us so that the full-size
+      // workgroups are resident before the smaller ones fill the CUs (they
+      // would otherwise wait for two free slots on one CU).
+      BwdArgs big = a;
+      big.fit_mode = 2;
+      a.fit_mode = 1;
+      a.w = bwd_ws_wave(d, c, b->split_c, b->split_r);
+      HIP_TRY(hipEventRecord(b->ev_fork, st));
+      HIP_TRY(hipStreamWaitEvent(b->bwd_stream, b->ev_fork, 0));
+      launch_step_bwd_wave(big, lds, std::min(c.S, 2 * b->n_cu), st);
+      HIP_TRY(hipGetLastError());
+      launch_delay(1500, b->bwd_stream);
+      launch_step_bwd_wave(a, (size_t)a.w.total * sizeof(float), c.S, b->bwd_stream);
+      HIP_TRY(hipGetLastError());
+      HIP_TRY(hipEventRecord(b->ev_join, b->bwd_stream));
+      HIP_TRY(hipStreamWaitEvent(st, b->ev_join, 0));
+    }
   }
   if (actions)
     launch_actions_bwd(a.models, a.scenes, a.x, u, a.gu, gu, a.gxi, c.S, st);

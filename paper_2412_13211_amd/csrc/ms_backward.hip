@@ -86,128 +86,142 @@ __device__ __forceinline__ void row_nodes(const msa::Eng& E, int r, int& na, int
 }
 
 // Reverse of a robot contact's row updates in sweep it.  Lanes 0..15 carry the
-// robot's joints; lane 0 carries the target side and the scalars.
+// robot's joints in registers; the target side (a free body or a door /
+// drawer joint, none for furniture and planes) is carried in registers by
+// every lane alike, so the sums over the joints are the only exchanges; lane
+// 0 writes the target side and the contact's adjoints back at the end.
 __device__ void robot_contact_bar(msa::Eng& E, int it, int ci, float* L) {
   using namespace msa;
   const int lane = lane_id(), j = lane & 15;
   const bool own = lane < 16 && j < E.nb;
   const WS& w = E.w;
-  const long e = w.con + (long)ci * CR, cb = w.conb + (long)ci * CB;
-  const long lb = w.lamb + ci * 3;
+  const long e = w.con + (long)ci * CR, cb = w.conb + (long)ci * CB, lb = w.lamb + ci * 3;
+  const long rr = (long)ci * 3 * ND + j;
   const int row = E.nlim + ci;
-  float* vR = L + w.vR;
-  float* vRb = L + w.vRb;
-  const float* rJ = L + w.rJ + (long)ci * 3 * ND;
-  const float* rW = L + w.rw + (long)ci * 3 * ND;
-  float* rJb = L + w.rJb + (long)ci * 3 * ND;
-  float* rWb = L + w.rwb + (long)ci * 3 * ND;
   const float mu = E.pr.mu;
-  if (E.row_ok(ci, 1) && E.row_ok(ci, 2)) {
+  const Ids id = E.ids(e);
+  const bool tf = id.tk == 3, tx = id.tk == 2;
+  // robot side: joint j's velocity, its adjoint, the three rows' J and
+  // M~^-1 J entries and their adjoints
+  float vr = 0.f, vrb = 0.f, J[3] = {0.f, 0.f, 0.f}, Wr[3] = {0.f, 0.f, 0.f};
+  float Jb[3] = {0.f, 0.f, 0.f}, Wrb[3] = {0.f, 0.f, 0.f};
+  if (own) {
+    vr = L[w.vR + j];
+    vrb = L[w.vRb + j];
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+      J[k] = L[w.rJ + rr + k * ND];
+      Wr[k] = L[w.rw + rr + k * ND];
+    }
+  }
+  Eng::FSide B;
+  Eng::XSide X;
+  if (tf) E.fs_load(B, id.ti, -1.f);
+  if (tx) E.xs_load(X, id.ti);
+  Eng::RowAcc R;
+  R.p = E.v3(e + C_P);
+  R.d[0] = E.v3(e + C_N);
+  R.d[1] = E.v3(e + C_T1);
+  R.d[2] = E.v3(e + C_T2);
+  for (int k = 0; k < 3; ++k) R.db[k] = V{0.f, 0.f, 0.f};
+  R.pb = V{0.f, 0.f, 0.f};
+  auto t_apply = [&](int di, float dl) {
+    if (tf) Eng::fs_apply(B, R, di, dl);
+    else if (tx) Eng::xs_apply(X, R, di, dl);
+  };
+  auto t_apply_bar = [&](int di, float dl) -> float {
+    if (tf) return Eng::fs_apply_bar(B, R, di, dl);
+    if (tx) return Eng::xs_apply_bar(X, R, di, dl);
+    return 0.f;
+  };
+  auto t_rowvel = [&](int di) -> float {
+    if (tf) return Eng::fs_rowvel(B, R, di);
+    if (tx) return Eng::xs_rowvel(X, R, di);
+    return 0.f;
+  };
+  auto t_rowvel_bar = [&](int di, float rb) {
+    if (tf) Eng::fs_rowvel_bar(B, R, di, rb);
+    else if (tx) Eng::xs_rowvel_bar(X, R, di, rb);
+  };
+  const float W0 = L[e + C_W], W1 = L[e + C_W + 1], W2 = L[e + C_W + 2];
+  float lb0 = L[lb], lb1 = L[lb + 1], lb2 = L[lb + 2];
+  float Wb0 = 0.f, Wb1 = 0.f, Wb2 = 0.f, biasb = 0.f;
+  if (W1 >= 1e-12f && W2 >= 1e-12f) {
     const float y1 = E.tape_at(it, row, 1), y2 = E.tape_at(it, row, 2);
     const float lim = mu * E.normal_after(it, ci);
     float o1, o2, p1, p2;
     const bool proj = disk_proj(y1, y2, lim, o1, o2);
     E.prev_fric(it, ci, p1, p2);
     const float d1 = o1 - p1, d2 = o2 - p2;
-    if (own) {
-      float v = vR[j];
-      v += rW[2 * ND + j] * (-d2);
-      v += rW[ND + j] * (-d1);
-      vR[j] = v;
-    }
-    if (lane == 0) {
-      E.apply(ci, 2, -d2, Eng::SB);
-      E.apply(ci, 1, -d1, Eng::SB);
-    }
-    wsync();
-    float a1 = 0.f, a2 = 0.f;
-    if (own) {
-      float vb = vRb[j];
-      a1 = rW[ND + j] * vb;
-      a2 = rW[2 * ND + j] * vb;
-      rWb[ND + j] += vb * d1;
-      rWb[2 * ND + j] += vb * d2;
-    }
-    float b1 = 0.f, b2 = 0.f;
-    if (lane == 0) {
-      b1 = E.apply_bar(ci, 1, d1, Eng::SB);
-      b2 = E.apply_bar(ci, 2, d2, Eng::SB);
-    }
-    const float d1b = sum16_b(a1) + bcast0(b1), d2b = sum16_b(a2) + bcast0(b2);
+    vr += Wr[2] * (-d2);
+    vr += Wr[1] * (-d1);
+    t_apply(2, -d2);
+    t_apply(1, -d1);
+    const float a1 = own ? Wr[1] * vrb : 0.f, a2 = own ? Wr[2] * vrb : 0.f;
+    Wrb[1] += vrb * d1;
+    Wrb[2] += vrb * d2;
+    const float b1 = t_apply_bar(1, d1);
+    const float b2 = t_apply_bar(2, d2);
+    const float d1b = sum16_b(a1) + b1, d2b = sum16_b(a2) + b2;
     float yb1, yb2, limb;
-    Eng::fric_bar(y1, y2, lim, proj, L[lb + 1] + d1b, L[lb + 2] + d2b, yb1, yb2, limb);
+    Eng::fric_bar(y1, y2, lim, proj, lb1 + d1b, lb2 + d2b, yb1, yb2, limb);
     const float l1 = -d1b + yb1, l2 = -d2b + yb2;
-    const float W1 = L[e + C_W + 1], W2 = L[e + C_W + 2];
-    float c1 = 0.f, c2 = 0.f;
-    if (own) {
-      c1 = rJ[ND + j] * vR[j];
-      c2 = rJ[2 * ND + j] * vR[j];
-    }
-    float s1 = 0.f, s2 = 0.f;
-    if (lane == 0) {
-      s1 = E.rowvel(ci, 1, Eng::SB);
-      s2 = E.rowvel(ci, 2, Eng::SB);
-    }
-    const float r1 = sum16_b(c1) + bcast0(s1), r2 = sum16_b(c2) + bcast0(s2);
+    const float r1 = sum16_b(own ? J[1] * vr : 0.f) + t_rowvel(1);
+    const float r2 = sum16_b(own ? J[2] * vr : 0.f) + t_rowvel(2);
     const float rb1 = -yb1 / W1, rb2 = -yb2 / W2;
-    wsync();
-    if (lane == 0) {
-      L[lb] += mu * limb;
-      L[cb + B_W + 1] += yb1 * r1 / (W1 * W1);
-      L[cb + B_W + 2] += yb2 * r2 / (W2 * W2);
-      E.rowvel_bar(ci, 1, rb1, Eng::SB);
-      E.rowvel_bar(ci, 2, rb2, Eng::SB);
-      L[lb + 1] = l1;
-      L[lb + 2] = l2;
-    }
-    if (own) {
-      float v = vR[j];
-      rJb[ND + j] += rb1 * v;
-      rJb[2 * ND + j] += rb2 * v;
-      float vb = vRb[j];
-      vb += rb1 * rJ[ND + j];
-      vb += rb2 * rJ[2 * ND + j];
-      vRb[j] = vb;
-    }
-    wsync();
+    lb0 += mu * limb;
+    Wb1 += yb1 * r1 / (W1 * W1);
+    Wb2 += yb2 * r2 / (W2 * W2);
+    t_rowvel_bar(1, rb1);
+    t_rowvel_bar(2, rb2);
+    lb1 = l1;
+    lb2 = l2;
+    Jb[1] += rb1 * vr;
+    Jb[2] += rb2 * vr;
+    vrb += rb1 * J[1];
+    vrb += rb2 * J[2];
   }
-  if (E.row_ok(ci, 0)) {
+  if (W0 >= 1e-12f) {
     const float y = E.tape_at(it, row, 0);
     const float nl = y > 0.f ? y : 0.f;
-    const float pl = E.prev_normal(it, ci);
-    const float dl = nl - pl;
-    if (own) vR[j] += rW[j] * (-dl);
-    if (lane == 0) E.apply(ci, 0, -dl, Eng::SB);
-    wsync();
-    float a0 = 0.f;
-    if (own) {
-      float vb = vRb[j];
-      a0 = rW[j] * vb;
-      rWb[j] += vb * dl;
-    }
-    float b0 = 0.f;
-    if (lane == 0) b0 = E.apply_bar(ci, 0, dl, Eng::SB);
-    const float dlb = sum16_b(a0) + bcast0(b0);
+    const float dl = nl - E.prev_normal(it, ci);
+    vr += Wr[0] * (-dl);
+    t_apply(0, -dl);
+    const float a0 = own ? Wr[0] * vrb : 0.f;
+    Wrb[0] += vrb * dl;
+    const float dlb = sum16_b(a0) + t_apply_bar(0, dl);
     float lold, yb;
-    Eng::normal_bar(y, L[lb] + dlb, dlb, lold, yb);
-    const float W = L[e + C_W];
-    float c0 = own ? rJ[j] * vR[j] : 0.f;
-    float s0 = 0.f;
-    if (lane == 0) s0 = E.rowvel(ci, 0, Eng::SB);
-    const float r = sum16_b(c0) + bcast0(s0) + L[e + C_BIAS];
-    const float rb = -yb / W;
-    wsync();
-    if (lane == 0) {
-      L[cb + B_W] += yb * r / (W * W);
-      L[cb + B_BIAS] += rb;
-      E.rowvel_bar(ci, 0, rb, Eng::SB);
-      L[lb] = lold;
+    Eng::normal_bar(y, lb0 + dlb, dlb, lold, yb);
+    const float r = sum16_b(own ? J[0] * vr : 0.f) + t_rowvel(0) + L[e + C_BIAS];
+    const float rb = -yb / W0;
+    Wb0 += yb * r / (W0 * W0);
+    biasb += rb;
+    t_rowvel_bar(0, rb);
+    Jb[0] += rb * vr;
+    vrb += rb * J[0];
+    lb0 = lold;
+  }
+  if (own) {
+    L[w.vR + j] = vr;
+    L[w.vRb + j] = vrb;
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+      L[w.rJb + rr + k * ND] += Jb[k];
+      L[w.rwb + rr + k * ND] += Wrb[k];
     }
-    if (own) {
-      rJb[j] += rb * vR[j];
-      vRb[j] += rb * rJ[j];
-    }
-    wsync();
+  }
+  if (lane == 0) {
+    L[lb] = lb0;
+    L[lb + 1] = lb1;
+    L[lb + 2] = lb2;
+    for (int k = 0; k < 3; ++k) E.a3(cb + B_D + k * 3, R.db[k]);
+    E.a3(cb + B_P, R.pb);
+    L[cb + B_W] += Wb0;
+    L[cb + B_W + 1] += Wb1;
+    L[cb + B_W + 2] += Wb2;
+    L[cb + B_BIAS] += biasb;
+    if (tf) E.fs_store(B);
+    if (tx) E.xs_store(X);
   }
 }
 
@@ -966,11 +980,11 @@ __device__ void bwd_scene(const BwdArgs& a, int s, float* L) {
     // it and it - 1
     const float* tape_g = rec + RL.tape + (size_t)si * a.pr.K * RL.tsw;
     E.tb = Buf{L + w.tring, 1};
-    E.tsw = RL.tsw;
+    E.tsw = w.trs;
     E.tmask = 1;
     const int R3 = 3 * (E.nlim + E.nc);
     auto stage = [&](int it) {
-      float* dst = L + w.tring + (it & 1) * RL.tsw;
+      float* dst = L + w.tring + (it & 1) * w.trs;
       const float* src = tape_g + (size_t)it * RL.tsw;
       for (int i = lane; i < R3; i += 64) dst[i] = src[i];
     };
@@ -1065,17 +1079,117 @@ __device__ void bwd_scene(const BwdArgs& a, int s, float* L) {
     for (int k = 0; k < 8; ++k) a.cycles[(size_t)s * 8 + k] = cyc[k];
 }
 
+// does every substep's contact list of scene s hold at most cc contacts and
+// rc robot contacts?  cost: the sum over the substeps of contacts + 64 robot
+// contacts (the reverse sweeps take about that many contact reversals)
+__device__ bool rec_fits(const float* rec, const RecLayout& RL, int nsub, int s, int cc, int rc, int* cost = nullptr) {
+  const float* cr = rec + (size_t)s * RL.total + RL.con;
+  bool ok = true;
+  int c = 0;
+  for (int si = 0; si < nsub; ++si, cr += RL.cstride) {
+    const int NCf = __float_as_int(cr[0]), NL = __float_as_int(cr[1]), NR = __float_as_int(cr[2]);
+    ok = ok && NL >= 0 && NL <= 2 * AMAX && NCf - NL <= cc && NR <= rc;
+    c += (NCf - NL) + 64 * NR;
+  }
+  if (cost) *cost = c;
+  return ok;
+}
+
+// wave-level inclusive prefix sum
+__device__ __forceinline__ int wave_scan(int v) {
+  const int lane = threadIdx.x & 63;
+#pragma unroll
+  for (int o = 1; o < 64; o <<= 1) {
+    const int t = __shfl_up(v, o, 64);
+    if (lane >= o) v += t;
+  }
+  return v;
+}
+
 }  // namespace
+
+// the LDS layout must hold the scene's lists (else the scene is flagged and
+// left out)
+__device__ void bwd_checked(const BwdArgs& a, int s, float* lds) {
+  if (!rec_fits(a.rec, a.RL, a.pr.nsub, s, a.w.ccap, a.w.rcap)) {
+    if (lane_id() == 0) a.status[s] |= MS_ST_RECORD;
+    return;
+  }
+  bwd_scene(a, s, lds);
+}
 
 __global__ __launch_bounds__(64) void k_step_bwd_wave(BwdArgs a) {
   extern __shared__ float lds[];
-  const int slot = blockIdx.x;
-  if (slot >= a.S) return;
-  bwd_scene(a, a.order[slot], lds);
+  // mode 2 loops over the first *n_over positions; modes 0 and 1 take one
+  // position each (one call site keeps the scene's code inlined)
+  const bool loop = a.fit_mode == 2;
+  const int end = loop ? *a.n_over : a.S;
+  const int step = loop ? (int)gridDim.x : a.S;
+  for (int pos = (a.fit_mode == 1 ? *a.n_over : 0) + (int)blockIdx.x; pos < end; pos += step) {
+    bwd_checked(a, a.order[pos], lds);
+    wsync();
+  }
 }
 
-void launch_step_bwd_wave(const BwdArgs& a, size_t lds_bytes, hipStream_t st) {
-  hipLaunchKernelGGL(k_step_bwd_wave, dim3(a.S), dim3(64), lds_bytes, st, a);
+// counting sort of the scenes by (group, cost): one workgroup, keys clamped
+// to [0, NKEY); output position f = group * NKEY + (NKEY - 1 - key)
+constexpr int NKEY = 4096;
+__global__ __launch_bounds__(1024) void k_bwd_order(const float* rec, RecLayout RL, int S, int nsub, int fit_c,
+                                                    int fit_r, int* order, int* n_over) {
+  __shared__ int cnt[2 * NKEY];
+  __shared__ int wsum[16];
+  const int t = threadIdx.x;
+  for (int i = t; i < 2 * NKEY; i += 1024) cnt[i] = 0;
+  __syncthreads();
+  auto slot_of = [&](int s) {
+    int c = 0;
+    const bool fits = rec_fits(rec, RL, nsub, s, fit_c, fit_r, &c);
+    const int g = fit_c > 0 && !fits ? 0 : 1;
+    const int k = c < 0 ? 0 : (c >= NKEY ? NKEY - 1 : c);
+    return g * NKEY + (NKEY - 1 - k);
+  };
+  for (int s = t; s < S; s += 1024) atomicAdd(&cnt[slot_of(s)], 1);
+  __syncthreads();
+  // exclusive scan: thread t owns entries 8t .. 8t + 7
+  int loc[8], sum = 0;
+#pragma unroll
+  for (int i = 0; i < 8; ++i) {
+    loc[i] = cnt[8 * t + i];
+    sum += loc[i];
+  }
+  const int inc = wave_scan(sum);
+  if ((t & 63) == 63) wsum[t >> 6] = inc;
+  __syncthreads();
+  int base = inc - sum;
+  for (int wv = 0; wv < (t >> 6); ++wv) base += wsum[wv];
+  // thread NKEY / 8 owns the first entry of group 1
+  if (t == NKEY / 8) *n_over = base;
+  __syncthreads();
+#pragma unroll
+  for (int i = 0; i < 8; ++i) {
+    cnt[8 * t + i] = base;
+    base += loc[i];
+  }
+  __syncthreads();
+  for (int s = t; s < S; s += 1024) order[atomicAdd(&cnt[slot_of(s)], 1)] = s;
+}
+
+// one wavefront that waits about `ticks` of the 100 MHz wall clock (a
+// bounded wait: the clock always advances)
+__global__ __launch_bounds__(64) void k_delay(long long ticks) {
+  const long long t0 = (long long)wall_clock64();
+  while ((long long)wall_clock64() - t0 < ticks) __builtin_amdgcn_s_sleep(2);
+}
+
+void launch_delay(long long ticks, hipStream_t st) { hipLaunchKernelGGL(k_delay, dim3(1), dim3(64), 0, st, ticks); }
+
+void launch_bwd_order(const float* rec, const RecLayout& RL, int S, int nsub, int fit_c, int fit_r, int* order,
+                      int* n_over, hipStream_t st) {
+  hipLaunchKernelGGL(k_bwd_order, dim3(1), dim3(1024), 0, st, rec, RL, S, nsub, fit_c, fit_r, order, n_over);
+}
+
+void launch_step_bwd_wave(const BwdArgs& a, size_t lds_bytes, int grid, hipStream_t st) {
+  hipLaunchKernelGGL(k_step_bwd_wave, dim3(grid), dim3(64), lds_bytes, st, a);
 }
 const void* step_bwd_wave_ptr() { return reinterpret_cast<const void*>(&k_step_bwd_wave); }
 

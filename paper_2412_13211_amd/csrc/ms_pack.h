@@ -155,7 +155,7 @@ inline ParamLayout param_layout(const Counts& c) {
 }
 
 struct ScratchLayout {
-  size_t queue, status, debug, cycles, act, actb, total;
+  size_t queue, status, debug, cycles, act, actb, bwd_order, bwd_nover, total;
 };
 inline ScratchLayout scratch_layout(const Counts& c, int n_sub) {
   ScratchLayout s;
@@ -166,6 +166,8 @@ inline ScratchLayout scratch_layout(const Counts& c, int n_sub) {
   s.cycles = o; o = align256(o + sizeof(unsigned long long) * 8 * (size_t)c.S);
   s.act = o; o = align256(o + sizeof(float) * 16 * (size_t)c.S);
   s.actb = o; o = align256(o + sizeof(float) * 16 * (size_t)c.S);
+  s.bwd_order = o; o = align256(o + sizeof(int) * (size_t)c.S);
+  s.bwd_nover = o; o = align256(o + 256);
   s.total = o;
   return s;
 }

@@ -190,6 +190,49 @@ def test_backward_alias_and_determinism():
     assert np.array_equal(gu.cpu().numpy().astype(np.float64), a1[1])
 
 
+def test_split_launch_matches_one_launch():
+    """Scenes reversed in the smaller LDS layout and the others in the full
+    one, on two streams, give the single launch's result bit for bit; the
+    split caps are forced so that both launches get scenes."""
+    ms = _ms()
+    b = sg.make(2, 32)
+    x = advanced_state(b, 3)
+    u = b.controls_for(3)
+    g = np.random.default_rng(5).normal(size=x.size)
+    mb = ms.MsBatch(b, backward=True)
+    auto = mb.get_backward_split()
+    say(f"automatic split caps {auto}")
+    assert 0 < auto[0] <= b.contact_cap and 0 < auto[1] <= b.robot_contact_cap
+    # contact counts of the same step from the forward kernel's diagnostics
+    mb.enable_debug(True)
+    mb.step(torch.as_tensor(x.astype(np.float32)).cuda(), torch.as_tensor(u.astype(np.float32)).cuda())
+    dbg = mb.debug_contacts()
+    mb.enable_debug(False)
+    nmax, rmax = dbg[:, :, 0].max(axis=1).astype(int), dbg[:, :, 1].max(axis=1).astype(int)
+    cc = max(int(np.median(nmax)), 1)
+    rc = max(int(rmax.max()), 1)
+    small = (nmax <= cc) & (rmax <= rc)
+    say(f"forced caps ({cc}, {rc}): {small.sum()} scenes in the smaller layout, {(~small).sum()} in the full one")
+    assert small.any() and not small.all()
+    flags = mb.get_schedule()[0]
+    mb.set_schedule(flags | ms.MS_SCHED_BWD_ONE_LAUNCH)
+    one = gpu_vjp(mb, x, u, g)
+    mb.set_schedule(flags)
+    for caps in [(cc, rc), auto]:
+        mb.set_backward_split(*caps)
+        assert mb.get_backward_split() == caps
+        sp = gpu_vjp(mb, x, u, g)
+        assert np.array_equal(sp[0], one[0]) and np.array_equal(sp[1], one[1]), caps
+    mb.set_backward_split(0)
+    assert mb.get_backward_split() == (0, 0)
+    assert np.array_equal(gpu_vjp(mb, x, u, g)[0], one[0])
+    mb.set_backward_split(-1)
+    assert mb.get_backward_split() == auto
+    with pytest.raises(ms.MsError, match="split caps"):
+        mb.set_backward_split(b.contact_cap + 1, 1)
+    assert np.all(mb.status() == 0)
+
+
 def test_backward_without_workspace_is_an_error():
     ms = _ms()
     b = sg.make(2, 4)
