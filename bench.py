@@ -98,11 +98,14 @@ def load_traffic(name, nscenes, src_hash, flags, graph_bit):
     return d.get("bytes_per_launch")
 
 
-def time_fwd_bwd(mb, x0, U, args, flags, stream, torch):
+def time_fwd_bwd(mb, x0, U, args, flags, stream, torch, keep_records=True):
     """Forward + backward over a horizon of T control steps: T steps forward
-    keeping every state, then T vector-Jacobian products in reverse (each
-    recomputes its step's substeps).  Inputs resident in HBM; HIP events on
-    the launch stream."""
+    keeping every state, then T vector-Jacobian products in reverse.  With
+    keep_records every forward step also writes its record (substep states,
+    contact lists, Gauss-Seidel tape: T x sizes.record bytes resident in HBM)
+    and the backward reads it; without, each backward step runs its forward
+    step again to record it.  Inputs resident in HBM; HIP events on the
+    launch stream."""
     T = max(1, args.bwd_steps)
     S = mb.S
     mb.set_schedule(flags)
@@ -110,14 +113,21 @@ def time_fwd_bwd(mb, x0, U, args, flags, stream, torch):
     g0 = torch.randn_like(x0) * 1e-3
     gx = g0.clone()
     gu = torch.empty((S, 16), dtype=torch.float32, device=x0.device)
+    recs = [mb.new_record() for _ in range(T)] if keep_records else None
 
     def once():
         for t in range(T):
-            mb.step(xs[t], U[t % U.shape[0]], out=xs[t + 1])
+            if recs is not None:
+                mb.step_record(xs[t], U[t % U.shape[0]], recs[t], out=xs[t + 1])
+            else:
+                mb.step(xs[t], U[t % U.shape[0]], out=xs[t + 1])
         ev_mid.record(stream)
         gx.copy_(g0)
         for t in range(T - 1, -1, -1):
-            mb.step_backward(xs[t], U[t % U.shape[0]], gx, gx_in=gx, gu=gu)
+            if recs is not None:
+                mb.step_backward_recorded(xs[t], U[t % U.shape[0]], recs[t], gx, gx_in=gx, gu=gu)
+            else:
+                mb.step_backward(xs[t], U[t % U.shape[0]], gx, gx_in=gx, gu=gu)
 
     ev0, ev_mid, ev1 = (torch.cuda.Event(enable_timing=True) for _ in range(3))
     once()  # warm-up (graph capture for the forward)
@@ -131,9 +141,13 @@ def time_fwd_bwd(mb, x0, U, args, flags, stream, torch):
     fwd_ms = ev0.elapsed_time(ev_mid)
     bwd_ms = ev_mid.elapsed_time(ev1)
     ok = bool(torch.isfinite(gx).all().item() and torch.isfinite(gu).all().item())
-    return {"value": round(S * T / wall, 1), "unit": "env-steps/s", "horizon": T,
-            "ms_per_step": round(1e3 * wall / T, 4), "fwd_ms_per_step": round(fwd_ms / T, 4),
-            "bwd_ms_per_step": round(bwd_ms / T, 4), "finite": ok}
+    out = {"value": round(S * T / wall, 1), "unit": "env-steps/s", "horizon": T,
+           "ms_per_step": round(1e3 * wall / T, 4), "fwd_ms_per_step": round(fwd_ms / T, 4),
+           "bwd_ms_per_step": round(bwd_ms / T, 4), "finite": ok}
+    if recs is not None:
+        out["record_bytes_per_step"] = int(mb.sizes.record)
+    del recs
+    return out
 
 
 def time_env_outputs(mb, b, x0, U, args, flags, stream, torch, ms, sg):
@@ -275,6 +289,7 @@ def main():
         wall_plain, gpu_ms_plain = run(args.steps, ms.MS_SCHED_STAGE_STATIC | ms.MS_SCHED_PER_SUBSTEP |
                                        ms.MS_SCHED_CULL, True)
     fwd_bwd = None if args.no_bwd else time_fwd_bwd(mb, x0, U, args, flags, stream, torch)
+    fwd_bwd_rc = None if args.no_bwd else time_fwd_bwd(mb, x0, U, args, flags, stream, torch, keep_records=False)
     st = mb.status()
     env_out = time_env_outputs(mb, b, x0, U, args, flags, stream, torch, ms, sg)
     value = S * args.steps / wall
@@ -316,6 +331,7 @@ def main():
     }
     if fwd_bwd is not None:
         out["fwd_bwd"] = fwd_bwd
+        out["fwd_bwd_recompute"] = fwd_bwd_rc
     if env_out is not None:
         out["env_outputs"] = env_out
     if not args.no_cpu:

@@ -164,6 +164,7 @@ typedef struct {
   size_t scratch;  /* device bytes: queue counters, schedule tables, per-scene status, debug */
   size_t tape;     /* device bytes of the adjoint workspace ms_step_backward needs */
   size_t lds;      /* LDS bytes per scene workgroup (information only) */
+  size_t record;   /* device bytes of one control step's record (ms_step_record) */
 } ms_sizes;
 
 typedef struct {
@@ -240,6 +241,27 @@ ms_status ms_step(ms_batch* b, const void* state_in_dev, const float* controls_d
 ms_status ms_step_backward(ms_batch* b, const void* state_in_dev, const float* controls_dev,
                            const void* grad_state_out_dev, void* grad_state_in_dev, float* grad_controls_dev,
                            void* hip_stream);
+
+/* ms_step that also writes the step's record into record_dev (caller-owned
+ * device memory of ms_query_sizes().record bytes, float-aligned): the state
+ * at every substep start and at the end, each substep's contact list and the
+ * pre-projection value of every Gauss-Seidel row update -- what the adjoint
+ * of Sec. 3's step T needs, so that ms_step_backward_recorded need not run
+ * the step again.  state_out_dev is the same, bit for bit, as ms_step's (it
+ * may alias state_in_dev; record_dev may not alias either).  Runs the
+ * step's fused launch whatever the schedule (no graph, no per-substep
+ * launches).  Stream-ordered. */
+ms_status ms_step_record(ms_batch* b, const void* state_in_dev, const float* controls_dev, void* state_out_dev,
+                         void* record_dev, void* hip_stream);
+
+/* ms_step_backward from the record ms_step_record wrote for the same
+ * (state_in, controls): the same results bit for bit, without running the
+ * step again and without the tape buffer (unless MS_SCHED_BWD_REFERENCE is
+ * set: then the record is not read and the tape buffer is needed).  The
+ * record is only read. */
+ms_status ms_step_backward_recorded(ms_batch* b, const void* state_in_dev, const float* controls_dev,
+                                    const void* record_dev, const void* grad_state_out_dev, void* grad_state_in_dev,
+                                    float* grad_controls_dev, void* hip_stream);
 
 /* Typed device views into a state buffer (no copy, no device work). */
 ms_status ms_get_state(const ms_batch* b, const void* state_dev, ms_state_view* out);

@@ -27,7 +27,8 @@ MS_SCHED_BWD_ONE_LAUNCH = 64
 MS_ST_NONFINITE, MS_ST_OVERFLOW, MS_ST_DEGENERATE, MS_ST_ROBOT_OVERFLOW = 1, 2, 4, 8
 
 EXPORTS = ["ms_query_sizes", "ms_state_floats", "ms_create_batch", "ms_destroy_batch", "ms_set_schedule",
-           "ms_get_schedule", "ms_set_backward_split", "ms_get_backward_split", "ms_autotune", "ms_step", "ms_step_backward", "ms_get_state", "ms_set_state",
+           "ms_get_schedule", "ms_set_backward_split", "ms_get_backward_split", "ms_autotune", "ms_step", "ms_step_backward",
+           "ms_step_record", "ms_step_backward_recorded", "ms_get_state", "ms_set_state",
            "ms_scene_status", "ms_set_force_outputs", "ms_reset_robots", "ms_spawn_check", "ms_enable_debug",
            "ms_debug_contacts", "ms_enable_phase_profile", "ms_phase_cycles", "ms_set_task_robot",
            "ms_set_grip_outputs", "ms_task_begin", "ms_task_update", "ms_task_categorize", "ms_last_error"]
@@ -59,7 +60,7 @@ class SceneDesc(C.Structure):
 
 class Sizes(C.Structure):
     _fields_ = [("params", C.c_size_t), ("state", C.c_size_t), ("scratch", C.c_size_t), ("tape", C.c_size_t),
-                ("lds", C.c_size_t)]
+                ("lds", C.c_size_t), ("record", C.c_size_t)]
 
 
 class StateView(C.Structure):
@@ -117,6 +118,8 @@ def lib():
             "ms_autotune": [vp, vp, vp, vp, i32, vp, vp, vp],
             "ms_step": [vp, vp, vp, vp, vp],
             "ms_step_backward": [vp, vp, vp, vp, vp, vp, vp],
+            "ms_step_record": [vp, vp, vp, vp, vp, vp],
+            "ms_step_backward_recorded": [vp, vp, vp, vp, vp, vp, vp, vp],
             "ms_get_state": [vp, vp, vp],
             "ms_set_state": [vp, vp, vp, vp, vp],
             "ms_scene_status": [vp, vp],
@@ -284,6 +287,44 @@ class MsBatch:
         _check(lib().ms_step_backward(self.h, _ptr_t(x), _ptr_t(u), _ptr_t(gx_out), _ptr_t(gx_in), _ptr_t(gu),
                                       _stream(stream)), "ms_step_backward")
         return gx_in, gu
+
+    def new_record(self):
+        """Device buffer for one control step's record (``step_record``)."""
+        return self.torch.empty(max(self.sizes.record, 4) // 4, dtype=self.torch.float32, device=self.device)
+
+    def step_record(self, x, u, rec, out=None, stream=None):
+        """``step`` that also writes the step's record into ``rec`` (from
+        ``new_record``) for ``step_backward_recorded``."""
+        self._check_state(x, "state_in")
+        self._check_controls(u)
+        self._check_record(rec)
+        if out is None:
+            out = self.torch.empty_like(x)
+        self._check_state(out, "state_out")
+        _check(lib().ms_step_record(self.h, _ptr_t(x), _ptr_t(u), _ptr_t(out), _ptr_t(rec), _stream(stream)),
+               "ms_step_record")
+        return out
+
+    def step_backward_recorded(self, x, u, rec, gx_out, gx_in=None, gu=None, stream=None):
+        """``step_backward`` from the record ``step_record`` wrote for the
+        same (x, u): the step is not run again."""
+        self._check_state(x, "state_in")
+        self._check_controls(u)
+        self._check_record(rec)
+        self._check_state(gx_out, "grad_state_out")
+        if gx_in is None:
+            gx_in = self.torch.empty_like(x)
+        if gu is None:
+            gu = self.torch.empty_like(u)
+        _check(lib().ms_step_backward_recorded(self.h, _ptr_t(x), _ptr_t(u), _ptr_t(rec), _ptr_t(gx_out),
+                                               _ptr_t(gx_in), _ptr_t(gu), _stream(stream)),
+               "ms_step_backward_recorded")
+        return gx_in, gu
+
+    def _check_record(self, rec):
+        if not (rec.is_cuda and rec.dtype == self.torch.float32 and rec.is_contiguous()
+                and rec.numel() * 4 >= self.sizes.record):
+            raise MsError(f"record must be a contiguous float32 device tensor of at least {self.sizes.record} bytes")
 
     def enable_forces(self, on=True):
         """Contact-force outputs written by every following ``step``: returns

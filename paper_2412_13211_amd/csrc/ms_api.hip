@@ -263,6 +263,7 @@ ms_status ms_query_sizes(const ms_batch_desc* d, const ms_scene_desc* sc, ms_siz
   out->scratch = scratch_layout(c, d->n_substeps).total;
   out->tape = bwd_bytes(d, c);
   out->lds = (size_t)lds_for(d, c, true).total * sizeof(float);
+  out->record = (size_t)bwd_rec(d, c).total * (size_t)c.S * sizeof(float);
   return MS_OK;
 }
 
@@ -438,8 +439,9 @@ ms_status ms_step(ms_batch* b, const void* x_in, const float* u, void* x_out, vo
 
 // The forward kernel in record mode: one fused launch per control step (the
 // batch's persistent / staging / culling choices), no state output.
-ms_status enqueue_record(ms_batch* b, const void* x_in, const float* u, float* rec, hipStream_t st) {
-  KArgs a = make_args(b, x_in, u, nullptr);
+ms_status enqueue_record(ms_batch* b, const void* x_in, const float* u, float* rec, hipStream_t st,
+                         void* x_out = nullptr) {
+  KArgs a = make_args(b, x_in, u, x_out);
   a.mode = step_mode(b);
   a.debug = nullptr;
   a.phase_cycles = nullptr;
@@ -573,11 +575,22 @@ ms_status ms_task_categorize(ms_batch* b, const ms_task* tasks, const ms_episode
   return MS_OK;
 }
 
-ms_status ms_step_backward(ms_batch* b, const void* x_in, const float* u, const void* gx_out, void* gx_in,
-                           float* gu, void* hip_stream) {
+ms_status ms_step_record(ms_batch* b, const void* x_in, const float* u, void* x_out, void* record, void* hip_stream) {
+  if (!b) return fail(MS_E_INVALID, "null batch");
+  if (!x_in || !u || !x_out || !record) return fail(MS_E_INVALID, "ms_step_record: null buffer");
+  if (reinterpret_cast<uintptr_t>(record) % sizeof(float)) return fail(MS_E_INVALID, "ms_step_record: misaligned record");
+  hipStream_t st = static_cast<hipStream_t>(hip_stream);
+  const float* ut = control_targets(b, x_in, u, st);
+  HIP_TRY(hipGetLastError());
+  return enqueue_record(b, x_in, ut, static_cast<float*>(record), st, x_out);
+}
+
+static ms_status step_backward_impl(ms_batch* b, const void* x_in, const float* u, const float* given_rec,
+                             const void* gx_out, void* gx_in, float* gu, void* hip_stream) {
   if (!b) return fail(MS_E_INVALID, "null batch");
   if (!x_in || !u || !gx_out || !gx_in || !gu) return fail(MS_E_INVALID, "ms_step_backward: null buffer");
-  if (!b->tape) return fail(MS_E_STATE, "ms_step_backward: the batch was created without a tape buffer");
+  if (!b->tape && (!given_rec || (b->sched.flags & MS_SCHED_BWD_REFERENCE)))
+    return fail(MS_E_STATE, "ms_step_backward: the batch was created without a tape buffer");
   const Counts& c = b->cnt;
   const ms_batch_desc* d = &b->desc;
   BwdArgs a;
@@ -612,9 +625,13 @@ ms_status ms_step_backward(ms_batch* b, const void* x_in, const float* u, const 
     a.w = bwd_ws(d, c);
     launch_step_bwd(a, st);
   } else {
-    float* rec = reinterpret_cast<float*>(b->tape);
-    ms_status rs = enqueue_record(b, x_in, ut, rec, st);
-    if (rs != MS_OK) return rs;
+    const float* rec = given_rec;
+    if (!rec) {
+      float* tr = reinterpret_cast<float*>(b->tape);
+      ms_status rs = enqueue_record(b, x_in, ut, tr, st);
+      if (rs != MS_OK) return rs;
+      rec = tr;
+    }
     a.rec = rec;
     a.RL = bwd_rec(d, c);
     a.w = ww;
@@ -655,6 +672,19 @@ ms_status ms_step_backward(ms_batch* b, const void* x_in, const float* u, const 
     launch_actions_bwd(a.models, a.scenes, a.x, u, a.gu, gu, a.gxi, c.S, st);
   HIP_TRY(hipGetLastError());
   return MS_OK;
+}
+
+ms_status ms_step_backward(ms_batch* b, const void* x_in, const float* u, const void* gx_out, void* gx_in, float* gu,
+                           void* hip_stream) {
+  return step_backward_impl(b, x_in, u, nullptr, gx_out, gx_in, gu, hip_stream);
+}
+
+ms_status ms_step_backward_recorded(ms_batch* b, const void* x_in, const float* u, const void* record,
+                                    const void* gx_out, void* gx_in, float* gu, void* hip_stream) {
+  if (!record) return fail(MS_E_INVALID, "ms_step_backward_recorded: null record");
+  if (reinterpret_cast<uintptr_t>(record) % sizeof(float))
+    return fail(MS_E_INVALID, "ms_step_backward_recorded: misaligned record");
+  return step_backward_impl(b, x_in, u, static_cast<const float*>(record), gx_out, gx_in, gu, hip_stream);
 }
 
 ms_status ms_get_state(const ms_batch* b, const void* x, ms_state_view* out) {

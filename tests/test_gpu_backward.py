@@ -233,6 +233,41 @@ def test_split_launch_matches_one_launch():
     assert np.all(mb.status() == 0)
 
 
+@pytest.mark.parametrize("cfg,n", [(2, 16), (5, 8)])
+def test_recorded_step_and_backward_match(cfg, n):
+    """ms_step_record gives ms_step's state bit for bit and a record from
+    which ms_step_backward_recorded gives ms_step_backward's results bit for
+    bit (also when the record is reused after other steps ran)."""
+    ms = _ms()
+    b = sg.make(cfg, n)
+    x = advanced_state(b, 2)
+    u = b.controls_for(2)
+    g = np.random.default_rng(17).normal(size=x.size)
+    mb = ms.MsBatch(b, backward=True)
+    xt = torch.as_tensor(x.astype(np.float32)).cuda()
+    ut = torch.as_tensor(np.asarray(u, np.float32)).cuda().contiguous()
+    gt = torch.as_tensor(g.astype(np.float32)).cuda()
+    rec = mb.new_record()
+    assert rec.numel() * 4 >= mb.sizes.record > 0
+    y_ref = mb.step(xt, ut)
+    y_rec = mb.step_record(xt, ut, rec)
+    torch.cuda.synchronize()
+    assert torch.equal(y_ref, y_rec)
+    gx_ref, gu_ref = mb.step_backward(xt, ut, gt)
+    mb.step(y_ref, ut)                      # other work between the record and its use
+    gx_rec, gu_rec = mb.step_backward_recorded(xt, ut, rec, gt)
+    torch.cuda.synchronize()
+    assert torch.equal(gx_ref, gx_rec) and torch.equal(gu_ref, gu_rec)
+    # in place on the state: out aliases x
+    x2 = xt.clone()
+    mb.step_record(x2, ut, rec, out=x2)
+    torch.cuda.synchronize()
+    assert torch.equal(x2, y_ref)
+    with pytest.raises(ms.MsError, match="record"):
+        mb.step_record(xt, ut, rec[:8])
+    assert not np.any(mb.status() & 16)     # record and recomputation agree
+
+
 def test_backward_without_workspace_is_an_error():
     ms = _ms()
     b = sg.make(2, 4)
