@@ -88,6 +88,9 @@ enum {
   MS_SCHED_CULL = 16,         /* bounding-sphere pre-test before sphere-pair tests */
   MS_SCHED_BWD_REFERENCE = 32, /* ms_step_backward on the lane-per-scene kernel that
                                   recomputes everything itself (slow; a cross-check) */
+  MS_SCHED_STATIC_ORDER = 128,  /* process the scenes in the order fixed at creation
+                                   (by static size) instead of by decreasing cost as the
+                                   previous step measured it (contacts, robot contacts) */
   MS_SCHED_BWD_ONE_LAUNCH = 64  /* ms_step_backward in one wavefront launch sized for the
                                   contact caps.  Without it the scenes whose contact
                                   lists fit a smaller LDS layout (more workgroups per

@@ -24,6 +24,7 @@ MS_SCHED_STAGE_STATIC = 8
 MS_SCHED_CULL = 16
 MS_SCHED_BWD_REFERENCE = 32
 MS_SCHED_BWD_ONE_LAUNCH = 64
+MS_SCHED_STATIC_ORDER = 128
 MS_ST_NONFINITE, MS_ST_OVERFLOW, MS_ST_DEGENERATE, MS_ST_ROBOT_OVERFLOW = 1, 2, 4, 8
 
 EXPORTS = ["ms_query_sizes", "ms_state_floats", "ms_create_batch", "ms_destroy_batch", "ms_set_schedule",

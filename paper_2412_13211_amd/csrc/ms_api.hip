@@ -149,6 +149,19 @@ const float* control_targets(ms_batch* b, const void* x_in, const float* u, hipS
 int step_mode(const ms_batch* b) { return b->desc.control_mode == MS_CTRL_ACTIONS ? MS_CTRL_PD : b->desc.control_mode; }
 
 // Enqueue one control step with the current schedule (no graph).
+// the order of a step's scenes: by the cost keys the previous step wrote
+// (a counting sort that also zeroes the work counter), or the static one
+void set_step_order(ms_batch* b, KArgs& a, hipStream_t st) {
+  a.cost = reinterpret_cast<int*>(b->scratch + b->sl.fwd_cost);
+  if (b->sched.flags & MS_SCHED_STATIC_ORDER) {
+    if (a.persistent) launch_reset_queue(a.queue, st);
+    return;
+  }
+  int* ord = reinterpret_cast<int*>(b->scratch + b->sl.fwd_order);
+  launch_cost_order(a.cost, b->cnt.S, ord, a.persistent ? a.queue : nullptr, st);
+  a.order = ord;
+}
+
 ms_status enqueue_step(ms_batch* b, const void* x_in, const float* u, void* x_out, hipStream_t st) {
   u = control_targets(b, x_in, u, st);
   HIP_TRY(hipGetLastError());
@@ -160,6 +173,8 @@ ms_status enqueue_step(ms_batch* b, const void* x_in, const float* u, void* x_ou
                 "or robot_contact_cap or disable furniture staging", lds, b->max_lds);
   const bool per_sub = (b->sched.flags & MS_SCHED_PER_SUBSTEP) != 0;
   const int launches = per_sub ? b->desc.n_substeps : 1;
+  set_step_order(b, a, st);
+  HIP_TRY(hipGetLastError());
   for (int k = 0; k < launches; ++k) {
     KArgs ak = a;
     if (per_sub) {
@@ -169,7 +184,7 @@ ms_status enqueue_step(ms_batch* b, const void* x_in, const float* u, void* x_ou
     }
     int grid = b->cnt.S;
     if (ak.persistent) {
-      launch_reset_queue(ak.queue, st);
+      if (k > 0) launch_reset_queue(ak.queue, st);
       grid = persistent_grid(b, lds);
     }
     launch_step(ak, grid, lds, st);
@@ -333,8 +348,16 @@ ms_status ms_create_batch(const ms_batch_desc* d, const ms_scene_desc* sc, void*
   (void)hipFuncSetAttribute(spawn_check_kernel_ptr(), hipFuncAttributeMaxDynamicSharedMemorySize, (int)b->max_lds);
   (void)hipFuncSetAttribute(step_bwd_wave_ptr(), hipFuncAttributeMaxDynamicSharedMemorySize, (int)b->max_lds);
   choose_bwd_split(b, b->split_c, b->split_r);
-  // status starts at zero
+  // status starts at zero; the first step's cost keys follow the static
+  // order (decreasing keys along it)
+  std::vector<int> cost0(c.S);
+  {
+    const int* ord = reinterpret_cast<const int*>(host.data() + pl.order);
+    for (int p = 0; p < c.S; ++p) cost0[ord[p]] = 2 * (int)((4095LL * (c.S - 1 - p)) / std::max(c.S - 1, 1));
+  }
   hipError_t e = hipMemsetAsync(b->scratch + b->sl.status, 0, sizeof(uint32_t) * c.S, stream);
+  if (e == hipSuccess)
+    e = hipMemcpyAsync(b->scratch + b->sl.fwd_cost, cost0.data(), sizeof(int) * c.S, hipMemcpyHostToDevice, stream);
   if (e == hipSuccess) e = hipStreamSynchronize(stream);
   if (e != hipSuccess) {
     release_handles(b);
@@ -356,7 +379,7 @@ ms_status ms_destroy_batch(ms_batch* b) {
 ms_status ms_set_schedule(ms_batch* b, const ms_schedule* s) {
   if (!b || !s) return fail(MS_E_INVALID, "null argument");
   const int known = MS_SCHED_PERSISTENT | MS_SCHED_GRAPH | MS_SCHED_PER_SUBSTEP | MS_SCHED_STAGE_STATIC | MS_SCHED_CULL |
-                    MS_SCHED_BWD_REFERENCE | MS_SCHED_BWD_ONE_LAUNCH;
+                    MS_SCHED_BWD_REFERENCE | MS_SCHED_BWD_ONE_LAUNCH | MS_SCHED_STATIC_ORDER;
   if (s->flags & ~known) return fail(MS_E_INVALID, "unknown schedule flags 0x%x", s->flags);
   if (s->grid < 0) return fail(MS_E_INVALID, "grid must be >= 0");
   KArgs a = make_args(b, nullptr, nullptr, nullptr);
@@ -452,11 +475,9 @@ ms_status enqueue_record(ms_batch* b, const void* x_in, const float* u, float* r
   a.RL = bwd_rec(&b->desc, b->cnt);
   size_t lds = lds_bytes_of(a);
   if (lds > b->max_lds) return fail(MS_E_UNSUPPORTED, "scene working set needs %zu B of LDS", lds);
-  int grid = b->cnt.S;
-  if (a.persistent) {
-    launch_reset_queue(a.queue, st);
-    grid = persistent_grid(b, lds);
-  }
+  set_step_order(b, a, st);
+  HIP_TRY(hipGetLastError());
+  const int grid = a.persistent ? persistent_grid(b, lds) : b->cnt.S;
   launch_step(a, grid, lds, st);
   HIP_TRY(hipGetLastError());
   return MS_OK;

@@ -154,6 +154,7 @@ struct KArgs {
   uint32_t* debug;         // [S][n_sub][4] or null
   unsigned long long* phase_cycles;  // [S][8] shader-clock cycles per phase, or null
   int* queue;              // work counter (persistent schedule)
+  int* cost;               // [S] cost keys the step writes for the next step's order, or null
   int S, NF, NA;
   int n_sub, sub0, n_sub_total;  // substeps in this launch, index of the first, substeps per control step
   int K, mode, ccap, rcap;
@@ -172,6 +173,9 @@ struct KArgs {
 
 void launch_step(const KArgs& a, int grid, size_t lds_bytes, hipStream_t st);
 void launch_reset_queue(int* q, hipStream_t st);
+// order = the scenes by decreasing cost key (cost >> 1, clamped to [0, 4095]);
+// also zeroes the work counter q when q is non-null
+void launch_cost_order(const int* cost, int S, int* order, int* q, hipStream_t st);
 void launch_actions(const DModel* models, const DScene* scenes, const float* x, const float* a, float* tgt, int S,
                     hipStream_t st);
 void launch_actions_bwd(const DModel* models, const DScene* scenes, const float* x, const float* a,

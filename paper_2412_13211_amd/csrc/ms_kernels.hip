@@ -1759,6 +1759,10 @@ __device__ __forceinline__ void run_scene(const KArgs& a, int s, float* L) {
     wave_sync();
   }
   float* rec = REC ? a.rec + (size_t)s * a.RL.total : nullptr;
+  // cost key for the next step's order: the time of a scene grows about
+  // linearly with its contacts, its robot contacts (each some 50 others)
+  // and its free bodies (each some 30)
+  int cost_acc = 30 * S.nf;
   for (int k = 0; k < a.n_sub; ++k) {
     int NC, NR, NL;
     uint64_t keysum = 0;
@@ -1770,6 +1774,7 @@ __device__ __forceinline__ void run_scene(const KArgs& a, int s, float* L) {
     MS_PHASE(0)
     phase_contacts(a, S, L, rb, NC, NR, NL, status, keysum);
     if (rec) rec_contacts(a, L, NC, NL, NR, rec + a.RL.con + ks * a.RL.cstride);
+    cost_acc += (NC - NL) + 50 * NR;
     MS_PHASE(1)
     phase_dynamics(a, S, L, rb, vR);
     MS_PHASE(2)
@@ -1821,6 +1826,7 @@ __device__ __forceinline__ void run_scene(const KArgs& a, int s, float* L) {
   if (lane == 0) {
     if (a.sub0 == 0) a.status[s] = status;
     else a.status[s] |= status;
+    if (a.cost) a.cost[s] = a.sub0 == 0 ? cost_acc : a.cost[s] + cost_acc - 30 * S.nf;
     if (prof) {
       for (int k = 0; k < 8; ++k) {
         if (a.sub0 == 0) a.phase_cycles[(size_t)s * 8 + k] = cyc[k];
@@ -2031,6 +2037,55 @@ void launch_step(const KArgs& a, int grid, size_t lds_bytes, hipStream_t st) {
   else hipLaunchKernelGGL(k_step, dim3(grid), dim3(WAVE), lds_bytes, st, a);
 }
 void launch_reset_queue(int* q, hipStream_t st) { hipLaunchKernelGGL(k_reset_queue, dim3(1), dim3(64), 0, st, q); }
+
+// counting sort of the scenes by decreasing cost key: one workgroup of 1024
+// lanes, a histogram over the 4096 keys in LDS, its exclusive prefix sum
+// (four entries per lane, then across the lanes), then a scatter
+constexpr int NKEY = 4096;
+__global__ __launch_bounds__(1024) void k_cost_order(const int* cost, int S, int* order, int* q) {
+  __shared__ int cnt[NKEY];
+  __shared__ int wsum[16];
+  const int t = threadIdx.x;
+  if (q && t == 0) q[0] = 0;
+  for (int i = t; i < NKEY; i += 1024) cnt[i] = 0;
+  __syncthreads();
+  auto slot_of = [&](int s) {
+    int k = cost[s] >> 1;
+    k = k < 0 ? 0 : (k >= NKEY ? NKEY - 1 : k);
+    return NKEY - 1 - k;
+  };
+  for (int s = t; s < S; s += 1024) atomicAdd(&cnt[slot_of(s)], 1);
+  __syncthreads();
+  int loc[4], sum = 0;
+#pragma unroll
+  for (int i = 0; i < 4; ++i) {
+    loc[i] = cnt[4 * t + i];
+    sum += loc[i];
+  }
+  int inc = sum;
+  const int lane = t & 63;
+#pragma unroll
+  for (int o = 1; o < 64; o <<= 1) {
+    const int v = __shfl_up(inc, o, 64);
+    if (lane >= o) inc += v;
+  }
+  if (lane == 63) wsum[t >> 6] = inc;
+  __syncthreads();
+  int base = inc - sum;
+  for (int w = 0; w < (t >> 6); ++w) base += wsum[w];
+  __syncthreads();
+#pragma unroll
+  for (int i = 0; i < 4; ++i) {
+    cnt[4 * t + i] = base;
+    base += loc[i];
+  }
+  __syncthreads();
+  for (int s = t; s < S; s += 1024) order[atomicAdd(&cnt[slot_of(s)], 1)] = s;
+}
+
+void launch_cost_order(const int* cost, int S, int* order, int* q, hipStream_t st) {
+  hipLaunchKernelGGL(k_cost_order, dim3(1), dim3(1024), 0, st, cost, S, order, q);
+}
 void launch_actions(const DModel* models, const DScene* scenes, const float* x, const float* a, float* tgt, int S,
                     hipStream_t st) {
   if (S <= 0) return;

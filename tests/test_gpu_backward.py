@@ -325,18 +325,27 @@ def test_rollout_gradient_checkpointed():
     mb = ms.MsBatch(b, backward=True)
     x0t = torch.as_tensor(x0.astype(np.float32)).cuda()
     Ut = torch.as_tensor(U).cuda().requires_grad_(True)
-    xT = rollout(mb, x0t, Ut, every=every)
-    fr = xT[32 * S: 32 * S + 16 * b.n_free].view(b.n_free, 16)
     start = x0t[32 * S: 32 * S + 16 * b.n_free].view(b.n_free, 16)
     goal_t = torch.as_tensor(goal, dtype=torch.float32, device="cuda")
     bi = torch.as_tensor(box, device="cuda")
     qg = torch.as_tensor(qgoal, dtype=torch.float32, device="cuda")
-    loss = ((fr[bi, 0:3] - (start[bi, 0:3] + goal_t)) ** 2).sum() + \
-        ((xT[:16 * S].view(S, 16) - (x0t[:16 * S].view(S, 16) + qg)) ** 2).sum()
-    loss.backward()
+
+    def loss_of(xT):
+        fr = xT[32 * S: 32 * S + 16 * b.n_free].view(b.n_free, 16)
+        return ((fr[bi, 0:3] - (start[bi, 0:3] + goal_t)) ** 2).sum() + \
+            ((xT[:16 * S].view(S, 16) - (x0t[:16 * S].view(S, 16) + qg)) ** 2).sum()
+
+    xT = rollout(mb, x0t, Ut, every=every)
+    loss_of(xT).backward()
     mine = Ut.grad.cpu().numpy().astype(np.float64)
     share = stable.mean()
     err = np.linalg.norm((mine - ref)[stable]) / np.linalg.norm(ref)
     say(f"rollout T={T} every={every}: smooth share {share:.3f} rel err {err:.2e}")
     assert share >= 0.5
     assert err <= GRAD_TOL
+    # keeping every step's record instead of checkpoints: the same, bit for bit
+    Ut2 = torch.as_tensor(U).cuda().requires_grad_(True)
+    xT2 = rollout(mb, x0t, Ut2, records=True)
+    assert torch.equal(xT2.detach(), xT.detach())
+    loss_of(xT2).backward()
+    assert torch.equal(Ut2.grad, Ut.grad)
