@@ -179,8 +179,8 @@ struct WS {
   int fmax, ntmax, ccap, rcap, K, nsub, ss;
   int st, gA, gB, ub, tape;
   int kR, kp, ka, ko, kc, kIcw, ks, kI, kIc, sph, tl;
-  int fR, fIw, fIi;
-  int xR, xbc, xa, xo, xM, xC;
+  int fR, fIw, fIi, fim;  // fim: inverse masses of the free bodies
+  int xR, xbc, xa, xo, xM, xC, xty;  // xty: door / drawer joint kinds (0 revolute, 1 prismatic)
   int tau, arm, L, z, rv, ra, rfl, rff;
   int vR, vA, vF, lam, llam, con, lim, rJ, rw;
   int vRb, vAb, vFb, lamb, llamb, limb, conb, rJb, rwb, fb, xb;
@@ -218,9 +218,9 @@ MSA_HD inline WS ws_layout(int fmax, int ntmax, int ccap, int rcap, int K, int n
   w.kIcw = take(ND * 6); w.ks = take(ND * 6); w.kI = take(ND * 36); w.kIc = take(ND * 36);
   w.sph = take(wave ? 0 : SPH * 3);  // sphere centres: only the lane kernel's contact search reads them
   w.tl = take(wave ? 0 : (ND + 1) * (w.ntmax + 1));
-  w.fR = take(fm * 9); w.fIw = take(fm * 9); w.fIi = take(fm * 9);
+  w.fR = take(fm * 9); w.fIw = take(fm * 9); w.fIi = take(fm * 9); w.fim = take(fm);
   w.xR = take(AMAX * 9); w.xbc = take(AMAX * 3); w.xa = take(AMAX * 3); w.xo = take(AMAX * 3);
-  w.xM = take(AMAX); w.xC = take(AMAX);
+  w.xM = take(AMAX); w.xC = take(AMAX); w.xty = take(AMAX);
   w.tau = take(ND); w.arm = take(ND); w.L = take(ND * ND); w.z = take(ND);
   w.rv = take(ND * 6); w.ra = take(ND * 6); w.rfl = take(ND * 6); w.rff = take(ND * 6);
   w.vR = take(ND); w.vA = take(AMAX); w.vF = take(fm * 6);
@@ -565,6 +565,7 @@ struct Eng {
       }
       at(w.xM + x) = Mx;
       at(w.xC + x) = Cx;
+      at(w.xty + x) = (float)A.type;
     }
   }
 
@@ -585,6 +586,7 @@ struct Eng {
           Ii[r * 3 + c] = R[r * 3] * (1.f / F.Ib[0]) * R[c * 3] + R[r * 3 + 1] * (1.f / F.Ib[1]) * R[c * 3 + 1] +
                           R[r * 3 + 2] * (1.f / F.Ib[2]) * R[c * 3 + 2];
         }
+      at(w.fim + f) = 1.f / F.mass;
       for (int t = 0; t < 9; ++t) {
         at(w.fR + f * 9 + t) = R[t];
         at(w.fIw + f * 9 + t) = Iw[t];
@@ -929,7 +931,7 @@ struct Eng {
   }
   MSA_HD float aux_J(int x, V d, V p, float sgn) const {
     V a = v3(w.xa + x * 3);
-    return sgn * (sc.A[x].type == 0 ? dot(d, cross(a, p - v3(w.xo + x * 3))) : dot(d, a));
+    return sgn * (at(w.xty + x) == 0.f ? dot(d, cross(a, p - v3(w.xo + x * 3))) : dot(d, a));
   }
   MSA_HD void rows() {
     const DModel& M = *sc.M;
@@ -1008,7 +1010,7 @@ struct Eng {
     free_side(f, d, p, sgn, lin, ang);
     float Ii[9];
     ld9(w.fIi + f * 9, Ii);
-    V ilin = lin * (1.f / sc.F[f].mass);
+    V ilin = lin * at(w.fim + f);
     V iang = rmv(Ii, ang);
     return dot(lin, ilin) + dot(ang, iang);
   }
@@ -1046,7 +1048,7 @@ struct Eng {
   MSA_HD void free_apply(int f, V lin, V ang, float dl) const {
     float Ii[9];
     ld9(w.fIi + f * 9, Ii);
-    a3(w.vF + f * 6, lin * (1.f / sc.F[f].mass) * dl);
+    a3(w.vF + f * 6, lin * at(w.fim + f) * dl);
     a3(w.vF + f * 6 + 3, rmv(Ii, ang) * dl);
   }
   MSA_HD void apply(int ci, int di, float dl, int sides = SAB) const {
@@ -1300,7 +1302,7 @@ struct Eng {
   // contact-point adjoints (the joint axis and origin do not move)
   MSA_HD void aux_J_bar(long e, long cb, int di, int ti, float Jb) const {
     V d = dir(e, di), a = v3(w.xa + ti * 3);
-    if (sc.A[ti].type == 0) {
+    if (at(w.xty + ti) == 0.f) {
       V ev = v3(e + C_P) - v3(w.xo + ti * 3);
       a3(cb + B_D + di * 3, -(cross(a, ev) * Jb));
       a3(cb + B_P, -(cross(d, a) * Jb));
@@ -1351,7 +1353,7 @@ struct Eng {
     free_side(f, d, p, sgn, lin, ang);
     float Ii[9];
     ld9(w.fIi + f * 9, Ii);
-    float im = 1.f / sc.F[f].mass;
+    float im = at(w.fim + f);
     V vb = v3(w.vFb + f * 6), wb = v3(w.vFb + f * 6 + 3);
     float dlb = dot(lin * im, vb) + dot(rmv(Ii, ang), wb);
     V iab = wb * dl;
@@ -1451,7 +1453,7 @@ struct Eng {
   MSA_HD void fs_load(FSide& S, int f, float sgn) const {
     S.f = f;
     S.sgn = sgn;
-    S.im = 1.f / sc.F[f].mass;
+    S.im = at(w.fim + f);
     S.x = v3(cur_s + fro(f));
     ld9(w.fIi + f * 9, S.Ii);
     S.v = v3(w.vF + f * 6);
@@ -1525,7 +1527,7 @@ struct Eng {
   };
   MSA_HD void xs_load(XSide& X, int x) const {
     X.x = x;
-    X.type = sc.A[x].type;
+    X.type = (int)at(w.xty + x);
     X.a = v3(w.xa + x * 3);
     X.o = v3(w.xo + x * 3);
     X.M = at(w.xM + x);
@@ -1739,7 +1741,7 @@ struct Eng {
     free_side(f, d, p, sgn, lin, ang);
     float Ii[9];
     ld9(w.fIi + f * 9, Ii);
-    float im = 1.f / sc.F[f].mass;
+    float im = at(w.fim + f);
     V linb = lin * (2.f * Wb * im);
     V angb = (rmv(Ii, ang) + rtmv(Ii, ang)) * Wb;
     long ib = w.fb + f * FB + F_IIB;
