@@ -660,7 +660,9 @@ static ms_status step_backward_impl(ms_batch* b, const void* x_in, const float* 
     const bool split = b->split_c > 0 && !(b->sched.flags & MS_SCHED_BWD_ONE_LAUNCH);
     int* bord = reinterpret_cast<int*>(b->scratch + b->sl.bwd_order);
     int* nover = reinterpret_cast<int*>(b->scratch + b->sl.bwd_nover);
-    launch_bwd_order(rec, a.RL, c.S, d->n_substeps, split ? b->split_c : 0, split ? b->split_r : 0, bord, nover, st);
+    int* bslot = reinterpret_cast<int*>(b->scratch + b->sl.bwd_slot);
+    launch_bwd_order(rec, a.RL, c.S, d->n_substeps, split ? b->split_c : 0, split ? b->split_r : 0, bslot, bord, nover,
+                     st);
     HIP_TRY(hipGetLastError());
     a.order = bord;
     a.n_over = nover;

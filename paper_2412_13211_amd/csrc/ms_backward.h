@@ -49,12 +49,14 @@ struct BwdArgs {
 inline int bwd_stride(int S) { return (S + 63) & ~63; }
 void launch_step_bwd(const BwdArgs& a, hipStream_t st);
 void launch_step_bwd_wave(const BwdArgs& a, size_t lds_bytes, int grid, hipStream_t st);
+// one wavefront waiting about `ticks` of the 100 MHz wall clock
+void launch_delay(long long ticks, hipStream_t st);
 // the adjoint's scene order from the record (scenes overflowing fit_c
 // contacts or fit_r robot contacts in some substep first, fit_c = 0: none;
-// each group by decreasing estimated cost) and the size of the first group
-void launch_delay(long long ticks, hipStream_t st);
-void launch_bwd_order(const float* rec, const RecLayout& RL, int S, int nsub, int fit_c, int fit_r, int* order,
-                      int* n_over, hipStream_t st);
+// each group by decreasing estimated cost) and the size of the first group;
+// slot: [S] ints of scratch
+void launch_bwd_order(const float* rec, const RecLayout& RL, int S, int nsub, int fit_c, int fit_r, int* slot,
+                      int* order, int* n_over, hipStream_t st);
 const void* step_bwd_wave_ptr();
 
 // status bit set when the record and the recomputed joint-limit rows disagree

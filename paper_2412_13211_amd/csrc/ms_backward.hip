@@ -229,35 +229,6 @@ __device__ __forceinline__ void zero_lds(float* L, long off, int n) {
   for (int i = lane_id(); i < n; i += 64) L[off + i] = 0.f;
 }
 
-// explicit M~^-1 from the Cholesky factor: lane k < ND solves M~ x = e_k
-// (rows and columns past the robot's degrees of freedom are zero); M~ is
-// symmetric, so column k is stored as row k
-__device__ __forceinline__ void build_minv(const msa::Eng& E, float* L) {
-  const int lane = lane_id();
-  if (lane >= ND) return;
-  const int nb = E.nb;
-  const long Lf = E.w.L;
-  float x[ND];
-#pragma unroll
-  for (int i = 0; i < ND; ++i) x[i] = i == lane ? 1.f : 0.f;
-#pragma unroll
-  for (int i = 0; i < ND; ++i) {
-    float s = x[i];
-#pragma unroll
-    for (int k = 0; k < i; ++k) s -= L[Lf + i * ND + k] * x[k];
-    x[i] = i < nb && lane < nb ? s / L[Lf + i * ND + i] : 0.f;
-  }
-#pragma unroll
-  for (int i = ND - 1; i >= 0; --i) {
-    float s = x[i];
-#pragma unroll
-    for (int k = i + 1; k < ND; ++k) s -= L[Lf + k * ND + i] * x[k];
-    x[i] = i < nb && lane < nb ? s / L[Lf + i * ND + i] : 0.f;
-  }
-#pragma unroll
-  for (int i = 0; i < ND; ++i) L[E.w.Minv + lane * ND + i] = x[i];
-}
-
 // contact rows (the same quantities as the engine's rows(), limit rows
 // excepted): one lane per contact for the tangents, bias and the free-body
 // and door/drawer shares of W; then one lane per robot row (contact,
@@ -1131,23 +1102,28 @@ __global__ __launch_bounds__(64) void k_step_bwd_wave(BwdArgs a) {
   }
 }
 
-// counting sort of the scenes by (group, cost): one workgroup, keys clamped
-// to [0, NKEY); output position f = group * NKEY + (NKEY - 1 - key)
+// sort slot of each scene: group * NKEY + (NKEY - 1 - key), the cost key
+// clamped to [0, NKEY), group 0 for the scenes that overflow (fit_c, fit_r)
 constexpr int NKEY = 4096;
-__global__ __launch_bounds__(1024) void k_bwd_order(const float* rec, RecLayout RL, int S, int nsub, int fit_c,
-                                                    int fit_r, int* order, int* n_over) {
+__global__ __launch_bounds__(256) void k_bwd_keys(const float* rec, RecLayout RL, int S, int nsub, int fit_c,
+                                                  int fit_r, int* slot) {
+  const int s = blockIdx.x * 256 + threadIdx.x;
+  if (s >= S) return;
+  int c = 0;
+  const bool fits = rec_fits(rec, RL, nsub, s, fit_c, fit_r, &c);
+  const int g = fit_c > 0 && !fits ? 0 : 1;
+  const int k = c < 0 ? 0 : (c >= NKEY ? NKEY - 1 : c);
+  slot[s] = g * NKEY + (NKEY - 1 - k);
+}
+
+// counting sort of the scenes by their slots: one workgroup
+__global__ __launch_bounds__(1024) void k_bwd_order(const int* slot, int S, int* order, int* n_over) {
   __shared__ int cnt[2 * NKEY];
   __shared__ int wsum[16];
   const int t = threadIdx.x;
   for (int i = t; i < 2 * NKEY; i += 1024) cnt[i] = 0;
   __syncthreads();
-  auto slot_of = [&](int s) {
-    int c = 0;
-    const bool fits = rec_fits(rec, RL, nsub, s, fit_c, fit_r, &c);
-    const int g = fit_c > 0 && !fits ? 0 : 1;
-    const int k = c < 0 ? 0 : (c >= NKEY ? NKEY - 1 : c);
-    return g * NKEY + (NKEY - 1 - k);
-  };
+  auto slot_of = [&](int s) { return slot[s]; };
   for (int s = t; s < S; s += 1024) atomicAdd(&cnt[slot_of(s)], 1);
   __syncthreads();
   // exclusive scan: thread t owns entries 8t .. 8t + 7
@@ -1183,9 +1159,10 @@ __global__ __launch_bounds__(64) void k_delay(long long ticks) {
 
 void launch_delay(long long ticks, hipStream_t st) { hipLaunchKernelGGL(k_delay, dim3(1), dim3(64), 0, st, ticks); }
 
-void launch_bwd_order(const float* rec, const RecLayout& RL, int S, int nsub, int fit_c, int fit_r, int* order,
-                      int* n_over, hipStream_t st) {
-  hipLaunchKernelGGL(k_bwd_order, dim3(1), dim3(1024), 0, st, rec, RL, S, nsub, fit_c, fit_r, order, n_over);
+void launch_bwd_order(const float* rec, const RecLayout& RL, int S, int nsub, int fit_c, int fit_r, int* slot,
+                      int* order, int* n_over, hipStream_t st) {
+  hipLaunchKernelGGL(k_bwd_keys, dim3((S + 255) / 256), dim3(256), 0, st, rec, RL, S, nsub, fit_c, fit_r, slot);
+  hipLaunchKernelGGL(k_bwd_order, dim3(1), dim3(1024), 0, st, slot, S, order, n_over);
 }
 
 void launch_step_bwd_wave(const BwdArgs& a, size_t lds_bytes, int grid, hipStream_t st) {

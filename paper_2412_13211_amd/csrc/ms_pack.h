@@ -155,7 +155,7 @@ inline ParamLayout param_layout(const Counts& c) {
 }
 
 struct ScratchLayout {
-  size_t queue, status, debug, cycles, act, actb, bwd_order, bwd_nover, fwd_cost, fwd_order, total;
+  size_t queue, status, debug, cycles, act, actb, bwd_order, bwd_nover, bwd_slot, fwd_cost, fwd_order, total;
 };
 inline ScratchLayout scratch_layout(const Counts& c, int n_sub) {
   ScratchLayout s;
@@ -168,6 +168,7 @@ inline ScratchLayout scratch_layout(const Counts& c, int n_sub) {
   s.actb = o; o = align256(o + sizeof(float) * 16 * (size_t)c.S);
   s.bwd_order = o; o = align256(o + sizeof(int) * (size_t)c.S);
   s.bwd_nover = o; o = align256(o + 256);
+  s.bwd_slot = o; o = align256(o + sizeof(int) * (size_t)c.S);
   s.fwd_cost = o; o = align256(o + sizeof(int) * (size_t)c.S);
   s.fwd_order = o; o = align256(o + sizeof(int) * (size_t)c.S);
   s.total = o;
