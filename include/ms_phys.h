@@ -91,6 +91,14 @@ enum {
   MS_SCHED_STATIC_ORDER = 128,  /* process the scenes in the order fixed at creation
                                    (by static size) instead of by decreasing cost as the
                                    previous step measured it (contacts, robot contacts) */
+  MS_SCHED_FWD_ONE_LAUNCH = 256, /* the persistent step in one launch sized for the contact
+                                    caps.  Without it, when a smaller contact cap fits more
+                                    workgroups per CU, the scenes whose previous-step contact
+                                    counts leave room under it run in that layout and the
+                                    others in the full one (side by side, the second on a
+                                    library-owned stream joined back); a scene that
+                                    overflows the smaller layout anyway is stepped again in
+                                    the full one.  The results are the same bit for bit */
   MS_SCHED_BWD_ONE_LAUNCH = 64  /* ms_step_backward in one wavefront launch sized for the
                                   contact caps.  Without it the scenes whose contact
                                   lists fit a smaller LDS layout (more workgroups per
@@ -218,6 +226,17 @@ ms_status ms_get_schedule(const ms_batch* b, ms_schedule* out);
  * MS_E_INVALID when a cap exceeds the batch's.  Either output may be null. */
 ms_status ms_set_backward_split(ms_batch* b, int32_t contact_cap, int32_t robot_contact_cap);
 ms_status ms_get_backward_split(const ms_batch* b, int32_t* contact_cap, int32_t* robot_contact_cap);
+
+/* Contact cap of the smaller layout of the persistent step (see
+ * MS_SCHED_FWD_ONE_LAUNCH); contact_cap 0 turns the split off, < 0 restores
+ * the library's choice.  Error MS_E_INVALID when contact_cap is not below
+ * the batch's.  Drops captured graphs. */
+ms_status ms_set_forward_split(ms_batch* b, int32_t contact_cap);
+/* The cap in use for the current schedule and output settings, and (if
+ * n_full or n_retry is non-null; synchronises the device) how many scenes
+ * the last split step routed to the full layout and stepped again after
+ * overflowing the smaller one.  Any output may be null. */
+ms_status ms_get_forward_split(ms_batch* b, int32_t* contact_cap, int32_t* n_full, int32_t* n_retry);
 
 /* Time the candidate schedules on the given state / controls (the state is
  * not modified: a copy in tmp_state_dev is stepped) and keep the fastest.

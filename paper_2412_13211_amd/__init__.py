@@ -25,10 +25,12 @@ MS_SCHED_CULL = 16
 MS_SCHED_BWD_REFERENCE = 32
 MS_SCHED_BWD_ONE_LAUNCH = 64
 MS_SCHED_STATIC_ORDER = 128
+MS_SCHED_FWD_ONE_LAUNCH = 256
 MS_ST_NONFINITE, MS_ST_OVERFLOW, MS_ST_DEGENERATE, MS_ST_ROBOT_OVERFLOW = 1, 2, 4, 8
 
 EXPORTS = ["ms_query_sizes", "ms_state_floats", "ms_create_batch", "ms_destroy_batch", "ms_set_schedule",
-           "ms_get_schedule", "ms_set_backward_split", "ms_get_backward_split", "ms_autotune", "ms_step", "ms_step_backward",
+           "ms_get_schedule", "ms_set_backward_split", "ms_get_backward_split",
+           "ms_set_forward_split", "ms_get_forward_split", "ms_autotune", "ms_step", "ms_step_backward",
            "ms_step_record", "ms_step_backward_recorded", "ms_get_state", "ms_set_state",
            "ms_scene_status", "ms_set_force_outputs", "ms_reset_robots", "ms_spawn_check", "ms_enable_debug",
            "ms_debug_contacts", "ms_enable_phase_profile", "ms_phase_cycles", "ms_set_task_robot",
@@ -116,6 +118,8 @@ def lib():
             "ms_get_schedule": [vp, vp],
             "ms_set_backward_split": [vp, i32, i32],
             "ms_get_backward_split": [vp, vp, vp],
+            "ms_set_forward_split": [vp, i32],
+            "ms_get_forward_split": [vp, vp, vp, vp],
             "ms_autotune": [vp, vp, vp, vp, i32, vp, vp, vp],
             "ms_step": [vp, vp, vp, vp, vp],
             "ms_step_backward": [vp, vp, vp, vp, vp, vp, vp],
@@ -470,6 +474,19 @@ class MsBatch:
         cc, rc = C.c_int32(), C.c_int32()
         _check(lib().ms_get_backward_split(self.h, C.byref(cc), C.byref(rc)), "ms_get_backward_split")
         return cc.value, rc.value
+
+    def set_forward_split(self, contact_cap):
+        """Contact cap of the persistent step's smaller layout (0: one
+        launch; < 0: the library's choice)."""
+        _check(lib().ms_set_forward_split(self.h, int(contact_cap)), "ms_set_forward_split")
+
+    def get_forward_split(self, counts=False):
+        """The cap in use; with counts=True also (scenes routed to the full
+        layout, scenes stepped again) of the last split step (synchronises)."""
+        cc, nf, nr = C.c_int32(), C.c_int32(), C.c_int32()
+        _check(lib().ms_get_forward_split(self.h, C.byref(cc), C.byref(nf) if counts else None,
+                                          C.byref(nr) if counts else None), "ms_get_forward_split")
+        return (cc.value, nf.value, nr.value) if counts else cc.value
 
     def autotune(self, x, u, reps=5, stream=None):
         tmp = self.torch.empty_like(x)

@@ -58,6 +58,10 @@ struct ms_batch {
   // split adjoint launches: contact caps of the smaller LDS layout (0: no
   // split), the stream of the full-size launch and the fork / join events
   int split_c, split_r;
+  // the forward's smaller layout: contact cap per (furniture staging, force
+  // outputs), -1 until computed, 0 for none; a forced cap (>= 0) or -1
+  int fsplit[2][2];
+  int fsplit_force;
   hipStream_t bwd_stream;
   hipEvent_t ev_fork, ev_join;
   // graphs keyed by (x_in, u, x_out)
@@ -150,16 +154,93 @@ int step_mode(const ms_batch* b) { return b->desc.control_mode == MS_CTRL_ACTION
 
 // Enqueue one control step with the current schedule (no graph).
 // the order of a step's scenes: by the cost keys the previous step wrote
-// (a counting sort that also zeroes the work counter), or the static one
-void set_step_order(ms_batch* b, KArgs& a, hipStream_t st) {
+// (a counting sort that also zeroes the work counters), the scenes routed to
+// the full layout first when fit_c > 0; or the static order
+void set_step_order(ms_batch* b, KArgs& a, hipStream_t st, int fit_c) {
   a.cost = reinterpret_cast<int*>(b->scratch + b->sl.fwd_cost);
+  a.maxc = reinterpret_cast<int*>(b->scratch + b->sl.fwd_maxc);
   if (b->sched.flags & MS_SCHED_STATIC_ORDER) {
     if (a.persistent) launch_reset_queue(a.queue, st);
     return;
   }
   int* ord = reinterpret_cast<int*>(b->scratch + b->sl.fwd_order);
-  launch_cost_order(a.cost, b->cnt.S, ord, a.persistent ? a.queue : nullptr, st);
+  a.n_over = reinterpret_cast<int*>(b->scratch + b->sl.fwd_nover);
+  a.retry = reinterpret_cast<int*>(b->scratch + b->sl.fwd_retry);
+  launch_cost_order(a.cost, a.maxc, b->cnt.S, fit_c, std::max(b->desc.robot_contact_cap, 1), ord,
+                    const_cast<int*>(a.n_over), a.persistent ? a.queue : nullptr, a.retry, st);
   a.order = ord;
+}
+
+// Workgroups of the forward kernel per CU at an LDS size (the occupancy
+// query, capped by the measured LDS rule of bwd_per_cu)
+int fwd_per_cu(size_t lds) {
+  int n = 0;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, step_kernel_ptr(), WAVE, lds) != hipSuccess) n = 0;
+  return std::min(n, (int)(size_t{163840} / (lds + 1024)));
+}
+
+LdsLayout fwd_layout(const ms_batch* b, int cc, int stage, int force) {
+  const Counts& c = b->cnt;
+  return make_layout(std::max(c.fmax, 1), c.smax, cc, std::max(b->desc.robot_contact_cap, 1), stage, force,
+                     std::max(c.nsph_max, 1));
+}
+
+// Contact cap of the forward's smaller layout: the largest one (not below
+// half the batch's) that fits more workgroups per CU, 0 for none.  Scenes
+// whose last contact counts leave room under it run in it; a scene that
+// overflows it anyway is stepped again in the full layout.
+int fwd_split_cap(ms_batch* b, int stage, int force) {
+  if (b->fsplit_force >= 0) return b->fsplit_force;
+  int& v = b->fsplit[stage][force];
+  if (v >= 0) return v;
+  v = 0;
+  const int cap = b->desc.contact_cap;
+  const size_t full = (size_t)fwd_layout(b, cap, stage, force).total * sizeof(float);
+  const int occ = fwd_per_cu(full);
+  if (occ <= 0) return v;
+  for (int k = cap - 1; k >= std::max(cap / 2, 1); --k)
+    if (fwd_per_cu((size_t)fwd_layout(b, k, stage, force).total * sizeof(float)) > occ) {
+      v = k;
+      break;
+    }
+  return v;
+}
+
+// One fused launch of a control step (persistent or not), or the split form:
+// the scenes routed to the full layout on st (a grid of one per CU looping
+// over them), the others in the smaller layout on the second stream after a
+// 15 us wait (as in the adjoint's split), joined back; then a retry launch
+// for the scenes that overflowed the smaller layout.
+ms_status launch_fused(ms_batch* b, KArgs& a, size_t lds, hipStream_t st) {
+  const int force = (b->frc_robot != nullptr || b->grip != nullptr) ? 1 : 0;
+  const int fc = (a.persistent && !(b->sched.flags & (MS_SCHED_STATIC_ORDER | MS_SCHED_FWD_ONE_LAUNCH)))
+                     ? fwd_split_cap(b, a.stage_static, force)
+                     : 0;
+  set_step_order(b, a, st, fc);
+  HIP_TRY(hipGetLastError());
+  if (fc <= 0) {
+    launch_step(a, a.persistent ? persistent_grid(b, lds) : b->cnt.S, lds, st);
+    HIP_TRY(hipGetLastError());
+    return MS_OK;
+  }
+  KArgs big = a, small = a, rt = a;
+  big.fit_mode = 2;
+  small.fit_mode = 1;
+  small.L = fwd_layout(b, fc, a.stage_static, force);
+  rt.fit_mode = 3;
+  const size_t lds_s = lds_bytes_of(small);
+  HIP_TRY(hipEventRecord(b->ev_fork, st));
+  HIP_TRY(hipStreamWaitEvent(b->bwd_stream, b->ev_fork, 0));
+  launch_step(big, std::min(b->cnt.S, b->n_cu), lds, st);
+  HIP_TRY(hipGetLastError());
+  launch_delay(1500, b->bwd_stream);
+  launch_step(small, persistent_grid(b, lds_s), lds_s, b->bwd_stream);
+  HIP_TRY(hipGetLastError());
+  HIP_TRY(hipEventRecord(b->ev_join, b->bwd_stream));
+  HIP_TRY(hipStreamWaitEvent(st, b->ev_join, 0));
+  launch_step(rt, std::min(b->cnt.S, b->n_cu), lds, st);
+  HIP_TRY(hipGetLastError());
+  return MS_OK;
 }
 
 ms_status enqueue_step(ms_batch* b, const void* x_in, const float* u, void* x_out, hipStream_t st) {
@@ -172,8 +253,9 @@ ms_status enqueue_step(ms_batch* b, const void* x_in, const float* u, void* x_ou
     return fail(MS_E_UNSUPPORTED, "scene working set needs %zu B of LDS (device limit %zu B); lower contact_cap "
                 "or robot_contact_cap or disable furniture staging", lds, b->max_lds);
   const bool per_sub = (b->sched.flags & MS_SCHED_PER_SUBSTEP) != 0;
-  const int launches = per_sub ? b->desc.n_substeps : 1;
-  set_step_order(b, a, st);
+  if (!per_sub) return launch_fused(b, a, lds, st);
+  const int launches = b->desc.n_substeps;
+  set_step_order(b, a, st, 0);
   HIP_TRY(hipGetLastError());
   for (int k = 0; k < launches; ++k) {
     KArgs ak = a;
@@ -332,6 +414,8 @@ ms_status ms_create_batch(const ms_batch_desc* d, const ms_scene_desc* sc, void*
   b->task_robot.finger_l = b->task_robot.finger_r = -1;
   b->grip = nullptr;
   b->cap_stream = b->bwd_stream = nullptr;
+  for (int i = 0; i < 4; ++i) b->fsplit[i / 2][i % 2] = -1;
+  b->fsplit_force = -1;
   b->ev_fork = b->ev_join = nullptr;
   if (hipStreamCreateWithFlags(&b->cap_stream, hipStreamNonBlocking) != hipSuccess ||
       hipStreamCreateWithFlags(&b->bwd_stream, hipStreamNonBlocking) != hipSuccess ||
@@ -356,6 +440,7 @@ ms_status ms_create_batch(const ms_batch_desc* d, const ms_scene_desc* sc, void*
     for (int p = 0; p < c.S; ++p) cost0[ord[p]] = 2 * (int)((4095LL * (c.S - 1 - p)) / std::max(c.S - 1, 1));
   }
   hipError_t e = hipMemsetAsync(b->scratch + b->sl.status, 0, sizeof(uint32_t) * c.S, stream);
+  if (e == hipSuccess) e = hipMemsetAsync(b->scratch + b->sl.fwd_maxc, 0, sizeof(int) * c.S, stream);
   if (e == hipSuccess)
     e = hipMemcpyAsync(b->scratch + b->sl.fwd_cost, cost0.data(), sizeof(int) * c.S, hipMemcpyHostToDevice, stream);
   if (e == hipSuccess) e = hipStreamSynchronize(stream);
@@ -379,7 +464,8 @@ ms_status ms_destroy_batch(ms_batch* b) {
 ms_status ms_set_schedule(ms_batch* b, const ms_schedule* s) {
   if (!b || !s) return fail(MS_E_INVALID, "null argument");
   const int known = MS_SCHED_PERSISTENT | MS_SCHED_GRAPH | MS_SCHED_PER_SUBSTEP | MS_SCHED_STAGE_STATIC | MS_SCHED_CULL |
-                    MS_SCHED_BWD_REFERENCE | MS_SCHED_BWD_ONE_LAUNCH | MS_SCHED_STATIC_ORDER;
+                    MS_SCHED_BWD_REFERENCE | MS_SCHED_BWD_ONE_LAUNCH | MS_SCHED_STATIC_ORDER |
+                    MS_SCHED_FWD_ONE_LAUNCH;
   if (s->flags & ~known) return fail(MS_E_INVALID, "unknown schedule flags 0x%x", s->flags);
   if (s->grid < 0) return fail(MS_E_INVALID, "grid must be >= 0");
   KArgs a = make_args(b, nullptr, nullptr, nullptr);
@@ -413,6 +499,32 @@ ms_status ms_set_backward_split(ms_batch* b, int32_t contact_cap, int32_t robot_
                 b->desc.contact_cap, std::max(b->desc.robot_contact_cap, 1));
   b->split_c = contact_cap;
   b->split_r = robot_contact_cap;
+  return MS_OK;
+}
+
+ms_status ms_set_forward_split(ms_batch* b, int32_t contact_cap) {
+  if (!b) return fail(MS_E_INVALID, "null batch");
+  if (contact_cap >= b->desc.contact_cap)
+    return fail(MS_E_INVALID, "forward split cap %d must be below the batch's contact_cap %d", contact_cap,
+                b->desc.contact_cap);
+  drop_graphs(b);
+  b->fsplit_force = contact_cap < 0 ? -1 : contact_cap;
+  return MS_OK;
+}
+
+ms_status ms_get_forward_split(ms_batch* b, int32_t* contact_cap, int32_t* n_full, int32_t* n_retry) {
+  if (!b) return fail(MS_E_INVALID, "null batch");
+  const int force = (b->frc_robot != nullptr || b->grip != nullptr) ? 1 : 0;
+  const int stage = (b->sched.flags & MS_SCHED_STAGE_STATIC) ? 1 : 0;
+  if (contact_cap) *contact_cap = fwd_split_cap(b, stage, force);
+  if (n_full || n_retry) {
+    int v[2] = {0, 0};
+    HIP_TRY(hipDeviceSynchronize());
+    HIP_TRY(hipMemcpy(&v[0], b->scratch + b->sl.fwd_nover, sizeof(int), hipMemcpyDeviceToHost));
+    HIP_TRY(hipMemcpy(&v[1], b->scratch + b->sl.fwd_retry, sizeof(int), hipMemcpyDeviceToHost));
+    if (n_full) *n_full = v[0];
+    if (n_retry) *n_retry = v[1];
+  }
   return MS_OK;
 }
 
@@ -475,12 +587,7 @@ ms_status enqueue_record(ms_batch* b, const void* x_in, const float* u, float* r
   a.RL = bwd_rec(&b->desc, b->cnt);
   size_t lds = lds_bytes_of(a);
   if (lds > b->max_lds) return fail(MS_E_UNSUPPORTED, "scene working set needs %zu B of LDS", lds);
-  set_step_order(b, a, st);
-  HIP_TRY(hipGetLastError());
-  const int grid = a.persistent ? persistent_grid(b, lds) : b->cnt.S;
-  launch_step(a, grid, lds, st);
-  HIP_TRY(hipGetLastError());
-  return MS_OK;
+  return launch_fused(b, a, lds, st);
 }
 
 ms_status ms_reset_robots(ms_batch* b, void* x, const uint8_t* mask, const float* base, const float* noise,

@@ -155,6 +155,14 @@ struct KArgs {
   unsigned long long* phase_cycles;  // [S][8] shader-clock cycles per phase, or null
   int* queue;              // work counter (persistent schedule)
   int* cost;               // [S] cost keys the step writes for the next step's order, or null
+  int* maxc;               // [S] largest contact count | largest robot-contact count << 16 over the step's substeps, or null
+  // split launches (persistent only): 0 takes every position of the order;
+  // 1 the positions from *n_over on, leaving a scene whose contact lists
+  // overflow the launch's layout whole to the retry list; 2 the first
+  // *n_over positions; 3 the retry list.  Work counters queue[0], [1], [2].
+  int fit_mode;
+  const int* n_over;
+  int* retry;              // [1 + S]: count, then scene indices
   int S, NF, NA;
   int n_sub, sub0, n_sub_total;  // substeps in this launch, index of the first, substeps per control step
   int K, mode, ccap, rcap;
@@ -173,9 +181,13 @@ struct KArgs {
 
 void launch_step(const KArgs& a, int grid, size_t lds_bytes, hipStream_t st);
 void launch_reset_queue(int* q, hipStream_t st);
-// order = the scenes by decreasing cost key (cost >> 1, clamped to [0, 4095]);
-// also zeroes the work counter q when q is non-null
-void launch_cost_order(const int* cost, int S, int* order, int* q, hipStream_t st);
+// order = the scenes by decreasing cost key (cost >> 1, clamped to [0, 4095]),
+// those whose last contact counts (maxc) do not leave 8 contacts and 2 robot
+// contacts of room under (fit_c, fit_r) first (fit_c = 0: none), *n_over
+// their count; also zeroes the work counters q[0..2] and the retry count
+// (each pointer may be null)
+void launch_cost_order(const int* cost, const int* maxc, int S, int fit_c, int fit_r, int* order, int* n_over, int* q,
+                       int* retry, hipStream_t st);
 void launch_actions(const DModel* models, const DScene* scenes, const float* x, const float* a, float* tgt, int S,
                     hipStream_t st);
 void launch_actions_bwd(const DModel* models, const DScene* scenes, const float* x, const float* a,

@@ -367,8 +367,16 @@ __device__ __forceinline__ void rec_contacts(const KArgs& a, const float* L, int
     R[2] = __int_as_float(NR);
     R[3] = 0.f;
   }
+  // the fields the contact phase wrote (side codes, normal, point, gap,
+  // key; limit rows: side code and gap); the rest, which later phases fill
+  // in LDS, as zeros so that the record holds no stale values
   const float* C = L + a.L.con;
-  for (int i = lane; i < NC * CSTR; i += WAVE) R[4 + i] = C[i];
+  for (int i = lane; i < NC * CSTR; i += WAVE) {
+    const int f = i % CSTR;
+    const bool contact = i / CSTR >= NL;
+    const bool keep = f == C_INFO || f == C_PHI || (contact && (f < C_IW || f == C_KEY));
+    R[4 + i] = keep ? C[i] : 0.f;
+  }
 }
 
 // ---------------------------------------------------------------- phases
@@ -1761,8 +1769,8 @@ __device__ __forceinline__ void run_scene(const KArgs& a, int s, float* L) {
   float* rec = REC ? a.rec + (size_t)s * a.RL.total : nullptr;
   // cost key for the next step's order: the time of a scene grows about
   // linearly with its contacts, its robot contacts (each some 50 others)
-  // and its free bodies (each some 30)
-  int cost_acc = 30 * S.nf;
+  // and its free bodies (each some 30); the largest lists for its routing
+  int cost_acc = 30 * S.nf, max_nc = 0, max_nr = 0;
   for (int k = 0; k < a.n_sub; ++k) {
     int NC, NR, NL;
     uint64_t keysum = 0;
@@ -1773,8 +1781,13 @@ __device__ __forceinline__ void run_scene(const KArgs& a, int s, float* L) {
     phase_kinematics(a, S, L, rb);
     MS_PHASE(0)
     phase_contacts(a, S, L, rb, NC, NR, NL, status, keysum);
+    // a launch in a smaller layout gives up a scene at its first overflowing
+    // contact list; everything written so far the retry writes again alike
+    if (a.fit_mode == 1 && (status & 10u)) break;
     if (rec) rec_contacts(a, L, NC, NL, NR, rec + a.RL.con + ks * a.RL.cstride);
     cost_acc += (NC - NL) + 50 * NR;
+    max_nc = max(max_nc, NC - NL);
+    max_nr = max(max_nr, NR);
     MS_PHASE(1)
     phase_dynamics(a, S, L, rb, vR);
     MS_PHASE(2)
@@ -1795,6 +1808,13 @@ __device__ __forceinline__ void run_scene(const KArgs& a, int s, float* L) {
       d[2] = (uint32_t)keysum;
       d[3] = (uint32_t)(keysum >> 32);
     }
+  }
+  // a launch in a smaller layout stores nothing of a scene whose lists
+  // overflowed it: the retry launch steps it again in the full layout, from
+  // the unchanged input state
+  if (a.fit_mode == 1 && (status & 10u)) {
+    if (lane == 0) a.retry[1 + atomicAdd(a.retry, 1)] = s;
+    return;
   }
   store_scene(a, S, L, rb, status);
   if (MODE == 2 && a.grip) {
@@ -1827,6 +1847,10 @@ __device__ __forceinline__ void run_scene(const KArgs& a, int s, float* L) {
     if (a.sub0 == 0) a.status[s] = status;
     else a.status[s] |= status;
     if (a.cost) a.cost[s] = a.sub0 == 0 ? cost_acc : a.cost[s] + cost_acc - 30 * S.nf;
+    if (a.maxc) {
+      const int m = a.sub0 == 0 ? 0 : a.maxc[s];
+      a.maxc[s] = max(m & 0xffff, max_nc) | (max(m >> 16, max_nr) << 16);
+    }
     if (prof) {
       for (int k = 0; k < 8; ++k) {
         if (a.sub0 == 0) a.phase_cycles[(size_t)s * 8 + k] = cyc[k];
@@ -1838,17 +1862,20 @@ __device__ __forceinline__ void run_scene(const KArgs& a, int s, float* L) {
 
 template <int MODE>
 __device__ __forceinline__ void step_body(const KArgs& a, float* lds) {
-  // one call site: the persistent form pulls scene indices from the queue,
-  // the plain form takes its block index once
-  int idx = a.persistent ? 0 : (int)blockIdx.x;
+  // one call site: the persistent form pulls positions from its work
+  // counter, the plain form takes its block index once
+  const int qi = a.fit_mode == 2 ? 1 : (a.fit_mode == 3 ? 2 : 0);
+  const int base = a.fit_mode == 1 ? *a.n_over : 0;
+  const int end = a.fit_mode == 2 ? *a.n_over : (a.fit_mode == 3 ? a.retry[0] : a.S);
+  int pos = a.persistent ? 0 : base + (int)blockIdx.x;
   for (;;) {
     if (a.persistent) {
       int got = 0;
-      if (threadIdx.x == 0) got = atomicAdd(a.queue, 1);
-      idx = __shfl(got, 0, WAVE);
+      if (threadIdx.x == 0) got = atomicAdd(a.queue + qi, 1);
+      pos = base + __shfl(got, 0, WAVE);
     }
-    if (idx >= a.S) break;
-    run_scene<MODE>(a, a.order[idx], lds);
+    if (pos >= end) break;
+    run_scene<MODE>(a, a.fit_mode == 3 ? a.retry[1 + pos] : a.order[pos], lds);
     if (!a.persistent) break;
     __syncthreads();
   }
@@ -2038,28 +2065,36 @@ void launch_step(const KArgs& a, int grid, size_t lds_bytes, hipStream_t st) {
 }
 void launch_reset_queue(int* q, hipStream_t st) { hipLaunchKernelGGL(k_reset_queue, dim3(1), dim3(64), 0, st, q); }
 
-// counting sort of the scenes by decreasing cost key: one workgroup of 1024
-// lanes, a histogram over the 4096 keys in LDS, its exclusive prefix sum
-// (four entries per lane, then across the lanes), then a scatter
+// counting sort of the scenes by (group, decreasing cost key): one
+// workgroup of 1024 lanes, a histogram over 2 x 4096 slots in LDS, its
+// exclusive prefix sum (eight entries per lane, then across the lanes), then
+// a scatter
 constexpr int NKEY = 4096;
-__global__ __launch_bounds__(1024) void k_cost_order(const int* cost, int S, int* order, int* q) {
-  __shared__ int cnt[NKEY];
+__global__ __launch_bounds__(1024) void k_cost_order(const int* cost, const int* maxc, int S, int fit_c, int fit_r,
+                                                     int* order, int* n_over, int* q, int* retry) {
+  __shared__ int cnt[2 * NKEY];
   __shared__ int wsum[16];
   const int t = threadIdx.x;
-  if (q && t == 0) q[0] = 0;
-  for (int i = t; i < NKEY; i += 1024) cnt[i] = 0;
+  if (t < 3 && q) q[t] = 0;
+  if (t == 0 && retry) retry[0] = 0;
+  for (int i = t; i < 2 * NKEY; i += 1024) cnt[i] = 0;
   __syncthreads();
   auto slot_of = [&](int s) {
     int k = cost[s] >> 1;
     k = k < 0 ? 0 : (k >= NKEY ? NKEY - 1 : k);
-    return NKEY - 1 - k;
+    int g = 1;
+    if (fit_c > 0 && maxc) {
+      const int m = maxc[s];
+      if ((m & 0xffff) + 8 > fit_c || (m >> 16) + 2 > fit_r) g = 0;
+    }
+    return g * NKEY + (NKEY - 1 - k);
   };
   for (int s = t; s < S; s += 1024) atomicAdd(&cnt[slot_of(s)], 1);
   __syncthreads();
-  int loc[4], sum = 0;
+  int loc[8], sum = 0;
 #pragma unroll
-  for (int i = 0; i < 4; ++i) {
-    loc[i] = cnt[4 * t + i];
+  for (int i = 0; i < 8; ++i) {
+    loc[i] = cnt[8 * t + i];
     sum += loc[i];
   }
   int inc = sum;
@@ -2073,18 +2108,21 @@ __global__ __launch_bounds__(1024) void k_cost_order(const int* cost, int S, int
   __syncthreads();
   int base = inc - sum;
   for (int w = 0; w < (t >> 6); ++w) base += wsum[w];
+  // lane NKEY / 8 owns the first entry of group 1
+  if (t == NKEY / 8 && n_over) *n_over = base;
   __syncthreads();
 #pragma unroll
-  for (int i = 0; i < 4; ++i) {
-    cnt[4 * t + i] = base;
+  for (int i = 0; i < 8; ++i) {
+    cnt[8 * t + i] = base;
     base += loc[i];
   }
   __syncthreads();
   for (int s = t; s < S; s += 1024) order[atomicAdd(&cnt[slot_of(s)], 1)] = s;
 }
 
-void launch_cost_order(const int* cost, int S, int* order, int* q, hipStream_t st) {
-  hipLaunchKernelGGL(k_cost_order, dim3(1), dim3(1024), 0, st, cost, S, order, q);
+void launch_cost_order(const int* cost, const int* maxc, int S, int fit_c, int fit_r, int* order, int* n_over, int* q,
+                       int* retry, hipStream_t st) {
+  hipLaunchKernelGGL(k_cost_order, dim3(1), dim3(1024), 0, st, cost, maxc, S, fit_c, fit_r, order, n_over, q, retry);
 }
 void launch_actions(const DModel* models, const DScene* scenes, const float* x, const float* a, float* tgt, int S,
                     hipStream_t st) {

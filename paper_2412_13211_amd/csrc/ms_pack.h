@@ -155,7 +155,8 @@ inline ParamLayout param_layout(const Counts& c) {
 }
 
 struct ScratchLayout {
-  size_t queue, status, debug, cycles, act, actb, bwd_order, bwd_nover, bwd_slot, fwd_cost, fwd_order, total;
+  size_t queue, status, debug, cycles, act, actb, bwd_order, bwd_nover, bwd_slot, fwd_cost, fwd_order, fwd_maxc,
+      fwd_nover, fwd_retry, total;
 };
 inline ScratchLayout scratch_layout(const Counts& c, int n_sub) {
   ScratchLayout s;
@@ -171,6 +172,9 @@ inline ScratchLayout scratch_layout(const Counts& c, int n_sub) {
   s.bwd_slot = o; o = align256(o + sizeof(int) * (size_t)c.S);
   s.fwd_cost = o; o = align256(o + sizeof(int) * (size_t)c.S);
   s.fwd_order = o; o = align256(o + sizeof(int) * (size_t)c.S);
+  s.fwd_maxc = o; o = align256(o + sizeof(int) * (size_t)c.S);
+  s.fwd_nover = o; o = align256(o + 256);
+  s.fwd_retry = o; o = align256(o + sizeof(int) * (1 + (size_t)c.S));
   s.total = o;
   return s;
 }

@@ -167,6 +167,85 @@ def test_schedules_bitwise_equal():
             assert np.array_equal(got, ref), flags | cull
 
 
+def _split_outputs(mb, ms, x, u, record):
+    """One step: (state out, record or None, status, robot force, body force)."""
+    xt = torch.as_tensor(np.asarray(x, np.float32)).cuda()
+    ut = torch.as_tensor(np.asarray(u, np.float32)).cuda()
+    if record:
+        rec = mb.new_record()
+        rec.zero_()
+        y = mb.step_record(xt, ut, rec)
+    else:
+        rec = None
+        y = mb.step(xt, ut)
+    torch.cuda.synchronize()
+    rf, bf = getattr(mb, "robot_force", None), getattr(mb, "body_force", None)
+    fr = rf.cpu().numpy().copy() if rf is not None else None
+    fb = bf.cpu().numpy().copy() if bf is not None else None
+    return (y.cpu().numpy(), None if rec is None else rec.cpu().numpy(), mb.status().copy(), fr, fb)
+
+
+def _same(a, b):
+    ok = True
+    for name, p, q in zip(("state", "record", "status", "robot force", "body force"), a, b):
+        if (p is None) != (q is None) or (p is not None and not np.array_equal(p, q)):
+            bad = np.flatnonzero(p != q) if p is not None and q is not None and p.shape == q.shape else []
+            say(f"   {name} differs at {len(bad)} entries, first {bad[:8]}")
+            ok = False
+    return ok
+
+
+@pytest.mark.parametrize("extra", ["plain", "graph", "record", "forces"])
+def test_forward_split_bitwise_equal(extra):
+    """The persistent step split into a smaller and the full LDS layout
+    (scenes routed by their previous contact counts, a scene that overflows
+    the smaller layout stepped again in the full one) gives the single
+    launch's state, record, forces and status bit for bit.  A fresh batch's
+    first step routes every scene to the smaller layout, so the scenes with
+    more contacts than its cap take the retry path; the second step routes
+    them to the full layout."""
+    ms = _ms()
+    b = sg.make(3, 64)
+    x, u = b.state0, b.controls(0)
+    flags = ms.MS_SCHED_PERSISTENT | ms.MS_SCHED_CULL | (ms.MS_SCHED_GRAPH if extra == "graph" else 0)
+    ref_mb = ms.MsBatch(b, backward=extra == "record")
+    ref_mb.set_schedule(flags | ms.MS_SCHED_FWD_ONE_LAUNCH)
+    if extra == "forces":
+        ref_mb.enable_forces(True)
+    auto = ref_mb.get_forward_split()
+    ref = _split_outputs(ref_mb, ms, x, u, extra == "record")
+    # the step's contact counts (the diagnostics of a plain step)
+    cnt_mb = ms.MsBatch(b)
+    cnt_mb.set_schedule(ms.MS_SCHED_CULL)
+    cnt_mb.enable_debug(True)
+    _split_outputs(cnt_mb, ms, x, u, False)
+    nmax = cnt_mb.debug_contacts()[:, :, 0].max(axis=1).astype(int)
+    cc = max(int(np.median(nmax)), 9)
+    say(f"[forward split, {extra}] automatic cap {auto}, forced cap {cc}; scenes above it {(nmax > cc).sum()}")
+    assert auto > 0 and (nmax > cc).any() and (nmax + 8 <= cc).any()
+    mb = ms.MsBatch(b, backward=extra == "record")
+    mb.set_schedule(flags)
+    if extra == "forces":
+        mb.enable_forces(True)
+    mb.set_forward_split(cc)
+    got = _split_outputs(mb, ms, x, u, extra == "record")
+    cap, n_full, n_retry = mb.get_forward_split(counts=True)
+    say(f"   first step: {n_full} scenes in the full layout, {n_retry} stepped again")
+    assert cap == cc and n_full == 0 and n_retry == int((nmax > cc).sum())
+    assert _same(got, ref)
+    got = _split_outputs(mb, ms, x, u, extra == "record")
+    cap, n_full, n_retry = mb.get_forward_split(counts=True)
+    say(f"   second step: {n_full} scenes in the full layout, {n_retry} stepped again")
+    assert n_full == int((nmax + 8 > cc).sum()) and n_retry == 0
+    assert _same(got, ref)
+    # the library's own cap
+    mb.set_forward_split(-1)
+    assert mb.get_forward_split() == auto
+    assert _same(_split_outputs(mb, ms, x, u, extra == "record"), ref)
+    with pytest.raises(ms.MsError, match="split cap"):
+        mb.set_forward_split(b.contact_cap)
+
+
 def test_culled_contacts_equal_brute_force_full_size():
     """The bounding-volume pre-test keeps exactly the brute-force contact sets
     (4096 uneven scenes, 5 control steps, every substep)."""
