@@ -210,10 +210,14 @@ int fwd_split_cap(ms_batch* b, int stage, int force) {
 // the scenes routed to the full layout on st (a grid of one per CU looping
 // over them), the others in the smaller layout on the second stream after a
 // 15 us wait (as in the adjoint's split), joined back; then a retry launch
-// for the scenes that overflowed the smaller layout.
+// for the scenes that overflowed the smaller layout.  Not while st is being
+// captured: a replayed graph runs the two branches one after the other.
 ms_status launch_fused(ms_batch* b, KArgs& a, size_t lds, hipStream_t st) {
   const int force = (b->frc_robot != nullptr || b->grip != nullptr) ? 1 : 0;
-  const int fc = (a.persistent && !(b->sched.flags & (MS_SCHED_STATIC_ORDER | MS_SCHED_FWD_ONE_LAUNCH)))
+  hipStreamCaptureStatus cap = hipStreamCaptureStatusNone;
+  HIP_TRY(hipStreamIsCapturing(st, &cap));
+  const int fc = (a.persistent && cap == hipStreamCaptureStatusNone &&
+                  !(b->sched.flags & (MS_SCHED_STATIC_ORDER | MS_SCHED_FWD_ONE_LAUNCH)))
                      ? fwd_split_cap(b, a.stage_static, force)
                      : 0;
   set_step_order(b, a, st, fc);
@@ -882,7 +886,8 @@ ms_status ms_autotune(ms_batch* b, const void* x, const float* u, void* tmp, int
   if (reps <= 0) reps = 5;
   hipStream_t st = static_cast<hipStream_t>(hip_stream);
   const ms_schedule saved = b->sched;
-  const int base_flags[] = {MS_SCHED_GRAPH | MS_SCHED_CULL, MS_SCHED_GRAPH | MS_SCHED_PERSISTENT | MS_SCHED_CULL};
+  const int base_flags[] = {MS_SCHED_GRAPH | MS_SCHED_CULL, MS_SCHED_GRAPH | MS_SCHED_PERSISTENT | MS_SCHED_CULL,
+                            MS_SCHED_PERSISTENT | MS_SCHED_CULL};
   const int stage_opts[] = {MS_SCHED_STAGE_STATIC, 0};
   ms_schedule best = saved;
   float best_ms = 1e30f;

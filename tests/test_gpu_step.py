@@ -228,15 +228,18 @@ def test_forward_split_bitwise_equal(extra):
     if extra == "forces":
         mb.enable_forces(True)
     mb.set_forward_split(cc)
+    # a captured step (graph schedule) runs in one launch: a replayed graph
+    # would run the two branches one after the other
+    split = extra != "graph"
     got = _split_outputs(mb, ms, x, u, extra == "record")
     cap, n_full, n_retry = mb.get_forward_split(counts=True)
     say(f"   first step: {n_full} scenes in the full layout, {n_retry} stepped again")
-    assert cap == cc and n_full == 0 and n_retry == int((nmax > cc).sum())
+    assert cap == cc and n_full == 0 and n_retry == (int((nmax > cc).sum()) if split else 0)
     assert _same(got, ref)
     got = _split_outputs(mb, ms, x, u, extra == "record")
     cap, n_full, n_retry = mb.get_forward_split(counts=True)
     say(f"   second step: {n_full} scenes in the full layout, {n_retry} stepped again")
-    assert n_full == int((nmax + 8 > cc).sum()) and n_retry == 0
+    assert n_full == (int((nmax + 8 > cc).sum()) if split else 0) and n_retry == 0
     assert _same(got, ref)
     # the library's own cap
     mb.set_forward_split(-1)
