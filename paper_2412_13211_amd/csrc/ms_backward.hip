@@ -890,54 +890,87 @@ __device__ void bwd_scene(const BwdArgs& a, int s, float* L) {
     if (lane == 0) {
       E.build_lims();
       if (E.nlim != NL) E.status |= MS_ST_RECORD;
+      LV.cnt[2] = E.nlim;
+      LV.cnt[4] = (int)E.status;
+    }
+    wsync();
+    // level schedule: level(r) = 1 + the largest level of the earlier rows
+    // sharing a dynamic node.  Each row's nodes packed per lane; then one
+    // pass over the rows with the last level of node j in lane j's register
+    // (read with readlane); then per-level counts, offsets and the order
+    E.nlim = LV.cnt[2];
+    {
       const int R = E.nlim + E.nc;
-      for (int k = 0; k < 64; ++k) LV.last[k] = 0;
-      int maxl = 0;
-      for (int r = 0; r < R; ++r) {
+      for (int r = lane; r < R; r += 64) {
         int n1, n2;
         row_nodes(E, r, n1, n2);
-        int lv = LV.last[n1];
-        if (n2 >= 0 && LV.last[n2] > lv) lv = LV.last[n2];
-        ++lv;
-        LV.last[n1] = lv;
-        if (n2 >= 0) LV.last[n2] = lv;
-        LV.lvl[r] = lv;
-        if (lv > maxl) maxl = lv;
+        const bool robot = r >= E.nlim && E.ids(w.con + (long)(r - E.nlim) * CR).ok == 0;
+        LV.lvl[r] = n1 | ((n2 + 1) << 8) | (robot ? 1 << 16 : 0);
       }
-      for (int l = 0; l <= maxl + 1; ++l) {
+      wsync();
+      int last = 0, maxl = 0;
+      for (int base = 0; base < R; base += 64) {
+        const int pkv = base + lane < R ? LV.lvl[base + lane] : 0;
+        int mine = 0;
+        const int n = R - base < 64 ? R - base : 64;
+        for (int k = 0; k < n; ++k) {
+          const int pk = __builtin_amdgcn_readlane(pkv, k);
+          const int n1 = pk & 0xff, n2 = ((pk >> 8) & 0xff) - 1;
+          int lv = __builtin_amdgcn_readlane(last, n1);
+          if (n2 >= 0) {
+            const int l2 = __builtin_amdgcn_readlane(last, n2);
+            lv = l2 > lv ? l2 : lv;
+          }
+          ++lv;
+          if (lane == n1 || lane == n2) last = lv;
+          if (lane == k) mine = lv | (pk & (1 << 16));
+          maxl = lv > maxl ? lv : maxl;
+        }
+        wsync();
+        if (base + lane < R) LV.lvl[base + lane] = mine;
+      }
+      for (int l = lane; l <= maxl + 1; l += 64) {
         LV.loff[l] = 0;
         LV.rob[l] = -1;
       }
-      for (int r = 0; r < R; ++r) {
-        bool robot = r >= E.nlim && E.ids(w.con + (long)(r - E.nlim) * CR).ok == 0;
-        if (robot) LV.rob[LV.lvl[r]] = r;
-        else LV.loff[LV.lvl[r]] += 1;
+      wsync();
+      for (int r = lane; r < R; r += 64) {
+        const int v = LV.lvl[r], lv = v & 0xffff;
+        if (v >> 16) LV.rob[lv] = r;
+        else atomicAdd(&LV.loff[lv], 1);
       }
-      int acc = 0;
-      for (int l = 1; l <= maxl; ++l) {
-        int c = LV.loff[l];
-        LV.loff[l - 1] = acc;
-        acc += c;
+      wsync();
+      if (lane == 0) {
+        int acc = 0;
+        for (int l = 1; l <= maxl; ++l) {
+          const int c = LV.loff[l];
+          LV.loff[l - 1] = acc;
+          acc += c;
+        }
+        LV.loff[maxl] = acc;
       }
-      LV.loff[maxl] = acc;
-      // fill: loff[l - 1] is the running write position of level l
-      for (int r = 0; r < R; ++r) {
-        bool robot = r >= E.nlim && E.ids(w.con + (long)(r - E.nlim) * CR).ok == 0;
-        if (!robot) LV.order[LV.loff[LV.lvl[r] - 1]++] = r;
+      wsync();
+      // fill (rows of one level touch disjoint bodies, so their order within
+      // the level does not change any result): loff[l - 1] is the running
+      // write position of level l
+      for (int r = lane; r < R; r += 64) {
+        const int v = LV.lvl[r];
+        if (!(v >> 16)) LV.order[atomicAdd(&LV.loff[(v & 0xffff) - 1], 1)] = r;
       }
-      // restore the offsets
-      acc = 0;
-      for (int l = 1; l <= maxl; ++l) {
-        int end = LV.loff[l - 1];
-        LV.loff[l - 1] = acc;
-        acc = end;
+      wsync();
+      if (lane == 0) {
+        // restore the offsets
+        int acc = 0;
+        for (int l = 1; l <= maxl; ++l) {
+          const int end = LV.loff[l - 1];
+          LV.loff[l - 1] = acc;
+          acc = end;
+        }
+        LV.loff[maxl] = acc;
+        LV.cnt[0] = E.nc;
+        LV.cnt[1] = E.nrob;
+        LV.cnt[3] = maxl;
       }
-      LV.loff[maxl] = acc;
-      LV.cnt[0] = E.nc;
-      LV.cnt[1] = E.nrob;
-      LV.cnt[2] = E.nlim;
-      LV.cnt[3] = maxl;
-      LV.cnt[4] = (int)E.status;
     }
     wsync();
     phase(2);
