@@ -559,33 +559,37 @@ __device__ __forceinline__ void recompute_wave(msa::Eng& E, float* L, const floa
   }
   wsync();
   // Gauss-Jordan elimination without pivoting (M~ is symmetric positive
-  // definite): 16 pivots between the two buffers, so the inverse ends where
-  // it started; lane owns entries lane, lane + 64, lane + 128, lane + 192
-  for (int p = 0; p < ND; ++p) {
-    const float* A = L + ((p & 1) ? w.Minv : w.L);
-    float* B = L + ((p & 1) ? w.L : w.Minv);
-    float piv = A[p * ND + p];
-    if (p < nb && !(piv > 0.f)) {
-      if (lane == 0) E.status |= Eng::MS_DEGENERATE_BIT;
-      piv = 1e-30f;
+  // definite), in registers: lane i < 16 holds row i; pivot p's row is read
+  // from lane p with readlane (the pivot loop is unrolled, so every register
+  // index is a constant); rows and columns past the robot's degrees of
+  // freedom are identity and stay so
+  if (lane < ND) {
+    float a[ND];
+#pragma unroll
+    for (int k = 0; k < ND; ++k) a[k] = L[w.L + lane * ND + k];
+    bool degen = false;
+#pragma unroll
+    for (int p = 0; p < ND; ++p) {
+      float prow[ND];
+#pragma unroll
+      for (int k = 0; k < ND; ++k) prow[k] = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(a[k]), p));
+      float piv = prow[p];
+      if (p < nb && !(piv > 0.f)) {
+        degen = true;
+        piv = 1e-30f;
+      }
+      const float inv = 1.f / piv;
+      const float f = a[p];
+      const bool own = lane == p;
+#pragma unroll
+      for (int k = 0; k < ND; ++k) {
+        if (k == p) a[k] = own ? inv : -f * inv;
+        else a[k] = own ? prow[k] * inv : a[k] - f * (prow[k] * inv);
+      }
     }
-    const float inv = 1.f / piv;
-    for (int e = lane; e < ND * ND; e += 64) {
-      const int i = e >> 4, k = e & 15;
-      float v;
-      if (i == p && k == p) v = inv;
-      else if (i == p) v = A[p * ND + k] * inv;
-      else if (k == p) v = -A[i * ND + p] * inv;
-      else v = A[e] - A[i * ND + p] * (A[p * ND + k] * inv);
-      B[e] = v;
-    }
-    wsync();
-  }
-  // the inverse is in w.L after an even number of pivots: move it and clear
-  // the padding
-  for (int e = lane; e < ND * ND; e += 64) {
-    const int i = e >> 4, k = e & 15;
-    L[w.Minv + e] = i < nb && k < nb ? L[w.L + e] : 0.f;
+    if (degen && lane == 0) E.status |= Eng::MS_DEGENERATE_BIT;
+#pragma unroll
+    for (int k = 0; k < ND; ++k) L[w.Minv + lane * ND + k] = lane < nb && k < nb ? a[k] : 0.f;
   }
 }
 
