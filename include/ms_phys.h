@@ -17,12 +17,17 @@
  *   - "_dev" pointers are device memory on the batch's device; "host" ones
  *     are host memory.  The caller owns every buffer; the library allocates
  *     no device memory (it binds the params / scratch / tape buffers the
- *     caller allocated from ms_query_sizes) and keeps only host objects and
- *     HIP graphs.
- *   - Stream-ordered calls (ms_step, ms_step_backward, ms_set_state) enqueue
- *     work on hip_stream (a hipStream_t, may be null = default stream) and
- *     return without synchronising.  Argument errors are detected before
- *     anything is enqueued and leave all buffers untouched.
+ *     caller allocated from ms_query_sizes) and keeps only host objects: HIP
+ *     graphs, a capture stream, and a second stream with two events for
+ *     split launches (all at default priority).
+ *   - Stream-ordered calls (ms_step, ms_step_record, ms_step_backward,
+ *     ms_step_backward_recorded, ms_set_state) enqueue work on hip_stream (a
+ *     hipStream_t, may be null = default stream) and return without
+ *     synchronising.  A split launch runs part of the work on the library's
+ *     second stream, forked from and joined back onto hip_stream with events,
+ *     so later work on hip_stream sees all of it; calls on one batch from
+ *     several streams at once are not supported.  Argument errors are
+ *     detected before anything is enqueued and leave all buffers untouched.
  *   - Numeric faults are per scene: status bits, read with ms_scene_status.
  *
  * State layout (float32, one flat buffer of ms_state_floats() floats):
