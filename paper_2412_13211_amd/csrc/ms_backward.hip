@@ -35,24 +35,23 @@ namespace {
 
 __device__ __forceinline__ int lane_id() { return threadIdx.x; }
 __device__ __forceinline__ void wsync() { __syncthreads(); }
-__device__ __forceinline__ float bcast0(float v) { return __shfl(v, 0, 64); }
-// sum over lanes 0..15 (other lanes pass 0), returned in every lane
-__device__ __forceinline__ float sum16_b(float v) {
-  v += __shfl_xor(v, 8, 64);
-  v += __shfl_xor(v, 4, 64);
-  v += __shfl_xor(v, 2, 64);
-  v += __shfl_xor(v, 1, 64);
-  return __shfl(v, 0, 64);
+__device__ __forceinline__ float bcast0(float v) { return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), 0)); }
+// value of the lane N places along within its row of 16 lanes (DPP row
+// rotation: a VALU operand modifier, no LDS crossbar)
+template <int N>
+__device__ __forceinline__ float row_ror(float v) {
+  return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0x120 + N, 0xf, 0xf, false));
 }
-
 // sum within each 16-lane group, returned in every lane of the group
 __device__ __forceinline__ float sum16(float v) {
-  v += __shfl_xor(v, 8, 64);
-  v += __shfl_xor(v, 4, 64);
-  v += __shfl_xor(v, 2, 64);
-  v += __shfl_xor(v, 1, 64);
+  v += row_ror<8>(v);
+  v += row_ror<4>(v);
+  v += row_ror<2>(v);
+  v += row_ror<1>(v);
   return v;
 }
+// sum over lanes 0..15 (other lanes pass 0), returned in every lane
+__device__ __forceinline__ float sum16_b(float v) { return bcast0(sum16(v)); }
 
 // level-schedule views inside the LDS block
 struct Lv {

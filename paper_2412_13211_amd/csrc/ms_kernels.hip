@@ -97,13 +97,23 @@ __device__ __forceinline__ int prefix_below(uint64_t m) {
 }
 __device__ __forceinline__ float bcast(float v, int src) { return __shfl(v, src, WAVE); }
 __device__ __forceinline__ int bcasti(int v, int src) { return __shfl(v, src, WAVE); }
+// value of the lane N places along within its row of 16 lanes (DPP row
+// rotation: a VALU operand modifier, no LDS crossbar)
+template <int N>
+__device__ __forceinline__ float row_ror(float v) {
+  return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0x120 + N, 0xf, 0xf, false));
+}
 // sum over aligned groups of 16 lanes (result in every lane of the group)
 __device__ __forceinline__ float sum16(float v) {
-  v += __shfl_xor(v, 8, WAVE);
-  v += __shfl_xor(v, 4, WAVE);
-  v += __shfl_xor(v, 2, WAVE);
-  v += __shfl_xor(v, 1, WAVE);
+  v += row_ror<8>(v);
+  v += row_ror<4>(v);
+  v += row_ror<2>(v);
+  v += row_ror<1>(v);
   return v;
+}
+// lane src's value in every lane (src uniform)
+__device__ __forceinline__ float lane_val(float v, int src) {
+  return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), src));
 }
 __device__ __forceinline__ void wave_sync() { __syncthreads(); }
 
@@ -1516,7 +1526,7 @@ __device__ __forceinline__ void phase_pgs(const KArgs& a, const Scene& S, float*
         onb(n, t1, t2);
         SideReg B;
         side_load(F, A, (info >> 16) & 0xffff, p, B);
-        float dn = bcast(sum16(lane < ND ? Jn * vR : 0.f), 0);
+        float dn = lane_val(sum16(lane < ND ? Jn * vR : 0.f), 0);
         float r = dn - dot(n, side_vel(B, p)) + bias;
         float nl = l0;
         if (iw0 > 0.f) nl = fmaxf(0.f, l0 - r * iw0);
@@ -1529,7 +1539,7 @@ __device__ __forceinline__ void phase_pgs(const KArgs& a, const Scene& S, float*
           float vj = __shfl(vR, j, WAVE);
           float part = lane < ND ? J1 * vj : (lane < 2 * ND ? J2 * vj : 0.f);
           float dsum = sum16(part);
-          float d1 = bcast(dsum, 0), d2 = bcast(dsum, ND);
+          float d1 = lane_val(dsum, 0), d2 = lane_val(dsum, ND);
           f3 uB = side_vel(B, p);
           float y1, y2;
           friction_disk(l1, l2, d1 - dot(t1, uB), d2 - dot(t2, uB), iw1, iw2, mu * nl, y1, y2);
