@@ -207,8 +207,8 @@ def main():
                     help="only run a plain device copy of BYTES bytes 5 times (HBM counter calibration)")
     args = ap.parse_args()
     if args.gpus != 1:
-        print(f"bench.py measures one GPU only: the step has no cross-GPU exchange and this build runs on "
-              f"a single MI355X (asked for --gpus {args.gpus}).", file=sys.stderr)
+        print(f"bench.py measures one GPU only: scenes are independent and the step has no cross-GPU "
+              f"exchange, so G GPUs run G independent batches (asked for --gpus {args.gpus}).", file=sys.stderr)
         sys.exit(2)
 
     import torch
