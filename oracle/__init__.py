@@ -6,8 +6,13 @@ shares no code with the GPU path: it reads the same generated scene arrays
 through its own reader (``ms_oracle.hpp``).
 
 Parity status per function (details in the design notes):
-  or_step      pinned by closed forms and invariants (tests/test_oracle_*.py)
-  or_vjp/jvp   pinned by central finite differences and the dot-product test
+  or_step      pinned by closed forms and invariants (tests/test_oracle_*.py),
+               including the robot and door / drawer contact rows, joint-limit
+               rows, implicit PD drive, joint damping, gyroscopic term and the
+               robot contact cap (tests/_pins.py); each of those pins is shown
+               to fail on a copy with a planted mistake (tests/_mutants.py)
+  or_vjp/jvp   pinned by central finite differences, the dot-product test and
+               the ballistic and sliding closed-form sensitivities
   multi-contact friction at finite PGS sweeps: parity unpinned beyond the
   single-contact closed forms and physical-plausibility checks.
 """
@@ -38,6 +43,31 @@ def build(force=False):
     return LIB
 
 
+def source_texts():
+    """The oracle's source files by name (ms_oracle.cpp and its headers)."""
+    out = {}
+    for p in SRC + HDR:
+        with open(p) as f:
+            out[os.path.basename(p)] = f.read()
+    return out
+
+
+def build_variant(texts, out_dir, opt="-O1"):
+    """Compile another text of the oracle's sources (the tests plant single
+    mistakes in a copy to show that a pin catches them) in ``out_dir``;
+    ``texts`` maps file names to contents, as source_texts() returns them.
+    Returns the library's path."""
+    os.makedirs(out_dir, exist_ok=True)
+    for name, text in texts.items():
+        with open(os.path.join(out_dir, name), "w") as f:
+            f.write(text)
+    src = os.path.join(out_dir, "ms_oracle.cpp")
+    out_path = os.path.join(out_dir, "liboracle_variant.so")
+    subprocess.check_call(["g++", opt, "-std=c++17", "-ffp-contract=off", "-fno-fast-math", "-fPIC", "-shared",
+                           "-w", "-o", out_path, src, "-lpthread"])
+    return out_path
+
+
 class OrScene(C.Structure):
     _fields_ = [("n_scenes", C.c_int32), ("n_models", C.c_int32)] + [
         (n, C.c_void_p) for n in [
@@ -53,7 +83,7 @@ class OrScene(C.Structure):
 class OrParams(C.Structure):
     _fields_ = [("h", C.c_double), ("mu", C.c_double), ("baumgarte", C.c_double), ("margin", C.c_double),
                 ("gravity", C.c_double * 3), ("n_sub", C.c_int32), ("pgs_iters", C.c_int32),
-                ("control_mode", C.c_int32), ("contact_cap", C.c_int32)]
+                ("control_mode", C.c_int32), ("contact_cap", C.c_int32), ("robot_contact_cap", C.c_int32)]
 
 
 class OrDebug(C.Structure):
@@ -64,15 +94,17 @@ class OrDebug(C.Structure):
                 ("grip_finger_r", C.c_int32), ("grip", C.c_void_p)]
 
 
-_lib = None
+_libs = {}
 
 
-def lib():
-    global _lib
-    if _lib is None:
-        if not os.path.exists(LIB):
+def lib(path=None):
+    """The oracle library (ctypes), built on first use; ``path`` loads another
+    build of the same source (the tests' planted-mistake copies)."""
+    path = LIB if path is None else path
+    if path not in _libs:
+        if path == LIB and not os.path.exists(LIB):
             build()
-        L = C.CDLL(LIB)
+        L = C.CDLL(path)
         vp = C.c_void_p
         for name, args in [("or_step", [vp, vp, vp, vp, vp, C.c_int, vp]),
                            ("or_vjp", [vp, vp, vp, vp, vp, vp, vp, C.c_int]),
@@ -93,8 +125,8 @@ def lib():
         L.or_onb.restype = None
         L.or_quat_update.argtypes = [vp, vp, C.c_double, vp]
         L.or_quat_update.restype = None
-        _lib = L
-    return _lib
+        _libs[path] = L
+    return _libs[path]
 
 
 def _ptr(a):
@@ -112,8 +144,9 @@ class Oracle:
              "static_box", "plane", "aux_type", "aux_rot", "aux_pos", "aux_axis", "aux_box", "aux_mass",
              "aux_inertia", "aux_limit"]
 
-    def __init__(self, batch, threads=0, **overrides):
+    def __init__(self, batch, threads=0, lib_path=None, **overrides):
         self.batch = batch
+        self._L = lib(lib_path)
         self.threads = threads
         self._keep = {}
         sc = OrScene()
@@ -138,6 +171,7 @@ class Oracle:
         p.pgs_iters = get("pgs_iters")
         p.control_mode = get("control_mode")
         p.contact_cap = get("contact_cap")
+        p.robot_contact_cap = get("robot_contact_cap")
         self.params = p
         self.S = batch.n_scenes
         self.nsf = batch.state_floats
@@ -170,7 +204,7 @@ class Oracle:
             dbg.dump_cap = dump_cap
             if self.grip_cfg is not None:
                 dbg.grip_ee, dbg.grip_finger_l, dbg.grip_finger_r = self.grip_cfg
-        rc = lib().or_step(C.byref(self.sc), C.byref(self.params), _ptr(x), _ptr(u), _ptr(out), self.threads,
+        rc = self._L.or_step(C.byref(self.sc), C.byref(self.params), _ptr(x), _ptr(u), _ptr(out), self.threads,
                            C.byref(dbg) if dbg is not None else None)
         if rc != 0:
             raise RuntimeError(f"or_step failed: {rc}")
@@ -181,7 +215,7 @@ class Oracle:
         x = np.ascontiguousarray(x, np.float64)
         u = np.ascontiguousarray(u, np.float64).reshape(self.S, 16)
         out = np.empty(self.nsf, np.float64)
-        if lib().or_step_f32(C.byref(self.sc), C.byref(self.params), _ptr(x), _ptr(u), _ptr(out), self.threads):
+        if self._L.or_step_f32(C.byref(self.sc), C.byref(self.params), _ptr(x), _ptr(u), _ptr(out), self.threads):
             raise RuntimeError("or_step_f32 failed")
         return out
 
@@ -203,7 +237,7 @@ class Oracle:
         x = np.ascontiguousarray(x, np.float64)
         out = np.zeros(self.S, np.int32)
         phi = np.zeros(self.S, np.float64)
-        if lib().or_spawn_check(C.byref(self.sc), _ptr(x), _ptr(out), _ptr(phi), self.threads):
+        if self._L.or_spawn_check(C.byref(self.sc), _ptr(x), _ptr(out), _ptr(phi), self.threads):
             raise RuntimeError("or_spawn_check failed")
         return (out, phi) if with_phi else out
 
@@ -213,7 +247,7 @@ class Oracle:
         g = np.ascontiguousarray(gx_out, np.float64)
         gx = np.zeros(self.nsf, np.float64)
         gu = np.zeros((self.S, 16), np.float64)
-        rc = lib().or_vjp(C.byref(self.sc), C.byref(self.params), _ptr(x), _ptr(u), _ptr(g), _ptr(gx), _ptr(gu),
+        rc = self._L.or_vjp(C.byref(self.sc), C.byref(self.params), _ptr(x), _ptr(u), _ptr(g), _ptr(gx), _ptr(gu),
                           self.threads)
         if rc != 0:
             raise RuntimeError("or_vjp failed")
@@ -225,7 +259,7 @@ class Oracle:
         dx = np.ascontiguousarray(dx, np.float64)
         du = np.ascontiguousarray(du, np.float64).reshape(self.S, 16)
         out = np.zeros(self.nsf, np.float64)
-        rc = lib().or_jvp(C.byref(self.sc), C.byref(self.params), _ptr(x), _ptr(u), _ptr(dx), _ptr(du), _ptr(out),
+        rc = self._L.or_jvp(C.byref(self.sc), C.byref(self.params), _ptr(x), _ptr(u), _ptr(dx), _ptr(du), _ptr(out),
                           self.threads)
         if rc != 0:
             raise RuntimeError("or_jvp failed")
@@ -235,7 +269,7 @@ class Oracle:
         x = np.ascontiguousarray(x, np.float64)
         u = np.ascontiguousarray(u, np.float64).reshape(self.S, 16)
         out = np.zeros(self.S, np.float64)
-        lib().or_flops(C.byref(self.sc), C.byref(self.params), _ptr(x), _ptr(u), _ptr(out))
+        self._L.or_flops(C.byref(self.sc), C.byref(self.params), _ptr(x), _ptr(u), _ptr(out))
         return out
 
     # ---- probes -------------------------------------------------------
@@ -245,7 +279,7 @@ class Oracle:
         sph = np.zeros((max(ns, 1), 3))
         org = np.zeros((16, 3))
         rot = np.zeros((16, 9))
-        nb = lib().or_fk(C.byref(self.sc), model, _ptr(q), _ptr(sph), _ptr(org), _ptr(rot))
+        nb = self._L.or_fk(C.byref(self.sc), model, _ptr(q), _ptr(sph), _ptr(org), _ptr(rot))
         return sph[:ns], org[:nb], rot[:nb].reshape(nb, 3, 3)
 
     def dynamics(self, model, q, qd, g=(0.0, 0.0, -9.81)):
@@ -254,7 +288,7 @@ class Oracle:
         g = np.ascontiguousarray(g, np.float64)
         M = np.zeros((16, 16))
         Cb = np.zeros(16)
-        nb = lib().or_dynamics(C.byref(self.sc), model, _ptr(q), _ptr(qd), _ptr(g), _ptr(M), _ptr(Cb))
+        nb = self._L.or_dynamics(C.byref(self.sc), model, _ptr(q), _ptr(qd), _ptr(g), _ptr(M), _ptr(Cb))
         return M[:nb, :nb], Cb[:nb]
 
     def aba(self, model, q, qd, tau, arm=None, g=(0.0, 0.0, -9.81)):
@@ -264,13 +298,13 @@ class Oracle:
         arm = np.zeros(16) if arm is None else np.ascontiguousarray(arm, np.float64)
         g = np.ascontiguousarray(g, np.float64)
         out = np.zeros(16)
-        nb = lib().or_aba(C.byref(self.sc), model, _ptr(q), _ptr(qd), _ptr(tau), _ptr(arm), _ptr(g), _ptr(out))
+        nb = self._L.or_aba(C.byref(self.sc), model, _ptr(q), _ptr(qd), _ptr(tau), _ptr(arm), _ptr(g), _ptr(out))
         return out[:nb]
 
     def kinetic_energy(self, model, q, qd):
         q = np.ascontiguousarray(q, np.float64)
         qd = np.ascontiguousarray(qd, np.float64)
-        return lib().or_kinetic_energy(C.byref(self.sc), model, _ptr(q), _ptr(qd))
+        return self._L.or_kinetic_energy(C.byref(self.sc), model, _ptr(q), _ptr(qd))
 
 
 def pair(kind, c, r, prim):

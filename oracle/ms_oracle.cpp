@@ -627,11 +627,22 @@ template <class T> void substep(const SceneC& c, const or_params& pr, StateS<T>&
 
   // 3. contacts (canonical order: owner class, owner index, target class, target index)
   std::vector<Contact<T>> con;
-  bool overflow = false;
+  bool overflow = false, robot_overflow = false;
+  int n_robot = 0;
   const double margin = pr.margin;
+  // caps: a robot-owned contact beyond robot_contact_cap is dropped first;
+  // then any contact beyond contact_cap (both keep the canonical-order prefix)
   auto emit = [&](const Contact<T>& ct) {
-    if ((int)con.size() < pr.contact_cap) con.push_back(ct);
-    else overflow = true;
+    if (ct.robot_owner && n_robot >= pr.robot_contact_cap) {
+      robot_overflow = true;
+      return;
+    }
+    if ((int)con.size() < pr.contact_cap) {
+      con.push_back(ct);
+      if (ct.robot_owner) ++n_robot;
+    } else {
+      overflow = true;
+    }
   };
   auto aux_obb = [&](int x, V3<T>& bc, M3<T>& R) {
     const Kin<T>& k = wk.ak[x];
@@ -734,6 +745,7 @@ template <class T> void substep(const SceneC& c, const or_params& pr, StateS<T>&
     }
   }
   if (overflow) status |= 2u;
+  if (robot_overflow) status |= 8u;
 
   // 4. unconstrained velocities ------------------------------------------
   T vR[ND];

@@ -77,12 +77,16 @@ typedef struct {
 
 typedef struct {
   double h, mu, baumgarte, margin, gravity[3];
-  int32_t n_sub, pgs_iters, control_mode, contact_cap;
+  int32_t n_sub, pgs_iters, control_mode;
+  int32_t contact_cap;        // contacts kept per scene and substep (first in canonical order)
+  int32_t robot_contact_cap;  // robot-owned contacts kept per scene and substep; the
+                              // robot's later contacts are dropped before the total cap
 } or_params;
 
 // Optional per-scene diagnostics (any pointer may be null).
 typedef struct {
-  uint32_t* status;        // [S] bit0 non-finite, bit1 contact overflow, bit2 degenerate row
+  uint32_t* status;        // [S] bit0 non-finite, bit1 contact overflow, bit2 degenerate row,
+                           // bit3 robot contact overflow
   int32_t* n_contacts;     // [S][n_sub]
   uint64_t* key_hash;      // [S][n_sub] sum of mixed contact keys
   uint64_t* act_hash;      // [S][n_sub] hash of the PGS active set (clamps / projections)
