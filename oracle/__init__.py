@@ -89,7 +89,8 @@ class OrParams(C.Structure):
 class OrDebug(C.Structure):
     _fields_ = [("status", C.c_void_p), ("n_contacts", C.c_void_p), ("key_hash", C.c_void_p),
                 ("act_hash", C.c_void_p), ("dump_cap", C.c_int32), ("dump_keys", C.c_void_p),
-                ("dump_phi", C.c_void_p), ("dump_lambda", C.c_void_p), ("robot_force", C.c_void_p),
+                ("dump_phi", C.c_void_p), ("dump_lambda", C.c_void_p), ("dump_y", C.c_void_p),
+                ("robot_force", C.c_void_p),
                 ("robot_body_force", C.c_void_p), ("grip_ee", C.c_uint32), ("grip_finger_l", C.c_int32),
                 ("grip_finger_r", C.c_int32), ("grip", C.c_void_p)]
 
@@ -108,7 +109,7 @@ def lib(path=None):
         vp = C.c_void_p
         for name, args in [("or_step", [vp, vp, vp, vp, vp, C.c_int, vp]),
                            ("or_vjp", [vp, vp, vp, vp, vp, vp, vp, C.c_int]),
-                           ("or_step_f32", [vp, vp, vp, vp, vp, C.c_int]),
+                           ("or_step_f32", [vp, vp, vp, vp, vp, C.c_int, vp]),
                            ("or_jvp", [vp, vp, vp, vp, vp, vp, vp, C.c_int]),
                            ("or_flops", [vp, vp, vp, vp, vp]),
                            ("or_fk", [vp, C.c_int, vp, vp, vp, vp]),
@@ -198,6 +199,7 @@ class Oracle:
                 d["dump_keys"] = np.zeros((self.S, dump_cap), np.uint64)
                 d["dump_phi"] = np.zeros((self.S, dump_cap), np.float64)
                 d["dump_lambda"] = np.zeros((self.S, dump_cap, 3), np.float64)
+                d["dump_y"] = np.zeros((self.S, self.params.pgs_iters, dump_cap, 3), np.float64)
             dbg = OrDebug()
             for k, v in d.items():
                 setattr(dbg, k, _ptr(v))
@@ -210,14 +212,28 @@ class Oracle:
             raise RuntimeError(f"or_step failed: {rc}")
         return (out, d) if dbg is not None else out
 
-    def step_f32(self, x, u):
-        """The same step with float intermediates (error floor of FP32 evaluation)."""
+    def step_f32(self, x, u, dump_cap=0):
+        """The same step in IEEE single precision (error floor of an FP32
+        evaluation); with dump_cap also the last substep's impulses and
+        pre-projection values, as step() gives them."""
         x = np.ascontiguousarray(x, np.float64)
         u = np.ascontiguousarray(u, np.float64).reshape(self.S, 16)
         out = np.empty(self.nsf, np.float64)
-        if self._L.or_step_f32(C.byref(self.sc), C.byref(self.params), _ptr(x), _ptr(u), _ptr(out), self.threads):
+        d = {}
+        dbg = None
+        if dump_cap:
+            d = dict(dump_keys=np.zeros((self.S, dump_cap), np.uint64),
+                     dump_phi=np.zeros((self.S, dump_cap), np.float64),
+                     dump_lambda=np.zeros((self.S, dump_cap, 3), np.float64),
+                     dump_y=np.zeros((self.S, self.params.pgs_iters, dump_cap, 3), np.float64))
+            dbg = OrDebug()
+            for k, v in d.items():
+                setattr(dbg, k, _ptr(v))
+            dbg.dump_cap = dump_cap
+        if self._L.or_step_f32(C.byref(self.sc), C.byref(self.params), _ptr(x), _ptr(u), _ptr(out), self.threads,
+                               C.byref(dbg) if dbg is not None else None):
             raise RuntimeError("or_step_f32 failed")
-        return out
+        return (out, d) if dump_cap else out
 
     def rollout(self, x0, controls, debug=False):
         xs = [np.asarray(x0, np.float64)]

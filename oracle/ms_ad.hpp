@@ -148,6 +148,37 @@ inline cdouble Sqrt(const cdouble& a) { ++g_flops; return cdouble(std::sqrt(a.v)
 inline cdouble Sin(const cdouble& a) { ++g_flops; return cdouble(std::sin(a.v)); }
 inline cdouble Cos(const cdouble& a) { ++g_flops; return cdouble(std::cos(a.v)); }
 
+// --------------------------------------------------------------------- f32s
+// IEEE binary32 evaluation: every operation rounds to float, and a double
+// operand (a parameter such as h, or a literal) is rounded to float first, so
+// no intermediate is carried in double.  Used for the FP32 error floor.
+struct f32s {
+  float v;
+  f32s() : v(0.0f) {}
+  f32s(double x) : v((float)x) {}
+  f32s& operator+=(const f32s& o) { v = v + o.v; return *this; }
+  f32s& operator-=(const f32s& o) { v = v - o.v; return *this; }
+  f32s& operator*=(const f32s& o) { v = v * o.v; return *this; }
+  f32s& operator/=(const f32s& o) { v = v / o.v; return *this; }
+};
+inline double val(const f32s& x) { return x.v; }
+inline f32s operator+(f32s a, const f32s& b) { return a += b; }
+inline f32s operator-(f32s a, const f32s& b) { return a -= b; }
+inline f32s operator*(f32s a, const f32s& b) { return a *= b; }
+inline f32s operator/(f32s a, const f32s& b) { return a /= b; }
+inline f32s operator-(const f32s& a) { f32s r; r.v = -a.v; return r; }
+inline f32s operator+(const f32s& a, double b) { return a + f32s(b); }
+inline f32s operator+(double a, const f32s& b) { return f32s(a) + b; }
+inline f32s operator-(const f32s& a, double b) { return a - f32s(b); }
+inline f32s operator-(double a, const f32s& b) { return f32s(a) - b; }
+inline f32s operator*(const f32s& a, double b) { return a * f32s(b); }
+inline f32s operator*(double a, const f32s& b) { return f32s(a) * b; }
+inline f32s operator/(const f32s& a, double b) { return a / f32s(b); }
+inline f32s operator/(double a, const f32s& b) { return f32s(a) / b; }
+inline f32s Sqrt(const f32s& a) { f32s r; r.v = std::sqrt(a.v); return r; }
+inline f32s Sin(const f32s& a) { f32s r; r.v = std::sin(a.v); return r; }
+inline f32s Cos(const f32s& a) { f32s r; r.v = std::cos(a.v); return r; }
+
 inline double Sqrt(double a) { return std::sqrt(a); }
 inline double val(float x) { return x; }
 inline float Sqrt(float a) { return std::sqrt(a); }

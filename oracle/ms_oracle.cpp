@@ -565,7 +565,17 @@ template <class T> void art_row(const ArtModel& m, const Kin<T>& k, int body, co
 }
 
 template <class P> struct TestScalarT { using type = double; };
-template <> struct TestScalarT<cdouble> { using type = cdouble; };
+
+// Operation count of one emit decision (the signed distance alone), charged
+// to the counting scalar in place of the decision's own evaluation, which
+// also forms n and p and, for an axis-aligned box, multiplies by an identity
+// rotation:  plane n.c - d - r: 7;  axis-aligned box c - m, clamp, |c - y| - r
+// (inside: e - |c|): 13;  oriented box R^T (c - x) then as an axis-aligned
+// box: 28;  sphere |c_A - c_B| - r_A - r_B: 11.
+enum { COST_PLANE = 7, COST_AABB = 13, COST_OBB = 28, COST_SPHERE = 11 };
+template <class T> void count_decision(int n) {
+  if constexpr (std::is_same<T, cdouble>::value) g_flops += (uint64_t)n;
+}
 
 // One substep of one scene (see the header for the sequence of steps).
 template <class T> void substep(const SceneC& c, const or_params& pr, StateS<T>& st, const T* u, int isub,
@@ -662,6 +672,7 @@ template <class T> void substep(const SceneC& c, const or_params& pr, StateS<T>&
     V3<P> nP, pP;
     for (int pl = 0; pl < (int)c.planes.size(); ++pl) {
       if (pl == 0 && skip_floor) continue;
+      count_decision<T>(COST_PLANE);
       P phi = g_plane<P>(cp, r, c.planes[pl].data(), nP, pP);
       if (val(phi) < margin) {
         Contact<T> ct;
@@ -678,6 +689,7 @@ template <class T> void substep(const SceneC& c, const or_params& pr, StateS<T>&
       V3<P> bc{P(bx[0]), P(bx[1]), P(bx[2])};
       M3<P> RI;
       for (int i = 0; i < 9; ++i) RI[i] = P(I3[i]);
+      count_decision<T>(COST_AABB);
       P phi = g_box<P>(cp, r, bc, RI, &bx[3], nP, pP);
       if (val(phi) < margin) {
         Contact<T> ct;
@@ -692,6 +704,7 @@ template <class T> void substep(const SceneC& c, const or_params& pr, StateS<T>&
     for (int x = 0; x < NA; ++x) {
       V3<T> bc; M3<T> R;
       aux_obb(x, bc, R);
+      count_decision<T>(COST_OBB);
       P phi = g_box<P>(cp, r, val3(bc), valM(R), &c.aux_box[x][3], nP, pP);
       if (val(phi) < margin) {
         Contact<T> ct;
@@ -707,10 +720,12 @@ template <class T> void substep(const SceneC& c, const or_params& pr, StateS<T>&
       const FreeC& fg = c.fr[g];
       P phi;
       if (fg.type == 0) {
+        count_decision<T>(COST_OBB);
         phi = g_box<P>(cp, r, val3(st.fr[g].x), valM(wk.fR[g]), fg.half, nP, pP);
       } else {
         if (is_vertex) continue;                      // box vertices do not test free spheres
         if (is_sphere_owner && g <= self_free) continue;  // sphere pairs counted once
+        count_decision<T>(COST_SPHERE);
         phi = g_sphere<P>(cp, r, val3(st.fr[g].x), fg.half[0], nP, pP);
       }
       if (val(phi) < margin) {
@@ -873,11 +888,18 @@ template <class T> void substep(const SceneC& c, const or_params& pr, StateS<T>&
   std::vector<std::array<T, 3>> lam(NC, {T(0.0), T(0.0), T(0.0)});
   std::vector<T> llam(lims.size(), T(0.0));
   uint64_t act = 0x12345ull;
+  // diagnostics: pre-projection values of the last substep's row updates
+  auto tape_y = [&](int it, int row, int slot, const T& y) {
+    if (!dbg || !dbg->dump_y || isub != n_sub - 1 || row >= dbg->dump_cap) return;
+    dbg->dump_y[(((size_t)s * pr.pgs_iters + it) * dbg->dump_cap + row) * 3 + slot] = val(y);
+  };
+  const int NLm = (int)lims.size();
   for (int it = 0; it < pr.pgs_iters; ++it) {
     for (size_t li = 0; li < lims.size(); ++li) {
       Lim& L = lims[li];
       T r = L.sgn * vA[L.x] + L.bias;
       T y = llam[li] - r / L.W;
+      tape_y(it, (int)li, 0, y);
       bool on = val(y) > 0.0;
       T nl = on ? y : T(0.0);
       T dl = nl - llam[li];
@@ -890,6 +912,7 @@ template <class T> void substep(const SceneC& c, const or_params& pr, StateS<T>&
       if (rw.ok[0]) {
         T r = rowvel(ci, 0) + rw.bias;
         T y = lam[ci][0] - r / rw.W[0];
+        tape_y(it, NLm + ci, 0, y);
         bool on = val(y) > 0.0;
         T nl = on ? y : T(0.0);
         T dl = nl - lam[ci][0];
@@ -901,6 +924,8 @@ template <class T> void substep(const SceneC& c, const or_params& pr, StateS<T>&
         T r1 = rowvel(ci, 1), r2 = rowvel(ci, 2);
         T y1 = lam[ci][1] - r1 / rw.W[1];
         T y2 = lam[ci][2] - r2 / rw.W[2];
+        tape_y(it, NLm + ci, 1, y1);
+        tape_y(it, NLm + ci, 2, y2);
         T lim = pr.mu * lam[ci][0];
         T nn = y1 * y1 + y2 * y2;
         bool proj = val(nn) > val(lim) * val(lim);
@@ -1203,10 +1228,11 @@ int or_step(const or_scene* sc, const or_params* pr, const double* x_in, const d
   return 0;
 }
 
-// The same step evaluated in single precision (every stored intermediate is a
-// float): an estimate of the error floor of any FP32 evaluation of the step.
+// The same step evaluated in IEEE single precision (every operation rounds to
+// float, parameters and literals included; contact decisions as in or_step):
+// an estimate of the error floor of any FP32 evaluation of the step.
 int or_step_f32(const or_scene* sc, const or_params* pr, const double* x_in, const double* u, double* x_out,
-                int threads) {
+                int threads, or_debug* dbg) {
   if (!sc || !pr || !x_in || !u || !x_out) return -1;
   std::vector<ArtModel> robots = load_models(sc);
   Layout L = layout_of(sc);
@@ -1215,13 +1241,13 @@ int or_step_f32(const or_scene* sc, const or_params* pr, const double* x_in, con
   parallel_scenes(S, threads, [&](int s) {
     SceneC c;
     load_scene(sc, robots, s, c);
-    StateS<float> st;
-    gather(sc, L, s, xin.data(), st, [](size_t, double v) { return (float)v; });
-    float us[ND];
-    for (int j = 0; j < ND; ++j) us[j] = (float)u[(size_t)s * ND + j];
+    StateS<f32s> st;
+    gather(sc, L, s, xin.data(), st, [](size_t, double v) { return f32s(v); });
+    f32s us[ND];
+    for (int j = 0; j < ND; ++j) us[j] = f32s(u[(size_t)s * ND + j]);
     uint32_t status = 0;
-    control_step<float>(c, *pr, st, us, status, nullptr, s);
-    scatter(sc, L, s, st, [&](size_t i, float v) { x_out[i] = v; });
+    control_step<f32s>(c, *pr, st, us, status, dbg, s);
+    scatter(sc, L, s, st, [&](size_t i, const f32s& v) { x_out[i] = val(v); });
   });
   return 0;
 }

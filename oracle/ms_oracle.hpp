@@ -94,6 +94,9 @@ typedef struct {
   uint64_t* dump_keys;     // [S][dump_cap]
   double* dump_phi;        // [S][dump_cap]
   double* dump_lambda;     // [S][dump_cap][3] final impulses
+  double* dump_y;          // [S][pgs_iters][dump_cap][3] pre-projection value of every
+                           // Gauss-Seidel row update in the last substep (limit rows
+                           // first, then contacts; normal, tangent 1, tangent 2)
   double* robot_force;     // [S] sum over substeps of robot-owned normal impulses / h
   double* robot_body_force;  // [NF][3] sum over substeps of the force the robot's
                              // contacts exert on each free body (impulse / h)
@@ -112,7 +115,7 @@ int or_step(const or_scene* sc, const or_params* pr, const double* x_in, const d
 
 // The same control step evaluated with float intermediates (FP32 error floor).
 int or_step_f32(const or_scene* sc, const or_params* pr, const double* x_in, const double* u,
-                double* x_out, int threads);
+                double* x_out, int threads, or_debug* dbg);
 
 // Vector-Jacobian product of one control step: given gx_out = dL/dx_out,
 // returns dL/dx_in (gx_in) and dL/du (gu), by reverse-mode differentiation of
