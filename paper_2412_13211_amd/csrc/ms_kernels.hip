@@ -445,21 +445,28 @@ __device__ __forceinline__ void phase_kinematics(const KArgs& a, const Scene& S,
     for (int t = 0; t < 9; ++t) Rw[t] = t % 4 == 0 ? 1.f : 0.f;
     pw[0] = pw[1] = pw[2] = 0.f;
   }
-  // W_i <- W_anc o W_i ; anc <- anc(anc), until every lane reaches the root
-  for (int round = 0; round < 5; ++round) {
-    if (!__ballot(anc >= 0)) break;
-    int src = anc >= 0 ? anc : lane;
+  // W_i <- W_parent o W_i in depth order (round d composes the bodies of
+  // depth d onto their finished parents).  A body's origin is then computed
+  // as R_parent xtp + p_parent, the very operations that place a point of the
+  // parent at the same local position: coincident spheres on adjacent links
+  // (a capsule's end sphere and the next capsule's first) land on the same
+  // world point bit for bit and give one consistent duplicated contact, not
+  // two that differ by rounding and make Gauss-Seidel trade impulse between
+  // them sweep after sweep.  (Composing by pointer jumping takes fewer
+  // rounds but associates the products differently.)
+  const int depth = lane < nb ? __popc(M->anc[lane]) - 1 : -1;
+  for (int d = 1; d < ND; ++d) {
+    if (!__ballot(depth >= d)) break;
+    const int src = (depth == d && anc >= 0) ? anc : lane;
     float Ra[9], pa[3];
     for (int t = 0; t < 9; ++t) Ra[t] = bcast(Rw[t], src);
     for (int t = 0; t < 3; ++t) pa[t] = bcast(pw[t], src);
-    int aa = bcasti(anc, src);
-    if (anc >= 0) {
+    if (depth == d && anc >= 0) {
       float Rn[9];
       mm(Ra, Rw, Rn);
       f3 pn = mv(Ra, mk3(pw[0], pw[1], pw[2]));
       for (int t = 0; t < 9; ++t) Rw[t] = Rn[t];
       pw[0] = pn.x + pa[0]; pw[1] = pn.y + pa[1]; pw[2] = pn.z + pa[2];
-      anc = aa;
     }
   }
   if (lane < nb) {
@@ -1194,6 +1201,21 @@ __device__ __forceinline__ void phase_dynamics(const KArgs& a, const Scene& S, f
     }
     if (lane < ND && lane >= nb)
       for (int i = 0; i < ND; ++i) rb.Minv[i * ND + lane] = 0.f;
+  }
+  wave_sync();
+  // M~^-1 is symmetric, but its columns round independently.  The rows read
+  // it row-wise for W = J M~^-1 J^T and the sweeps column-wise for
+  // w = M~^-1 J^T; with the two triangles averaged both see the same numbers
+  // in the same order, so a robot row's update applies exactly the W its
+  // impulse was computed with (otherwise the mismatch accumulates sweep after
+  // sweep on redundant contact sets, e.g. more robot contacts than DoFs).
+  for (int e = lane; e < ND * ND; e += WAVE) {
+    const int i = e / ND, k = e % ND;
+    if (i < k) {
+      const float m = 0.5f * (rb.Minv[e] + rb.Minv[k * ND + i]);
+      rb.Minv[e] = m;
+      rb.Minv[k * ND + i] = m;
+    }
   }
   wave_sync();
   // unconstrained robot velocity, held in lanes 0..15
