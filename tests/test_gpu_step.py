@@ -3,14 +3,16 @@
 Single control steps are teacher-forced: both sides start from the same
 float32-representable states taken along oracle trajectories.  Bars: position
 error <= 1e-5 m and velocity error <= 1e-4 m/s (rad/s) per step, or, where
-larger, 10x the larger of the deviation of the oracle's own single-precision
-evaluation from its FP64 result and the oracle's change under 1-ulp float32
-input perturbations (contact-rich states amplify rounding: the speculative bias
-scales position rounding by 1/h, Gauss-Seidel on many coupled robot rows
-amplifies it further); 100-step trajectories <= 1e-3 m where the per-substep contact sets
-agree all along and the oracle with float32 rounding noise injected every
-step stays within 1e-3 m of itself (chaos screen).  Contact sets are compared
-per substep through the count and an order-independent sum of mixed keys.
+larger, 4x the deviation of the oracle's own IEEE single-precision evaluation
+from its FP64 result, or 10x the oracle's change under 1-ulp float32 input
+perturbations (contact-rich states amplify rounding: the speculative bias
+scales position rounding by 1/h, a float32 position near 3 m rounds by
+2.4e-7 m, i.e. 1.2e-4 m/s at h = 2 ms); at most 35 % of the scene-steps may
+need the scaled bar.  100-step trajectories <= 1e-3 m where the per-substep
+contact sets agree all along and the oracle with float32 rounding noise
+injected every step stays within 1e-3 m of itself (chaos screen); at least
+half of the scenes must be kept.  Contact sets are compared per substep
+through the count and an order-independent sum of mixed keys.
 """
 import numpy as np
 import pytest
@@ -76,6 +78,7 @@ def test_single_step_parity(name, mk, steps):
     n_match = n_tot = 0
     worst = (0.0, 0.0)
     n_relaxed = 0
+    worst_ratio = 0.0
     for t, x in states.items():
         u = b.controls_for(t)
         xo, d = o.step(x, u, debug=True)
@@ -86,14 +89,15 @@ def test_single_step_parity(name, mk, steps):
         pe, ve = errors(o, b, xo, xg)
         ps, vs = fp32_sensitivity(o, b, x, u)
         pf, vf = errors(o, b, xo, o.step_f32(x, u))
-        tol_p = np.maximum.reduce([np.full_like(ps, POS_TOL), 10 * ps, 10 * pf])
-        tol_v = np.maximum.reduce([np.full_like(vs, VEL_TOL), 10 * vs, 10 * vf])
+        tol_p = np.maximum.reduce([np.full_like(ps, POS_TOL), 10 * ps, 4 * pf])
+        tol_v = np.maximum.reduce([np.full_like(vs, VEL_TOL), 10 * vs, 4 * vf])
         n_match += int(same.sum())
         n_tot += len(same)
         strict = same & (pe <= POS_TOL) & (ve <= VEL_TOL)
         n_relaxed += int((same & ~strict).sum())
         if same.any():
             worst = (max(worst[0], pe[same].max()), max(worst[1], ve[same].max()))
+            worst_ratio = max(worst_ratio, float(np.max(np.maximum(pe / tol_p, ve / tol_v)[same])))
         say(f"  t={t}: contact sets equal in {same.sum()}/{len(same)} scenes; "
             f"max pos err {pe[same].max() if same.any() else 0:.3e} m, vel err {ve[same].max() if same.any() else 0:.3e}; "
             f"within the fixed bars {strict.sum()}")
@@ -104,15 +108,19 @@ def test_single_step_parity(name, mk, steps):
         assert np.all(ve[same] <= tol_v[same]), (t, np.nonzero(ve > tol_v))
     assert n_match >= 0.8 * n_tot, f"contact sets differ in {n_tot - n_match} of {n_tot} scene-steps"
     assert n_relaxed <= 0.35 * n_tot, f"{n_relaxed} of {n_tot} scene-steps needed the conditioning-scaled bar"
-    say(f"  worst over matching scenes: pos {worst[0]:.3e} m, vel {worst[1]:.3e}; conditioning-scaled bar used in "
-        f"{n_relaxed}/{n_tot}")
+    say(f"  summary {name}: contact sets equal in {n_match}/{n_tot} scene-steps; worst pos {worst[0]:.3e} m, "
+        f"vel {worst[1]:.3e}; scaled bar used in {n_relaxed}/{n_tot}; max err/bar {worst_ratio:.3f}")
 
 
-def test_free_run_100_steps_cfg1():
+FREE_RUNS = [("cfg1", lambda: sg.make(1)), ("cfg2", lambda: sg.make(2, 32)), ("cfg5", lambda: sg.make(5, 32))]
+
+
+@pytest.mark.parametrize("name,mk", FREE_RUNS, ids=[c[0] for c in FREE_RUNS])
+def test_free_run_100_steps(name, mk):
     ms = _ms()
-    b = sg.make(1)
+    b = mk()
     o = oracle.Oracle(b)
-    say("[free-run] cfg1 100 control steps")
+    say(f"[free-run] {name} S={b.n_scenes}: 100 control steps")
     mb = ms.MsBatch(b)
     mb.enable_debug(True)
     xo = b.state0.astype(np.float64)
@@ -134,7 +142,9 @@ def test_free_run_100_steps_cfg1():
         f"pos err (kept) max {pe[keep].max() if keep.any() else 0:.3e} m; all scenes max {pe.max():.3e}")
     for i in range(b.n_scenes):
         say(f"    scene {i}: gpu err {pe[i]:.2e} m, noisy-oracle err {pc[i]:.2e} m, contacts equal {same_all[i]}")
-    assert keep.sum() >= 4
+    say(f"  summary {name}: kept {keep.sum()}/{b.n_scenes}; worst kept pos err "
+        f"{pe[keep].max() if keep.any() else 0:.3e} m")
+    assert keep.sum() >= b.n_scenes // 2
     assert np.all(pe[keep] <= 1e-3)
 
 
@@ -350,6 +360,40 @@ def test_contact_cap_overflow_flagged():
     xg = gpu_step(mb, b.state0, np.zeros((1, 16)))
     pe, ve = errors(o, b, xo, xg)
     assert pe.max() <= POS_TOL and ve.max() <= VEL_TOL
+
+
+def test_robot_contact_cap_matches_oracle():
+    """Robot contact cap: an arm lying on the floor with more robot contacts
+    than the cap keeps the first ones in canonical order on both sides (the
+    rest dropped, status bit 8), with the same step."""
+    ms = _ms()
+    b = sg.make(1)
+    o64 = oracle.Oracle(b)
+    x = b.state0.astype(np.float64)
+    for t in range(80):
+        x = o64.step(x, b.controls_for(t))
+    x = x.astype(np.float32).astype(np.float64)
+    u = b.controls_for(80)
+    rcap = 4
+    o = oracle.Oracle(b, robot_contact_cap=rcap)
+    xo, d = o.step(x, u, debug=True)
+    mb = ms.MsBatch(b, robot_contact_cap=rcap)
+    mb.enable_debug(True)
+    xg = gpu_step(mb, x, u)
+    st = mb.status()
+    capped = (d["status"] & ms.MS_ST_ROBOT_OVERFLOW) != 0
+    say(f"[robot cap] cfg1 t=80, cap {rcap}: scenes over the cap {capped.sum()}/{b.n_scenes}")
+    assert capped.sum() >= 4
+    assert np.array_equal(capped, (st & ms.MS_ST_ROBOT_OVERFLOW) != 0)
+    same = same_contacts(d, mb.debug_contacts())
+    pe, ve = errors(o, b, xo, xg)
+    pf, vf = errors(o, b, xo, o.step_f32(x, u))
+    ps, vs = fp32_sensitivity(o, b, x, u)
+    tol_p = np.maximum.reduce([np.full_like(ps, POS_TOL), 10 * ps, 4 * pf])
+    tol_v = np.maximum.reduce([np.full_like(vs, VEL_TOL), 10 * vs, 4 * vf])
+    say(f"  contact sets equal {same.sum()}/{b.n_scenes}; max pos {pe[same].max():.2e} vel {ve[same].max():.2e}")
+    assert same.all()
+    assert np.all(pe <= tol_p) and np.all(ve <= tol_v)
 
 
 def test_invalid_arguments_leave_state_untouched():
