@@ -181,6 +181,20 @@ class SceneBatch:
                 raise ValueError(self.ctrl_kind)
         return out
 
+    def push_goals(self, scenes=None) -> np.ndarray:
+        """Differentiation workload: per scene a seeded goal for its first free
+        body (the pushed box), its start position moved by U[-0.1, 0.1] m in
+        x and y ([len(scenes), 3], float64)."""
+        rows = range(self.n_scenes) if scenes is None else scenes
+        ids = self.scene_ids()
+        fr = split_state(self.state0, self.n_scenes, self.n_free, self.n_aux)["free"]
+        out = np.zeros((len(rows), 3))
+        for r, row in enumerate(rows):
+            g = _rng(self.seed, self.cfg_id, int(ids[row]), 3_000_000)
+            out[r] = fr[int(self.free_off[row]), 0:3]
+            out[r, 0:2] += g.uniform(-0.1, 0.1, 2)
+        return out
+
     def control_sequence(self, n_steps=None, scenes=None) -> np.ndarray:
         n = self.n_steps if n_steps is None else n_steps
         return np.stack([self.controls(t, scenes) for t in range(n)])
