@@ -243,11 +243,47 @@ ms_status ms_set_forward_split(ms_batch* b, int32_t contact_cap);
  * overflowing the smaller one.  Any output may be null. */
 ms_status ms_get_forward_split(ms_batch* b, int32_t* contact_cap, int32_t* n_full, int32_t* n_retry);
 
-/* Time the candidate schedules on the given state / controls (the state is
- * not modified: a copy in tmp_state_dev is stepped) and keep the fastest.
- * Synchronises the stream.  Writes the chosen schedule and its time. */
+/* Forward autotuner (the batched step's launch schedule, Sec. 4.2's many
+ * parallel environments on one device): times every candidate schedule on
+ * the given state / controls (the state is not modified: a copy in
+ * tmp_state_dev is stepped; each candidate runs 2 + reps steps) and keeps the
+ * fastest.  Candidates: the persistent split launch (for each contact cap of
+ * the smaller layout at which its workgroups per CU step up), the persistent
+ * one launch, the graph replay of the persistent step and of one workgroup
+ * per scene; each with and without furniture staged in LDS; persistent forms
+ * with the grid filling every resident slot or one workgroup per CU fewer.
+ * With a cache file set (ms_set_autotune_cache) a cached choice for the same
+ * key is applied without timing, and a new choice is appended.  Synchronises
+ * the stream.  Writes the chosen schedule (its forward split cap: see
+ * ms_get_forward_split) and its time in ms per control step (the cached
+ * time on a cache hit).  On error the previous schedule is kept. */
 ms_status ms_autotune(ms_batch* b, const void* state_dev, const float* controls_dev, void* tmp_state_dev,
                       int32_t reps, void* hip_stream, ms_schedule* chosen, float* ms_per_step);
+
+/* Backward autotuner: times ms_step_backward (record + adjoint) from the
+ * given state / controls / state adjoint (gx_in_dev, gu_dev: outputs it may
+ * overwrite; gx_out_dev must not alias gx_in_dev) for the adjoint's layouts:
+ * one launch in the full layout, or the split launch with each smaller
+ * contact cap at which the workgroups per CU step up (4 or 8 robot
+ * contacts); keeps the fastest (ms_get_backward_split reads it back) and
+ * writes it to split_c / split_r (0 / 0: no split) with its time.  Needs the
+ * tape buffer (MS_E_STATE otherwise).  Cached like ms_autotune. */
+ms_status ms_autotune_backward(ms_batch* b, const void* state_dev, const float* controls_dev,
+                               const void* gx_out_dev, void* gx_in_dev, float* gu_dev, int32_t reps,
+                               void* hip_stream, int32_t* split_c, int32_t* split_r, float* ms_per_step);
+
+/* Autotune cache: a JSON-lines file (one object per tuned configuration:
+ * "key", the choice, "ms_per_step"), read and appended by ms_autotune and
+ * ms_autotune_backward; path null or "" turns caching off (the default).
+ * The key is the device architecture (e.g. gfx950), "fwd" or "bwd", and a
+ * 64-bit hash of the batch description, the scene-content counts, the CU
+ * count, the force-output setting and the library's source version.
+ * Processes sharing one file must not tune at the same time. */
+ms_status ms_set_autotune_cache(ms_batch* b, const char* path);
+/* The cache key of the forward (backward != 0: backward) tuning of this
+ * batch, NUL-terminated into out (n bytes, 128 suffice), and whether the last
+ * tuning took its choice from the cache (from_cache may be null). */
+ms_status ms_autotune_key(const ms_batch* b, int32_t backward, char* out, size_t n, int32_t* from_cache);
 
 /* One control step of every scene: state_out = T(state_in, controls).
  * state_out may alias state_in.  controls_dev: float32 [S][16]. */
@@ -471,6 +507,22 @@ ms_status ms_debug_contacts(const ms_batch* b, uint32_t* out_host);
  * load/store.  Enabled by ms_enable_phase_profile (adds clock reads). */
 ms_status ms_enable_phase_profile(ms_batch* b, int32_t on);
 ms_status ms_phase_cycles(const ms_batch* b, unsigned long long* out_host);
+
+/* Measurement probes: the achievable rates of the device as this library is
+ * built, the second denominators of the step's rooflines next to the
+ * published peaks (8 TB/s HBM, 157.3 TFLOP/s FP32 vector).  Both enqueue one
+ * kernel on hip_stream; the caller times it (e.g. with HIP events).
+ *   ms_probe_copy: a streaming copy of `bytes` (multiple of 16) from src_dev
+ *     to dst_dev (both 16-byte aligned, not overlapping); 2 x bytes of HBM
+ *     traffic when the buffers exceed the on-chip caches.
+ *   ms_probe_fma: `blocks` workgroups of 256 lanes, each lane running eight
+ *     independent FP32 FMA chains of 16 x iters FMAs; out_dev: a device
+ *     scratch of 1024 floats (written only in a case that never occurs);
+ *     *flops (host, may be null) receives the FLOPs the launch executes
+ *     (2 per FMA).
+ * Invalid sizes or alignment return MS_E_INVALID before anything is enqueued. */
+ms_status ms_probe_copy(const void* src_dev, void* dst_dev, size_t bytes, void* hip_stream);
+ms_status ms_probe_fma(void* out_dev, int32_t blocks, int32_t iters, void* hip_stream, double* flops);
 
 /* Message of the last failed call on this thread (empty if none). */
 const char* ms_last_error(void);

@@ -30,11 +30,13 @@ MS_ST_NONFINITE, MS_ST_OVERFLOW, MS_ST_DEGENERATE, MS_ST_ROBOT_OVERFLOW = 1, 2, 
 
 EXPORTS = ["ms_query_sizes", "ms_state_floats", "ms_create_batch", "ms_destroy_batch", "ms_set_schedule",
            "ms_get_schedule", "ms_set_backward_split", "ms_get_backward_split",
-           "ms_set_forward_split", "ms_get_forward_split", "ms_autotune", "ms_step", "ms_step_backward",
+           "ms_set_forward_split", "ms_get_forward_split", "ms_autotune", "ms_autotune_backward",
+           "ms_set_autotune_cache", "ms_autotune_key", "ms_step", "ms_step_backward",
            "ms_step_record", "ms_step_backward_recorded", "ms_get_state", "ms_set_state",
            "ms_scene_status", "ms_set_force_outputs", "ms_reset_robots", "ms_spawn_check", "ms_enable_debug",
            "ms_debug_contacts", "ms_enable_phase_profile", "ms_phase_cycles", "ms_set_task_robot",
-           "ms_set_grip_outputs", "ms_task_begin", "ms_task_update", "ms_task_categorize", "ms_last_error"]
+           "ms_set_grip_outputs", "ms_task_begin", "ms_task_update", "ms_task_categorize", "ms_probe_copy",
+           "ms_probe_fma", "ms_last_error"]
 PHASES = ["drive+kinematics", "contacts", "dynamics", "rows", "levels", "pgs", "integrate", "load/store"]
 
 
@@ -121,6 +123,9 @@ def lib():
             "ms_set_forward_split": [vp, i32],
             "ms_get_forward_split": [vp, vp, vp, vp],
             "ms_autotune": [vp, vp, vp, vp, i32, vp, vp, vp],
+            "ms_autotune_backward": [vp, vp, vp, vp, vp, vp, i32, vp, vp, vp, vp],
+            "ms_set_autotune_cache": [vp, C.c_char_p],
+            "ms_autotune_key": [vp, i32, C.c_char_p, C.c_size_t, vp],
             "ms_step": [vp, vp, vp, vp, vp],
             "ms_step_backward": [vp, vp, vp, vp, vp, vp, vp],
             "ms_step_record": [vp, vp, vp, vp, vp, vp],
@@ -140,6 +145,8 @@ def lib():
             "ms_task_begin": [vp, vp, vp, vp, vp, vp, vp, vp],
             "ms_task_update": [vp, vp, vp, vp, vp, vp, vp, vp],
             "ms_task_categorize": [vp, vp, vp, vp, vp],
+            "ms_probe_copy": [vp, vp, C.c_size_t, vp],
+            "ms_probe_fma": [vp, i32, i32, vp, vp],
         }
         for name, args in sig.items():
             f = getattr(L, name)
@@ -496,6 +503,28 @@ class MsBatch:
                                  C.byref(ms)), "ms_autotune")
         return (s.flags, s.grid), ms.value
 
+    def autotune_backward(self, x, u, gx_out, reps=3, stream=None):
+        """ms_autotune_backward: returns ((split_c, split_r), ms per step)."""
+        gx_in = self.torch.empty_like(x)
+        gu = self.torch.empty_like(u)
+        c, r, ms = C.c_int32(), C.c_int32(), C.c_float()
+        _check(lib().ms_autotune_backward(self.h, _ptr_t(x), _ptr_t(u), _ptr_t(gx_out), _ptr_t(gx_in), _ptr_t(gu),
+                                          reps, _stream(stream), C.byref(c), C.byref(r), C.byref(ms)),
+               "ms_autotune_backward")
+        return (c.value, r.value), ms.value
+
+    def set_autotune_cache(self, path):
+        _check(lib().ms_set_autotune_cache(self.h, None if path is None else str(path).encode()),
+               "ms_set_autotune_cache")
+
+    def autotune_key(self, backward=False):
+        """(cache key, whether the last tuning came from the cache)."""
+        buf = C.create_string_buffer(256)
+        fc = C.c_int32()
+        _check(lib().ms_autotune_key(self.h, 1 if backward else 0, buf, C.c_size_t(256), C.byref(fc)),
+               "ms_autotune_key")
+        return buf.value.decode(), bool(fc.value)
+
     def status(self):
         out = np.zeros(self.S, np.uint32)
         rc = lib().ms_scene_status(self.h, _ptr_np(out))
@@ -547,3 +576,22 @@ class MsBatch:
         return {"q": x[: 16 * S].view(S, 16), "qd": x[16 * S: 32 * S].view(S, 16),
                 "free": x[32 * S: 32 * S + 16 * NF].view(NF, 16),
                 "aux": x[32 * S + 16 * NF: 32 * S + 16 * NF + 4 * NA].view(NA, 4)}
+
+
+def probe_copy(src, dst, stream=None):
+    """Enqueue the streaming-copy probe (ms_probe_copy) from ``src`` to ``dst``
+    (contiguous device tensors of equal byte size, a multiple of 16)."""
+    n = src.numel() * src.element_size()
+    if dst.numel() * dst.element_size() != n:
+        raise MsError("probe_copy: src and dst sizes differ")
+    _check(lib().ms_probe_copy(_ptr_t(src), _ptr_t(dst), C.c_size_t(n), _stream(stream)), "ms_probe_copy")
+
+
+def probe_fma(out, blocks, iters, stream=None):
+    """Enqueue the FP32 FMA-chain probe (ms_probe_fma); ``out`` is a device
+    tensor of at least 1024 floats.  Returns the FLOPs the launch executes."""
+    if out.numel() < 1024:
+        raise MsError("probe_fma: out needs 1024 floats")
+    fl = C.c_double()
+    _check(lib().ms_probe_fma(_ptr_t(out), int(blocks), int(iters), _stream(stream), C.byref(fl)), "ms_probe_fma")
+    return fl.value

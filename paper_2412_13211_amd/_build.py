@@ -8,7 +8,8 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 LIB = os.path.join(HERE, "libms_phys.so")
-SOURCES = [os.path.join(HERE, "csrc", f) for f in ("ms_kernels.hip", "ms_backward.hip", "ms_tasks.hip", "ms_api.hip")]
+SOURCES = [os.path.join(HERE, "csrc", f) for f in ("ms_kernels.hip", "ms_backward.hip", "ms_tasks.hip", "ms_api.hip",
+                                                   "ms_probe.hip")]
 HEADERS = [os.path.join(HERE, "csrc", f) for f in ("ms_internal.h", "ms_pack.h", "ms_adjoint.h", "ms_backward.h", "ms_tasks.h")] + \
     [os.path.join(ROOT, "include", "ms_phys.h")]
 
@@ -28,6 +29,16 @@ FLAGS = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC",
 FILE_FLAGS = {"ms_backward.hip": ["-fno-math-errno", "-freciprocal-math", "-fapprox-func"]}
 
 
+def source_hash() -> str:
+    """Version of the library's sources (part of the autotune cache key)."""
+    import hashlib
+    h = hashlib.sha256()
+    for p in sorted(SOURCES + HEADERS):
+        with open(p, "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()[:16]
+
+
 def build(force: bool = True, verbose: bool = False) -> str:
     import tempfile
     newest = max(os.path.getmtime(p) for p in SOURCES + HEADERS)
@@ -39,7 +50,7 @@ def build(force: bool = True, verbose: bool = False) -> str:
         for src in SOURCES:
             obj = os.path.join(td, os.path.basename(src) + ".o")
             cmd = [HIPCC] + FLAGS + FILE_FLAGS.get(os.path.basename(src), []) + \
-                ["-I", os.path.join(ROOT, "include"), "-c", src, "-o", obj]
+                [f'-DMS_SOURCE_HASH="{source_hash()}"', "-I", os.path.join(ROOT, "include"), "-c", src, "-o", obj]
             if verbose:
                 print(" ".join(cmd), file=sys.stderr)
             procs.append(subprocess.Popen(cmd))

@@ -67,6 +67,11 @@ struct ms_batch {
   // graphs keyed by (x_in, u, x_out)
   std::map<std::tuple<const void*, const void*, void*>, hipGraphExec_t> graphs;
   std::map<std::tuple<const void*, const void*, void*>, hipGraph_t> graph_defs;
+  // autotuner: device architecture (e.g. gfx950), cache file ("" = none),
+  // whether the last ms_autotune / ms_autotune_backward took its choice from it
+  std::string arch;
+  std::string tune_cache;
+  bool fwd_from_cache, bwd_from_cache;
 };
 
 namespace {
@@ -421,6 +426,9 @@ ms_status ms_create_batch(const ms_batch_desc* d, const ms_scene_desc* sc, void*
   for (int i = 0; i < 4; ++i) b->fsplit[i / 2][i % 2] = -1;
   b->fsplit_force = -1;
   b->ev_fork = b->ev_join = nullptr;
+  b->arch = prop.gcnArchName;
+  if (b->arch.find(':') != std::string::npos) b->arch = b->arch.substr(0, b->arch.find(':'));
+  b->fwd_from_cache = b->bwd_from_cache = false;
   if (hipStreamCreateWithFlags(&b->cap_stream, hipStreamNonBlocking) != hipSuccess ||
       hipStreamCreateWithFlags(&b->bwd_stream, hipStreamNonBlocking) != hipSuccess ||
       hipEventCreateWithFlags(&b->ev_fork, hipEventDisableTiming) != hipSuccess ||
@@ -575,6 +583,7 @@ ms_status ms_step(ms_batch* b, const void* x_in, const float* u, void* x_out, vo
   HIP_TRY(hipGraphLaunch(it->second, st));
   return MS_OK;
 }
+
 
 // The forward kernel in record mode: one fused launch per control step (the
 // batch's persistent / staging / culling choices), no state output.
@@ -880,46 +889,288 @@ ms_status ms_debug_contacts(const ms_batch* b, uint32_t* out) {
   return MS_OK;
 }
 
+// ---------------------------------------------------------------- autotuner
+//
+// Forward: the forms (persistent split launch, persistent one launch, graph
+// replay of the persistent step, graph replay of one workgroup per scene),
+// each with and without the furniture staged in LDS, the persistent grid
+// (every resident slot, or one workgroup per CU fewer) and, for the split
+// form, the smaller layout's contact cap at each step of the occupancy it
+// gives.  Backward: the adjoint's smaller layout (none, or each contact cap
+// at a step of its occupancy, with 4 or 8 robot contacts).  Choices are
+// cached per (device architecture, configuration hash) in a JSON-lines file
+// when one is set.
+
+}  // extern "C"
+
+namespace {
+
+#ifndef MS_SOURCE_HASH
+#define MS_SOURCE_HASH "unversioned"
+#endif
+
+uint64_t fnv1a(uint64_t h, const void* p, size_t n) {
+  const unsigned char* c = static_cast<const unsigned char*>(p);
+  for (size_t i = 0; i < n; ++i) h = (h ^ c[i]) * 1099511628211ull;
+  return h;
+}
+
+std::string tune_key(const ms_batch* b, const char* what) {
+  const ms_batch_desc& d = b->desc;
+  const Counts& c = b->cnt;
+  const int iv[] = {d.n_scenes, d.n_substeps, d.pgs_iters, d.control_mode, d.contact_cap, d.robot_contact_cap,
+                    c.S, c.M, c.NF, c.NS, c.NP, c.NA, c.fmax, c.smax, c.pmax, c.amax, c.nsph_max, b->n_cu,
+                    (b->frc_robot != nullptr || b->grip != nullptr) ? 1 : 0};
+  const float fv[] = {d.h, d.mu, d.baumgarte, d.margin};
+  uint64_t h = 1469598103934665603ull;
+  h = fnv1a(h, iv, sizeof iv);
+  h = fnv1a(h, fv, sizeof fv);
+  h = fnv1a(h, MS_SOURCE_HASH, std::strlen(MS_SOURCE_HASH));
+  char buf[128];
+  std::snprintf(buf, sizeof buf, "%s:%s:%016llx", b->arch.c_str(), what, (unsigned long long)h);
+  return buf;
+}
+
+// integer field `name` of a cache line, or false
+bool cache_int(const char* line, const char* name, long& v) {
+  char pat[64];
+  std::snprintf(pat, sizeof pat, "\"%s\": ", name);
+  const char* p = std::strstr(line, pat);
+  if (!p) return false;
+  return std::sscanf(p + std::strlen(pat), "%ld", &v) == 1;
+}
+
+// the last line of the cache file whose key is `key`
+bool cache_lookup(const std::string& path, const std::string& key, std::string& line_out) {
+  FILE* f = std::fopen(path.c_str(), "r");
+  if (!f) return false;
+  const std::string pat = "\"key\": \"" + key + "\"";
+  char line[1024];
+  bool found = false;
+  while (std::fgets(line, sizeof line, f))
+    if (std::strstr(line, pat.c_str())) {
+      line_out = line;
+      found = true;
+    }
+  std::fclose(f);
+  return found;
+}
+
+void cache_append(const std::string& path, const std::string& line) {
+  FILE* f = std::fopen(path.c_str(), "a");
+  if (!f) return;
+  std::fputs(line.c_str(), f);
+  std::fputc('\n', f);
+  std::fclose(f);
+}
+
+float cache_ms(const std::string& line) {
+  const char* p = std::strstr(line.c_str(), "\"ms_per_step\": ");
+  float v = -1.f;
+  if (p) std::sscanf(p + 15, "%f", &v);
+  return v;
+}
+
+// contact caps below `cap` (down to cap / 2) at which the occupancy per CU of
+// the layout steps up: the largest cap of each occupancy above full's
+template <class PerCu>
+std::vector<int> occupancy_steps(int cap, PerCu per_cu) {
+  std::vector<int> out;
+  int last = per_cu(cap);
+  for (int k = cap - 1; k >= std::max(cap / 2, 1); --k) {
+    const int o = per_cu(k);
+    if (o > last) {
+      out.push_back(k);
+      last = o;
+    }
+  }
+  return out;
+}
+
+// time `reps` calls of fn on st after two untimed ones; ms per call or < 0
+template <class F>
+float time_calls(hipStream_t st, int reps, F fn) {
+  hipEvent_t e0, e1;
+  if (hipEventCreate(&e0) != hipSuccess) return -1.f;
+  if (hipEventCreate(&e1) != hipSuccess) {
+    (void)hipEventDestroy(e0);
+    return -1.f;
+  }
+  bool ok = fn() && fn();
+  (void)hipEventRecord(e0, st);
+  for (int r = 0; r < reps && ok; ++r) ok = fn();
+  (void)hipEventRecord(e1, st);
+  float ms = -1.f;
+  if (ok && hipEventSynchronize(e1) == hipSuccess && hipEventElapsedTime(&ms, e0, e1) == hipSuccess) ms /= reps;
+  else ms = -1.f;
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  return ms;
+}
+
+}  // namespace
+
+extern "C" {
+
+ms_status ms_set_autotune_cache(ms_batch* b, const char* path) {
+  if (!b) return fail(MS_E_INVALID, "null batch");
+  b->tune_cache = path ? path : "";
+  return MS_OK;
+}
+
+ms_status ms_autotune_key(const ms_batch* b, int32_t backward, char* out, size_t n, int32_t* from_cache) {
+  if (!b || !out || n == 0) return fail(MS_E_INVALID, "null argument");
+  const std::string k = tune_key(b, backward ? "bwd" : "fwd");
+  if (k.size() + 1 > n) return fail(MS_E_INVALID, "ms_autotune_key: buffer of %zu bytes, %zu needed", n, k.size() + 1);
+  std::memcpy(out, k.c_str(), k.size() + 1);
+  if (from_cache) *from_cache = backward ? b->bwd_from_cache : b->fwd_from_cache;
+  return MS_OK;
+}
+
 ms_status ms_autotune(ms_batch* b, const void* x, const float* u, void* tmp, int32_t reps, void* hip_stream,
                       ms_schedule* chosen, float* ms_per_step) {
   if (!b || !x || !u || !tmp) return fail(MS_E_INVALID, "null argument");
   if (reps <= 0) reps = 5;
   hipStream_t st = static_cast<hipStream_t>(hip_stream);
-  const ms_schedule saved = b->sched;
-  const int base_flags[] = {MS_SCHED_GRAPH | MS_SCHED_CULL, MS_SCHED_GRAPH | MS_SCHED_PERSISTENT | MS_SCHED_CULL,
-                            MS_SCHED_PERSISTENT | MS_SCHED_CULL};
-  const int stage_opts[] = {MS_SCHED_STAGE_STATIC, 0};
-  ms_schedule best = saved;
-  float best_ms = 1e30f;
-  hipEvent_t e0, e1;
-  HIP_TRY(hipEventCreate(&e0));
-  HIP_TRY(hipEventCreate(&e1));
-  size_t bytes = ((size_t)b->cnt.S * 32 + (size_t)b->cnt.NF * 16 + (size_t)b->cnt.NA * 4) * sizeof(float);
-  for (int bf : base_flags)
-    for (int so : stage_opts) {
-      ms_schedule s{bf | so, 0};
-      if (ms_set_schedule(b, &s) != MS_OK) continue;
-      if (hipMemcpyAsync(tmp, x, bytes, hipMemcpyDeviceToDevice, st) != hipSuccess) continue;
-      if (ms_step(b, tmp, u, tmp, st) != MS_OK) continue;  // warm-up (and capture)
-      (void)hipEventRecord(e0, st);
-      bool ok = true;
-      for (int r = 0; r < reps && ok; ++r) ok = ms_step(b, tmp, u, tmp, st) == MS_OK;
-      (void)hipEventRecord(e1, st);
-      if (!ok || hipEventSynchronize(e1) != hipSuccess) continue;
-      float ms = 0.f;
-      (void)hipEventElapsedTime(&ms, e0, e1);
-      ms /= reps;
-      if (ms < best_ms) {
-        best_ms = ms;
-        best = s;
+  const std::string key = tune_key(b, "fwd");
+  b->fwd_from_cache = false;
+  if (!b->tune_cache.empty()) {
+    std::string line;
+    long fl = 0, gr = 0, fs = -1;
+    if (cache_lookup(b->tune_cache, key, line) && cache_int(line.c_str(), "flags", fl) &&
+        cache_int(line.c_str(), "grid", gr) && cache_int(line.c_str(), "fwd_split", fs)) {
+      ms_schedule s{(int32_t)fl, (int32_t)gr};
+      if (ms_set_schedule(b, &s) == MS_OK && ms_set_forward_split(b, (int32_t)fs) == MS_OK) {
+        b->fwd_from_cache = true;
+        if (chosen) *chosen = b->sched;
+        if (ms_per_step) *ms_per_step = cache_ms(line);
+        return MS_OK;
       }
     }
-  (void)hipEventDestroy(e0);
-  (void)hipEventDestroy(e1);
-  ms_status rs = ms_set_schedule(b, best_ms < 1e29f ? &best : &saved);
+  }
+  const ms_schedule saved = b->sched;
+  const int saved_fs = b->fsplit_force;
+  const int P = MS_SCHED_PERSISTENT, G = MS_SCHED_GRAPH, CU = MS_SCHED_CULL;
+  const int forms[] = {P | CU, P | CU | MS_SCHED_FWD_ONE_LAUNCH, G | P | CU, G | CU};
+  const int force = (b->frc_robot != nullptr || b->grip != nullptr) ? 1 : 0;
+  struct Cand { int flags, grid, fsplit; };
+  std::vector<Cand> cands;
+  for (int stage : {(int)MS_SCHED_STAGE_STATIC, 0}) {
+    const int si = stage ? 1 : 0;
+    const size_t full = (size_t)fwd_layout(b, b->desc.contact_cap, si, force).total * sizeof(float);
+    if (full > b->max_lds) continue;
+    for (int form : forms) {
+      const int fl = form | stage;
+      std::vector<int> splits{-1};
+      if (form == (P | CU)) {
+        splits = occupancy_steps(b->desc.contact_cap, [&](int k) {
+          return fwd_per_cu((size_t)fwd_layout(b, k, si, force).total * sizeof(float));
+        });
+        if (splits.empty()) continue;   // no smaller layout: the same as one launch
+      }
+      for (int fs : splits) {
+        std::vector<int> grids{0};
+        if (form & P) {
+          const size_t lds = fs > 0 ? (size_t)fwd_layout(b, fs, si, force).total * sizeof(float) : full;
+          const int per_cu = fwd_per_cu(lds);
+          if (per_cu > 1 && b->n_cu * (per_cu - 1) < b->cnt.S) grids.push_back(b->n_cu * (per_cu - 1));
+        }
+        for (int g : grids) cands.push_back({fl, g, fs});
+      }
+    }
+  }
+  const size_t bytes = ((size_t)b->cnt.S * 32 + (size_t)b->cnt.NF * 16 + (size_t)b->cnt.NA * 4) * sizeof(float);
+  Cand best{saved.flags, saved.grid, saved_fs};
+  float best_ms = 1e30f;
+  for (const Cand& c : cands) {
+    ms_schedule s{c.flags, c.grid};
+    if (ms_set_schedule(b, &s) != MS_OK) continue;
+    if (ms_set_forward_split(b, c.fsplit) != MS_OK) continue;
+    if (hipMemcpyAsync(tmp, x, bytes, hipMemcpyDeviceToDevice, st) != hipSuccess) continue;
+    const float ms = time_calls(st, reps, [&] { return ms_step(b, tmp, u, tmp, st) == MS_OK; });
+    if (ms > 0.f && ms < best_ms) {
+      best_ms = ms;
+      best = c;
+    }
+  }
+  ms_schedule bs{best.flags, best.grid};
+  ms_status rs = ms_set_schedule(b, &bs);
+  if (rs == MS_OK) rs = ms_set_forward_split(b, best.fsplit);
+  if (rs != MS_OK) {
+    (void)ms_set_schedule(b, &saved);
+    (void)ms_set_forward_split(b, saved_fs);
+    return rs;
+  }
   if (chosen) *chosen = b->sched;
   if (ms_per_step) *ms_per_step = best_ms;
-  return rs;
+  if (!b->tune_cache.empty() && best_ms < 1e29f) {
+    char line[512];
+    std::snprintf(line, sizeof line,
+                  "{\"key\": \"%s\", \"flags\": %d, \"grid\": %d, \"fwd_split\": %d, \"ms_per_step\": %.5f, "
+                  "\"candidates\": %zu}",
+                  key.c_str(), best.flags, best.grid, best.fsplit, best_ms, cands.size());
+    cache_append(b->tune_cache, line);
+  }
+  return MS_OK;
+}
+
+ms_status ms_autotune_backward(ms_batch* b, const void* x, const float* u, const void* gx_out, void* gx_in,
+                               float* gu, int32_t reps, void* hip_stream, int32_t* split_c, int32_t* split_r,
+                               float* ms_per_step) {
+  if (!b || !x || !u || !gx_out || !gx_in || !gu) return fail(MS_E_INVALID, "null argument");
+  if (!b->tape) return fail(MS_E_STATE, "ms_autotune_backward: the batch has no tape buffer");
+  if (reps <= 0) reps = 3;
+  hipStream_t st = static_cast<hipStream_t>(hip_stream);
+  const std::string key = tune_key(b, "bwd");
+  b->bwd_from_cache = false;
+  if (!b->tune_cache.empty()) {
+    std::string line;
+    long c = 0, r = 0;
+    if (cache_lookup(b->tune_cache, key, line) && cache_int(line.c_str(), "split_c", c) &&
+        cache_int(line.c_str(), "split_r", r) && ms_set_backward_split(b, (int32_t)c, (int32_t)r) == MS_OK) {
+      b->bwd_from_cache = true;
+      if (split_c) *split_c = b->split_c;
+      if (split_r) *split_r = b->split_r;
+      if (ms_per_step) *ms_per_step = cache_ms(line);
+      return MS_OK;
+    }
+  }
+  const int sc0 = b->split_c, sr0 = b->split_r;
+  const ms_batch_desc* d = &b->desc;
+  std::vector<std::pair<int, int>> cands{{0, 0}};
+  const int rfull = std::max(d->robot_contact_cap, 1);
+  for (int r : {std::min(rfull, 8), std::min(rfull, 4)}) {
+    std::vector<int> ks = occupancy_steps(d->contact_cap + 1, [&](int k) {
+      const int kk = std::min(k, d->contact_cap);
+      return bwd_per_cu((size_t)bwd_ws_wave(d, b->cnt, kk, k > d->contact_cap ? rfull : r).total * sizeof(float));
+    });
+    for (int k : ks)
+      if (std::find(cands.begin(), cands.end(), std::make_pair(k, r)) == cands.end()) cands.push_back({k, r});
+  }
+  std::pair<int, int> best{sc0, sr0};
+  float best_ms = 1e30f;
+  for (auto& c : cands) {
+    if (c.first == 0) b->split_c = b->split_r = 0;
+    else if (ms_set_backward_split(b, c.first, c.second) != MS_OK) continue;
+    const float ms = time_calls(st, reps, [&] { return ms_step_backward(b, x, u, gx_out, gx_in, gu, st) == MS_OK; });
+    if (ms > 0.f && ms < best_ms) {
+      best_ms = ms;
+      best = {b->split_c, b->split_r};
+    }
+  }
+  b->split_c = best.first;
+  b->split_r = best.second;
+  if (split_c) *split_c = b->split_c;
+  if (split_r) *split_r = b->split_r;
+  if (ms_per_step) *ms_per_step = best_ms;
+  if (!b->tune_cache.empty() && best_ms < 1e29f) {
+    char line[512];
+    std::snprintf(line, sizeof line,
+                  "{\"key\": \"%s\", \"split_c\": %d, \"split_r\": %d, \"ms_per_step\": %.5f, \"candidates\": %zu}",
+                  key.c_str(), best.first, best.second, best_ms, cands.size());
+    cache_append(b->tune_cache, line);
+  }
+  return MS_OK;
 }
 
 }  // extern "C"

@@ -48,15 +48,40 @@ def test_set_state_masked_copy():
     assert np.array_equal(x.cpu().numpy(), src)
 
 
-def test_autotune_status_and_errors():
+def test_autotune_status_and_errors(tmp_path):
     import paper_2412_13211_amd as ms
     b = sg.make(2, 256)
     mb = ms.MsBatch(b)
     x = torch.as_tensor(b.state0).cuda()
     u = torch.as_tensor(b.controls(0)).cuda()
+    cache = tmp_path / "tune.jsonl"
+    mb.set_autotune_cache(cache)
     (flags, grid), t = mb.autotune(x, u, reps=2)
-    known = ms.MS_SCHED_PERSISTENT | ms.MS_SCHED_GRAPH | ms.MS_SCHED_STAGE_STATIC | ms.MS_SCHED_CULL
-    assert flags & ~known == 0 and t > 0
+    key, hit = mb.autotune_key()
+    known = ms.MS_SCHED_PERSISTENT | ms.MS_SCHED_GRAPH | ms.MS_SCHED_STAGE_STATIC | ms.MS_SCHED_CULL | \
+        ms.MS_SCHED_FWD_ONE_LAUNCH
+    assert flags & ~known == 0 and t > 0 and grid >= 0
+    assert key.startswith("gfx950:fwd:") and not hit
+    lines = cache.read_text().splitlines()
+    assert len(lines) == 1 and f'"key": "{key}"' in lines[0] and f'"flags": {flags}' in lines[0]
+    # a second batch of the same configuration takes the cached choice without timing
+    mb2 = ms.MsBatch(b)
+    mb2.set_autotune_cache(cache)
+    (flags2, grid2), t2 = mb2.autotune(x, u, reps=2)
+    assert (flags2, grid2) == (flags, grid) and mb2.autotune_key() == (key, True)
+    assert mb2.get_forward_split() == mb.get_forward_split()
+    assert len(cache.read_text().splitlines()) == 1
+    # a different configuration has a different key
+    mb3 = ms.MsBatch(sg.make(2, 128))
+    assert mb3.autotune_key()[0] != key
+    # backward tuning needs the adjoint workspace; with it, a choice and its key
+    with pytest.raises(ms.MsError, match="tape"):
+        mb.autotune_backward(x, u, x.clone())
+    mbb = ms.MsBatch(b, backward=True)
+    mbb.set_autotune_cache(cache)
+    (sc, sr), tb = mbb.autotune_backward(x, u, torch.randn_like(x) * 1e-3, reps=1)
+    assert tb > 0 and (sc, sr) == mbb.get_backward_split()
+    assert mbb.autotune_key(backward=True)[0].startswith("gfx950:bwd:")
     y = mb.step(x, u)
     torch.cuda.synchronize()
     assert np.count_nonzero(mb.status()) == 0
