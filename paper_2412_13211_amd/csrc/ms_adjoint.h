@@ -1,22 +1,34 @@
-// ms_adjoint.h -- reverse-mode adjoint of one control step, one thread per scene.
+// ms_adjoint.h -- adjoint engine of one control step (reverse mode): the
+// per-scene state, workspace layout and primitive reverses shared by the two
+// adjoint kernels of ms_backward.hip.
 //
-// The vector-Jacobian product behind ms_step_backward.  A thread owns one
-// scene: it recomputes the control step in FP32 (same contact rules and
-// canonical row order as the forward kernel; dynamics by CRBA + Cholesky,
-// Gauss-Seidel sequentially in the canonical order, which is the order the
-// level schedule reproduces), recording the pre-projection value of every
-// row update, then walks the substeps backwards:
+// The vector-Jacobian product behind ms_step_backward walks the substeps of
+// a control step backwards:
 //   integrate^T -> Gauss-Seidel^T (velocities reconstructed from the recorded
-//   values) -> rows^T -> bias^T -> dynamics^T -> contacts^T -> kinematics^T -> drive^T.
-// Derivatives of the joint-space mass matrix and bias force with respect to
-// q and qd use forward-mode tangents of CRBA / RNEA, one joint direction at a
-// time; every other derivative is a hand-written reverse of its primitive.
+//   pre-projection values) -> rows^T -> bias^T -> dynamics^T -> contacts^T ->
+//   kinematics^T -> drive^T.
 // Convention at the kinks: max(0, y) has slope 0 at y = 0, a friction disk
 // projection exactly on the boundary counts as inside, contacts appear and
 // disappear only between evaluations (the contact set is held fixed).
 //
-// The code is plain C++ (host and device) so that it runs unchanged on the
-// CPU; all scene-sized arrays live in a per-scene workspace in global memory.
+// Two users:
+//   - the product path, k_step_bwd_wave (ms_backward.hip): one 64-lane
+//     wavefront per scene with its workspace (ws_layout(..., wave = true)) in
+//     LDS.  It reads the record the forward kernel wrote (substep states,
+//     contact lists, Gauss-Seidel tape) and recomputes kinematics, dynamics,
+//     M~^-1 and the rows across the lanes; the per-scene engine Eng below
+//     supplies the record access, the row bookkeeping and the single-lane
+//     pieces (limit rows, free-body and door / drawer sides);
+//   - the reference schedule k_step_bwd (MS_SCHED_BWD_REFERENCE): one thread
+//     per scene runs the whole engine alone, recomputing the step itself
+//     (contacts, CRBA + Cholesky, sequential Gauss-Seidel in the canonical
+//     order the level schedule reproduces), with derivatives of the mass
+//     matrix and bias force by forward-mode tangents of CRBA / RNEA, in a
+//     per-scene workspace in global memory.  It is the independent
+//     cross-check of the wavefront kernel.
+//
+// The code is plain C++ (host and device) so that the engine also runs on
+// the CPU.
 #pragma once
 #include "ms_internal.h"
 
