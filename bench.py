@@ -148,7 +148,8 @@ def load_traffic(name, nscenes, src_hash, flags, graph_bit):
         return None
     if (int(d.get("schedule_flags", -1)) & ~graph_bit) != (int(flags) & ~graph_bit):
         return None
-    return d.get("bytes_per_launch")
+    # per control step (all of the step's launches), like `achieved`
+    return d.get("bytes_per_control_step", d.get("bytes_per_launch"))
 
 
 def time_fwd_bwd(mb, x0, U, args, flags, stream, torch, keep_records=True, grid=0):
@@ -388,6 +389,8 @@ def main():
     ap.add_argument("--schedule", default="auto", help="auto | graph | graph-persistent | persistent | fused | plain")
     ap.add_argument("--tune-cache", default=os.path.join(ROOT, "paper_2412_13211_amd", "autotune_cache.jsonl"),
                     help="autotune cache file (JSON lines; '' for none)")
+    ap.add_argument("--no-graph", action="store_true", help="skip the graph-captured comparison runs")
+    ap.add_argument("--no-peaks", action="store_true", help="skip the copy and FMA-chain probes")
     ap.add_argument("--no-extra", action="store_true",
                     help="skip the other workloads (cfg4 and cfg5 forward+backward, cfg2 at the paper's rate)")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="BYTES",
@@ -491,11 +494,12 @@ def main():
     # the batched graph-captured form: one persistent launch per control step
     # replayed from a hipGraph (with and without furniture staged in LDS)
     graph_forms = {}
-    for gf in (ms.MS_SCHED_GRAPH | ms.MS_SCHED_PERSISTENT | ms.MS_SCHED_CULL,
-               ms.MS_SCHED_GRAPH | ms.MS_SCHED_PERSISTENT | ms.MS_SCHED_CULL | ms.MS_SCHED_STAGE_STATIC):
+    for gf in (() if args.no_graph else
+               (ms.MS_SCHED_GRAPH | ms.MS_SCHED_PERSISTENT | ms.MS_SCHED_CULL,
+                ms.MS_SCHED_GRAPH | ms.MS_SCHED_PERSISTENT | ms.MS_SCHED_CULL | ms.MS_SCHED_STAGE_STATIC)):
         graph_forms[gf] = run(args.steps, gf, True)
-    gflags = min(graph_forms, key=lambda k: graph_forms[k][0])
-    wall_graph, gpu_ms_graph = graph_forms[gflags]
+    gflags = min(graph_forms, key=lambda k: graph_forms[k][0]) if graph_forms else 0
+    wall_graph, gpu_ms_graph = graph_forms[gflags] if graph_forms else (float("nan"), float("nan"))
     print(f"[bench] main form {1e3 * wall / args.steps:.3f} ms, graph-captured {1e3 * wall_graph / args.steps:.3f} ms, "
           f"plain {1e3 * wall_plain / args.steps:.3f} ms", file=sys.stderr, flush=True)
     fwd_bwd = None if args.no_bwd else time_fwd_bwd(mb, x0, U, args, flags, stream, torch, grid=grid)
@@ -503,7 +507,7 @@ def main():
                                                       grid=grid)
     st = mb.status()
     env_out = time_env_outputs(mb, b, x0, U, args, flags, stream, torch, ms, sg)
-    peaks = measured_peaks(ms, torch, stream)
+    peaks = None if args.no_peaks else measured_peaks(ms, torch, stream)
     extra = {}
     if not args.no_extra:
         print("[bench] cfg4 forward+backward", file=sys.stderr, flush=True)
@@ -548,20 +552,21 @@ def main():
                      "flops_model": "oracle op count of one control step (64-scene mean); each emit decision "
                                     "charged its signed-distance cost",
                      "kernel_ms_per_launch": round(launch_ms, 5),
-                     "measured_peak": peaks["fp32_fma_tflops"],
-                     "frac_of_measured_peak": round(achieved_tflops / peaks["fp32_fma_tflops"], 6)},
+                     "measured_peak": peaks and peaks["fp32_fma_tflops"],
+                     "frac_of_measured_peak": peaks and round(achieved_tflops / peaks["fp32_fma_tflops"], 6)},
         "hbm_roofline": {"achieved": round(hbm_gbs, 3), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                          "frac": round(hbm_gbs / HBM_PEAK_GBS, 6), "bytes_per_env_step_batch": bytes_step,
-                         "measured_peak": peaks["hbm_copy_gbs"],
-                         "frac_of_measured_peak": round(hbm_gbs / peaks["hbm_copy_gbs"], 6)},
+                         "measured_peak": peaks and peaks["hbm_copy_gbs"],
+                         "frac_of_measured_peak": peaks and round(hbm_gbs / peaks["hbm_copy_gbs"], 6)},
         "measured_peaks": peaks,
         "plain_per_substep": None if args.no_plain else {
             "value": round(S * args.steps / wall_plain, 1), "unit": "env-steps/s",
             "ms_per_step": round(1e3 * wall_plain / args.steps, 4)},
-        "graph_captured": {"value": round(S * args.steps / wall_graph, 1), "unit": "env-steps/s",
-                           "ms_per_step": round(1e3 * wall_graph / args.steps, 4),
-                           "kernel_ms_per_step": round(gpu_ms_graph / args.steps, 5), "schedule_flags": int(gflags),
-                           "vs_plain_per_substep": None if args.no_plain else round(wall_plain / wall_graph, 3)},
+        "graph_captured": None if args.no_graph else {
+            "value": round(S * args.steps / wall_graph, 1), "unit": "env-steps/s",
+            "ms_per_step": round(1e3 * wall_graph / args.steps, 4),
+            "kernel_ms_per_step": round(gpu_ms_graph / args.steps, 5), "schedule_flags": int(gflags),
+            "vs_plain_per_substep": None if args.no_plain else round(wall_plain / wall_graph, 3)},
         "scene_status_nonzero": int(np.count_nonzero(st)),
     }
     if fwd_bwd is not None:
