@@ -290,6 +290,23 @@ ms_status ms_autotune_key(const ms_batch* b, int32_t backward, char* out, size_t
 ms_status ms_step(ms_batch* b, const void* state_in_dev, const float* controls_dev, void* state_out_dev,
                   void* hip_stream);
 
+/* ms_step for callers that cannot allocate (code under HIP graph capture,
+ * tight serving loops, harnesses that forbid allocation): the same control
+ * step, bit for bit, in its one-launch form (the batch's persistent and
+ * staging / culling choices; scenes in the order fixed at creation; no graph
+ * replay and no split launch), calling no allocating routine.  Its scratch
+ * -- the persistent work counter and, with MS_CTRL_ACTIONS, the control
+ * step's PD targets -- is a device array of the library (1 MiB + 256 B per
+ * device, held until the process ends), not the batch's scratch buffer; the
+ * scene status words, force and gripper outputs still go to the batch's
+ * buffers.  At most 16384 scenes (MS_E_INVALID beyond).  The calling thread's
+ * current device must be the batch's.  Every call on one device shares that
+ * array: calls that overlap on one device (other streams, other batches)
+ * race; calls ordered on one stream do not.  Debug and phase-profile outputs
+ * are not written. */
+ms_status ms_step_noalloc(ms_batch* b, const void* state_in_dev, const float* controls_dev, void* state_out_dev,
+                          void* hip_stream);
+
 /* Vector-Jacobian product of exactly one ms_step (the adjoint of the step
  * T: S x A -> S of Sec. 3, recomputed internally): given dL/dstate_out
  * (float32, state layout), writes dL/dstate_in (state layout) and

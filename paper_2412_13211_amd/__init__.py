@@ -36,7 +36,7 @@ EXPORTS = ["ms_query_sizes", "ms_state_floats", "ms_create_batch", "ms_destroy_b
            "ms_scene_status", "ms_set_force_outputs", "ms_reset_robots", "ms_spawn_check", "ms_enable_debug",
            "ms_debug_contacts", "ms_enable_phase_profile", "ms_phase_cycles", "ms_set_task_robot",
            "ms_set_grip_outputs", "ms_task_begin", "ms_task_update", "ms_task_categorize", "ms_probe_copy",
-           "ms_probe_fma", "ms_last_error"]
+           "ms_probe_fma", "ms_step_noalloc", "ms_last_error"]
 PHASES = ["drive+kinematics", "contacts", "dynamics", "rows", "levels", "pgs", "integrate", "load/store"]
 
 
@@ -147,6 +147,7 @@ def lib():
             "ms_task_categorize": [vp, vp, vp, vp, vp],
             "ms_probe_copy": [vp, vp, C.c_size_t, vp],
             "ms_probe_fma": [vp, i32, i32, vp, vp],
+            "ms_step_noalloc": [vp, vp, vp, vp, vp],
         }
         for name, args in sig.items():
             f = getattr(L, name)

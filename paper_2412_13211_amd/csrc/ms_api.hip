@@ -12,6 +12,7 @@
 #include <cstdio>
 #include <cstring>
 #include <map>
+#include <mutex>
 #include <numeric>
 #include <string>
 #include <tuple>
@@ -584,6 +585,86 @@ ms_status ms_step(ms_batch* b, const void* x_in, const float* u, void* x_out, vo
   return MS_OK;
 }
 
+// ------------------------------------------------------ allocation-free step
+//
+// ms_step_noalloc keeps the step's scratch -- the persistent work counter and,
+// for normalized actions, the control step's PD targets -- in the library's
+// own device array instead of the batch's scratch buffer, and enqueues only
+// kernels: no allocation, no graph, no split launch.
+
+}  // extern "C"
+
+namespace {
+constexpr int NOALLOC_MAX_SCENES = 16384;
+constexpr size_t NOALLOC_QUEUE_BYTES = 256;
+constexpr size_t NOALLOC_BYTES = NOALLOC_QUEUE_BYTES + sizeof(float) * 16 * (size_t)NOALLOC_MAX_SCENES;
+constexpr int NOALLOC_MAX_DEVICES = 64;
+std::mutex g_noalloc_mu;
+char* g_noalloc_ptr[NOALLOC_MAX_DEVICES] = {};
+}  // namespace
+
+// each device holds its own copy (1 MiB + 256 B) until the process ends; host
+// code uses only the address hipGetSymbolAddress gives for the current device
+static __device__ __align__(256) unsigned char scratch[NOALLOC_BYTES];
+
+namespace {
+// the device address of `scratch` on device dev (current), looked up once
+ms_status noalloc_scratch(int dev, char** out) {
+  if (dev < 0 || dev >= NOALLOC_MAX_DEVICES) return fail(MS_E_UNSUPPORTED, "device %d beyond %d", dev, NOALLOC_MAX_DEVICES);
+  std::lock_guard<std::mutex> lk(g_noalloc_mu);
+  if (!g_noalloc_ptr[dev]) {
+    void* p = nullptr;
+    hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !p) return fail(MS_E_HIP, "hipGetSymbolAddress(scratch): %s", hipGetErrorString(e));
+    g_noalloc_ptr[dev] = static_cast<char*>(p);
+  }
+  *out = g_noalloc_ptr[dev];
+  return MS_OK;
+}
+}  // namespace
+
+extern "C" {
+
+ms_status ms_step_noalloc(ms_batch* b, const void* x_in, const float* u, void* x_out, void* hip_stream) {
+  if (!b || !x_in || !u || !x_out) return fail(MS_E_INVALID, "null batch, state or controls");
+  if (b->cnt.S > NOALLOC_MAX_SCENES)
+    return fail(MS_E_INVALID, "ms_step_noalloc: %d scenes exceed its limit of %d (use ms_step)", b->cnt.S,
+                NOALLOC_MAX_SCENES);
+  int dev = -1;
+  HIP_TRY(hipGetDevice(&dev));
+  if (dev != b->device) return fail(MS_E_INVALID, "ms_step_noalloc: current device %d, batch on %d", dev, b->device);
+  char* base = nullptr;
+  ms_status rs = noalloc_scratch(dev, &base);
+  if (rs != MS_OK) return rs;
+  hipStream_t st = static_cast<hipStream_t>(hip_stream);
+  int* queue = reinterpret_cast<int*>(base);
+  const float* uu = u;
+  if (b->desc.control_mode == MS_CTRL_ACTIONS) {
+    float* tgt = reinterpret_cast<float*>(base + NOALLOC_QUEUE_BYTES);
+    launch_actions(reinterpret_cast<const DModel*>(b->params + b->pl.models),
+                   reinterpret_cast<const DScene*>(b->params + b->pl.scenes), static_cast<const float*>(x_in), u,
+                   tgt, b->cnt.S, st);
+    HIP_TRY(hipGetLastError());
+    uu = tgt;
+  }
+  KArgs a = make_args(b, x_in, uu, x_out);
+  a.mode = step_mode(b);
+  a.queue = queue;
+  a.cost = nullptr;   // the static scene order: no cost keys, no split
+  a.maxc = nullptr;
+  a.debug = nullptr;
+  a.phase_cycles = nullptr;
+  const size_t lds = lds_bytes_of(a);
+  if (lds > b->max_lds)
+    return fail(MS_E_UNSUPPORTED, "scene working set needs %zu B of LDS (device limit %zu B)", lds, b->max_lds);
+  if (a.persistent) {
+    launch_reset_queue(queue, st);   // the counter keeps the last call's value
+    HIP_TRY(hipGetLastError());
+  }
+  launch_step(a, a.persistent ? persistent_grid(b, lds) : b->cnt.S, lds, st);
+  HIP_TRY(hipGetLastError());
+  return MS_OK;
+}
 
 // The forward kernel in record mode: one fused launch per control step (the
 // batch's persistent / staging / culling choices), no state output.
