@@ -92,3 +92,59 @@ def test_ballistic_sensitivity_closed_form():
     assert gx[32 + 8] == pytest.approx(20 * 0.005, rel=1e-12)   # dx_N / dv_0 = N h
     assert gx[32 + 0] == pytest.approx(1.0, rel=1e-12)
     assert np.abs(gu).max() == 0.0
+
+
+def test_differentiation_workload_horizon_central_fd():
+    """The differentiation workload's gradient over its whole horizon: two
+    scenes of the 256-scene batch, 50 control steps, loss = squared distance
+    of the pushed box to its seeded goal; the chained VJP against central
+    differences (eps = 1e-4) of the FP64 rollout on sampled torque components
+    whose perturbed rollouts keep every substep's contact and active sets."""
+    b = sg.make(4)
+    pick = [3, 117]
+    sub = b.subset(pick)
+    o = oracle.Oracle(sub)
+    T = b.n_steps
+    U = np.stack([b.controls(t, pick) for t in range(T)]).astype(np.float64)
+    goals = b.push_goals(pick)
+    box = np.array([sub.free_off[s] for s in range(sub.n_scenes)])
+
+    def rollout(Uv):
+        xs, hashes = [sub.state0.astype(np.float64)], []
+        for t in range(T):
+            x, d = o.step(xs[-1], Uv[t], debug=True)
+            xs.append(x)
+            hashes.append((d["key_hash"].copy(), d["act_hash"].copy()))
+        return xs, hashes
+
+    def losses(x):
+        fr = sg.split_state(x, sub.n_scenes, sub.n_free, sub.n_aux)["free"]
+        return ((fr[box, 0:3] - goals) ** 2).sum(axis=1)
+
+    xs, h0 = rollout(U)
+    fr = sg.split_state(xs[-1], sub.n_scenes, sub.n_free, sub.n_aux)["free"]
+    g = np.zeros_like(xs[0])
+    sg.split_state(g, sub.n_scenes, sub.n_free, sub.n_aux)["free"][box, 0:3] = 2 * (fr[box, 0:3] - goals)
+    gU = np.zeros_like(U)
+    for t in range(T - 1, -1, -1):
+        g, gu = o.vjp(xs[t], U[t], g)
+        gU[t] = gu
+    rng = np.random.default_rng(5)
+    eps = 1e-4
+    checked = 0
+    for trial in range(16):
+        s, t, j = int(rng.integers(2)), int(rng.integers(T)), int(rng.integers(15))
+        e = np.zeros_like(U)
+        e[t, s, j] = eps
+        xp, hp = rollout(U + e)
+        xm, hm = rollout(U - e)
+        same = all(np.array_equal(a[k][s], c[k][s]) and np.array_equal(a2[k][s], c[k][s])
+                   for a, a2, c in zip(hp, hm, h0) for k in (0, 1))
+        if not same:
+            continue
+        fd = (losses(xp[-1])[s] - losses(xm[-1])[s]) / (2 * eps)
+        scale = np.abs(gU[:, s]).max()
+        assert abs(gU[t, s, j] - fd) <= 1e-3 * scale, (s, t, j, gU[t, s, j], fd)
+        checked += 1
+    print(f"horizon FD: {checked} of 16 sampled components keep their contact and active sets")
+    assert checked >= 6, checked
