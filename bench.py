@@ -462,13 +462,18 @@ def main():
     grid = 0
     if args.schedule == "auto":
         mb.set_autotune_cache(args.tune_cache or None)
-        (flags, grid), t_auto = mb.autotune(x0, U[0], reps=3)
+        # tune on the state the timed steps start from (after the warm-up)
+        xw = x0.clone()
+        for t in range(min(args.warmup, n_ctrl)):
+            xw = mb.step(xw, U[t])
+        uw = U[min(args.warmup, n_ctrl - 1)]
+        (flags, grid), t_auto = mb.autotune(xw, uw, reps=5)
         key, hit = mb.autotune_key()
         tune = {"key": key, "from_cache": hit, "flags": int(flags), "grid": int(grid),
                 "fwd_split_cap": int(mb.get_forward_split()), "tuned_ms_per_step": round(float(t_auto), 4)}
         if not args.no_bwd:
             g0 = torch.randn_like(x0) * 1e-3
-            (bc, br), t_b = mb.autotune_backward(x0, U[0], g0, reps=2)
+            (bc, br), t_b = mb.autotune_backward(xw, uw, g0, reps=2)
             bkey, bhit = mb.autotune_key(backward=True)
             tune["backward"] = {"key": bkey, "from_cache": bhit, "split_cap": [int(bc), int(br)],
                                 "tuned_ms_per_step": round(float(t_b), 4)}

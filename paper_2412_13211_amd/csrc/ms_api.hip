@@ -158,6 +158,12 @@ const float* control_targets(ms_batch* b, const void* x_in, const float* u, hipS
 }
 int step_mode(const ms_batch* b) { return b->desc.control_mode == MS_CTRL_ACTIONS ? MS_CTRL_PD : b->desc.control_mode; }
 
+// robot contacts of the forward's smaller layout: the batch's cap.  (A lower
+// one saves 192 B of LDS per robot contact, but a scene whose robot contacts
+// jump past it within a step is retried after the join, adding about one
+// scene's step time to the control step.)
+int fwd_split_rcap(const ms_batch* b) { return std::max(b->desc.robot_contact_cap, 1); }
+
 // Enqueue one control step with the current schedule (no graph).
 // the order of a step's scenes: by the cost keys the previous step wrote
 // (a counting sort that also zeroes the work counters), the scenes routed to
@@ -172,7 +178,7 @@ void set_step_order(ms_batch* b, KArgs& a, hipStream_t st, int fit_c) {
   int* ord = reinterpret_cast<int*>(b->scratch + b->sl.fwd_order);
   a.n_over = reinterpret_cast<int*>(b->scratch + b->sl.fwd_nover);
   a.retry = reinterpret_cast<int*>(b->scratch + b->sl.fwd_retry);
-  launch_cost_order(a.cost, a.maxc, b->cnt.S, fit_c, std::max(b->desc.robot_contact_cap, 1), ord,
+  launch_cost_order(a.cost, a.maxc, b->cnt.S, fit_c, fwd_split_rcap(b), ord,
                     const_cast<int*>(a.n_over), a.persistent ? a.queue : nullptr, a.retry, st);
   a.order = ord;
 }
@@ -185,16 +191,19 @@ int fwd_per_cu(size_t lds) {
   return std::min(n, (int)(size_t{163840} / (lds + 1024)));
 }
 
-LdsLayout fwd_layout(const ms_batch* b, int cc, int stage, int force) {
+// rc < 0: the batch's robot contact cap
+LdsLayout fwd_layout(const ms_batch* b, int cc, int stage, int force, int rc = -1) {
   const Counts& c = b->cnt;
-  return make_layout(std::max(c.fmax, 1), c.smax, cc, std::max(b->desc.robot_contact_cap, 1), stage, force,
-                     std::max(c.nsph_max, 1));
+  return make_layout(std::max(c.fmax, 1), c.smax, cc, rc < 0 ? std::max(b->desc.robot_contact_cap, 1) : rc, stage,
+                     force, std::max(c.nsph_max, 1));
 }
 
-// Contact cap of the forward's smaller layout: the largest one (not below
-// half the batch's) that fits more workgroups per CU, 0 for none.  Scenes
-// whose last contact counts leave room under it run in it; a scene that
-// overflows it anyway is stepped again in the full layout.
+
+// Contact cap of the forward's smaller layout: among the caps from 3/4 of the
+// batch's up, the largest one of the highest workgroups-per-CU count above the
+// full layout's, 0 for none.  Scenes whose last contact counts leave room
+// under it run in it; a scene that overflows it anyway is stepped again in
+// the full layout.  (The autotuner also tries the lower caps down to half.)
 int fwd_split_cap(ms_batch* b, int stage, int force) {
   if (b->fsplit_force >= 0) return b->fsplit_force;
   int& v = b->fsplit[stage][force];
@@ -204,11 +213,14 @@ int fwd_split_cap(ms_batch* b, int stage, int force) {
   const size_t full = (size_t)fwd_layout(b, cap, stage, force).total * sizeof(float);
   const int occ = fwd_per_cu(full);
   if (occ <= 0) return v;
-  for (int k = cap - 1; k >= std::max(cap / 2, 1); --k)
-    if (fwd_per_cu((size_t)fwd_layout(b, k, stage, force).total * sizeof(float)) > occ) {
+  int best = occ;
+  for (int k = cap - 1; k >= std::max((3 * cap) / 4, 1); --k) {
+    const int o = fwd_per_cu((size_t)fwd_layout(b, k, stage, force, fwd_split_rcap(b)).total * sizeof(float));
+    if (o > best) {
+      best = o;
       v = k;
-      break;
     }
+  }
   return v;
 }
 
@@ -236,7 +248,8 @@ ms_status launch_fused(ms_batch* b, KArgs& a, size_t lds, hipStream_t st) {
   KArgs big = a, small = a, rt = a;
   big.fit_mode = 2;
   small.fit_mode = 1;
-  small.L = fwd_layout(b, fc, a.stage_static, force);
+  small.L = fwd_layout(b, fc, a.stage_static, force, fwd_split_rcap(b));
+  small.rcap = std::min(a.rcap, small.L.rcap);  // a scene with more robot contacts gives up (status 8) and is retried
   rt.fit_mode = 3;
   const size_t lds_s = lds_bytes_of(small);
   HIP_TRY(hipEventRecord(b->ev_fork, st));
@@ -977,7 +990,9 @@ ms_status ms_debug_contacts(const ms_batch* b, uint32_t* out) {
 // each with and without the furniture staged in LDS, the persistent grid
 // (every resident slot, or one workgroup per CU fewer) and, for the split
 // form, the smaller layout's contact cap at each step of the occupancy it
-// gives.  Backward: the adjoint's smaller layout (none, or each contact cap
+// gives, down to 3/4 of the batch's cap (below it, the scenes whose lists
+// grow over a rollout would crowd the full-layout launch, which a few timed
+// steps from one state do not show).  Backward: the adjoint's smaller layout (none, or each contact cap
 // at a step of its occupancy, with 4 or 8 robot contacts).  Choices are
 // cached per (device architecture, configuration hash) in a JSON-lines file
 // when one is set.
@@ -1052,13 +1067,13 @@ float cache_ms(const std::string& line) {
   return v;
 }
 
-// contact caps below `cap` (down to cap / 2) at which the occupancy per CU of
-// the layout steps up: the largest cap of each occupancy above full's
+// contact caps below `cap` (down to `lowest`) at which the occupancy per CU
+// of the layout steps up: the largest cap of each occupancy above full's
 template <class PerCu>
-std::vector<int> occupancy_steps(int cap, PerCu per_cu) {
+std::vector<int> occupancy_steps(int cap, PerCu per_cu, int lowest) {
   std::vector<int> out;
   int last = per_cu(cap);
-  for (int k = cap - 1; k >= std::max(cap / 2, 1); --k) {
+  for (int k = cap - 1; k >= std::max(lowest, 1); --k) {
     const int o = per_cu(k);
     if (o > last) {
       out.push_back(k);
@@ -1144,15 +1159,18 @@ ms_status ms_autotune(ms_batch* b, const void* x, const float* u, void* tmp, int
       const int fl = form | stage;
       std::vector<int> splits{-1};
       if (form == (P | CU)) {
+        // the full layout's occupancy, then the smaller layout's at each cap
         splits = occupancy_steps(b->desc.contact_cap, [&](int k) {
-          return fwd_per_cu((size_t)fwd_layout(b, k, si, force).total * sizeof(float));
-        });
+          const int rc = k == b->desc.contact_cap ? -1 : fwd_split_rcap(b);
+          return fwd_per_cu((size_t)fwd_layout(b, k, si, force, rc).total * sizeof(float));
+        }, (3 * b->desc.contact_cap) / 4);
         if (splits.empty()) continue;   // no smaller layout: the same as one launch
       }
       for (int fs : splits) {
         std::vector<int> grids{0};
         if (form & P) {
-          const size_t lds = fs > 0 ? (size_t)fwd_layout(b, fs, si, force).total * sizeof(float) : full;
+          const size_t lds = fs > 0 ? (size_t)fwd_layout(b, fs, si, force, fwd_split_rcap(b)).total * sizeof(float)
+                                    : full;
           const int per_cu = fwd_per_cu(lds);
           if (per_cu > 1 && b->n_cu * (per_cu - 1) < b->cnt.S) grids.push_back(b->n_cu * (per_cu - 1));
         }
@@ -1224,7 +1242,7 @@ ms_status ms_autotune_backward(ms_batch* b, const void* x, const float* u, const
     std::vector<int> ks = occupancy_steps(d->contact_cap + 1, [&](int k) {
       const int kk = std::min(k, d->contact_cap);
       return bwd_per_cu((size_t)bwd_ws_wave(d, b->cnt, kk, k > d->contact_cap ? rfull : r).total * sizeof(float));
-    });
+    }, (d->contact_cap + 1) / 2);
     for (int k : ks)
       if (std::find(cands.begin(), cands.end(), std::make_pair(k, r)) == cands.end()) cands.push_back({k, r});
   }

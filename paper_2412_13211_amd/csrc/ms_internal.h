@@ -74,17 +74,19 @@ struct DAux {
 // Offsets (in floats) of the regions of one scene's LDS block.
 struct LdsLayout {
   int fmax, smax, ccap, rcap, owners, ntmax;
-  int robot, sph, fr, aux, stat, plane, own, con, rows, lvl, cand, frc, total;
+  int robot, sph, fr, aux, stat, plane, own, con, rows, dyn, lvl, cand, frc, total;
 };
 
 __host__ __device__ inline int lds_align4(int x) { return (x + 3) & ~3; }
 
-// Robot block (persistent over a substep): q qd tau arm u vst [6*16]; R[16*9]
-// p[16*3] s[16*6]; D uu qdd [3*16]; Minv[16*16].
-constexpr int ROBOT_FLOATS = 6 * ND + ND * 9 + ND * 3 + ND * 6 + ND * 3 + ND * ND;
-// Articulated-body scratch (only inside the dynamics phase, shares the space of
-// the robot contact rows): IA[16*36] pA c U [3*16*6] T S2 [2*16*16] Ia[48] Uc[16*16].
-constexpr int DYN_FLOATS = ND * 36 + 3 * ND * 6 + 3 * ND * ND + 48;
+// Robot block (persistent over a substep): q qd tau arm u [5*16]; R[16*9]
+// p[16*3] s[16*6]; Minv[16*16].
+constexpr int ROBOT_FLOATS = 5 * ND + ND * 9 + ND * 3 + ND * 6 + ND * ND;
+// Articulated-body scratch (only inside the dynamics phase, which runs before
+// the contacts are generated, so it shares the space of the contact list and
+// the robot contact rows): IA[16*36] pA c U [3*16*6] T S2 [2*16*16] Ia[48]
+// Uc[16*16] D uu qdd [3*16].
+constexpr int DYN_FLOATS = ND * 36 + 3 * ND * 6 + 3 * ND * ND + 48 + 3 * ND;
 constexpr int FREE_FLOATS = 37;     // per free body (odd stride: conflict-free LDS banks)
 constexpr int FSTR = FREE_FLOATS;
 constexpr int AUX_FLOATS = 32;      // per aux joint
@@ -110,9 +112,16 @@ __host__ __device__ inline LdsLayout make_layout(int fmax, int smax, int ccap, i
   L.stat = o;  o += lds_align4(L.smax * 6);
   L.plane = o; o += PMAX * 4;
   L.own = o;   o += lds_align4((L.owners + 1) / 2);        // uint16 owner table
-  L.con = o;   o += lds_align4(ccap * CON_FLOATS);
-  L.rows = o;  o += lds_align4(rcap * ROW_FLOATS > DYN_FLOATS ? rcap * ROW_FLOATS : DYN_FLOATS);
-  L.lvl = o;   o += lds_align4(3 * ccap + 4 + (ccap + 1) / 2);  // level, level offsets, robot row per level, order
+  L.con = o;
+  L.dyn = o;
+  L.rows = o + lds_align4(ccap * CON_FLOATS);
+  {
+    const int cr = lds_align4(ccap * CON_FLOATS) + lds_align4(rcap * ROW_FLOATS);
+    o += cr > DYN_FLOATS ? cr : DYN_FLOATS;
+  }
+  // uint16 level offsets and robot row per level [ccap + 2] each, order [ccap]
+  // (each contact's level sits in its record)
+  L.lvl = o;   o += lds_align4((3 * ccap + 4 + 1) / 2);
   L.cand = o;  o += lds_align4(L.ntmax);                       // two uint16 candidate lists
   L.frc = o;   o += force ? lds_align4(fmax * FRC_FLOATS) : 0;  // force-output accumulators
   L.total = o;

@@ -134,13 +134,13 @@ __device__ __forceinline__ void crf(const float* v, const float* f, float* out) 
 
 // ------------------------------------------------------------ LDS views
 struct Robot {
-  float *q, *qd, *tau, *arm, *u, *vst;  // [16] each (vst: unconstrained velocity)
+  float *q, *qd, *tau, *arm, *u;        // [16] each
   float *R, *p, *s;                     // [16][9], [16][3], [16][6]
-  float *D, *uu, *qdd;                  // [16]
   float *Minv;                          // [16][16]
   // articulated-body scratch, valid only inside the dynamics phase (it shares
-  // the LDS of the robot contact rows, which are built afterwards)
+  // the LDS of the contact list and the robot contact rows, built afterwards)
   float *IA, *pA, *cc, *U, *T, *S2, *Ia, *Uc;
+  float *D, *uu, *qdd;                  // [16]
 };
 __device__ __forceinline__ Robot robot_view(float* base, float* dyn) {
   Robot r;
@@ -150,13 +150,9 @@ __device__ __forceinline__ Robot robot_view(float* base, float* dyn) {
   r.tau = o; o += ND;
   r.arm = o; o += ND;
   r.u = o; o += ND;
-  r.vst = o; o += ND;
   r.R = o; o += ND * 9;
   r.p = o; o += ND * 3;
   r.s = o; o += ND * 6;
-  r.D = o; o += ND;
-  r.uu = o; o += ND;
-  r.qdd = o; o += ND;
   r.Minv = o; o += ND * ND;
   o = dyn;
   r.IA = o; o += ND * 36;
@@ -167,6 +163,9 @@ __device__ __forceinline__ Robot robot_view(float* base, float* dyn) {
   r.S2 = o; o += ND * ND;
   r.Ia = o; o += 48;
   r.Uc = o; o += ND * ND;
+  r.D = o; o += ND;
+  r.uu = o; o += ND;
+  r.qdd = o; o += ND;
   return r;
 }
 // free-body fields (structure of arrays, stride fmax)
@@ -1390,10 +1389,12 @@ __device__ __forceinline__ int phase_levels(const KArgs& a, float* L, int NC, in
   const LdsLayout& Y = a.L;
   float* C = L + Y.con;
   const int cc = Y.ccap;
-  int* lvl = reinterpret_cast<int*>(L + Y.lvl);       // [cc] level of contact
-  int* loff = lvl + cc;                               // [cc + 2] level offsets
-  int* rob = loff + cc + 2;                           // [cc + 2] robot row of each level (-1)
-  uint16_t* order = reinterpret_cast<uint16_t*>(rob + cc + 2);  // [cc]
+  // each row's level in its contact record (C_LVL); per level the offset of
+  // its rows in `order` and its robot row (0xffff: none)
+  uint16_t* loff = reinterpret_cast<uint16_t*>(L + Y.lvl);  // [cc + 2]
+  uint16_t* rob = loff + cc + 2;                            // [cc + 2]
+  uint16_t* order = rob + cc + 2;                           // [cc]
+  auto lvl_of = [&](int ci) { return __float_as_int(C[ci * CSTR + C_LVL]); };
   int reg = 0;  // level of node `lane`
   int maxl = 0;
   for (int base = 0; base < NC; base += WAVE) {
@@ -1410,24 +1411,24 @@ __device__ __forceinline__ int phase_levels(const KArgs& a, float* L, int NC, in
       if (lane == k) mylvl = lv;
       maxl = max(maxl, lv);
     }
-    if (base + lane < NC) lvl[base + lane] = mylvl;
+    if (base + lane < NC) C[(base + lane) * CSTR + C_LVL] = __int_as_float(mylvl);
   }
-  for (int e = lane; e <= maxl + 1; e += WAVE) rob[e] = -1;
+  for (int e = lane; e <= maxl + 1; e += WAVE) rob[e] = 0xffff;
   wave_sync();
-  for (int rr = lane; rr < NR; rr += WAVE) rob[lvl[NL + rr]] = NL + rr;
+  for (int rr = lane; rr < NR; rr += WAVE) rob[lvl_of(NL + rr)] = (uint16_t)(NL + rr);
   int pos = 0;
   for (int lv = 1; lv <= maxl; ++lv) {
-    if (lane == 0) loff[lv - 1] = pos;
+    if (lane == 0) loff[lv - 1] = (uint16_t)pos;
     for (int base = 0; base < NC; base += WAVE) {
       int ci = base + lane;
       bool isr = ci >= NL && ci < NL + NR;
-      bool m = ci < NC && !isr && lvl[ci] == lv;
+      bool m = ci < NC && !isr && lvl_of(ci) == lv;
       uint64_t mk = __ballot(m);
       if (m) order[pos + prefix_below(mk)] = (uint16_t)ci;
       pos += __popcll(mk);
     }
   }
-  if (lane == 0) loff[maxl] = pos;
+  if (lane == 0) loff[maxl] = (uint16_t)pos;
   wave_sync();
   return maxl;
 }
@@ -1510,10 +1511,9 @@ __device__ __forceinline__ void phase_pgs(const KArgs& a, const Scene& S, float*
   float* F = L + Y.fr;
   float* A = L + Y.aux;
   const float* Rw = L + Y.rows;
-  const Robot RB = robot_view(L + Y.robot, L + Y.rows);
-  const int* lvl = reinterpret_cast<const int*>(L + Y.lvl);
-  const int* loff = lvl + cc;
-  const int* rob = loff + cc + 2;
+  const Robot RB = robot_view(L + Y.robot, L + Y.dyn);
+  const uint16_t* loff = reinterpret_cast<const uint16_t*>(L + Y.lvl);
+  const uint16_t* rob = loff + cc + 2;
   const uint16_t* order = reinterpret_cast<const uint16_t*>(rob + cc + 2);
   const float mu = a.mu;
   const int j = lane & 15;
@@ -1521,7 +1521,7 @@ __device__ __forceinline__ void phase_pgs(const KArgs& a, const Scene& S, float*
   for (int it = 0; it < a.K; ++it) {
 #pragma unroll 1
     for (int lv = 1; lv <= maxl; ++lv) {
-      const int rc = rob[lv];
+      const int rc = rob[lv] == 0xffff ? -1 : (int)rob[lv];
       const int o0 = loff[lv - 1], o1 = loff[lv];
       if (rc >= 0) {
         // the level's robot row: lanes 0..15 hold the robot joint velocities
@@ -1772,7 +1772,7 @@ __device__ __forceinline__ void run_scene(const KArgs& a, int s, float* L) {
   S.nf = ds.nf; S.ns = ds.ns; S.np = ds.np; S.na = ds.na; S.nfo = ds.nown;
   S.f0 = ds.f0; S.s0 = ds.s0; S.p0 = ds.p0; S.a0 = ds.a0;
   S.hold = a.scenes[s].hold;
-  Robot rb = robot_view(L + a.L.robot, L + a.L.rows);
+  Robot rb = robot_view(L + a.L.robot, L + a.L.dyn);
   const bool prof = a.phase_cycles != nullptr;
   unsigned long long cyc[8] = {0, 0, 0, 0, 0, 0, 0, 0};
   unsigned long long tc = prof ? clock64() : 0;
@@ -1812,6 +1812,11 @@ __device__ __forceinline__ void run_scene(const KArgs& a, int s, float* L) {
     phase_drive(a, S, rb);
     phase_kinematics(a, S, L, rb);
     MS_PHASE(0)
+    // unconstrained dynamics first: it needs only the frames, and its
+    // articulated-body scratch is dead before the contact list is written
+    // into the same LDS
+    phase_dynamics(a, S, L, rb, vR);
+    MS_PHASE(2)
     phase_contacts(a, S, L, rb, NC, NR, NL, status, keysum);
     // a launch in a smaller layout gives up a scene at its first overflowing
     // contact list; everything written so far the retry writes again alike
@@ -1821,8 +1826,6 @@ __device__ __forceinline__ void run_scene(const KArgs& a, int s, float* L) {
     max_nc = max(max_nc, NC - NL);
     max_nr = max(max_nr, NR);
     MS_PHASE(1)
-    phase_dynamics(a, S, L, rb, vR);
-    MS_PHASE(2)
     phase_rows(a, S, L, rb, NC, NR, NL, status);
     MS_PHASE(3)
     int maxl = phase_levels(a, L, NC, NR, NL);
@@ -1948,7 +1951,7 @@ __global__ __launch_bounds__(WAVE) void k_spawn_check(KArgs a, uint8_t* collide)
   S.f0 = ds.f0; S.s0 = ds.s0; S.p0 = ds.p0; S.a0 = ds.a0;
   S.hold = a.scenes[s].hold;
   float* L = lds;
-  Robot rb = robot_view(L + a.L.robot, L + a.L.rows);
+  Robot rb = robot_view(L + a.L.robot, L + a.L.dyn);
   load_scene(a, S, L, rb);
   phase_kinematics(a, S, L, rb);
   const LdsLayout& Y = a.L;

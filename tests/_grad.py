@@ -2,13 +2,15 @@
 oracle's adjoint restricted to where it is locally smooth.
 
 Projected Gauss-Seidel is piecewise smooth: max(0, y), the friction-disk
-projection and contact emission switch at y = 0, on the disk boundary and at
-phi = margin.  Sequential sweeps over redundant contacts (a box lying flat on
+projection, a row's bias (speculative or Baumgarte) and contact emission
+switch at y = 0, on the disk boundary, at phi = 0 and at phi = margin.  Sequential sweeps over redundant contacts (a box lying flat on
 a plane) sit exactly on such switches, where the derivative is undefined and
 FP32 and FP64 may take different sides.  A component of the oracle's adjoint
 counts as smooth when it moves by less than 1e-4 of the scene's gradient
-scale under 1e-7 perturbations of the state (relative and absolute); the
-1e-3 relative bar applies to those components.
+scale under each of 8 random 1e-7 perturbations of the state (relative and
+absolute); the 1e-3 relative bar applies to those components.  (Where kinks
+are dense, three perturbations left components in the mask that jump by
+several times the smooth part's norm under a fourth.)
 """
 import numpy as np
 
@@ -29,7 +31,7 @@ def scene_vectors(b, gx, gu):
     return out
 
 
-def oracle_vjp_smooth(o, b, x, u, g, trials=3, eps=1e-7, seed=1):
+def oracle_vjp_smooth(o, b, x, u, g, trials=8, eps=1e-7, seed=1):
     """Oracle VJP per scene and a mask of its locally smooth components."""
     rng = np.random.default_rng(seed)
     x = np.asarray(x, np.float64)
@@ -48,6 +50,8 @@ def oracle_vjp_smooth(o, b, x, u, g, trials=3, eps=1e-7, seed=1):
 
 
 def compare(ref, mask, scale, mine):
-    """Per scene: ||g - g*||_2 over the smooth components / max(||g*||_2, 1e-8)."""
-    return np.array([np.linalg.norm((mine[s] - ref[s])[mask[s]]) / max(np.linalg.norm(ref[s]), 1e-8)
+    """Per scene: ||g - g*||_2 / max(||g*||_2, 1e-8), both norms over the
+    smooth components only (a large non-smooth component must not dilute the
+    error of the others)."""
+    return np.array([np.linalg.norm((mine[s] - ref[s])[mask[s]]) / max(np.linalg.norm(ref[s][mask[s]]), 1e-8)
                      for s in range(len(ref))])

@@ -16,6 +16,7 @@ import scenegen as sg
 
 AUX_SLOTS = 4
 CON_FLOATS = 17
+PHI_FIELD = 14   # the entry's gap (signed distance; a limit row's distance to its limit)
 
 
 def layout(batch):
@@ -48,6 +49,12 @@ def counts(L, rec_scene, k):
     return int(h[0]), int(h[1]), int(h[2])
 
 
+def gaps(L, rec_scene, k, n):
+    """Gap of each of the first n list entries of substep k (float64)."""
+    o = L["con"] + k * L["cstride"] + 4
+    return np.asarray(rec_scene[o:o + n * CON_FLOATS], np.float64).reshape(n, CON_FLOATS)[:, PHI_FIELD]
+
+
 def tape(batch, L, rec_scene, k, n):
     """Pre-projection values [pgs_iters][n][3] of substep k."""
     o = L["tape"] + k * batch.pgs_iters * L["tsw"]
@@ -57,7 +64,9 @@ def tape(batch, L, rec_scene, k, n):
 
 def decisions(y, mu):
     """Branch taken at every row update: the normal clamp (y_n > 0) and the
-    friction-disk projection (|y_t| > mu max(0, y_n)).  y: [K][n][3]."""
+    friction-disk projection (|y_t| > mu max(0, y_n)).  y: [K][n][3].
+    (The third branch of a row, the bias of a gap (speculative for a gap
+    >= 0, Baumgarte for a penetration), is the sign of `gaps`.)"""
     yn = y[..., 0]
     lim = mu * np.maximum(yn, 0.0)
     return yn > 0.0, y[..., 1] ** 2 + y[..., 2] ** 2 > lim ** 2

@@ -229,10 +229,15 @@ def test_forward_split_bitwise_equal(extra):
     cnt_mb.set_schedule(ms.MS_SCHED_CULL)
     cnt_mb.enable_debug(True)
     _split_outputs(cnt_mb, ms, x, u, False)
-    nmax = cnt_mb.debug_contacts()[:, :, 0].max(axis=1).astype(int)
+    dbg = cnt_mb.debug_contacts()
+    nmax = dbg[:, :, 0].max(axis=1).astype(int)
+    rmax = dbg[:, :, 1].max(axis=1).astype(int)
     cc = max(int(np.median(nmax)), 9)
-    say(f"[forward split, {extra}] automatic cap {auto}, forced cap {cc}; scenes above it {(nmax > cc).sum()}")
-    assert auto > 0 and (nmax > cc).any() and (nmax + 8 <= cc).any()
+    rc = b.robot_contact_cap           # robot contacts of the smaller layout
+    over = (nmax > cc) | (rmax > rc)                # overflow the smaller layout
+    routed = (nmax + 8 > cc) | (rmax + 2 > rc)      # sent to the full layout by last step's counts
+    say(f"[forward split, {extra}] automatic cap {auto}, forced cap {cc}; scenes above it {over.sum()}")
+    assert auto > 0 and over.any() and (~routed).any()
     mb = ms.MsBatch(b, backward=extra == "record")
     mb.set_schedule(flags)
     if extra == "forces":
@@ -244,12 +249,12 @@ def test_forward_split_bitwise_equal(extra):
     got = _split_outputs(mb, ms, x, u, extra == "record")
     cap, n_full, n_retry = mb.get_forward_split(counts=True)
     say(f"   first step: {n_full} scenes in the full layout, {n_retry} stepped again")
-    assert cap == cc and n_full == 0 and n_retry == (int((nmax > cc).sum()) if split else 0)
+    assert cap == cc and n_full == 0 and n_retry == (int(over.sum()) if split else 0)
     assert _same(got, ref)
     got = _split_outputs(mb, ms, x, u, extra == "record")
     cap, n_full, n_retry = mb.get_forward_split(counts=True)
     say(f"   second step: {n_full} scenes in the full layout, {n_retry} stepped again")
-    assert n_full == (int((nmax + 8 > cc).sum()) if split else 0) and n_retry == 0
+    assert n_full == (int(routed.sum()) if split else 0) and n_retry == 0
     assert _same(got, ref)
     # the library's own cap
     mb.set_forward_split(-1)
