@@ -82,11 +82,13 @@ __host__ __device__ inline int lds_align4(int x) { return (x + 3) & ~3; }
 // Robot block (persistent over a substep): q qd tau arm u [5*16]; R[16*9]
 // p[16*3] s[16*6]; Minv[16*16].
 constexpr int ROBOT_FLOATS = 5 * ND + ND * 9 + ND * 3 + ND * 6 + ND * ND;
-// Articulated-body scratch (only inside the dynamics phase, which runs before
-// the contacts are generated, so it shares the space of the contact list and
-// the robot contact rows): IA[16*36] pA c U [3*16*6] T S2 [2*16*16] Ia[48]
-// Uc[16*16] D uu qdd [3*16].
-constexpr int DYN_FLOATS = ND * 36 + 3 * ND * 6 + 3 * ND * ND + 48 + 3 * ND;
+// Dynamics scratch (only inside the dynamics phase, which runs before the
+// contacts are generated, so it shares the space of the contact list and the
+// robot contact rows): per body COM, mass and world inertia about the COM
+// [16*BI_FLOATS], velocity-product accelerations and body forces [2*16*6],
+// M~ [16*16], tau - C [16].
+constexpr int BI_FLOATS = 11;       // odd stride
+constexpr int DYN_FLOATS = ND * BI_FLOATS + 2 * ND * 6 + ND * ND + ND;
 constexpr int FREE_FLOATS = 37;     // per free body (odd stride: conflict-free LDS banks)
 constexpr int FSTR = FREE_FLOATS;
 constexpr int AUX_FLOATS = 32;      // per aux joint

@@ -137,10 +137,12 @@ struct Robot {
   float *q, *qd, *tau, *arm, *u;        // [16] each
   float *R, *p, *s;                     // [16][9], [16][3], [16][6]
   float *Minv;                          // [16][16]
-  // articulated-body scratch, valid only inside the dynamics phase (it shares
-  // the LDS of the contact list and the robot contact rows, built afterwards)
-  float *IA, *pA, *cc, *U, *T, *S2, *Ia, *Uc;
-  float *D, *uu, *qdd;                  // [16]
+  // dynamics scratch, valid only inside the dynamics phase (it shares the
+  // LDS of the contact list and the robot contact rows, built afterwards):
+  // per body COM, mass and world inertia about the COM [16][BI_FLOATS],
+  // velocity-product accelerations and body forces [16][6] each, M~ [16][16],
+  // tau - C [16]
+  float *bI, *cc, *fo, *Mt, *rhs;
 };
 __device__ __forceinline__ Robot robot_view(float* base, float* dyn) {
   Robot r;
@@ -155,17 +157,11 @@ __device__ __forceinline__ Robot robot_view(float* base, float* dyn) {
   r.s = o; o += ND * 6;
   r.Minv = o; o += ND * ND;
   o = dyn;
-  r.IA = o; o += ND * 36;
-  r.pA = o; o += ND * 6;
+  r.bI = o; o += ND * BI_FLOATS;
   r.cc = o; o += ND * 6;
-  r.U = o; o += ND * 6;
-  r.T = o; o += ND * ND;
-  r.S2 = o; o += ND * ND;
-  r.Ia = o; o += 48;
-  r.Uc = o; o += ND * ND;
-  r.D = o; o += ND;
-  r.uu = o; o += ND;
-  r.qdd = o; o += ND;
+  r.fo = o; o += ND * 6;
+  r.Mt = o; o += ND * ND;
+  r.rhs = o; o += ND;
   return r;
 }
 // free-body fields (structure of arrays, stride fmax)
@@ -965,12 +961,15 @@ __device__ __forceinline__ void phase_contacts(const KArgs& a, const Scene& S, f
   wave_sync();
 }
 
-// Articulated-body algorithm (Featherstone 2008, Table 7.1) with world-
-// aligned axes and each body's quantities referred to its own origin p_i (on
-// the joint axis): the transform between a body and its parent is a pure
-// translation, and lever arms stay at link length, which keeps FP32 free of
-// the cancellation that origin-referred inertias of distant links suffer.
-// Also the columns of the inverse of M~ = M + diag(arm).
+// Joint-space dynamics of the robot: M~ = M + diag(arm) by the composite-
+// rigid-body algorithm and the bias forces C(q, qd) by recursive Newton-Euler
+// (Featherstone 2008, Sec. 6.2 and 5.3), then M~^-1 by Gauss-Jordan
+// elimination and qdd = M~^-1 (tau - C).  Axes are world-aligned and each
+// body's quantities are referred to its own origin p_i (on the joint axis):
+// sums over a subtree take every member's inertia, force or motion straight
+// to p_i with lever arms of link length, which keeps FP32 free of the
+// cancellation that origin-referred inertias of distant links suffer, and no
+// tree recursion runs serially over the bodies.
 
 // motion vector m given at point P, expressed at point Q (d = Q - P)
 __device__ __forceinline__ void shift_motion(const float* m, f3 d, float* out) {
@@ -994,220 +993,185 @@ __device__ __forceinline__ void s_at(const Robot& rb, const DModel* M, int k, f3
     for (int t = 0; t < 6; ++t) out[t] = s[t];
   }
 }
+// A rigid (or composite) inertia about a point P: mass m, first moment
+// h = m (c - P) and rotational inertia J about P (symmetric: xx yy zz xy xz
+// yz).  As a spatial matrix [[J, h x], [(h x)^T, m 1]] applied to the motion
+// (w, v): n = J w + h x v, f = m v - h x w.
+struct RI {
+  float m, h[3], J[6];
+};
+__device__ __forceinline__ void ri_apply(const RI& I, const float* mv6, float* out) {
+  const f3 w = mk3(mv6[0], mv6[1], mv6[2]), v = mk3(mv6[3], mv6[4], mv6[5]), h = mk3(I.h[0], I.h[1], I.h[2]);
+  const f3 hv = cross(h, v), hw = cross(h, w);
+  out[0] = I.J[0] * w.x + I.J[3] * w.y + I.J[4] * w.z + hv.x;
+  out[1] = I.J[3] * w.x + I.J[1] * w.y + I.J[5] * w.z + hv.y;
+  out[2] = I.J[4] * w.x + I.J[5] * w.y + I.J[2] * w.z + hv.z;
+  out[3] = I.m * v.x - hw.x;
+  out[4] = I.m * v.y - hw.y;
+  out[5] = I.m * v.z - hw.z;
+}
+// add a body (mass m, COM offset d from P, rotational inertia Jc about its
+// COM) to an inertia about P (parallel axis: J += Jc + m (|d|^2 1 - d d^T))
+__device__ __forceinline__ void ri_add(RI& I, float m, f3 d, const float* Jc) {
+  const float dd = dot(d, d);
+  I.m += m;
+  I.h[0] += m * d.x; I.h[1] += m * d.y; I.h[2] += m * d.z;
+  I.J[0] += Jc[0] + m * (dd - d.x * d.x);
+  I.J[1] += Jc[1] + m * (dd - d.y * d.y);
+  I.J[2] += Jc[2] + m * (dd - d.z * d.z);
+  I.J[3] += Jc[3] - m * d.x * d.y;
+  I.J[4] += Jc[4] - m * d.x * d.z;
+  I.J[5] += Jc[5] - m * d.y * d.z;
+}
 
 __device__ __forceinline__ void phase_dynamics(const KArgs& a, const Scene& S, float* L, const Robot& rb, float& vR) {
   const int lane = lane_id();
   const DModel* M = S.M;
   const int nb = S.nb;
-  // pass 1 (lane per body): twist v_i at p_i = sum over k in anc-or-self(i) of
-  // s_k qd_k; c_i = v_i x (s_i qd_i); rigid inertia at p_i; pA_i = v_i x* I_i v_i
+  // M~ starts as zero, with identity rows and columns past the robot's DoFs
+  for (int e = lane; e < ND * ND; e += WAVE) {
+    const int r = e / ND, c = e % ND;
+    rb.Mt[e] = (r >= nb || c >= nb) && r == c ? 1.f : 0.f;
+  }
+  // pass 1 (lane per body): COM and world inertia about the COM (kept for the
+  // subtree sums); twist v_i = sum over k in anc-or-self(i) of s_k qd_k at
+  // p_i; the velocity-product acceleration c_i = v_i x (s_i qd_i); the
+  // velocity-product force p_i = v_i x* (I_i v_i)
+  RI Ib{0.f, {0.f, 0.f, 0.f}, {0.f, 0.f, 0.f, 0.f, 0.f, 0.f}};
+  float vp[6] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
+  f3 pi = mk3(0.f, 0.f, 0.f);
   if (lane < nb) {
     const int i = lane;
-    const f3 pi = body_p(rb, i);
-    float v[6] = {0, 0, 0, 0, 0, 0};
-    int am = M->anc[i];
+    pi = body_p(rb, i);
+    const float* R = rb.R + i * 9;
+    const f3 d = mv(R, mk3(M->com[i][0], M->com[i][1], M->com[i][2]));
+    const float* ic = M->Ic[i];
+    const float Bb[9] = {ic[0], ic[3], ic[4], ic[3], ic[1], ic[5], ic[4], ic[5], ic[2]};
+    float RB[9];
+    mm(R, Bb, RB);
+    float Jc[6];
+    const int rr[6] = {0, 1, 2, 0, 0, 1}, cc6[6] = {0, 1, 2, 1, 2, 2};
+#pragma unroll
+    for (int t = 0; t < 6; ++t) {
+      const int r = rr[t], q = cc6[t];
+      Jc[t] = RB[r * 3] * R[q * 3] + RB[r * 3 + 1] * R[q * 3 + 1] + RB[r * 3 + 2] * R[q * 3 + 2];
+    }
+    const float m = M->mass[i];
+    ri_add(Ib, m, d, Jc);
+    float* bI = rb.bI + i * BI_FLOATS;
+    bI[0] = pi.x + d.x; bI[1] = pi.y + d.y; bI[2] = pi.z + d.z;
+    bI[3] = m;
+    for (int t = 0; t < 6; ++t) bI[4 + t] = Jc[t];
+    float v[6] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
+    const int am = M->anc[i];
     #pragma unroll 1
-    for (int k = 0; k <= i; ++k)
+    for (int k = 0; k < nb; ++k)
       if ((am >> k) & 1) {
         float sk[6];
         s_at(rb, M, k, pi, sk);
-        float qd = rb.qd[k];
+        const float qd = rb.qd[k];
         for (int t = 0; t < 6; ++t) v[t] += sk[t] * qd;
       }
-    float vJ[6];
-    float qd = rb.qd[i];
+    float vJ[6], Iv[6];
+    const float qd = rb.qd[i];
     for (int t = 0; t < 6; ++t) vJ[t] = rb.s[i * 6 + t] * qd;
     crm(v, vJ, rb.cc + i * 6);
-    const float* R = rb.R + i * 9;
-    float m = M->mass[i];
-    f3 c = mv(R, mk3(M->com[i][0], M->com[i][1], M->com[i][2]));  // COM relative to p_i
-    const float* ic = M->Ic[i];
-    float Ib[9] = {ic[0], ic[3], ic[4], ic[3], ic[1], ic[5], ic[4], ic[5], ic[2]};
-    float RI[9], Icw[9];
-    mm(R, Ib, RI);
-    for (int r = 0; r < 3; ++r)
-      for (int q = 0; q < 3; ++q)
-        Icw[r * 3 + q] = RI[r * 3] * R[q * 3] + RI[r * 3 + 1] * R[q * 3 + 1] + RI[r * 3 + 2] * R[q * 3 + 2];
-    float cc2 = dot(c, c);
-    float* IA = rb.IA + i * 36;
-    float cv[3] = {c.x, c.y, c.z};
-    for (int r = 0; r < 3; ++r)
-      for (int q = 0; q < 3; ++q) IA[r * 6 + q] = Icw[r * 3 + q] - m * cv[r] * cv[q] + (r == q ? m * cc2 : 0.f);
-    float cx[9] = {0.f, -c.z, c.y, c.z, 0.f, -c.x, -c.y, c.x, 0.f};
-    for (int r = 0; r < 3; ++r)
-      for (int q = 0; q < 3; ++q) {
-        IA[r * 6 + 3 + q] = m * cx[r * 3 + q];
-        IA[(3 + r) * 6 + q] = m * cx[q * 3 + r];
-        IA[(3 + r) * 6 + 3 + q] = r == q ? m : 0.f;
-      }
-    float Iv[6];
-    for (int r = 0; r < 6; ++r) {
-      float acc = 0.f;
-      for (int q = 0; q < 6; ++q) acc += IA[r * 6 + q] * v[q];
-      Iv[r] = acc;
-    }
-    crf(v, Iv, rb.pA + i * 6);
+    ri_apply(Ib, v, Iv);
+    crf(v, Iv, vp);
   }
   wave_sync();
-  // pass 2 (inward, serial over bodies): U, D, u at p_i; the articulated
-  // inertia I^a = IA - U U^T / D and bias p^a = pA + I^a c + U u / D are
-  // translated to the parent's origin and added there
-  float* Ia_s = rb.Ia;
-  #pragma unroll 1
-  for (int i = nb - 1; i >= 0; --i) {
-    const float* IA = rb.IA + i * 36;
-    const float* s = rb.s + i * 6;
-    const int par = M->parent[i];
-    // U = IA s and IA c, one row per lane
-    if (lane < 6) {
-      float accU = 0.f, accC = 0.f;
-#pragma unroll
-      for (int q = 0; q < 6; ++q) {
-        float e = IA[lane * 6 + q];
-        accU += e * s[q];
-        accC += e * rb.cc[i * 6 + q];
-      }
-      rb.U[i * 6 + lane] = accU;
-      Ia_s[36 + lane] = accC;
-    }
-    wave_sync();
-    if (lane == 0) {
-      float D = rb.arm[i], uu = rb.tau[i], Uc = 0.f;
-#pragma unroll
-      for (int r = 0; r < 6; ++r) {
-        float Ur = rb.U[i * 6 + r];
-        D += s[r] * Ur;
-        uu -= s[r] * rb.pA[i * 6 + r];
-        Uc += Ur * rb.cc[i * 6 + r];
-      }
-      rb.D[i] = D;
-      rb.uu[i] = uu;
-      if (par >= 0) {
-        float invD = 1.f / D;
-        float pa[6], pq[6];
-#pragma unroll
-        for (int r = 0; r < 6; ++r) {
-          float Ur = rb.U[i * 6 + r];
-          pa[r] = rb.pA[i * 6 + r] + Ia_s[36 + r] - Ur * Uc * invD + Ur * uu * invD;
-        }
-        shift_force(pa, body_p(rb, i) - body_p(rb, par), pq);
-#pragma unroll
-        for (int r = 0; r < 6; ++r) rb.pA[par * 6 + r] += pq[r];
-      }
-    }
-    wave_sync();
-    if (par >= 0) {
-      if (lane < 36) {
-        const float Di = rb.D[i];
-        const int r = lane / 6, q = lane % 6;
-        Ia_s[lane] = IA[lane] - rb.U[i * 6 + r] * rb.U[i * 6 + q] / Di;
-      }
-      wave_sync();
-      if (lane < 36) {
-        // translate a symmetric 6x6 [[A, B], [B^T, C]] from p_i to p_par:
-        // A' = A + Dx B^T - B Dx - Dx C Dx, B' = B + Dx C, C' = C, Dx = [d]x, d = p_i - p_par
-        f3 d = body_p(rb, i) - body_p(rb, par);
-        float Dx[9] = {0.f, -d.z, d.y, d.z, 0.f, -d.x, -d.y, d.x, 0.f};
-        const int r = lane / 6, q = lane % 6;
-        float val = Ia_s[lane];
-        if (r < 3 && q < 3) {
-          for (int k = 0; k < 3; ++k) {
-            val += Dx[r * 3 + k] * Ia_s[q * 6 + 3 + k];   // Dx B^T
-            val -= Ia_s[r * 6 + 3 + k] * Dx[k * 3 + q];   // B Dx
-            float cd = 0.f;
-            for (int l = 0; l < 3; ++l) cd += Ia_s[(3 + k) * 6 + 3 + l] * Dx[l * 3 + q];
-            val -= Dx[r * 3 + k] * cd;                     // Dx C Dx
-          }
-        } else if (r < 3) {
-          for (int k = 0; k < 3; ++k) val += Dx[r * 3 + k] * Ia_s[(3 + k) * 6 + q];
-        } else if (q < 3) {
-          for (int k = 0; k < 3; ++k) val += Dx[q * 3 + k] * Ia_s[(3 + k) * 6 + r];
-        }
-        rb.IA[par * 36 + lane] += val;
-      }
-      wave_sync();
-    }
-  }
-  // tables: T[i][k] = U_i . s_k (k strict ancestor of i, s_k taken to p_i);
-  // S2[i][k] = s_i . U_k / D_k (k strict descendant of i, U_k taken to p_i)
-  #pragma unroll 1
-  for (int e = lane; e < ND * ND; e += WAVE) {
-    int i = e / ND, k = e % ND;
-    float tv = 0.f, sv = 0.f;
-    if (i < nb && k < nb) {
-      f3 pi = body_p(rb, i);
-      if (k < i && ((M->anc[i] >> k) & 1)) {
-        float sk[6];
-        s_at(rb, M, k, pi, sk);
-        for (int t = 0; t < 6; ++t) tv += rb.U[i * 6 + t] * sk[t];
-      }
-      if (k > i && ((M->anc[k] >> i) & 1)) {
-        float Uk[6];
-        shift_force(rb.U + k * 6, body_p(rb, k) - pi, Uk);
-        for (int t = 0; t < 6; ++t) sv += rb.s[i * 6 + t] * Uk[t];
-        sv /= rb.D[k];
-      }
-    }
-    rb.T[e] = tv;
-    rb.S2[e] = sv;
-  }
-  // forward-dynamics right-hand side b_i = u_i - U_i . (a0 + sum_{k in anc-or-self(i)} c_k), at p_i
+  // pass 2 (lane per body): bias acceleration (qdd = 0, gravity as the base's
+  // acceleration -g) a_i = -g + sum over anc-or-self of c_k, taken to p_i;
+  // body force f_i = I_i a_i + p_i; the subtree's composite inertia about p_i
+  RI Ic{0.f, {0.f, 0.f, 0.f}, {0.f, 0.f, 0.f, 0.f, 0.f, 0.f}};
   if (lane < nb) {
     const int i = lane;
-    const f3 pi = body_p(rb, i);
     float acc6[6] = {0.f, 0.f, 0.f, -a.g[0], -a.g[1], -a.g[2]};
-    int am = M->anc[i];
+    const int am = M->anc[i];
     #pragma unroll 1
-    for (int k = 0; k <= i; ++k)
+    for (int k = 0; k < nb; ++k) {
       if ((am >> k) & 1) {
         float ck[6];
         shift_motion(rb.cc + k * 6, pi - body_p(rb, k), ck);
         for (int t = 0; t < 6; ++t) acc6[t] += ck[t];
       }
-    float b = rb.uu[i];
-    for (int t = 0; t < 6; ++t) b -= rb.U[i * 6 + t] * acc6[t];
-    rb.pA[i * 6] = b;  // pA is no longer needed: reuse its first slot for b_i
-  }
-  wave_sync();
-  // lanes 0..nb-1: column j of M~^-1 (force e_j, no velocity, no gravity);
-  // lane 16: the forward dynamics qdd.  Two triangular recurrences over the
-  // tables, kept rolled with the running column in LDS (one column per lane):
-  // a fully unrolled register form costs the kernel half its occupancy.
-  {
-    const bool col = lane < nb;
-    const bool fd = lane == ND;
-    float* uc = rb.Uc;  // [16][16]: u of column j at uc[i * ND + j]
-    if (col) {
-#pragma unroll 1
-      for (int i = nb - 1; i >= 0; --i) {
-        float acc = (i == lane) ? 1.f : 0.f;
-#pragma unroll 4
-        for (int k = i + 1; k < nb; ++k) acc -= rb.S2[i * ND + k] * uc[k * ND + lane];
-        uc[i * ND + lane] = acc;
+      if ((M->anc[k] >> i) & 1) {
+        const float* bk = rb.bI + k * BI_FLOATS;
+        ri_add(Ic, bk[3], mk3(bk[0], bk[1], bk[2]) - pi, bk + 4);
       }
     }
-    if (col || fd) {
-      float* outc = col ? rb.Minv + lane : rb.qdd;
-      const int os = col ? ND : 1;
-#pragma unroll 1
-      for (int i = 0; i < nb; ++i) {
-        float acc = col ? uc[i * ND + lane] : rb.pA[i * 6];
-#pragma unroll 4
-        for (int k = 0; k < i; ++k) acc -= rb.T[i * ND + k] * outc[k * os];
-        outc[i * os] = acc / rb.D[i];
-      }
-      for (int i = nb; i < ND; ++i) outc[i * os] = 0.f;
-    }
-    if (lane < ND && lane >= nb)
-      for (int i = 0; i < ND; ++i) rb.Minv[i * ND + lane] = 0.f;
+    float fi[6];
+    ri_apply(Ib, acc6, fi);
+    for (int t = 0; t < 6; ++t) rb.fo[i * 6 + t] = fi[t] + vp[t];
   }
   wave_sync();
-  // M~^-1 is symmetric, but its columns round independently.  The rows read
-  // it row-wise for W = J M~^-1 J^T and the sweeps column-wise for
-  // w = M~^-1 J^T; with the two triangles averaged both see the same numbers
-  // in the same order, so a robot row's update applies exactly the W its
-  // impulse was computed with (otherwise the mismatch accumulates sweep after
-  // sweep on redundant contact sets, e.g. more robot contacts than DoFs).
+  // pass 3 (lane per body): C_i = s_i . (sum of the subtree's body forces at
+  // p_i); row i of M~: M_ij = s_j . (I^c_i s_i) for j in anc-or-self(i), all
+  // at p_i, plus the armature on the diagonal; the right-hand side tau - C
+  if (lane < nb) {
+    const int i = lane;
+    float F[6] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
+    #pragma unroll 1
+    for (int k = 0; k < nb; ++k)
+      if ((M->anc[k] >> i) & 1) {
+        float fk[6];
+        shift_force(rb.fo + k * 6, body_p(rb, k) - pi, fk);
+        for (int t = 0; t < 6; ++t) F[t] += fk[t];
+      }
+    const float* si = rb.s + i * 6;
+    float C = 0.f, G[6];
+    for (int t = 0; t < 6; ++t) C += si[t] * F[t];
+    rb.rhs[i] = rb.tau[i] - C;
+    ri_apply(Ic, si, G);
+    float Mii = 0.f;
+    for (int t = 0; t < 6; ++t) Mii += si[t] * G[t];
+    rb.Mt[i * ND + i] = Mii + rb.arm[i];
+    const int am = M->anc[i];
+    #pragma unroll 1
+    for (int j = 0; j < i; ++j)
+      if ((am >> j) & 1) {
+        float sj[6];
+        s_at(rb, M, j, pi, sj);
+        float v = 0.f;
+        for (int t = 0; t < 6; ++t) v += sj[t] * G[t];
+        rb.Mt[i * ND + j] = v;
+        rb.Mt[j * ND + i] = v;
+      }
+  }
+  wave_sync();
+  // M~^-1 by Gauss-Jordan elimination without pivoting (M~ is symmetric
+  // positive definite) in registers: lane r < 16 holds row r, the pivot row
+  // is read from its lane with readlane (the loops are unrolled, so every
+  // register index is a constant); the identity past the robot's DoFs stays
+  if (lane < ND) {
+    float e[ND];
+#pragma unroll
+    for (int k = 0; k < ND; ++k) e[k] = rb.Mt[lane * ND + k];
+#pragma unroll
+    for (int p = 0; p < ND; ++p) {
+      float prow[ND];
+#pragma unroll
+      for (int k = 0; k < ND; ++k) prow[k] = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(e[k]), p));
+      const float inv = 1.f / prow[p];
+      const float f = e[p];
+      const bool own = lane == p;
+#pragma unroll
+      for (int k = 0; k < ND; ++k) {
+        if (k == p) e[k] = own ? inv : -f * inv;
+        else e[k] = own ? prow[k] * inv : e[k] - f * (prow[k] * inv);
+      }
+    }
+#pragma unroll
+    for (int k = 0; k < ND; ++k) rb.Minv[lane * ND + k] = lane < nb && k < nb ? e[k] : 0.f;
+  }
+  wave_sync();
+  // M~^-1 is symmetric, but the elimination rounds its two triangles
+  // differently.  The rows read it row-wise for W = J M~^-1 J^T and the sweeps
+  // column-wise for w = M~^-1 J^T; with the two triangles averaged both see
+  // the same numbers in the same order, so a robot row's update applies
+  // exactly the W its impulse was computed with (otherwise the mismatch
+  // accumulates sweep after sweep on redundant contact sets, e.g. more robot
+  // contacts than DoFs).
   for (int e = lane; e < ND * ND; e += WAVE) {
     const int i = e / ND, k = e % ND;
     if (i < k) {
@@ -1217,9 +1181,14 @@ __device__ __forceinline__ void phase_dynamics(const KArgs& a, const Scene& S, f
     }
   }
   wave_sync();
-  // unconstrained robot velocity, held in lanes 0..15
+  // unconstrained robot velocity qd + h M~^-1 (tau - C), held in lanes 0..15
   vR = 0.f;
-  if (lane < ND) vR = lane < nb ? rb.qd[lane] + a.h * rb.qdd[lane] : rb.qd[lane];
+  if (lane < ND) {
+    float qdd = 0.f;
+    if (lane < nb)
+      for (int k = 0; k < nb; ++k) qdd += rb.Minv[lane * ND + k] * rb.rhs[k];
+    vR = rb.qd[lane] + a.h * qdd;
+  }
   // free bodies: v* = v + h g ; w* = w - h Iw^-1 (w x Iw w)
   float* F = L + a.L.fr;
   const int fm = a.L.fmax;
