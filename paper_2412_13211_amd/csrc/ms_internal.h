@@ -121,9 +121,9 @@ __host__ __device__ inline LdsLayout make_layout(int fmax, int smax, int ccap, i
     const int cr = lds_align4(ccap * CON_FLOATS) + lds_align4(rcap * ROW_FLOATS);
     o += cr > DYN_FLOATS ? cr : DYN_FLOATS;
   }
-  // uint16 level offsets and robot row per level [ccap + 2] each, order [ccap]
-  // (each contact's level sits in its record)
-  L.lvl = o;   o += lds_align4((3 * ccap + 4 + 1) / 2);
+  // uint16 level offsets and robot row per level [ccap + 2] each, order and
+  // level of each row [ccap] each
+  L.lvl = o;   o += lds_align4((4 * ccap + 4 + 1) / 2);
   L.cand = o;  o += lds_align4(L.ntmax);                       // two uint16 candidate lists
   L.frc = o;   o += force ? lds_align4(fmax * FRC_FLOATS) : 0;  // force-output accumulators
   L.total = o;

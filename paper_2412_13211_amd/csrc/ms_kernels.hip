@@ -85,6 +85,13 @@ __device__ __forceinline__ void onb(f3 n, f3& t1, f3& t2) {
   t1 = {1.f + sg * n.x * n.x * a, sg * b, -sg * n.x};
   t2 = {b, sg + n.y * n.y * a, -n.y};
 }
+// the same basis from a precomputed a = -1 / (sign(n.z) + n.z) (bit for bit)
+__device__ __forceinline__ void onb_a(f3 n, float a, f3& t1, f3& t2) {
+  float sg = copysignf(1.f, n.z);
+  float b = n.x * n.y * a;
+  t1 = {1.f + sg * n.x * n.x * a, sg * b, -sg * n.x};
+  t2 = {b, sg + n.y * n.y * a, -n.y};
+}
 __device__ __forceinline__ uint64_t mix64(uint64_t z) {
   z += 0x9E3779B97F4A7C15ull;
   z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
@@ -178,7 +185,11 @@ enum AF {
 // contact fields (structure of arrays, stride ccap)
 // C_KEY: owner sphere index or box vertex (bits 0..7), target class (8..9),
 // target index (10..31)
-enum CF { C_INFO = 0, C_N = 1, C_P = 4, C_IW = 7, C_BIAS = 10, C_LAM = 11, C_PHI = 14, C_LVL = 15, C_KEY = 16 };
+// From the rows phase on, the gap and key slots (dead by then: the gap is in
+// the bias, the key in the record) hold the tangent basis factor C_ONB (see
+// onb_a) and the normal-tangent couplings C_WTN = (t1, t2) . K n of the
+// contact's two sides (K: inverse inertia at the contact point).
+enum CF { C_INFO = 0, C_N = 1, C_P = 4, C_IW = 7, C_BIAS = 10, C_LAM = 11, C_PHI = 14, C_KEY = 16, C_ONB = 14, C_WTN = 15 };
 
 // side kinds packed in a contact's info word: A in bits 0..15, B in 16..31,
 // each (kind << 8) | index
@@ -1272,9 +1283,10 @@ __device__ __forceinline__ void phase_rows(const KArgs& a, const Scene& S, float
     }
     f3 n = mk3(C[(ci) * CSTR + C_N + 0], C[(ci) * CSTR + C_N + 1], C[(ci) * CSTR + C_N + 2]);
     f3 p = mk3(C[(ci) * CSTR + C_P + 0], C[(ci) * CSTR + C_P + 1], C[(ci) * CSTR + C_P + 2]);
+    const float ta = -1.f / (copysignf(1.f, n.z) + n.z);
     f3 t1, t2;
-    onb(n, t1, t2);
-    float W0 = 0.f, W1 = 0.f, W2 = 0.f;
+    onb_a(n, ta, t1, t2);
+    float W0 = 0.f, W1 = 0.f, W2 = 0.f, W1n = 0.f, W2n = 0.f;
 #pragma unroll
     for (int sd = 0; sd < 2; ++sd) {
       int sv = sd == 0 ? sA : sB;
@@ -1286,9 +1298,12 @@ __device__ __forceinline__ void phase_rows(const KArgs& a, const Scene& S, float
         for (int t = 0; t < 6; ++t) Ii[t] = F[(idx) * FSTR + F_II + t];
         float im = F[(idx) * FSTR + F_IM];
         f3 r0 = cross(r, n), r1 = cross(r, t1), r2 = cross(r, t2);
-        W0 += im + dot(r0, smv(Ii, r0));
+        const f3 k0 = smv(Ii, r0);
+        W0 += im + dot(r0, k0);
         W1 += im + dot(r1, smv(Ii, r1));
         W2 += im + dot(r2, smv(Ii, r2));
+        W1n += dot(r1, k0);
+        W2n += dot(r2, k0);
       } else if (k == K_AUX) {
         f3 col = aux_col(A, idx, p);
         float im = A[A_IM * AMAX + idx];
@@ -1296,12 +1311,17 @@ __device__ __forceinline__ void phase_rows(const KArgs& a, const Scene& S, float
         W0 += J0 * J0 * im;
         W1 += J1 * J1 * im;
         W2 += J2 * J2 * im;
+        W1n += J1 * J0 * im;
+        W2n += J2 * J0 * im;
       }
     }
     C[(ci) * CSTR + C_IW + 0] = W0;
     C[(ci) * CSTR + C_IW + 1] = W1;
     C[(ci) * CSTR + C_IW + 2] = W2;
     C[(ci) * CSTR + C_BIAS] = bias;
+    C[(ci) * CSTR + C_ONB] = ta;
+    C[(ci) * CSTR + C_WTN + 0] = W1n;
+    C[(ci) * CSTR + C_WTN + 1] = W2n;
     for (int t = 0; t < 3; ++t) C[(ci) * CSTR + C_LAM + t] = 0.f;
   }
   wave_sync();
@@ -1318,7 +1338,7 @@ __device__ __forceinline__ void phase_rows(const KArgs& a, const Scene& S, float
       f3 n = mk3(C[(ci) * CSTR + C_N + 0], C[(ci) * CSTR + C_N + 1], C[(ci) * CSTR + C_N + 2]);
       f3 p = mk3(C[(ci) * CSTR + C_P + 0], C[(ci) * CSTR + C_P + 1], C[(ci) * CSTR + C_P + 2]);
       f3 t1, t2;
-      onb(n, t1, t2);
+      onb_a(n, C[(ci) * CSTR + C_ONB], t1, t2);
       f3 dir = d == 0 ? n : (d == 1 ? t1 : t2);
       row[d * ND + j] = robot_J(M, rb, S.nb, body, j, dir, p);
     }
@@ -1358,12 +1378,13 @@ __device__ __forceinline__ int phase_levels(const KArgs& a, float* L, int NC, in
   const LdsLayout& Y = a.L;
   float* C = L + Y.con;
   const int cc = Y.ccap;
-  // each row's level in its contact record (C_LVL); per level the offset of
-  // its rows in `order` and its robot row (0xffff: none)
+  // per level the offset of its rows in `order` and its robot row (0xffff:
+  // none); each row's level
   uint16_t* loff = reinterpret_cast<uint16_t*>(L + Y.lvl);  // [cc + 2]
   uint16_t* rob = loff + cc + 2;                            // [cc + 2]
   uint16_t* order = rob + cc + 2;                           // [cc]
-  auto lvl_of = [&](int ci) { return __float_as_int(C[ci * CSTR + C_LVL]); };
+  uint16_t* lvl = order + cc;                               // [cc]
+  auto lvl_of = [&](int ci) { return (int)lvl[ci]; };
   int reg = 0;  // level of node `lane`
   int maxl = 0;
   for (int base = 0; base < NC; base += WAVE) {
@@ -1380,7 +1401,7 @@ __device__ __forceinline__ int phase_levels(const KArgs& a, float* L, int NC, in
       if (lane == k) mylvl = lv;
       maxl = max(maxl, lv);
     }
-    if (base + lane < NC) C[(base + lane) * CSTR + C_LVL] = __int_as_float(mylvl);
+    if (base + lane < NC) lvl[base + lane] = (uint16_t)mylvl;
   }
   for (int e = lane; e <= maxl + 1; e += WAVE) rob[e] = 0xffff;
   wave_sync();
@@ -1461,7 +1482,7 @@ __device__ __forceinline__ void friction_disk(float l1, float l2, float r1, floa
   float nn = y1 * y1 + y2 * y2;
   if (nn > lim * lim) {
     if (lim > 0.f) {
-      float sc = lim / sqrtf(nn);
+      float sc = lim * rsqrtf(nn);
       y1 *= sc;
       y2 *= sc;
     } else {
@@ -1514,7 +1535,7 @@ __device__ __forceinline__ void phase_pgs(const KArgs& a, const Scene& S, float*
           w2 += m * row[2 * ND + k];
         }
         f3 t1, t2;
-        onb(n, t1, t2);
+        onb_a(n, c[C_ONB], t1, t2);
         SideReg B;
         side_load(F, A, (info >> 16) & 0xffff, p, B);
         float dn = lane_val(sum16(lane < ND ? Jn * vR : 0.f), 0);
@@ -1582,29 +1603,33 @@ __device__ __forceinline__ void phase_pgs(const KArgs& a, const Scene& S, float*
         SideReg SA, SB;
         side_load(F, A, sA, p, SA);
         side_load(F, A, sB, p, SB);
-        float r = dot(n, side_vel(SA, p) - side_vel(SB, p)) + bias;
+        const f3 u = side_vel(SA, p) - side_vel(SB, p);
+        float r = dot(n, u) + bias;
         float nl = l0;
         if (iw0 > 0.f) nl = fmaxf(0.f, l0 - r * iw0);
         if (tape) tape[it * a.RL.tsw + ci * 3] = l0 - r * iw0;
         float dl = nl - l0;
-        side_impulse(SA, p, n * dl);
-        side_impulse(SB, p, n * (-dl));
+        f3 P = n * dl;
         if (iw1 > 0.f && iw2 > 0.f) {
+          // the friction pair sees the velocity after the normal update: its
+          // tangential parts are t . u + dl (t . K n), with the couplings
+          // t . K n of the two sides' inverse inertias from the rows phase;
+          // the normal and friction impulses are then applied together
           f3 t1, t2;
-          onb(n, t1, t2);
-          f3 du = side_vel(SA, p) - side_vel(SB, p);
+          onb_a(n, c[C_ONB], t1, t2);
+          const float u1 = dot(t1, u) + dl * c[C_WTN], u2 = dot(t2, u) + dl * c[C_WTN + 1];
           float y1, y2;
-          friction_disk(l1, l2, dot(t1, du), dot(t2, du), iw1, iw2, mu * nl, y1, y2);
+          friction_disk(l1, l2, u1, u2, iw1, iw2, mu * nl, y1, y2);
           if (tape) {
-            tape[it * a.RL.tsw + ci * 3 + 1] = l1 - dot(t1, du) * iw1;
-            tape[it * a.RL.tsw + ci * 3 + 2] = l2 - dot(t2, du) * iw2;
+            tape[it * a.RL.tsw + ci * 3 + 1] = l1 - u1 * iw1;
+            tape[it * a.RL.tsw + ci * 3 + 2] = l2 - u2 * iw2;
           }
-          f3 P = t1 * (y1 - l1) + t2 * (y2 - l2);
-          side_impulse(SA, p, P);
-          side_impulse(SB, p, P * (-1.f));
+          P = P + t1 * (y1 - l1) + t2 * (y2 - l2);
           l1 = y1;
           l2 = y2;
         }
+        side_impulse(SA, p, P);
+        side_impulse(SB, p, P * (-1.f));
         side_store(F, A, SA);
         side_store(F, A, SB);
         c[C_LAM] = nl;
