@@ -74,7 +74,7 @@ struct DAux {
 // Offsets (in floats) of the regions of one scene's LDS block.
 struct LdsLayout {
   int fmax, smax, ccap, rcap, owners, ntmax;
-  int robot, sph, fr, aux, stat, plane, own, con, rows, dyn, lvl, cand, frc, total;
+  int robot, sph, fr, aux, stat, plane, own, con, rows, dyn, cmask, nch, lvl, cand, frc, total;
 };
 
 __host__ __device__ inline int lds_align4(int x) { return (x + 3) & ~3; }
@@ -117,8 +117,14 @@ __host__ __device__ inline LdsLayout make_layout(int fmax, int smax, int ccap, i
   L.con = o;
   L.dyn = o;
   L.rows = o + lds_align4(ccap * CON_FLOATS);
+  // the free bodies' culling masks (per body and 64-target chunk, 64 bits)
+  // live in the robot rows' space: the contact phase fills them before the
+  // rows phase builds the rows
+  L.nch = (L.ntmax + WAVE - 1) / WAVE;
+  L.cmask = L.rows;
   {
-    const int cr = lds_align4(ccap * CON_FLOATS) + lds_align4(rcap * ROW_FLOATS);
+    const int rw = lds_align4(rcap * ROW_FLOATS), mk = lds_align4(fmax * L.nch * 2);
+    const int cr = lds_align4(ccap * CON_FLOATS) + (rw > mk ? rw : mk);
     o += cr > DYN_FLOATS ? cr : DYN_FLOATS;
   }
   // uint16 level offsets and robot row per level [ccap + 2] each, order and

@@ -924,42 +924,111 @@ __device__ __forceinline__ void phase_contacts(const KArgs& a, const Scene& S, f
         }
       }
     }
-    int obase = S.nsph;
-    for (int f = 0; f < S.nf; ++f) {
+    // free bodies.  Bounding-sphere culling, transposed: the lanes hold one
+    // 64-target chunk's bounds (loaded once per substep), the bodies' bounds
+    // come from their lanes by readlane, and one ballot per (body, chunk) goes
+    // to the mask table.  Target bounds: planes exactly; furniture boxes as
+    // their boxes; door / drawer boxes and free bodies as bounding spheres.
+    // Sphere-against-box distances are compared squared (the slack covers the
+    // rounding), so no square root is taken.
+    {
       const float* F = X.F;
       const int fm = X.fm;
-      const bool fbox = F[(f) * FSTR + F_TYPE] == 0.f;
-      const int members = fbox ? 8 : 1;
-      f3 c = mk3(F[(f) * FSTR + F_X + 0], F[(f) * FSTR + F_X + 1], F[(f) * FSTR + F_X + 2]);
-      f3 h = mk3(F[(f) * FSTR + F_H + 0], F[(f) * FSTR + F_H + 1], F[(f) * FSTR + F_H + 2]);
-      const float R = fbox ? sqrtf(dot(h, h)) : h.x;
       const int gbase = S.np + S.ns + S.na;
-      const int nbc = compact(NT, listB, [](int i) { return i; }, [&](int t) {
-        if (t >= gbase) {
-          int g = t - gbase;
-          if (g == f) return false;
-          bool gbox = F[(g) * FSTR + F_TYPE] == 0.f;
-          if (!gbox && fbox) return false;
-          if (!gbox && !fbox && g <= f) return false;
-        }
-        return sphere_near_target(X, c, R, t, slack);
-      });
-      if (nbc > 0) {
-        const int total = members * nbc;
-        const float inv = 1.f / (float)nbc;
-        for (int base = 0; base < total; base += WAVE) {
-          int idx = base + lane;
-          PairOut po;
-          bool isrob = false, hit = false;
-          if (idx < total) {
-            int k, ci;
-            divmod(idx, nbc, inv, k, ci);
-            hit = eval_pair(X, obase + k, listB[ci], po, isrob);
+      uint32_t* msk = reinterpret_cast<uint32_t*>(L + Y.cmask);
+      const int nch = (NT + WAVE - 1) / WAVE;
+      // lane f: body f's bounding sphere
+      f3 fc = mk3(0.f, 0.f, 0.f);
+      float fR = 0.f;
+      int fb = 0;
+      if (lane < S.nf) {
+        fc = mk3(F[(lane) * FSTR + F_X + 0], F[(lane) * FSTR + F_X + 1], F[(lane) * FSTR + F_X + 2]);
+        f3 h = mk3(F[(lane) * FSTR + F_H + 0], F[(lane) * FSTR + F_H + 1], F[(lane) * FSTR + F_H + 2]);
+        fb = F[(lane) * FSTR + F_TYPE] == 0.f ? 1 : 0;
+        fR = fb ? sqrtf(dot(h, h)) : h.x;
+      }
+      for (int ch = 0; ch < nch; ++ch) {
+        const int t = ch * WAVE + lane;
+        // this lane's target: a plane (pn, pd), or a box (ctr, half) grown by rt
+        bool valid = t < NT, isplane = false;
+        f3 ctr = mk3(0.f, 0.f, 0.f), half = mk3(0.f, 0.f, 0.f);
+        float rt = 0.f, pd = 0.f;
+        int g = -1, gbox = 0;
+        if (valid) {
+          if (t < S.np) {
+            isplane = true;
+            ctr = mk3(X.Pl[t * 4], X.Pl[t * 4 + 1], X.Pl[t * 4 + 2]);
+            pd = X.Pl[t * 4 + 3];
+          } else if (t < S.np + S.ns) {
+            const float* bx = X.St + (t - S.np) * 6;
+            ctr = mk3(bx[0], bx[1], bx[2]);
+            half = mk3(bx[3], bx[4], bx[5]);
+          } else if (t < gbase) {
+            const int x = t - S.np - S.ns;
+            ctr = mk3(Ax[(A_BC + 0) * AMAX + x], Ax[(A_BC + 1) * AMAX + x], Ax[(A_BC + 2) * AMAX + x]);
+            f3 h = mk3(Ax[(A_BH + 0) * AMAX + x], Ax[(A_BH + 1) * AMAX + x], Ax[(A_BH + 2) * AMAX + x]);
+            rt = sqrtf(dot(h, h));
+          } else {
+            g = t - gbase;
+            ctr = mk3(F[(g) * FSTR + F_X + 0], F[(g) * FSTR + F_X + 1], F[(g) * FSTR + F_X + 2]);
+            f3 h = mk3(F[(g) * FSTR + F_H + 0], F[(g) * FSTR + F_H + 1], F[(g) * FSTR + F_H + 2]);
+            gbox = F[(g) * FSTR + F_TYPE] == 0.f ? 1 : 0;
+            rt = gbox ? sqrtf(dot(h, h)) : h.x;
           }
-          emit(X, a.rcap, hit, isrob, po, E);
+        }
+#pragma unroll 1
+        for (int f = 0; f < S.nf; ++f) {
+          const f3 c = mk3(lane_val(fc.x, f), lane_val(fc.y, f), lane_val(fc.z, f));
+          const float R = lane_val(fR, f);
+          const int fbox = __builtin_amdgcn_readlane(fb, f);
+          bool m;
+          if (isplane) {
+            m = dot(ctr, c) - pd - R < slack;
+          } else {
+            const f3 q = mk3(fmaxf(fabsf(c.x - ctr.x) - half.x, 0.f), fmaxf(fabsf(c.y - ctr.y) - half.y, 0.f),
+                             fmaxf(fabsf(c.z - ctr.z) - half.z, 0.f));
+            const float lim = R + rt + slack;
+            m = dot(q, q) < lim * lim;
+          }
+          // pair rules of free-body targets: not itself; box vertices skip
+          // free spheres; sphere pairs once
+          if (g >= 0 && (g == f || (!gbox && (fbox || g <= f)))) m = false;
+          const uint64_t mk = __ballot(valid && m);
+          if (lane == 0) {
+            msk[(f * nch + ch) * 2] = (uint32_t)mk;
+            msk[(f * nch + ch) * 2 + 1] = (uint32_t)(mk >> 32);
+          }
         }
       }
-      obase += members;
+      wave_sync();
+      int obase = S.nsph;
+      for (int f = 0; f < S.nf; ++f) {
+        const bool fbox = F[(f) * FSTR + F_TYPE] == 0.f;
+        const int members = fbox ? 8 : 1;
+        // body f's candidates in increasing target order, from its masks
+        int nbc = 0;
+        for (int ch = 0; ch < nch; ++ch) {
+          const uint64_t mk = (uint64_t)msk[(f * nch + ch) * 2] | ((uint64_t)msk[(f * nch + ch) * 2 + 1] << 32);
+          if ((mk >> lane) & 1ull) listB[nbc + prefix_below(mk)] = (uint16_t)(ch * WAVE + lane);
+          nbc += __popcll(mk);
+        }
+        if (nbc > 0) {
+          const int total = members * nbc;
+          const float inv = 1.f / (float)nbc;
+          for (int base = 0; base < total; base += WAVE) {
+            int idx = base + lane;
+            PairOut po;
+            bool isrob = false, hit = false;
+            if (idx < total) {
+              int k, ci;
+              divmod(idx, nbc, inv, k, ci);
+              hit = eval_pair(X, obase + k, listB[ci], po, isrob);
+            }
+            emit(X, a.rcap, hit, isrob, po, E);
+          }
+        }
+        obase += members;
+      }
     }
   }
   uint64_t ks = E.ks;
