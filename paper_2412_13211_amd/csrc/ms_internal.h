@@ -117,13 +117,13 @@ __host__ __device__ inline LdsLayout make_layout(int fmax, int smax, int ccap, i
   L.con = o;
   L.dyn = o;
   L.rows = o + lds_align4(ccap * CON_FLOATS);
-  // the free bodies' culling masks (per body and 64-target chunk, 64 bits)
+  // the culling masks (per robot or free body and 64-target chunk, 64 bits)
   // live in the robot rows' space: the contact phase fills them before the
   // rows phase builds the rows
   L.nch = (L.ntmax + WAVE - 1) / WAVE;
   L.cmask = L.rows;
   {
-    const int rw = lds_align4(rcap * ROW_FLOATS), mk = lds_align4(fmax * L.nch * 2);
+    const int rw = lds_align4(rcap * ROW_FLOATS), mk = lds_align4((fmax > ND ? fmax : ND) * L.nch * 2);
     const int cr = lds_align4(ccap * CON_FLOATS) + (rw > mk ? rw : mk);
     o += cr > DYN_FLOATS ? cr : DYN_FLOATS;
   }

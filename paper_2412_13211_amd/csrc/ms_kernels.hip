@@ -819,6 +819,132 @@ __device__ __forceinline__ bool box_near_target(const ConCtx& X, f3 bc, f3 he, i
   return dist_point_box(c - bc, he) - rad < slack;
 }
 
+// Bound of one culling target, held by a lane: a plane (n in ctr, offset pd)
+// or an axis-aligned box (centre ctr, half extents half) grown by rt: planes
+// exactly, furniture boxes as their boxes, door / drawer boxes and free
+// bodies as bounding spheres.  g: the free body a target is (-1: none).
+struct TBound {
+  bool valid, isplane;
+  f3 ctr, half;
+  float rt, pd;
+  int g, gbox;
+};
+__device__ __forceinline__ void target_bound(const ConCtx& X, int t, TBound& B) {
+  B.valid = t >= 0 && t < X.NT;
+  B.isplane = false;
+  B.ctr = mk3(0.f, 0.f, 0.f);
+  B.half = mk3(0.f, 0.f, 0.f);
+  B.rt = 0.f;
+  B.pd = 0.f;
+  B.g = -1;
+  B.gbox = 0;
+  if (!B.valid) return;
+  const float* F = X.F;
+  const float* A = X.A;
+  const int gbase = X.np + X.ns + X.na;
+  if (t < X.np) {
+    B.isplane = true;
+    B.ctr = mk3(X.Pl[t * 4], X.Pl[t * 4 + 1], X.Pl[t * 4 + 2]);
+    B.pd = X.Pl[t * 4 + 3];
+  } else if (t < X.np + X.ns) {
+    const float* bx = X.St + (t - X.np) * 6;
+    B.ctr = mk3(bx[0], bx[1], bx[2]);
+    B.half = mk3(bx[3], bx[4], bx[5]);
+  } else if (t < gbase) {
+    const int x = t - X.np - X.ns;
+    B.ctr = mk3(A[(A_BC + 0) * AMAX + x], A[(A_BC + 1) * AMAX + x], A[(A_BC + 2) * AMAX + x]);
+    f3 h = mk3(A[(A_BH + 0) * AMAX + x], A[(A_BH + 1) * AMAX + x], A[(A_BH + 2) * AMAX + x]);
+    B.rt = sqrtf(dot(h, h));
+  } else {
+    const int g = t - gbase;
+    B.g = g;
+    B.ctr = mk3(F[(g) * FSTR + F_X + 0], F[(g) * FSTR + F_X + 1], F[(g) * FSTR + F_X + 2]);
+    f3 h = mk3(F[(g) * FSTR + F_H + 0], F[(g) * FSTR + F_H + 1], F[(g) * FSTR + F_H + 2]);
+    B.gbox = F[(g) * FSTR + F_TYPE] == 0.f ? 1 : 0;
+    B.rt = B.gbox ? sqrtf(dot(h, h)) : h.x;
+  }
+}
+// conservative: may sphere (c, R) come within `slack` of the bound?  Sphere-
+// to-box distances are compared squared (slack covers the rounding).
+__device__ __forceinline__ bool bound_near(const TBound& B, f3 c, float R, float slack) {
+  if (B.isplane) return dot(B.ctr, c) - B.pd - R < slack;
+  const f3 q = mk3(fmaxf(fabsf(c.x - B.ctr.x) - B.half.x, 0.f), fmaxf(fabsf(c.y - B.ctr.y) - B.half.y, 0.f),
+                   fmaxf(fabsf(c.z - B.ctr.z) - B.half.z, 0.f));
+  const float lim = R + B.rt + slack;
+  return dot(q, q) < lim * lim;
+}
+
+// Exact tests of bodies' owners against their culled candidates (body b:
+// mem(b) owners from owner index obase(b); candidates: the set bits of its
+// masks, bit j of chunk ch standing for target tgt(ch, j)), packed into full
+// chunks: consecutive bodies are grouped while the group's pairs fit one
+// chunk and its candidate lists fit lst[cap]; a body with more than a chunk
+// of pairs runs alone over several.  Pairs are enumerated (body, owner,
+// candidate) in increasing order, so the contacts come out in canonical order.
+template <class Mem, class Obase, class Tgt>
+__device__ __forceinline__ void exact_grouped(const ConCtx& X, int rcap, int nbod, const uint32_t* msk, int nch,
+                                              Mem mem, Obase obase, Tgt tgt, uint16_t* lst, int cap, EmitState& E) {
+  const int lane = lane_id();
+  auto mask_of = [&](int b, int ch) -> uint64_t {
+    return (uint64_t)msk[(b * nch + ch) * 2] | ((uint64_t)msk[(b * nch + ch) * 2 + 1] << 32);
+  };
+  int b = 0;
+  while (b < nbod) {
+    // lane gi: group member gi's first pair, list offset, candidates, owner base, body
+    int ng = 0, pairs = 0, cands = 0;
+    int gP = 0, gQ = 0, gC = 1, gO = 0, gB = 0;
+    while (b < nbod) {
+      int cnt = 0;
+      for (int ch = 0; ch < nch; ++ch) cnt += __popcll(mask_of(b, ch));
+      cnt = __builtin_amdgcn_readfirstlane(cnt);
+      const int m = mem(b);
+      if (cnt == 0 || m == 0) {
+        ++b;
+        continue;
+      }
+      if (ng > 0 && (pairs + m * cnt > WAVE || cands + cnt > cap)) break;
+      if (lane == ng) {
+        gP = pairs;
+        gQ = cands;
+        gC = cnt;
+        gO = obase(b);
+        gB = b;
+      }
+      pairs += m * cnt;
+      cands += cnt;
+      ++ng;
+      ++b;
+      if (pairs > WAVE) break;
+    }
+    if (ng == 0) break;
+    // the members' candidate lists, in target order
+    for (int gi = 0; gi < ng; ++gi) {
+      const int bb = __builtin_amdgcn_readlane(gB, gi);
+      int q = __builtin_amdgcn_readlane(gQ, gi);
+      for (int ch = 0; ch < nch; ++ch) {
+        const uint64_t mk = mask_of(bb, ch);
+        if ((mk >> lane) & 1ull) lst[q + prefix_below(mk)] = (uint16_t)tgt(ch, lane);
+        q += __popcll(mk);
+      }
+    }
+    for (int base = 0; base < pairs; base += WAVE) {
+      const int idx = base + lane;
+      int gi = 0;
+      for (int j = 1; j < ng; ++j) gi += idx >= __builtin_amdgcn_readlane(gP, j) ? 1 : 0;
+      const int P = __shfl(gP, gi, WAVE), Q = __shfl(gQ, gi, WAVE), Cn = __shfl(gC, gi, WAVE),
+                O = __shfl(gO, gi, WAVE);
+      PairOut po;
+      bool isrob = false, hit = false;
+      if (idx < pairs) {
+        int k, ci;
+        divmod(idx - P, Cn, 1.f / (float)Cn, k, ci);
+        hit = eval_pair(X, O + k, lst[Q + ci], po, isrob);
+      }
+      emit(X, rcap, hit, isrob, po, E);
+    }
+  }
+}
+
 __device__ __forceinline__ void phase_contacts(const KArgs& a, const Scene& S, float* L, const Robot& rb, int& NC, int& NR, int& NL,
                                uint32_t& status, uint64_t& keysum) {
   const int lane = lane_id();
@@ -901,99 +1027,79 @@ __device__ __forceinline__ void phase_contacts(const KArgs& a, const Scene& S, f
       f3 bc = (lo + hi) * 0.5f, he = (hi - lo) * 0.5f;
       const int nra = compact(NT, listA, [](int i) { return i; },
                               [&](int t) { return box_near_target(X, bc, he, t, slack); });
-      for (int b = 0; b < S.nb; ++b) {
-        const int cnt = M->sph_count[b];
-        if (cnt == 0 || nra == 0) continue;
-        float4 bs = M->bsph[b];
-        f3 c = mv(rb.R + b * 9, mk3(bs.x, bs.y, bs.z)) + body_p(rb, b);
-        const int nbc = compact(nra, listB, [&](int i) { return (int)listA[i]; },
-                                [&](int t) { return sphere_near_target(X, c, bs.w, t, slack); });
-        if (nbc == 0) continue;
-        const int first = M->sph_first[b], total = cnt * nbc;
-        const float inv = 1.f / (float)nbc;
-        for (int base = 0; base < total; base += WAVE) {
-          int idx = base + lane;
-          PairOut po;
-          bool isrob = false, hit = false;
-          if (idx < total) {
-            int k, ci;
-            divmod(idx, nbc, inv, k, ci);
-            hit = eval_pair(X, first + k, listB[ci], po, isrob);
+      // the robot bodies' bounding spheres against the robot's candidates,
+      // transposed as for the free bodies below: lanes over a chunk of the
+      // candidates, a loop over the bodies, one ballot per (body, chunk)
+      uint32_t* msk = reinterpret_cast<uint32_t*>(L + Y.cmask);
+      const int ncA = (nra + WAVE - 1) / WAVE;
+      f3 bcen = mk3(0.f, 0.f, 0.f);
+      float bR = 0.f;
+      if (lane < S.nb) {
+        float4 bs = M->bsph[lane];
+        bcen = mv(rb.R + lane * 9, mk3(bs.x, bs.y, bs.z)) + body_p(rb, lane);
+        bR = bs.w;
+      }
+      for (int ch = 0; ch < ncA; ++ch) {
+        const int i = ch * WAVE + lane;
+        TBound B;
+        target_bound(X, i < nra ? (int)listA[i] : -1, B);
+#pragma unroll 1
+        for (int b = 0; b < S.nb; ++b) {
+          bool m = false;
+          if (M->sph_count[b] > 0) {
+            const f3 c = mk3(lane_val(bcen.x, b), lane_val(bcen.y, b), lane_val(bcen.z, b));
+            m = B.valid && bound_near(B, c, lane_val(bR, b), slack);
           }
-          emit(X, a.rcap, hit, isrob, po, E);
+          const uint64_t mk = __ballot(m);
+          if (lane == 0) {
+            msk[(b * ncA + ch) * 2] = (uint32_t)mk;
+            msk[(b * ncA + ch) * 2 + 1] = (uint32_t)(mk >> 32);
+          }
         }
       }
+      wave_sync();
+      exact_grouped(
+          X, a.rcap, S.nb, msk, ncA, [&](int b) { return M->sph_count[b]; }, [&](int b) { return M->sph_first[b]; },
+          [&](int ch, int j) { return (int)listA[ch * WAVE + j]; }, listB, Y.ntmax, E);
     }
     // free bodies.  Bounding-sphere culling, transposed: the lanes hold one
     // 64-target chunk's bounds (loaded once per substep), the bodies' bounds
     // come from their lanes by readlane, and one ballot per (body, chunk) goes
-    // to the mask table.  Target bounds: planes exactly; furniture boxes as
-    // their boxes; door / drawer boxes and free bodies as bounding spheres.
-    // Sphere-against-box distances are compared squared (the slack covers the
-    // rounding), so no square root is taken.
+    // to the mask table; then the exact tests, grouped.
     {
       const float* F = X.F;
       const int fm = X.fm;
-      const int gbase = S.np + S.ns + S.na;
       uint32_t* msk = reinterpret_cast<uint32_t*>(L + Y.cmask);
       const int nch = (NT + WAVE - 1) / WAVE;
-      // lane f: body f's bounding sphere
+      // lane f: body f's bounding sphere, kind and first owner index
       f3 fc = mk3(0.f, 0.f, 0.f);
       float fR = 0.f;
-      int fb = 0;
+      int fb = 0, fmem = 0;
       if (lane < S.nf) {
         fc = mk3(F[(lane) * FSTR + F_X + 0], F[(lane) * FSTR + F_X + 1], F[(lane) * FSTR + F_X + 2]);
         f3 h = mk3(F[(lane) * FSTR + F_H + 0], F[(lane) * FSTR + F_H + 1], F[(lane) * FSTR + F_H + 2]);
         fb = F[(lane) * FSTR + F_TYPE] == 0.f ? 1 : 0;
         fR = fb ? sqrtf(dot(h, h)) : h.x;
+        fmem = fb ? 8 : 1;
       }
+      int fob = fmem;  // inclusive scan of the owners per body
+      for (int off = 1; off < WAVE; off <<= 1) {
+        const int v = __shfl_up(fob, off, WAVE);
+        if (lane >= off) fob += v;
+      }
+      fob += S.nsph - fmem;
       for (int ch = 0; ch < nch; ++ch) {
-        const int t = ch * WAVE + lane;
-        // this lane's target: a plane (pn, pd), or a box (ctr, half) grown by rt
-        bool valid = t < NT, isplane = false;
-        f3 ctr = mk3(0.f, 0.f, 0.f), half = mk3(0.f, 0.f, 0.f);
-        float rt = 0.f, pd = 0.f;
-        int g = -1, gbox = 0;
-        if (valid) {
-          if (t < S.np) {
-            isplane = true;
-            ctr = mk3(X.Pl[t * 4], X.Pl[t * 4 + 1], X.Pl[t * 4 + 2]);
-            pd = X.Pl[t * 4 + 3];
-          } else if (t < S.np + S.ns) {
-            const float* bx = X.St + (t - S.np) * 6;
-            ctr = mk3(bx[0], bx[1], bx[2]);
-            half = mk3(bx[3], bx[4], bx[5]);
-          } else if (t < gbase) {
-            const int x = t - S.np - S.ns;
-            ctr = mk3(Ax[(A_BC + 0) * AMAX + x], Ax[(A_BC + 1) * AMAX + x], Ax[(A_BC + 2) * AMAX + x]);
-            f3 h = mk3(Ax[(A_BH + 0) * AMAX + x], Ax[(A_BH + 1) * AMAX + x], Ax[(A_BH + 2) * AMAX + x]);
-            rt = sqrtf(dot(h, h));
-          } else {
-            g = t - gbase;
-            ctr = mk3(F[(g) * FSTR + F_X + 0], F[(g) * FSTR + F_X + 1], F[(g) * FSTR + F_X + 2]);
-            f3 h = mk3(F[(g) * FSTR + F_H + 0], F[(g) * FSTR + F_H + 1], F[(g) * FSTR + F_H + 2]);
-            gbox = F[(g) * FSTR + F_TYPE] == 0.f ? 1 : 0;
-            rt = gbox ? sqrtf(dot(h, h)) : h.x;
-          }
-        }
+        TBound B;
+        target_bound(X, ch * WAVE + lane, B);
 #pragma unroll 1
         for (int f = 0; f < S.nf; ++f) {
           const f3 c = mk3(lane_val(fc.x, f), lane_val(fc.y, f), lane_val(fc.z, f));
-          const float R = lane_val(fR, f);
           const int fbox = __builtin_amdgcn_readlane(fb, f);
-          bool m;
-          if (isplane) {
-            m = dot(ctr, c) - pd - R < slack;
-          } else {
-            const f3 q = mk3(fmaxf(fabsf(c.x - ctr.x) - half.x, 0.f), fmaxf(fabsf(c.y - ctr.y) - half.y, 0.f),
-                             fmaxf(fabsf(c.z - ctr.z) - half.z, 0.f));
-            const float lim = R + rt + slack;
-            m = dot(q, q) < lim * lim;
-          }
+          bool m = B.valid && bound_near(B, c, lane_val(fR, f), slack);
           // pair rules of free-body targets: not itself; box vertices skip
           // free spheres; sphere pairs once
-          if (g >= 0 && (g == f || (!gbox && (fbox || g <= f)))) m = false;
-          const uint64_t mk = __ballot(valid && m);
+          if (B.g >= 0 && (B.g == f || (!B.gbox && (fbox || B.g <= f)))) m = false;
+          const uint64_t mk = __ballot(m);
           if (lane == 0) {
             msk[(f * nch + ch) * 2] = (uint32_t)mk;
             msk[(f * nch + ch) * 2 + 1] = (uint32_t)(mk >> 32);
@@ -1001,34 +1107,10 @@ __device__ __forceinline__ void phase_contacts(const KArgs& a, const Scene& S, f
         }
       }
       wave_sync();
-      int obase = S.nsph;
-      for (int f = 0; f < S.nf; ++f) {
-        const bool fbox = F[(f) * FSTR + F_TYPE] == 0.f;
-        const int members = fbox ? 8 : 1;
-        // body f's candidates in increasing target order, from its masks
-        int nbc = 0;
-        for (int ch = 0; ch < nch; ++ch) {
-          const uint64_t mk = (uint64_t)msk[(f * nch + ch) * 2] | ((uint64_t)msk[(f * nch + ch) * 2 + 1] << 32);
-          if ((mk >> lane) & 1ull) listB[nbc + prefix_below(mk)] = (uint16_t)(ch * WAVE + lane);
-          nbc += __popcll(mk);
-        }
-        if (nbc > 0) {
-          const int total = members * nbc;
-          const float inv = 1.f / (float)nbc;
-          for (int base = 0; base < total; base += WAVE) {
-            int idx = base + lane;
-            PairOut po;
-            bool isrob = false, hit = false;
-            if (idx < total) {
-              int k, ci;
-              divmod(idx, nbc, inv, k, ci);
-              hit = eval_pair(X, obase + k, listB[ci], po, isrob);
-            }
-            emit(X, a.rcap, hit, isrob, po, E);
-          }
-        }
-        obase += members;
-      }
+      exact_grouped(
+          X, a.rcap, S.nf, msk, nch, [&](int f) { return __builtin_amdgcn_readlane(fmem, f); },
+          [&](int f) { return __builtin_amdgcn_readlane(fob, f); }, [&](int ch, int j) { return ch * WAVE + j; }, listA,
+          2 * Y.ntmax, E);
     }
   }
   uint64_t ks = E.ks;
