@@ -1581,19 +1581,28 @@ struct SideReg {
   int kind, idx;
   f3 x, v, w, col;
   float im, qv;
-  float Ii[6];  // symmetric world inverse inertia
+  // symmetric world inverse inertia (xx yy zz xy xz yz), named scalars so
+  // that the whole side stays in registers
+  float i0, i1, i2, i3, i4, i5;
 };
 __device__ __forceinline__ void side_load(const float* F, const float* A, int sv, f3 p, SideReg& S) {
   S.kind = side_kind(sv);
   S.idx = side_idx(sv);
+  S.x = S.v = S.w = S.col = mk3(0.f, 0.f, 0.f);
+  S.im = S.qv = 0.f;
+  S.i0 = S.i1 = S.i2 = S.i3 = S.i4 = S.i5 = 0.f;
   if (S.kind == K_FREE) {
     const float* f = F + S.idx * FSTR;
     S.x = mk3(f[F_X], f[F_X + 1], f[F_X + 2]);
     S.v = mk3(f[F_V], f[F_V + 1], f[F_V + 2]);
     S.w = mk3(f[F_W], f[F_W + 1], f[F_W + 2]);
     S.im = f[F_IM];
-#pragma unroll
-    for (int t = 0; t < 6; ++t) S.Ii[t] = f[F_II + t];
+    S.i0 = f[F_II + 0];
+    S.i1 = f[F_II + 1];
+    S.i2 = f[F_II + 2];
+    S.i3 = f[F_II + 3];
+    S.i4 = f[F_II + 4];
+    S.i5 = f[F_II + 5];
   } else if (S.kind == K_AUX) {
     S.col = aux_col(A, S.idx, p);
     S.qv = A[A_V * AMAX + S.idx];
@@ -1609,8 +1618,10 @@ __device__ __forceinline__ f3 side_vel(const SideReg& S, f3 p) {
 // apply the impulse P at p
 __device__ __forceinline__ void side_impulse(SideReg& S, f3 p, f3 P) {
   if (S.kind == K_FREE) {
+    const f3 q = cross(p - S.x, P);
     S.v = S.v + P * S.im;
-    S.w = S.w + smv(S.Ii, cross(p - S.x, P));
+    S.w = S.w + mk3(S.i0 * q.x + S.i3 * q.y + S.i4 * q.z, S.i3 * q.x + S.i1 * q.y + S.i5 * q.z,
+                    S.i4 * q.x + S.i5 * q.y + S.i2 * q.z);
   } else if (S.kind == K_AUX) {
     S.qv += dot(S.col, P) * S.im;
   }
