@@ -109,7 +109,7 @@ __host__ __device__ inline LdsLayout make_layout(int fmax, int smax, int ccap, i
   int o = 0;
   L.robot = o; o += lds_align4(ROBOT_FLOATS);
   L.sph = o;   o += nsph * 4;   // world sphere centres and radii of the robot
-  L.fr = o;    o += lds_align4(fmax * FREE_FLOATS);
+  L.fr = o;    o += lds_align4((fmax + 1) * FREE_FLOATS);  // + a zero record (static side)
   L.aux = o;   o += AMAX * AUX_FLOATS;
   L.stat = o;  o += lds_align4(L.smax * 6);
   L.plane = o; o += PMAX * 4;

@@ -270,6 +270,9 @@ __device__ __forceinline__ void load_scene(const KArgs& a, const Scene& S, float
     F[(f) * FSTR + F_H + 0] = d.half[0]; F[(f) * FSTR + F_H + 1] = d.half[1]; F[(f) * FSTR + F_H + 2] = d.half[2];
     F[(f) * FSTR + F_IB + 0] = d.Ib[0]; F[(f) * FSTR + F_IB + 1] = d.Ib[1]; F[(f) * FSTR + F_IB + 2] = d.Ib[2];
   }
+  // the zero record past the free bodies: the static side of a contact row
+  // in the sweeps (no mass, no velocity)
+  if (lane < FREE_FLOATS) F[fm * FSTR + lane] = 0.f;
   float* A = L + Y.aux;
   if (lane < S.na) {
     const float* xs = a.x_in + (size_t)a.S * 2 * ND + (size_t)a.NF * 16 + (size_t)(S.a0 + lane) * 4;
@@ -1641,17 +1644,12 @@ __device__ __forceinline__ void friction_disk(float l1, float l2, float r1, floa
                                               float& y1, float& y2) {
   y1 = l1 - r1 * iw1;
   y2 = l2 - r2 * iw2;
-  float nn = y1 * y1 + y2 * y2;
-  if (nn > lim * lim) {
-    if (lim > 0.f) {
-      float sc = lim * rsqrtf(nn);
-      y1 *= sc;
-      y2 *= sc;
-    } else {
-      y1 = 0.f;
-      y2 = 0.f;
-    }
-  }
+  const float nn = y1 * y1 + y2 * y2;
+  // outside the disk: scaled onto it (onto 0 for a radius of 0); selects,
+  // not branches, so the lanes of a level do not split
+  const float sc = nn > lim * lim ? (lim > 0.f ? lim * rsqrtf(nn) : 0.f) : 1.f;
+  y1 *= sc;
+  y2 *= sc;
 }
 
 __device__ __forceinline__ void phase_pgs(const KArgs& a, const Scene& S, float* L, int NC, int NL, int maxl,
@@ -1669,6 +1667,9 @@ __device__ __forceinline__ void phase_pgs(const KArgs& a, const Scene& S, float*
   const uint16_t* order = reinterpret_cast<const uint16_t*>(rob + cc + 2);
   const float mu = a.mu;
   const int j = lane & 15;
+  // the zero record's velocities (kept zero by every update that uses it)
+  if (lane < 6) F[Y.fmax * FSTR + F_V + lane] = 0.f;
+  wave_sync();
 #pragma unroll 1
   for (int it = 0; it < a.K; ++it) {
 #pragma unroll 1
@@ -1758,14 +1759,32 @@ __device__ __forceinline__ void phase_pgs(const KArgs& a, const Scene& S, float*
           c[C_LAM] = nl;
           continue;
         }
-        f3 n = mk3(c[C_N], c[C_N + 1], c[C_N + 2]);
-        f3 p = mk3(c[C_P], c[C_P + 1], c[C_P + 2]);
-        float iw0 = c[C_IW], iw1 = c[C_IW + 1], iw2 = c[C_IW + 2];
+        // side A is a free body (the owner); side B a free body, a door /
+        // drawer or static.  A static B reads and writes the zero record past
+        // the scene's free bodies (no mass, no velocity), so both sides run
+        // the same loads and arithmetic without branches; a door / drawer
+        // adds its joint's part in a branch of its own.
+        const f3 n = mk3(c[C_N], c[C_N + 1], c[C_N + 2]);
+        const f3 p = mk3(c[C_P], c[C_P + 1], c[C_P + 2]);
+        const float iw0 = c[C_IW], iw1 = c[C_IW + 1], iw2 = c[C_IW + 2];
         float l1 = c[C_LAM + 1], l2 = c[C_LAM + 2];
-        SideReg SA, SB;
-        side_load(F, A, sA, p, SA);
-        side_load(F, A, sB, p, SB);
-        const f3 u = side_vel(SA, p) - side_vel(SB, p);
+        const int kB = side_kind(sB);
+        float* fa = F + side_idx(sA) * FSTR;
+        float* fb = F + (kB == K_FREE ? side_idx(sB) : Y.fmax) * FSTR;
+        const f3 xa = mk3(fa[F_X], fa[F_X + 1], fa[F_X + 2]), xb = mk3(fb[F_X], fb[F_X + 1], fb[F_X + 2]);
+        f3 va = mk3(fa[F_V], fa[F_V + 1], fa[F_V + 2]), wa = mk3(fa[F_W], fa[F_W + 1], fa[F_W + 2]);
+        f3 vb = mk3(fb[F_V], fb[F_V + 1], fb[F_V + 2]), wb = mk3(fb[F_W], fb[F_W + 1], fb[F_W + 2]);
+        const f3 ra = p - xa, rb = p - xb;
+        f3 u = (va + cross(wa, ra)) - (vb + cross(wb, rb));
+        f3 col = mk3(0.f, 0.f, 0.f);
+        float qv = 0.f, imx = 0.f;
+        const int xi = side_idx(sB);
+        if (kB == K_AUX) {
+          col = aux_col(A, xi, p);
+          qv = A[A_V * AMAX + xi];
+          imx = A[A_IM * AMAX + xi];
+          u = u - col * qv;
+        }
         float r = dot(n, u) + bias;
         float nl = l0;
         if (iw0 > 0.f) nl = fmaxf(0.f, l0 - r * iw0);
@@ -1790,10 +1809,23 @@ __device__ __forceinline__ void phase_pgs(const KArgs& a, const Scene& S, float*
           l1 = y1;
           l2 = y2;
         }
-        side_impulse(SA, p, P);
-        side_impulse(SB, p, P * (-1.f));
-        side_store(F, A, SA);
-        side_store(F, A, SB);
+        {
+          const float ima = fa[F_IM], imb = fb[F_IM];
+          const f3 qa = cross(ra, P), qb = cross(rb, P);
+          const float* ia = fa + F_II;
+          const float* ib = fb + F_II;
+          va = va + P * ima;
+          wa = wa + mk3(ia[0] * qa.x + ia[3] * qa.y + ia[4] * qa.z, ia[3] * qa.x + ia[1] * qa.y + ia[5] * qa.z,
+                        ia[4] * qa.x + ia[5] * qa.y + ia[2] * qa.z);
+          vb = vb - P * imb;
+          wb = wb - mk3(ib[0] * qb.x + ib[3] * qb.y + ib[4] * qb.z, ib[3] * qb.x + ib[1] * qb.y + ib[5] * qb.z,
+                        ib[4] * qb.x + ib[5] * qb.y + ib[2] * qb.z);
+          fa[F_V] = va.x; fa[F_V + 1] = va.y; fa[F_V + 2] = va.z;
+          fa[F_W] = wa.x; fa[F_W + 1] = wa.y; fa[F_W + 2] = wa.z;
+          fb[F_V] = vb.x; fb[F_V + 1] = vb.y; fb[F_V + 2] = vb.z;
+          fb[F_W] = wb.x; fb[F_W + 1] = wb.y; fb[F_W + 2] = wb.z;
+          if (kB == K_AUX) A[A_V * AMAX + xi] = qv - dot(col, P) * imx;
+        }
         c[C_LAM] = nl;
         c[C_LAM + 1] = l1;
         c[C_LAM + 2] = l2;
