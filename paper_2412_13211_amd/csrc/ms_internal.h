@@ -130,7 +130,12 @@ __host__ __device__ inline LdsLayout make_layout(int fmax, int smax, int ccap, i
   // uint16 level offsets and robot row per level [ccap + 2] each, order and
   // level of each row [ccap] each
   L.lvl = o;   o += lds_align4((4 * ccap + 4 + 1) / 2);
-  L.cand = o;  o += lds_align4(L.ntmax);                       // two uint16 candidate lists
+  // two uint16 candidate lists; after the contact phase the level schedule's
+  // per-node row masks (64-bit, per node and 64-row chunk)
+  {
+    const int masks = (1 + AMAX + fmax) * ((ccap + WAVE - 1) / WAVE) * 2;
+    L.cand = o;  o += lds_align4(L.ntmax > masks ? L.ntmax : masks);
+  }
   L.frc = o;   o += force ? lds_align4(fmax * FRC_FLOATS) : 0;  // force-output accumulators
   L.total = o;
   return L;

@@ -576,6 +576,7 @@ struct ConCtx {
   const float* St;
   int nsph, np, ns, na, nf, NT;
   float margin;
+  bool hash;  // keep the contact-set hash (diagnostics only)
 };
 
 struct PairOut {
@@ -722,7 +723,7 @@ __device__ __forceinline__ void emit(const ConCtx& X, int rcap, bool hit, bool i
     C[(pos) * CSTR + C_P + 0] = p.x; C[(pos) * CSTR + C_P + 1] = p.y; C[(pos) * CSTR + C_P + 2] = p.z;
     C[(pos) * CSTR + C_PHI] = po.phi;
     C[(pos) * CSTR + C_KEY] = __int_as_float(po.osub | (int)((po.tkey >> 24) << 8) | (int)((po.tkey & 0xffffffu) << 10));
-    E.ks += mix64(((uint64_t)po.okey << 32) | po.tkey);
+    if (X.hash) E.ks += mix64(((uint64_t)po.okey << 32) | po.tkey);
   }
   uint64_t mkept = __ballot(keep);
   E.n = min(E.n + __popcll(mkept), X.cc);
@@ -966,6 +967,7 @@ __device__ __forceinline__ void phase_contacts(const KArgs& a, const Scene& S, f
   X.nsph = S.nsph; X.np = S.np; X.ns = S.ns; X.na = S.na; X.nf = S.nf;
   X.NT = S.np + S.ns + S.na + S.nf;
   X.margin = a.margin;
+  X.hash = a.debug != nullptr;
   float* C = X.C;
   const int cc = X.cc;
   const float* Ax = X.A;
@@ -1046,7 +1048,7 @@ __device__ __forceinline__ void phase_contacts(const KArgs& a, const Scene& S, f
         const int i = ch * WAVE + lane;
         TBound B;
         target_bound(X, i < nra ? (int)listA[i] : -1, B);
-#pragma unroll 1
+#pragma unroll 4
         for (int b = 0; b < S.nb; ++b) {
           bool m = false;
           if (M->sph_count[b] > 0) {
@@ -1094,7 +1096,7 @@ __device__ __forceinline__ void phase_contacts(const KArgs& a, const Scene& S, f
       for (int ch = 0; ch < nch; ++ch) {
         TBound B;
         target_bound(X, ch * WAVE + lane, B);
-#pragma unroll 1
+#pragma unroll 4
         for (int f = 0; f < S.nf; ++f) {
           const f3 c = mk3(lane_val(fc.x, f), lane_val(fc.y, f), lane_val(fc.z, f));
           const int fbox = __builtin_amdgcn_readlane(fb, f);
@@ -1527,46 +1529,98 @@ __device__ __forceinline__ void phase_rows(const KArgs& a, const Scene& S, float
 
 // Level schedule: level(k) = 1 + max level of earlier rows sharing a node.
 // Then an order list grouped by level; each level's robot row is kept apart.
+// The nodes are the robot (0), the door / drawer joints (1 + x) and the free
+// bodies (1 + AMAX + f); static targets are no node.  For every node a bit
+// mask of the rows touching it (LDS atomics, one bit per row) gives each row
+// the previous row on each of its nodes, and the levels are the longest-path
+// depths of that DAG, relaxed over the lanes until no level changes (as many
+// rounds as the deepest chain, instead of one serial pass over the rows).
+__device__ __forceinline__ void row_nodes(int inf, int& na, int& nbn) {
+  na = node_of(inf & 0xffff);
+  nbn = side_kind(inf & 0xffff) == K_LIMIT ? 63 : node_of((inf >> 16) & 0xffff);
+}
 __device__ __forceinline__ int phase_levels(const KArgs& a, float* L, int NC, int NR, int NL) {
   const int lane = lane_id();
   const LdsLayout& Y = a.L;
-  float* C = L + Y.con;
+  const float* C = L + Y.con;
   const int cc = Y.ccap;
   // per level the offset of its rows in `order` and its robot row (0xffff:
-  // none); each row's level
+  // none); each row's level.  While the levels are found, loff and rob hold
+  // each row's previous row on its first and second node (0xffff: none).
   uint16_t* loff = reinterpret_cast<uint16_t*>(L + Y.lvl);  // [cc + 2]
   uint16_t* rob = loff + cc + 2;                            // [cc + 2]
   uint16_t* order = rob + cc + 2;                           // [cc]
   uint16_t* lvl = order + cc;                               // [cc]
-  auto lvl_of = [&](int ci) { return (int)lvl[ci]; };
-  int reg = 0;  // level of node `lane`
-  int maxl = 0;
-  for (int base = 0; base < NC; base += WAVE) {
-    int info = 0;
-    if (base + lane < NC) info = __float_as_int(C[(base + lane) * CSTR + C_INFO]);
-    int cnt = min(WAVE, NC - base);
-    int mylvl = 0;
-    for (int k = 0; k < cnt; ++k) {
-      int inf = __builtin_amdgcn_readlane(info, k);
-      int na = node_of(inf & 0xffff), nbn = node_of((inf >> 16) & 0xffff);
-      if (side_kind(inf & 0xffff) == K_LIMIT) nbn = 63;
-      int lv = max(__builtin_amdgcn_readlane(reg, na), __builtin_amdgcn_readlane(reg, nbn)) + 1;
-      if (lane == na || (lane == nbn && nbn != 63)) reg = lv;
-      if (lane == k) mylvl = lv;
-      maxl = max(maxl, lv);
+  const int nch = (NC + WAVE - 1) / WAVE;
+  const int nnode = 1 + AMAX + Y.fmax;
+  unsigned long long* nm = reinterpret_cast<unsigned long long*>(L + Y.cand);  // [nnode][nch]
+  for (int e = lane; e < nnode * nch; e += WAVE) nm[e] = 0ull;
+  wave_sync();
+  for (int ch = 0; ch < nch; ++ch) {
+    const int r = ch * WAVE + lane;
+    if (r < NC) {
+      int na, nbn;
+      row_nodes(__float_as_int(C[r * CSTR + C_INFO]), na, nbn);
+      const unsigned long long bit = 1ull << lane;
+      atomicOr(nm + na * nch + ch, bit);
+      if (nbn != 63) atomicOr(nm + nbn * nch + ch, bit);
     }
-    if (base + lane < NC) lvl[base + lane] = (uint16_t)mylvl;
   }
+  wave_sync();
+  // the previous row touching node n before row r (-1: none)
+  auto prev = [&](int n, int r) {
+    int w = r >> 6;
+    unsigned long long m = nm[n * nch + w] & ((1ull << (r & 63)) - 1ull);
+    while (m == 0ull && w > 0) {
+      --w;
+      m = nm[n * nch + w];
+    }
+    return m ? w * WAVE + 63 - __clzll((long long)m) : -1;
+  };
+  for (int ch = 0; ch < nch; ++ch) {
+    const int r = ch * WAVE + lane;
+    if (r < NC) {
+      int na, nbn;
+      row_nodes(__float_as_int(C[r * CSTR + C_INFO]), na, nbn);
+      const int pa = prev(na, r), pb = nbn == 63 ? -1 : prev(nbn, r);
+      loff[r] = (uint16_t)(pa < 0 ? 0xffff : pa);
+      rob[r] = (uint16_t)(pb < 0 ? 0xffff : pb);
+      lvl[r] = 1;
+    }
+  }
+  wave_sync();
+  // relax: level(r) = 1 + max(level(prev on node A), level(prev on node B))
+  for (;;) {
+    bool changed = false;
+    for (int ch = 0; ch < nch; ++ch) {
+      const int r = ch * WAVE + lane;
+      if (r < NC) {
+        const int pa = loff[r], pb = rob[r];
+        const int la = pa == 0xffff ? 0 : lvl[pa], lb = pb == 0xffff ? 0 : lvl[pb];
+        const int nl = 1 + max(la, lb);
+        if (nl != lvl[r]) {
+          lvl[r] = (uint16_t)nl;
+          changed = true;
+        }
+      }
+    }
+    if (!__ballot(changed)) break;
+    wave_sync();
+  }
+  int maxl = 0;
+  for (int r = lane; r < NC; r += WAVE) maxl = max(maxl, (int)lvl[r]);
+  for (int off = 32; off > 0; off >>= 1) maxl = max(maxl, __shfl_xor(maxl, off, WAVE));
+  wave_sync();
   for (int e = lane; e <= maxl + 1; e += WAVE) rob[e] = 0xffff;
   wave_sync();
-  for (int rr = lane; rr < NR; rr += WAVE) rob[lvl_of(NL + rr)] = (uint16_t)(NL + rr);
+  for (int rr = lane; rr < NR; rr += WAVE) rob[lvl[NL + rr]] = (uint16_t)(NL + rr);
   int pos = 0;
   for (int lv = 1; lv <= maxl; ++lv) {
     if (lane == 0) loff[lv - 1] = (uint16_t)pos;
     for (int base = 0; base < NC; base += WAVE) {
       int ci = base + lane;
       bool isr = ci >= NL && ci < NL + NR;
-      bool m = ci < NC && !isr && lvl_of(ci) == lv;
+      bool m = ci < NC && !isr && lvl[ci] == lv;
       uint64_t mk = __ballot(m);
       if (m) order[pos + prefix_below(mk)] = (uint16_t)ci;
       pos += __popcll(mk);
@@ -2157,6 +2211,7 @@ __global__ __launch_bounds__(WAVE) void k_spawn_check(KArgs a, uint8_t* collide)
   X.nsph = S.nsph; X.np = S.np; X.ns = S.ns; X.na = S.na; X.nf = S.nf;
   X.NT = S.np + S.ns + S.na + S.nf;
   X.margin = 0.f;
+  X.hash = false;
   const int NT = X.NT, total = S.nsph * NT;
   const float invNT = NT > 0 ? 1.f / (float)NT : 0.f;
   bool hit = false;
