@@ -123,6 +123,11 @@ __device__ __forceinline__ float lane_val(float v, int src) {
   return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), src));
 }
 __device__ __forceinline__ void wave_sync() { __syncthreads(); }
+// Ordering of LDS accesses between the lanes of the one wavefront of a
+// workgroup: the LDS executes a wavefront's instructions in issue order, so a
+// read issued after a write sees it; only the compiler must not move memory
+// accesses across (no wait for outstanding accesses, unlike the barrier).
+__device__ __forceinline__ void lds_order() { asm volatile("" ::: "memory"); }
 
 // spatial 6-vectors [angular; linear] in world coordinates
 struct s6 {
@@ -1718,7 +1723,7 @@ __device__ __forceinline__ void phase_pgs(const KArgs& a, const Scene& S, float*
   const Robot RB = robot_view(L + Y.robot, L + Y.dyn);
   const uint16_t* loff = reinterpret_cast<const uint16_t*>(L + Y.lvl);
   const uint16_t* rob = loff + cc + 2;
-  const uint16_t* order = reinterpret_cast<const uint16_t*>(rob + cc + 2);
+  const uint16_t* order = rob + cc + 2;
   const float mu = a.mu;
   const int j = lane & 15;
   // the zero record's velocities (kept zero by every update that uses it)
@@ -1726,10 +1731,12 @@ __device__ __forceinline__ void phase_pgs(const KArgs& a, const Scene& S, float*
   wave_sync();
 #pragma unroll 1
   for (int it = 0; it < a.K; ++it) {
+    int o1 = 0;  // a level's rows start where the previous level's end
 #pragma unroll 1
     for (int lv = 1; lv <= maxl; ++lv) {
       const int rc = rob[lv] == 0xffff ? -1 : (int)rob[lv];
-      const int o0 = loff[lv - 1], o1 = loff[lv];
+      const int o0 = o1;
+      o1 = loff[lv];
       if (rc >= 0) {
         // the level's robot row: lanes 0..15 hold the robot joint velocities
         const float* row = Rw + (rc - NL) * ROW_FLOATS;
@@ -1789,17 +1796,17 @@ __device__ __forceinline__ void phase_pgs(const KArgs& a, const Scene& S, float*
           cw[C_LAM + 1] = l1;
           cw[C_LAM + 2] = l2;
         }
-        // a scheduling fence: keeps the robot row's registers from living
-        // into the per-lane rows below (they touch disjoint nodes)
-        wave_sync();
+        // the per-lane rows below touch other nodes; the fence also keeps the
+        // robot row's registers from living into them
+        lds_order();
       }
       // the level's other rows, one lane each (they share no node)
 #pragma unroll 1
       for (int e = o0 + lane; e < o1; e += WAVE) {
         const int ci = order[e];
         float* c = C + ci * CSTR;
-        int info = __float_as_int(c[C_INFO]);
-        int sA = info & 0xffff, sB = (info >> 16) & 0xffff;
+        const int info = __float_as_int(c[C_INFO]);
+        const int sA = info & 0xffff, sB = (info >> 16) & 0xffff;
         float bias = c[C_BIAS];
         float l0 = c[C_LAM];
         if (side_kind(sA) == K_LIMIT) {
@@ -1822,9 +1829,9 @@ __device__ __forceinline__ void phase_pgs(const KArgs& a, const Scene& S, float*
         const f3 p = mk3(c[C_P], c[C_P + 1], c[C_P + 2]);
         const float iw0 = c[C_IW], iw1 = c[C_IW + 1], iw2 = c[C_IW + 2];
         float l1 = c[C_LAM + 1], l2 = c[C_LAM + 2];
-        const int kB = side_kind(sB);
+        const int kB = side_kind(sB), xi = side_idx(sB);
         float* fa = F + side_idx(sA) * FSTR;
-        float* fb = F + (kB == K_FREE ? side_idx(sB) : Y.fmax) * FSTR;
+        float* fb = F + (kB == K_FREE ? xi : Y.fmax) * FSTR;
         const f3 xa = mk3(fa[F_X], fa[F_X + 1], fa[F_X + 2]), xb = mk3(fb[F_X], fb[F_X + 1], fb[F_X + 2]);
         f3 va = mk3(fa[F_V], fa[F_V + 1], fa[F_V + 2]), wa = mk3(fa[F_W], fa[F_W + 1], fa[F_W + 2]);
         f3 vb = mk3(fb[F_V], fb[F_V + 1], fb[F_V + 2]), wb = mk3(fb[F_W], fb[F_W + 1], fb[F_W + 2]);
@@ -1832,7 +1839,6 @@ __device__ __forceinline__ void phase_pgs(const KArgs& a, const Scene& S, float*
         f3 u = (va + cross(wa, ra)) - (vb + cross(wb, rb));
         f3 col = mk3(0.f, 0.f, 0.f);
         float qv = 0.f, imx = 0.f;
-        const int xi = side_idx(sB);
         if (kB == K_AUX) {
           col = aux_col(A, xi, p);
           qv = A[A_V * AMAX + xi];
@@ -1884,7 +1890,7 @@ __device__ __forceinline__ void phase_pgs(const KArgs& a, const Scene& S, float*
         c[C_LAM + 1] = l1;
         c[C_LAM + 2] = l2;
       }
-      wave_sync();
+      lds_order();
     }
   }
 }
