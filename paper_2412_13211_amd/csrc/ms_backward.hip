@@ -35,6 +35,11 @@ namespace {
 
 __device__ __forceinline__ int lane_id() { return threadIdx.x; }
 __device__ __forceinline__ void wsync() { __syncthreads(); }
+// Ordering of LDS accesses between the lanes of the workgroup's one
+// wavefront: the LDS executes a wavefront's instructions in issue order, so a
+// read issued after a write sees it; only the compiler must not move memory
+// accesses across (no wait for outstanding accesses, unlike the barrier).
+__device__ __forceinline__ void lds_order() { asm volatile("" ::: "memory"); }
 __device__ __forceinline__ float bcast0(float v) { return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), 0)); }
 // value of the lane N places along within its row of 16 lanes (DPP row
 // rotation: a VALU operand modifier, no LDS crossbar)
@@ -1021,7 +1026,7 @@ __device__ void bwd_scene(const BwdArgs& a, int s, float* L) {
     // Gauss-Seidel sweeps in reverse, levels in reverse
     for (int it = a.pr.K - 1; it >= 0; --it) {
       if (it >= 1) stage(it - 1);
-      wsync();
+      lds_order();
       for (int lv = maxl; lv >= 1; --lv) {
         const int rr = LV.rob[lv];
         if (rr >= 0) robot_contact_bar(E, it, rr - E.nlim, L);
@@ -1031,7 +1036,7 @@ __device__ void bwd_scene(const BwdArgs& a, int s, float* L) {
           if (r < E.nlim) E.limit_bar(it, r);
           else E.contact_bar(it, r - E.nlim);
         }
-        wsync();
+        lds_order();
       }
     }
     phase(4);
