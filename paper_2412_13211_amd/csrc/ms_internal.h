@@ -127,9 +127,10 @@ __host__ __device__ inline LdsLayout make_layout(int fmax, int smax, int ccap, i
     const int cr = lds_align4(ccap * CON_FLOATS) + (rw > mk ? rw : mk);
     o += cr > DYN_FLOATS ? cr : DYN_FLOATS;
   }
-  // uint16 level offsets and robot row per level [ccap + 2] each, order and
-  // level of each row [ccap] each
-  L.lvl = o;   o += lds_align4((4 * ccap + 4 + 1) / 2);
+  // level schedule: uint16 group offsets and robot row per level [ccap + 2]
+  // each, the groups by level (uint32) [ccap], each group's level [ccap] and
+  // first row [ccap + 1] (uint16)
+  L.lvl = o;   o += lds_align4((6 * ccap + 5 + 1) / 2);
   // two uint16 candidate lists; after the contact phase the level schedule's
   // per-node row masks (64-bit, per node and 64-row chunk)
   {

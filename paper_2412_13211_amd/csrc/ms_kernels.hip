@@ -1532,50 +1532,79 @@ __device__ __forceinline__ void phase_rows(const KArgs& a, const Scene& S, float
   wave_sync();
 }
 
-// Level schedule: level(k) = 1 + max level of earlier rows sharing a node.
-// Then an order list grouped by level; each level's robot row is kept apart.
+// Level schedule.  Rows are first merged into groups: a run of consecutive
+// rows (in canonical order) between one free body and static targets is one
+// group, run by one lane in order with the body's state in registers; every
+// other row is a group of its own.  level(g) = 1 + max level of earlier
+// groups sharing a node, so that executing the levels in order performs the
+// sequential row updates exactly.  Then an order list of the groups grouped
+// by level; each level's robot row is kept apart.
 // The nodes are the robot (0), the door / drawer joints (1 + x) and the free
 // bodies (1 + AMAX + f); static targets are no node.  For every node a bit
-// mask of the rows touching it (LDS atomics, one bit per row) gives each row
-// the previous row on each of its nodes, and the levels are the longest-path
-// depths of that DAG, relaxed over the lanes until no level changes (as many
-// rounds as the deepest chain, instead of one serial pass over the rows).
+// mask of the groups touching it (LDS atomics, one bit per group) gives each
+// group the previous group on each of its nodes, and the levels are the
+// longest-path depths of that DAG, relaxed over the lanes until no level
+// changes (as many rounds as the deepest chain).
 __device__ __forceinline__ void row_nodes(int inf, int& na, int& nbn) {
   na = node_of(inf & 0xffff);
   nbn = side_kind(inf & 0xffff) == K_LIMIT ? 63 : node_of((inf >> 16) & 0xffff);
+}
+// a row between a free body and a static target (may join its predecessor's group)
+__device__ __forceinline__ bool row_single(int inf) {
+  return side_kind(inf & 0xffff) == K_FREE && side_kind((inf >> 16) & 0xffff) == K_STATIC;
 }
 __device__ __forceinline__ int phase_levels(const KArgs& a, float* L, int NC, int NR, int NL) {
   const int lane = lane_id();
   const LdsLayout& Y = a.L;
   const float* C = L + Y.con;
   const int cc = Y.ccap;
-  // per level the offset of its rows in `order` and its robot row (0xffff:
-  // none); each row's level.  While the levels are found, loff and rob hold
-  // each row's previous row on its first and second node (0xffff: none).
-  uint16_t* loff = reinterpret_cast<uint16_t*>(L + Y.lvl);  // [cc + 2]
-  uint16_t* rob = loff + cc + 2;                            // [cc + 2]
-  uint16_t* order = rob + cc + 2;                           // [cc]
-  uint16_t* lvl = order + cc;                               // [cc]
-  const int nch = (NC + WAVE - 1) / WAVE;
+  // per level the offset of its groups in `order` and its robot row (0xffff:
+  // none); the groups of each level (first row | rows << 16); each group's
+  // level and first row.  While the levels are found, loff and rob hold each
+  // group's previous group on its first and second node (0xffff: none).
+  uint16_t* loff = reinterpret_cast<uint16_t*>(L + Y.lvl);     // [cc + 2]
+  uint16_t* rob = loff + cc + 2;                               // [cc + 2]
+  uint32_t* order = reinterpret_cast<uint32_t*>(rob + cc + 2);  // [cc]
+  uint16_t* lvl = reinterpret_cast<uint16_t*>(order + cc);     // [cc]
+  uint16_t* gfirst = lvl + cc;                                 // [cc + 1]
+  // group starts and first rows
+  int NG = 0;
+  for (int base = 0; base < NC; base += WAVE) {
+    const int r = base + lane;
+    bool st = false;
+    if (r < NC) {
+      const int inf = __float_as_int(C[r * CSTR + C_INFO]);
+      st = true;
+      if (r > 0 && row_single(inf)) {
+        const int pinf = __float_as_int(C[(r - 1) * CSTR + C_INFO]);
+        st = !(row_single(pinf) && (pinf & 0xffff) == (inf & 0xffff));
+      }
+    }
+    const uint64_t mk = __ballot(st);
+    if (st) gfirst[NG + prefix_below(mk)] = (uint16_t)r;
+    NG += __popcll(mk);
+  }
+  if (lane == 0) gfirst[NG] = (uint16_t)NC;
+  const int nch = (NG + WAVE - 1) / WAVE;
   const int nnode = 1 + AMAX + Y.fmax;
   unsigned long long* nm = reinterpret_cast<unsigned long long*>(L + Y.cand);  // [nnode][nch]
   for (int e = lane; e < nnode * nch; e += WAVE) nm[e] = 0ull;
-  wave_sync();
+  lds_order();
   for (int ch = 0; ch < nch; ++ch) {
-    const int r = ch * WAVE + lane;
-    if (r < NC) {
+    const int g = ch * WAVE + lane;
+    if (g < NG) {
       int na, nbn;
-      row_nodes(__float_as_int(C[r * CSTR + C_INFO]), na, nbn);
+      row_nodes(__float_as_int(C[gfirst[g] * CSTR + C_INFO]), na, nbn);
       const unsigned long long bit = 1ull << lane;
       atomicOr(nm + na * nch + ch, bit);
       if (nbn != 63) atomicOr(nm + nbn * nch + ch, bit);
     }
   }
-  wave_sync();
-  // the previous row touching node n before row r (-1: none)
-  auto prev = [&](int n, int r) {
-    int w = r >> 6;
-    unsigned long long m = nm[n * nch + w] & ((1ull << (r & 63)) - 1ull);
+  lds_order();
+  // the previous group touching node n before group g (-1: none)
+  auto prev = [&](int n, int g) {
+    int w = g >> 6;
+    unsigned long long m = nm[n * nch + w] & ((1ull << (g & 63)) - 1ull);
     while (m == 0ull && w > 0) {
       --w;
       m = nm[n * nch + w];
@@ -1583,51 +1612,59 @@ __device__ __forceinline__ int phase_levels(const KArgs& a, float* L, int NC, in
     return m ? w * WAVE + 63 - __clzll((long long)m) : -1;
   };
   for (int ch = 0; ch < nch; ++ch) {
-    const int r = ch * WAVE + lane;
-    if (r < NC) {
+    const int g = ch * WAVE + lane;
+    if (g < NG) {
       int na, nbn;
-      row_nodes(__float_as_int(C[r * CSTR + C_INFO]), na, nbn);
-      const int pa = prev(na, r), pb = nbn == 63 ? -1 : prev(nbn, r);
-      loff[r] = (uint16_t)(pa < 0 ? 0xffff : pa);
-      rob[r] = (uint16_t)(pb < 0 ? 0xffff : pb);
-      lvl[r] = 1;
+      row_nodes(__float_as_int(C[gfirst[g] * CSTR + C_INFO]), na, nbn);
+      const int pa = prev(na, g), pb = nbn == 63 ? -1 : prev(nbn, g);
+      loff[g] = (uint16_t)(pa < 0 ? 0xffff : pa);
+      rob[g] = (uint16_t)(pb < 0 ? 0xffff : pb);
+      lvl[g] = 1;
     }
   }
-  wave_sync();
-  // relax: level(r) = 1 + max(level(prev on node A), level(prev on node B))
+  lds_order();
+  // relax: level(g) = 1 + max(level(prev on node A), level(prev on node B))
   for (;;) {
     bool changed = false;
     for (int ch = 0; ch < nch; ++ch) {
-      const int r = ch * WAVE + lane;
-      if (r < NC) {
-        const int pa = loff[r], pb = rob[r];
+      const int g = ch * WAVE + lane;
+      if (g < NG) {
+        const int pa = loff[g], pb = rob[g];
         const int la = pa == 0xffff ? 0 : lvl[pa], lb = pb == 0xffff ? 0 : lvl[pb];
         const int nl = 1 + max(la, lb);
-        if (nl != lvl[r]) {
-          lvl[r] = (uint16_t)nl;
+        if (nl != lvl[g]) {
+          lvl[g] = (uint16_t)nl;
           changed = true;
         }
       }
     }
     if (!__ballot(changed)) break;
-    wave_sync();
+    lds_order();
   }
   int maxl = 0;
-  for (int r = lane; r < NC; r += WAVE) maxl = max(maxl, (int)lvl[r]);
+  for (int g = lane; g < NG; g += WAVE) maxl = max(maxl, (int)lvl[g]);
   for (int off = 32; off > 0; off >>= 1) maxl = max(maxl, __shfl_xor(maxl, off, WAVE));
-  wave_sync();
+  lds_order();
   for (int e = lane; e <= maxl + 1; e += WAVE) rob[e] = 0xffff;
-  wave_sync();
-  for (int rr = lane; rr < NR; rr += WAVE) rob[lvl[NL + rr]] = (uint16_t)(NL + rr);
+  lds_order();
+  // robot rows are groups of their own: rob[level] = the row
+  for (int g = lane; g < NG; g += WAVE) {
+    const int r = gfirst[g];
+    if (r >= NL && r < NL + NR) rob[lvl[g]] = (uint16_t)r;
+  }
   int pos = 0;
   for (int lv = 1; lv <= maxl; ++lv) {
     if (lane == 0) loff[lv - 1] = (uint16_t)pos;
-    for (int base = 0; base < NC; base += WAVE) {
-      int ci = base + lane;
-      bool isr = ci >= NL && ci < NL + NR;
-      bool m = ci < NC && !isr && lvl[ci] == lv;
+    for (int base = 0; base < NG; base += WAVE) {
+      const int g = base + lane;
+      bool m = false;
+      int r = 0;
+      if (g < NG) {
+        r = gfirst[g];
+        m = !(r >= NL && r < NL + NR) && lvl[g] == lv;
+      }
       uint64_t mk = __ballot(m);
-      if (m) order[pos + prefix_below(mk)] = (uint16_t)ci;
+      if (m) order[pos + prefix_below(mk)] = (uint32_t)r | ((uint32_t)(gfirst[g + 1] - r) << 16);
       pos += __popcll(mk);
     }
   }
@@ -1723,7 +1760,7 @@ __device__ __forceinline__ void phase_pgs(const KArgs& a, const Scene& S, float*
   const Robot RB = robot_view(L + Y.robot, L + Y.dyn);
   const uint16_t* loff = reinterpret_cast<const uint16_t*>(L + Y.lvl);
   const uint16_t* rob = loff + cc + 2;
-  const uint16_t* order = rob + cc + 2;
+  const uint32_t* order = reinterpret_cast<const uint32_t*>(rob + cc + 2);
   const float mu = a.mu;
   const int j = lane & 15;
   // the zero record's velocities (kept zero by every update that uses it)
@@ -1803,7 +1840,60 @@ __device__ __forceinline__ void phase_pgs(const KArgs& a, const Scene& S, float*
       // the level's other rows, one lane each (they share no node)
 #pragma unroll 1
       for (int e = o0 + lane; e < o1; e += WAVE) {
-        const int ci = order[e];
+        const uint32_t ge = order[e];
+        const int gn = ge >> 16;
+        if (gn > 1) {
+          // a group: consecutive rows between one free body and static
+          // targets, in order, with the body's velocities in registers
+          const int c0 = ge & 0xffff;
+          float* fa = F + side_idx(__float_as_int(C[c0 * CSTR + C_INFO]) & 0xffff) * FSTR;
+          const f3 xa = mk3(fa[F_X], fa[F_X + 1], fa[F_X + 2]);
+          f3 va = mk3(fa[F_V], fa[F_V + 1], fa[F_V + 2]), wa = mk3(fa[F_W], fa[F_W + 1], fa[F_W + 2]);
+          const float ima = fa[F_IM];
+          const float i0 = fa[F_II], i1 = fa[F_II + 1], i2 = fa[F_II + 2], i3 = fa[F_II + 3], i4 = fa[F_II + 4],
+                      i5 = fa[F_II + 5];
+#pragma unroll 1
+          for (int ci = c0; ci < c0 + gn; ++ci) {
+            float* c = C + ci * CSTR;
+            const f3 n = mk3(c[C_N], c[C_N + 1], c[C_N + 2]);
+            const f3 p = mk3(c[C_P], c[C_P + 1], c[C_P + 2]);
+            const float iw0 = c[C_IW], iw1 = c[C_IW + 1], iw2 = c[C_IW + 2], bias = c[C_BIAS];
+            const float l0 = c[C_LAM];
+            float l1 = c[C_LAM + 1], l2 = c[C_LAM + 2];
+            const f3 ra = p - xa;
+            const f3 u = va + cross(wa, ra);
+            const float r = dot(n, u) + bias;
+            float nl = l0;
+            if (iw0 > 0.f) nl = fmaxf(0.f, l0 - r * iw0);
+            if (tape) tape[it * a.RL.tsw + ci * 3] = l0 - r * iw0;
+            const float dl = nl - l0;
+            f3 P = n * dl;
+            if (iw1 > 0.f && iw2 > 0.f) {
+              f3 t1, t2;
+              onb_a(n, c[C_ONB], t1, t2);
+              const float u1 = dot(t1, u) + dl * c[C_WTN], u2 = dot(t2, u) + dl * c[C_WTN + 1];
+              float y1, y2;
+              friction_disk(l1, l2, u1, u2, iw1, iw2, mu * nl, y1, y2);
+              if (tape) {
+                tape[it * a.RL.tsw + ci * 3 + 1] = l1 - u1 * iw1;
+                tape[it * a.RL.tsw + ci * 3 + 2] = l2 - u2 * iw2;
+              }
+              P = P + t1 * (y1 - l1) + t2 * (y2 - l2);
+              l1 = y1;
+              l2 = y2;
+            }
+            const f3 q = cross(ra, P);
+            va = va + P * ima;
+            wa = wa + mk3(i0 * q.x + i3 * q.y + i4 * q.z, i3 * q.x + i1 * q.y + i5 * q.z, i4 * q.x + i5 * q.y + i2 * q.z);
+            c[C_LAM] = nl;
+            c[C_LAM + 1] = l1;
+            c[C_LAM + 2] = l2;
+          }
+          fa[F_V] = va.x; fa[F_V + 1] = va.y; fa[F_V + 2] = va.z;
+          fa[F_W] = wa.x; fa[F_W + 1] = wa.y; fa[F_W + 2] = wa.z;
+          continue;
+        }
+        const int ci = ge & 0xffff;
         float* c = C + ci * CSTR;
         const int info = __float_as_int(c[C_INFO]);
         const int sA = info & 0xffff, sB = (info >> 16) & 0xffff;
