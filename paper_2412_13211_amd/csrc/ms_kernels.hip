@@ -883,71 +883,94 @@ __device__ __forceinline__ bool bound_near(const TBound& B, f3 c, float R, float
   return dot(q, q) < lim * lim;
 }
 
+// position of the k-th (from 0) set bit of m (k < popcount(m))
+__device__ __forceinline__ int select_bit(uint64_t m, int k) {
+  int pos = 0;
+  uint32_t x = (uint32_t)m;
+  int c = __popc(x);
+  if (k >= c) {
+    k -= c;
+    pos = 32;
+    x = (uint32_t)(m >> 32);
+  }
+  c = __popc(x & 0xffffu);
+  if (k >= c) { k -= c; pos += 16; x >>= 16; }
+  c = __popc(x & 0xffu);
+  if (k >= c) { k -= c; pos += 8; x >>= 8; }
+  c = __popc(x & 0xfu);
+  if (k >= c) { k -= c; pos += 4; x >>= 4; }
+  c = __popc(x & 0x3u);
+  if (k >= c) { k -= c; pos += 2; x >>= 2; }
+  if (k >= (int)(x & 1u)) pos += 1;
+  return pos;
+}
+
 // Exact tests of bodies' owners against their culled candidates (body b:
 // mem(b) owners from owner index obase(b); candidates: the set bits of its
 // masks, bit j of chunk ch standing for target tgt(ch, j)), packed into full
 // chunks: consecutive bodies are grouped while the group's pairs fit one
-// chunk and its candidate lists fit lst[cap]; a body with more than a chunk
-// of pairs runs alone over several.  Pairs are enumerated (body, owner,
-// candidate) in increasing order, so the contacts come out in canonical order.
+// chunk; a body with more than a chunk of pairs runs alone over several.
+// Pairs are enumerated (body, owner, candidate) in increasing order, so the
+// contacts come out in canonical order.  A lane finds its body by comparing
+// its pair index with the members' first pairs, and its candidate as the
+// set bit of that rank in the body's masks.
 template <class Mem, class Obase, class Tgt>
 __device__ __forceinline__ void exact_grouped(const ConCtx& X, int rcap, int nbod, const uint32_t* msk, int nch,
-                                              Mem mem, Obase obase, Tgt tgt, uint16_t* lst, int cap, EmitState& E) {
+                                              Mem mem, Obase obase, Tgt tgt, EmitState& E) {
   const int lane = lane_id();
   auto mask_of = [&](int b, int ch) -> uint64_t {
     return (uint64_t)msk[(b * nch + ch) * 2] | ((uint64_t)msk[(b * nch + ch) * 2 + 1] << 32);
   };
+  // lane b: body b's candidate count
+  int bcnt = 0;
+  if (lane < nbod)
+    for (int ch = 0; ch < nch; ++ch) bcnt += __popcll(mask_of(lane, ch));
   int b = 0;
   while (b < nbod) {
-    // lane gi: group member gi's first pair, list offset, candidates, owner base, body
-    int ng = 0, pairs = 0, cands = 0;
-    int gP = 0, gQ = 0, gC = 1, gO = 0, gB = 0;
+    // lane gi: group member gi's first pair, candidates, owner base, body
+    int ng = 0, pairs = 0;
+    int gP = 0, gC = 1, gO = 0, gB = 0;
     while (b < nbod) {
-      int cnt = 0;
-      for (int ch = 0; ch < nch; ++ch) cnt += __popcll(mask_of(b, ch));
-      cnt = __builtin_amdgcn_readfirstlane(cnt);
+      const int cnt = __builtin_amdgcn_readlane(bcnt, b);
       const int m = mem(b);
       if (cnt == 0 || m == 0) {
         ++b;
         continue;
       }
-      if (ng > 0 && (pairs + m * cnt > WAVE || cands + cnt > cap)) break;
+      if (ng > 0 && pairs + m * cnt > WAVE) break;
       if (lane == ng) {
         gP = pairs;
-        gQ = cands;
         gC = cnt;
         gO = obase(b);
         gB = b;
       }
       pairs += m * cnt;
-      cands += cnt;
       ++ng;
       ++b;
       if (pairs > WAVE) break;
     }
     if (ng == 0) break;
-    // the members' candidate lists, in target order
-    for (int gi = 0; gi < ng; ++gi) {
-      const int bb = __builtin_amdgcn_readlane(gB, gi);
-      int q = __builtin_amdgcn_readlane(gQ, gi);
-      for (int ch = 0; ch < nch; ++ch) {
-        const uint64_t mk = mask_of(bb, ch);
-        if ((mk >> lane) & 1ull) lst[q + prefix_below(mk)] = (uint16_t)tgt(ch, lane);
-        q += __popcll(mk);
-      }
-    }
     for (int base = 0; base < pairs; base += WAVE) {
       const int idx = base + lane;
       int gi = 0;
       for (int j = 1; j < ng; ++j) gi += idx >= __builtin_amdgcn_readlane(gP, j) ? 1 : 0;
-      const int P = __shfl(gP, gi, WAVE), Q = __shfl(gQ, gi, WAVE), Cn = __shfl(gC, gi, WAVE),
-                O = __shfl(gO, gi, WAVE);
+      const int P = __shfl(gP, gi, WAVE), Cn = __shfl(gC, gi, WAVE), O = __shfl(gO, gi, WAVE),
+                Bb = __shfl(gB, gi, WAVE);
       PairOut po;
       bool isrob = false, hit = false;
       if (idx < pairs) {
         int k, ci;
         divmod(idx - P, Cn, 1.f / (float)Cn, k, ci);
-        hit = eval_pair(X, O + k, lst[Q + ci], po, isrob);
+        int ch = 0;
+        uint64_t m = mask_of(Bb, 0);
+        int c = __popcll(m);
+        while (ci >= c) {
+          ci -= c;
+          ++ch;
+          m = mask_of(Bb, ch);
+          c = __popcll(m);
+        }
+        hit = eval_pair(X, O + k, tgt(ch, select_bit(m, ci)), po, isrob);
       }
       emit(X, rcap, hit, isrob, po, E);
     }
@@ -1070,7 +1093,7 @@ __device__ __forceinline__ void phase_contacts(const KArgs& a, const Scene& S, f
       wave_sync();
       exact_grouped(
           X, a.rcap, S.nb, msk, ncA, [&](int b) { return M->sph_count[b]; }, [&](int b) { return M->sph_first[b]; },
-          [&](int ch, int j) { return (int)listA[ch * WAVE + j]; }, listB, Y.ntmax, E);
+          [&](int ch, int j) { return (int)listA[ch * WAVE + j]; }, E);
     }
     // free bodies.  Bounding-sphere culling, transposed: the lanes hold one
     // 64-target chunk's bounds (loaded once per substep), the bodies' bounds
@@ -1119,8 +1142,7 @@ __device__ __forceinline__ void phase_contacts(const KArgs& a, const Scene& S, f
       wave_sync();
       exact_grouped(
           X, a.rcap, S.nf, msk, nch, [&](int f) { return __builtin_amdgcn_readlane(fmem, f); },
-          [&](int f) { return __builtin_amdgcn_readlane(fob, f); }, [&](int ch, int j) { return ch * WAVE + j; }, listA,
-          2 * Y.ntmax, E);
+          [&](int f) { return __builtin_amdgcn_readlane(fob, f); }, [&](int ch, int j) { return ch * WAVE + j; }, E);
     }
   }
   uint64_t ks = E.ks;
