@@ -181,10 +181,11 @@ enum { F_XB = 0, F_RB = 3, F_IIB = 12, F_IWB = 21, FB = 30 };
 // door / drawer adjoint record
 enum { X_RB = 0, X_BCB = 9, X_QB = 12, XB = 16 };
 
-// level schedule arrays (ints): level of row, rows by level, level offsets,
-// robot row of each level, last level of each dynamic node, counters
+// level schedule arrays (ints): level of row (then of group), groups by
+// level, level offsets, robot row of each level, first row of each group,
+// last level of each dynamic node, counters
 MSA_HD inline int lv_rows(int ccap) { return 2 * AMAX + ccap; }
-MSA_HD inline int lv_ints(int ccap) { return 4 * lv_rows(ccap) + 4 + 64 + 8; }
+MSA_HD inline int lv_ints(int ccap) { return 5 * lv_rows(ccap) + 5 + 64 + 8; }
 
 struct WS {
   int wave;  // the wavefront kernel's LDS layout
@@ -1574,12 +1575,26 @@ struct Eng {
     X.vb += rb * J;
   }
   MSA_HD void contact_bar_reg(int it, int ci, int oi, int tk, int ti) const {
-    const long e = w.con + (long)ci * CR, cb = w.conb + (long)ci * CB, lb = w.lamb + ci * 3;
-    const int row = nlim + ci;
     const bool two = tk == 3;
     FSide A, B;
     fs_load(A, oi, 1.f);
     if (two) fs_load(B, ti, -1.f);
+    contact_bar_core(it, ci, A, B, two);
+    fs_store(A);
+    if (two) fs_store(B);
+  }
+  // reverse of a run of rows ci0 .. ci0 + n - 1 between one free body and
+  // static targets, last row first, with the body's side in registers
+  MSA_HD void contact_group_bar(int it, int ci0, int n) const {
+    FSide A, B;
+    fs_load(A, ids(w.con + (long)ci0 * CR).oi, 1.f);
+    for (int ci = ci0 + n - 1; ci >= ci0; --ci) contact_bar_core(it, ci, A, B, false);
+    fs_store(A);
+  }
+  // the register form's arithmetic between the sides' load and store
+  MSA_HD void contact_bar_core(int it, int ci, FSide& A, FSide& B, bool two) const {
+    const long e = w.con + (long)ci * CR, cb = w.conb + (long)ci * CB, lb = w.lamb + ci * 3;
+    const int row = nlim + ci;
     RowAcc R;
     R.p = v3(e + C_P);
     R.d[0] = v3(e + C_N);
@@ -1649,8 +1664,6 @@ struct Eng {
     at(cb + B_W + 1) += Wb1;
     at(cb + B_W + 2) += Wb2;
     at(cb + B_BIAS) += biasb;
-    fs_store(A);
-    if (two) fs_store(B);
   }
 
   // reverse of contact_update (sweep it): friction pair, then normal

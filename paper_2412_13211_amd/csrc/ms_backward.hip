@@ -60,7 +60,7 @@ __device__ __forceinline__ float sum16_b(float v) { return bcast0(sum16(v)); }
 
 // level-schedule views inside the LDS block
 struct Lv {
-  int *lvl, *order, *loff, *rob, *last, *cnt;
+  int *lvl, *order, *loff, *rob, *gfirst, *last, *cnt;
 };
 __device__ __forceinline__ Lv lv_view(float* L, const msa::WS& w) {
   Lv v;
@@ -70,6 +70,7 @@ __device__ __forceinline__ Lv lv_view(float* L, const msa::WS& w) {
   v.order = p; p += R;
   v.loff = p; p += R + 2;
   v.rob = p; p += R + 2;
+  v.gfirst = p; p += R + 1;
   v.last = p; p += 64;
   v.cnt = p;  // [0] nc, [1] nrob, [2] nlim, [3] maxl, [4] status
   return v;
@@ -902,25 +903,53 @@ __device__ void bwd_scene(const BwdArgs& a, int s, float* L) {
       LV.cnt[4] = (int)E.status;
     }
     wsync();
-    // level schedule: level(r) = 1 + the largest level of the earlier rows
-    // sharing a dynamic node.  Each row's nodes packed per lane; then one
-    // pass over the rows with the last level of node j in lane j's register
-    // (read with readlane); then per-level counts, offsets and the order
+    // level schedule.  Rows are merged into groups first: a run of
+    // consecutive rows between one free body and static targets is one group
+    // (reversed by one lane, last row first, with the body in registers);
+    // every other row is a group of its own.  level(g) = 1 + the largest
+    // level of the earlier groups sharing a dynamic node.  Each row's nodes
+    // packed per lane; the groups' first rows; one pass over the groups with
+    // the last level of node j in lane j's register (read with readlane);
+    // then per-level counts, offsets and the order (entries: first row |
+    // rows << 16)
     E.nlim = LV.cnt[2];
     {
       const int R = E.nlim + E.nc;
       for (int r = lane; r < R; r += 64) {
         int n1, n2;
         row_nodes(E, r, n1, n2);
-        const bool robot = r >= E.nlim && E.ids(w.con + (long)(r - E.nlim) * CR).ok == 0;
-        LV.lvl[r] = n1 | ((n2 + 1) << 8) | (robot ? 1 << 16 : 0);
+        bool robot = false, single = false;
+        if (r >= E.nlim) {
+          const Ids id = E.ids(w.con + (long)(r - E.nlim) * CR);
+          robot = id.ok == 0;
+          single = id.ok != 0 && (id.tk == 0 || id.tk == 1);
+        }
+        LV.lvl[r] = n1 | ((n2 + 1) << 8) | (robot ? 1 << 16 : 0) | (single ? 1 << 17 : 0);
       }
       wsync();
-      int last = 0, maxl = 0;
+      int G = 0;
       for (int base = 0; base < R; base += 64) {
-        const int pkv = base + lane < R ? LV.lvl[base + lane] : 0;
+        const int r = base + lane;
+        bool st = false;
+        if (r < R) {
+          const int pk = LV.lvl[r];
+          st = true;
+          if (r > 0 && (pk >> 17) & 1) {
+            const int pp = LV.lvl[r - 1];
+            st = !(((pp >> 17) & 1) && (pp & 0xff) == (pk & 0xff));
+          }
+        }
+        const uint64_t mk = __ballot(st);
+        if (st) LV.gfirst[G + __popcll(mk & ((1ull << lane) - 1ull))] = r;
+        G += __popcll(mk);
+      }
+      if (lane == 0) LV.gfirst[G] = R;
+      wsync();
+      int last = 0, maxl = 0;
+      for (int base = 0; base < G; base += 64) {
+        const int pkv = base + lane < G ? LV.lvl[LV.gfirst[base + lane]] : 0;
         int mine = 0;
-        const int n = R - base < 64 ? R - base : 64;
+        const int n = G - base < 64 ? G - base : 64;
         for (int k = 0; k < n; ++k) {
           const int pk = __builtin_amdgcn_readlane(pkv, k);
           const int n1 = pk & 0xff, n2 = ((pk >> 8) & 0xff) - 1;
@@ -935,16 +964,18 @@ __device__ void bwd_scene(const BwdArgs& a, int s, float* L) {
           maxl = lv > maxl ? lv : maxl;
         }
         wsync();
-        if (base + lane < R) LV.lvl[base + lane] = mine;
+        // group g's first row is at index >= g, so the packs still to be
+        // read (groups past this chunk) are not overwritten
+        if (base + lane < G) LV.lvl[base + lane] = mine;
       }
       for (int l = lane; l <= maxl + 1; l += 64) {
         LV.loff[l] = 0;
         LV.rob[l] = -1;
       }
       wsync();
-      for (int r = lane; r < R; r += 64) {
-        const int v = LV.lvl[r], lv = v & 0xffff;
-        if (v >> 16) LV.rob[lv] = r;
+      for (int g = lane; g < G; g += 64) {
+        const int v = LV.lvl[g], lv = v & 0xffff;
+        if (v >> 16) LV.rob[lv] = LV.gfirst[g];
         else atomicAdd(&LV.loff[lv], 1);
       }
       wsync();
@@ -958,12 +989,15 @@ __device__ void bwd_scene(const BwdArgs& a, int s, float* L) {
         LV.loff[maxl] = acc;
       }
       wsync();
-      // fill (rows of one level touch disjoint bodies, so their order within
-      // the level does not change any result): loff[l - 1] is the running
-      // write position of level l
-      for (int r = lane; r < R; r += 64) {
-        const int v = LV.lvl[r];
-        if (!(v >> 16)) LV.order[atomicAdd(&LV.loff[(v & 0xffff) - 1], 1)] = r;
+      // fill (groups of one level touch disjoint bodies, so their order
+      // within the level does not change any result): loff[l - 1] is the
+      // running write position of level l
+      for (int g = lane; g < G; g += 64) {
+        const int v = LV.lvl[g];
+        if (!(v >> 16)) {
+          const int r0 = LV.gfirst[g];
+          LV.order[atomicAdd(&LV.loff[(v & 0xffff) - 1], 1)] = r0 | ((LV.gfirst[g + 1] - r0) << 16);
+        }
       }
       wsync();
       if (lane == 0) {
@@ -1032,8 +1066,9 @@ __device__ void bwd_scene(const BwdArgs& a, int s, float* L) {
         if (rr >= 0) robot_contact_bar(E, it, rr - E.nlim, L);
         const int o0 = LV.loff[lv - 1], o1 = LV.loff[lv];
         for (int k = o0 + lane; k < o1; k += 64) {
-          const int r = LV.order[k];
-          if (r < E.nlim) E.limit_bar(it, r);
+          const int ge = LV.order[k], r = ge & 0xffff, gn = ge >> 16;
+          if (gn > 1) E.contact_group_bar(it, r - E.nlim, gn);
+          else if (r < E.nlim) E.limit_bar(it, r);
           else E.contact_bar(it, r - E.nlim);
         }
         lds_order();
@@ -1049,9 +1084,11 @@ __device__ void bwd_scene(const BwdArgs& a, int s, float* L) {
       if (rr >= 0 && lane == 0) E.rows_bar_one(rr - E.nlim, false);
       const int o0 = LV.loff[lv - 1], o1 = LV.loff[lv];
       for (int k = o0 + lane; k < o1; k += 64) {
-        const int r = LV.order[k];
-        if (r < E.nlim) E.rows_bar_limit(r);
-        else E.rows_bar_one(r - E.nlim, false);
+        const int ge = LV.order[k], r0 = ge & 0xffff, gn = ge >> 16;
+        for (int r = r0; r < r0 + gn; ++r) {
+          if (r < E.nlim) E.rows_bar_limit(r);
+          else E.rows_bar_one(r - E.nlim, false);
+        }
       }
       wsync();
     }
@@ -1065,8 +1102,9 @@ __device__ void bwd_scene(const BwdArgs& a, int s, float* L) {
       if (rr >= 0 && lane == 0) E.contact_geom_bar(rr - E.nlim);
       const int o0 = LV.loff[lv - 1], o1 = LV.loff[lv];
       for (int k = o0 + lane; k < o1; k += 64) {
-        const int r = LV.order[k];
-        if (r >= E.nlim) E.contact_geom_bar(r - E.nlim);
+        const int ge = LV.order[k], r0 = ge & 0xffff, gn = ge >> 16;
+        for (int r = r0; r < r0 + gn; ++r)
+          if (r >= E.nlim) E.contact_geom_bar(r - E.nlim);
       }
       wsync();
     }
