@@ -88,7 +88,8 @@ constexpr int ROBOT_FLOATS = 5 * ND + ND * 9 + ND * 3 + ND * 6 + ND * ND;
 // [16*BI_FLOATS], velocity-product accelerations and body forces [2*16*6],
 // M~ [16*16], tau - C [16].
 constexpr int BI_FLOATS = 11;       // odd stride
-constexpr int DYN_FLOATS = ND * BI_FLOATS + 2 * ND * 6 + ND * ND + ND;
+constexpr int DSUM_FLOATS = 17;     // odd stride: a_i (6), composite inertia (10) / subtree force (6), G_i (6)
+constexpr int DYN_FLOATS = ND * BI_FLOATS + 2 * ND * 6 + ND * ND + ND + ND * DSUM_FLOATS;
 constexpr int FREE_FLOATS = 37;     // per free body (odd stride: conflict-free LDS banks)
 constexpr int FSTR = FREE_FLOATS;
 constexpr int AUX_FLOATS = 32;      // per aux joint

@@ -153,8 +153,9 @@ struct Robot {
   // LDS of the contact list and the robot contact rows, built afterwards):
   // per body COM, mass and world inertia about the COM [16][BI_FLOATS],
   // velocity-product accelerations and body forces [16][6] each, M~ [16][16],
-  // tau - C [16]
-  float *bI, *cc, *fo, *Mt, *rhs;
+  // tau - C [16], the per-body sums of the pair-lane reductions
+  // [16][DSUM_FLOATS]
+  float *bI, *cc, *fo, *Mt, *rhs, *dsum;
 };
 __device__ __forceinline__ Robot robot_view(float* base, float* dyn) {
   Robot r;
@@ -174,6 +175,7 @@ __device__ __forceinline__ Robot robot_view(float* base, float* dyn) {
   r.fo = o; o += ND * 6;
   r.Mt = o; o += ND * ND;
   r.rhs = o; o += ND;
+  r.dsum = o; o += ND * DSUM_FLOATS;
   return r;
 }
 // free-body fields (structure of arrays, stride fmax)
@@ -1227,10 +1229,17 @@ __device__ __forceinline__ void phase_dynamics(const KArgs& a, const Scene& S, f
     const int r = e / ND, c = e % ND;
     rb.Mt[e] = (r >= nb || c >= nb) && r == c ? 1.f : 0.f;
   }
+  // The sums over a body's ancestors or descendants run over pair lanes: in
+  // each of four rounds, row q (lanes 16 q .. 16 q + 15) serves body
+  // i = 4 r + q and lane k of the row the other body k; the row's 16 terms
+  // are added by a 16-lane reduction, and lane 0 of the row leaves the sum in
+  // LDS for body i's own lane.  (One lane per body looping over the other
+  // bodies made each sum a chain of 16 dependent LDS rounds.)
+  const int q = lane >> 4, kq = lane & 15;
   // pass 1 (lane per body): COM and world inertia about the COM (kept for the
-  // subtree sums); twist v_i = sum over k in anc-or-self(i) of s_k qd_k at
-  // p_i; the velocity-product acceleration c_i = v_i x (s_i qd_i); the
-  // velocity-product force p_i = v_i x* (I_i v_i)
+  // subtree sums); (pair lanes) twist v_i = sum over k in anc-or-self(i) of
+  // s_k qd_k at p_i; (lane per body) the velocity-product acceleration
+  // c_i = v_i x (s_i qd_i) and force p_i = v_i x* (I_i v_i)
   RI Ib{0.f, {0.f, 0.f, 0.f}, {0.f, 0.f, 0.f, 0.f, 0.f, 0.f}};
   float vp[6] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
   f3 pi = mk3(0.f, 0.f, 0.f);
@@ -1247,8 +1256,8 @@ __device__ __forceinline__ void phase_dynamics(const KArgs& a, const Scene& S, f
     const int rr[6] = {0, 1, 2, 0, 0, 1}, cc6[6] = {0, 1, 2, 1, 2, 2};
 #pragma unroll
     for (int t = 0; t < 6; ++t) {
-      const int r = rr[t], q = cc6[t];
-      Jc[t] = RB[r * 3] * R[q * 3] + RB[r * 3 + 1] * R[q * 3 + 1] + RB[r * 3 + 2] * R[q * 3 + 2];
+      const int r = rr[t], qq = cc6[t];
+      Jc[t] = RB[r * 3] * R[qq * 3] + RB[r * 3 + 1] * R[qq * 3 + 1] + RB[r * 3 + 2] * R[qq * 3 + 2];
     }
     const float m = M->mass[i];
     ri_add(Ib, m, d, Jc);
@@ -1256,17 +1265,25 @@ __device__ __forceinline__ void phase_dynamics(const KArgs& a, const Scene& S, f
     bI[0] = pi.x + d.x; bI[1] = pi.y + d.y; bI[2] = pi.z + d.z;
     bI[3] = m;
     for (int t = 0; t < 6; ++t) bI[4 + t] = Jc[t];
-    float v[6] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
-    const int am = M->anc[i];
-    #pragma unroll 1
-    for (int k = 0; k < nb; ++k)
-      if ((am >> k) & 1) {
-        float sk[6];
-        s_at(rb, M, k, pi, sk);
-        const float qd = rb.qd[k];
-        for (int t = 0; t < 6; ++t) v[t] += sk[t] * qd;
-      }
-    float vJ[6], Iv[6];
+  }
+  for (int r0 = 0; r0 < nb; r0 += 4) {
+    const int i = r0 + q;
+    float t6[6] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
+    if (i < nb && kq < nb && ((M->anc[i] >> kq) & 1)) {
+      float sk[6];
+      s_at(rb, M, kq, body_p(rb, i), sk);
+      const float qd = rb.qd[kq];
+      for (int t = 0; t < 6; ++t) t6[t] = sk[t] * qd;
+    }
+    for (int t = 0; t < 6; ++t) t6[t] = sum16(t6[t]);
+    if (kq == 0 && i < nb)
+      for (int t = 0; t < 6; ++t) rb.fo[i * 6 + t] = t6[t];  // v_i (fo is free until pass 2 ends)
+  }
+  lds_order();
+  if (lane < nb) {
+    const int i = lane;
+    float v[6], vJ[6], Iv[6];
+    for (int t = 0; t < 6; ++t) v[t] = rb.fo[i * 6 + t];
     const float qd = rb.qd[i];
     for (int t = 0; t < 6; ++t) vJ[t] = rb.s[i * 6 + t] * qd;
     crm(v, vJ, rb.cc + i * 6);
@@ -1274,63 +1291,86 @@ __device__ __forceinline__ void phase_dynamics(const KArgs& a, const Scene& S, f
     crf(v, Iv, vp);
   }
   wave_sync();
-  // pass 2 (lane per body): bias acceleration (qdd = 0, gravity as the base's
+  // pass 2 (pair lanes): bias acceleration (qdd = 0, gravity as the base's
   // acceleration -g) a_i = -g + sum over anc-or-self of c_k, taken to p_i;
-  // body force f_i = I_i a_i + p_i; the subtree's composite inertia about p_i
+  // the subtree's composite inertia about p_i; then (lane per body) the body
+  // force f_i = I_i a_i + p_i
+  for (int r0 = 0; r0 < nb; r0 += 4) {
+    const int i = r0 + q;
+    float ta[6] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
+    RI tc{0.f, {0.f, 0.f, 0.f}, {0.f, 0.f, 0.f, 0.f, 0.f, 0.f}};
+    if (i < nb && kq < nb) {
+      const f3 p_i = body_p(rb, i);
+      if ((M->anc[i] >> kq) & 1) shift_motion(rb.cc + kq * 6, p_i - body_p(rb, kq), ta);
+      if ((M->anc[kq] >> i) & 1) {
+        const float* bk = rb.bI + kq * BI_FLOATS;
+        ri_add(tc, bk[3], mk3(bk[0], bk[1], bk[2]) - p_i, bk + 4);
+      }
+    }
+    for (int t = 0; t < 6; ++t) ta[t] = sum16(ta[t]);
+    tc.m = sum16(tc.m);
+    for (int t = 0; t < 3; ++t) tc.h[t] = sum16(tc.h[t]);
+    for (int t = 0; t < 6; ++t) tc.J[t] = sum16(tc.J[t]);
+    if (kq == 0 && i < nb) {
+      float* o = rb.dsum + i * DSUM_FLOATS;
+      for (int t = 0; t < 6; ++t) o[t] = ta[t];
+      o[6] = tc.m;
+      for (int t = 0; t < 3; ++t) o[7 + t] = tc.h[t];
+      for (int t = 0; t < 6; ++t) o[10 + t] = tc.J[t];
+    }
+  }
+  lds_order();
   RI Ic{0.f, {0.f, 0.f, 0.f}, {0.f, 0.f, 0.f, 0.f, 0.f, 0.f}};
   if (lane < nb) {
     const int i = lane;
-    float acc6[6] = {0.f, 0.f, 0.f, -a.g[0], -a.g[1], -a.g[2]};
-    const int am = M->anc[i];
-    #pragma unroll 1
-    for (int k = 0; k < nb; ++k) {
-      if ((am >> k) & 1) {
-        float ck[6];
-        shift_motion(rb.cc + k * 6, pi - body_p(rb, k), ck);
-        for (int t = 0; t < 6; ++t) acc6[t] += ck[t];
-      }
-      if ((M->anc[k] >> i) & 1) {
-        const float* bk = rb.bI + k * BI_FLOATS;
-        ri_add(Ic, bk[3], mk3(bk[0], bk[1], bk[2]) - pi, bk + 4);
-      }
-    }
+    const float* o = rb.dsum + i * DSUM_FLOATS;
+    float acc6[6] = {o[0], o[1], o[2], o[3] - a.g[0], o[4] - a.g[1], o[5] - a.g[2]};
+    Ic.m = o[6];
+    for (int t = 0; t < 3; ++t) Ic.h[t] = o[7 + t];
+    for (int t = 0; t < 6; ++t) Ic.J[t] = o[10 + t];
     float fi[6];
     ri_apply(Ib, acc6, fi);
     for (int t = 0; t < 6; ++t) rb.fo[i * 6 + t] = fi[t] + vp[t];
   }
   wave_sync();
-  // pass 3 (lane per body): C_i = s_i . (sum of the subtree's body forces at
-  // p_i); row i of M~: M_ij = s_j . (I^c_i s_i) for j in anc-or-self(i), all
-  // at p_i, plus the armature on the diagonal; the right-hand side tau - C
+  // pass 3: (pair lanes) the subtree's body forces at p_i; (lane per body)
+  // C_i = s_i . that sum, the right-hand side tau - C, G_i = I^c_i s_i and
+  // M_ii; (pair lanes) M_ij = s_j . G_i for j a strict ancestor of i, all at
+  // p_i, plus the armature on the diagonal
+  for (int r0 = 0; r0 < nb; r0 += 4) {
+    const int i = r0 + q;
+    float tf[6] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
+    if (i < nb && kq < nb && ((M->anc[kq] >> i) & 1))
+      shift_force(rb.fo + kq * 6, body_p(rb, kq) - body_p(rb, i), tf);
+    for (int t = 0; t < 6; ++t) tf[t] = sum16(tf[t]);
+    if (kq == 0 && i < nb)
+      for (int t = 0; t < 6; ++t) rb.dsum[i * DSUM_FLOATS + t] = tf[t];
+  }
+  lds_order();
   if (lane < nb) {
     const int i = lane;
-    float F[6] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
-    #pragma unroll 1
-    for (int k = 0; k < nb; ++k)
-      if ((M->anc[k] >> i) & 1) {
-        float fk[6];
-        shift_force(rb.fo + k * 6, body_p(rb, k) - pi, fk);
-        for (int t = 0; t < 6; ++t) F[t] += fk[t];
-      }
     const float* si = rb.s + i * 6;
     float C = 0.f, G[6];
-    for (int t = 0; t < 6; ++t) C += si[t] * F[t];
+    for (int t = 0; t < 6; ++t) C += si[t] * rb.dsum[i * DSUM_FLOATS + t];
     rb.rhs[i] = rb.tau[i] - C;
     ri_apply(Ic, si, G);
     float Mii = 0.f;
     for (int t = 0; t < 6; ++t) Mii += si[t] * G[t];
     rb.Mt[i * ND + i] = Mii + rb.arm[i];
-    const int am = M->anc[i];
-    #pragma unroll 1
-    for (int j = 0; j < i; ++j)
-      if ((am >> j) & 1) {
-        float sj[6];
-        s_at(rb, M, j, pi, sj);
-        float v = 0.f;
-        for (int t = 0; t < 6; ++t) v += sj[t] * G[t];
-        rb.Mt[i * ND + j] = v;
-        rb.Mt[j * ND + i] = v;
-      }
+    for (int t = 0; t < 6; ++t) rb.dsum[i * DSUM_FLOATS + 6 + t] = G[t];
+  }
+  lds_order();
+  for (int r0 = 0; r0 < nb; r0 += 4) {
+    const int i = r0 + q, j = kq;
+    if (i < nb && j < i && ((M->anc[i] >> j) & 1)) {
+      float sj[6];
+      s_at(rb, M, j, body_p(rb, i), sj);
+      const float* G = rb.dsum + i * DSUM_FLOATS + 6;
+      float v = 0.f;
+      for (int t = 0; t < 6; ++t) v += sj[t] * G[t];
+      rb.Mt[i * ND + j] = v;
+      rb.Mt[j * ND + i] = v;
+    }
   }
   wave_sync();
   // M~^-1 by Gauss-Jordan elimination without pivoting (M~ is symmetric
