@@ -1123,22 +1123,29 @@ __device__ __forceinline__ void phase_contacts(const KArgs& a, const Scene& S, f
         if (lane >= off) fob += v;
       }
       fob += S.nsph - fmem;
+      // the bodies' spheres (centre, radius; the radius negative for a free
+      // sphere) where every lane reads them with one broadcast load
+      float4* fbd = reinterpret_cast<float4*>(L + Y.cmask + lds_align4((Y.fmax > ND ? Y.fmax : ND) * Y.nch * 2));
+      if (lane < S.nf) fbd[lane] = make_float4(fc.x, fc.y, fc.z, fb ? fR : -fR);
+      lds_order();
       for (int ch = 0; ch < nch; ++ch) {
         TBound B;
         target_bound(X, ch * WAVE + lane, B);
-#pragma unroll 4
+        uint64_t mym = 0;  // lane f: body f's mask of this chunk
+#pragma unroll 2
         for (int f = 0; f < S.nf; ++f) {
-          const f3 c = mk3(lane_val(fc.x, f), lane_val(fc.y, f), lane_val(fc.z, f));
-          const int fbox = __builtin_amdgcn_readlane(fb, f);
-          bool m = B.valid && bound_near(B, c, lane_val(fR, f), slack);
+          const float4 bd = fbd[f];
+          const bool fbox = bd.w >= 0.f;
+          bool m = B.valid && bound_near(B, mk3(bd.x, bd.y, bd.z), fabsf(bd.w), slack);
           // pair rules of free-body targets: not itself; box vertices skip
           // free spheres; sphere pairs once
           if (B.g >= 0 && (B.g == f || (!B.gbox && (fbox || B.g <= f)))) m = false;
           const uint64_t mk = __ballot(m);
-          if (lane == 0) {
-            msk[(f * nch + ch) * 2] = (uint32_t)mk;
-            msk[(f * nch + ch) * 2 + 1] = (uint32_t)(mk >> 32);
-          }
+          mym = lane == f ? mk : mym;
+        }
+        if (lane < S.nf) {
+          msk[(lane * nch + ch) * 2] = (uint32_t)mym;
+          msk[(lane * nch + ch) * 2 + 1] = (uint32_t)(mym >> 32);
         }
       }
       wave_sync();
