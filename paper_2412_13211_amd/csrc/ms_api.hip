@@ -98,6 +98,8 @@ KArgs make_args(const ms_batch* b, const void* x_in, const float* u, void* x_out
   a.scenes = reinterpret_cast<const DScene*>(b->params + b->pl.scenes);
   a.free = reinterpret_cast<const DFree*>(b->params + b->pl.free);
   a.statics = reinterpret_cast<const float*>(b->params + b->pl.statics);
+  a.sgrid = reinterpret_cast<const float*>(b->params + b->pl.sgrid);
+  a.sg_nw = b->pl.sg_nw;
   a.planes = reinterpret_cast<const float4*>(b->params + b->pl.planes);
   a.aux = reinterpret_cast<const DAux*>(b->params + b->pl.aux);
   a.order = reinterpret_cast<const int*>(b->params + b->pl.order);

@@ -164,11 +164,21 @@ __host__ __device__ inline RecLayout rec_layout(int fmax, int ccap, int K, int n
   return r;
 }
 
+// Per-scene grid over the furniture (xy, SGRID x SGRID cells): a header of
+// four floats (x0, y0, 1 / cell width, 1 / cell depth) then per cell a bit
+// mask over the scene's furniture boxes (sg_nw 64-bit words) of the boxes
+// whose xy extent (grown by 1 mm) overlaps the cell.  A query over the cells
+// a sphere's xy extent overlaps finds every box it can come near.
+constexpr int SGRID = 8;
+__host__ __device__ inline int sgrid_floats(int nw) { return 4 + SGRID * SGRID * nw * 2; }
+
 struct KArgs {
   const DModel* models;
   const DScene* scenes;
   const DFree* free;
   const float* statics;
+  const float* sgrid;      // [S][sgrid_floats(sg_nw)]
+  int sg_nw;
   const float4* planes;
   const DAux* aux;
   const int* order;        // scene processing order (cost-sorted)

@@ -1097,14 +1097,20 @@ __device__ __forceinline__ void phase_contacts(const KArgs& a, const Scene& S, f
           X, a.rcap, S.nb, msk, ncA, [&](int b) { return M->sph_count[b]; }, [&](int b) { return M->sph_first[b]; },
           [&](int ch, int j) { return (int)listA[ch * WAVE + j]; }, E);
     }
-    // free bodies.  Bounding-sphere culling, transposed: the lanes hold one
-    // 64-target chunk's bounds (loaded once per substep), the bodies' bounds
-    // come from their lanes by readlane, and one ballot per (body, chunk) goes
-    // to the mask table; then the exact tests, grouped.
+    // free bodies.  Bounding-sphere culling in two parts.  Furniture: each
+    // body's lane looks up the cells of the scene's furniture grid its sphere
+    // overlaps and tests only the boxes registered there.  Planes, door /
+    // drawer boxes and free bodies, transposed: the lanes hold a chunk of
+    // those targets' bounds, the loop runs over the bodies (their spheres by
+    // broadcast loads from LDS), one ballot per body and chunk.  Both set the
+    // bodies' bits in the mask table with LDS atomics; then the exact tests,
+    // grouped.  The grid only skips boxes the bounding test would reject, so
+    // the candidates are those of a test against every target.
     {
       const float* F = X.F;
       const int fm = X.fm;
       uint32_t* msk = reinterpret_cast<uint32_t*>(L + Y.cmask);
+      unsigned long long* msk64 = reinterpret_cast<unsigned long long*>(msk);
       const int nch = (NT + WAVE - 1) / WAVE;
       // lane f: body f's bounding sphere, kind and first owner index
       f3 fc = mk3(0.f, 0.f, 0.f);
@@ -1127,11 +1133,51 @@ __device__ __forceinline__ void phase_contacts(const KArgs& a, const Scene& S, f
       // sphere) where every lane reads them with one broadcast load
       float4* fbd = reinterpret_cast<float4*>(L + Y.cmask + lds_align4((Y.fmax > ND ? Y.fmax : ND) * Y.nch * 2));
       if (lane < S.nf) fbd[lane] = make_float4(fc.x, fc.y, fc.z, fb ? fR : -fR);
+      for (int e = lane; e < S.nf * nch; e += WAVE) msk64[e] = 0ull;
       lds_order();
-      for (int ch = 0; ch < nch; ++ch) {
+      // furniture, by the grid (lane per body)
+      if (lane < S.nf && S.ns > 0) {
+        const int nw = a.sg_nw;
+        const float* g = a.sgrid + (size_t)sgrid_floats(nw) * S.s;
+        const unsigned long long* cells = reinterpret_cast<const unsigned long long*>(g + 4);
+        const float reach = fR + slack + 2e-3f;
+        const int x0 = max(0, min(SGRID - 1, (int)floorf((fc.x - reach - g[0]) * g[2])));
+        const int x1 = max(0, min(SGRID - 1, (int)floorf((fc.x + reach - g[0]) * g[2])));
+        const int y0 = max(0, min(SGRID - 1, (int)floorf((fc.y - reach - g[1]) * g[3])));
+        const int y1 = max(0, min(SGRID - 1, (int)floorf((fc.y + reach - g[1]) * g[3])));
+        for (int w = 0; w < nw; ++w) {
+          unsigned long long cand = 0ull;
+          for (int cy = y0; cy <= y1; ++cy)
+            for (int cx = x0; cx <= x1; ++cx) cand |= cells[(cy * SGRID + cx) * nw + w];
+          while (cand) {
+            const int bit = __ffsll((long long)cand) - 1;
+            cand &= cand - 1ull;
+            const int bi = w * 64 + bit;
+            const float* bx = X.St + bi * 6;
+            TBound B;
+            B.valid = true;
+            B.isplane = false;
+            B.ctr = mk3(bx[0], bx[1], bx[2]);
+            B.half = mk3(bx[3], bx[4], bx[5]);
+            B.rt = 0.f;
+            B.pd = 0.f;
+            B.g = -1;
+            B.gbox = 0;
+            if (bound_near(B, fc, fR, slack)) {
+              const int t = S.np + bi;
+              atomicOr(msk64 + lane * nch + (t >> 6), 1ull << (t & 63));
+            }
+          }
+        }
+      }
+      // planes, door / drawer boxes and free bodies (transposed)
+      const int NO = S.np + S.na + S.nf;
+      for (int base = 0; base < NO; base += WAVE) {
+        const int l = base + lane;
+        const int t = l < S.np ? l : S.ns + l;  // the target index of other-target l
         TBound B;
-        target_bound(X, ch * WAVE + lane, B);
-        uint64_t mym = 0;  // lane f: body f's mask of this chunk
+        target_bound(X, l < NO ? t : -1, B);
+        uint64_t mym = 0;  // lane f: body f's bits over this chunk of other targets
 #pragma unroll 2
         for (int f = 0; f < S.nf; ++f) {
           const float4 bd = fbd[f];
@@ -1143,10 +1189,14 @@ __device__ __forceinline__ void phase_contacts(const KArgs& a, const Scene& S, f
           const uint64_t mk = __ballot(m);
           mym = lane == f ? mk : mym;
         }
-        if (lane < S.nf) {
-          msk[(lane * nch + ch) * 2] = (uint32_t)mym;
-          msk[(lane * nch + ch) * 2 + 1] = (uint32_t)(mym >> 32);
-        }
+        if (lane < S.nf)
+          while (mym) {
+            const int bit = __ffsll((long long)mym) - 1;
+            mym &= mym - 1ull;
+            const int lo = base + bit;
+            const int tt = lo < S.np ? lo : S.ns + lo;
+            atomicOr(msk64 + lane * nch + (tt >> 6), 1ull << (tt & 63));
+          }
       }
       wave_sync();
       exact_grouped(

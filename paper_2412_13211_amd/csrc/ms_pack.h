@@ -135,7 +135,8 @@ inline void quat_R(const float* q, float* R) {
 }
 
 struct ParamLayout {
-  size_t models, scenes, free, statics, planes, aux, order, free_off, aux_off, total;
+  size_t models, scenes, free, statics, sgrid, planes, aux, order, free_off, aux_off, total;
+  int sg_nw;  // 64-bit words per furniture grid cell
 };
 
 inline ParamLayout param_layout(const Counts& c) {
@@ -145,6 +146,8 @@ inline ParamLayout param_layout(const Counts& c) {
   p.scenes = o; o = align256(o + sizeof(DScene) * c.S);
   p.free = o; o = align256(o + sizeof(DFree) * std::max(c.NF, 1));
   p.statics = o; o = align256(o + sizeof(float) * 6 * std::max(c.NS, 1));
+  p.sg_nw = std::max((c.smax + 63) / 64, 1);
+  p.sgrid = o; o = align256(o + sizeof(float) * (size_t)sgrid_floats(p.sg_nw) * c.S);
   p.planes = o; o = align256(o + sizeof(float4) * std::max(c.NP, 1));
   p.aux = o; o = align256(o + sizeof(DAux) * std::max(c.NA, 1));
   p.order = o; o = align256(o + sizeof(int) * c.S);
@@ -290,6 +293,39 @@ inline void pack_params(const ms_scene_desc* sc, const Counts& c, const ParamLay
     fr[f].mass = sc->free_mass[f];
   }
   if (c.NS > 0) std::memcpy(host.data() + pl.statics, sc->static_box, sizeof(float) * 6 * c.NS);
+  // furniture grids (see KArgs::sgrid): cells over the xy extent of the
+  // scene's boxes; a box goes into every cell its xy extent grown by 1 mm
+  // overlaps (double arithmetic, so the float query on the device, which
+  // grows its own extent by more, never misses one)
+  for (int s = 0; s < c.S; ++s) {
+    float* g = reinterpret_cast<float*>(host.data() + pl.sgrid) + (size_t)sgrid_floats(pl.sg_nw) * s;
+    const int s0 = sc->static_off[s], ns = sc->static_off[s + 1] - s0;
+    double lo[2] = {0.0, 0.0}, hi[2] = {1.0, 1.0};
+    for (int i = 0; i < ns; ++i)
+      for (int d = 0; d < 2; ++d) {
+        const double a = (double)sc->static_box[(s0 + i) * 6 + d] - sc->static_box[(s0 + i) * 6 + 3 + d];
+        const double b = (double)sc->static_box[(s0 + i) * 6 + d] + sc->static_box[(s0 + i) * 6 + 3 + d];
+        lo[d] = i == 0 ? a : std::min(lo[d], a);
+        hi[d] = i == 0 ? b : std::max(hi[d], b);
+      }
+    double inv[2];
+    for (int d = 0; d < 2; ++d) inv[d] = SGRID / std::max(hi[d] - lo[d], 1e-3);
+    g[0] = (float)lo[0];
+    g[1] = (float)lo[1];
+    g[2] = (float)inv[0];
+    g[3] = (float)inv[1];
+    uint64_t* cells = reinterpret_cast<uint64_t*>(g + 4);
+    for (int i = 0; i < ns; ++i) {
+      int c0[2], c1[2];
+      for (int d = 0; d < 2; ++d) {
+        const double ctr = sc->static_box[(s0 + i) * 6 + d], half = sc->static_box[(s0 + i) * 6 + 3 + d];
+        c0[d] = std::max(0, std::min(SGRID - 1, (int)std::floor((ctr - half - 1e-3 - lo[d]) * inv[d])));
+        c1[d] = std::max(0, std::min(SGRID - 1, (int)std::floor((ctr + half + 1e-3 - lo[d]) * inv[d])));
+      }
+      for (int y = c0[1]; y <= c1[1]; ++y)
+        for (int x = c0[0]; x <= c1[0]; ++x) cells[(y * SGRID + x) * pl.sg_nw + i / 64] |= 1ull << (i % 64);
+    }
+  }
   if (c.NP > 0) std::memcpy(host.data() + pl.planes, sc->plane, sizeof(float) * 4 * c.NP);
   DAux* ax = reinterpret_cast<DAux*>(host.data() + pl.aux);
   for (int x = 0; x < c.NA; ++x) {
