@@ -248,6 +248,7 @@ struct Scene {
   const DModel* M;
   const float* hold;  // [16] hold targets (global)
   int s, nb, nsph, nf, ns, np, na, nfo, f0, s0, p0, a0;
+  float gx0, gy0, gix, giy;  // furniture grid: origin and inverse cell sizes (xy)
 };
 
 __device__ __forceinline__ void load_scene(const KArgs& a, const Scene& S, float* L, const Robot& rb) {
@@ -1060,8 +1061,35 @@ __device__ __forceinline__ void phase_contacts(const KArgs& a, const Scene& S, f
         hi.y = fmaxf(hi.y, __shfl_xor(hi.y, off, WAVE)); hi.z = fmaxf(hi.z, __shfl_xor(hi.z, off, WAVE));
       }
       f3 bc = (lo + hi) * 0.5f, he = (hi - lo) * 0.5f;
-      const int nra = compact(NT, listA, [](int i) { return i; },
-                              [&](int t) { return box_near_target(X, bc, he, t, slack); });
+      // the robot's candidate targets in increasing order; the furniture
+      // boxes of four chunks are loaded together
+      int nra = 0;
+      for (int base = 0; base < NT; base += 4 * WAVE) {
+        float bx[4][6];
+        if (S.ns > 0) {
+#pragma unroll
+          for (int u = 0; u < 4; ++u) {
+            const int si = max(0, min(S.ns - 1, base + u * WAVE + lane - S.np));
+#pragma unroll
+            for (int e = 0; e < 6; ++e) bx[u][e] = X.St[si * 6 + e];
+          }
+        }
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+          const int t = base + u * WAVE + lane;
+          bool m = false;
+          if (t < NT) {
+            if (t >= S.np && t < S.np + S.ns)
+              m = fabsf(bc.x - bx[u][0]) < he.x + bx[u][3] + slack && fabsf(bc.y - bx[u][1]) < he.y + bx[u][4] + slack &&
+                  fabsf(bc.z - bx[u][2]) < he.z + bx[u][5] + slack;
+            else
+              m = box_near_target(X, bc, he, t, slack);
+          }
+          const uint64_t mk = __ballot(m);
+          if (m) listA[nra + prefix_below(mk)] = (uint16_t)t;
+          nra += __popcll(mk);
+        }
+      }
       // the robot bodies' bounding spheres against the robot's candidates,
       // transposed as for the free bodies below: lanes over a chunk of the
       // candidates, a loop over the bodies, one ballot per (body, chunk)
@@ -1135,38 +1163,83 @@ __device__ __forceinline__ void phase_contacts(const KArgs& a, const Scene& S, f
       if (lane < S.nf) fbd[lane] = make_float4(fc.x, fc.y, fc.z, fb ? fR : -fR);
       for (int e = lane; e < S.nf * nch; e += WAVE) msk64[e] = 0ull;
       lds_order();
-      // furniture, by the grid (lane per body)
+      // furniture, by the grid (lane per body): the words of every cell the
+      // sphere overlaps are loaded together, then the candidates' boxes four
+      // at a time
       if (lane < S.nf && S.ns > 0) {
-        const int nw = a.sg_nw;
-        const float* g = a.sgrid + (size_t)sgrid_floats(nw) * S.s;
-        const unsigned long long* cells = reinterpret_cast<const unsigned long long*>(g + 4);
+        const int nw = a.sg_nw, nws = (S.ns + WAVE - 1) / WAVE;
+        const unsigned long long* cells =
+            reinterpret_cast<const unsigned long long*>(a.sgrid + (size_t)sgrid_floats(nw) * S.s + 4);
         const float reach = fR + slack + 2e-3f;
-        const int x0 = max(0, min(SGRID - 1, (int)floorf((fc.x - reach - g[0]) * g[2])));
-        const int x1 = max(0, min(SGRID - 1, (int)floorf((fc.x + reach - g[0]) * g[2])));
-        const int y0 = max(0, min(SGRID - 1, (int)floorf((fc.y - reach - g[1]) * g[3])));
-        const int y1 = max(0, min(SGRID - 1, (int)floorf((fc.y + reach - g[1]) * g[3])));
-        for (int w = 0; w < nw; ++w) {
-          unsigned long long cand = 0ull;
-          for (int cy = y0; cy <= y1; ++cy)
-            for (int cx = x0; cx <= x1; ++cx) cand |= cells[(cy * SGRID + cx) * nw + w];
-          while (cand) {
-            const int bit = __ffsll((long long)cand) - 1;
-            cand &= cand - 1ull;
-            const int bi = w * 64 + bit;
-            const float* bx = X.St + bi * 6;
-            TBound B;
-            B.valid = true;
-            B.isplane = false;
-            B.ctr = mk3(bx[0], bx[1], bx[2]);
-            B.half = mk3(bx[3], bx[4], bx[5]);
-            B.rt = 0.f;
-            B.pd = 0.f;
-            B.g = -1;
-            B.gbox = 0;
-            if (bound_near(B, fc, fR, slack)) {
-              const int t = S.np + bi;
-              atomicOr(msk64 + lane * nch + (t >> 6), 1ull << (t & 63));
+        const int x0 = max(0, min(SGRID - 1, (int)floorf((fc.x - reach - S.gx0) * S.gix)));
+        const int x1 = max(0, min(SGRID - 1, (int)floorf((fc.x + reach - S.gx0) * S.gix)));
+        const int y0 = max(0, min(SGRID - 1, (int)floorf((fc.y - reach - S.gy0) * S.giy)));
+        const int y1 = max(0, min(SGRID - 1, (int)floorf((fc.y + reach - S.gy0) * S.giy)));
+        const int ncell = (x1 - x0 + 1) * (y1 - y0 + 1);
+        for (int wg = 0; wg < nws; wg += 4) {
+          unsigned long long cw[4] = {0ull, 0ull, 0ull, 0ull};
+          int cx = x0, cy = y0;
+          for (int k0 = 0; k0 < ncell; k0 += 4) {
+#pragma unroll
+            for (int kk = 0; kk < 4; ++kk) {
+              const bool kv = k0 + kk < ncell;
+              const unsigned long long* c = cells + (min(cy, y1) * SGRID + cx) * nw;
+#pragma unroll
+              for (int u = 0; u < 4; ++u) {
+                const unsigned long long v = c[min(wg + u, nw - 1)];
+                cw[u] |= (kv && wg + u < nws) ? v : 0ull;
+              }
+              if (++cx > x1) {
+                cx = x0;
+                ++cy;
+              }
             }
+          }
+          // the candidates in increasing order, taken from the words in turn
+          unsigned long long cur = cw[0], n1 = cw[1], n2 = cw[2], n3 = cw[3];
+          int wb = wg * 64;
+          auto refill = [&]() {
+            while (cur == 0ull && (n1 | n2 | n3) != 0ull) {
+              cur = n1;
+              n1 = n2;
+              n2 = n3;
+              n3 = 0ull;
+              wb += 64;
+            }
+          };
+          refill();
+          while (cur) {
+            int bi[4];
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+              refill();
+              bi[u] = cur ? wb + __ffsll((long long)cur) - 1 : -1;
+              cur &= cur - 1ull;
+            }
+            float bx[4][6];
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+              const float* src = X.St + (bi[u] >= 0 ? bi[u] : bi[0]) * 6;
+#pragma unroll
+              for (int e = 0; e < 6; ++e) bx[u][e] = src[e];
+            }
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+              TBound B;
+              B.valid = true;
+              B.isplane = false;
+              B.ctr = mk3(bx[u][0], bx[u][1], bx[u][2]);
+              B.half = mk3(bx[u][3], bx[u][4], bx[u][5]);
+              B.rt = 0.f;
+              B.pd = 0.f;
+              B.g = -1;
+              B.gbox = 0;
+              if (bi[u] >= 0 && bound_near(B, fc, fR, slack)) {
+                const int t = S.np + bi[u];
+                atomicOr(msk64 + lane * nch + (t >> 6), 1ull << (t & 63));
+              }
+            }
+            refill();
           }
         }
       }
@@ -2229,6 +2302,13 @@ __device__ __forceinline__ void run_scene(const KArgs& a, int s, float* L) {
   S.nf = ds.nf; S.ns = ds.ns; S.np = ds.np; S.na = ds.na; S.nfo = ds.nown;
   S.f0 = ds.f0; S.s0 = ds.s0; S.p0 = ds.p0; S.a0 = ds.a0;
   S.hold = a.scenes[s].hold;
+  {
+    const float* g = a.sgrid + (size_t)sgrid_floats(a.sg_nw) * s;
+    S.gx0 = g[0];
+    S.gy0 = g[1];
+    S.gix = g[2];
+    S.giy = g[3];
+  }
   Robot rb = robot_view(L + a.L.robot, L + a.L.dyn);
   const bool prof = a.phase_cycles != nullptr;
   unsigned long long cyc[8] = {0, 0, 0, 0, 0, 0, 0, 0};
