@@ -94,8 +94,8 @@ enum {
   MS_SCHED_BWD_REFERENCE = 32, /* ms_step_backward on the lane-per-scene kernel that
                                   recomputes everything itself (slow; a cross-check) */
   MS_SCHED_STATIC_ORDER = 128,  /* process the scenes in the order fixed at creation
-                                   (by static size) instead of by decreasing cost as the
-                                   previous step measured it (contacts, robot contacts) */
+                                   (by static size) instead of by decreasing time as the
+                                   previous step measured it for each scene */
   MS_SCHED_FWD_ONE_LAUNCH = 256, /* the persistent step in one launch sized for the contact
                                     caps.  Without it, when a smaller contact cap fits more
                                     workgroups per CU, the scenes whose previous-step contact

@@ -167,7 +167,7 @@ int step_mode(const ms_batch* b) { return b->desc.control_mode == MS_CTRL_ACTION
 int fwd_split_rcap(const ms_batch* b) { return std::max(b->desc.robot_contact_cap, 1); }
 
 // Enqueue one control step with the current schedule (no graph).
-// the order of a step's scenes: by the cost keys the previous step wrote
+// the order of a step's scenes: by the scene times the previous step wrote
 // (a counting sort that also zeroes the work counters), the scenes routed to
 // the full layout first when fit_c > 0; or the static order
 void set_step_order(ms_batch* b, KArgs& a, hipStream_t st, int fit_c) {
@@ -460,12 +460,12 @@ ms_status ms_create_batch(const ms_batch_desc* d, const ms_scene_desc* sc, void*
   (void)hipFuncSetAttribute(spawn_check_kernel_ptr(), hipFuncAttributeMaxDynamicSharedMemorySize, (int)b->max_lds);
   (void)hipFuncSetAttribute(step_bwd_wave_ptr(), hipFuncAttributeMaxDynamicSharedMemorySize, (int)b->max_lds);
   choose_bwd_split(b, b->split_c, b->split_r);
-  // status starts at zero; the first step's cost keys follow the static
-  // order (decreasing keys along it)
+  // status starts at zero; the first step's scene times (which order the
+  // step) decrease along the static order
   std::vector<int> cost0(c.S);
   {
     const int* ord = reinterpret_cast<const int*>(host.data() + pl.order);
-    for (int p = 0; p < c.S; ++p) cost0[ord[p]] = 2 * (int)((4095LL * (c.S - 1 - p)) / std::max(c.S - 1, 1));
+    for (int p = 0; p < c.S; ++p) cost0[ord[p]] = (int)std::min<long long>(4096LL * (c.S - p), 0x7fffffffLL);
   }
   hipError_t e = hipMemsetAsync(b->scratch + b->sl.status, 0, sizeof(uint32_t) * c.S, stream);
   if (e == hipSuccess) e = hipMemsetAsync(b->scratch + b->sl.fwd_maxc, 0, sizeof(int) * c.S, stream);

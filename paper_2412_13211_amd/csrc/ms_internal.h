@@ -189,7 +189,7 @@ struct KArgs {
   uint32_t* debug;         // [S][n_sub][4] or null
   unsigned long long* phase_cycles;  // [S][8] shader-clock cycles per phase, or null
   int* queue;              // work counter (persistent schedule)
-  int* cost;               // [S] cost keys the step writes for the next step's order, or null
+  int* cost;               // [S] each scene's time in the step (shader clock / 16), for the next step's order, or null
   int* maxc;               // [S] largest contact count | largest robot-contact count << 16 over the step's substeps, or null
   // split launches (persistent only): 0 takes every position of the order;
   // 1 the positions from *n_over on, leaving a scene whose contact lists
@@ -216,7 +216,7 @@ struct KArgs {
 
 void launch_step(const KArgs& a, int grid, size_t lds_bytes, hipStream_t st);
 void launch_reset_queue(int* q, hipStream_t st);
-// order = the scenes by decreasing cost key (cost >> 1, clamped to [0, 4095]),
+// order = the scenes by decreasing cost (a scene time; keyed by its logarithm),
 // those whose last contact counts (maxc) do not leave 8 contacts and 2 robot
 // contacts of room under (fit_c, fit_r) first (fit_c = 0: none), *n_over
 // their count; also zeroes the work counters q[0..2] and the retry count

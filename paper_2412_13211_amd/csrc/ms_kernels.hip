@@ -1545,13 +1545,14 @@ __device__ __forceinline__ void phase_dynamics(const KArgs& a, const Scene& S, f
     }
   }
   wave_sync();
-  // unconstrained robot velocity qd + h M~^-1 (tau - C), held in lanes 0..15
-  vR = 0.f;
-  if (lane < ND) {
+  // unconstrained robot velocity qd + h M~^-1 (tau - C): joint j in lane j
+  // of each 16-lane row (the four copies are equal)
+  {
+    const int j = lane & 15;
     float qdd = 0.f;
-    if (lane < nb)
-      for (int k = 0; k < nb; ++k) qdd += rb.Minv[lane * ND + k] * rb.rhs[k];
-    vR = rb.qd[lane] + a.h * qdd;
+    if (j < nb)
+      for (int k = 0; k < nb; ++k) qdd += rb.Minv[j * ND + k] * rb.rhs[k];
+    vR = rb.qd[j] + a.h * qdd;
   }
   // free bodies: v* = v + h g ; w* = w - h Iw^-1 (w x Iw w)
   float* F = L + a.L.fr;
@@ -1700,8 +1701,17 @@ __device__ __forceinline__ void phase_rows(const KArgs& a, const Scene& S, float
     if (d < 3) {
 #pragma unroll
       for (int k = 0; k < ND; ++k) w += rb.Minv[j * ND + k] * row[d * ND + k];
-      float Wr = sum16(row[d * ND + j] * w);
-      if (j == 0) C[(ci) * CSTR + C_IW + d] += Wr;
+    }
+    const float wn = __shfl(w, j, WAVE);  // M~^-1 J_n^T
+    if (d < 3) {
+      // W_dd, and the couplings J_d M~^-1 J_n^T of the tangents (added to
+      // the other side's part of C_WTN)
+      const float Wr = sum16(row[d * ND + j] * w);
+      const float Wc = sum16(row[d * ND + j] * wn);
+      if (j == 0) {
+        C[(ci) * CSTR + C_IW + d] += Wr;
+        if (d > 0) C[(ci) * CSTR + C_WTN + d - 1] += Wc;
+      }
     }
     wave_sync();
   }
@@ -1967,7 +1977,8 @@ __device__ __forceinline__ void phase_pgs(const KArgs& a, const Scene& S, float*
       const int o0 = o1;
       o1 = loff[lv];
       if (rc >= 0) {
-        // the level's robot row: lanes 0..15 hold the robot joint velocities
+        // the level's robot row: lane j of each 16-lane row holds joint
+        // velocity j; row d < 3 of the wave forms J_d . v in one reduction
         const float* row = Rw + (rc - NL) * ROW_FLOATS;
         const float* c = C + rc * CSTR;
         int info = __float_as_int(c[C_INFO]);
@@ -1976,7 +1987,9 @@ __device__ __forceinline__ void phase_pgs(const KArgs& a, const Scene& S, float*
         float iw0 = c[C_IW], iw1 = c[C_IW + 1], iw2 = c[C_IW + 2];
         float bias = c[C_BIAS];
         float l0 = c[C_LAM], l1 = c[C_LAM + 1], l2 = c[C_LAM + 2];
-        const float Jn = row[j], J1 = row[ND + j], J2 = row[2 * ND + j];
+        const float wtn1 = c[C_WTN], wtn2 = c[C_WTN + 1];
+        const int dr = lane >> 4;
+        const float Jd = row[(dr < 3 ? dr : 2) * ND + j];
         // lane j's entries of w = M~^-1 J^T; M~^-1 is symmetric, so lane j
         // reads its column (consecutive across the lanes: no bank conflicts)
         float wn = 0.f, w1 = 0.f, w2 = 0.f;
@@ -1991,33 +2004,33 @@ __device__ __forceinline__ void phase_pgs(const KArgs& a, const Scene& S, float*
         onb_a(n, c[C_ONB], t1, t2);
         SideReg B;
         side_load(F, A, (info >> 16) & 0xffff, p, B);
-        float dn = lane_val(sum16(lane < ND ? Jn * vR : 0.f), 0);
-        float r = dn - dot(n, side_vel(B, p)) + bias;
+        const float dsum = sum16(dr < 3 ? Jd * vR : 0.f);
+        const float dn = lane_val(dsum, 0), d1 = lane_val(dsum, ND), d2 = lane_val(dsum, 2 * ND);
+        const f3 uB = side_vel(B, p);
+        float r = dn - dot(n, uB) + bias;
         float nl = l0;
         if (iw0 > 0.f) nl = fmaxf(0.f, l0 - r * iw0);
         if (tape && lane == 0) tape[it * a.RL.tsw + rc * 3] = l0 - r * iw0;
-        float dl = nl - l0;
-        if (lane < ND) vR += wn * dl;
-        side_impulse(B, p, n * (-dl));
+        const float dl = nl - l0;
+        float dl1 = 0.f, dl2 = 0.f;
         if (iw1 > 0.f && iw2 > 0.f) {
-          // both tangent dot products in one reduction: lanes 0..15 t1, 16..31 t2
-          float vj = __shfl(vR, j, WAVE);
-          float part = lane < ND ? J1 * vj : (lane < 2 * ND ? J2 * vj : 0.f);
-          float dsum = sum16(part);
-          float d1 = lane_val(dsum, 0), d2 = lane_val(dsum, ND);
-          f3 uB = side_vel(B, p);
+          // the friction pair sees the velocity after the normal update:
+          // t . u + dl (t . K n), the couplings of both sides from the rows
+          // phase; the impulses are then applied together
+          const float u1 = d1 - dot(t1, uB) + dl * wtn1, u2 = d2 - dot(t2, uB) + dl * wtn2;
           float y1, y2;
-          friction_disk(l1, l2, d1 - dot(t1, uB), d2 - dot(t2, uB), iw1, iw2, mu * nl, y1, y2);
+          friction_disk(l1, l2, u1, u2, iw1, iw2, mu * nl, y1, y2);
           if (tape && lane == 0) {
-            tape[it * a.RL.tsw + rc * 3 + 1] = l1 - (d1 - dot(t1, uB)) * iw1;
-            tape[it * a.RL.tsw + rc * 3 + 2] = l2 - (d2 - dot(t2, uB)) * iw2;
+            tape[it * a.RL.tsw + rc * 3 + 1] = l1 - u1 * iw1;
+            tape[it * a.RL.tsw + rc * 3 + 2] = l2 - u2 * iw2;
           }
-          float dl1 = y1 - l1, dl2 = y2 - l2;
-          if (lane < ND) vR += w1 * dl1 + w2 * dl2;
-          side_impulse(B, p, (t1 * dl1 + t2 * dl2) * (-1.f));
+          dl1 = y1 - l1;
+          dl2 = y2 - l2;
           l1 = y1;
           l2 = y2;
         }
+        vR += wn * dl + w1 * dl1 + w2 * dl2;
+        side_impulse(B, p, (n * dl + t1 * dl1 + t2 * dl2) * (-1.f));
         if (lane == 0) {
           side_store(F, A, B);
           float* cw = C + rc * CSTR;
@@ -2310,6 +2323,7 @@ __device__ __forceinline__ void run_scene(const KArgs& a, int s, float* L) {
     S.giy = g[3];
   }
   Robot rb = robot_view(L + a.L.robot, L + a.L.dyn);
+  const unsigned long long t_scene = a.cost ? clock64() : 0ull;
   const bool prof = a.phase_cycles != nullptr;
   unsigned long long cyc[8] = {0, 0, 0, 0, 0, 0, 0, 0};
   unsigned long long tc = prof ? clock64() : 0;
@@ -2336,10 +2350,8 @@ __device__ __forceinline__ void run_scene(const KArgs& a, int s, float* L) {
     wave_sync();
   }
   float* rec = REC ? a.rec + (size_t)s * a.RL.total : nullptr;
-  // cost key for the next step's order: the time of a scene grows about
-  // linearly with its contacts, its robot contacts (each some 50 others)
-  // and its free bodies (each some 30); the largest lists for its routing
-  int cost_acc = 30 * S.nf, max_nc = 0, max_nr = 0;
+  // the largest contact lists of the step, for the next step's routing
+  int max_nc = 0, max_nr = 0;
   for (int k = 0; k < a.n_sub; ++k) {
     int NC, NR, NL;
     uint64_t keysum = 0;
@@ -2359,7 +2371,6 @@ __device__ __forceinline__ void run_scene(const KArgs& a, int s, float* L) {
     // contact list; everything written so far the retry writes again alike
     if (a.fit_mode == 1 && (status & 10u)) break;
     if (rec) rec_contacts(a, L, NC, NL, NR, rec + a.RL.con + ks * a.RL.cstride);
-    cost_acc += (NC - NL) + 50 * NR;
     max_nc = max(max_nc, NC - NL);
     max_nr = max(max_nr, NR);
     MS_PHASE(1)
@@ -2418,7 +2429,13 @@ __device__ __forceinline__ void run_scene(const KArgs& a, int s, float* L) {
   if (lane == 0) {
     if (a.sub0 == 0) a.status[s] = status;
     else a.status[s] |= status;
-    if (a.cost) a.cost[s] = a.sub0 == 0 ? cost_acc : a.cost[s] + cost_acc - 30 * S.nf;
+    if (a.cost) {
+      // the scene's time in this launch (shader clock / 16) orders the next
+      // step: a scene's time changes little from one step to the next
+      const long long dt = (long long)((clock64() - t_scene) >> 4);
+      const long long v = a.sub0 == 0 ? dt : (long long)a.cost[s] + dt;
+      a.cost[s] = (int)(v < 0x7fffffffLL ? v : 0x7fffffffLL);
+    }
     if (a.maxc) {
       const int m = a.sub0 == 0 ? 0 : a.maxc[s];
       a.maxc[s] = max(m & 0xffff, max_nc) | (max(m >> 16, max_nr) << 16);
@@ -2652,9 +2669,15 @@ __global__ __launch_bounds__(1024) void k_cost_order(const int* cost, const int*
   if (t == 0 && retry) retry[0] = 0;
   for (int i = t; i < 2 * NKEY; i += 1024) cnt[i] = 0;
   __syncthreads();
+  // the key of a scene time v > 0: its base-2 logarithm in steps of 1/128
   auto slot_of = [&](int s) {
-    int k = cost[s] >> 1;
-    k = k < 0 ? 0 : (k >= NKEY ? NKEY - 1 : k);
+    const int v = cost[s];
+    int k = 0;
+    if (v > 0) {
+      const int m = 31 - __clz(v);
+      const uint32_t f = m >= 7 ? ((uint32_t)v >> (m - 7)) & 127u : ((uint32_t)v << (7 - m)) & 127u;
+      k = min(NKEY - 1, m * 128 + (int)f);
+    }
     int g = 1;
     if (fit_c > 0 && maxc) {
       const int m = maxc[s];
