@@ -96,7 +96,7 @@ constexpr int AUX_FLOATS = 32;      // per aux joint
 constexpr int FRC_FLOATS = 5;       // per free body, force-output mode: force on it (3), end-effector and finger force
 constexpr int CON_FLOATS = 17;      // per contact (odd stride)
 constexpr int CSTR = CON_FLOATS;
-constexpr int ROW_FLOATS = 3 * ND;  // per robot contact: w = M~^-1 J^T [3][16] (J is formed where it is used)
+constexpr int ROW_FLOATS = 3 * ND;  // per robot contact: J [3][16] (normal, two tangents)
 
 __host__ __device__ inline LdsLayout make_layout(int fmax, int smax, int ccap, int rcap, int stage_static,
                                                  int force = 0, int nsph = SPH) {

@@ -1680,7 +1680,6 @@ __device__ __forceinline__ void phase_rows(const KArgs& a, const Scene& S, float
   }
   wave_sync();
   // robot rows: lane (d, j) builds J[d][j] = d . (dp/dq_j) and W = J M~^-1 J^T
-  // (the sweeps form w = M~^-1 J^T from a register copy of M~^-1's rows)
   float* Rw = L + Y.rows;
   const int d = lane >> 4, j = lane & 15;
   for (int rr = 0; rr < NR; ++rr) {
@@ -1959,12 +1958,18 @@ __device__ __forceinline__ void phase_pgs(const KArgs& a, const Scene& S, float*
   float* F = L + Y.fr;
   float* A = L + Y.aux;
   const float* Rw = L + Y.rows;
-  const Robot RB = robot_view(L + Y.robot, L + Y.dyn);
   const uint16_t* loff = reinterpret_cast<const uint16_t*>(L + Y.lvl);
   const uint16_t* rob = loff + cc + 2;
   const uint32_t* order = reinterpret_cast<const uint32_t*>(rob + cc + 2);
   const float mu = a.mu;
   const int j = lane & 15;
+  // w = M~^-1 J^T of the first robot rows, kept over the sweeps: in the
+  // robot's sphere centres and the culling lists (both dead until the next
+  // substep's kinematics and contacts)
+  float* wcA = L + Y.sph;
+  float* wcB = L + Y.cand;
+  const int wc1 = (Y.fr - Y.sph) / ROW_FLOATS, wc2 = (Y.frc - Y.cand) / ROW_FLOATS;
+  const float* Minv = robot_view(L + Y.robot, L + Y.dyn).Minv;
   // the zero record's velocities (kept zero by every update that uses it)
   if (lane < 6) F[Y.fmax * FSTR + F_V + lane] = 0.f;
   wave_sync();
@@ -1990,15 +1995,26 @@ __device__ __forceinline__ void phase_pgs(const KArgs& a, const Scene& S, float*
         const float wtn1 = c[C_WTN], wtn2 = c[C_WTN + 1];
         const int dr = lane >> 4;
         const float Jd = row[(dr < 3 ? dr : 2) * ND + j];
-        // lane j's entries of w = M~^-1 J^T; M~^-1 is symmetric, so lane j
-        // reads its column (consecutive across the lanes: no bank conflicts)
+        // lane j's entries of w = M~^-1 J^T: formed in the first sweep (M~^-1
+        // is symmetric, so lane j reads its column: consecutive across the
+        // lanes, no bank conflicts) and kept for the later ones where LDS
+        // that is dead during the sweeps has room
         float wn = 0.f, w1 = 0.f, w2 = 0.f;
+        const int rr = rc - NL;
+        float* wc = rr < wc1 ? wcA + rr * ROW_FLOATS : (rr < wc1 + wc2 ? wcB + (rr - wc1) * ROW_FLOATS : nullptr);
+        if (it == 0 || wc == nullptr) {
 #pragma unroll 8
-        for (int k = 0; k < ND; ++k) {
-          const float m = RB.Minv[k * ND + j];
-          wn += m * row[k];
-          w1 += m * row[ND + k];
-          w2 += m * row[2 * ND + k];
+          for (int k = 0; k < ND; ++k) {
+            const float m = Minv[k * ND + j];
+            wn += m * row[k];
+            w1 += m * row[ND + k];
+            w2 += m * row[2 * ND + k];
+          }
+          if (wc != nullptr && dr < 3) wc[lane] = dr == 0 ? wn : (dr == 1 ? w1 : w2);
+        } else {
+          wn = wc[j];
+          w1 = wc[ND + j];
+          w2 = wc[2 * ND + j];
         }
         f3 t1, t2;
         onb_a(n, c[C_ONB], t1, t2);
