@@ -2354,15 +2354,23 @@ __device__ __forceinline__ void run_scene(const KArgs& a, int s, float* L) {
   uint32_t status = 0;
   float frc = 0.f;
   if (MODE == 2) {
+    // the force sums of the control step: a launch that resumes the step
+    // (a.sub0 > 0) continues the sums so far, so that they add up in the
+    // order of one launch over the whole step
     float* FR = L + a.L.frc;
     float* A = L + a.L.aux;
+    const bool resume = a.sub0 > 0;
     for (int f = lane; f < S.nf; f += WAVE) {
       for (int t = 0; t < FRC_FLOATS; ++t) FR[(f) * FRC_FLOATS + t] = 0.f;
+      if (resume && a.frc_body)
+        for (int t = 0; t < 3; ++t) FR[(f) * FRC_FLOATS + R_FRC + t] = a.frc_body[(size_t)(S.f0 + f) * 4 + t];
+      if (resume && a.grip) FR[(f) * FRC_FLOATS + R_EE] = a.grip[2 * (size_t)(S.f0 + f)];
     }
     if (lane < S.na) {
-      A[A_EE * AMAX + lane] = 0.f;
+      A[A_EE * AMAX + lane] = resume && a.grip ? a.grip[2 * ((size_t)a.NF + S.a0 + lane)] : 0.f;
       A[A_FMIN * AMAX + lane] = 0.f;
     }
+    if (resume && a.frc_robot) frc = a.frc_robot[s];
     wave_sync();
   }
   float* rec = REC ? a.rec + (size_t)s * a.RL.total : nullptr;
@@ -2424,18 +2432,18 @@ __device__ __forceinline__ void run_scene(const KArgs& a, int s, float* L) {
       const bool isf = o < S.nf;
       float* dst = a.grip + 2 * (isf ? (size_t)(S.f0 + o) : (size_t)a.NF + S.a0 + (o - S.nf));
       const float fe = isf ? FR[o * FRC_FLOATS + R_EE] : A[A_EE * AMAX + o - S.nf];
-      dst[0] = a.sub0 == 0 ? fe : dst[0] + fe;
+      dst[0] = fe;
       if (last) dst[1] = isf ? FR[o * FRC_FLOATS + R_FMIN] : A[A_FMIN * AMAX + o - S.nf];
     }
   }
   if (MODE == 2 && a.frc_robot) {
     const float* FR = L + a.L.frc;
-    if (lane == 0) a.frc_robot[s] = a.sub0 == 0 ? frc : a.frc_robot[s] + frc;
+    if (lane == 0) a.frc_robot[s] = frc;
     for (int f = lane; f < S.nf; f += WAVE) {
       float* dst = a.frc_body + (size_t)(S.f0 + f) * 4;
       for (int t = 0; t < 3; ++t) {
         float v = FR[(f) * FRC_FLOATS + R_FRC + t];
-        dst[t] = a.sub0 == 0 ? v : dst[t] + v;
+        dst[t] = v;
       }
       dst[3] = 0.f;
     }
