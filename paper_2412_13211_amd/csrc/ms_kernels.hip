@@ -99,6 +99,14 @@ __device__ __forceinline__ uint64_t mix64(uint64_t z) {
   return z ^ (z >> 31);
 }
 __device__ __forceinline__ int lane_id() { return threadIdx.x; }
+// the lane index, opaque to the optimizer: address arithmetic on it stays
+// where it is used instead of being hoisted out of the scene loop into
+// registers that live (or spill) across the whole step
+__device__ __forceinline__ int lane_fresh() {
+  int l = lane_id();
+  asm volatile("" : "+v"(l));
+  return l;
+}
 __device__ __forceinline__ int prefix_below(uint64_t m) {
   return __builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0));
 }
@@ -255,9 +263,10 @@ __device__ __forceinline__ void load_scene(const KArgs& a, const Scene& S, float
   const int lane = lane_id();
   const LdsLayout& Y = a.L;
   if (lane < ND) {
-    rb.q[lane] = a.x_in[(size_t)S.s * ND + lane];
-    rb.qd[lane] = a.x_in[(size_t)a.S * ND + (size_t)S.s * ND + lane];
-    rb.u[lane] = a.u[(size_t)S.s * ND + lane];
+    const int ln = lane_fresh();
+    rb.q[lane] = a.x_in[(size_t)S.s * ND + ln];
+    rb.qd[lane] = a.x_in[(size_t)a.S * ND + (size_t)S.s * ND + ln];
+    rb.u[lane] = a.u[(size_t)S.s * ND + ln];
   }
   float* F = L + Y.fr;
   const int fm = Y.fmax;
@@ -301,7 +310,7 @@ __device__ __forceinline__ void load_scene(const KArgs& a, const Scene& S, float
   if (Y.smax > 0) {
     float* St = L + Y.stat;
     const float* src = a.statics + (size_t)S.s0 * 6;
-    for (int i = lane; i < S.ns * 6; i += WAVE) St[i] = src[i];
+    for (int i = lane_fresh(); i < S.ns * 6; i += WAVE) St[i] = src[i];
   }
   float* Pl = L + Y.plane;
   if (lane < S.np) {
@@ -328,8 +337,9 @@ __device__ __forceinline__ void store_scene(const KArgs& a, const Scene& S, floa
   if (lane < ND) {
     float q = rb.q[lane], qd = rb.qd[lane];
     bad |= !isfinite(q) || !isfinite(qd);
-    a.x_out[(size_t)S.s * ND + lane] = q;
-    a.x_out[(size_t)a.S * ND + (size_t)S.s * ND + lane] = qd;
+    const int ln = lane_fresh();
+    a.x_out[(size_t)S.s * ND + ln] = q;
+    a.x_out[(size_t)a.S * ND + (size_t)S.s * ND + ln] = qd;
   }
   const float* F = L + Y.fr;
   const int fm = Y.fmax;
@@ -1365,7 +1375,7 @@ __device__ __forceinline__ void phase_dynamics(const KArgs& a, const Scene& S, f
   // are added by a 16-lane reduction, and lane 0 of the row leaves the sum in
   // LDS for body i's own lane.  (One lane per body looping over the other
   // bodies made each sum a chain of 16 dependent LDS rounds.)
-  const int q = lane >> 4, kq = lane & 15;
+  const int lf = lane_fresh(), q = lf >> 4, kq = lf & 15;
   // pass 1 (lane per body): COM and world inertia about the COM (kept for the
   // subtree sums); (pair lanes) twist v_i = sum over k in anc-or-self(i) of
   // s_k qd_k at p_i; (lane per body) the velocity-product acceleration
