@@ -57,6 +57,10 @@ __device__ __forceinline__ float sum16(float v) {
 }
 // sum over lanes 0..15 (other lanes pass 0), returned in every lane
 __device__ __forceinline__ float sum16_b(float v) { return bcast0(sum16(v)); }
+// the sum of 16-lane row q (q = 0..3), read by every lane
+__device__ __forceinline__ float row_sum(float s16, int q) {
+  return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(s16), 16 * q));
+}
 
 // level-schedule views inside the LDS block
 struct Lv {
@@ -90,15 +94,19 @@ __device__ __forceinline__ void row_nodes(const msa::Eng& E, int r, int& na, int
   nbn = tk == 2 ? 1 + ti : (tk == 3 ? 1 + AMAX + ti : -1);
 }
 
-// Reverse of a robot contact's row updates in sweep it.  Lanes 0..15 carry the
-// robot's joints in registers; the target side (a free body or a door /
-// drawer joint, none for furniture and planes) is carried in registers by
-// every lane alike, so the sums over the joints are the only exchanges; lane
-// 0 writes the target side and the contact's adjoints back at the end.
+// Reverse of a robot contact's row updates in sweep it.  Lane j of each
+// 16-lane row carries the robot's joint j in registers (the four copies
+// equal); the target side (a free body or a door / drawer joint, none for
+// furniture and planes) is carried in registers by every lane alike, so the
+// sums over the joints are the only exchanges, and each 16-lane row forms
+// one of them: the friction part's four sums come from one reduction, the
+// normal part's two from another.  Lanes 0..15 write the joints back, lane 0
+// the target side and the contact's adjoints.
 __device__ void robot_contact_bar(msa::Eng& E, int it, int ci, float* L) {
   using namespace msa;
-  const int lane = lane_id(), j = lane & 15;
-  const bool own = lane < 16 && j < E.nb;
+  const int lane = lane_id(), j = lane & 15, q = lane >> 4;
+  const bool jv = j < E.nb;           // this lane holds joint j
+  const bool own = lane < 16 && jv;   // and writes it back
   const WS& w = E.w;
   const long e = w.con + (long)ci * CR, cb = w.conb + (long)ci * CB, lb = w.lamb + ci * 3;
   const long rr = (long)ci * 3 * ND + j;
@@ -110,7 +118,7 @@ __device__ void robot_contact_bar(msa::Eng& E, int it, int ci, float* L) {
   // M~^-1 J entries and their adjoints
   float vr = 0.f, vrb = 0.f, J[3] = {0.f, 0.f, 0.f}, Wr[3] = {0.f, 0.f, 0.f};
   float Jb[3] = {0.f, 0.f, 0.f}, Wrb[3] = {0.f, 0.f, 0.f};
-  if (own) {
+  if (jv) {
     vr = L[w.vR + j];
     vrb = L[w.vRb + j];
 #pragma unroll
@@ -162,17 +170,19 @@ __device__ void robot_contact_bar(msa::Eng& E, int it, int ci, float* L) {
     vr += Wr[1] * (-d1);
     t_apply(2, -d2);
     t_apply(1, -d1);
-    const float a1 = own ? Wr[1] * vrb : 0.f, a2 = own ? Wr[2] * vrb : 0.f;
+    // rows 0..3: w_1 . vbar, w_2 . vbar, J_1 . v, J_2 . v
+    const float part = !jv ? 0.f : (q == 0 ? Wr[1] * vrb : (q == 1 ? Wr[2] * vrb : (q == 2 ? J[1] * vr : J[2] * vr)));
+    const float s4 = sum16(part);
     Wrb[1] += vrb * d1;
     Wrb[2] += vrb * d2;
     const float b1 = t_apply_bar(1, d1);
     const float b2 = t_apply_bar(2, d2);
-    const float d1b = sum16_b(a1) + b1, d2b = sum16_b(a2) + b2;
+    const float d1b = row_sum(s4, 0) + b1, d2b = row_sum(s4, 1) + b2;
     float yb1, yb2, limb;
     Eng::fric_bar(y1, y2, lim, proj, lb1 + d1b, lb2 + d2b, yb1, yb2, limb);
     const float l1 = -d1b + yb1, l2 = -d2b + yb2;
-    const float r1 = sum16_b(own ? J[1] * vr : 0.f) + t_rowvel(1);
-    const float r2 = sum16_b(own ? J[2] * vr : 0.f) + t_rowvel(2);
+    const float r1 = row_sum(s4, 2) + t_rowvel(1);
+    const float r2 = row_sum(s4, 3) + t_rowvel(2);
     const float rb1 = -yb1 / W1, rb2 = -yb2 / W2;
     lb0 += mu * limb;
     Wb1 += yb1 * r1 / (W1 * W1);
@@ -192,12 +202,13 @@ __device__ void robot_contact_bar(msa::Eng& E, int it, int ci, float* L) {
     const float dl = nl - E.prev_normal(it, ci);
     vr += Wr[0] * (-dl);
     t_apply(0, -dl);
-    const float a0 = own ? Wr[0] * vrb : 0.f;
+    // rows 0..1: w_n . vbar, J_n . v
+    const float s2 = sum16(!jv ? 0.f : (q == 0 ? Wr[0] * vrb : J[0] * vr));
     Wrb[0] += vrb * dl;
-    const float dlb = sum16_b(a0) + t_apply_bar(0, dl);
+    const float dlb = row_sum(s2, 0) + t_apply_bar(0, dl);
     float lold, yb;
     Eng::normal_bar(y, lb0 + dlb, dlb, lold, yb);
-    const float r = sum16_b(own ? J[0] * vr : 0.f) + t_rowvel(0) + L[e + C_BIAS];
+    const float r = row_sum(s2, 1) + t_rowvel(0) + L[e + C_BIAS];
     const float rb = -yb / W0;
     Wb0 += yb * r / (W0 * W0);
     biasb += rb;
