@@ -124,8 +124,9 @@ __host__ __device__ inline LdsLayout make_layout(int fmax, int smax, int ccap, i
   L.nch = (L.ntmax + WAVE - 1) / WAVE;
   L.cmask = L.rows;
   {
-    // masks, then the free bodies' bounding spheres (4 floats each)
-    const int rw = lds_align4(rcap * ROW_FLOATS), mk = lds_align4((fmax > ND ? fmax : ND) * L.nch * 2) + fmax * 4;
+    // masks, then the robot's or the free bodies' bounding spheres (4 floats each)
+    const int rw = lds_align4(rcap * ROW_FLOATS),
+              mk = lds_align4((fmax > ND ? fmax : ND) * L.nch * 2) + (fmax > ND ? fmax : ND) * 4;
     const int cr = lds_align4(ccap * CON_FLOATS) + (rw > mk ? rw : mk);
     o += cr > DYN_FLOATS ? cr : DYN_FLOATS;
   }

@@ -1105,24 +1105,23 @@ __device__ __forceinline__ void phase_contacts(const KArgs& a, const Scene& S, f
       // candidates, a loop over the bodies, one ballot per (body, chunk)
       uint32_t* msk = reinterpret_cast<uint32_t*>(L + Y.cmask);
       const int ncA = (nra + WAVE - 1) / WAVE;
-      f3 bcen = mk3(0.f, 0.f, 0.f);
-      float bR = 0.f;
+      // the bodies' bounding spheres (centre, radius; a body without spheres
+      // radius -1) where every lane reads them with one broadcast load
+      float4* rbd = reinterpret_cast<float4*>(L + Y.cmask + lds_align4((Y.fmax > ND ? Y.fmax : ND) * Y.nch * 2));
       if (lane < S.nb) {
         float4 bs = M->bsph[lane];
-        bcen = mv(rb.R + lane * 9, mk3(bs.x, bs.y, bs.z)) + body_p(rb, lane);
-        bR = bs.w;
+        const f3 c = mv(rb.R + lane * 9, mk3(bs.x, bs.y, bs.z)) + body_p(rb, lane);
+        rbd[lane] = make_float4(c.x, c.y, c.z, M->sph_count[lane] > 0 ? bs.w : -1.f);
       }
+      lds_order();
       for (int ch = 0; ch < ncA; ++ch) {
         const int i = ch * WAVE + lane;
         TBound B;
         target_bound(X, i < nra ? (int)listA[i] : -1, B);
 #pragma unroll 4
         for (int b = 0; b < S.nb; ++b) {
-          bool m = false;
-          if (M->sph_count[b] > 0) {
-            const f3 c = mk3(lane_val(bcen.x, b), lane_val(bcen.y, b), lane_val(bcen.z, b));
-            m = B.valid && bound_near(B, c, lane_val(bR, b), slack);
-          }
+          const float4 bd = rbd[b];
+          const bool m = bd.w >= 0.f && B.valid && bound_near(B, mk3(bd.x, bd.y, bd.z), bd.w, slack);
           const uint64_t mk = __ballot(m);
           if (lane == 0) {
             msk[(b * ncA + ch) * 2] = (uint32_t)mk;
