@@ -112,6 +112,67 @@ def test_single_step_parity(name, mk, steps):
         f"vel {worst[1]:.3e}; scaled bar used in {n_relaxed}/{n_tot}; max err/bar {worst_ratio:.3f}")
 
 
+def test_robot_heavy_scenes_parity():
+    """The scenes with the most robot contacts (robot rows beyond those whose
+    w = M~^-1 J^T the sweeps keep in LDS, so both paths of the robot row run):
+    found by stepping a 512-scene cfg3 batch on the GPU, then one step from
+    the GPU's state compared with the oracle's step from the same state."""
+    ms = _ms()
+    b = sg.make(3, 512)
+    mb = ms.MsBatch(b)
+    mb.enable_debug(True)
+    x = torch.as_tensor(b.state0).cuda()
+    best = []  # (robot contacts in one substep, step, scene, state before the step)
+    for t in range(10):
+        xs = x.cpu().numpy().copy()
+        x = mb.step(x, torch.as_tensor(b.controls_for(t)).cuda())
+        torch.cuda.synchronize()
+        nr = mb.debug_contacts()[:, :, 1].max(axis=1).astype(int)
+        for s in np.argsort(-nr)[:8]:
+            best.append((int(nr[s]), t, int(s), xs))
+    best.sort(key=lambda e: -e[0])
+    picked, seen = [], set()
+    for nr, t, s, xs in best:
+        if s not in seen:
+            seen.add(s)
+            picked.append((nr, t, s, xs))
+        if len(picked) == 6:
+            break
+    say(f"[robot-heavy] robot contacts per substep of the picked scenes: {[p[0] for p in picked]}")
+    assert picked[0][0] >= 12
+    scenes = [p[2] for p in picked]
+    sub = b.subset(scenes)
+    parts = []
+    for nr, t, s, xs in picked:
+        st = sg.split_state(xs, b.n_scenes, b.n_free, b.n_aux)
+        parts.append((st["q"][s], st["qd"][s], st["free"][b.free_off[s]:b.free_off[s + 1]],
+                      st["aux"][b.aux_off[s]:b.aux_off[s + 1]]))
+    x0 = sg.join_state(np.stack([p[0] for p in parts]), np.stack([p[1] for p in parts]),
+                       np.concatenate([p[2] for p in parts]), np.concatenate([p[3] for p in parts]))
+    u = np.stack([b.controls_for(t)[s] for nr, t, s, xs in picked]).astype(np.float32)
+    x0 = x0.astype(np.float64)
+    o = oracle.Oracle(sub)
+    smb = ms.MsBatch(sub)
+    smb.enable_debug(True)
+    xo, d = o.step(x0, u, debug=True)
+    xg = gpu_step(smb, x0, u)
+    st = smb.status()
+    assert not np.any(st & (ms.MS_ST_NONFINITE | ms.MS_ST_OVERFLOW | ms.MS_ST_ROBOT_OVERFLOW)), st
+    dbg = smb.debug_contacts()
+    say(f"  robot contacts per substep on the GPU: {dbg[:, :, 1].max(axis=1).tolist()}")
+    same = same_contacts(d, dbg)
+    pe, ve = errors(o, sub, xo, xg)
+    ps, vs = fp32_sensitivity(o, sub, x0, u)
+    pf, vf = errors(o, sub, xo, o.step_f32(x0, u))
+    tol_p = np.maximum.reduce([np.full_like(ps, POS_TOL), 10 * ps, 4 * pf])
+    tol_v = np.maximum.reduce([np.full_like(vs, VEL_TOL), 10 * vs, 4 * vf])
+    for i in range(len(scenes)):
+        say(f"    scene {scenes[i]}: contacts equal {same[i]}; pos err {pe[i]:.2e} (bar {tol_p[i]:.2e}), "
+            f"vel err {ve[i]:.2e} (bar {tol_v[i]:.2e})")
+    assert same.sum() >= len(scenes) // 2
+    assert np.all(pe[same] <= tol_p[same]) and np.all(ve[same] <= tol_v[same])
+
+
 FREE_RUNS = [("cfg1", lambda: sg.make(1)), ("cfg2", lambda: sg.make(2, 32)), ("cfg5", lambda: sg.make(5, 32))]
 
 
