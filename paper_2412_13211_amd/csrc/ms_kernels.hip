@@ -665,41 +665,51 @@ __device__ __forceinline__ bool eval_pair(const ConCtx& X, int o, int t, PairOut
     }
     tkey = t;
     bside = K_STATIC << 8;
-  } else if (t < X.np + X.ns) {
-    int bi = t - X.np;
-    const float* bx = X.St + bi * 6;
-    phi = box_test(c, r, mk3(bx[0], bx[1], bx[2]), nullptr, mk3(bx[3], bx[4], bx[5]), nrm);
-    tkey = (1 << 24) | bi;
-    bside = K_STATIC << 8;
-  } else if (t < X.np + X.ns + X.na) {
-    int x = t - X.np - X.ns;
-    float Rx[9];
-    for (int k = 0; k < 9; ++k) Rx[k] = A[(A_R + k) * AMAX + x];
-    phi = box_test(c, r, mk3(A[(A_BC + 0) * AMAX + x], A[(A_BC + 1) * AMAX + x], A[(A_BC + 2) * AMAX + x]), Rx,
-                   mk3(A[(A_BH + 0) * AMAX + x], A[(A_BH + 1) * AMAX + x], A[(A_BH + 2) * AMAX + x]), nrm);
-    tkey = (2 << 24) | x;
-    bside = (K_AUX << 8) | x;
   } else {
-    int g = t - X.np - X.ns - X.na;
-    bool gbox = F[(g) * FSTR + F_TYPE] == 0.f;
-    allowed = g != of;
-    if (!gbox && okind == 1) allowed = false;           // box vertices skip free spheres
-    if (!gbox && okind == 2 && g <= of) allowed = false;  // sphere pairs once
+    // box targets (furniture, door / drawer boxes, free boxes) share one box
+    // test, so that a chunk of pairs with mixed targets runs it once; a
+    // furniture box is axis-aligned (the identity rotation is exact)
+    float Rb[9] = {1.f, 0.f, 0.f, 0.f, 1.f, 0.f, 0.f, 0.f, 1.f};
+    f3 bc, he;
+    bool sphere = false;
+    if (t < X.np + X.ns) {
+      const int bi = t - X.np;
+      const float* bx = X.St + bi * 6;
+      bc = mk3(bx[0], bx[1], bx[2]);
+      he = mk3(bx[3], bx[4], bx[5]);
+      tkey = (1 << 24) | bi;
+      bside = K_STATIC << 8;
+    } else if (t < X.np + X.ns + X.na) {
+      const int x = t - X.np - X.ns;
+      for (int k = 0; k < 9; ++k) Rb[k] = A[(A_R + k) * AMAX + x];
+      bc = mk3(A[(A_BC + 0) * AMAX + x], A[(A_BC + 1) * AMAX + x], A[(A_BC + 2) * AMAX + x]);
+      he = mk3(A[(A_BH + 0) * AMAX + x], A[(A_BH + 1) * AMAX + x], A[(A_BH + 2) * AMAX + x]);
+      tkey = (2 << 24) | x;
+      bside = (K_AUX << 8) | x;
+    } else {
+      const int g = t - X.np - X.ns - X.na;
+      const bool gbox = F[(g) * FSTR + F_TYPE] == 0.f;
+      allowed = g != of;
+      if (!gbox && okind == 1) allowed = false;           // box vertices skip free spheres
+      if (!gbox && okind == 2 && g <= of) allowed = false;  // sphere pairs once
+      bc = mk3(F[(g) * FSTR + F_X + 0], F[(g) * FSTR + F_X + 1], F[(g) * FSTR + F_X + 2]);
+      he = mk3(F[(g) * FSTR + F_H + 0], F[(g) * FSTR + F_H + 1], F[(g) * FSTR + F_H + 2]);
+      if (gbox)
+        for (int k = 0; k < 9; ++k) Rb[k] = F[(g) * FSTR + F_R + k];
+      sphere = !gbox;
+      tkey = (3 << 24) | g;
+      bside = (K_FREE << 8) | g;
+    }
     if (allowed) {
-      f3 xg = mk3(F[(g) * FSTR + F_X + 0], F[(g) * FSTR + F_X + 1], F[(g) * FSTR + F_X + 2]);
-      if (gbox) {
-        float Rg[9];
-        for (int k = 0; k < 9; ++k) Rg[k] = F[(g) * FSTR + F_R + k];
-        phi = box_test(c, r, xg, Rg, mk3(F[(g) * FSTR + F_H + 0], F[(g) * FSTR + F_H + 1], F[(g) * FSTR + F_H + 2]), nrm);
-      } else {
-        f3 d = c - xg;
+      if (sphere) {
+        f3 d = c - bc;
         float dist = sqrtf(dot(d, d));
-        phi = dist - r - F[(g) * FSTR + F_H + 0];
+        phi = dist - r - he.x;
         nrm = dist < 1e-12f ? mk3(0.f, 0.f, 1.f) : d * (1.f / dist);
+      } else {
+        phi = box_test(c, r, bc, Rb, he, nrm);
       }
     }
-    tkey = (3 << 24) | g;
-    bside = (K_FREE << 8) | g;
   }
   out.phi = phi;
   out.n = nrm;
