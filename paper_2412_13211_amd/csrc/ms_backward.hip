@@ -1045,7 +1045,32 @@ __device__ void bwd_scene(const BwdArgs& a, int s, float* L) {
       const float* src = tape_g + (size_t)it * RL.tsw;
       for (int i = lane; i < R3; i += 64) dst[i] = src[i];
     };
+    // a reverse sweep reads its own tape slot and the previous sweep's; the
+    // sweep two back is loaded into registers a sweep ahead and written to
+    // its slot once that slot is free, so that no sweep waits for the record
+    constexpr int TPF = 8;  // tape floats per lane carried in registers (the rest staged directly)
+    float pf[TPF];
+    auto fetch = [&](int it) {
+      const float* src = tape_g + (size_t)it * RL.tsw;
+#pragma unroll
+      for (int k = 0; k < TPF; ++k) {
+        const int i = lane + 64 * k;
+        pf[k] = i < R3 ? src[i] : 0.f;
+      }
+    };
+    auto put = [&](int it) {
+      float* dst = L + w.tring + (it & 1) * w.trs;
+#pragma unroll
+      for (int k = 0; k < TPF; ++k) {
+        const int i = lane + 64 * k;
+        if (i < R3) dst[i] = pf[k];
+      }
+      const float* src = tape_g + (size_t)it * RL.tsw;
+      for (int i = lane + 64 * TPF; i < R3; i += 64) dst[i] = src[i];
+    };
     if (a.pr.K > 0) stage(a.pr.K - 1);
+    if (a.pr.K > 1) stage(a.pr.K - 2);
+    if (a.pr.K > 2) fetch(a.pr.K - 3);
     // adjoint accumulators of this substep
     zero_lds(L, w.gB, w.ss);
     zero_lds(L, w.vRb, ND);
@@ -1070,7 +1095,10 @@ __device__ void bwd_scene(const BwdArgs& a, int s, float* L) {
     phase(3);
     // Gauss-Seidel sweeps in reverse, levels in reverse
     for (int it = a.pr.K - 1; it >= 0; --it) {
-      if (it >= 1) stage(it - 1);
+      if (it >= 1 && it <= a.pr.K - 2) {
+        put(it - 1);
+        if (it >= 2) fetch(it - 2);
+      }
       lds_order();
       for (int lv = maxl; lv >= 1; --lv) {
         const int rr = LV.rob[lv];
