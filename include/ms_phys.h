@@ -260,14 +260,18 @@ ms_status ms_get_forward_split(ms_batch* b, int32_t* contact_cap, int32_t* n_ful
 ms_status ms_autotune(ms_batch* b, const void* state_dev, const float* controls_dev, void* tmp_state_dev,
                       int32_t reps, void* hip_stream, ms_schedule* chosen, float* ms_per_step);
 
-/* Backward autotuner: times ms_step_backward (record + adjoint) from the
- * given state / controls / state adjoint (gx_in_dev, gu_dev: outputs it may
- * overwrite; gx_out_dev must not alias gx_in_dev) for the adjoint's layouts:
- * one launch in the full layout, or the split launch with each smaller
- * contact cap at which the workgroups per CU step up (4 or 8 robot
- * contacts); keeps the fastest (ms_get_backward_split reads it back) and
- * writes it to split_c / split_r (0 / 0: no split) with its time.  Needs the
- * tape buffer (MS_E_STATE otherwise).  Cached like ms_autotune. */
+/* Backward autotuner: records the control step from the given state /
+ * controls once into the tape buffer, then times the adjoint launches of
+ * ms_step_backward from that record with the given state adjoint (gx_in_dev,
+ * gu_dev: outputs it may overwrite; gx_out_dev must not alias gx_in_dev) for
+ * the adjoint's layouts: one launch in the full layout, or the split launch
+ * with each smaller contact cap at which the workgroups per CU step up (4 or
+ * 8 robot contacts), each in two rounds of reps calls (the faster round
+ * counts); keeps the fastest, or within 2 % of it the split with the most
+ * robot contacts in its smaller layout (ms_get_backward_split reads it back),
+ * and writes
+ * it to split_c / split_r (0 / 0: no split) with its time per call.  Needs
+ * the tape buffer (MS_E_STATE otherwise).  Cached like ms_autotune. */
 ms_status ms_autotune_backward(ms_batch* b, const void* state_dev, const float* controls_dev,
                                const void* gx_out_dev, void* gx_in_dev, float* gu_dev, int32_t reps,
                                void* hip_stream, int32_t* split_c, int32_t* split_r, float* ms_per_step);

@@ -1248,17 +1248,51 @@ ms_status ms_autotune_backward(ms_batch* b, const void* x, const float* u, const
     for (int k : ks)
       if (std::find(cands.begin(), cands.end(), std::make_pair(k, r)) == cands.end()) cands.push_back({k, r});
   }
-  std::pair<int, int> best{sc0, sr0};
-  float best_ms = 1e30f;
-  for (auto& c : cands) {
-    if (c.first == 0) b->split_c = b->split_r = 0;
-    else if (ms_set_backward_split(b, c.first, c.second) != MS_OK) continue;
-    const float ms = time_calls(st, reps, [&] { return ms_step_backward(b, x, u, gx_out, gx_in, gu, st) == MS_OK; });
-    if (ms > 0.f && ms < best_ms) {
-      best_ms = ms;
-      best = {b->split_c, b->split_r};
+  // the candidates time the adjoint launches alone, from one record of this
+  // step in the tape buffer (the record does not depend on the split: timed
+  // with it, the candidates' differences drowned in the recording's time);
+  // the reference path, or a workspace beyond LDS, records in each call
+  const float* rec = nullptr;
+  {
+    const msa::WS ww = bwd_ws_wave(d, b->cnt);
+    if (!(b->sched.flags & MS_SCHED_BWD_REFERENCE) && (size_t)ww.total * sizeof(float) <= b->max_lds) {
+      const float* ut = control_targets(b, x, u, st);
+      HIP_TRY(hipGetLastError());
+      const ms_status rs = enqueue_record(b, x, ut, reinterpret_cast<float*>(b->tape), st);
+      if (rs != MS_OK) return rs;
+      rec = reinterpret_cast<const float*>(b->tape);
     }
   }
+  // two rounds over the candidates, each kept at its faster round: the
+  // candidates are a few percent apart, about the spread of one timing
+  std::pair<int, int> best{sc0, sr0};
+  float best_ms = 1e30f;
+  std::vector<float> cand_ms(cands.size(), 1e30f);
+  std::vector<std::pair<int, int>> applied(cands);
+  for (int round = 0; round < 2; ++round)
+    for (size_t i = 0; i < cands.size(); ++i) {
+      const auto& c = cands[i];
+      if (c.first == 0) b->split_c = b->split_r = 0;
+      else if (ms_set_backward_split(b, c.first, c.second) != MS_OK) continue;
+      applied[i] = {b->split_c, b->split_r};
+      const float ms =
+          time_calls(st, reps, [&] { return step_backward_impl(b, x, u, rec, gx_out, gx_in, gu, st) == MS_OK; });
+      if (ms > 0.f) cand_ms[i] = std::min(cand_ms[i], ms);
+    }
+  for (size_t i = 0; i < cands.size(); ++i)
+    if (cand_ms[i] < best_ms) {
+      best_ms = cand_ms[i];
+      best = applied[i];
+    }
+  // within 2 % of the fastest, the split with the most robot contacts in its
+  // smaller layout: the tuning step is one state, and a horizon whose robot
+  // contacts grow sends fewer scenes to the full layout with it
+  for (size_t i = 0; i < cands.size(); ++i)
+    if (cand_ms[i] <= 1.02f * best_ms && applied[i].first > 0 &&
+        (best.first == 0 || applied[i].second > best.second)) {
+      best = applied[i];
+      best_ms = cand_ms[i];
+    }
   b->split_c = best.first;
   b->split_r = best.second;
   if (split_c) *split_c = b->split_c;
