@@ -1262,9 +1262,35 @@ __device__ __forceinline__ void phase_contacts(const KArgs& a, const Scene& S, f
           }
         }
       }
-      // planes, door / drawer boxes and free bodies (transposed)
+      // planes, door / drawer boxes and free bodies (transposed).  With at
+      // most 32 such targets both halves of the wave hold them, and each
+      // ballot serves two bodies (the lower half's and the upper half's).
       const int NO = S.np + S.na + S.nf;
-      for (int base = 0; base < NO; base += WAVE) {
+      if (NO <= WAVE / 2) {
+        const int hh = lane >> 5, l = lane & 31;
+        const int t = l < S.np ? l : S.ns + l;  // the target index of other-target l
+        TBound B;
+        target_bound(X, l < NO ? t : -1, B);
+        uint64_t mym = 0;  // lane f: body f's bits over the other targets
+#pragma unroll 2
+        for (int f0 = 0; f0 < S.nf; f0 += 2) {
+          const int f = f0 + hh;
+          const float4 bd = fbd[f < S.nf ? f : S.nf - 1];
+          const bool fbox = bd.w >= 0.f;
+          bool m = f < S.nf && B.valid && bound_near(B, mk3(bd.x, bd.y, bd.z), fabsf(bd.w), slack);
+          if (B.g >= 0 && (B.g == f || (!B.gbox && (fbox || B.g <= f)))) m = false;
+          const uint64_t mk = __ballot(m);
+          mym = lane == f0 ? (mk & 0xffffffffull) : (lane == f0 + 1 ? (mk >> 32) : mym);
+        }
+        if (lane < S.nf)
+          while (mym) {
+            const int bit = __ffsll((long long)mym) - 1;
+            mym &= mym - 1ull;
+            const int tt = bit < S.np ? bit : S.ns + bit;
+            atomicOr(msk64 + lane * nch + (tt >> 6), 1ull << (tt & 63));
+          }
+      }
+      for (int base = 0; NO > WAVE / 2 && base < NO; base += WAVE) {
         const int l = base + lane;
         const int t = l < S.np ? l : S.ns + l;  // the target index of other-target l
         TBound B;
@@ -1393,7 +1419,7 @@ __device__ __forceinline__ void phase_dynamics(const KArgs& a, const Scene& S, f
   float vp[6] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
   f3 pi = mk3(0.f, 0.f, 0.f);
   if (lane < nb) {
-    const int i = lane;
+    const int i = lane_fresh();
     pi = body_p(rb, i);
     const float* R = rb.R + i * 9;
     const f3 d = mv(R, mk3(M->com[i][0], M->com[i][1], M->com[i][2]));
