@@ -77,3 +77,19 @@ def test_null_arguments_rejected():
     assert L.ms_step(None, None, None, None, None) == -1
     assert L.ms_destroy_batch(None) == -1
     assert L.ms_query_sizes(None, None, None) == -1
+
+
+def test_python_constants_match_header():
+    """Every MS_* enumerator the binding defines has the header's value (the
+    binding marshals flags and reads status bits by these numbers)."""
+    hdr = open(os.path.join(ROOT, "include", "ms_phys.h")).read()
+    hdr = re.sub(r"/\*.*?\*/", "", hdr, flags=re.S)
+    values = {}
+    for body in re.findall(r"enum\s*\{(.*?)\}", hdr, flags=re.S):
+        for name, val in re.findall(r"(MS_[A-Z0-9_]+)\s*=\s*(-?\w+)", body):
+            values[name] = int(val.rstrip("uU"), 0)
+    names = [n for n in dir(ms) if re.fullmatch(r"MS_[A-Z0-9_]+", n) and isinstance(getattr(ms, n), int)]
+    checked = [n for n in names if n in values]
+    assert len(checked) >= 20, checked
+    for n in checked:
+        assert getattr(ms, n) == values[n], (n, getattr(ms, n), values[n])
